@@ -1,0 +1,36 @@
+"""Loader for the oracle's plain-C Wilson operator (test infrastructure only).
+
+Builds ``oracle/liboracle_wilson.so`` with gcc if it is missing or older than
+its source, then loads it with ctypes.
+"""
+import ctypes
+import os
+import subprocess
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "wilson.c")
+LIB = os.path.join(_HERE, "liboracle_wilson.so")
+_lib = None
+
+
+def build(force=False):
+    """Compile the oracle C source with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
+                               SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        L.oracle_wilson_apply.argtypes = [
+            ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long, ctypes.c_int]
+        L.oracle_wilson_apply.restype = None
+        _lib = L
+    return _lib

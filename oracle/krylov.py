@@ -1,0 +1,125 @@
+"""Oracle: Arnoldi / one GMRES(d) cycle, harmonic Ritz values, Leja order
+(test infrastructure only).
+
+Sec. 3: the GMRES polynomial is built from the harmonic Ritz values of a
+single GMRES(d) cycle, Leja ordered for stability.  The paper cites, but does
+not define, harmonic Ritz values and Leja ordering; readings used here:
+
+* Arnoldi with classical Gram-Schmidt applied twice (CGS2), started from the
+  normalised vector b.  Breakdown (h_{j+1,j} <= 1e-14 ||H||_F) truncates the
+  cycle to d_eff = j+1 steps: the Krylov space is then invariant.
+* Harmonic Ritz values: eigenvalues of H_d + |h_{d+1,d}|^2 H_d^{-H} e_d e_d^T,
+  which are the roots of the GMRES residual polynomial.
+* Leja order: first the value of largest modulus, then repeatedly the value
+  maximising sum_i log|theta - theta_i| over those already chosen.  Candidates
+  are first sorted by (Re, Im) so that exact ties go to the earlier one; an
+  exact duplicate (log = -inf) is placed last.
+
+Pins (tests/test_oracle_krylov.py): the Arnoldi relation; pi(M) b equals the
+GMRES residual obtained independently by least squares on an explicit Krylov
+basis; Cayley-Hamilton on a 1^4 lattice (n = 12); breakdown at kappa = 0;
+the Leja choice rule and permutation property.
+"""
+import numpy as np
+
+
+def arnoldi(op, b, d, breakdown_rtol=1e-14):
+    """d steps of Arnoldi (CGS2) on op from b.
+
+    Returns (V, H, beta, d_eff): V is (d_eff+1, n) with orthonormal rows (the
+    last row is zero on breakdown), H is (d_eff+1, d_eff), beta = ||b||.
+    """
+    b = np.asarray(b, dtype=np.complex128)
+    n = b.size
+    V = np.zeros((d + 1, n), dtype=np.complex128)
+    H = np.zeros((d + 1, d), dtype=np.complex128)
+    beta = np.linalg.norm(b)
+    V[0] = b / beta
+    d_eff = d
+    for j in range(d):
+        w = op(V[j])
+        Vj = V[: j + 1]
+        h = Vj.conj() @ w
+        w = w - Vj.T @ h
+        h2 = Vj.conj() @ w
+        w = w - Vj.T @ h2
+        H[: j + 1, j] = h + h2
+        hn = np.linalg.norm(w)
+        H[j + 1, j] = hn
+        if hn <= breakdown_rtol * np.linalg.norm(H[: j + 2, : j + 1]):
+            H[j + 1, j] = 0.0
+            d_eff = j + 1
+            break
+        V[j + 1] = w / hn
+    return V[: d_eff + 1], H[: d_eff + 1, :d_eff], beta, d_eff
+
+
+def harmonic_ritz(H):
+    """Harmonic Ritz values from an Arnoldi Hessenberg H of shape (d+1, d)."""
+    d = H.shape[1]
+    Hd = H[:d, :d]
+    h = H[d, d - 1]
+    A = Hd.copy()
+    if h != 0:
+        ed = np.zeros(d, dtype=np.complex128)
+        ed[-1] = 1.0
+        f = np.linalg.solve(Hd.conj().T, ed)
+        A[:, d - 1] += abs(h) ** 2 * f
+    return np.linalg.eigvals(A)
+
+
+def leja_order(theta):
+    """Leja ordering of a finite set of complex values (see module docstring)."""
+    th = np.asarray(theta, dtype=np.complex128)
+    cand = th[np.lexsort((th.imag, th.real))]
+    d = len(cand)
+    if d == 0:
+        return cand
+    chosen = [int(np.argmax(np.abs(cand)))]
+    taken = np.zeros(d, dtype=bool)
+    taken[chosen[0]] = True
+    S = np.zeros(d)
+    with np.errstate(divide="ignore"):
+        for _ in range(d - 1):
+            S = S + np.log(np.abs(cand - cand[chosen[-1]]))
+            score = np.where(taken, -np.inf, S)
+            free = np.flatnonzero(~taken)
+            best = free[int(np.argmax(score[free]))]
+            chosen.append(int(best))
+            taken[best] = True
+    return cand[chosen]
+
+
+def gmres_residual(H, beta):
+    """GMRES least-squares solution y and residual norm from H (d+1, d)."""
+    d = H.shape[1]
+    rhs = np.zeros(H.shape[0], dtype=np.complex128)
+    rhs[0] = beta
+    y, *_ = np.linalg.lstsq(H, rhs, rcond=None)
+    return y, np.linalg.norm(rhs - H @ y)
+
+
+class GmresPoly:
+    """Leja-ordered roots of one GMRES(d) cycle; degree of p is len(roots) - 1."""
+
+    def __init__(self, roots, inner=None):
+        self.roots = np.asarray(roots, dtype=np.complex128)
+        self.inner = inner            # GmresPoly of p_in for a double polynomial
+
+    @property
+    def d(self):
+        return len(self.roots)
+
+    @property
+    def degree(self):
+        if self.inner is None:
+            return self.d - 1
+        return self.inner.d * self.d - 1
+
+
+def gmres_poly(op, b, d):
+    """One GMRES(d) cycle on op from b -> (GmresPoly, d_eff, relative residual)."""
+    V, H, beta, d_eff = arnoldi(op, b, d)
+    _, res = gmres_residual(H, beta)
+    roots = leja_order(harmonic_ritz(H))
+    return GmresPoly(roots), d_eff, res / beta

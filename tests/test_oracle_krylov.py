@@ -1,0 +1,149 @@
+"""Pins of the oracle's GMRES cycle, harmonic Ritz values, Leja order and
+GMRES polynomials (Sec. 3, Sec. 5) against independent mathematics."""
+import numpy as np
+import pytest
+
+from oracle import krylov, poly
+from oracle import lattice as LT
+from oracle.philox import z4_noise
+from oracle.wilson import WilsonOp
+from paper_2402_00016_amd import inputs
+
+
+@pytest.fixture(scope="module")
+def op44():
+    dims = (4, 4, 4, 4)
+    return WilsonOp(dims, 0.115, inputs.gauge_links(dims, 0.5, seed=1))
+
+
+def _krylov_lstsq_residual(A, b, d):
+    """GMRES residual from an explicit (monomial) Krylov basis by least squares:
+    min_c ||b - A K c||, K = [b, Ab, ..., A^{d-1} b] (columns normalised)."""
+    K = [b / np.linalg.norm(b)]
+    for _ in range(d - 1):
+        w = A(K[-1])
+        K.append(w / np.linalg.norm(w))
+    K = np.stack(K, axis=1)
+    AK = np.stack([A(K[:, j]) for j in range(d)], axis=1)
+    c, *_ = np.linalg.lstsq(AK, b, rcond=None)
+    return b - AK @ c
+
+
+def test_arnoldi_relation(op44):
+    b = z4_noise(1, 0x100, 0, op44.n)
+    V, H, beta, d_eff = krylov.arnoldi(op44, b, 16)
+    assert d_eff == 16
+    MV = op44(V[:16])
+    assert np.allclose(MV.T, V.T @ H, atol=1e-12)
+    assert np.allclose(V.conj() @ V.T, np.eye(17), atol=1e-13)
+
+
+@pytest.mark.parametrize("d", [4, 8])
+def test_pi_times_b_is_gmres_residual(op44, d):
+    b = z4_noise(1, 0x100, 0, op44.n)
+    P, d_eff, rel = krylov.gmres_poly(op44, b, d)
+    r_pi = poly.apply_pi(op44, P.roots, b)
+    r_ls = _krylov_lstsq_residual(op44, b, d)
+    assert np.linalg.norm(r_pi - r_ls) < 1e-8 * np.linalg.norm(b)
+    assert abs(np.linalg.norm(r_pi) / np.linalg.norm(b) - rel) < 1e-10
+
+
+def test_pi_equals_one_minus_M_p(op44):
+    """pi(M) = 1 - M p(M): product form vs the sum expansion (Sec. 3)."""
+    b = z4_noise(1, 0x100, 0, op44.n)
+    P, _, _ = krylov.gmres_poly(op44, b, 16)
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        x = rng.standard_normal(op44.n) + 1j * rng.standard_normal(op44.n)
+        lhs = poly.apply_pi(op44, P.roots, x)
+        rhs = x - op44(poly.apply_p(op44, P.roots, x))
+        assert np.linalg.norm(lhs - rhs) < 1e-12 * np.linalg.norm(x)
+    lam = np.array([0.3 + 0.1j, 1.2 - 0.4j, 0.9])
+    pi_l = np.prod([1 - lam / t for t in P.roots], axis=0)
+    assert np.allclose(pi_l, 1 - lam * poly.eval_p(P.roots, lam), atol=1e-12)
+
+
+def test_degree_fifteen_polynomial_accuracy(op44):
+    """GMRES(16) on the 4^4 field: p has degree 15 and pi(M) b is small."""
+    b = z4_noise(1, 0x100, 0, op44.n)
+    P, d_eff, rel = krylov.gmres_poly(op44, b, 16)
+    assert P.degree == 15 and d_eff == 16
+    assert rel < 1e-3
+
+
+def test_cayley_hamilton_full_krylov():
+    """n = 12 (1^4 lattice): GMRES(12) spans everything, so p(M) = M^-1."""
+    dims = (1, 1, 1, 1)
+    U = inputs.gauge_links(dims, 0.5, seed=4)
+    op = WilsonOp(dims, 0.1, U)
+    M = LT.dense_wilson(dims, 0.1, U)
+    b = z4_noise(3, 0x100, 0, 12)
+    P, d_eff, rel = krylov.gmres_poly(op, b, 12)
+    x = np.arange(12) + 1j
+    assert np.linalg.norm(poly.apply_p(op, P.roots, x) - np.linalg.solve(M, x)) < 1e-9 * np.linalg.norm(x)
+
+
+def test_breakdown_at_kappa_zero():
+    dims = (2, 2, 2, 2)
+    op = WilsonOp(dims, 0.0, inputs.gauge_links(dims, 0.5, seed=1))
+    b = z4_noise(1, 0x100, 0, op.n)
+    P, d_eff, rel = krylov.gmres_poly(op, b, 16)
+    assert d_eff == 1
+    assert np.allclose(P.roots, [1.0])
+    x = z4_noise(2, 0, 0, op.n)
+    assert np.allclose(poly.apply_p(op, P.roots, x), x)
+
+
+def test_leja_rule_properties():
+    rng = np.random.default_rng(8)
+    th = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    L = krylov.leja_order(th)
+    assert np.allclose(np.sort_complex(L), np.sort_complex(th))       # a permutation
+    assert abs(L[0]) == np.max(np.abs(th))
+    for k in range(1, len(L)):
+        prods = [np.sum(np.log(np.abs(c - L[:k]))) for c in L[k:]]
+        assert np.argmax(prods) == 0                                   # greedy choice
+    # duplicates go last; permutation of the input does not change the order
+    th2 = np.concatenate([th[:5], th[:2]])
+    L2 = krylov.leja_order(th2)
+    assert np.allclose(np.sort_complex(L2[-2:]), np.sort_complex(th[:2]))
+    assert np.array_equal(krylov.leja_order(th[::-1]), L)
+
+
+def test_scalar_poly_matches_vector_on_plane_waves():
+    """Free field: plane waves with chi an eigenvector of the symbol are
+    eigenvectors of M, so p(M) psi = p(lambda) psi (single and double)."""
+    dims = (4, 4, 4, 4)
+    kappa = 0.12
+    op = WilsonOp(dims, kappa, inputs.unit_links(dims))
+    b = z4_noise(5, 0x100, 0, op.n)
+    P, _, _ = krylov.gmres_poly(op, b, 9)
+    D, _, _ = poly.double_poly(op, b, 4, 5)
+    p = LT.free_momenta(dims)[37]
+    w, Q = np.linalg.eig(LT.free_symbol(p, kappa))
+    chi = np.outer(Q[:, 0], [0.3, 1.0 - 0.5j, 0.2j])
+    psi = LT.plane_wave(dims, p, chi)
+    assert np.allclose(op(psi), w[0] * psi, atol=1e-12)
+    for Poly in (P, D):
+        got = poly.apply_poly(op, Poly, psi)
+        assert np.allclose(got, poly.eval_poly(Poly, w[0]) * psi, atol=1e-11)
+
+
+def test_double_polynomial_identities(op44):
+    b = z4_noise(1, 0x100, 0, op44.n)
+    D, (di, do), (ri, ro) = poly.double_poly(op44, b, 4, 4)
+    assert D.degree == 15 and poly.matvec_count(D) == 15
+    # outer residual: pi_out(phi_in(M)) b equals the GMRES residual on phi_in
+    phi = poly.phi(op44, D.inner.roots)
+    r_pi = poly.apply_pi(phi, D.roots, b)
+    r_ls = _krylov_lstsq_residual(phi, b, 4)
+    assert np.linalg.norm(r_pi - r_ls) < 1e-8 * np.linalg.norm(b)
+    # p_double(M) = p_in(M) p_out(phi_in(M)) and 1 - M p_double = pi_out(phi_in)
+    x = z4_noise(9, 0, 0, op44.n)
+    lhs = x - op44(poly.apply_poly(op44, D, x))
+    assert np.linalg.norm(lhs - poly.apply_pi(phi, D.roots, x)) < 1e-11 * np.linalg.norm(x)
+    # 16 x 16 costs 255 operator applications per vector
+    D16, _, _ = poly.double_poly(op44, b, 16, 16)
+    op44.matvecs = 0
+    poly.apply_poly(op44, D16, x)
+    assert op44.matvecs == 255 == D16.degree
