@@ -1,0 +1,232 @@
+/*
+ * mpmc.h -- C ABI of libmpmc.so: Multipolynomial Monte Carlo trace estimation
+ * of Tr(Theta M^-1) for the Wilson-Dirac matrix M on one AMD Instinct MI355X
+ * (gfx950).  Every compute step behind these calls is a HIP kernel of this
+ * library; no call falls back to the CPU.
+ *
+ * Paper: P. Lashomb, R. B. Morgan, T. Whyte, W. Wilcox, "Multipolynomial Monte
+ * Carlo Trace Estimation", Lattice 2023 (arXiv:2402.00016).  Citations below
+ * name its sections and equations.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by all calls
+ * ---------------------------------------------------------------------------
+ * Lattice:   dims = {Lx, Ly, Lz, Lt}; site s = x + Lx*(y + Ly*(z + Lz*t));
+ *            V = Lx*Ly*Lz*Lt sites, n = 12 V complex unknowns.
+ * Operator:  (M psi)(x) = psi(x) - kappa sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu)
+ *                                              + (1 + gamma_mu) U_mu(x-mu)^H psi(x-mu) ]
+ *            DeGrand-Rossi gammas, periodic space, a factor -1 on hops across
+ *            the time boundary when t_antiperiodic != 0.  M^H = g5 M g5.
+ * Theta:     MPMC_THETA_I (identity) or MPMC_THETA_G5 (gamma5 = diag(1,1,-1,-1)
+ *            in spin), the inserted operator of Tr(Theta M^-1) (Sec. 1 eq. 1).
+ * Canonical vectors: complex double, [rhs][site][spin 4][colour 3]; component
+ *            c = (s*4 + spin)*3 + colour.
+ * Internal vectors ("internal layout", what the kernels read and write):
+ *            element (s, k = spin*3 + colour, r) of a batch of nrhs vectors at
+ *            index (s*12 + k)*nrhs + r, i.e. site-major with the right-hand
+ *            sides innermost, so neighbouring lanes of a wavefront read
+ *            neighbouring right-hand sides of the same site.
+ *              MPMC_FP64  -- complex double (16 B per element)
+ *              MPMC_FP32  -- complex float  (8 B per element)
+ *              MPMC_FP16S -- complex half (4 B per element) followed, at byte
+ *                            offset align256(V*12*nrhs*4), by one float scale
+ *                            per (site, rhs) at index s*nrhs + r; the value is
+ *                            half * scale (storage format; arithmetic is FP32).
+ *            mpmc_vector_bytes() returns the buffer size.
+ * Noise:     Z(4) entries i^k, k from Philox4x32-10 (Salmon et al., SC'11):
+ *            key = (seed mod 2^32, seed >> 32), counter = (c / 64, noise index,
+ *            stream, 0), k = (word[(c % 64) / 16] >> 2 (c % 16)) & 3.
+ *            Noise vectors are regenerated from (seed, stream, index), never
+ *            stored by the caller (Sec. 1: "Z(4) noise").
+ *
+ * Memory and ownership: every pointer named x, y, b, Z, U, canon or internal
+ * is a DEVICE pointer owned by the caller (e.g. a torch tensor's data_ptr()),
+ * unless its name ends in _host.  Handles (mpmc_ctx, mpmc_poly, mpmc_defl,
+ * mpmc_net) are owned by the library and released only by their _destroy
+ * call.  The library allocates its own device workspace inside the context.
+ *
+ * Ordering: work is enqueued on the context's HIP stream.  Calls that return
+ * values through _host pointers or through d_eff/relres/iters outputs
+ * synchronise that stream before returning; the others do not.
+ *
+ * Errors: every int-returning call returns MPMC_OK (0) or a negative status;
+ * mpmc_last_error(ctx) returns a message for the last failure on ctx
+ * (mpmc_last_error(NULL) for failures of mpmc_create).  No exceptions cross
+ * the ABI.  A context is not thread-safe; calls on one context must not
+ * overlap.
+ */
+#ifndef MPMC_H
+#define MPMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpmc_ctx mpmc_ctx;
+typedef struct mpmc_poly mpmc_poly;
+typedef struct mpmc_defl mpmc_defl;
+typedef struct mpmc_net mpmc_net;
+
+enum {
+    MPMC_OK = 0,
+    MPMC_EINVAL = -1,   /* bad argument (null pointer, size, enum value)        */
+    MPMC_ENOMEM = -2,   /* device allocation failed                             */
+    MPMC_EHIP = -3,     /* HIP runtime error                                    */
+    MPMC_ENOCONV = -4,  /* iteration limit reached; outputs hold the last iterate */
+    MPMC_ENUMERIC = -5, /* NaN/Inf detected in a residual or a small eigenproblem */
+    MPMC_ESTATE = -6    /* handle belongs to another context / wrong kind       */
+};
+
+enum { MPMC_FP64 = 0, MPMC_FP32 = 1, MPMC_FP16S = 2 };
+enum { MPMC_THETA_I = 0, MPMC_THETA_G5 = 1 };
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context for one lattice.  links_host: canonical gauge field,
+ * complex double [V][4][3][3] (U[s][mu][a][b] = row a, column b of U_mu(s)),
+ * host memory, copied to the device.  stream: hipStream_t or NULL (null
+ * stream).  The Wilson-Dirac matrix itself is defined only implicitly by the
+ * paper (Sec. 1-2); its form is the one stated at the top of this header. */
+int mpmc_create(const int dims[4], double kappa, int t_antiperiodic,
+                const double *links_host, void *stream, mpmc_ctx **out);
+void mpmc_destroy(mpmc_ctx *ctx);
+const char *mpmc_last_error(const mpmc_ctx *ctx);
+int mpmc_set_stream(mpmc_ctx *ctx, void *stream);
+
+/* Bytes of an internal-layout buffer holding nrhs vectors in precision prec. */
+int mpmc_vector_bytes(const mpmc_ctx *ctx, int nrhs, int prec, size_t *bytes);
+
+/* Number of right-hand-side operator applications (Table 1's "MVP") issued on
+ * this context since creation or the last reset. */
+int mpmc_mvp_count(const mpmc_ctx *ctx, uint64_t *mvps_host);
+int mpmc_mvp_reset(mpmc_ctx *ctx);
+
+/* Canonical complex double <-> internal layout of precision prec (device to
+ * device; FP16S packing picks the per-(site, rhs) scale max|component|). */
+int mpmc_pack(mpmc_ctx *ctx, const void *canon, void *internal, int nrhs, int prec);
+int mpmc_unpack(mpmc_ctx *ctx, const void *internal, void *canon, int nrhs, int prec);
+
+/* Z(4) noise vectors with indices first .. first+nrhs-1 of (seed, stream),
+ * written in internal layout of precision prec (values are exact in every
+ * precision).  Sec. 1: the Hutchinson noise. */
+int mpmc_noise(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first,
+               int nrhs, int prec, void *internal);
+
+/* ------------------------------------------------------------------ operator */
+
+/* y = Theta * op(x), op = M (dagger = 0) or M^H (dagger = 1), for nrhs
+ * internal-layout vectors of precision prec; x and y must not overlap.  The
+ * matrix-vector product ("MVP") of Table 1. */
+int mpmc_apply_M(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec,
+                 int dagger, int theta);
+
+/* -------------------------------------------------------------- polynomials */
+
+/* One GMRES(d) cycle (Sec. 3): Arnoldi with CGS2 for d steps from the
+ * normalised Z(4) vector (seed, stream, index 0), then the harmonic Ritz values
+ * eig(H_d + |h_{d+1,d}|^2 H_d^-H e_d e_d^T) in Leja order (largest modulus
+ * first, then maximal sum of log distances), all in FP64 on the device.
+ * The polynomial p has degree d-1 and satisfies pi(M) = 1 - M p(M) with
+ * pi(M) = prod_i (1 - M/theta_i).
+ * inner == NULL: the cycle runs on M.  inner != NULL: it runs on
+ *   phi_in(M) = M p_in(M) and the result is the double polynomial
+ *   p_in(M) p_out(phi_in(M)) of degree d_in*d - 1 (Sec. 5).
+ * defl != NULL: the start vector and every Arnoldi vector are projected with
+ *   Q = I - Z U^H, so the polynomial fits the undeflated spectrum (Sec. 7).
+ * Outputs: *out (new handle), *d_eff (< d after a happy breakdown, which is not
+ * an error), *relres = ||pi(op) b|| / ||b|| from the GMRES least squares.
+ * Synchronises. */
+int mpmc_gmres_poly(mpmc_ctx *ctx, const mpmc_poly *inner, const mpmc_defl *defl,
+                    uint64_t seed, uint32_t stream, int d, mpmc_poly **out,
+                    int *d_eff, double *relres);
+
+/* Build a polynomial from given Leja-ordered roots (complex double, host),
+ * optionally as the outer factor of a double polynomial with inner. */
+int mpmc_poly_create(mpmc_ctx *ctx, const double *roots_host, int d,
+                     const mpmc_poly *inner, mpmc_poly **out);
+/* Roots (complex double, host, capacity *d on entry) and sizes.  degree is
+ * the degree of p; matvecs the MVPs per vector of mpmc_apply_poly. */
+int mpmc_poly_roots(const mpmc_poly *p, double *roots_host, int *d);
+int mpmc_poly_info(const mpmc_poly *p, int *d, int *d_inner, int *degree, int *matvecs);
+/* Scalar p(lambda) for k complex values (host in, host out): used for the
+ * deflation coefficients p_l(lambda_i) - p_{l+1}(lambda_i) (Sec. 7). */
+int mpmc_poly_eval(const mpmc_poly *p, const double *lam_host, double *out_host, int k);
+void mpmc_poly_destroy(mpmc_poly *p);
+
+/* y = p(M) x for nrhs internal-layout vectors of precision prec (FP64 or FP32):
+ * y = sum_k w_k / theta_k, w_1 = x, w_{k+1} = w_k - M w_k / theta_k (Sec. 3,
+ * with the expansion read so that pi = 1 - M p holds), and for a double
+ * polynomial p_in(M) [p_out(phi_in(M)) x] (Sec. 5).  x and y must not overlap. */
+int mpmc_apply_poly(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y,
+                    int nrhs, int prec);
+
+/* ---------------------------------------------------------------- deflation */
+
+/* Eigenpairs for deflation (Sec. 7, acceptance rule of Sec. 8): m steps of
+ * polynomial-preconditioned Arnoldi on phi_in(M) = M p_in(M) (on M itself if
+ * p_in == NULL) from the Z(4) vector (seed, stream, 0); Ritz pairs of H_m by
+ * an FP64 Hessenberg QR + inverse iteration on the device; the nev Ritz values
+ * of smallest modulus give z = V_m s (unit norm) and lambda = z^H M z; left
+ * vectors u_i = g5 z_j with lambda_j the conjugate partner of lambda_i (j = i
+ * when |Im lambda_i| < real_tol), scaled to u_i^H z_i = 1; a pair is accepted
+ * when ||M z - lambda z|| and ||M^H u - conj(lambda) u||/||u|| are both below
+ * accept_tol.  *k_out = accepted count (may be 0).  Synchronises. */
+int mpmc_deflate(mpmc_ctx *ctx, const mpmc_poly *p_in, uint64_t seed, uint32_t stream,
+                 int m, int nev, double accept_tol, double real_tol,
+                 mpmc_defl **out, int *k_out);
+/* Import k eigentriples: lam_host complex double [k]; Z, U canonical complex
+ * double [k][n] device arrays (copied). */
+int mpmc_defl_create(mpmc_ctx *ctx, const double *lam_host, const void *Z, const void *U,
+                     int k, mpmc_defl **out);
+/* Export: lam_host [k] and, if non-NULL, Z/U canonical [k][n] device buffers. */
+int mpmc_defl_export(const mpmc_defl *d, double *lam_host, void *Z, void *U, int *k);
+void mpmc_defl_destroy(mpmc_defl *d);
+
+/* -------------------------------------------------------------------- solve */
+
+/* x = M^-1 b for nrhs FP64 internal-layout vectors (Sec. 1: the main expense;
+ * Sec. 8: deflated GMRES).  Restarted GMRES(restart) with FP64 defect
+ * correction: the outer loop forms r = b - M x in FP64, the inner cycle runs
+ * in inner_prec (MPMC_FP64 or MPMC_FP32), and x += e in FP64, until every
+ * right-hand side has ||b - M x|| / ||b|| <= tol (true FP64 residual).  With
+ * defl, x starts from Z Lambda^-1 U^H b and each restart adds Z Lambda^-1 U^H r.
+ * net (may be NULL) is a right preconditioner inside the inner cycle
+ * (flexible GMRES); it changes cost, never the converged x.  Outputs (host):
+ * iters_host = total inner iterations, relres_host[nrhs] = final true
+ * relative residuals.  Returns MPMC_ENOCONV after max_outer cycles.
+ * Synchronises. */
+int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl,
+               const mpmc_net *net, int restart, double tol, int inner_prec,
+               int max_outer, int *iters_host, double *relres_host);
+
+/* ---------------------------------------------------------------- estimators */
+
+/* Samples of one Monte Carlo level (Sec. 2 eq. 2, Sec. 6, Sec. 7), for noise
+ * vectors eta_j = Z(4)(seed, stream, first + j), j < nnoise:
+ *   X_j = eta_j^H Theta A eta_j - [deflation term],
+ *   A = upper - lower, upper = M^-1 when the upper handle is NULL (solved with
+ *   mpmc_solve to solve_tol with GMRES(solve_restart), solve_inner_prec, defl
+ *   and net), lower = 0 when the lower handle is NULL.
+ * When both are polynomials and defl is given, the deflation term is
+ *   sum_i c_i (eta^H Theta z_i)(u_i^H eta), c_i = upper(lambda_i) - lower(lambda_i),
+ * and *corr_host = sum_i c_i u_i^H Theta z_i (the exact trace of the removed
+ * part); otherwise *corr_host = 0.
+ * prec: precision of the polynomial applications (MPMC_FP64 or MPMC_FP32);
+ * dot products and samples are accumulated in FP64.  Noise vectors are
+ * processed in batches of at most max_batch right-hand sides (0 = all).
+ * samples_host: complex double [nnoise]; mvps_host (may be NULL): MVPs used.
+ * Synchronises. */
+int mpmc_level_estimate(mpmc_ctx *ctx, const mpmc_poly *upper, const mpmc_poly *lower,
+                        const mpmc_defl *defl, int theta, uint64_t seed, uint32_t stream,
+                        uint64_t first, int nnoise, int prec, int max_batch,
+                        double solve_tol, int solve_restart, int solve_inner_prec,
+                        const mpmc_net *net, double *samples_host, double *corr_host,
+                        uint64_t *mvps_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MPMC_H */

@@ -1,0 +1,349 @@
+// Batched vector kernels on internal-layout vectors: the Gram-Schmidt dot
+// products and updates of the GMRES/Arnoldi cycles, norms, quadratic forms
+// eta^H Theta y of the trace estimators, precision conversions.
+//
+// Reductions are per right-hand side and always accumulate in FP64.  A
+// workgroup is a 2-D tile: x = RT consecutive right-hand sides (the innermost
+// index of the layout, so a wavefront reads one contiguous run), y = CT site
+// lanes.  Each workgroup reduces its sites in LDS and writes one partial per
+// (vector, workgroup, rhs); a second kernel adds the partials in a fixed order,
+// so results are bitwise reproducible (no atomics).
+#include <type_traits>
+
+#include "common.h"
+
+namespace {
+
+constexpr int JB = 4;   // basis vectors per thread in the multi-dot
+
+struct Tiling {
+    int RT, CT;         // block = RT x CT threads
+    int ntile;          // rhs tiles
+    int NB;             // site blocks
+};
+
+Tiling tiling(const mpmc_ctx *ctx, int N, int groups) {
+    Tiling t;
+    t.RT = N >= 64 ? 64 : (N >= 32 ? 32 : (N >= 16 ? 16 : (N >= 8 ? 8 : (N >= 4 ? 4 : (N >= 2 ? 2 : 1)))));
+    t.CT = 256 / t.RT;
+    t.ntile = (N + t.RT - 1) / t.RT;
+    const long target = (long)ctx->num_cu * 2048;   // threads in flight
+    long nb = target / (256L * t.ntile * (groups > 0 ? groups : 1));
+    const long maxnb = (ctx->V + t.CT - 1) / t.CT;
+    if (nb < 1) nb = 1;
+    if (nb > maxnb) nb = maxnb;
+    if (nb > 2048) nb = 2048;
+    t.NB = (int)nb;
+    return t;
+}
+
+template <int P>
+__device__ __forceinline__ cpx<double> ldd(const VecRef &v, long e, long si) {
+    auto x = Store<P>::ld(v.d, v.sc, e, si);
+    return mk((double)x.re, (double)x.im);
+}
+
+// partial[j][blk][r] = sum over this block's sites of conj(V_j) Theta w
+template <int P>
+__global__ __launch_bounds__(256) void k_multidot(VecRef Vb, long vstride, int vN, int nv, VecRef w, int N, long V,
+                                                  int theta, double2 *__restrict__ partial, int NB) {
+    __shared__ double2 red[JB][256];
+    const int RT = blockDim.x, CT = blockDim.y;
+    const int r = blockIdx.y * RT + threadIdx.x;
+    const int j0 = blockIdx.z * JB;
+    cpx<double> acc[JB];
+#pragma unroll
+    for (int q = 0; q < JB; ++q) acc[q] = mk(0.0, 0.0);
+    if (r < N) {
+        for (long s = (long)blockIdx.x * CT + threadIdx.y; s < V; s += (long)NB * CT) {
+            cpx<double> wv[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                wv[k] = ldd<P>(w, (s * 12 + k) * N + r, s * N + r);
+                if (theta && k >= 6) wv[k] = mk(-wv[k].re, -wv[k].im);
+            }
+#pragma unroll
+            for (int q = 0; q < JB; ++q) {
+                const int j = j0 + q;
+                if (j < nv) {
+                    VecRef vj;
+                    vj.d = (char *)Vb.d + (size_t)j * vstride * sizeof(typename Store<P>::real) * 2;
+                    vj.sc = nullptr;
+                    const int vr = vN == 1 ? 0 : r;
+#pragma unroll
+                    for (int k = 0; k < 12; ++k) acc[q] = acc[q] + conjmul(ldd<P>(vj, (s * 12 + k) * vN + vr, 0), wv[k]);
+                }
+            }
+        }
+    }
+    const int tid = threadIdx.y * RT + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < JB; ++q) red[q][tid] = make_double2(acc[q].re, acc[q].im);
+    __syncthreads();
+    for (int h = CT / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.y < h) {
+#pragma unroll
+            for (int q = 0; q < JB; ++q) {
+                double2 a = red[q][tid], b = red[q][tid + h * RT];
+                red[q][tid] = make_double2(a.x + b.x, a.y + b.y);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.y == 0 && r < N) {
+#pragma unroll
+        for (int q = 0; q < JB; ++q) {
+            const int j = j0 + q;
+            if (j < nv) partial[((long)j * NB + blockIdx.x) * N + r] = red[q][threadIdx.x];
+        }
+    }
+}
+
+// out[j*N + r] (+)= sum_b partial[j][b][r]; one workgroup per (j, r).
+__global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ partial, int NB, int N,
+                                                double2 *__restrict__ out, int accumulate, int only_real) {
+    __shared__ double2 red[256];
+    const int jr = blockIdx.x;
+    const int j = jr / N, r = jr % N;
+    double2 a = make_double2(0, 0);
+    for (int b = threadIdx.x; b < NB; b += blockDim.x) {
+        double2 v = partial[((long)j * NB + b) * N + r];
+        a.x += v.x;
+        a.y += v.y;
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[threadIdx.x].x += red[threadIdx.x + h].x;
+            red[threadIdx.x].y += red[threadIdx.x + h].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double2 v = red[0];
+        if (only_real) v.y = 0;
+        if (accumulate) {
+            out[jr].x += v.x;
+            out[jr].y += v.y;
+        } else {
+            out[jr] = v;
+        }
+    }
+}
+
+// w += sign * sum_j h[j*N + r] V_j ; optional partial[blk][r] = sum |w|^2
+template <int P>
+__global__ __launch_bounds__(256) void k_multiaxpy(VecRef Vb, long vstride, int vN, int nv, VecRef w, int N, long V,
+                                                   const double2 *__restrict__ h, double sign,
+                                                   double2 *__restrict__ partial, int NB, int ldh) {
+    using T = typename Store<P>::real;
+    __shared__ double red[256];
+    const int RT = blockDim.x, CT = blockDim.y;
+    const int r = blockIdx.y * RT + threadIdx.x;
+    double nrm = 0;
+    if (r < N) {
+        for (long s = (long)blockIdx.x * CT + threadIdx.y; s < V; s += (long)NB * CT) {
+            cpx<T> acc[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                auto v = Store<P>::ld(w.d, w.sc, (s * 12 + k) * N + r, 0);
+                acc[k] = mk((T)v.re, (T)v.im);
+            }
+            for (int j = 0; j < nv; ++j) {
+                const double2 hj = h[(long)j * ldh + r];
+                const cpx<T> c = mk((T)(sign * hj.x), (T)(sign * hj.y));
+                const void *vj = (const char *)Vb.d + (size_t)j * vstride * sizeof(T) * 2;
+                const int vr = vN == 1 ? 0 : r;
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    auto v = Store<P>::ld(vj, nullptr, (s * 12 + k) * vN + vr, 0);
+                    acc[k] = acc[k] + c * mk((T)v.re, (T)v.im);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                Store<P>::st(w.d, (s * 12 + k) * N + r, acc[k]);
+                nrm += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
+            }
+        }
+    }
+    if (!partial) return;
+    const int tid = threadIdx.y * RT + threadIdx.x;
+    red[tid] = nrm;
+    __syncthreads();
+    for (int hh = CT / 2; hh > 0; hh >>= 1) {
+        if ((int)threadIdx.y < hh) red[tid] += red[tid + hh * RT];
+        __syncthreads();
+    }
+    if (threadIdx.y == 0 && r < N) partial[(long)blockIdx.x * N + r] = make_double2(red[threadIdx.x], 0.0);
+}
+
+// y = a * x + b * y   (uniform complex coefficients)
+template <int P>
+__global__ void k_axpby(VecRef x, VecRef y, long total, double2 a, double2 b) {
+    using T = typename Store<P>::real;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    auto xv = Store<P>::ld(x.d, nullptr, e, 0);
+    auto yv = Store<P>::ld(y.d, nullptr, e, 0);
+    cpx<T> r = mk((T)a.x, (T)a.y) * mk((T)xv.re, (T)xv.im) + mk((T)b.x, (T)b.y) * mk((T)yv.re, (T)yv.im);
+    Store<P>::st(y.d, e, r);
+}
+
+// y[e] = coef[r] * x[e] (coef per rhs, FP64) ; invert_sqrt: coef = 1/sqrt(re(c)) (0 if c == 0)
+template <int P>
+__global__ void k_scale_rhs(VecRef x, VecRef y, long total, int N, const double2 *__restrict__ coef, int mode) {
+    using T = typename Store<P>::real;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const int r = (int)(e % N);
+    double2 c = coef[r];
+    if (mode == 1) {
+        const double q = c.x;
+        c = make_double2(q > 0 ? 1.0 / sqrt(q) : 0.0, 0.0);
+    } else if (mode == 2) {   // divide by c
+        const double d = c.x * c.x + c.y * c.y;
+        c = d > 0 ? make_double2(c.x / d, -c.y / d) : make_double2(0.0, 0.0);
+    }
+    auto xv = Store<P>::ld(x.d, nullptr, e, 0);
+    Store<P>::st(y.d, e, mk((T)c.x, (T)c.y) * mk((T)xv.re, (T)xv.im));
+}
+
+// precision conversion between two non-FP16S layouts, or from FP16S
+template <int PX, int PY>
+__global__ void k_convert(VecRef x, VecRef y, long V, int N) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= V * N) return;
+    const long s = t / N;
+    const int r = (int)(t - s * N);
+    using TY = typename Store<PY>::real;
+    if constexpr (PY == MPMC_FP16S) {
+        cpx<float> v[12];
+        float mx = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            auto a = Store<PX>::ld(x.d, x.sc, (s * 12 + k) * N + r, s * N + r);
+            v[k] = mk((float)a.re, (float)a.im);
+            mx = fmaxf(mx, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        }
+        const float inv = mx > 0.f ? 1.0f / mx : 0.f;
+        __half2 *d = reinterpret_cast<__half2 *>(y.d);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) d[(s * 12 + k) * N + r] = __floats2half2_rn(v[k].re * inv, v[k].im * inv);
+        y.sc[s * N + r] = mx;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            auto a = Store<PX>::ld(x.d, x.sc, (s * 12 + k) * N + r, s * N + r);
+            Store<PY>::st(y.d, (s * 12 + k) * N + r, mk((TY)a.re, (TY)a.im));
+        }
+    }
+}
+
+template <typename F>
+int dispatch_prec(mpmc_ctx *ctx, int prec, F &&f) {
+    switch (prec) {
+        case MPMC_FP64: f(std::integral_constant<int, MPMC_FP64>()); break;
+        case MPMC_FP32: f(std::integral_constant<int, MPMC_FP32>()); break;
+        default: return set_err(ctx, MPMC_EINVAL, "precision %d not supported by this kernel", prec);
+    }
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
+}  // namespace
+
+// h[j*N + r] (+)= V_j^H Theta w for j < nv.  Vb: nv vectors spaced vstride
+// elements (complex) apart.
+int blas_multi_dot(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv, const void *w, int nrhs, int prec,
+                   double *h_dev, int accumulate, int theta) {
+    if (nv <= 0) return MPMC_OK;
+    const int groups = (nv + JB - 1) / JB;
+    Tiling t = tiling(ctx, nrhs, groups);
+    double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)nv * t.NB * nrhs * sizeof(double2));
+    if (!part) return MPMC_ENOMEM;
+    dim3 blk(t.RT, t.CT), grd(t.NB, t.ntile, groups);
+    int rc = dispatch_prec(ctx, prec, [&](auto P) {
+        k_multidot<decltype(P)::value><<<grd, blk, 0, ctx->stream>>>(
+            vref(ctx, Vb, nrhs, prec), vstride, vN, nv, vref(ctx, w, nrhs, prec), nrhs, ctx->V, theta, part, t.NB);
+    });
+    RET_IF(rc);
+    k_reduce<<<nv * nrhs, 256, 0, ctx->stream>>>(part, t.NB, nrhs, (double2 *)h_dev, accumulate, 0);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
+int blas_dot(mpmc_ctx *ctx, const void *x, const void *y, int nrhs, int prec, int theta, double *out_dev) {
+    return blas_multi_dot(ctx, x, 0, nrhs, 1, y, nrhs, prec, out_dev, 0, theta);
+}
+
+int blas_norm2(mpmc_ctx *ctx, const void *x, int nrhs, int prec, double *out_dev) {
+    return blas_multi_dot(ctx, x, 0, nrhs, 1, x, nrhs, prec, out_dev, 0, 0);
+}
+
+// w += sign * sum_j h[j*ldh + r] V_j ; if norm2_dev: norm2_dev[r] = ||w_r||^2 (after update)
+int blas_multi_axpy(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv, void *w, int nrhs, int prec,
+                    const double *h_dev, int ldh, double sign, double *norm2_dev) {
+    Tiling t = tiling(ctx, nrhs, 1);
+    double2 *part = nullptr;
+    if (norm2_dev) {
+        part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)t.NB * nrhs * sizeof(double2));
+        if (!part) return MPMC_ENOMEM;
+    }
+    dim3 blk(t.RT, t.CT), grd(t.NB, t.ntile, 1);
+    int rc = dispatch_prec(ctx, prec, [&](auto P) {
+        k_multiaxpy<decltype(P)::value><<<grd, blk, 0, ctx->stream>>>(
+            vref(ctx, Vb, nrhs, prec), vstride, vN, nv, vref(ctx, w, nrhs, prec), nrhs, ctx->V,
+            (const double2 *)h_dev, sign, part, t.NB, ldh);
+    });
+    RET_IF(rc);
+    if (norm2_dev) {
+        k_reduce<<<nrhs, 256, 0, ctx->stream>>>(part, t.NB, nrhs, (double2 *)norm2_dev, 0, 1);
+        HIP_OR_RET(ctx, hipGetLastError());
+    }
+    return MPMC_OK;
+}
+
+int blas_axpby(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, double2 a, double2 b) {
+    const long total = ctx->V * 12 * nrhs;
+    return dispatch_prec(ctx, prec, [&](auto P) {
+        k_axpby<decltype(P)::value><<<grid_for(total, 256), 256, 0, ctx->stream>>>(
+            vref(ctx, x, nrhs, prec), vref(ctx, y, nrhs, prec), total, a, b);
+    });
+}
+
+// y = coef[r] x  (mode 0), y = x / sqrt(re coef[r]) (mode 1), y = x / coef[r] (mode 2)
+int blas_scale_rhs(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, const double *coef_dev, int mode) {
+    const long total = ctx->V * 12 * nrhs;
+    return dispatch_prec(ctx, prec, [&](auto P) {
+        k_scale_rhs<decltype(P)::value><<<grid_for(total, 256), 256, 0, ctx->stream>>>(
+            vref(ctx, x, nrhs, prec), vref(ctx, y, nrhs, prec), total, nrhs, (const double2 *)coef_dev, mode);
+    });
+}
+
+int blas_convert(mpmc_ctx *ctx, const void *x, int px, void *y, int py, int nrhs) {
+    const long work = ctx->V * nrhs;
+    VecRef xr = vref(ctx, x, nrhs, px), yr = vref(ctx, y, nrhs, py);
+    const unsigned g = grid_for(work, 256);
+    hipStream_t st = ctx->stream;
+#define CONV(A, B) \
+    if (px == A && py == B) k_convert<A, B><<<g, 256, 0, st>>>(xr, yr, ctx->V, nrhs); else
+    CONV(MPMC_FP64, MPMC_FP32)
+    CONV(MPMC_FP32, MPMC_FP64)
+    CONV(MPMC_FP64, MPMC_FP16S)
+    CONV(MPMC_FP16S, MPMC_FP64)
+    CONV(MPMC_FP32, MPMC_FP16S)
+    CONV(MPMC_FP16S, MPMC_FP32)
+    CONV(MPMC_FP64, MPMC_FP64)
+    CONV(MPMC_FP32, MPMC_FP32)
+    return set_err(ctx, MPMC_EINVAL, "blas_convert: %d -> %d unsupported", px, py);
+#undef CONV
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
+int blas_zero(mpmc_ctx *ctx, void *y, int nrhs, int prec) {
+    HIP_OR_RET(ctx, hipMemsetAsync(y, 0, vec_bytes(ctx, nrhs, prec), ctx->stream));
+    return MPMC_OK;
+}

@@ -1,0 +1,318 @@
+// Internal declarations shared by the HIP sources of libmpmc.so (gfx950).
+// Nothing here is part of the C ABI; the ABI is include/mpmc.h.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/mpmc.h"
+
+#define MPMC_API extern "C" __attribute__((visibility("default")))
+
+// ---------------------------------------------------------------- context --
+
+struct WsBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct mpmc_ctx {
+    int dims[4];
+    long V;            // sites
+    long n;            // 12 V complex unknowns
+    double kappa;
+    int t_antiperiodic;
+    hipStream_t stream;
+    int device;
+    // device data
+    double *links64;   // canonical [V][4][3][3] complex double
+    float *links32;    // same, complex float
+    int *nbr;          // [V][8]: forward mu=0..3 then backward mu=0..3; bit 31 = time-boundary sign
+    uint64_t mvps;     // right-hand-side operator applications issued
+    std::string err;
+    std::vector<WsBuf> ws;      // fixed workspace slots (reduction partials, dense scratch)
+    std::vector<WsBuf> stack;   // scoped scratch buffers (see Scratch)
+    int top;
+    int num_cu;
+};
+
+struct mpmc_poly {
+    const mpmc_ctx *ctx;
+    std::vector<double> roots;  // 2*d doubles (complex), Leja ordered
+    int d;
+    const mpmc_poly *inner;     // not owned; the caller keeps p_in alive
+};
+
+struct mpmc_defl {
+    const mpmc_ctx *ctx;
+    int k;
+    std::vector<double> lam;    // 2*k doubles (complex)
+    double *Z;                  // device FP64 internal layout, k single-rhs vectors [k][n]
+    double *U;                  // same
+    double *lam_dev;            // device copy of lam
+};
+
+// Fixed workspace slots, used only inside one kernel launch sequence.
+enum WsSlot {
+    WS_PARTIAL = 0,   // reduction partials
+    WS_DENSE,         // small dense FP64 matrices
+    WS_NSLOTS
+};
+
+void *ws_get(mpmc_ctx *ctx, int slot, size_t bytes);   // nullptr on failure (ctx->err set)
+
+// Scoped scratch: buffers taken from the context's stack are released when
+// the Scratch object is destroyed.  Buffers are kept between calls, so a
+// repeated call sequence allocates only the first time.
+void *stack_get(mpmc_ctx *ctx, size_t bytes);
+struct Scratch {
+    mpmc_ctx *ctx;
+    int base;
+    explicit Scratch(mpmc_ctx *c) : ctx(c), base(c->top) {}
+    ~Scratch() { ctx->top = base; }
+    void *get(size_t bytes) { return stack_get(ctx, bytes); }
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+};
+
+int set_err(const mpmc_ctx *ctx, int code, const char *fmt, ...);
+
+#define HIP_OR_RET(ctx, call)                                                              \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return set_err((ctx), MPMC_EHIP, "%s: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                           __FILE__, __LINE__);                                            \
+    } while (0)
+
+#define RET_IF(x)            \
+    do {                     \
+        int rc_ = (x);       \
+        if (rc_ != MPMC_OK)  \
+            return rc_;      \
+    } while (0)
+
+static inline int prec_ok(int prec) { return prec == MPMC_FP64 || prec == MPMC_FP32 || prec == MPMC_FP16S; }
+
+size_t vec_bytes(const mpmc_ctx *ctx, int nrhs, int prec);
+size_t fp16s_scale_offset(const mpmc_ctx *ctx, int nrhs);
+
+// ------------------------------------------------------- complex helpers --
+
+template <typename T>
+struct cpx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> mk(T r, T i) {
+    cpx<T> c;
+    c.re = r;
+    c.im = i;
+    return c;
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator+(cpx<T> a, cpx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator-(cpx<T> a, cpx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator*(cpx<T> a, cpx<T> b) {
+    return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> operator*(T s, cpx<T> a) { return mk(s * a.re, s * a.im); }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> conjmul(cpx<T> a, cpx<T> b) {  // conj(a) * b
+    return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re);
+}
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> cconj(cpx<T> a) { return mk(a.re, -a.im); }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> times_i(cpx<T> a) { return mk(-a.im, a.re); }
+template <typename T>
+__host__ __device__ __forceinline__ cpx<T> times_mi(cpx<T> a) { return mk(a.im, -a.re); }
+
+// ------------------------------------------------- storage of one element --
+// Element (s, k, r) of an internal-layout batch lives at e = (s*12 + k)*N + r;
+// FP16S vectors keep one FP32 scale per (s, r) at sc = s*N + r.
+
+template <int P>
+struct Store;
+
+template <>
+struct Store<MPMC_FP64> {
+    using real = double;
+    __device__ static cpx<double> ld(const void *d, const float *, long e, long) {
+        double2 v = reinterpret_cast<const double2 *>(d)[e];
+        return mk(v.x, v.y);
+    }
+    __device__ static void st(void *d, long e, cpx<double> v) {
+        reinterpret_cast<double2 *>(d)[e] = make_double2(v.re, v.im);
+    }
+};
+
+template <>
+struct Store<MPMC_FP32> {
+    using real = float;
+    __device__ static cpx<float> ld(const void *d, const float *, long e, long) {
+        float2 v = reinterpret_cast<const float2 *>(d)[e];
+        return mk(v.x, v.y);
+    }
+    __device__ static void st(void *d, long e, cpx<float> v) {
+        reinterpret_cast<float2 *>(d)[e] = make_float2(v.re, v.im);
+    }
+};
+
+template <>
+struct Store<MPMC_FP16S> {
+    using real = float;
+    __device__ static cpx<float> ld(const void *d, const float *sc, long e, long si) {
+        __half2 h = reinterpret_cast<const __half2 *>(d)[e];
+        float s = sc[si];
+        float2 f = __half22float2(h);
+        return mk(f.x * s, f.y * s);
+    }
+};
+
+// Host-side view of a vector batch: data pointer plus the FP16S scale array.
+struct VecRef {
+    void *d;
+    float *sc;
+};
+
+VecRef vref(const mpmc_ctx *ctx, const void *p, int nrhs, int prec);
+
+// ------------------------------------------------------------- Philox --
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), written from the
+// published round function: two 32x32->64 multiplies per round, key bumped
+// by the Weyl constants between rounds.
+
+struct u32x4 {
+    uint32_t v[4];
+};
+
+__device__ __forceinline__ u32x4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t lo0 = 0xD2511F53u * c0;
+        uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        uint32_t lo1 = 0xCD9E8D57u * c2;
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+    }
+    u32x4 o;
+    o.v[0] = c0;
+    o.v[1] = c1;
+    o.v[2] = c2;
+    o.v[3] = c3;
+    return o;
+}
+
+// Z(4) symbols of the 12 components of site s for noise index idx: bits 2k..2k+1
+// of the returned word hold the symbol of component s*12 + k.
+__device__ __forceinline__ uint32_t z4_site_symbols(uint64_t seed, uint32_t stream, uint32_t idx, long s) {
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const long c0 = s * 12;
+    const uint32_t b0 = (uint32_t)(c0 >> 6);
+    const uint32_t b1 = (uint32_t)((c0 + 11) >> 6);
+    u32x4 w0 = philox10(b0, idx, stream, 0u, k0, k1);
+    u32x4 w1 = w0;
+    if (b1 != b0) w1 = philox10(b1, idx, stream, 0u, k0, k1);
+    uint32_t out = 0;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const long c = c0 + k;
+        const u32x4 &w = ((uint32_t)(c >> 6) == b0) ? w0 : w1;
+        const int j = (int)(c & 63);
+        const uint32_t sym = (w.v[j >> 4] >> (2 * (j & 15))) & 3u;
+        out |= sym << (2 * k);
+    }
+    return out;
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> z4_value(uint32_t sym) {
+    // i^sym
+    return mk<T>(sym == 0 ? T(1) : (sym == 2 ? T(-1) : T(0)), sym == 1 ? T(1) : (sym == 3 ? T(-1) : T(0)));
+}
+
+// ------------------------------------------------------------ launches --
+
+static inline unsigned grid_for(long work, int block) {
+    return (unsigned)((work + block - 1) / block);
+}
+
+// Map the hardware workgroup id to a logical tile id so that each of the 8
+// XCDs (which receive workgroups round-robin) processes one contiguous range
+// of tiles, keeping stencil neighbours in the same XCD's L2.
+__device__ __forceinline__ unsigned xcd_tile(unsigned bid, unsigned nblocks) {
+    const unsigned nx = 8;
+    const unsigned per = nblocks / nx, rem = nblocks % nx;
+    const unsigned xcd = bid % nx, slot = bid / nx;
+    // XCD x receives per (+1 if x < rem) workgroups and owns the tile range
+    // starting at x*per + min(x, rem).
+    return xcd * per + (xcd < rem ? xcd : rem) + slot;
+}
+
+// ---------------------------------------------------- cross-file host API --
+// context.hip
+int launch_noise(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, int prec, void *internal);
+
+// blas.hip.  Basis vectors Vb[j] are spaced vstride complex elements apart and
+// hold vN right-hand sides (vN == nrhs, or vN == 1 for single vectors that are
+// shared by all right-hand sides, e.g. deflation vectors).
+int blas_multi_dot(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv, const void *w, int nrhs,
+                   int prec, double *h_dev, int accumulate, int theta);
+int blas_dot(mpmc_ctx *ctx, const void *x, const void *y, int nrhs, int prec, int theta, double *out_dev);
+int blas_norm2(mpmc_ctx *ctx, const void *x, int nrhs, int prec, double *out_dev);
+int blas_multi_axpy(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv, void *w, int nrhs, int prec,
+                    const double *h_dev, int ldh, double sign, double *norm2_dev);
+int blas_axpby(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, double2 a, double2 b);
+int blas_scale_rhs(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, const double *coef_dev, int mode);
+int blas_convert(mpmc_ctx *ctx, const void *x, int px, void *y, int py, int nrhs);
+int blas_zero(mpmc_ctx *ctx, void *y, int nrhs, int prec);
+
+// wilson.hip: out = alpha a + beta Theta op(b); y += gamma out (y may be null)
+int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, void *y, int nrhs, int prec,
+                       double2 alpha, double2 beta, double2 gamma, int dagger, int theta);
+
+// dense.hip
+int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, double beta, double *roots_dev,
+                        double *info_dev);
+int dense_hess_eigs(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, double *ev_dev, double *info_dev);
+int dense_inverse_iteration(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, const double *mu_dev, int k,
+                            double *Y_dev);
+int dense_givens_step(mpmc_ctx *ctx, double *H, int ldc, int j, int N, double *cs, double *g, double *res);
+int dense_backsolve(mpmc_ctx *ctx, const double *H, int ldc, int k, int N, const double *g, double *y);
+
+// krylov.hip
+int poly_apply_internal(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec);
+int poly_matvecs(const mpmc_poly *p);
+void poly_eval_host(const mpmc_poly *p, const double *lam, double *out, int k);
+
+// deflate.hip (FP64, nrhs internal-layout vectors x)
+//   c[i*nrhs + r] = u_i^H x_r (divided by lambda_i if divide_by_lambda)
+int defl_coeffs(mpmc_ctx *ctx, const mpmc_defl *d, const void *x, int nrhs, double *c_dev, int divide_by_lambda);
+//   x_r += sign * sum_i c[i*nrhs + r] z_i
+int defl_add(mpmc_ctx *ctx, const mpmc_defl *d, const double *c_dev, void *x, int nrhs, double sign);
+//   x <- (I - Z U^H) x
+int defl_project(mpmc_ctx *ctx, const mpmc_defl *d, void *x, int nrhs);
+
+// solve.hip
+int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl, const mpmc_net *net,
+                   int restart, double tol, int inner_prec, int max_outer, int *iters, double *relres_host);

@@ -1,0 +1,310 @@
+// GMRES polynomials (Sec. 3) and double polynomials (Sec. 5).
+//
+// mpmc_gmres_poly runs one GMRES(d) cycle on the device: d Arnoldi steps with
+// classical Gram-Schmidt applied twice (two fused dot/update passes per step,
+// FP64 sums), breakdown detection on the device (no host round trip per
+// step), then the harmonic Ritz values and their Leja order in one FP64
+// single-wavefront kernel.  mpmc_apply_poly evaluates
+//     p(M) x = sum_k w_k / theta_k,  w_1 = x,  w_{k+1} = w_k - M w_k / theta_k
+// with one fused Wilson kernel per step (w update and y accumulation in the
+// same pass), and the double polynomial as p_in(M) [p_out(phi_in(M)) x].
+#include <cmath>
+#include <complex>
+
+#include "common.h"
+
+// ------------------------------------------------------------ Arnoldi --
+
+// After the second Gram-Schmidt pass: H(:, j) += h2, h_{j+1,j} = ||w||,
+// breakdown test against the running Frobenius norm, coefficient 1/h for the
+// new basis vector (0 after a breakdown, which keeps later vectors zero).
+__global__ void k_arnoldi_finalize(double2 *Hcol, const double2 *h2, int j, const double2 *nrm2, double *state,
+                                   double2 *scale) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // state[0] = running ||H||_F^2, state[1] = d_eff (or -1 while none)
+    double fro = state[0];
+    for (int i = 0; i <= j; ++i) {
+        Hcol[i].x += h2[i].x;
+        Hcol[i].y += h2[i].y;
+        fro += Hcol[i].x * Hcol[i].x + Hcol[i].y * Hcol[i].y;
+    }
+    const double hn = sqrt(fmax(nrm2[0].x, 0.0));
+    fro += hn * hn;
+    state[0] = fro;
+    const bool broken = state[1] >= 0;
+    if (broken || hn <= 1e-14 * sqrt(fro) || !(hn == hn)) {
+        Hcol[j + 1] = make_double2(0.0, 0.0);
+        if (!broken) state[1] = j + 1;
+        scale[0] = make_double2(0.0, 0.0);
+    } else {
+        Hcol[j + 1] = make_double2(hn, 0.0);
+        scale[0] = make_double2(1.0 / hn, 0.0);
+    }
+}
+
+__global__ void k_arnoldi_init(double *state, double2 *scale, const double2 *nrm2) {
+    state[0] = 0.0;
+    state[1] = -1.0;
+    const double b = sqrt(fmax(nrm2[0].x, 0.0));
+    scale[0] = make_double2(b > 0 ? 1.0 / b : 0.0, 0.0);
+    state[2] = b;
+}
+
+struct OpDesc {
+    const mpmc_poly *inner;   // nullptr: M; else phi_in(M) = M p_in(M)
+    const mpmc_defl *defl;    // project each new vector with Q = I - Z U^H
+};
+
+static int apply_op(mpmc_ctx *ctx, const OpDesc &op, const void *x, void *y) {
+    Scratch S(ctx);
+    if (!op.inner) {
+        RET_IF(wilson_launch_full(ctx, x, nullptr, y, nullptr, 1, MPMC_FP64, make_double2(0, 0),
+                                  make_double2(1, 0), make_double2(0, 0), 0, 0));
+    } else {
+        void *t = S.get(vec_bytes(ctx, 1, MPMC_FP64));
+        if (!t) return MPMC_ENOMEM;
+        RET_IF(poly_apply_internal(ctx, op.inner, x, t, 1, MPMC_FP64));
+        RET_IF(wilson_launch_full(ctx, t, nullptr, y, nullptr, 1, MPMC_FP64, make_double2(0, 0),
+                                  make_double2(1, 0), make_double2(0, 0), 0, 0));
+    }
+    if (op.defl) RET_IF(defl_project(ctx, op.defl, y, 1));
+    return MPMC_OK;
+}
+
+// d Arnoldi steps (FP64, one rhs) from b (overwritten by v_0).  V: (d+1) vectors
+// of n complex doubles, H: column-major (d+1) x d, ld = d+1.  state (device):
+// [0] ||H||_F^2, [1] d_eff or -1, [2] ||b||.
+int arnoldi_run(mpmc_ctx *ctx, const OpDesc &op, double *V, double *H, int d, double *state, Scratch &S) {
+    const long n = ctx->n;
+    double2 *sc = (double2 *)S.get(sizeof(double2) * (d + 8));
+    double2 *h2 = (double2 *)S.get(sizeof(double2) * (d + 8));
+    void *w = S.get(vec_bytes(ctx, 1, MPMC_FP64));
+    if (!sc || !h2 || !w) return MPMC_ENOMEM;
+    HIP_OR_RET(ctx, hipMemsetAsync(H, 0, sizeof(double2) * (size_t)(d + 1) * d, ctx->stream));
+    if (op.defl) RET_IF(defl_project(ctx, op.defl, V, 1));
+    RET_IF(blas_norm2(ctx, V, 1, MPMC_FP64, (double *)sc));
+    k_arnoldi_init<<<1, 1, 0, ctx->stream>>>(state, sc + 1, sc);
+    HIP_OR_RET(ctx, hipGetLastError());
+    RET_IF(blas_scale_rhs(ctx, V, V, 1, MPMC_FP64, (double *)(sc + 1), 0));
+    for (int j = 0; j < d; ++j) {
+        double *vj = V + 2 * (size_t)j * n;
+        double *vj1 = V + 2 * (size_t)(j + 1) * n;
+        double *Hcol = H + 2 * (size_t)j * (d + 1);
+        RET_IF(apply_op(ctx, op, vj, w));
+        // CGS pass 1: H(:, j) = V^H w ; w -= V H(:, j)
+        RET_IF(blas_multi_dot(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, Hcol, 0, 0));
+        RET_IF(blas_multi_axpy(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, Hcol, 1, -1.0, nullptr));
+        // CGS pass 2 with the norm fused into the update
+        RET_IF(blas_multi_dot(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, (double *)h2, 0, 0));
+        RET_IF(blas_multi_axpy(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, (double *)h2, 1, -1.0, (double *)sc));
+        k_arnoldi_finalize<<<1, 1, 0, ctx->stream>>>((double2 *)Hcol, h2, j, sc, state, sc + 1);
+        HIP_OR_RET(ctx, hipGetLastError());
+        RET_IF(blas_scale_rhs(ctx, w, vj1, 1, MPMC_FP64, (double *)(sc + 1), 0));
+    }
+    return MPMC_OK;
+}
+
+// ---------------------------------------------------------- handles --
+
+static int validate_poly(const mpmc_ctx *ctx, const mpmc_poly *p) {
+    if (!p) return set_err(ctx, MPMC_EINVAL, "null polynomial");
+    if (p->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "polynomial belongs to another context");
+    if (p->inner && p->inner->inner) return set_err(ctx, MPMC_EINVAL, "only double (not triple) polynomials");
+    return MPMC_OK;
+}
+
+int poly_matvecs(const mpmc_poly *p) {
+    if (!p->inner) return p->d - 1;
+    return (p->d - 1) * p->inner->d + (p->inner->d - 1);
+}
+
+static std::complex<double> eval_single(const std::vector<double> &roots, int d, std::complex<double> lam) {
+    std::complex<double> w(1.0, 0.0);
+    std::complex<double> th0(roots[0], roots[1]);
+    std::complex<double> y = w / th0;
+    for (int k = 0; k + 1 < d; ++k) {
+        std::complex<double> th(roots[2 * k], roots[2 * k + 1]);
+        std::complex<double> thn(roots[2 * k + 2], roots[2 * k + 3]);
+        w = w * (1.0 - lam / th);
+        y += w / thn;
+    }
+    return y;
+}
+
+void poly_eval_host(const mpmc_poly *p, const double *lam, double *out, int k) {
+    for (int i = 0; i < k; ++i) {
+        std::complex<double> l(lam[2 * i], lam[2 * i + 1]), v;
+        if (!p->inner) {
+            v = eval_single(p->roots, p->d, l);
+        } else {
+            std::complex<double> pin = eval_single(p->inner->roots, p->inner->d, l);
+            v = pin * eval_single(p->roots, p->d, l * pin);
+        }
+        out[2 * i] = v.real();
+        out[2 * i + 1] = v.imag();
+    }
+}
+
+MPMC_API int mpmc_poly_create(mpmc_ctx *ctx, const double *roots_host, int d, const mpmc_poly *inner,
+                              mpmc_poly **out) {
+    if (!ctx) return MPMC_EINVAL;
+    if (!roots_host || d < 1 || !out) return set_err(ctx, MPMC_EINVAL, "mpmc_poly_create: bad argument");
+    if (inner) RET_IF(validate_poly(ctx, inner));
+    if (inner && inner->inner) return set_err(ctx, MPMC_EINVAL, "mpmc_poly_create: inner must be single");
+    for (int i = 0; i < d; ++i)
+        if (!(std::isfinite(roots_host[2 * i]) && std::isfinite(roots_host[2 * i + 1])) ||
+            (roots_host[2 * i] == 0 && roots_host[2 * i + 1] == 0))
+            return set_err(ctx, MPMC_EINVAL, "mpmc_poly_create: root %d is zero or not finite", i);
+    mpmc_poly *p = new mpmc_poly();
+    p->ctx = ctx;
+    p->d = d;
+    p->roots.assign(roots_host, roots_host + 2 * d);
+    p->inner = inner;
+    *out = p;
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_poly_roots(const mpmc_poly *p, double *roots_host, int *d) {
+    if (!p || !d) return MPMC_EINVAL;
+    if (roots_host) {
+        if (*d < p->d) return set_err(p->ctx, MPMC_EINVAL, "mpmc_poly_roots: capacity %d < %d", *d, p->d);
+        for (int i = 0; i < 2 * p->d; ++i) roots_host[i] = p->roots[i];
+    }
+    *d = p->d;
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_poly_info(const mpmc_poly *p, int *d, int *d_inner, int *degree, int *matvecs) {
+    if (!p) return MPMC_EINVAL;
+    if (d) *d = p->d;
+    if (d_inner) *d_inner = p->inner ? p->inner->d : 0;
+    if (degree) *degree = p->inner ? p->inner->d * p->d - 1 : p->d - 1;
+    if (matvecs) *matvecs = poly_matvecs(p);
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_poly_eval(const mpmc_poly *p, const double *lam_host, double *out_host, int k) {
+    if (!p || (k > 0 && (!lam_host || !out_host)) || k < 0) return MPMC_EINVAL;
+    poly_eval_host(p, lam_host, out_host, k);
+    return MPMC_OK;
+}
+
+MPMC_API void mpmc_poly_destroy(mpmc_poly *p) { delete p; }
+
+// ------------------------------------------------------ gmres_poly --
+
+MPMC_API int mpmc_gmres_poly(mpmc_ctx *ctx, const mpmc_poly *inner, const mpmc_defl *defl, uint64_t seed,
+                             uint32_t stream, int d, mpmc_poly **out, int *d_eff, double *relres) {
+    if (!ctx) return MPMC_EINVAL;
+    if (!out || d < 1 || d > 500) return set_err(ctx, MPMC_EINVAL, "mpmc_gmres_poly: bad argument (d=%d)", d);
+    if (inner) RET_IF(validate_poly(ctx, inner));
+    if (inner && inner->inner) return set_err(ctx, MPMC_EINVAL, "mpmc_gmres_poly: inner must be a single polynomial");
+    if (defl && defl->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "deflation set belongs to another context");
+    *out = nullptr;
+    Scratch S(ctx);
+    const long n = ctx->n;
+    double *V = (double *)S.get(sizeof(double2) * (size_t)(d + 1) * n);
+    double *H = (double *)S.get(sizeof(double2) * (size_t)(d + 1) * d);
+    double *state = (double *)S.get(sizeof(double) * 8);
+    double *roots = (double *)S.get(sizeof(double2) * (d + 2));
+    double *info = (double *)S.get(sizeof(double) * 4);
+    if (!V || !H || !state || !roots || !info) return MPMC_ENOMEM;
+    RET_IF(launch_noise(ctx, seed, stream, 0, 1, MPMC_FP64, V));
+    OpDesc op{inner, (defl && defl->k > 0) ? defl : nullptr};
+    RET_IF(arnoldi_run(ctx, op, V, H, d, state, S));
+    double hs[3];
+    HIP_OR_RET(ctx, hipMemcpyAsync(hs, state, sizeof hs, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    const int de = hs[1] >= 0 ? (int)hs[1] : d;
+    const double beta = hs[2];
+    if (!(beta > 0)) return set_err(ctx, MPMC_ENUMERIC, "mpmc_gmres_poly: zero start vector");
+    RET_IF(dense_harmonic_leja(ctx, H, d + 1, de, beta, roots, info));
+    std::vector<double> r(2 * de);
+    double inf[2];
+    HIP_OR_RET(ctx, hipMemcpyAsync(r.data(), roots, sizeof(double) * 2 * de, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_RET(ctx, hipMemcpyAsync(inf, info, sizeof inf, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    if (inf[1] != 0) return set_err(ctx, MPMC_ENUMERIC, "mpmc_gmres_poly: small eigenproblem failed (%g)", inf[1]);
+    mpmc_poly *p = new mpmc_poly();
+    p->ctx = ctx;
+    p->d = de;
+    p->roots = r;
+    p->inner = inner;
+    *out = p;
+    if (d_eff) *d_eff = de;
+    if (relres) *relres = de < d ? 0.0 : inf[0];
+    return MPMC_OK;
+}
+
+// ------------------------------------------------------ apply_poly --
+
+static int apply_single(mpmc_ctx *ctx, const std::vector<double> &roots, int d, const void *x, void *y, int nrhs,
+                        int prec) {
+    Scratch S(ctx);
+    auto th = [&](int k) { return std::complex<double>(roots[2 * k], roots[2 * k + 1]); };
+    auto inv = [&](int k) {
+        std::complex<double> v = 1.0 / th(k);
+        return make_double2(v.real(), v.imag());
+    };
+    // y = x / theta_1
+    {
+        double2 c = inv(0);
+        RET_IF(blas_axpby(ctx, x, y, nrhs, prec, c, make_double2(0, 0)));
+    }
+    if (d == 1) return MPMC_OK;
+    void *wa = S.get(vec_bytes(ctx, nrhs, prec));
+    void *wb = S.get(vec_bytes(ctx, nrhs, prec));
+    if (!wa || !wb) return MPMC_ENOMEM;
+    const void *cur = x;
+    for (int k = 0; k + 1 < d; ++k) {
+        void *nxt = (cur == wa) ? wb : wa;
+        double2 c = inv(k);
+        RET_IF(wilson_launch_full(ctx, cur, cur, nxt, y, nrhs, prec, make_double2(1, 0), make_double2(-c.x, -c.y),
+                                  inv(k + 1), 0, 0));
+        cur = nxt;
+    }
+    return MPMC_OK;
+}
+
+int poly_apply_internal(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec) {
+    if (prec != MPMC_FP64 && prec != MPMC_FP32)
+        return set_err(ctx, MPMC_EINVAL, "polynomial application supports FP64 and FP32 storage");
+    Scratch S(ctx);
+    if (!p->inner) return apply_single(ctx, p->roots, p->d, x, y, nrhs, prec);
+    // u = p_out(phi_in) x : u = x/v_1, w_{k+1} = w_k - phi(w_k)/v_k, phi(w) = M p_in(M) w
+    const size_t vb = vec_bytes(ctx, nrhs, prec);
+    void *u = S.get(vb);
+    void *t = S.get(vb);
+    void *wa = S.get(vb);
+    void *wb = S.get(vb);
+    if (!u || !t || !wa || !wb) return MPMC_ENOMEM;
+    auto inv = [&](int k) {
+        std::complex<double> v = 1.0 / std::complex<double>(p->roots[2 * k], p->roots[2 * k + 1]);
+        return make_double2(v.real(), v.imag());
+    };
+    RET_IF(blas_axpby(ctx, x, u, nrhs, prec, inv(0), make_double2(0, 0)));
+    const void *cur = x;
+    for (int k = 0; k + 1 < p->d; ++k) {
+        void *nxt = (cur == wa) ? wb : wa;
+        RET_IF(apply_single(ctx, p->inner->roots, p->inner->d, cur, t, nrhs, prec));
+        double2 c = inv(k);
+        RET_IF(wilson_launch_full(ctx, t, cur, nxt, u, nrhs, prec, make_double2(1, 0), make_double2(-c.x, -c.y),
+                                  inv(k + 1), 0, 0));
+        cur = nxt;
+    }
+    return apply_single(ctx, p->inner->roots, p->inner->d, u, y, nrhs, prec);
+}
+
+MPMC_API int mpmc_apply_poly(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec) {
+    if (!ctx) return MPMC_EINVAL;
+    RET_IF(validate_poly(ctx, p));
+    if (!x || !y || nrhs < 1) return set_err(ctx, MPMC_EINVAL, "mpmc_apply_poly: bad argument");
+    if (x == y) return set_err(ctx, MPMC_EINVAL, "mpmc_apply_poly: x and y must not alias");
+    return poly_apply_internal(ctx, p, x, y, nrhs, prec);
+}
+
+// Arnoldi on M (inner == nullptr) or on phi_in(M) = M p_in(M), for the deflation build.
+int arnoldi_run_ext(mpmc_ctx *ctx, const mpmc_poly *inner, double *V, double *H, int d, double *state, Scratch &S) {
+    OpDesc op{inner, nullptr};
+    return arnoldi_run(ctx, op, V, H, d, state, S);
+}

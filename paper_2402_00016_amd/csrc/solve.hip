@@ -1,0 +1,172 @@
+// Main solves M x = b for a batch of right-hand sides (Sec. 1: the main
+// expense of the method; Sec. 8: deflated GMRES).
+//
+// Mixed-precision defect correction: the outer loop keeps x and r = b - M x in
+// FP64 and tests the TRUE residual; each inner restarted GMRES(m) cycle runs in
+// the inner precision (FP64 or FP32 storage, FP64 dot products) on r and
+// returns a correction e, x += e.  All right-hand sides advance together: one
+// Wilson launch, one Gram-Schmidt dot launch and one update launch per inner
+// iteration serve the whole batch, and the per-rhs Hessenberg/Givens state
+// lives on the device.  With a deflation set, x starts at Z Lambda^-1 U^H b and
+// each restart adds Z Lambda^-1 U^H r (projection of the small eigen-components).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+// H column j (rows 0..j) += h2; h_{j+1,j} = sqrt(nrm2); scale = 1/h_{j+1,j}
+__global__ void k_finalize_batch(double2 *Hcol, const double2 *h2, int j, int N, const double2 *nrm2,
+                                 double2 *scale) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    for (int i = 0; i <= j; ++i) {
+        Hcol[(long)i * N + r].x += h2[(long)i * N + r].x;
+        Hcol[(long)i * N + r].y += h2[(long)i * N + r].y;
+    }
+    const double hn = sqrt(fmax(nrm2[r].x, 0.0));
+    Hcol[(long)(j + 1) * N + r] = make_double2(hn, 0.0);
+    scale[r] = make_double2(hn > 1e-290 ? 1.0 / hn : 0.0, 0.0);
+}
+
+__global__ void k_init_g(double2 *g, int m, int N, const double2 *rn2) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)(m + 1) * N) return;
+    const int r = (int)(t % N);
+    g[t] = t < N ? make_double2(sqrt(fmax(rn2[r].x, 0.0)), 0.0) : make_double2(0.0, 0.0);
+}
+
+}  // namespace
+
+int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl *defl, const mpmc_net *net,
+                   int m, double tol, int inner_prec, int max_outer, int *iters_out, double *relres_host) {
+    if (net) return set_err(ctx, MPMC_EINVAL, "mpmc_solve: learned preconditioner not available in this build");
+    if (inner_prec != MPMC_FP64 && inner_prec != MPMC_FP32)
+        return set_err(ctx, MPMC_EINVAL, "mpmc_solve: inner precision must be FP64 or FP32");
+    Scratch S(ctx);
+    const long n = ctx->n;
+    const size_t vb64 = vec_bytes(ctx, N, MPMC_FP64), vbi = vec_bytes(ctx, N, inner_prec);
+    const long vstride = n * N;   // complex elements between basis vectors
+    double *r = (double *)S.get(vb64);
+    void *V = S.get(vbi * (m + 1));
+    void *w = S.get(vbi);
+    void *e = S.get(vbi);
+    double *H = (double *)S.get(sizeof(double2) * (size_t)(m + 1) * (m + 1) * N);
+    double *h2 = (double *)S.get(sizeof(double2) * (size_t)(m + 1) * N);
+    double *cs = (double *)S.get(sizeof(double2) * (size_t)2 * m * N);
+    double *g = (double *)S.get(sizeof(double2) * (size_t)(m + 1) * N);
+    double *y = (double *)S.get(sizeof(double2) * (size_t)m * N);
+    double *res = (double *)S.get(sizeof(double) * N);
+    double *sc = (double *)S.get(sizeof(double2) * 4 * N);   // [0..N) norms, [N..2N) scales
+    double *dc = defl && defl->k ? (double *)S.get(sizeof(double2) * (size_t)defl->k * N) : nullptr;
+    if (!r || !V || !w || !e || !H || !h2 || !cs || !g || !y || !res || !sc || (defl && defl->k && !dc))
+        return MPMC_ENOMEM;
+    double *nrm = sc, *scale = sc + 2 * N;
+
+    std::vector<double> bn2(2 * N), rn2(2 * N), resh(N);
+    RET_IF(blas_norm2(ctx, b, N, MPMC_FP64, nrm));
+    HIP_OR_RET(ctx, hipMemcpyAsync(bn2.data(), nrm, sizeof(double2) * N, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_RET(ctx, hipMemsetAsync(x, 0, vb64, ctx->stream));
+    if (dc) {
+        RET_IF(defl_coeffs(ctx, defl, b, N, dc, 1));
+        RET_IF(defl_add(ctx, defl, dc, x, N, 1.0));
+    }
+    HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < N; ++i)
+        if (!std::isfinite(bn2[2 * i])) return set_err(ctx, MPMC_ENUMERIC, "mpmc_solve: rhs %d is not finite", i);
+
+    int total = 0;
+    bool converged = false;
+    std::vector<double> rel(N, 1.0);
+    auto true_residual = [&]() -> int {
+        RET_IF(wilson_launch_full(ctx, x, b, r, nullptr, N, MPMC_FP64, make_double2(1, 0), make_double2(-1, 0),
+                                  make_double2(0, 0), 0, 0));
+        RET_IF(blas_norm2(ctx, r, N, MPMC_FP64, nrm));
+        HIP_OR_RET(ctx, hipMemcpyAsync(rn2.data(), nrm, sizeof(double2) * N, hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+        bool all = true;
+        for (int i = 0; i < N; ++i) {
+            if (!std::isfinite(rn2[2 * i])) return set_err(ctx, MPMC_ENUMERIC, "mpmc_solve: residual %d is not finite", i);
+            rel[i] = bn2[2 * i] > 0 ? std::sqrt(std::max(rn2[2 * i], 0.0) / bn2[2 * i]) : 0.0;
+            if (rel[i] > tol) all = false;
+        }
+        converged = all;
+        return MPMC_OK;
+    };
+
+    for (int outer = 0; outer < max_outer; ++outer) {
+        RET_IF(true_residual());
+        if (converged) break;
+        if (dc) {
+            RET_IF(defl_coeffs(ctx, defl, r, N, dc, 1));
+            RET_IF(defl_add(ctx, defl, dc, x, N, 1.0));
+            RET_IF(true_residual());
+            if (converged) break;
+        }
+        // inner targets: the final tolerance for an FP64 cycle; FP32 cycles
+        // stop near single precision and the outer loop corrects the rest
+        std::vector<double> target(N);
+        for (int i = 0; i < N; ++i) {
+            const double rn = std::sqrt(std::max(rn2[2 * i], 0.0)), bn = std::sqrt(std::max(bn2[2 * i], 0.0));
+            double t = 0.5 * tol * bn;
+            if (inner_prec == MPMC_FP32) t = std::max(t, 2e-6 * rn);
+            target[i] = t;
+        }
+        RET_IF(blas_convert(ctx, r, MPMC_FP64, V, inner_prec, N));
+        RET_IF(blas_scale_rhs(ctx, V, V, N, inner_prec, nrm, 1));
+        HIP_OR_RET(ctx, hipMemsetAsync(H, 0, sizeof(double2) * (size_t)(m + 1) * (m + 1) * N, ctx->stream));
+        k_init_g<<<grid_for((long)(m + 1) * N, 256), 256, 0, ctx->stream>>>((double2 *)g, m, N, (const double2 *)nrm);
+        HIP_OR_RET(ctx, hipGetLastError());
+        const size_t es = inner_prec == MPMC_FP64 ? 16 : 8;
+        int jdone = 0;
+        for (int j = 0; j < m; ++j) {
+            void *vj = (char *)V + (size_t)j * vstride * es;
+            void *vj1 = (char *)V + (size_t)(j + 1) * vstride * es;
+            double *Hcol = H + 2 * (size_t)j * (m + 1) * N;
+            RET_IF(wilson_launch_full(ctx, vj, nullptr, w, nullptr, N, inner_prec, make_double2(0, 0),
+                                      make_double2(1, 0), make_double2(0, 0), 0, 0));
+            RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, 0, 0));
+            RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, N, -1.0, nullptr));
+            RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, inner_prec, h2, 0, 0));
+            RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, inner_prec, h2, N, -1.0, nrm));
+            k_finalize_batch<<<grid_for(N, 64), 64, 0, ctx->stream>>>((double2 *)Hcol, (const double2 *)h2, j, N,
+                                                                      (const double2 *)nrm, (double2 *)scale);
+            HIP_OR_RET(ctx, hipGetLastError());
+            RET_IF(blas_scale_rhs(ctx, w, vj1, N, inner_prec, scale, 0));
+            RET_IF(dense_givens_step(ctx, H, m + 1, j, N, cs, g, res));
+            jdone = j + 1;
+            if ((j + 1) % 10 == 0 && j + 1 < m) {
+                HIP_OR_RET(ctx, hipMemcpyAsync(resh.data(), res, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+                HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+                bool all = true;
+                for (int i = 0; i < N; ++i) all = all && resh[i] <= target[i];
+                if (all) break;
+            }
+        }
+        RET_IF(dense_backsolve(ctx, H, m + 1, jdone, N, g, y));
+        HIP_OR_RET(ctx, hipMemsetAsync(e, 0, vbi, ctx->stream));
+        RET_IF(blas_multi_axpy(ctx, V, vstride, N, jdone, e, N, inner_prec, y, N, 1.0, nullptr));
+        // x += e (in FP64)
+        RET_IF(blas_convert(ctx, e, inner_prec, r, MPMC_FP64, N));
+        RET_IF(blas_axpby(ctx, r, x, N, MPMC_FP64, make_double2(1, 0), make_double2(1, 0)));
+        total += jdone;
+    }
+    if (!converged) RET_IF(true_residual());
+    if (iters_out) *iters_out = total;
+    if (relres_host)
+        for (int i = 0; i < N; ++i) relres_host[i] = rel[i];
+    if (!converged) return set_err(ctx, MPMC_ENOCONV, "mpmc_solve: not converged after %d outer cycles", max_outer);
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl, const mpmc_net *net,
+                        int restart, double tol, int inner_prec, int max_outer, int *iters_host, double *relres_host) {
+    if (!ctx) return MPMC_EINVAL;
+    if (!b || !x || nrhs < 1 || restart < 1 || restart > 400 || !(tol > 0) || max_outer < 1)
+        return set_err(ctx, MPMC_EINVAL, "mpmc_solve: bad argument");
+    if (b == x) return set_err(ctx, MPMC_EINVAL, "mpmc_solve: b and x must not alias");
+    if (defl && defl->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "deflation set belongs to another context");
+    return solve_internal(ctx, b, x, nrhs, defl, net, restart, tol, inner_prec, max_outer, iters_host, relres_host);
+}

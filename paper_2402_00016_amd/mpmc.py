@@ -1,0 +1,379 @@
+"""ctypes binding of libmpmc.so (C ABI in include/mpmc.h).
+
+Argument marshalling only: every function below forwards to the C entry point
+of the same name; every compute step runs in the library's HIP kernels.
+Device buffers are torch tensors on the current HIP device (passed as
+``data_ptr()``), and the context runs on torch's current stream unless another
+stream is given.  If the library is missing this module raises at import time:
+there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("MPMC_LIB", os.path.join(HERE, "libmpmc.so"))
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32, FP16S = 0, 1, 2
+THETA_I, THETA_G5 = 0, 1
+PREC = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
+THETA = {"I": THETA_I, "g5": THETA_G5}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libmpmc.so not found at %s: build it with `python -m paper_2402_00016_amd.build` "
+                      "(there is no CPU fallback)" % LIB_PATH)
+
+_L = ctypes.CDLL(LIB_PATH)
+_vp, _i, _u32, _u64, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+_pi, _pd, _pu64, _psz = (ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_size_t))
+
+_SIGS = {
+    "mpmc_create": ([_pi, _d, _i, _vp, _vp, ctypes.POINTER(_vp)], _i),
+    "mpmc_destroy": ([_vp], None),
+    "mpmc_last_error": ([_vp], ctypes.c_char_p),
+    "mpmc_set_stream": ([_vp, _vp], _i),
+    "mpmc_vector_bytes": ([_vp, _i, _i, _psz], _i),
+    "mpmc_mvp_count": ([_vp, _pu64], _i),
+    "mpmc_mvp_reset": ([_vp], _i),
+    "mpmc_pack": ([_vp, _vp, _vp, _i, _i], _i),
+    "mpmc_unpack": ([_vp, _vp, _vp, _i, _i], _i),
+    "mpmc_noise": ([_vp, _u64, _u32, _u64, _i, _i, _vp], _i),
+    "mpmc_apply_M": ([_vp, _vp, _vp, _i, _i, _i, _i], _i),
+    "mpmc_gmres_poly": ([_vp, _vp, _vp, _u64, _u32, _i, ctypes.POINTER(_vp), _pi, _pd], _i),
+    "mpmc_poly_create": ([_vp, _vp, _i, _vp, ctypes.POINTER(_vp)], _i),
+    "mpmc_poly_roots": ([_vp, _vp, _pi], _i),
+    "mpmc_poly_info": ([_vp, _pi, _pi, _pi, _pi], _i),
+    "mpmc_poly_eval": ([_vp, _vp, _vp, _i], _i),
+    "mpmc_poly_destroy": ([_vp], None),
+    "mpmc_apply_poly": ([_vp, _vp, _vp, _vp, _i, _i], _i),
+    "mpmc_deflate": ([_vp, _vp, _u64, _u32, _i, _i, _d, _d, ctypes.POINTER(_vp), _pi], _i),
+    "mpmc_defl_create": ([_vp, _vp, _vp, _vp, _i, ctypes.POINTER(_vp)], _i),
+    "mpmc_defl_export": ([_vp, _vp, _vp, _vp, _pi], _i),
+    "mpmc_defl_destroy": ([_vp], None),
+    "mpmc_solve": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
+    "mpmc_level_estimate": ([_vp, _vp, _vp, _vp, _i, _u64, _u32, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp,
+                             _pu64], _i),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_L, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class MpmcError(RuntimeError):
+    def __init__(self, rc, msg):
+        super().__init__("mpmc error %d: %s" % (rc, msg))
+        self.rc = rc
+
+
+def _check(rc, ctx):
+    if rc != OK:
+        msg = _L.mpmc_last_error(ctx)
+        raise MpmcError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _h(obj):
+    return None if obj is None else obj.handle
+
+
+# ------------------------------------------------------------- same-name calls
+
+def mpmc_create(dims, kappa, t_antiperiodic, links_host, stream=None):
+    links = np.ascontiguousarray(links_host, dtype=np.complex128)
+    d = (ctypes.c_int * 4)(*[int(v) for v in dims])
+    out = _vp()
+    _check(_L.mpmc_create(d, float(kappa), int(t_antiperiodic), links.ctypes.data, stream, ctypes.byref(out)), None)
+    return out
+
+
+def mpmc_destroy(ctx):
+    _L.mpmc_destroy(ctx)
+
+
+def mpmc_last_error(ctx):
+    m = _L.mpmc_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def mpmc_vector_bytes(ctx, nrhs, prec):
+    b = ctypes.c_size_t()
+    _check(_L.mpmc_vector_bytes(ctx, int(nrhs), int(prec), ctypes.byref(b)), ctx)
+    return b.value
+
+
+def mpmc_mvp_count(ctx):
+    v = ctypes.c_uint64()
+    _check(_L.mpmc_mvp_count(ctx, ctypes.byref(v)), ctx)
+    return v.value
+
+
+def mpmc_mvp_reset(ctx):
+    _check(_L.mpmc_mvp_reset(ctx), ctx)
+
+
+def mpmc_pack(ctx, canon, internal, nrhs, prec):
+    _check(_L.mpmc_pack(ctx, _ptr(canon), _ptr(internal), int(nrhs), int(prec)), ctx)
+
+
+def mpmc_unpack(ctx, internal, canon, nrhs, prec):
+    _check(_L.mpmc_unpack(ctx, _ptr(internal), _ptr(canon), int(nrhs), int(prec)), ctx)
+
+
+def mpmc_noise(ctx, seed, stream, first, nrhs, prec, internal):
+    _check(_L.mpmc_noise(ctx, int(seed), int(stream), int(first), int(nrhs), int(prec), _ptr(internal)), ctx)
+
+
+def mpmc_apply_M(ctx, x, y, nrhs, prec, dagger=0, theta=THETA_I):
+    _check(_L.mpmc_apply_M(ctx, _ptr(x), _ptr(y), int(nrhs), int(prec), int(dagger), int(theta)), ctx)
+
+
+def mpmc_gmres_poly(ctx, inner, defl, seed, stream, d):
+    out, de, rr = _vp(), ctypes.c_int(), ctypes.c_double()
+    _check(_L.mpmc_gmres_poly(ctx, _h(inner), _h(defl), int(seed), int(stream), int(d), ctypes.byref(out),
+                              ctypes.byref(de), ctypes.byref(rr)), ctx)
+    return out, de.value, rr.value
+
+
+def mpmc_poly_create(ctx, roots, inner=None):
+    r = np.ascontiguousarray(roots, dtype=np.complex128)
+    out = _vp()
+    _check(_L.mpmc_poly_create(ctx, r.ctypes.data, len(r), _h(inner), ctypes.byref(out)), ctx)
+    return out
+
+
+def mpmc_poly_roots(handle):
+    d = ctypes.c_int(0)
+    _check(_L.mpmc_poly_roots(handle, None, ctypes.byref(d)), None)
+    r = np.zeros(d.value, dtype=np.complex128)
+    _check(_L.mpmc_poly_roots(handle, r.ctypes.data, ctypes.byref(d)), None)
+    return r
+
+
+def mpmc_poly_info(handle):
+    v = [ctypes.c_int() for _ in range(4)]
+    _check(_L.mpmc_poly_info(handle, *[ctypes.byref(x) for x in v]), None)
+    return dict(d=v[0].value, d_inner=v[1].value, degree=v[2].value, matvecs=v[3].value)
+
+
+def mpmc_poly_eval(handle, lam):
+    lam = np.ascontiguousarray(np.atleast_1d(lam), dtype=np.complex128)
+    out = np.zeros_like(lam)
+    _check(_L.mpmc_poly_eval(handle, lam.ctypes.data, out.ctypes.data, len(lam)), None)
+    return out
+
+
+def mpmc_poly_destroy(handle):
+    _L.mpmc_poly_destroy(handle)
+
+
+def mpmc_apply_poly(ctx, poly, x, y, nrhs, prec):
+    _check(_L.mpmc_apply_poly(ctx, _h(poly), _ptr(x), _ptr(y), int(nrhs), int(prec)), ctx)
+
+
+def mpmc_deflate(ctx, p_in, seed, stream, m, nev, accept_tol=1e-3, real_tol=2e-4):
+    out, k = _vp(), ctypes.c_int()
+    _check(_L.mpmc_deflate(ctx, _h(p_in), int(seed), int(stream), int(m), int(nev), float(accept_tol),
+                           float(real_tol), ctypes.byref(out), ctypes.byref(k)), ctx)
+    return out, k.value
+
+
+def mpmc_defl_create(ctx, lam, Z, U):
+    lam = np.ascontiguousarray(lam, dtype=np.complex128)
+    out = _vp()
+    _check(_L.mpmc_defl_create(ctx, lam.ctypes.data if len(lam) else None, _ptr(Z), _ptr(U), len(lam),
+                               ctypes.byref(out)), ctx)
+    return out
+
+
+def mpmc_defl_export(handle, Z=None, U=None):
+    k = ctypes.c_int()
+    _check(_L.mpmc_defl_export(handle, None, None, None, ctypes.byref(k)), None)
+    lam = np.zeros(k.value, dtype=np.complex128)
+    _check(_L.mpmc_defl_export(handle, lam.ctypes.data if k.value else None, _ptr(Z), _ptr(U), ctypes.byref(k)), None)
+    return lam
+
+
+def mpmc_defl_destroy(handle):
+    _L.mpmc_defl_destroy(handle)
+
+
+def mpmc_solve(ctx, b, x, nrhs, defl=None, net=None, restart=50, tol=1e-8, inner_prec=FP64, max_outer=100,
+               raise_on_noconv=True):
+    its = ctypes.c_int()
+    rel = np.zeros(nrhs)
+    rc = _L.mpmc_solve(ctx, _ptr(b), _ptr(x), int(nrhs), _h(defl), _h(net), int(restart), float(tol),
+                       int(inner_prec), int(max_outer), ctypes.byref(its), rel.ctypes.data)
+    if rc != ENOCONV or raise_on_noconv:
+        _check(rc, ctx)
+    return its.value, rel, rc
+
+
+def mpmc_level_estimate(ctx, upper, lower, defl, theta, seed, stream, first, nnoise, prec, max_batch=0,
+                        solve_tol=1e-8, solve_restart=50, solve_inner_prec=FP64, net=None):
+    samples = np.zeros(nnoise, dtype=np.complex128)
+    corr = np.zeros(1, dtype=np.complex128)
+    mvps = ctypes.c_uint64()
+    _check(_L.mpmc_level_estimate(ctx, _h(upper), _h(lower), _h(defl), int(theta), int(seed), int(stream),
+                                  int(first), int(nnoise), int(prec), int(max_batch), float(solve_tol),
+                                  int(solve_restart), int(solve_inner_prec), _h(net), samples.ctypes.data,
+                                  corr.ctypes.data, ctypes.byref(mvps)), ctx)
+    return samples, complex(corr[0]), mvps.value
+
+
+# ---------------------------------------------------------- object wrappers
+
+class _Handle:
+    """Owns a library handle and frees it with the matching _destroy call."""
+
+    _destroy = None
+
+    def __init__(self, handle, owner):
+        self.handle = handle
+        self.owner = owner      # keeps the context (and inner polynomials) alive
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            type(self)._destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Poly(_Handle):
+    _destroy = staticmethod(mpmc_poly_destroy)
+
+    def __init__(self, handle, owner, inner=None, d_eff=None, relres=None):
+        super().__init__(handle, owner)
+        self.inner = inner
+        self.d_eff = d_eff
+        self.relres = relres
+
+    @property
+    def roots(self):
+        return mpmc_poly_roots(self.handle)
+
+    @property
+    def info(self):
+        return mpmc_poly_info(self.handle)
+
+    def eval(self, lam):
+        return mpmc_poly_eval(self.handle, lam)
+
+
+class Defl(_Handle):
+    _destroy = staticmethod(mpmc_defl_destroy)
+
+    def __init__(self, handle, owner, k):
+        super().__init__(handle, owner)
+        self.k = k
+
+    @property
+    def lam(self):
+        return mpmc_defl_export(self.handle)
+
+
+class Context:
+    """One lattice on the current HIP device (torch tensors as device buffers)."""
+
+    def __init__(self, dims, kappa, links, t_antiperiodic=True, stream=None):
+        import torch
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.dims = tuple(int(d) for d in dims)
+        self.V = int(np.prod(self.dims))
+        self.n = 12 * self.V
+        self.kappa = float(kappa)
+        self.handle = mpmc_create(self.dims, kappa, t_antiperiodic, links, ctypes.c_void_p(stream))
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            mpmc_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # buffers
+    def vector(self, nrhs, prec=FP64):
+        return self.torch.empty(mpmc_vector_bytes(self.handle, nrhs, prec), dtype=self.torch.uint8, device="cuda")
+
+    def pack(self, canon, prec=FP64):
+        """canon: complex128 tensor (nrhs, n) on the device -> internal buffer."""
+        canon = canon.contiguous()
+        nrhs = canon.shape[0]
+        out = self.vector(nrhs, prec)
+        mpmc_pack(self.handle, canon, out, nrhs, prec)
+        return out
+
+    def unpack(self, internal, nrhs, prec=FP64):
+        out = self.torch.empty((nrhs, self.n), dtype=self.torch.complex128, device="cuda")
+        mpmc_unpack(self.handle, internal, out, nrhs, prec)
+        return out
+
+    def noise(self, seed, stream, first, nrhs, prec=FP64):
+        out = self.vector(nrhs, prec)
+        mpmc_noise(self.handle, seed, stream, first, nrhs, prec, out)
+        return out
+
+    def apply_M(self, x, nrhs, prec=FP64, dagger=False, theta=THETA_I, out=None):
+        y = self.vector(nrhs, prec) if out is None else out
+        mpmc_apply_M(self.handle, x, y, nrhs, prec, int(dagger), theta)
+        return y
+
+    @property
+    def mvps(self):
+        return mpmc_mvp_count(self.handle)
+
+    # polynomials
+    def gmres_poly(self, seed, stream, d, inner=None, defl=None):
+        h, de, rr = mpmc_gmres_poly(self.handle, inner, defl, seed, stream, d)
+        return Poly(h, (self, inner, defl), inner=inner, d_eff=de, relres=rr)
+
+    def poly_from_roots(self, roots, inner=None):
+        return Poly(mpmc_poly_create(self.handle, roots, inner), (self, inner), inner=inner)
+
+    def apply_poly(self, poly, x, nrhs, prec=FP64, out=None):
+        y = self.vector(nrhs, prec) if out is None else out
+        mpmc_apply_poly(self.handle, poly, x, y, nrhs, prec)
+        return y
+
+    # deflation
+    def deflate(self, p_in, seed, stream, m, nev, accept_tol=1e-3, real_tol=2e-4):
+        h, k = mpmc_deflate(self.handle, p_in, seed, stream, m, nev, accept_tol, real_tol)
+        return Defl(h, (self, p_in), k)
+
+    def defl_from_arrays(self, lam, Z, U):
+        return Defl(mpmc_defl_create(self.handle, lam, Z, U), self, len(lam))
+
+    def defl_vectors(self, defl):
+        Z = self.torch.empty((max(defl.k, 1), self.n), dtype=self.torch.complex128, device="cuda")
+        U = self.torch.empty_like(Z)
+        lam = mpmc_defl_export(defl.handle, Z, U)
+        return lam, Z[:defl.k], U[:defl.k]
+
+    # solves and levels
+    def solve(self, b, nrhs, defl=None, restart=50, tol=1e-8, inner_prec=FP64, max_outer=100, x=None):
+        x = self.vector(nrhs, FP64) if x is None else x
+        its, rel, rc = mpmc_solve(self.handle, b, x, nrhs, defl, None, restart, tol, inner_prec, max_outer)
+        return x, its, rel
+
+    def level(self, upper, lower, defl, theta, seed, stream, first, nnoise, prec=FP64, max_batch=0,
+              solve_tol=1e-8, solve_restart=50, solve_inner_prec=FP64):
+        return mpmc_level_estimate(self.handle, upper, lower, defl, theta, seed, stream, first, nnoise, prec,
+                                   max_batch, solve_tol, solve_restart, solve_inner_prec, None)

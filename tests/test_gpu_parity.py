@@ -1,0 +1,314 @@
+"""GPU parity: every call of the C ABI against the FP64 oracle on the same
+seeded inputs (run on an MI355X; marked gpu).
+
+Tolerances (derived from the arithmetic):
+* Z(4) noise, indexing, pack/unpack in FP64: bit-exact.
+* FP64 operator: ||y_gpu - y_oracle|| / ||y_oracle|| <= 1e-13 (sums of ~100
+  terms in a different order, unit roundoff 1.1e-16).
+* FP32 operator: <= 2e-6 (FP32 links and spinors, unit roundoff 6e-8, ~100
+  terms per component).
+* FP16S operator output: <= 1.5e-3 (half storage, 2^-11 relative to the
+  per-(site, rhs) maximum).
+* FP64 polynomials / solves / level samples: 1e-10 relative (spec bound).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from oracle import deflation as ODF  # noqa: E402
+from oracle import estimator as OES  # noqa: E402
+from oracle import krylov as OK  # noqa: E402
+from oracle import lattice as OLT  # noqa: E402
+from oracle import poly as OP  # noqa: E402
+from oracle import solve as OS  # noqa: E402
+from oracle.philox import z4_noise, z4_noise_batch  # noqa: E402
+from oracle.wilson import WilsonOp  # noqa: E402
+from paper_2402_00016_amd import inputs  # noqa: E402
+from paper_2402_00016_amd import mpmc  # noqa: E402
+
+FP64, FP32, FP16S = mpmc.FP64, mpmc.FP32, mpmc.FP16S
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def f44():
+    dims, kappa = (4, 4, 4, 4), 0.115
+    U = inputs.gauge_links(dims, 0.5, seed=1)
+    return dims, kappa, U, WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ------------------------------------------------------------------ noise --
+
+@pytest.mark.parametrize("prec", [FP64, FP32, FP16S])
+@pytest.mark.parametrize("N,seed,stream,first", [(1, 1, 0, 0), (5, 7, 3, 11), (64, 2 ** 40 + 5, 0x100, 1000)])
+def test_noise_bit_exact(f44, prec, N, seed, stream, first):
+    dims, kappa, U, op, ctx = f44
+    eta = ctx.noise(seed, stream, first, N, prec)
+    got = host(ctx.unpack(eta, N, prec))
+    ref = z4_noise_batch(seed, stream, first, N, op.n)
+    assert np.array_equal(got, ref)
+
+
+def test_noise_bit_exact_ragged_lattice():
+    dims = (3, 5, 2, 7)
+    U = inputs.gauge_links(dims, 0.4, seed=5)
+    ctx = mpmc.Context(dims, 0.1, U)
+    n = 12 * int(np.prod(dims))
+    got = host(ctx.unpack(ctx.noise(9, 2, 3, 3, FP64), 3, FP64))
+    assert np.array_equal(got, z4_noise_batch(9, 2, 3, 3, n))
+
+
+# ----------------------------------------------------------- pack/unpack --
+
+def test_pack_roundtrip(f44):
+    dims, kappa, U, op, ctx = f44
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((7, op.n)) + 1j * rng.standard_normal((7, op.n))
+    Xd = torch.from_numpy(X).cuda()
+    assert np.array_equal(host(ctx.unpack(ctx.pack(Xd, FP64), 7, FP64)), X)
+    assert rel(host(ctx.unpack(ctx.pack(Xd, FP32), 7, FP32)), X) < 1e-7
+    assert rel(host(ctx.unpack(ctx.pack(Xd, FP16S), 7, FP16S)), X) < 1e-3
+
+
+# -------------------------------------------------------------- operator --
+
+TOL = {FP64: 1e-13, FP32: 2e-6, FP16S: 1.5e-3}
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32, FP16S])
+@pytest.mark.parametrize("N", [1, 3, 64, 65])
+@pytest.mark.parametrize("dagger,theta", [(0, 0), (1, 0), (0, 1)])
+def test_apply_M_parity(f44, prec, N, dagger, theta):
+    dims, kappa, U, op, ctx = f44
+    rng = np.random.default_rng(N + 10 * dagger + 100 * theta)
+    X = rng.standard_normal((N, op.n)) + 1j * rng.standard_normal((N, op.n))
+    x = ctx.pack(torch.from_numpy(X).cuda(), prec)
+    y = ctx.apply_M(x, N, prec, dagger=dagger, theta=theta)
+    got = host(ctx.unpack(y, N, prec))
+    Xin = host(ctx.unpack(x, N, prec))          # what the kernel actually read
+    ref = op.dagger(Xin) if dagger else op(Xin)
+    if theta:
+        ref = OLT.spin_op(ref, OLT.GAMMA5)
+    assert rel(got, ref) < TOL[prec]
+
+
+def test_apply_M_free_field_and_kappa0():
+    dims = (4, 4, 4, 6)
+    ctx = mpmc.Context(dims, 0.11, inputs.unit_links(dims))
+    p = OLT.free_momenta(dims)[77]
+    chi = (np.arange(12).reshape(4, 3) + 1j).astype(np.complex128)
+    psi = OLT.plane_wave(dims, p, chi)
+    y = host(ctx.unpack(ctx.apply_M(ctx.pack(torch.from_numpy(psi[None]).cuda()), 1), 1))[0]
+    assert rel(y, OLT.plane_wave(dims, p, OLT.free_symbol(p, 0.11) @ chi)) < 1e-13
+    ctx0 = mpmc.Context(dims, 0.0, inputs.gauge_links(dims, 0.5, seed=3))
+    e = ctx0.noise(1, 0, 0, 2)
+    assert torch.equal(ctx0.apply_M(e, 2), e)
+
+
+@pytest.mark.parametrize("L,N,prec", [(8, 128, FP32), (16, 64, FP32), (24, 64, FP32), (8, 16, FP64)])
+def test_apply_M_full_size_sampled(L, N, prec):
+    """Full-size shapes in the bench launch configuration; the oracle checks
+    two sampled right-hand sides (first and last) of the Z(4) input."""
+    dims = (L, L, L, L)
+    U = inputs.gauge_links(dims, 0.4, seed=4)
+    ctx = mpmc.Context(dims, 0.1245, U)
+    op = WilsonOp(dims, 0.1245, U)
+    eta = ctx.noise(3, 0, 0, N, prec)
+    y = ctx.apply_M(eta, N, prec)
+    full = ctx.unpack(y, N, prec)
+    for r in (0, N - 1):
+        got = full[r].cpu().numpy()
+        ref = op(z4_noise(3, 0, r, op.n))
+        assert rel(got, ref) < TOL[prec]
+    del y, full, eta
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------ polynomials --
+
+def _match_sets(a, b):
+    """max over a of the distance to the nearest element of b (and vice versa)."""
+    a, b = np.asarray(a), np.asarray(b)
+    d1 = max(np.min(np.abs(b - x)) for x in a)
+    d2 = max(np.min(np.abs(a - x)) for x in b)
+    return max(d1, d2)
+
+
+@pytest.mark.parametrize("d", [4, 9, 16])
+def test_gmres_poly_roots_parity(f44, d):
+    dims, kappa, U, op, ctx = f44
+    P = ctx.gmres_poly(1, 0x100, d)
+    ref, de, rr = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), d)
+    assert P.d_eff == de == d
+    roots = P.roots
+    assert _match_sets(roots, ref.roots) < 1e-9 * np.max(np.abs(ref.roots))
+    assert abs(abs(roots[0]) - abs(ref.roots[0])) < 1e-9     # Leja starts at the largest modulus
+    assert abs(P.relres - rr) < 1e-9 * max(rr, 1e-12) + 1e-13
+
+
+def test_gmres_poly_breakdown_kappa0():
+    dims = (2, 2, 2, 2)
+    ctx = mpmc.Context(dims, 0.0, inputs.gauge_links(dims, 0.5, seed=1))
+    P = ctx.gmres_poly(1, 0x100, 16)
+    assert P.d_eff == 1
+    assert np.allclose(P.roots, [1.0])
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (FP32, 2e-5)])
+def test_apply_poly_parity(f44, prec, tol):
+    dims, kappa, U, op, ctx = f44
+    ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 16)
+    P = ctx.poly_from_roots(ref.roots)
+    N = 5
+    eta = ctx.noise(4, 1, 0, N, prec)
+    got = host(ctx.unpack(ctx.apply_poly(P, eta, N, prec), N, prec))
+    E = z4_noise_batch(4, 1, 0, N, op.n)
+    want = np.stack([OP.apply_p(op, ref.roots, e) for e in E])
+    assert rel(got, want) < tol
+    assert P.info["degree"] == 15 and P.info["matvecs"] == 15
+
+
+def test_pi_equals_one_minus_M_p_on_gpu(f44):
+    """pi(M) = 1 - M p(M) with the GPU's own roots: residual of the GMRES cycle."""
+    dims, kappa, U, op, ctx = f44
+    P = ctx.gmres_poly(1, 0x100, 16)
+    b = ctx.noise(1, 0x100, 0, 1)
+    Mp = host(ctx.unpack(ctx.apply_M(ctx.apply_poly(P, b, 1), 1), 1))[0]
+    bb = z4_noise(1, 0x100, 0, op.n)
+    lhs = OP.apply_pi(op, P.roots, bb)
+    # b - M p(M) b cancels to ||pi(M) b|| ~ 1e-5 ||b||: FP64 rounding of the
+    # O(||b||) terms is amplified by ||b|| / ||pi(M) b||
+    amp = np.linalg.norm(bb) / np.linalg.norm(lhs)
+    assert rel(bb - Mp, lhs) < 1e-14 * amp
+    assert abs(np.linalg.norm(lhs) / np.linalg.norm(bb) - P.relres) < 1e-10
+
+
+def test_double_poly_parity(f44):
+    dims, kappa, U, op, ctx = f44
+    b = z4_noise(1, 0x100, 0, op.n)
+    Dref, _, _ = OP.double_poly(op, b, 5, 4)
+    Pin = ctx.gmres_poly(1, 0x100, 5)
+    Pd = ctx.gmres_poly(1, 0x100, 4, inner=Pin)
+    assert _match_sets(Pin.roots, Dref.inner.roots) < 1e-9
+    assert _match_sets(Pd.roots, Dref.roots) < 1e-8
+    assert Pd.info["degree"] == 19 and Pd.info["matvecs"] == 19
+    # application with the oracle's roots imported on both levels
+    Pi2 = ctx.poly_from_roots(Dref.inner.roots)
+    Pd2 = ctx.poly_from_roots(Dref.roots, inner=Pi2)
+    eta = ctx.noise(8, 2, 0, 3)
+    got = host(ctx.unpack(ctx.apply_poly(Pd2, eta, 3), 3))
+    want = np.stack([OP.apply_poly(op, Dref, e) for e in z4_noise_batch(8, 2, 0, 3, op.n)])
+    assert rel(got, want) < 1e-12
+    lam = np.array([0.3 + 0.2j, 0.9, 1.4 - 0.1j])
+    assert np.allclose(Pd2.eval(lam), OP.eval_poly(Dref, lam), rtol=1e-13)
+
+
+# -------------------------------------------------------------- deflation --
+
+def test_deflate_parity():
+    dims, kappa = (4, 4, 4, 4), 0.2
+    U = inputs.gauge_links(dims, 0.5, seed=21)
+    op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    Pin_ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 4)
+    Pin = ctx.poly_from_roots(Pin_ref.roots)
+    D = ctx.deflate(Pin, 1, 0x200, m=80, nev=10)
+    Dref, info = ODF.pp_arnoldi_eigs(op, Pin_ref.roots, z4_noise(1, 0x200, 0, op.n), 80, 10)
+    assert D.k >= 1 and abs(D.k - Dref.k) <= 2
+    lam, Z, Uv = ctx.defl_vectors(D)
+    assert _match_sets(lam, Dref.lam) < 1e-7
+    Zh, Uh = Z.cpu().numpy(), Uv.cpu().numpy()
+    for i in range(D.k):
+        assert abs(np.vdot(Uh[i], Zh[i]) - 1) < 1e-10
+        assert np.linalg.norm(op(Zh[i]) - lam[i] * Zh[i]) < 1e-3
+        u = Uh[i] / np.linalg.norm(Uh[i])
+        assert np.linalg.norm(op.dagger(u) - np.conj(lam[i]) * u) < 1e-3
+
+
+# ------------------------------------------------------------------ solve --
+
+@pytest.mark.parametrize("inner", [FP64, FP32])
+def test_solve_true_residual(f44, inner):
+    dims, kappa, U, op, ctx = f44
+    N = 6
+    b = ctx.noise(5, 0, 0, N, FP64)
+    x, its, relres = ctx.solve(b, N, restart=20, tol=1e-10, inner_prec=inner)
+    X = host(ctx.unpack(x, N))
+    B = z4_noise_batch(5, 0, 0, N, op.n)
+    R = B - op(X)
+    rr = np.linalg.norm(R, axis=1) / np.linalg.norm(B, axis=1)
+    assert np.all(rr <= 1.05e-10)
+    assert np.allclose(rr, relres, rtol=1e-3, atol=1e-14)
+
+
+def test_solve_with_imported_deflation(f44):
+    dims, kappa, U, op, ctx = f44
+    Pin_ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 4)
+    Dref, _ = ODF.pp_arnoldi_eigs(op, Pin_ref.roots, z4_noise(1, 0x200, 0, op.n), 60, 8)
+    D = ctx.defl_from_arrays(Dref.lam, torch.from_numpy(Dref.Z).cuda(), torch.from_numpy(Dref.U).cuda())
+    b = ctx.noise(6, 0, 0, 4)
+    x, its, relres = ctx.solve(b, 4, defl=D, restart=20, tol=1e-10, inner_prec=FP32)
+    X = host(ctx.unpack(x, 4))
+    B = z4_noise_batch(6, 0, 0, 4, op.n)
+    assert np.all(np.linalg.norm(B - op(X), axis=1) / np.linalg.norm(B, axis=1) <= 1.05e-10)
+
+
+# ----------------------------------------------------------------- levels --
+
+def test_level_samples_parity(f44):
+    """Same noise, same (imported) polynomials and eigenpairs: per-sample
+    values of every level kind agree with the oracle to 1e-10."""
+    dims, kappa, U, op, ctx = f44
+    b = z4_noise(1, 0x100, 0, op.n)
+    P1, _, _ = OK.gmres_poly(op, b, 17)
+    P2, _, _ = OK.gmres_poly(op, b, 9)
+    Pin, _, _ = OK.gmres_poly(op, b, 4)
+    Dref, _ = ODF.pp_arnoldi_eigs(op, Pin.roots, z4_noise(1, 0x200, 0, op.n), 60, 8)
+    g1, g2 = ctx.poly_from_roots(P1.roots), ctx.poly_from_roots(P2.roots)
+    D = ctx.defl_from_arrays(Dref.lam, torch.from_numpy(Dref.Z).cuda(), torch.from_numpy(Dref.U).cuda())
+    N = 8
+    for theta, th in (("I", 0), ("g5", 1)):
+        # polynomial-difference level with deflation
+        X, T, mv = ctx.level(g1, g2, D, th, 3, 2, 0, N)
+        Xr, Tr = OES.level_samples(op, P1, P2, Dref, theta, 3, 2, 0, N)
+        assert rel(X, Xr) < 1e-10 and abs(T - Tr) < 1e-10 * max(1, abs(Tr))
+        assert mv == N * (16 + 8)
+        # last level
+        X, T, _ = ctx.level(g2, None, None, th, 3, 3, 0, N)
+        Xr, _ = OES.level_samples(op, P2, None, None, theta, 3, 3, 0, N)
+        assert rel(X, Xr) < 1e-10 and T == 0
+        # solve level: each side solves to relative residual 1e-12, so a sample
+        # can differ by |eta^H (x - x*)| <= ||eta||^2 ||M^-1|| 1e-12 per side
+        # (||eta||^2 = n, ||M^-1|| < 10 on this field)
+        X, T, _ = ctx.level(None, g1, None, th, 3, 1, 0, N, solve_tol=1e-12, solve_restart=30)
+        Xr, _ = OES.level_samples(op, None, P1, None, theta, 3, 1, 0, N, solve_tol=1e-12)
+        assert np.max(np.abs(X - Xr)) < 2 * op.n * 10 * 1e-12
+
+
+def test_plain_4444_estimate_vs_dense_exact(f44):
+    """4^4, kappa 0.115: 32 Z(4) noises, Hutchinson and the subtracted level
+    against the dense exact traces of M^-1 and M^-1 - p(M)."""
+    dims, kappa, U, op, ctx = f44
+    M = OLT.dense_wilson(dims, kappa, U)
+    Minv = np.linalg.inv(M)
+    P = ctx.gmres_poly(1, 0x100, 16)
+    Pm = OP.apply_p(op, P.roots, np.eye(op.n)).T
+    X, _, _ = ctx.level(None, None, None, 0, 1, 0, 0, 32, solve_tol=1e-10)
+    m, v = OES.level_stats(X)
+    assert abs(m - np.trace(Minv)) < 3.5 * np.sqrt(v / 32)
+    Xs, _, _ = ctx.level(None, P, None, 0, 1, 1, 0, 32, solve_tol=1e-12)
+    ms, vs = OES.level_stats(Xs)
+    assert abs(ms - np.trace(Minv - Pm)) < 3.5 * np.sqrt(vs / 32) + 1e-9
+    assert vs < 1e-3 * v
