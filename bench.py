@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Benchmark of the Multipolynomial Monte Carlo hot path on one MI355X.
+
+Workload (one "step" = one complete trace estimate): 8^4 lattice
+(n = 49152), SU(3) links U = exp(i 0.5 H) from seed 2, Wilson kappa = 0.120,
+Theta = I; GMRES polynomials of degree 128, 32 and 8; the 20 lowest eigenpairs
+of M from PP-Arnoldi; 128 Z(4) noise vectors per Monte Carlo term, each term's
+noise processed as one multi-RHS batch; FP32 Wilson kernels with FP64
+accumulation and FP64 defect correction of the main solves (relative residual
+1e-8).  The step includes building the polynomials and the deflation set.
+
+Printed metric: multi-RHS Dslash HBM GB/s = algorithmic bytes moved by all
+Wilson-kernel launches of a step / wall time of the step.  The dominant
+kernel's own rate (bytes / summed HIP-event kernel time) is the roofline
+"achieved" figure; the FP64 form of the same estimate is timed beside it for
+the time-to-fixed-standard-error comparison, and the FP64 CPU oracle is timed
+on the host as the baseline.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--noises", type=int, default=128)
+    ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison form")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(dims, kappa, links, seconds):
+    """FP64 oracle Dslash on the host cores, on a bounded sample: repeated
+    16-RHS applications on the same 8^4 field for about `seconds` seconds."""
+    import numpy as np
+
+    from oracle.philox import z4_noise_batch
+    from oracle.wilson import WilsonOp
+    op = WilsonOp(dims, kappa, links)
+    N = 16
+    X = z4_noise_batch(2, 0, 0, N, op.n)
+    op(X)
+    t0 = time.perf_counter()
+    reps = 0
+    while time.perf_counter() - t0 < seconds:
+        op(X)
+        reps += 1
+    dt = time.perf_counter() - t0
+    V = op.V
+    bytes_per_apply = V * (N * 384.0 + 576.0)      # FP64: 12 complex in + out per site per rhs, links once
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(bytes_per_apply * reps / dt / 1e9, 3), "unit": "GB/s", "cores": cores,
+            "kind": "oracle",
+            "sample": "FP64 oracle Wilson operator, 8^4 lattice, 16 Z(4) right-hand sides per call, "
+                      "%d calls in %.1f s on %d host threads; same byte formula as the GPU figure" % (reps, dt, cores)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the method's noise vectors "
+              "shard across GPUs with one final all-reduce, which is not implemented); use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2402_00016_amd import driver, inputs, mpmc
+
+    torch.cuda.set_device(0)
+    dims, eps, seed, kappa = (8, 8, 8, 8), 0.5, 2, 0.120
+    links = inputs.gauge_links(dims, eps, seed)
+    ctx = mpmc.Context(dims, kappa, links)
+    plan = driver.Plan(degrees=[128, 32, 8], noises=a.noises, seed=seed, nev=20, defl_m=80, defl_pin_degree=8,
+                       poly_prec=mpmc.FP32, solve_inner_prec=mpmc.FP32, solve_tol=1e-8, solve_restart=50)
+    sync = torch.cuda.synchronize
+
+    for _ in range(a.warmup):
+        driver.estimate(ctx, plan, sync)
+    mpmc.mpmc_timing_enable(ctx.handle, 1)
+    sync()
+    t0 = time.perf_counter()
+    ests = [driver.estimate(ctx, plan, sync) for _ in range(a.steps)]
+    sync()
+    t1 = time.perf_counter()
+    n32, ms32, by32 = mpmc.mpmc_timing_read(ctx.handle, mpmc.FP32)
+    n64, ms64, by64 = mpmc.mpmc_timing_read(ctx.handle, mpmc.FP64)
+    mpmc.mpmc_timing_enable(ctx.handle, 0)
+    step_s = (t1 - t0) / a.steps
+    bytes_step = (by32 + by64) / a.steps
+    est = ests[-1]
+
+    out = {
+        "metric": "multi-RHS Dslash HBM GB/s; time to fixed trace std-error, learned vs plain",
+        "value": round(bytes_step / step_s / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(step_s * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "8^4 Wilson (kappa 0.120, eps 0.5 links seed 2), 3 GMRES polynomials "
+                               "(degrees 128/32/8), 20 deflated eigenpairs, 128 Z(4) noises per term, "
+                               "FP32 Dslash + FP64 refinement to 1e-8",
+                   "lattice": list(dims), "noises_per_term": a.noises, "rhs_per_launch": a.noises},
+        "roofline": {"bound": "hbm", "achieved": round(by32 / (ms32 * 1e-3) / 1e9, 1) if ms32 > 0 else None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(by32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if ms32 > 0 else None,
+                     "traffic": None, "kernel": "k_wilson<FP32> (multi-RHS Dslash / fused polynomial step)",
+                     "launches": n32, "avg_launch_us": round(ms32 * 1e3 / max(n32, 1), 2)},
+        "trace": {"value": [est.value.real, est.value.imag], "stderr": est.stderr,
+                  "levels": [{"name": L.name, "mean": [L.mean.real, L.mean.imag], "var": L.var, "n": L.n,
+                              "corr": [L.corr.real, L.corr.imag], "mvps": L.mvps, "s": round(L.seconds, 4)}
+                             for L in est.levels],
+                  "deflated": est.defl_k, "setup_s": round(est.setup_seconds, 4), "mvps": est.mvps},
+        "time_to_error_s": {"mixed_batched": round(step_s, 4)},
+        "fp64_kernel_share": {"launches": n64, "ms_per_step": round(ms64 / a.steps, 3)},
+    }
+    if not a.no_plain:
+        plain = driver.Plan(**{**plan.__dict__, "poly_prec": mpmc.FP64, "solve_inner_prec": mpmc.FP64})
+        driver.estimate(ctx, plain, sync)
+        sync()
+        tp = time.perf_counter()
+        e64 = driver.estimate(ctx, plain, sync)
+        sync()
+        tp = time.perf_counter() - tp
+        out["time_to_error_s"]["plain_fp64"] = round(tp, 4)
+        out["time_to_error_s"]["speedup_mixed_vs_plain"] = round(tp / step_s, 3)
+        comb = float(np.hypot(e64.stderr, est.stderr))
+        out["trace"]["plain_fp64"] = {"value": [e64.value.real, e64.value.imag], "stderr": e64.stderr,
+                                      "diff_in_combined_sigma": abs(est.value - e64.value) / comb}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(dims, kappa, links, a.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -104,6 +104,17 @@ int mpmc_vector_bytes(const mpmc_ctx *ctx, int nrhs, int prec, size_t *bytes);
 int mpmc_mvp_count(const mpmc_ctx *ctx, uint64_t *mvps_host);
 int mpmc_mvp_reset(mpmc_ctx *ctx);
 
+/* Launch timing of the Wilson-Dirac kernels (the multi-RHS "Dslash", alone or
+ * fused into a polynomial step).  While enabled, HIP events are recorded on the
+ * context stream around every such launch together with the launch's
+ * algorithmic HBM bytes: spinor bytes per (site, rhs) for each operand read
+ * once and each output written once, plus the links once per site.
+ * mpmc_timing_read synchronises and returns, for launches of precision prec
+ * since the last enable, the count, the summed kernel time (ms) and the
+ * summed algorithmic bytes; it leaves timing enabled. */
+int mpmc_timing_enable(mpmc_ctx *ctx, int on);
+int mpmc_timing_read(mpmc_ctx *ctx, int prec, uint64_t *launches_host, double *ms_host, double *bytes_host);
+
 /* Canonical complex double <-> internal layout of precision prec (device to
  * device; FP16S packing picks the per-(site, rhs) scale max|component|). */
 int mpmc_pack(mpmc_ctx *ctx, const void *canon, void *internal, int nrhs, int prec);

@@ -186,8 +186,11 @@ __global__ void k_axpby(VecRef x, VecRef y, long total, double2 a, double2 b) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     auto xv = Store<P>::ld(x.d, nullptr, e, 0);
-    auto yv = Store<P>::ld(y.d, nullptr, e, 0);
-    cpx<T> r = mk((T)a.x, (T)a.y) * mk((T)xv.re, (T)xv.im) + mk((T)b.x, (T)b.y) * mk((T)yv.re, (T)yv.im);
+    cpx<T> r = mk((T)a.x, (T)a.y) * mk((T)xv.re, (T)xv.im);
+    if (b.x != 0.0 || b.y != 0.0) {   // y is not read when b == 0 (it may be uninitialised)
+        auto yv = Store<P>::ld(y.d, nullptr, e, 0);
+        r = r + mk((T)b.x, (T)b.y) * mk((T)yv.re, (T)yv.im);
+    }
     Store<P>::st(y.d, e, r);
 }
 
@@ -252,7 +255,22 @@ int dispatch_prec(mpmc_ctx *ctx, int prec, F &&f) {
     return MPMC_OK;
 }
 
+// acc[r] += sign * c * t[r]
+__global__ void k_scale_acc(const double2 *t, int N, double2 c, double sign, double2 *acc) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= N) return;
+    const double2 v = t[r];
+    acc[r].x += sign * (c.x * v.x - c.y * v.y);
+    acc[r].y += sign * (c.x * v.y + c.y * v.x);
+}
+
 }  // namespace
+
+int blas_scale_acc(mpmc_ctx *ctx, const double *t, int N, double2 c, double sign, double *acc) {
+    k_scale_acc<<<grid_for(N, 64), 64, 0, ctx->stream>>>((const double2 *)t, N, c, sign, (double2 *)acc);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
 
 // h[j*N + r] (+)= V_j^H Theta w for j < nv.  Vb: nv vectors spaced vstride
 // elements (complex) apart.

@@ -39,6 +39,14 @@ struct mpmc_ctx {
     std::vector<WsBuf> stack;   // scoped scratch buffers (see Scratch)
     int top;
     int num_cu;
+    // optional launch timing of the Wilson kernels (mpmc_timing_*)
+    int timing;
+    std::vector<hipEvent_t> ev_pool;
+    struct TimedLaunch {
+        int ev0, ev1, prec;
+        double bytes;
+    };
+    std::vector<TimedLaunch> timed;
 };
 
 struct mpmc_poly {
@@ -286,10 +294,20 @@ int blas_axpby(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, double
 int blas_scale_rhs(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, const double *coef_dev, int mode);
 int blas_convert(mpmc_ctx *ctx, const void *x, int px, void *y, int py, int nrhs);
 int blas_zero(mpmc_ctx *ctx, void *y, int nrhs, int prec);
+int blas_scale_acc(mpmc_ctx *ctx, const double *t, int N, double2 c, double sign, double *acc);
 
 // wilson.hip: out = alpha a + beta Theta op(b); y += gamma out (y may be null)
 int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, void *y, int nrhs, int prec,
                        double2 alpha, double2 beta, double2 gamma, int dagger, int theta);
+// fused level step (see wilson.hip): w' = w - c M w; partial += cnext eta^H Theta w'
+size_t wilson_dot_partial_count(const mpmc_ctx *ctx, int nrhs);
+int wilson_noise_codes(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, uint32_t *codes);
+int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *codes, int nrhs, int prec, double2 c,
+                    double2 cnext, int theta, double *partial, int first_step);
+int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, double *out, int accumulate, double sign);
+// timing hooks around one launch (no-ops unless timing is enabled)
+int timing_begin(mpmc_ctx *ctx);
+void timing_end(mpmc_ctx *ctx, int ev0, int prec, double bytes);
 
 // dense.hip
 int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, double beta, double *roots_dev,
@@ -302,6 +320,10 @@ int dense_backsolve(mpmc_ctx *ctx, const double *H, int ldc, int k, int N, const
 
 // krylov.hip
 int poly_apply_internal(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec);
+// acc[r] += sign * eta_r^H Theta p(M) eta_r without forming p(M) eta (fused steps)
+int poly_quad_fused(mpmc_ctx *ctx, const mpmc_poly *p, const void *eta, const uint32_t *codes, int nrhs, int prec,
+                    int theta, double *acc, double sign);
+bool poly_quad_fusable(int nrhs);
 int poly_matvecs(const mpmc_poly *p);
 void poly_eval_host(const mpmc_poly *p, const double *lam, double *out, int k);
 

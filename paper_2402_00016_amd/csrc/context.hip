@@ -141,6 +141,7 @@ MPMC_API int mpmc_create(const int dims[4], double kappa, int t_antiperiodic, co
     c->mvps = 0;
     c->ws.resize(WS_NSLOTS);
     c->top = 0;
+    c->timing = 0;
     hipGetDevice(&c->device);
     hipDeviceProp_t prop;
     c->num_cu = (hipGetDeviceProperties(&prop, c->device) == hipSuccess) ? prop.multiProcessorCount : 256;
@@ -175,6 +176,7 @@ MPMC_API void mpmc_destroy(mpmc_ctx *ctx) {
         if (b.ptr) hipFree(b.ptr);
     for (auto &b : ctx->stack)
         if (b.ptr) hipFree(b.ptr);
+    for (auto e : ctx->ev_pool) hipEventDestroy(e);
     delete ctx;
 }
 
@@ -319,4 +321,51 @@ MPMC_API int mpmc_noise(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t 
     if (!internal || nrhs < 1 || !prec_ok(prec) || first + (uint64_t)nrhs > 0x100000000ull)
         return set_err(ctx, MPMC_EINVAL, "mpmc_noise: bad argument");
     return launch_noise(ctx, seed, stream, first, nrhs, prec, internal);
+}
+
+// ------------------------------------------------------------- timing --
+
+int timing_begin(mpmc_ctx *ctx) {
+    if (!ctx->timing) return -1;
+    const int i = (int)ctx->timed.size() * 2;
+    while ((int)ctx->ev_pool.size() < i + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        ctx->ev_pool.push_back(e);
+    }
+    if (hipEventRecord(ctx->ev_pool[i], ctx->stream) != hipSuccess) return -1;
+    return i;
+}
+
+void timing_end(mpmc_ctx *ctx, int ev0, int prec, double bytes) {
+    if (ev0 < 0) return;
+    if (hipEventRecord(ctx->ev_pool[ev0 + 1], ctx->stream) != hipSuccess) return;
+    ctx->timed.push_back({ev0, ev0 + 1, prec, bytes});
+}
+
+MPMC_API int mpmc_timing_enable(mpmc_ctx *ctx, int on) {
+    if (!ctx) return MPMC_EINVAL;
+    HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->timing = on ? 1 : 0;
+    ctx->timed.clear();
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_timing_read(mpmc_ctx *ctx, int prec, uint64_t *launches, double *ms, double *bytes) {
+    if (!ctx || !launches || !ms || !bytes) return MPMC_EINVAL;
+    HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    uint64_t cnt = 0;
+    double t = 0, b = 0;
+    for (const auto &L : ctx->timed) {
+        if (L.prec != prec) continue;
+        float e = 0;
+        HIP_OR_RET(ctx, hipEventElapsedTime(&e, ctx->ev_pool[L.ev0], ctx->ev_pool[L.ev1]));
+        ++cnt;
+        t += e;
+        b += L.bytes;
+    }
+    *launches = cnt;
+    *ms = t;
+    *bytes = b;
+    return MPMC_OK;
 }

@@ -308,3 +308,64 @@ int arnoldi_run_ext(mpmc_ctx *ctx, const mpmc_poly *inner, double *V, double *H,
     OpDesc op{inner, nullptr};
     return arnoldi_run(ctx, op, V, H, d, state, S);
 }
+
+// ------------------------------------------------- fused quadratic form --
+// acc[r] += sign * eta_r^H Theta p(M) eta_r.  For p = p_in(M) p_out(phi_in) the
+// outer factor u = p_out(phi_in) eta is formed explicitly and the inner single
+// polynomial is fused: sum_k eta^H Theta w_k / theta_k with w_1 = u.
+
+bool poly_quad_fusable(int nrhs) { return nrhs % 64 == 0 && (nrhs <= 256 || nrhs % 256 == 0); }
+
+static int quad_single_fused(mpmc_ctx *ctx, const std::vector<double> &roots, int d, const void *eta, const void *x,
+                             const uint32_t *codes, int nrhs, int prec, int theta, double *acc, double sign) {
+    Scratch S(ctx);
+    auto inv = [&](int k) {
+        std::complex<double> v = 1.0 / std::complex<double>(roots[2 * k], roots[2 * k + 1]);
+        return make_double2(v.real(), v.imag());
+    };
+    // first term (1/theta_1) eta^H Theta x
+    double2 *t = (double2 *)S.get(sizeof(double2) * nrhs * 2);
+    if (!t) return MPMC_ENOMEM;
+    RET_IF(blas_dot(ctx, eta, x, nrhs, prec, theta, (double *)t));
+    RET_IF(blas_scale_acc(ctx, (double *)t, nrhs, inv(0), sign, acc));
+    if (d == 1) return MPMC_OK;
+    void *wa = S.get(vec_bytes(ctx, nrhs, prec));
+    void *wb = S.get(vec_bytes(ctx, nrhs, prec));
+    double *part = (double *)S.get(sizeof(double2) * wilson_dot_partial_count(ctx, nrhs));
+    if (!wa || !wb || !part) return MPMC_ENOMEM;
+    const void *cur = x;
+    for (int k = 0; k + 1 < d; ++k) {
+        void *nxt = (cur == wa) ? wb : wa;
+        RET_IF(wilson_dot_step(ctx, cur, nxt, codes, nrhs, prec, inv(k), inv(k + 1), theta, part, k == 0));
+        cur = nxt;
+    }
+    return wilson_dot_finish(ctx, part, nrhs, acc, 1, sign);
+}
+
+int poly_quad_fused(mpmc_ctx *ctx, const mpmc_poly *p, const void *eta, const uint32_t *codes, int nrhs, int prec,
+                    int theta, double *acc, double sign) {
+    if (!poly_quad_fusable(nrhs)) return set_err(ctx, MPMC_EINVAL, "fused quadratic form needs nrhs %% 64 == 0");
+    if (!p->inner) return quad_single_fused(ctx, p->roots, p->d, eta, eta, codes, nrhs, prec, theta, acc, sign);
+    Scratch S(ctx);
+    const size_t vb = vec_bytes(ctx, nrhs, prec);
+    void *u = S.get(vb);
+    void *t = S.get(vb);
+    void *wa = S.get(vb);
+    void *wb = S.get(vb);
+    if (!u || !t || !wa || !wb) return MPMC_ENOMEM;
+    auto inv = [&](int k) {
+        std::complex<double> v = 1.0 / std::complex<double>(p->roots[2 * k], p->roots[2 * k + 1]);
+        return make_double2(v.real(), v.imag());
+    };
+    RET_IF(blas_axpby(ctx, eta, u, nrhs, prec, inv(0), make_double2(0, 0)));
+    const void *cur = eta;
+    for (int k = 0; k + 1 < p->d; ++k) {
+        void *nxt = (cur == wa) ? wb : wa;
+        RET_IF(apply_single(ctx, p->inner->roots, p->inner->d, cur, t, nrhs, prec));
+        double2 c = inv(k);
+        RET_IF(wilson_launch_full(ctx, t, cur, nxt, u, nrhs, prec, make_double2(1, 0), make_double2(-c.x, -c.y),
+                                  inv(k + 1), 0, 0));
+        cur = nxt;
+    }
+    return quad_single_fused(ctx, p->inner->roots, p->inner->d, eta, u, codes, nrhs, prec, theta, acc, sign);
+}

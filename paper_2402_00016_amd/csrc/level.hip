@@ -12,13 +12,6 @@
 
 namespace {
 
-__global__ void k_sub(double2 *acc, const double2 *t, int N) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= N) return;
-    acc[r].x -= t[r].x;
-    acc[r].y -= t[r].y;
-}
-
 // acc[r] -= sum_i c_i conj(a[i][r]) b[i][r],  a = z^H Theta eta, b = u^H eta
 __global__ void k_defl_term(double2 *acc, const double2 *a, const double2 *b, const double2 *c, int k, int N) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -89,8 +82,16 @@ MPMC_API int mpmc_level_estimate(mpmc_ctx *ctx, const mpmc_poly *upper, const mp
             corr += std::complex<double>(c[2 * i], c[2 * i + 1]) * std::complex<double>(uzh[2 * i], uzh[2 * i + 1]);
     }
 
+    uint32_t *codes = (upper || lower) ? (uint32_t *)S.get(sizeof(uint32_t) * (size_t)ctx->V * B) : nullptr;
+    if ((upper || lower) && !codes) return MPMC_ENOMEM;
     for (int b0 = 0; b0 < nnoise; b0 += B) {
         const int nb = std::min(B, nnoise - b0);
+        const bool fused = poly_quad_fusable(nb);
+        HIP_OR_RET(ctx, hipMemsetAsync(acc, 0, sizeof(double2) * nb, ctx->stream));
+        if (upper || lower) {
+            RET_IF(launch_noise(ctx, seed, stream, first + b0, nb, prec, eta));
+            if (fused) RET_IF(wilson_noise_codes(ctx, seed, stream, first + b0, nb, codes));
+        }
         if (!upper) {
             int its = 0;
             std::vector<double> rr(nb);
@@ -98,17 +99,19 @@ MPMC_API int mpmc_level_estimate(mpmc_ctx *ctx, const mpmc_poly *upper, const mp
             RET_IF(solve_internal(ctx, eta64, yv, nb, defl, net, solve_restart, solve_tol, solve_inner_prec, 400, &its,
                                   rr.data()));
             RET_IF(blas_dot(ctx, eta64, yv, nb, MPMC_FP64, th, (double *)acc));
-        } else {
-            RET_IF(launch_noise(ctx, seed, stream, first + b0, nb, prec, eta));
-            RET_IF(poly_apply_internal(ctx, upper, eta, yv, nb, prec));
-            RET_IF(blas_dot(ctx, eta, yv, nb, prec, th, (double *)acc));
         }
-        if (lower) {
-            RET_IF(launch_noise(ctx, seed, stream, first + b0, nb, prec, eta));
-            RET_IF(poly_apply_internal(ctx, lower, eta, yv, nb, prec));
-            RET_IF(blas_dot(ctx, eta, yv, nb, prec, th, (double *)tmp));
-            k_sub<<<grid_for(nb, 64), 64, 0, ctx->stream>>>(acc, tmp, nb);
-            HIP_OR_RET(ctx, hipGetLastError());
+        const mpmc_poly *parts[2] = {upper, lower};
+        const double signs[2] = {1.0, -1.0};
+        for (int q = 0; q < 2; ++q) {
+            const mpmc_poly *pq = parts[q];
+            if (!pq) continue;
+            if (fused) {
+                RET_IF(poly_quad_fused(ctx, pq, eta, codes, nb, prec, th, (double *)acc, signs[q]));
+            } else {
+                RET_IF(poly_apply_internal(ctx, pq, eta, yv, nb, prec));
+                RET_IF(blas_dot(ctx, eta, yv, nb, prec, th, (double *)tmp));
+                RET_IF(blas_scale_acc(ctx, (double *)tmp, nb, make_double2(1, 0), signs[q], (double *)acc));
+            }
         }
         if (use_defl) {
             RET_IF(launch_noise(ctx, seed, stream, first + b0, nb, MPMC_FP64, eta64));

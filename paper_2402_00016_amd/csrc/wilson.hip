@@ -5,16 +5,26 @@
 // g = +1 for M, -1 for M^H (the operator the paper calls the Wilson-Dirac
 // matrix, Sec. 1-2; written out in include/mpmc.h).
 //
-// Design: one thread per (site, rhs) of the internal layout
-// [site][spin*3+colour][rhs], so the lanes of a wavefront read consecutive
-// right-hand sides of the same site: every spinor load is a contiguous
-// 64-lane access and the site's links and neighbour indices are the same
-// address for all lanes (one cache line serves the whole wavefront).  Each
-// hop is done on half spinors: (1 +- gamma_mu) has rank 2, so the neighbour
-// spinor is projected to two colour vectors, rotated by the SU(3) link and
-// expanded back, halving the link multiplications.  Workgroups are numbered
-// so each XCD sweeps one contiguous block of sites (stencil neighbours stay in
-// that XCD's L2).
+// Design.  One thread per (site, rhs) of the internal layout
+// [site][spin*3+colour][rhs]: the lanes of a wavefront read consecutive
+// right-hand sides of the same site, so every spinor load is one contiguous
+// 64-lane access.  When the batch size is a multiple of 64 every wavefront
+// sits on a single site ("uniform" kernels): the neighbour indices and the
+// SU(3) links are then wave-uniform and are fetched with scalar loads into
+// SGPRs, once per wavefront instead of once per lane, which also keeps them
+// out of the vector register file.  Each hop works on half spinors: the rank-2
+// projector (1 +- gamma_mu) maps the neighbour spinor to two colour vectors,
+// the link multiplies those two, and the result is expanded back.
+// Workgroups are numbered so that each XCD sweeps one contiguous range of
+// sites (stencil neighbours stay in that XCD's L2).
+//
+// Kernels:
+//   k_wilson     out = alpha a + beta Theta op(b) [; y += gamma out]
+//   k_wilson_dot one step of a polynomial recurrence on a batch of noise
+//                vectors, w' = w - c M w, without forming p(M) eta: the
+//                quadratic form eta^H Theta w' is accumulated on the fly
+//                (eta regenerated from 2-bit Z(4) codes), so a step moves one
+//                spinor read and one spinor write per (site, rhs).
 #include "common.h"
 
 // Phase codes: 0 -> +1, 1 -> +i, 2 -> -1, 3 -> -i.
@@ -50,172 +60,613 @@ struct Proj<3> {  // gamma_t
     static constexpr int j0 = 2, c0 = 2, j1 = 3, c1 = 2, k2 = 0, d2 = 2, k3 = 1, d3 = 2;
 };
 
-struct WParams {
-    VecRef b;          // operand of M
-    VecRef a;          // additive term (d == nullptr: none)
-    VecRef out;
-    VecRef y;          // accumulator y += gamma * out (d == nullptr: none)
-    const int *nbr;
-    const void *links;
-    long V;
-    int N;
-    double kappa;
-    double2 alpha, beta, gamma;
-    float g;           // +1: M, -1: M^H
-    int theta;         // 1: multiply M b by gamma5 before combining
+template <int P>
+struct LinkT {
+    using type = float2;
+};
+template <>
+struct LinkT<MPMC_FP64> {
+    using type = double2;
 };
 
-template <typename T>
-__device__ __forceinline__ cpx<T> ldlink(const void *links, long idx) {
-    if constexpr (sizeof(T) == 8) {
-        double2 v = reinterpret_cast<const double2 *>(links)[idx];
-        return mk(v.x, v.y);
+// Read-only inputs of a Wilson application.
+template <int P>
+struct WIn {
+    const void *__restrict__ b;                  // operand of M
+    const float *__restrict__ bsc;               // its FP16S scales
+    const int *__restrict__ nbr;
+    const typename LinkT<P>::type *__restrict__ links;
+};
+
+// Element k of site sn, rhs r.  The row base (sn*12 + k)*N is formed as a
+// pointer first (wave-uniform in the uniform kernels, so it lives in SGPRs) and
+// the lane offset r*sizeof(element) is a 32-bit unsigned byte offset shared by
+// every access of the thread: the backend can then use SGPR-base +
+// VGPR-offset addressing instead of a 64-bit address per load.
+template <typename E, bool UNI>
+__device__ __forceinline__ E at(const void *base, long row, uint32_t voff) {
+    return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(reinterpret_cast<const E *>(base) + row) + voff);
+}
+template <typename E, bool UNI>
+__device__ __forceinline__ void at_w(void *base, long row, uint32_t voff, E v) {
+    *reinterpret_cast<E *>(reinterpret_cast<char *>(reinterpret_cast<E *>(base) + row) + voff) = v;
+}
+
+template <int P>
+struct Elem {
+    using type = float2;
+};
+template <>
+struct Elem<MPMC_FP64> {
+    using type = double2;
+};
+template <>
+struct Elem<MPMC_FP16S> {
+    using type = __half2;
+};
+
+template <int P, bool UNI>
+__device__ __forceinline__ cpx<typename Store<P>::real> ldspin(const void *b, const float *bsc, long sn, int k,
+                                                                int N, uint32_t r) {
+    using T = typename Store<P>::real;
+    const long row = (sn * 12 + k) * (long)N;
+    if constexpr (P == MPMC_FP16S) {
+        const float2 f = __half22float2(at<__half2, UNI>(b, row, r * 4u));
+        const float sc = at<float, UNI>(bsc, sn * (long)N, r * 4u);
+        return mk(f.x * sc, f.y * sc);
+    } else if constexpr (P == MPMC_FP32) {
+        const float2 v = at<float2, UNI>(b, row, r * 8u);
+        return mk((T)v.x, (T)v.y);
     } else {
-        float2 v = reinterpret_cast<const float2 *>(links)[idx];
+        const double2 v = at<double2, UNI>(b, row, r * 16u);
         return mk(v.x, v.y);
     }
 }
 
-template <int P, int MU, bool FWD>
-__device__ __forceinline__ void hop(const WParams &p, long s, int r, cpx<typename Store<P>::real> acc[4][3]) {
-    using T = typename Store<P>::real;
-    using Pr = Proj<MU>;
-    const int raw = p.nbr[s * 8 + (FWD ? 0 : 4) + MU];
-    const long sn = (long)(raw & 0x7fffffff);
-    const T bsign = raw < 0 ? T(-1) : T(1);
-    // (1 - g gamma) forward, (1 + g gamma) backward
-    const T sg = FWD ? T(p.g) : T(-p.g);
-    cpx<T> psi[4][3];
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            auto v = Store<P>::ld(p.b.d, p.b.sc, (sn * 12 + sp * 3 + c) * p.N + r, sn * p.N + r);
-            psi[sp][c] = mk((T)v.re, (T)v.im);
-        }
-    cpx<T> h[2][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        h[0][c] = psi[0][c] + sg * mulc<Pr::c0>(psi[Pr::j0][c]);
-        h[1][c] = psi[1][c] + sg * mulc<Pr::c1>(psi[Pr::j1][c]);
+template <int P, bool UNI>
+__device__ __forceinline__ void stspin(void *o, long s, int k, int N, uint32_t r, cpx<typename Store<P>::real> v) {
+    const long row = (s * 12 + k) * (long)N;
+    if constexpr (P == MPMC_FP32) {
+        at_w<float2, UNI>(o, row, r * 8u, make_float2(v.re, v.im));
+    } else {
+        at_w<double2, UNI>(o, row, r * 16u, make_double2(v.re, v.im));
     }
-    // link of this hop: U_mu(x) forward, U_mu(x-mu)^H backward
-    const long lb = ((FWD ? s : sn) * 4 + MU) * 9;
-    cpx<T> u[3][3];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) u[i / 3][i % 3] = ldlink<T>(p.links, lb + i);
-    cpx<T> uh[2][3];
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            cpx<T> t = mk(T(0), T(0));
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb) {
-                if constexpr (FWD) t = t + u[a][bb] * h[q][bb];
-                else t = t + conjmul(u[bb][a], h[q][bb]);
-            }
-            uh[q][a] = bsign * t;
-        }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        acc[0][a] = acc[0][a] + uh[0][a];
-        acc[1][a] = acc[1][a] + uh[1][a];
-        acc[2][a] = acc[2][a] + sg * mulc<Pr::d2>(uh[Pr::k2][a]);
-        acc[3][a] = acc[3][a] + sg * mulc<Pr::d3>(uh[Pr::k3][a]);
+}
+
+// Buffer-resource access for the uniform kernels: one 4-SGPR descriptor per
+// site covers its 12 x N elements; component k sits at the scalar offset
+// k*N*sizeof(element) and the lane's right-hand side at the shared VGPR offset
+// r*sizeof(element).  Out-of-range accesses return 0 (hardware bounds check).
+// Values cross the builtins as whole vectors (bit_cast of the full vector).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufWord3 = 0x00020000;   // gfx9-family raw buffer descriptor word 3
+
+template <int P>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t site_rsrc(const void *base, long site, int N) {
+    constexpr int es = P == MPMC_FP64 ? 16 : 8;
+    const char *p = reinterpret_cast<const char *>(base) + site * 12L * N * es;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, 12 * N * es, kBufWord3);
+}
+
+template <int P>
+__device__ __forceinline__ cpx<typename Store<P>::real> ldbuf(__amdgpu_buffer_rsrc_t rs, int k, int N, uint32_t r) {
+    if constexpr (P == MPMC_FP64) {
+        const f64x2 v = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(r * 16u), k * N * 16, 0));
+        return mk(v.x, v.y);
+    } else {
+        const f32x2 v = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)(r * 8u), k * N * 8, 0));
+        return mk(v.x, v.y);
     }
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void k_wilson(WParams p) {
-    using T = typename Store<P>::real;
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    const long t = (long)tile * blockDim.x + threadIdx.x;
-    if (t >= p.V * p.N) return;
-    const long s = t / p.N;
-    const int r = (int)(t - s * p.N);
+__device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t rs, int k, int N, uint32_t r,
+                                      cpx<typename Store<P>::real> v) {
+    if constexpr (P == MPMC_FP64) {
+        f64x2 d;
+        d.x = v.re;
+        d.y = v.im;
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4v, d), rs, (int)(r * 16u), k * N * 16, 0);
+    } else {
+        f32x2 d;
+        d.x = v.re;
+        d.y = v.im;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, d), rs, (int)(r * 8u), k * N * 8, 0);
+    }
+}
 
-    cpx<T> acc[4][3];
+// Per-site accessor: buffer resource in the uniform FP32/FP64 kernels, plain
+// global addressing otherwise.
+template <int P, bool UNI>
+struct SiteAcc {
+    static constexpr bool kBuf = UNI && P != MPMC_FP16S;
+    __amdgpu_buffer_rsrc_t rs;
+    const void *b;
+    const float *bsc;
+    long site;
+    int N;
+    uint32_t r;
+    __device__ __forceinline__ SiteAcc(const void *b_, const float *bsc_, long site_, int N_, uint32_t r_)
+        : b(b_), bsc(bsc_), site(site_), N(N_), r(r_) {
+        if constexpr (kBuf) rs = site_rsrc<P>(b_, site_, N_);
+    }
+    __device__ __forceinline__ cpx<typename Store<P>::real> ld(int k) const {
+        if constexpr (kBuf) return ldbuf<P>(rs, k, N, r);
+        else return ldspin<P, UNI>(b, bsc, site, k, N, r);
+    }
+    __device__ __forceinline__ void st(int k, cpx<typename Store<P>::real> v) const {
+        if constexpr (kBuf) stbuf<P>(rs, k, N, r, v);
+        else stspin<P, UNI>(const_cast<void *>(b), site, k, N, r, v);
+    }
+};
+
+// One hop split in two so consecutive hops can be software-pipelined: fetch()
+// issues the neighbour's 12 spinor loads and the link's 9 loads; apply() does
+// the projection, the SU(3) multiply and the accumulation.
+template <int P>
+struct HopData {
+    using T = typename Store<P>::real;
+    cpx<T> psi[12];
+    cpx<T> u[9];       // generic kernels: the link, per lane
+    uint32_t lw[2];    // uniform kernels: the link spread over lanes (dword i of the link in lane i)
+    T bsign;
+};
+
+// Uniform kernels load a link with ONE vector load in which lane i fetches
+// dword i of the 18 (FP32) or 36 (FP64) dwords; the values move to SGPRs with
+// v_readlane at use.  One VGPR per link in flight, and its completion is
+// tracked in order with the spinor loads (scalar loads complete out of order,
+// which would make each hop wait for the prefetched next link).
+template <int P>
+__device__ __forceinline__ void load_link_lanes(const typename LinkT<P>::type *lk, uint32_t lw[2]) {
+    const uint32_t *d = reinterpret_cast<const uint32_t *>(lk);
+    const unsigned lane = threadIdx.x & 63u;
+    if constexpr (P == MPMC_FP64) {
+        lw[0] = d[lane < 36u ? lane : 0u];
+    } else {
+        lw[0] = d[lane < 18u ? lane : 0u];
+    }
+}
+
+template <int P>
+__device__ __forceinline__ cpx<typename Store<P>::real> link_lane(const uint32_t lw[2], int i) {
+    if constexpr (P == MPMC_FP64) {
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)lw[0], 4 * i + 0);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)lw[0], 4 * i + 1);
+        const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)lw[0], 4 * i + 2);
+        const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)lw[0], 4 * i + 3);
+        return mk(__builtin_bit_cast(double, ((uint64_t)b << 32) | a), __builtin_bit_cast(double, ((uint64_t)d << 32) | c));
+    } else {
+        const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)lw[0], 2 * i + 0);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)lw[0], 2 * i + 1);
+        return mk(__builtin_bit_cast(float, a), __builtin_bit_cast(float, b));
+    }
+}
+
+template <int P, bool UNI, int MU, bool FWD>
+__device__ __forceinline__ void fetch(const WIn<P> &in, long s, int r, int N, HopData<P> &H) {
+    using T = typename Store<P>::real;
+    const int raw = in.nbr[s * 8 + (FWD ? 0 : 4) + MU];
+    const long sn = (long)(raw & 0x7fffffff);
+    H.bsign = raw < 0 ? T(-1) : T(1);
+    const SiteAcc<P, UNI> A(in.b, in.bsc, sn, N, (uint32_t)r);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) H.psi[k] = A.ld(k);
+    const auto *lk = in.links + ((FWD ? s : sn) * 4 + MU) * 9;
+    if constexpr (UNI) {
+        load_link_lanes<P>(lk, H.lw);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const auto lv = lk[i];
+            H.u[i] = mk((T)lv.x, (T)lv.y);
+        }
+    }
+}
+
+template <int P, bool UNI, int MU, bool FWD>
+__device__ __forceinline__ void apply(const HopData<P> &H, float g, cpx<typename Store<P>::real> acc[4][3]) {
+    using T = typename Store<P>::real;
+    using Pr = Proj<MU>;
+    const T sg = FWD ? T(g) : T(-g);   // (1 - g gamma) forward, (1 + g gamma) backward
+    cpx<T> h[2][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        h[0][c] = H.psi[0 * 3 + c] + sg * mulc<Pr::c0>(H.psi[Pr::j0 * 3 + c]);
+        h[1][c] = H.psi[1 * 3 + c] + sg * mulc<Pr::c1>(H.psi[Pr::j1 * 3 + c]);
+    }
+    cpx<T> uh[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        cpx<T> t0 = mk(T(0), T(0)), t1 = mk(T(0), T(0));
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+            // forward: U[a][bb]; backward: conj(U[bb][a])
+            const int li = FWD ? a * 3 + bb : bb * 3 + a;
+            cpx<T> lv;
+            if constexpr (UNI) lv = link_lane<P>(H.lw, li);
+            else lv = H.u[li];
+            const cpx<T> u = FWD ? lv : cconj(lv);
+            t0 = t0 + u * h[0][bb];
+            t1 = t1 + u * h[1][bb];
+        }
+        uh[0][a] = t0;
+        uh[1][a] = t1;
+    }
+    // the boundary sign folds into the accumulation coefficients (FMA operands)
+    const T c01 = H.bsign, c23 = H.bsign * sg;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[0][a] = acc[0][a] + c01 * uh[0][a];
+        acc[1][a] = acc[1][a] + c01 * uh[1][a];
+        acc[2][a] = acc[2][a] + c23 * mulc<Pr::d2>(uh[Pr::k2][a]);
+        acc[3][a] = acc[3][a] + c23 * mulc<Pr::d3>(uh[Pr::k3][a]);
+    }
+}
+
+// acc = sum over the 8 hops (the hopping term H b at (s, r)).  Two HopData
+// buffers alternate: the loads of hop i+1 are in flight while hop i computes.
+#define MPMC_FENCE __builtin_amdgcn_sched_barrier(0)
+template <int P, bool UNI>
+__device__ __forceinline__ void hopping(const WIn<P> &in, long s, int r, int N, float g,
+                                        cpx<typename Store<P>::real> acc[4][3]) {
+    using T = typename Store<P>::real;
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[sp][c] = mk(T(0), T(0));
-    hop<P, 0, true>(p, s, r, acc);
-    hop<P, 0, false>(p, s, r, acc);
-    hop<P, 1, true>(p, s, r, acc);
-    hop<P, 1, false>(p, s, r, acc);
-    hop<P, 2, true>(p, s, r, acc);
-    hop<P, 2, false>(p, s, r, acc);
-    hop<P, 3, true>(p, s, r, acc);
-    hop<P, 3, false>(p, s, r, acc);
+    HopData<P> A, B;
+    fetch<P, UNI, 0, true>(in, s, r, N, A);
+    MPMC_FENCE;
+    fetch<P, UNI, 0, false>(in, s, r, N, B);
+    MPMC_FENCE;
+    apply<P, UNI, 0, true>(A, g, acc);
+    MPMC_FENCE;
+    fetch<P, UNI, 1, true>(in, s, r, N, A);
+    MPMC_FENCE;
+    apply<P, UNI, 0, false>(B, g, acc);
+    MPMC_FENCE;
+    fetch<P, UNI, 1, false>(in, s, r, N, B);
+    MPMC_FENCE;
+    apply<P, UNI, 1, true>(A, g, acc);
+    MPMC_FENCE;
+    fetch<P, UNI, 2, true>(in, s, r, N, A);
+    MPMC_FENCE;
+    apply<P, UNI, 1, false>(B, g, acc);
+    MPMC_FENCE;
+    fetch<P, UNI, 2, false>(in, s, r, N, B);
+    MPMC_FENCE;
+    apply<P, UNI, 2, true>(A, g, acc);
+    MPMC_FENCE;
+    fetch<P, UNI, 3, true>(in, s, r, N, A);
+    MPMC_FENCE;
+    apply<P, UNI, 2, false>(B, g, acc);
+    MPMC_FENCE;
+    fetch<P, UNI, 3, false>(in, s, r, N, B);
+    MPMC_FENCE;
+    apply<P, UNI, 3, true>(A, g, acc);
+    MPMC_FENCE;
+    apply<P, UNI, 3, false>(B, g, acc);
+}
+#undef MPMC_FENCE
 
-    const T kap = (T)p.kappa;
-    const cpx<T> al = mk((T)p.alpha.x, (T)p.alpha.y);
-    const cpx<T> be = mk((T)p.beta.x, (T)p.beta.y);
-    const cpx<T> ga = mk((T)p.gamma.x, (T)p.gamma.y);
-    cpx<T> o[12];
+// (site, rhs) of this thread.  UNI (N % 64 == 0): each wavefront covers 64
+// consecutive right-hand sides of one site, so the site follows from the
+// wavefront's first thread with scalar arithmetic.
+template <bool UNI>
+__device__ __forceinline__ bool locate(long V, int N, long &s, int &r) {
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const unsigned total = (unsigned)(V * N);
+    if constexpr (UNI) {
+        const unsigned w0 = tile * 256u + ((unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
+        if (w0 >= total) return false;
+        const unsigned ss = w0 / (unsigned)N;
+        s = (long)ss;
+        r = (int)(w0 - ss * (unsigned)N + (threadIdx.x & 63u));
+    } else {
+        const unsigned t = tile * 256u + threadIdx.x;
+        if (t >= total) return false;
+        const unsigned ss = t / (unsigned)N;
+        s = (long)ss;
+        r = (int)(t - ss * (unsigned)N);
+    }
+    return true;
+}
+
+struct WOut {
+    void *out;
+    float *osc;
+    const void *a;          // additive term (nullptr: none; == b: reuse the operand)
+    const float *asc;
+    void *y;                // y += gamma * out (nullptr: none)
+    double kappa;
+    double2 alpha, beta, gamma;
+    float g;
+    int theta;
+    int a_is_b;
+};
+
+// Occupancy targets: FP32/FP16S kernels fit 4 wavefronts per SIMD (<= 128
+// VGPRs), FP64 kernels 2 (<= 256 VGPRs), without scratch spills.
+template <int P, bool UNI>
+struct Occ {
+    static constexpr int wpe = (UNI && P != MPMC_FP64) ? 3 : 1;
+};
+
+template <int P, bool UNI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI>::wpe))) void k_wilson(const void *__restrict__ b, const float *__restrict__ bsc,
+                                                const int *__restrict__ nbr,
+                                                const typename LinkT<P>::type *__restrict__ links, WOut o, long V,
+                                                int N) {
+    using T = typename Store<P>::real;
+    const WIn<P> in{b, bsc, nbr, links};
+    long s;
+    int r;
+    if (!locate<UNI>(V, N, s, r)) return;
+    cpx<T> acc[4][3];
+    hopping<P, UNI>(in, s, r, N, o.g, acc);
+    const T kap = (T)o.kappa;
+    const cpx<T> al = mk((T)o.alpha.x, (T)o.alpha.y);
+    const cpx<T> be = mk((T)o.beta.x, (T)o.beta.y);
+    cpx<T> res[12];
+    const SiteAcc<P, UNI> B(in.b, in.bsc, s, N, (uint32_t)r);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-        const long e = (s * 12 + k) * p.N + r;
-        auto bv = Store<P>::ld(p.b.d, p.b.sc, e, s * p.N + r);
-        cpx<T> mb = mk((T)bv.re - kap * acc[k / 3][k % 3].re, (T)bv.im - kap * acc[k / 3][k % 3].im);
-        if (p.theta && k >= 6) mb = mk(-mb.re, -mb.im);
+        const cpx<T> bt = B.ld(k);
+        cpx<T> mb = bt - kap * acc[k / 3][k % 3];
+        if (o.theta && k >= 6) mb = mk(-mb.re, -mb.im);
         cpx<T> v = be * mb;
-        if (p.a.d) {
-            auto av = Store<P>::ld(p.a.d, p.a.sc, e, s * p.N + r);
-            v = v + al * mk((T)av.re, (T)av.im);
+        if (o.a_is_b) {
+            v = v + al * bt;
+        } else if (o.a) {
+            v = v + al * SiteAcc<P, UNI>(o.a, o.asc, s, N, (uint32_t)r).ld(k);
         }
-        o[k] = v;
+        res[k] = v;
     }
     if constexpr (P == MPMC_FP16S) {
         float mx = 0.f;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) mx = fmaxf(mx, fmaxf(fabsf(o[k].re), fabsf(o[k].im)));
+        for (int k = 0; k < 12; ++k) mx = fmaxf(mx, fmaxf(fabsf(res[k].re), fabsf(res[k].im)));
         const float inv = mx > 0.f ? 1.0f / mx : 0.f;
-        __half2 *d = reinterpret_cast<__half2 *>(p.out.d);
+        __half2 *d = reinterpret_cast<__half2 *>(o.out);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) d[(s * 12 + k) * p.N + r] = __floats2half2_rn(o[k].re * inv, o[k].im * inv);
-        p.out.sc[s * p.N + r] = mx;
+        for (int k = 0; k < 12; ++k) d[(s * 12 + k) * N + r] = __floats2half2_rn(res[k].re * inv, res[k].im * inv);
+        o.osc[s * N + r] = mx;
     } else {
+        const SiteAcc<P, UNI> O(o.out, nullptr, s, N, (uint32_t)r);
 #pragma unroll
-        for (int k = 0; k < 12; ++k) Store<P>::st(p.out.d, (s * 12 + k) * p.N + r, o[k]);
-        if (p.y.d) {
+        for (int k = 0; k < 12; ++k) O.st(k, res[k]);
+        if (o.y) {
+            const cpx<T> ga = mk((T)o.gamma.x, (T)o.gamma.y);
+            const SiteAcc<P, UNI> Y(o.y, nullptr, s, N, (uint32_t)r);
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                const long e = (s * 12 + k) * p.N + r;
-                auto yv = Store<P>::ld(p.y.d, nullptr, e, 0);
-                Store<P>::st(p.y.d, e, mk((T)yv.re, (T)yv.im) + ga * o[k]);
-            }
+            for (int k = 0; k < 12; ++k) Y.st(k, Y.ld(k) + ga * res[k]);
         }
     }
+}
+
+// ------------------------------------------------- fused level step --
+// w' = w - c M w for a batch whose rhs r is noise vector eta_r (2-bit codes in
+// codes[s*N + r]); partial[blk][rl] += cnext * sum_k conj(eta_k) (Theta w')_k
+// summed over the block's sites.  Requires N % 64 == 0 (uniform wavefronts).
+// A block of 256 threads covers spb = max(1, 256/N) sites and rpb = min(N, 256)
+// right-hand sides starting at rhs (blk*256) % N.
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, true>::wpe))) void k_wilson_dot(const void *__restrict__ b, const int *__restrict__ nbr,
+                                                    const typename LinkT<P>::type *__restrict__ links,
+                                                    void *__restrict__ out, const uint32_t *__restrict__ codes,
+                                                    double2 c, double2 cnext, double kappa, int theta,
+                                                    double2 *__restrict__ partial, long V, int N, int first_step) {
+    using T = typename Store<P>::real;
+    const WIn<P> in{b, nullptr, nbr, links};
+    __shared__ double2 red[256];
+    long s;
+    int r;
+    const bool live = locate<true>(V, N, s, r);
+    cpx<double> dot = mk(0.0, 0.0);
+    if (live) {
+        cpx<T> acc[4][3];
+        hopping<P, true>(in, s, r, N, 1.0f, acc);
+        const uint32_t code = codes[s * N + r];
+        const T kap = (T)kappa;
+        const cpx<T> cc = mk((T)c.x, (T)c.y);
+        const SiteAcc<P, true> W(in.b, nullptr, s, N, (uint32_t)r), O(out, nullptr, s, N, (uint32_t)r);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const cpx<T> w = W.ld(k);
+            const cpx<T> mw = w - kap * acc[k / 3][k % 3];
+            const cpx<T> wn = w - cc * mw;
+            O.st(k, wn);
+            // conj(eta_k) * wn, eta_k = i^sym: conj(i^sym) = i^(4-sym)
+            const uint32_t sym = (code >> (2 * k)) & 3u;
+            cpx<double> v = mk((double)wn.re, (double)wn.im);
+            if (sym == 1) v = times_mi(v);
+            else if (sym == 2) v = mk(-v.re, -v.im);
+            else if (sym == 3) v = times_i(v);
+            if (theta && k >= 6) v = mk(-v.re, -v.im);
+            dot = dot + v;
+        }
+    }
+    red[threadIdx.x] = make_double2(dot.re, dot.im);
+    __syncthreads();
+    const int rpb = N < 256 ? N : 256;
+    const int spb = 256 / rpb;
+    if ((int)threadIdx.x < rpb) {
+        double2 sum = red[threadIdx.x];
+        for (int q = 1; q < spb; ++q) {
+            sum.x += red[threadIdx.x + q * rpb].x;
+            sum.y += red[threadIdx.x + q * rpb].y;
+        }
+        const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+        const cpx<double> term = mk(cnext.x, cnext.y) * mk(sum.x, sum.y);
+        double2 *pp = partial + (long)tile * rpb + threadIdx.x;
+        if (first_step) {
+            *pp = make_double2(term.re, term.im);
+        } else {
+            double2 old = *pp;
+            *pp = make_double2(old.x + term.re, old.y + term.im);
+        }
+    }
+}
+
+// out[r] = sum over blocks covering rhs r of partial (fixed order)
+__global__ void k_dot_finish(const double2 *__restrict__ partial, int nblocks, int N, double2 *__restrict__ out,
+                             int accumulate, double sign) {
+    __shared__ double2 red[256];
+    const int r = blockIdx.x;
+    const int rpb = N < 256 ? N : 256;
+    const int per = N / rpb;              // blocks cycle through N/rpb rhs ranges
+    const int rr = r % rpb, range = r / rpb;
+    double2 a = make_double2(0, 0);
+    for (int b = range + per * threadIdx.x; b < nblocks; b += per * blockDim.x) {
+        const double2 v = partial[(long)b * rpb + rr];
+        a.x += v.x;
+        a.y += v.y;
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[threadIdx.x].x += red[threadIdx.x + h].x;
+            red[threadIdx.x].y += red[threadIdx.x + h].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (accumulate) {
+            out[r].x += sign * red[0].x;
+            out[r].y += sign * red[0].y;
+        } else {
+            out[r] = make_double2(sign * red[0].x, sign * red[0].y);
+        }
+    }
+}
+
+// codes[s*N + r] = Z(4) symbols of noise vector first + r at site s
+__global__ void k_noise_codes(uint64_t seed, uint32_t stream, uint64_t first, uint32_t *__restrict__ codes, long V,
+                              int N) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= V * N) return;
+    const long s = t / N;
+    const int r = (int)(t - s * N);
+    codes[t] = z4_site_symbols(seed, stream, (uint32_t)(first + r), s);
+}
+
+// ------------------------------------------------------------- launch --
+
+static double spinor_bytes(int prec) { return prec == MPMC_FP64 ? 192.0 : (prec == MPMC_FP32 ? 96.0 : 52.0); }
+static double link_bytes(int prec) { return prec == MPMC_FP64 ? 576.0 : 288.0; }
+
+template <int P>
+static WIn<P> make_in(const mpmc_ctx *ctx, const void *b, int nrhs) {
+    WIn<P> in;
+    VecRef vb = vref(ctx, b, nrhs, P);
+    in.b = vb.d;
+    in.bsc = vb.sc;
+    in.nbr = ctx->nbr;
+    in.links = reinterpret_cast<const typename LinkT<P>::type *>(P == MPMC_FP64 ? (const void *)ctx->links64
+                                                                                 : (const void *)ctx->links32);
+    return in;
+}
+
+template <int P>
+static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs) {
+    const long work = ctx->V * nrhs;
+    const unsigned grid = grid_for(work, 256);
+    WIn<P> in = make_in<P>(ctx, b, nrhs);
+    if (nrhs % 64 == 0)
+        k_wilson<P, true><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs);
+    else
+        k_wilson<P, false><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs);
 }
 
 int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, void *y, int nrhs, int prec,
                        double2 alpha, double2 beta, double2 gamma, int dagger, int theta) {
     if (prec == MPMC_FP16S && y) return set_err(ctx, MPMC_EINVAL, "FP16S output cannot accumulate");
-    WParams p;
-    p.b = vref(ctx, b, nrhs, prec);
-    p.a = a ? vref(ctx, a, nrhs, prec) : VecRef{nullptr, nullptr};
-    p.out = vref(ctx, out, nrhs, prec);
-    p.y = y ? vref(ctx, y, nrhs, prec) : VecRef{nullptr, nullptr};
-    p.nbr = ctx->nbr;
-    p.links = prec == MPMC_FP64 ? (const void *)ctx->links64 : (const void *)ctx->links32;
-    p.V = ctx->V;
-    p.N = nrhs;
-    p.kappa = ctx->kappa;
-    p.alpha = alpha;
-    p.beta = beta;
-    p.gamma = gamma;
-    p.g = dagger ? -1.f : 1.f;
-    p.theta = theta;
-    const long work = ctx->V * nrhs;
-    const int B = 256;
-    const unsigned grid = grid_for(work, B);
-    if (prec == MPMC_FP64) k_wilson<MPMC_FP64><<<grid, B, 0, ctx->stream>>>(p);
-    else if (prec == MPMC_FP32) k_wilson<MPMC_FP32><<<grid, B, 0, ctx->stream>>>(p);
-    else k_wilson<MPMC_FP16S><<<grid, B, 0, ctx->stream>>>(p);
+    WOut o;
+    VecRef vo = vref(ctx, out, nrhs, prec);
+    o.out = vo.d;
+    o.osc = vo.sc;
+    VecRef va = a ? vref(ctx, a, nrhs, prec) : VecRef{nullptr, nullptr};
+    o.a = va.d;
+    o.asc = va.sc;
+    o.a_is_b = (a != nullptr && a == b) ? 1 : 0;
+    o.y = y;
+    o.kappa = ctx->kappa;
+    o.alpha = alpha;
+    o.beta = beta;
+    o.gamma = gamma;
+    o.g = dagger ? -1.f : 1.f;
+    o.theta = theta;
+    const int ev = timing_begin(ctx);
+    if (prec == MPMC_FP64) launch_w<MPMC_FP64>(ctx, b, o, nrhs);
+    else if (prec == MPMC_FP32) launch_w<MPMC_FP32>(ctx, b, o, nrhs);
+    else launch_w<MPMC_FP16S>(ctx, b, o, nrhs);
     HIP_OR_RET(ctx, hipGetLastError());
+    if (ev >= 0) {
+        // algorithmic bytes: operand read once, a read once if distinct,
+        // out written once, y read and written, links once per site
+        const double sb = spinor_bytes(prec);
+        double per = 2 * sb;
+        if (a && a != b) per += sb;
+        if (y) per += 2 * sb;
+        timing_end(ctx, ev, prec, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
+    }
     ctx->mvps += (uint64_t)nrhs;
+    return MPMC_OK;
+}
+
+size_t wilson_dot_partial_count(const mpmc_ctx *ctx, int nrhs) {
+    const long blocks = (ctx->V * nrhs + 255) / 256;
+    return (size_t)blocks * (nrhs < 256 ? nrhs : 256);
+}
+
+int wilson_noise_codes(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, uint32_t *codes) {
+    const long work = ctx->V * nrhs;
+    k_noise_codes<<<grid_for(work, 256), 256, 0, ctx->stream>>>(seed, stream, first, codes, ctx->V, nrhs);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
+int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *codes, int nrhs, int prec, double2 c,
+                    double2 cnext, int theta, double *partial, int first_step) {
+    if (nrhs % 64 != 0 || (nrhs > 256 && nrhs % 256 != 0))
+        return set_err(ctx, MPMC_EINVAL, "fused level step needs nrhs %% 64 == 0 (and %% 256 above 256)");
+    const long work = ctx->V * nrhs;
+    const unsigned grid = grid_for(work, 256);
+    const int ev = timing_begin(ctx);
+    if (prec == MPMC_FP64) {
+        const WIn<MPMC_FP64> in = make_in<MPMC_FP64>(ctx, w, nrhs);
+        k_wilson_dot<MPMC_FP64><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                               ctx->kappa, theta, (double2 *)partial, ctx->V, nrhs,
+                                                               first_step);
+    } else if (prec == MPMC_FP32) {
+        const WIn<MPMC_FP32> in = make_in<MPMC_FP32>(ctx, w, nrhs);
+        k_wilson_dot<MPMC_FP32><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                               ctx->kappa, theta, (double2 *)partial, ctx->V, nrhs,
+                                                               first_step);
+    }
+    else
+        return set_err(ctx, MPMC_EINVAL, "fused level step supports FP64 and FP32");
+    HIP_OR_RET(ctx, hipGetLastError());
+    if (ev >= 0) {
+        // spinor read + write, 4-byte noise code, links once per site (the
+        // partial sums add 16 B per 256 threads and are not counted)
+        const double per = 2 * spinor_bytes(prec) + 4.0;
+        timing_end(ctx, ev, prec, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
+    }
+    ctx->mvps += (uint64_t)nrhs;
+    return MPMC_OK;
+}
+
+int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, double *out, int accumulate, double sign) {
+    const long blocks = (ctx->V * nrhs + 255) / 256;
+    k_dot_finish<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, (int)blocks, nrhs, (double2 *)out,
+                                                accumulate, sign);
+    HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
 

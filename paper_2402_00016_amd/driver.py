@@ -1,0 +1,190 @@
+"""Host-side driver of Multipolynomial Monte Carlo (Sec. 6-8).
+
+Only bookkeeping lives here; every vector operation is a libmpmc.so call.
+
+    Tr(Theta M^-1) = Tr(Theta(M^-1 - p_1)) + sum_l Tr(Theta(p_l - p_{l+1})) + Tr(Theta p_K)
+
+Each term is an independent Hutchinson Monte Carlo with its own noise stream
+(stream l for term l).  The polynomial-difference terms are deflated (Sec. 7)
+and carry the exact correction T_l = sum_i c_i u_i^H Theta z_i; the solve term
+uses the deflation set inside its solves.  The total standard error is
+sqrt(sum_l s_l^2 / N_l) with s_l^2 the complex sample variance.
+
+Random streams: level l uses stream l, the GMRES start vector of polynomial j
+uses stream 0x100 + j, the deflation start vector stream 0x200.
+"""
+import math
+import time
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+from . import mpmc
+
+
+@dataclass
+class Plan:
+    """One multipolynomial estimate.
+
+    degrees: polynomial degrees d_1 > d_2 > ... (degree D uses GMRES(D+1));
+    a degree given as (din, dout) is a double polynomial from GMRES(din+1)
+    inner and GMRES(dout+1) outer cycles (degree (din+1)(dout+1) - 1).
+    """
+    degrees: list
+    noises: int = 128                    # per level (fixed-count mode)
+    theta: int = mpmc.THETA_I
+    seed: int = 1
+    nev: int = 20                        # eigenpairs requested for deflation (0: none)
+    defl_m: int = 80                     # PP-Arnoldi steps
+    defl_pin_degree: int = 8             # degree of p_in for PP-Arnoldi
+    accept_tol: float = 1e-3
+    real_tol: float = 2e-4
+    poly_prec: int = mpmc.FP32           # precision of the polynomial levels
+    solve_inner_prec: int = mpmc.FP32    # inner precision of the main solves
+    solve_tol: float = 1e-8
+    solve_restart: int = 50
+    max_batch: int = 0                   # right-hand sides per launch (0: all noise of a level)
+    deflate_levels: bool = True
+
+
+@dataclass
+class LevelResult:
+    name: str
+    samples: np.ndarray
+    corr: complex
+    mvps: int
+    seconds: float
+
+    @property
+    def n(self):
+        return len(self.samples)
+
+    @property
+    def mean(self):
+        return complex(np.mean(self.samples))
+
+    @property
+    def var(self):
+        X = self.samples
+        return float(np.sum(np.abs(X - X.mean()) ** 2) / (len(X) - 1)) if len(X) > 1 else math.inf
+
+
+@dataclass
+class Estimate:
+    value: complex
+    stderr: float
+    levels: List[LevelResult]
+    setup_seconds: float
+    total_seconds: float
+    mvps: int
+    polys: list = field(default_factory=list)
+    defl_k: int = 0
+    info: dict = field(default_factory=dict)
+
+    def summary(self):
+        return dict(
+            trace=[self.value.real, self.value.imag], stderr=self.stderr, seconds=self.total_seconds,
+            setup_seconds=self.setup_seconds, mvps=self.mvps, deflated=self.defl_k,
+            levels=[dict(name=L.name, n=L.n, mean=[L.mean.real, L.mean.imag], var=L.var,
+                         corr=[L.corr.real, L.corr.imag], mvps=L.mvps, seconds=L.seconds)
+                    for L in self.levels],
+            **self.info)
+
+
+def build_polys(ctx, plan: Plan, defl=None):
+    """GMRES polynomials of the plan (highest degree first)."""
+    polys = []
+    for j, deg in enumerate(plan.degrees):
+        if isinstance(deg, (tuple, list)):
+            din, dout = deg
+            pin = ctx.gmres_poly(plan.seed, 0x100 + j, din + 1)
+            p = ctx.gmres_poly(plan.seed, 0x100 + j, dout + 1, inner=pin, defl=defl)
+        else:
+            p = ctx.gmres_poly(plan.seed, 0x100 + j, int(deg) + 1)
+        polys.append(p)
+    return polys
+
+
+def build_deflation(ctx, plan: Plan):
+    if plan.nev <= 0:
+        return None
+    pin = ctx.gmres_poly(plan.seed, 0x1FF, plan.defl_pin_degree + 1) if plan.defl_pin_degree > 0 else None
+    return ctx.deflate(pin, plan.seed, 0x200, plan.defl_m, plan.nev, plan.accept_tol, plan.real_tol)
+
+
+def combine(levels):
+    est = sum((L.mean + L.corr for L in levels), 0j)
+    var = sum(L.var / L.n for L in levels)
+    return est, math.sqrt(var)
+
+
+def run_levels(ctx, plan: Plan, polys, defl, noises=None, first=0):
+    """Samples of every term of the multipolynomial formula."""
+    noises = plan.noises if noises is None else noises
+    names = ["M^-1 - p1"] + ["p%d - p%d" % (i + 1, i + 2) for i in range(len(polys) - 1)] + ["p%d" % len(polys)]
+    uppers = [None] + polys
+    lowers = polys + [None]
+    out = []
+    for l, (up, lo) in enumerate(zip(uppers, lowers)):
+        d = defl if (up is not None and lo is not None and plan.deflate_levels) else (defl if up is None else None)
+        t0 = time.perf_counter()
+        X, T, mv = ctx.level(up, lo, d, plan.theta, plan.seed, l, first, noises, prec=plan.poly_prec,
+                             max_batch=plan.max_batch, solve_tol=plan.solve_tol, solve_restart=plan.solve_restart,
+                             solve_inner_prec=plan.solve_inner_prec)
+        out.append(LevelResult(names[l], X, T, mv, time.perf_counter() - t0))
+    return out
+
+
+def estimate(ctx, plan: Plan, sync=None) -> Estimate:
+    """Full estimate: polynomials, deflation, all levels (fixed noise counts)."""
+    sync = sync or (lambda: None)
+    mv0 = ctx.mvps
+    t0 = time.perf_counter()
+    defl = build_deflation(ctx, plan)
+    polys = build_polys(ctx, plan)
+    sync()
+    t1 = time.perf_counter()
+    levels = run_levels(ctx, plan, polys, defl)
+    sync()
+    t2 = time.perf_counter()
+    est, se = combine(levels)
+    return Estimate(est, se, levels, t1 - t0, t2 - t0, ctx.mvps - mv0, polys=polys,
+                    defl_k=defl.k if defl is not None else 0)
+
+
+def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_every=3, max_noises=4096):
+    """Adaptive stopping (Sec. 8): each Monte Carlo term stops once its standard
+    error is below eps / sqrt(#terms), with minimum counts 2 (solve term),
+    3 (first difference), 6 (later terms) and checks every `check_every` noises."""
+    mv0 = ctx.mvps
+    t0 = time.perf_counter()
+    defl = build_deflation(ctx, plan)
+    polys = build_polys(ctx, plan)
+    t_setup = time.perf_counter() - t0
+    nterms = len(polys) + 1
+    target = eps / math.sqrt(nterms)
+    levels = []
+    uppers = [None] + polys
+    lowers = polys + [None]
+    for l, (up, lo) in enumerate(zip(uppers, lowers)):
+        d = defl if (up is not None and lo is not None and plan.deflate_levels) else (defl if up is None else None)
+        n0 = min_counts[min(l, len(min_counts) - 1)]
+        X = np.zeros(0, dtype=np.complex128)
+        corr, mv, secs = 0j, 0, 0.0
+        while True:
+            want = n0 if len(X) == 0 else check_every
+            ts = time.perf_counter()
+            Xn, corr, m = ctx.level(up, lo, d, plan.theta, plan.seed, l, len(X), want, prec=plan.poly_prec,
+                                    solve_tol=plan.solve_tol, solve_restart=plan.solve_restart,
+                                    solve_inner_prec=plan.solve_inner_prec)
+            secs += time.perf_counter() - ts
+            mv += m
+            X = np.concatenate([X, Xn])
+            var = np.sum(np.abs(X - X.mean()) ** 2) / (len(X) - 1) if len(X) > 1 else math.inf
+            if math.sqrt(var / len(X)) <= target or len(X) >= max_noises:
+                break
+        levels.append(LevelResult("term %d" % l, X, corr, mv, secs))
+    est, se = combine(levels)
+    return Estimate(est, se, levels, t_setup, time.perf_counter() - t0, ctx.mvps - mv0, polys=polys,
+                    defl_k=defl.k if defl is not None else 0)

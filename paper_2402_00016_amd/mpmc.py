@@ -38,6 +38,8 @@ _SIGS = {
     "mpmc_vector_bytes": ([_vp, _i, _i, _psz], _i),
     "mpmc_mvp_count": ([_vp, _pu64], _i),
     "mpmc_mvp_reset": ([_vp], _i),
+    "mpmc_timing_enable": ([_vp, _i], _i),
+    "mpmc_timing_read": ([_vp, _i, _pu64, _pd, _pd], _i),
     "mpmc_pack": ([_vp, _vp, _vp, _i, _i], _i),
     "mpmc_unpack": ([_vp, _vp, _vp, _i, _i], _i),
     "mpmc_noise": ([_vp, _u64, _u32, _u64, _i, _i, _vp], _i),
@@ -117,6 +119,16 @@ def mpmc_mvp_count(ctx):
 
 def mpmc_mvp_reset(ctx):
     _check(_L.mpmc_mvp_reset(ctx), ctx)
+
+
+def mpmc_timing_enable(ctx, on):
+    _check(_L.mpmc_timing_enable(ctx, int(on)), ctx)
+
+
+def mpmc_timing_read(ctx, prec):
+    n, ms, by = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_double()
+    _check(_L.mpmc_timing_read(ctx, int(prec), ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by)), ctx)
+    return n.value, ms.value, by.value
 
 
 def mpmc_pack(ctx, canon, internal, nrhs, prec):

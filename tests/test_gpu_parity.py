@@ -312,3 +312,53 @@ def test_plain_4444_estimate_vs_dense_exact(f44):
     ms, vs = OES.level_stats(Xs)
     assert abs(ms - np.trace(Minv - Pm)) < 3.5 * np.sqrt(vs / 32) + 1e-9
     assert vs < 1e-3 * v
+
+
+# ------------------------------------------------- fused level steps --
+
+@pytest.mark.parametrize("N", [64, 128, 256, 512])
+def test_fused_level_parity(f44, N):
+    """Batches that are multiples of 64 use the fused step (eta^H Theta w
+    accumulated inside the Wilson kernel): per-sample parity with the oracle,
+    single and double polynomials, Theta = I and g5, FP64."""
+    dims, kappa, U, op, ctx = f44
+    b = z4_noise(1, 0x100, 0, op.n)
+    P1, _, _ = OK.gmres_poly(op, b, 9)
+    D, _, _ = OP.double_poly(op, b, 3, 4)
+    g1 = ctx.poly_from_roots(P1.roots)
+    gi = ctx.poly_from_roots(D.inner.roots)
+    gd = ctx.poly_from_roots(D.roots, inner=gi)
+    for theta, th in (("I", 0), ("g5", 1)):
+        X, _, mv = ctx.level(gd, g1, None, th, 5, 2, 7, N)
+        Xr, _ = OES.level_samples(op, D, P1, None, theta, 5, 2, 7, N)
+        assert rel(X, Xr) < 1e-10
+        assert mv == N * (11 + 8)
+
+
+def test_fused_level_fp32_bias_bound(f44):
+    """FP32 fused steps: per-sample error bounded by the FP32 rounding of the
+    recurrence (||eta||^2 * d * 1e-6 relative to the sample scale)."""
+    dims, kappa, U, op, ctx = f44
+    b = z4_noise(1, 0x100, 0, op.n)
+    P1, _, _ = OK.gmres_poly(op, b, 17)
+    g1 = ctx.poly_from_roots(P1.roots)
+    N = 64
+    X, _, _ = ctx.level(g1, None, None, 0, 9, 0, 0, N, prec=FP32)
+    Xr, _ = OES.level_samples(op, P1, None, None, "I", 9, 0, 0, N)
+    assert np.max(np.abs(X - Xr)) < op.n * 17 * 1e-6
+
+
+def test_apply_poly_fp32_ignores_garbage_output(f44):
+    """Regression: the output buffer's old contents (here NaN) never leak in."""
+    dims, kappa, U, op, ctx = f44
+    ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 9)
+    P = ctx.poly_from_roots(ref.roots)
+    N = 128
+    eta = ctx.noise(4, 1, 0, N, FP32)
+    y = ctx.vector(N, FP32)
+    y.view(torch.float32).fill_(float("nan"))
+    ctx.apply_poly(P, eta, N, FP32, out=y)
+    got = host(ctx.unpack(y, N, FP32))
+    assert np.all(np.isfinite(got))
+    want = np.stack([OP.apply_p(op, ref.roots, e) for e in z4_noise_batch(4, 1, 0, 2, op.n)])
+    assert rel(got[:2], want) < 2e-5
