@@ -174,6 +174,20 @@ void mpmc_poly_destroy(mpmc_poly *p);
 int mpmc_apply_poly(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y,
                     int nrhs, int prec);
 
+/* Exact Tr(Theta p(M)) by probing (Sec. 6: the last term of the
+ * multipolynomial formula is computed exactly with probing).  Sites are
+ * coloured by c(x) = sum_mu (x_mu mod period[mu]) prod_{nu<mu} period[nu]
+ * (period[mu] must divide L_mu); probe vector (c, alpha) is 1 on spin-colour
+ * component alpha of every site of colour c.  The sum of v^H Theta p(M) v over
+ * the 12 * prod(period) probes is the exact trace when, for every mu with
+ * period[mu] < L_mu, deg(p) < period[mu] <= L_mu / 2; *exact_host reports
+ * whether that holds (period[mu] = L_mu for all mu is always exact).
+ * prec: FP64 or FP32; probes are processed max_batch (rounded to a multiple
+ * of 12, 0 = 192) at a time.  trace_host: complex double; mvps_host may be NULL.
+ * Synchronises. */
+int mpmc_poly_trace(mpmc_ctx *ctx, const mpmc_poly *p, int theta, const int period[4], int prec,
+                    int max_batch, double *trace_host, int *exact_host, uint64_t *mvps_host);
+
 /* ---------------------------------------------------------------- deflation */
 
 /* Eigenpairs for deflation (Sec. 7, acceptance rule of Sec. 8): m steps of
@@ -195,6 +209,9 @@ int mpmc_defl_create(mpmc_ctx *ctx, const double *lam_host, const void *Z, const
 /* Export: lam_host [k] and, if non-NULL, Z/U canonical [k][n] device buffers. */
 int mpmc_defl_export(const mpmc_defl *d, double *lam_host, void *Z, void *U, int *k);
 void mpmc_defl_destroy(mpmc_defl *d);
+/* Keep only the first k eigentriples (they are stored by increasing |lambda|),
+ * e.g. the k lowest of a larger accepted set.  k larger than the set is a no-op. */
+int mpmc_defl_keep(mpmc_defl *d, int k);
 
 /* -------------------------------------------------------------------- solve */
 

@@ -264,6 +264,90 @@ __global__ void k_scale_acc(const double2 *t, int N, double2 c, double sign, dou
     acc[r].y += sign * (c.x * v.y + c.y * v.x);
 }
 
+// ---- single vectors (nrhs == 1): one thread per complex element ----
+// partial[j][blk] = sum over this block's elements of conj(V_j) Theta w
+template <int P>
+__global__ __launch_bounds__(256) void k_multidot1(VecRef Vb, long vstride, int nv, VecRef w, long n, int theta,
+                                                   double2 *__restrict__ partial, int NB) {
+    using T = typename Store<P>::real;
+    __shared__ double2 red[JB][256];
+    const int j0 = blockIdx.y * JB;
+    cpx<double> acc[JB];
+#pragma unroll
+    for (int q = 0; q < JB; ++q) acc[q] = mk(0.0, 0.0);
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)NB * 256) {
+        cpx<double> wv = ldd<P>(w, e, 0);
+        if (theta && (e % 12) >= 6) wv = mk(-wv.re, -wv.im);
+#pragma unroll
+        for (int q = 0; q < JB; ++q) {
+            const int j = j0 + q;
+            if (j < nv) {
+                VecRef vj;
+                vj.d = (char *)Vb.d + (size_t)j * vstride * sizeof(T) * 2;
+                vj.sc = nullptr;
+                acc[q] = acc[q] + conjmul(ldd<P>(vj, e, 0), wv);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < JB; ++q) red[q][threadIdx.x] = make_double2(acc[q].re, acc[q].im);
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+#pragma unroll
+            for (int q = 0; q < JB; ++q) {
+                red[q][threadIdx.x].x += red[q][threadIdx.x + h].x;
+                red[q][threadIdx.x].y += red[q][threadIdx.x + h].y;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < JB; ++q)
+            if (j0 + q < nv) partial[(long)(j0 + q) * NB + blockIdx.x] = red[q][0];
+    }
+}
+
+// w += sign * sum_j h[j*ldh] V_j ; optional partial[blk] = sum |w|^2
+template <int P>
+__global__ __launch_bounds__(256) void k_multiaxpy1(VecRef Vb, long vstride, int nv, VecRef w, long n,
+                                                    const double2 *__restrict__ h, int ldh, double sign,
+                                                    double2 *__restrict__ partial, int NB) {
+    using T = typename Store<P>::real;
+    __shared__ double red[256];
+    double nrm = 0;
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)NB * 256) {
+        auto v0 = Store<P>::ld(w.d, nullptr, e, 0);
+        cpx<T> acc = mk((T)v0.re, (T)v0.im);
+        for (int j = 0; j < nv; ++j) {
+            const double2 hj = h[(long)j * ldh];
+            const void *vj = (const char *)Vb.d + (size_t)j * vstride * sizeof(T) * 2;
+            auto v = Store<P>::ld(vj, nullptr, e, 0);
+            acc = acc + mk((T)(sign * hj.x), (T)(sign * hj.y)) * mk((T)v.re, (T)v.im);
+        }
+        Store<P>::st(w.d, e, acc);
+        nrm += (double)acc.re * acc.re + (double)acc.im * acc.im;
+    }
+    if (!partial) return;
+    red[threadIdx.x] = nrm;
+    __syncthreads();
+    for (int hh = 128; hh > 0; hh >>= 1) {
+        if ((int)threadIdx.x < hh) red[threadIdx.x] += red[threadIdx.x + hh];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(red[0], 0.0);
+}
+
+int nb_single(const mpmc_ctx *ctx, long n, int groups) {
+    long nb = (long)ctx->num_cu * 8 / (groups > 0 ? groups : 1);
+    const long maxnb = (n + 255) / 256;
+    if (nb < 8) nb = 8;
+    if (nb > maxnb) nb = maxnb;
+    if (nb > 2048) nb = 2048;
+    return (int)nb;
+}
+
 }  // namespace
 
 int blas_scale_acc(mpmc_ctx *ctx, const double *t, int N, double2 c, double sign, double *acc) {
@@ -278,6 +362,19 @@ int blas_multi_dot(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv, 
                    double *h_dev, int accumulate, int theta) {
     if (nv <= 0) return MPMC_OK;
     const int groups = (nv + JB - 1) / JB;
+    if (nrhs == 1 && vN == 1) {
+        const int NB = nb_single(ctx, ctx->n, groups);
+        double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)nv * NB * sizeof(double2));
+        if (!part) return MPMC_ENOMEM;
+        int rc = dispatch_prec(ctx, prec, [&](auto P) {
+            k_multidot1<decltype(P)::value><<<dim3(NB, groups), 256, 0, ctx->stream>>>(
+                vref(ctx, Vb, 1, prec), vstride, nv, vref(ctx, w, 1, prec), ctx->n, theta, part, NB);
+        });
+        RET_IF(rc);
+        k_reduce<<<nv, 256, 0, ctx->stream>>>(part, NB, 1, (double2 *)h_dev, accumulate, 0);
+        HIP_OR_RET(ctx, hipGetLastError());
+        return MPMC_OK;
+    }
     Tiling t = tiling(ctx, nrhs, groups);
     double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)nv * t.NB * nrhs * sizeof(double2));
     if (!part) return MPMC_ENOMEM;
@@ -303,6 +400,25 @@ int blas_norm2(mpmc_ctx *ctx, const void *x, int nrhs, int prec, double *out_dev
 // w += sign * sum_j h[j*ldh + r] V_j ; if norm2_dev: norm2_dev[r] = ||w_r||^2 (after update)
 int blas_multi_axpy(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv, void *w, int nrhs, int prec,
                     const double *h_dev, int ldh, double sign, double *norm2_dev) {
+    if (nrhs == 1 && vN == 1) {
+        const int NB = nb_single(ctx, ctx->n, 1);
+        double2 *part = nullptr;
+        if (norm2_dev) {
+            part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)NB * sizeof(double2));
+            if (!part) return MPMC_ENOMEM;
+        }
+        int rc = dispatch_prec(ctx, prec, [&](auto P) {
+            k_multiaxpy1<decltype(P)::value><<<NB, 256, 0, ctx->stream>>>(vref(ctx, Vb, 1, prec), vstride, nv,
+                                                                          vref(ctx, w, 1, prec), ctx->n,
+                                                                          (const double2 *)h_dev, ldh, sign, part, NB);
+        });
+        RET_IF(rc);
+        if (norm2_dev) {
+            k_reduce<<<1, 256, 0, ctx->stream>>>(part, NB, 1, (double2 *)norm2_dev, 0, 1);
+            HIP_OR_RET(ctx, hipGetLastError());
+        }
+        return MPMC_OK;
+    }
     Tiling t = tiling(ctx, nrhs, 1);
     double2 *part = nullptr;
     if (norm2_dev) {

@@ -75,6 +75,15 @@ MPMC_API void mpmc_defl_destroy(mpmc_defl *d) {
     delete d;
 }
 
+MPMC_API int mpmc_defl_keep(mpmc_defl *d, int k) {
+    if (!d || k < 0) return MPMC_EINVAL;
+    if (k < d->k) {
+        d->k = k;
+        d->lam.resize(2 * (size_t)k);
+    }
+    return MPMC_OK;
+}
+
 MPMC_API int mpmc_defl_create(mpmc_ctx *ctx, const double *lam_host, const void *Z, const void *U, int k,
                               mpmc_defl **out) {
     if (!ctx) return MPMC_EINVAL;

@@ -36,14 +36,27 @@ __device__ __forceinline__ zd ld(const double2 *p, long i) { return mk(p[i].x, p
 __device__ __forceinline__ void st(double2 *p, long i, zd v) { p[i] = make_double2(v.re, v.im); }
 
 // --------------------------------------------------- Hessenberg QR eigs --
-// A: n x n column-major (element (i, j) at A[i + j*lda]), upper Hessenberg,
-// destroyed.  ev: n eigenvalues.  Returns 0 or -1 (no convergence / NaN).
-// Called by all lanes of one workgroup.
-__device__ int hess_eigvals(double2 *A, int lda, int n, double2 *ev) {
+// Matrix accessors: column-major in global memory, or packed upper Hessenberg
+// in LDS (column j holds rows 0..min(j+1, n-1) at offset j(j+3)/2).
+struct GlobalMat {
+    double2 *A;
+    int lda;
+    __device__ __forceinline__ double2 &operator()(int i, int j) const { return A[i + (long)j * lda]; }
+};
+struct PackedMat {
+    double2 *A;
+    __device__ __forceinline__ double2 &operator()(int i, int j) const { return A[j * (j + 3) / 2 + i]; }
+};
+__host__ __device__ inline long packed_hess_size(int n) { return (long)(n - 1) * (n + 2) / 2 + n; }
+
+// Eigenvalues of the upper Hessenberg matrix held by `a` (destroyed): shifted
+// QR with Givens rotations, Wilkinson shifts, exceptional shifts every 11
+// iterations without deflation, deflation from the bottom.  Called by all lanes
+// of one workgroup; returns 0, or -1 on non-convergence or NaN.
+template <typename Mat>
+__device__ int hess_eigvals(Mat a, int n, double2 *ev, double2 *cs) {
+    // cs: 2n entries of rotation storage (cosines in .x of cs[k], sines in cs[n + k])
     const int tid = threadIdx.x, nt = blockDim.x;
-    __shared__ double cs_c[512];
-    __shared__ double2 cs_s[512];
-    auto a = [&](int i, int j) -> double2 & { return A[i + (long)j * lda]; };
     int hi = n - 1, iter = 0, total = 0;
     const int max_total = 60 * n + 100;
     int status = 0;
@@ -84,20 +97,18 @@ __device__ int hess_eigvals(double2 *A, int lda, int n, double2 *ev) {
         }
         if (++total > max_total) { status = -1; break; }
         ++iter;
-        // Wilkinson shift from the trailing 2x2 block
         const zd p = ld(&a(hi - 1, hi - 1), 0), q = ld(&a(hi - 1, hi), 0), r = ld(&a(hi, hi - 1), 0),
                  s = ld(&a(hi, hi), 0);
         const zd half_tr = 0.5 * (p + s), det = p * s - q * r;
         const zd disc = zsqrt(half_tr * half_tr - det);
         zd e1 = half_tr + disc, e2 = half_tr - disc;
         zd sigma = zabs(e1 - s) <= zabs(e2 - s) ? e1 : e2;
-        if (iter % 11 == 10) {   // exceptional shift breaks cycles
+        if (iter % 11 == 10) {
             const double m = zabs(r) + zabs(ld(&a(hi - 1, hi - 2 >= l ? hi - 2 : hi - 1), 0));
             sigma = s + mk(0.75 * m, 0.4375 * m);
         }
         for (int i = l + tid; i <= hi; i += nt) st(&a(i, i), 0, ld(&a(i, i), 0) - sigma);
         __syncthreads();
-        // QR: rotations G_k zero a(k+1, k)
         for (int k = l; k < hi; ++k) {
             const zd x = ld(&a(k, k), 0), y = ld(&a(k + 1, k), 0);
             const double ax = zabs(x), ay = zabs(y), rr = hypot(ax, ay);
@@ -108,7 +119,7 @@ __device__ int hess_eigvals(double2 *A, int lda, int n, double2 *ev) {
                 sn = mk(0.0, 0.0);
             } else if (ax == 0.0) {
                 c = 0.0;
-                sn = mk(y.re / ay, -y.im / ay);   // conj(y)/|y|
+                sn = mk(y.re / ay, -y.im / ay);
             } else {
                 c = ax / rr;
                 const zd ph = mk(x.re / ax, x.im / ax);
@@ -120,15 +131,14 @@ __device__ int hess_eigvals(double2 *A, int lda, int n, double2 *ev) {
                 st(&a(k + 1, j), 0, c * v - cconj(sn) * u);
             }
             if (tid == 0) {
-                cs_c[k - l] = c;
-                cs_s[k - l] = make_double2(sn.re, sn.im);
+                cs[k - l] = make_double2(c, 0.0);
+                cs[n + k - l] = make_double2(sn.re, sn.im);
             }
             __syncthreads();
         }
-        // RQ: apply G_k^H on the right
         for (int k = l; k < hi; ++k) {
-            const double c = cs_c[k - l];
-            const zd sn = mk(cs_s[k - l].x, cs_s[k - l].y);
+            const double c = cs[k - l].x;
+            const zd sn = mk(cs[n + k - l].x, cs[n + k - l].y);
             for (int i = l + tid; i <= k + 1; i += nt) {
                 const zd u = ld(&a(i, k), 0), v = ld(&a(i, k + 1), 0);
                 st(&a(i, k), 0, c * u + cconj(sn) * v);
@@ -215,116 +225,92 @@ __device__ void leja_order(double2 *ev, int n, double2 *tmp, double *S, int *tak
 }
 
 // ------------------------------------------------ harmonic Ritz + Leja --
-// H: (d+1) x d column-major with leading dimension ldh (Arnoldi matrix),
-// beta = ||b||.  work: >= 2*d*d + 4*d + 8 complex doubles.
-// out: roots[d] (Leja ordered), info[0] = relres, info[1] = status.
+// H: (d+1) x d column-major (leading dimension ldh), the Arnoldi matrix of a
+// GMRES(d) cycle; beta = ||b||.
+// Lane 0 runs the Givens QR of Hbar column by column: the first d-1 rotations
+// are also the QR of H_d, so r = R_d(d-1, d-1) and f = H_d^-H e_d = Q e_d / conj(r)
+// (R_d^H is lower triangular, so R_d^H g = e_d has g = e_d / conj(r)); the last
+// rotation gives the least-squares residual |g_d|.  The eigenvalues of
+// H_d + |h_{d+1,d}|^2 f e_d^T are found in LDS (packed) when it fits.
+// work (global): >= 2*d*d + 8*d + 16 complex doubles.
 __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh, int d, double beta,
-                                                      double2 *work, double2 *roots, double *info) {
+                                                      double2 *work, double2 *roots, double *info, int use_lds) {
+    extern __shared__ double2 lds_mat[];
     const int tid = threadIdx.x, nt = blockDim.x;
-    double2 *A = work;                 // d x d, lda = d
-    double2 *B = work + (long)d * d;   // d x d, H_d^H, then LU
-    double2 *f = B + (long)d * d;      // d
-    double2 *g = f + d;                // d+1 (least squares rhs)
-    double2 *tmp = g + d + 1;          // d
+    double2 *A = work;                 // d x d (global path)
+    double2 *f = work + (long)d * d;   // d
+    double2 *rot = f + d;              // d rotations: (c, 0) then s
+    double2 *rs = rot + d;             // d
+    double2 *tmp = rs + d;             // d
     double *S = (double *)(tmp + d);   // d doubles
     int *taken = (int *)(S + d);       // d ints
     __shared__ int s_status;
-    if (tid == 0) s_status = 0;
-    for (long e = tid; e < (long)d * d; e += nt) {
-        const int i = (int)(e % d), j = (int)(e / d);
-        A[e] = H[i + (long)j * ldh];
-        const double2 hji = H[j + (long)i * ldh];   // (H_d^H)(i, j) = conj(H_d(j, i))
-        B[e] = make_double2(hji.x, -hji.y);
-    }
-    __syncthreads();
-
-    // GMRES least-squares residual ||beta e1 - Hbar y|| by Givens on a copy of Hbar
-    // (reuse tmp/f storage sequentially on lane 0; d is small).
+    __shared__ double s_res;
     if (tid == 0) {
-        // residual via rotations applied column by column to a scratch column
+        s_status = 0;
         zd gk = mk(beta, 0.0);
-        double2 *cs = tmp;   // store (c, 0) and s in f
+        zd rdd = mk(0.0, 0.0);
         for (int j = 0; j < d; ++j) {
-            // column j of Hbar with previous rotations applied
-            // (rows 0..j+1); keep only the two entries we need at each rotation
-            zd col_j1 = ld(H, (j + 1) + (long)j * ldh);
-            zd x = ld(H, 0 + (long)j * ldh);
+            zd x = ld(H, (long)j * ldh);
             for (int i = 0; i < j; ++i) {
-                const double c = cs[i].x;
-                const zd sn = ld(f, i);
+                const double c = rot[i].x;
+                const zd sn = ld(rs, i);
                 const zd y = ld(H, (i + 1) + (long)j * ldh);
-                // rotated entries of rows i, i+1: only row i+1 feeds the next rotation
-                const zd xi = c * x + sn * y;
-                const zd yi = c * y - cconj(sn) * x;
-                (void)xi;
-                x = yi;
+                x = c * y - cconj(sn) * x;
             }
-            const double ax = zabs(x), ay = zabs(col_j1), rr = hypot(ax, ay);
+            if (j == d - 1) rdd = x;
+            const zd y = ld(H, (j + 1) + (long)j * ldh);
+            const double ax = zabs(x), ay = zabs(y), rr = hypot(ax, ay);
             double c;
             zd sn;
             if (rr == 0.0) { c = 1.0; sn = mk(0.0, 0.0); }
-            else if (ax == 0.0) { c = 0.0; sn = mk(col_j1.re / ay, -col_j1.im / ay); }
-            else { c = ax / rr; sn = (1.0 / rr) * (mk(x.re / ax, x.im / ax) * cconj(col_j1)); }
-            cs[j] = make_double2(c, 0.0);
-            st(f, j, sn);
-            gk = mk(0.0, 0.0) - cconj(sn) * gk;   // g_{j+1} = -conj(s) g_j
+            else if (ax == 0.0) { c = 0.0; sn = mk(y.re / ay, -y.im / ay); }
+            else { c = ax / rr; sn = (1.0 / rr) * (mk(x.re / ax, x.im / ax) * cconj(y)); }
+            rot[j] = make_double2(c, 0.0);
+            st(rs, j, sn);
+            gk = mk(0.0, 0.0) - cconj(sn) * gk;
         }
-        info[0] = beta > 0 ? zabs(gk) / beta : 0.0;
+        s_res = beta > 0 ? zabs(gk) / beta : 0.0;
+        // f = Q e_{d-1} / conj(rdd), Q = G_0^H ... G_{d-2}^H
+        for (int i = 0; i < d; ++i) f[i] = make_double2(0.0, 0.0);
+        f[d - 1] = make_double2(1.0, 0.0);
+        for (int k = d - 2; k >= 0; --k) {
+            const double c = rot[k].x;
+            const zd sn = ld(rs, k);
+            const zd u = ld(f, k), v = ld(f, k + 1);
+            st(f, k, c * u - sn * v);
+            st(f, k + 1, cconj(sn) * u + c * v);
+        }
+        if (zabs(rdd) == 0.0) s_status = -2;
+        const zd inv = zdiv(mk(1.0, 0.0), cconj(rdd));
+        for (int i = 0; i < d; ++i) st(f, i, ld(f, i) * inv);
     }
     __syncthreads();
-
     const zd h = ld(H, d + (long)(d - 1) * ldh);
-    if (zabs(h) > 0.0) {
-        // solve B f = e_d by Gaussian elimination with partial pivoting
-        for (int i = tid; i < d; i += nt) f[i] = make_double2(i == d - 1 ? 1.0 : 0.0, 0.0);
+    const double h2 = h.re * h.re + h.im * h.im;
+    const bool corr = h2 > 0.0 && s_status == 0;
+    int rc;
+    if (use_lds) {
+        PackedMat M{lds_mat};
+        for (int j = 0; j < d; ++j)
+            for (int i = tid; i <= (j + 1 < d ? j + 1 : d - 1); i += nt) {
+                zd v = ld(H, i + (long)j * ldh);
+                if (corr && j == d - 1) v = v + h2 * ld(f, i);
+                st(&M(i, j), 0, v);
+            }
         __syncthreads();
-        for (int k = 0; k < d; ++k) {
-            __shared__ int piv;
-            if (tid == 0) {
-                int p = k;
-                double best = zabs(ld(B, k + (long)k * d));
-                for (int i = k + 1; i < d; ++i) {
-                    const double v = zabs(ld(B, i + (long)k * d));
-                    if (v > best) { best = v; p = i; }
-                }
-                piv = p;
-                if (best == 0.0) s_status = -2;
-            }
-            __syncthreads();
-            const int p = piv;
-            if (p != k) {
-                for (int j = tid; j < d; j += nt) {
-                    double2 t = B[k + (long)j * d];
-                    B[k + (long)j * d] = B[p + (long)j * d];
-                    B[p + (long)j * d] = t;
-                }
-                if (tid == 0) { double2 t = f[k]; f[k] = f[p]; f[p] = t; }
-            }
-            __syncthreads();
-            const zd pk = ld(B, k + (long)k * d);
-            // eliminate rows below k
-            for (int i = k + 1 + tid; i < d; i += nt) {
-                const zd l = zdiv(ld(B, i + (long)k * d), pk);
-                for (int j = k + 1; j < d; ++j)
-                    st(B, i + (long)j * d, ld(B, i + (long)j * d) - l * ld(B, k + (long)j * d));
-                st(f, i, ld(f, i) - l * ld(f, k));
-                B[i + (long)k * d] = make_double2(0, 0);
-            }
-            __syncthreads();
-        }
-        if (tid == 0) {   // back substitution
-            for (int i = d - 1; i >= 0; --i) {
-                zd acc = ld(f, i);
-                for (int j = i + 1; j < d; ++j) acc = acc - ld(B, i + (long)j * d) * ld(f, j);
-                st(f, i, zdiv(acc, ld(B, i + (long)i * d)));
-            }
+        rc = hess_eigvals(M, d, roots, lds_mat + packed_hess_size(d));
+    } else {
+        GlobalMat M{A, d};
+        for (long e = tid; e < (long)d * d; e += nt) {
+            const int i = (int)(e % d), j = (int)(e / d);
+            zd v = (i <= j + 1) ? ld(H, i + (long)j * ldh) : mk(0.0, 0.0);
+            if (corr && j == d - 1) v = v + h2 * ld(f, i);
+            st(A, e, v);
         }
         __syncthreads();
-        const double h2 = h.re * h.re + h.im * h.im;
-        for (int i = tid; i < d; i += nt) st(A, i + (long)(d - 1) * d, ld(A, i + (long)(d - 1) * d) + h2 * ld(f, i));
-        __syncthreads();
+        rc = hess_eigvals(M, d, roots, rot);   // rot/rs (2d entries) are free again
     }
-    int rc = hess_eigvals(A, d, d, roots);
     if (rc && tid == 0) s_status = -1;
     __syncthreads();
     leja_order(roots, d, tmp, S, taken);
@@ -332,120 +318,185 @@ __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh,
         for (int i = 0; i < d; ++i)
             if (!(roots[i].x == roots[i].x) || !(roots[i].y == roots[i].y) || (roots[i].x == 0 && roots[i].y == 0))
                 s_status = -1;
+        info[0] = s_res;
         info[1] = (double)s_status;
     }
+}
+
+static size_t lds_limit(mpmc_ctx *ctx) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess) v = 65536;
+    return (size_t)v;
+}
+
+template <typename K>
+static bool want_lds(mpmc_ctx *ctx, K kernel, size_t bytes) {
+    if (bytes + 4096 > lds_limit(ctx)) return false;   // keep room for the small static LDS arrays
+    if (bytes > 65536 && hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
 }
 
 int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, double beta, double *roots_dev,
                         double *info_dev) {
     if (d < 1 || d > 500) return set_err(ctx, MPMC_EINVAL, "harmonic Ritz: d=%d out of range [1, 500]", d);
-    double2 *work = (double2 *)ws_get(ctx, WS_DENSE, ((size_t)2 * d * d + 8 * d + 16) * sizeof(double2));
+    double2 *work = (double2 *)ws_get(ctx, WS_DENSE, ((size_t)d * d + 8 * d + 16) * sizeof(double2));
     if (!work) return MPMC_ENOMEM;
-    k_harmonic_leja<<<1, 64, 0, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work, (double2 *)roots_dev,
-                                                info_dev);
+    const size_t lb = (size_t)(packed_hess_size(d) + 2 * d) * sizeof(double2);
+    const bool lds = want_lds(ctx, k_harmonic_leja, lb);
+    k_harmonic_leja<<<1, 64, lds ? lb : 0, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
+                                                          (double2 *)roots_dev, info_dev, lds ? 1 : 0);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
 
 // ------------------------------------------------- eigenvalues of H_m --
 __global__ __launch_bounds__(64) void k_hess_eigs(const double2 *H, int ldh, int m, double2 *work, double2 *ev,
-                                                  double *info) {
-    for (long e = threadIdx.x; e < (long)m * m; e += blockDim.x) {
-        const int i = (int)(e % m), j = (int)(e / m);
-        work[e] = H[i + (long)j * ldh];
+                                                  double *info, int use_lds) {
+    extern __shared__ double2 lds_mat[];
+    int rc;
+    if (use_lds) {
+        PackedMat M{lds_mat};
+        for (int j = 0; j < m; ++j)
+            for (int i = threadIdx.x; i <= (j + 1 < m ? j + 1 : m - 1); i += blockDim.x) M(i, j) = H[i + (long)j * ldh];
+        __syncthreads();
+        rc = hess_eigvals(M, m, ev, lds_mat + packed_hess_size(m));
+    } else {
+        for (long e = threadIdx.x; e < (long)m * m; e += blockDim.x) {
+            const int i = (int)(e % m), j = (int)(e / m);
+            work[e] = (i <= j + 1) ? H[i + (long)j * ldh] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        rc = hess_eigvals(GlobalMat{work, m}, m, ev, work + (size_t)m * m);
     }
-    __syncthreads();
-    int rc = hess_eigvals(work, m, m, ev);
     if (threadIdx.x == 0) info[0] = rc;
 }
 
 int dense_hess_eigs(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, double *ev_dev, double *info_dev) {
     if (m < 1 || m > 500) return set_err(ctx, MPMC_EINVAL, "Hessenberg eigenproblem: m=%d out of range", m);
-    double2 *work = (double2 *)ws_get(ctx, WS_DENSE, (size_t)m * m * sizeof(double2));
+    double2 *work = (double2 *)ws_get(ctx, WS_DENSE, ((size_t)m * m + 2 * m) * sizeof(double2));
     if (!work) return MPMC_ENOMEM;
-    k_hess_eigs<<<1, 64, 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev, info_dev);
+    const size_t lb = (size_t)(packed_hess_size(m) + 2 * m) * sizeof(double2);
+    const bool lds = want_lds(ctx, k_hess_eigs, lb);
+    k_hess_eigs<<<1, 64, lds ? lb : 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev,
+                                                      info_dev, lds ? 1 : 0);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
 
 // ------------------------------------------- inverse iteration vectors --
-// One workgroup per eigenvalue mu_q: two solves of (H_m - mu I) y = rhs by
-// Hessenberg LU with adjacent-row pivoting; y normalised.  Y: m x k column-major.
-__global__ __launch_bounds__(64) void k_inverse_iteration(const double2 *H, int ldh, int m, const double2 *mu,
-                                                          double2 *work, double2 *Y) {
-    const int q = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-    double2 *A = work + (size_t)q * ((size_t)m * m + m);
-    double2 *y = A + (size_t)m * m;
-    __shared__ double s_hn;
-    if (tid == 0) {
-        double mx = 0;
-        for (long e = 0; e < (long)m * m; ++e) {
-            const double2 v = H[(e % m) + (e / m) * (long)ldh];
-            mx = fmax(mx, hypot(v.x, v.y));
-        }
-        s_hn = mx;
-    }
-    __syncthreads();
-    const double hn = s_hn;
-    const zd mq = ld(mu, q);
+// One workgroup (one wavefront) per eigenvalue mu_q: three solves of
+// (H_m - mu I) y = y_prev by Hessenberg LU with adjacent-row pivoting, the row
+// operations spread over the lanes; y normalised after each solve.
+// Y: m x k column-major.  The factor lives in LDS (packed) when it fits.
+template <typename Mat>
+__device__ void inverse_iteration(Mat A, const double2 *H, int ldh, int m, zd mq, double hn, double2 *y) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ int s_swap;
+    __shared__ double2 s_red[64];
     for (int i = tid; i < m; i += nt) y[i] = make_double2(1.0, 0.0);
     for (int it = 0; it < 3; ++it) {
         __syncthreads();
-        for (long e = tid; e < (long)m * m; e += nt) {
-            const int i = (int)(e % m), j = (int)(e / m);
-            zd v = ld(H, i + (long)j * ldh);
-            if (i == j) v = v - mq;
-            if (i > j + 1) v = mk(0.0, 0.0);
-            st(A, e, v);
-        }
+        for (int j = 0; j < m; ++j)
+            for (int i = tid; i <= (j + 1 < m ? j + 1 : m - 1); i += nt) {
+                zd v = ld(H, i + (long)j * ldh);
+                if (i == j) v = v - mq;
+                st(&A(i, j), 0, v);
+            }
         __syncthreads();
-        if (tid == 0) {
-            for (int k = 0; k < m; ++k) {
-                if (k + 1 < m && zabs(ld(A, k + 1 + (long)k * m)) > zabs(ld(A, k + (long)k * m))) {
-                    for (int j = k; j < m; ++j) {
-                        double2 t = A[k + (long)j * m];
-                        A[k + (long)j * m] = A[k + 1 + (long)j * m];
-                        A[k + 1 + (long)j * m] = t;
-                    }
-                    double2 t = y[k];
+        for (int k = 0; k < m; ++k) {
+            if (tid == 0) {
+                s_swap = (k + 1 < m && zabs(ld(&A(k + 1, k), 0)) > zabs(ld(&A(k, k), 0))) ? 1 : 0;
+            }
+            __syncthreads();
+            if (s_swap) {
+                for (int j = k + tid; j < m; j += nt) {
+                    const double2 t = A(k, j);
+                    A(k, j) = A(k + 1, j);
+                    A(k + 1, j) = t;
+                }
+                if (tid == 0) {
+                    const double2 t = y[k];
                     y[k] = y[k + 1];
                     y[k + 1] = t;
                 }
-                zd pk = ld(A, k + (long)k * m);
-                if (zabs(pk) < DBL_EPSILON * hn) {
-                    pk = mk(DBL_EPSILON * (hn > 0 ? hn : 1.0), 0.0);
-                    st(A, k + (long)k * m, pk);
-                }
-                if (k + 1 < m) {
-                    const zd l = zdiv(ld(A, k + 1 + (long)k * m), pk);
-                    for (int j = k + 1; j < m; ++j)
-                        st(A, k + 1 + (long)j * m, ld(A, k + 1 + (long)j * m) - l * ld(A, k + (long)j * m));
-                    st(y, k + 1, ld(y, k + 1) - l * ld(y, k));
-                }
             }
-            for (int i = m - 1; i >= 0; --i) {
-                zd acc = ld(y, i);
-                for (int j = i + 1; j < m; ++j) acc = acc - ld(A, i + (long)j * m) * ld(y, j);
-                st(y, i, zdiv(acc, ld(A, i + (long)i * m)));
+            __syncthreads();
+            if (tid == 0 && zabs(ld(&A(k, k), 0)) < DBL_EPSILON * hn) A(k, k) = make_double2(DBL_EPSILON * hn, 0.0);
+            __syncthreads();
+            if (k + 1 < m) {
+                const zd l = zdiv(ld(&A(k + 1, k), 0), ld(&A(k, k), 0));
+                for (int j = k + 1 + tid; j < m; j += nt)
+                    st(&A(k + 1, j), 0, ld(&A(k + 1, j), 0) - l * ld(&A(k, j), 0));
+                if (tid == 0) st(y, k + 1, ld(y, k + 1) - l * ld(y, k));
             }
-            double nr = 0;
-            for (int i = 0; i < m; ++i) nr += y[i].x * y[i].x + y[i].y * y[i].y;
-            nr = sqrt(nr);
-            const double inv = nr > 0 ? 1.0 / nr : 0.0;
-            for (int i = 0; i < m; ++i) y[i] = make_double2(y[i].x * inv, y[i].y * inv);
+            __syncthreads();
         }
+        // back substitution, one row at a time with a lane reduction
+        for (int i = m - 1; i >= 0; --i) {
+            zd part = mk(0.0, 0.0);
+            for (int j = i + 1 + tid; j < m; j += nt) part = part + ld(&A(i, j), 0) * ld(y, j);
+            s_red[tid] = make_double2(part.re, part.im);
+            __syncthreads();
+            if (tid == 0) {
+                zd acc = ld(y, i);
+                for (int q = 0; q < nt; ++q) acc = acc - ld(s_red, q);
+                st(y, i, zdiv(acc, ld(&A(i, i), 0)));
+            }
+            __syncthreads();
+        }
+        zd part = mk(0.0, 0.0);
+        for (int i = tid; i < m; i += nt) part.re += y[i].x * y[i].x + y[i].y * y[i].y;
+        s_red[tid] = make_double2(part.re, 0.0);
+        __syncthreads();
+        double nr = 0;
+        for (int q = 0; q < nt; ++q) nr += s_red[q].x;
+        nr = sqrt(nr);
+        const double inv = nr > 0 ? 1.0 / nr : 0.0;
+        __syncthreads();
+        for (int i = tid; i < m; i += nt) y[i] = make_double2(y[i].x * inv, y[i].y * inv);
     }
     __syncthreads();
-    for (int i = tid; i < m; i += nt) Y[i + (long)q * m] = y[i];
+}
+
+__global__ __launch_bounds__(64) void k_inverse_iteration(const double2 *H, int ldh, int m, const double2 *mu,
+                                                          double2 *work, double2 *Y, int use_lds) {
+    extern __shared__ double2 lds_mat[];
+    const int q = blockIdx.x;
+    __shared__ double s_hn;
+    if (threadIdx.x == 0) {
+        double mx = 0;
+        for (int j = 0; j < m; ++j)
+            for (int i = 0; i <= (j + 1 < m ? j + 1 : m - 1); ++i) {
+                const double2 v = H[i + (long)j * ldh];
+                mx = fmax(mx, hypot(v.x, v.y));
+            }
+        s_hn = mx;
+    }
+    __syncthreads();
+    double2 *y = Y + (long)q * m;
+    if (use_lds) {
+        inverse_iteration(PackedMat{lds_mat}, H, ldh, m, ld(mu, q), s_hn, y);
+    } else {
+        inverse_iteration(GlobalMat{work + (size_t)q * m * m, m}, H, ldh, m, ld(mu, q), s_hn, y);
+    }
 }
 
 int dense_inverse_iteration(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, const double *mu_dev, int k,
                             double *Y_dev) {
     if (k < 1) return MPMC_OK;
-    double2 *work = (double2 *)ws_get(ctx, WS_DENSE, (size_t)k * ((size_t)m * m + m) * sizeof(double2));
-    if (!work) return MPMC_ENOMEM;
-    k_inverse_iteration<<<k, 64, 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, (const double2 *)mu_dev, work,
-                                                   (double2 *)Y_dev);
+    const size_t lb = (size_t)packed_hess_size(m) * sizeof(double2);
+    const bool lds = want_lds(ctx, k_inverse_iteration, lb);
+    double2 *work = nullptr;
+    if (!lds) {
+        work = (double2 *)ws_get(ctx, WS_DENSE, (size_t)k * m * m * sizeof(double2));
+        if (!work) return MPMC_ENOMEM;
+    }
+    k_inverse_iteration<<<k, 64, lds ? lb : 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, (const double2 *)mu_dev,
+                                                              work, (double2 *)Y_dev, lds ? 1 : 0);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }

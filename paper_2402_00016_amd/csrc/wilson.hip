@@ -448,6 +448,121 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI>
     }
 }
 
+// ---------------------------------------------------- single vectors --
+// nrhs == 1 (GMRES-polynomial and deflation Arnoldi cycles): eight lanes per
+// site, one hop each, so a single-vector matvec occupies 8x more wavefronts;
+// the eight 12-component contributions are summed with lane shuffles.
+template <typename T>
+__device__ __forceinline__ cpx<T> mulc_rt(cpx<T> z, int code) {
+    T a = z.re, b = z.im;
+    if (code & 1) {
+        const T t = a;
+        a = -b;
+        b = t;
+    }
+    if (code & 2) {
+        a = -a;
+        b = -b;
+    }
+    return mk(a, b);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, const int *__restrict__ nbr,
+                                                 const typename LinkT<P>::type *__restrict__ links, WOut o, long V) {
+    using T = typename Store<P>::real;
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long s = t >> 3;
+    const int h = (int)(t & 7);
+    const bool live = s < V;
+    cpx<T> c[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) c[k] = mk(T(0), T(0));
+    if (live) {
+        const int mu = h & 3;
+        const bool fwd = h < 4;
+        // (1 - gamma_mu) codes: j0, c0, j1, c1, k2, d2, k3, d3 (see Proj)
+        const int j0 = mu < 2 ? 3 : 2, c0 = mu == 0 ? 3 : (mu == 1 ? 0 : (mu == 2 ? 3 : 2));
+        const int j1 = mu < 2 ? 2 : 3, c1 = mu == 0 ? 3 : (mu == 1 ? 2 : (mu == 2 ? 1 : 2));
+        const int k2 = mu < 2 ? 1 : 0, d2 = mu == 0 ? 1 : (mu == 1 ? 2 : (mu == 2 ? 1 : 2));
+        const int k3 = mu < 2 ? 0 : 1, d3 = mu == 0 ? 1 : (mu == 1 ? 0 : (mu == 2 ? 3 : 2));
+        const T sg = fwd ? T(o.g) : T(-o.g);
+        const int raw = nbr[s * 8 + h];
+        const long sn = (long)(raw & 0x7fffffff);
+        const T bsign = raw < 0 ? T(-1) : T(1);
+        const typename Elem<P>::type *bp = reinterpret_cast<const typename Elem<P>::type *>(b) + sn * 12;
+        cpx<T> psi[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) psi[k] = mk((T)bp[k].x, (T)bp[k].y);
+        cpx<T> hh[2][3];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+            const cpx<T> pj0 = j0 == 3 ? psi[9 + cc] : psi[6 + cc];
+            const cpx<T> pj1 = j1 == 3 ? psi[9 + cc] : psi[6 + cc];
+            hh[0][cc] = psi[cc] + sg * mulc_rt(pj0, c0);
+            hh[1][cc] = psi[3 + cc] + sg * mulc_rt(pj1, c1);
+        }
+        const auto *lk = links + ((fwd ? s : sn) * 4 + mu) * 9;
+        cpx<T> uh[2][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cpx<T> t0 = mk(T(0), T(0)), t1 = mk(T(0), T(0));
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) {
+                const auto lv = fwd ? lk[a * 3 + bb] : lk[bb * 3 + a];
+                const cpx<T> u = mk((T)lv.x, fwd ? (T)lv.y : (T)-lv.y);
+                t0 = t0 + u * hh[0][bb];
+                t1 = t1 + u * hh[1][bb];
+            }
+            uh[0][a] = bsign * t0;
+            uh[1][a] = bsign * t1;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            c[a] = uh[0][a];
+            c[3 + a] = uh[1][a];
+            c[6 + a] = sg * mulc_rt(k2 ? uh[1][a] : uh[0][a], d2);
+            c[9 + a] = sg * mulc_rt(k3 ? uh[1][a] : uh[0][a], d3);
+        }
+    }
+    // sum the eight hops of a site (lanes 8q .. 8q+7)
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            c[k].re += __shfl_xor(c[k].re, off);
+            c[k].im += __shfl_xor(c[k].im, off);
+        }
+    }
+    if (!live || h != 0) return;
+    const T kap = (T)o.kappa;
+    const cpx<T> al = mk((T)o.alpha.x, (T)o.alpha.y);
+    const cpx<T> be = mk((T)o.beta.x, (T)o.beta.y);
+    const typename Elem<P>::type *sp = reinterpret_cast<const typename Elem<P>::type *>(b) + s * 12;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const cpx<T> bt = mk((T)sp[k].x, (T)sp[k].y);
+        cpx<T> mb = bt - kap * c[k];
+        if (o.theta && k >= 6) mb = mk(-mb.re, -mb.im);
+        cpx<T> v = be * mb;
+        if (o.a_is_b) {
+            v = v + al * bt;
+        } else if (o.a) {
+            const auto av = reinterpret_cast<const typename Elem<P>::type *>(o.a)[s * 12 + k];
+            v = v + al * mk((T)av.x, (T)av.y);
+        }
+        typename Elem<P>::type *op = reinterpret_cast<typename Elem<P>::type *>(o.out) + s * 12 + k;
+        op->x = v.re;
+        op->y = v.im;
+        if (o.y) {
+            typename Elem<P>::type *yp = reinterpret_cast<typename Elem<P>::type *>(o.y) + s * 12 + k;
+            const cpx<T> yn = mk((T)yp->x, (T)yp->y) + mk((T)o.gamma.x, (T)o.gamma.y) * v;
+            yp->x = yn.re;
+            yp->y = yn.im;
+        }
+    }
+}
+
 // ------------------------------------------------- fused level step --
 // w' = w - c M w for a batch whose rhs r is noise vector eta_r (2-bit codes in
 // codes[s*N + r]); partial[blk][rl] += cnext * sum_k conj(eta_k) (Theta w')_k
@@ -577,6 +692,12 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs) {
     const long work = ctx->V * nrhs;
     const unsigned grid = grid_for(work, 256);
     WIn<P> in = make_in<P>(ctx, b, nrhs);
+    if constexpr (P != MPMC_FP16S) {
+        if (nrhs == 1) {
+            k_wilson1<P><<<grid_for(ctx->V * 8, 256), 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, o, ctx->V);
+            return;
+        }
+    }
     if (nrhs % 64 == 0)
         k_wilson<P, true><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs);
     else

@@ -35,9 +35,10 @@ class Plan:
     noises: int = 128                    # per level (fixed-count mode)
     theta: int = mpmc.THETA_I
     seed: int = 1
-    nev: int = 20                        # eigenpairs requested for deflation (0: none)
-    defl_m: int = 80                     # PP-Arnoldi steps
-    defl_pin_degree: int = 8             # degree of p_in for PP-Arnoldi
+    nev: int = 20                        # eigenpairs kept for deflation (0: none)
+    defl_candidates: int = 40            # Ritz pairs tested for acceptance
+    defl_m: int = 150                    # PP-Arnoldi steps
+    defl_pin_degree: int = 32            # degree of p_in for PP-Arnoldi
     accept_tol: float = 1e-3
     real_tol: float = 2e-4
     poly_prec: int = mpmc.FP32           # precision of the polynomial levels
@@ -110,7 +111,10 @@ def build_deflation(ctx, plan: Plan):
     if plan.nev <= 0:
         return None
     pin = ctx.gmres_poly(plan.seed, 0x1FF, plan.defl_pin_degree + 1) if plan.defl_pin_degree > 0 else None
-    return ctx.deflate(pin, plan.seed, 0x200, plan.defl_m, plan.nev, plan.accept_tol, plan.real_tol)
+    D = ctx.deflate(pin, plan.seed, 0x200, plan.defl_m, max(plan.nev, plan.defl_candidates), plan.accept_tol,
+                    plan.real_tol)
+    D.keep(plan.nev)
+    return D
 
 
 def combine(levels):

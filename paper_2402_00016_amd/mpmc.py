@@ -51,10 +51,12 @@ _SIGS = {
     "mpmc_poly_eval": ([_vp, _vp, _vp, _i], _i),
     "mpmc_poly_destroy": ([_vp], None),
     "mpmc_apply_poly": ([_vp, _vp, _vp, _vp, _i, _i], _i),
+    "mpmc_poly_trace": ([_vp, _vp, _i, _pi, _i, _i, _vp, _pi, _pu64], _i),
     "mpmc_deflate": ([_vp, _vp, _u64, _u32, _i, _i, _d, _d, ctypes.POINTER(_vp), _pi], _i),
     "mpmc_defl_create": ([_vp, _vp, _vp, _vp, _i, ctypes.POINTER(_vp)], _i),
     "mpmc_defl_export": ([_vp, _vp, _vp, _vp, _pi], _i),
     "mpmc_defl_destroy": ([_vp], None),
+    "mpmc_defl_keep": ([_vp, _i], _i),
     "mpmc_solve": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
     "mpmc_level_estimate": ([_vp, _vp, _vp, _vp, _i, _u64, _u32, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp,
                              _pu64], _i),
@@ -190,6 +192,15 @@ def mpmc_apply_poly(ctx, poly, x, y, nrhs, prec):
     _check(_L.mpmc_apply_poly(ctx, _h(poly), _ptr(x), _ptr(y), int(nrhs), int(prec)), ctx)
 
 
+def mpmc_poly_trace(ctx, poly, theta, period, prec, max_batch=0):
+    per = (ctypes.c_int * 4)(*[int(v) for v in period])
+    tr = np.zeros(1, dtype=np.complex128)
+    exact, mvps = ctypes.c_int(), ctypes.c_uint64()
+    _check(_L.mpmc_poly_trace(ctx, _h(poly), int(theta), per, int(prec), int(max_batch), tr.ctypes.data,
+                              ctypes.byref(exact), ctypes.byref(mvps)), ctx)
+    return complex(tr[0]), bool(exact.value), mvps.value
+
+
 def mpmc_deflate(ctx, p_in, seed, stream, m, nev, accept_tol=1e-3, real_tol=2e-4):
     out, k = _vp(), ctypes.c_int()
     _check(_L.mpmc_deflate(ctx, _h(p_in), int(seed), int(stream), int(m), int(nev), float(accept_tol),
@@ -211,6 +222,10 @@ def mpmc_defl_export(handle, Z=None, U=None):
     lam = np.zeros(k.value, dtype=np.complex128)
     _check(_L.mpmc_defl_export(handle, lam.ctypes.data if k.value else None, _ptr(Z), _ptr(U), ctypes.byref(k)), None)
     return lam
+
+
+def mpmc_defl_keep(handle, k):
+    _check(_L.mpmc_defl_keep(handle, int(k)), None)
 
 
 def mpmc_defl_destroy(handle):
@@ -295,6 +310,10 @@ class Defl(_Handle):
     def lam(self):
         return mpmc_defl_export(self.handle)
 
+    def keep(self, k):
+        mpmc_defl_keep(self.handle, k)
+        self.k = min(self.k, int(k))
+
 
 class Context:
     """One lattice on the current HIP device (torch tensors as device buffers)."""
@@ -364,6 +383,11 @@ class Context:
         y = self.vector(nrhs, prec) if out is None else out
         mpmc_apply_poly(self.handle, poly, x, y, nrhs, prec)
         return y
+
+    def poly_trace(self, poly, theta=THETA_I, period=None, prec=FP64, max_batch=0):
+        """Exact Tr(Theta p(M)) by probing; period None = every site its own colour."""
+        period = self.dims if period is None else period
+        return mpmc_poly_trace(self.handle, poly, theta, period, prec, max_batch)
 
     # deflation
     def deflate(self, p_in, seed, stream, m, nev, accept_tol=1e-3, real_tol=2e-4):

@@ -362,3 +362,29 @@ def test_apply_poly_fp32_ignores_garbage_output(f44):
     assert np.all(np.isfinite(got))
     want = np.stack([OP.apply_p(op, ref.roots, e) for e in z4_noise_batch(4, 1, 0, 2, op.n)])
     assert rel(got[:2], want) < 2e-5
+
+
+# ---------------------------------------------------------------- probing --
+
+def test_poly_trace_probing_exact(f44):
+    """Exact Tr(Theta p(M)) by probing against the oracle's dense trace:
+    brute force (every site its own colour) for degree 15, and a 2x2x2x2 block
+    colouring for degree 1 (exact since 1 < 2 <= L/2)."""
+    dims, kappa, U, op, ctx = f44
+    b = z4_noise(1, 0x100, 0, op.n)
+    P, _, _ = OK.gmres_poly(op, b, 16)
+    Pm = OP.apply_p(op, P.roots, np.eye(op.n)).T
+    g = ctx.poly_from_roots(P.roots)
+    for theta, th in (("I", 0), ("g5", 1)):
+        G = np.kron(np.eye(OLT.volume(dims)), np.kron(OLT.theta_matrix(theta), np.eye(3)))
+        tr, exact, mv = ctx.poly_trace(g, theta=th, max_batch=192)
+        assert exact and mv == op.n * 15
+        assert abs(tr - np.trace(G @ Pm)) < 1e-10 * max(1.0, abs(np.trace(G @ Pm)))
+    P2, _, _ = OK.gmres_poly(op, b, 2)
+    P2m = OP.apply_p(op, P2.roots, np.eye(op.n)).T
+    tr2, exact2, mv2 = ctx.poly_trace(ctx.poly_from_roots(P2.roots), period=(2, 2, 2, 2))
+    assert exact2 and mv2 == 16 * 12 * 1
+    assert abs(tr2 - np.trace(P2m)) < 1e-10 * abs(np.trace(P2m))
+    # a too-coarse colouring is reported as inexact
+    _, exact3, _ = ctx.poly_trace(g, period=(2, 2, 2, 2))
+    assert not exact3
