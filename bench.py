@@ -82,7 +82,7 @@ def main():
     dims, eps, seed, kappa = (8, 8, 8, 8), 0.5, 2, 0.120
     links = inputs.gauge_links(dims, eps, seed)
     ctx = mpmc.Context(dims, kappa, links)
-    plan = driver.Plan(degrees=[128, 32, 8], noises=a.noises, seed=seed, nev=20, defl_candidates=40, defl_m=150,
+    plan = driver.Plan(degrees=[128, 32, 8], noises=a.noises, seed=seed, nev=20, defl_candidates=40, defl_m=136,
                        defl_pin_degree=32,
                        poly_prec=mpmc.FP32, solve_inner_prec=mpmc.FP32, solve_tol=1e-8, solve_restart=50)
     sync = torch.cuda.synchronize

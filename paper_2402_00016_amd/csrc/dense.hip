@@ -68,10 +68,11 @@ __device__ int hess_eigvals(Mat a, int n, double2 *ev, double2 *cs) {
         }
         int l = hi;
         while (l > 0) {
-            const double sub = zabs(ld(&a(l, l - 1), 0));
-            const double dia = zabs(ld(&a(l - 1, l - 1), 0)) + zabs(ld(&a(l, l), 0));
+            const double2 sv = a(l, l - 1), d0 = a(l - 1, l - 1), d1 = a(l, l);
+            const double sub = fabs(sv.x) + fabs(sv.y);
+            const double dia = fabs(d0.x) + fabs(d0.y) + fabs(d1.x) + fabs(d1.y);
             if (!(sub == sub)) { status = -1; break; }
-            if (sub <= DBL_EPSILON * dia || sub < 1e-300) break;
+            if (sub <= 0.5 * DBL_EPSILON * dia || sub < 1e-300) break;
             --l;
         }
         if (status) break;
@@ -111,19 +112,22 @@ __device__ int hess_eigvals(Mat a, int n, double2 *ev, double2 *cs) {
         __syncthreads();
         for (int k = l; k < hi; ++k) {
             const zd x = ld(&a(k, k), 0), y = ld(&a(k + 1, k), 0);
-            const double ax = zabs(x), ay = zabs(y), rr = hypot(ax, ay);
+            const double x2 = x.re * x.re + x.im * x.im, y2 = y.re * y.re + y.im * y.im;
             double c;
             zd sn;
-            if (rr == 0.0) {
+            if (y2 == 0.0) {
                 c = 1.0;
                 sn = mk(0.0, 0.0);
-            } else if (ax == 0.0) {
+            } else if (x2 == 0.0) {
+                const double iy = 1.0 / sqrt(y2);
                 c = 0.0;
-                sn = mk(y.re / ay, -y.im / ay);
+                sn = mk(y.re * iy, -y.im * iy);
             } else {
-                c = ax / rr;
-                const zd ph = mk(x.re / ax, x.im / ax);
-                sn = (1.0 / rr) * (ph * cconj(y));
+                // c = |x| / r, s = x conj(y) / (|x| r), with one reciprocal
+                const double ax = sqrt(x2), rr = sqrt(x2 + y2);
+                const double inv = 1.0 / (ax * rr);
+                c = ax * ax * inv;
+                sn = inv * (x * cconj(y));
             }
             for (int j = k + tid; j <= hi; j += nt) {
                 const zd u = ld(&a(k, j), 0), v = ld(&a(k + 1, j), 0);
