@@ -222,13 +222,54 @@ int mpmc_defl_keep(mpmc_defl *d, int k);
  * right-hand side has ||b - M x|| / ||b|| <= tol (true FP64 residual).  With
  * defl, x starts from Z Lambda^-1 U^H b and each restart adds Z Lambda^-1 U^H r.
  * net (may be NULL) is a right preconditioner inside the inner cycle
- * (flexible GMRES); it changes cost, never the converged x.  Outputs (host):
+ * (flexible GMRES, requires inner_prec = MPMC_FP32); it changes cost, never
+ * the converged x.  Outputs (host):
  * iters_host = total inner iterations, relres_host[nrhs] = final true
  * relative residuals.  Returns MPMC_ENOCONV after max_outer cycles.
  * Synchronises. */
 int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl,
                const mpmc_net *net, int restart, double tol, int inner_prec,
                int max_outer, int *iters_host, double *relres_host);
+
+/* ------------------------------------------------- learned preconditioner */
+/* Not part of the paper: a small learned right preconditioner N for the main
+ * solves (used by mpmc_solve / mpmc_level_estimate through their net
+ * argument, inside flexible GMRES with FP32 inner cycles).  N is a
+ * gauge-covariant LINEAR network of three parallel-transport layers with
+ * 1 -> 2 -> 2 -> 1 spinor fields:
+ *   out(x)[f', s', c] = sum_p sum_{f,s} W_p[(f',s'),(f,s)] (T_p in)(x)[f, s, c],
+ * p = 0: identity; p = 1..4: +mu, U_mu(x) in(x+mu); p = 5..8: -mu,
+ * U_mu(x-mu)^H in(x-mu), with the operator's time-boundary sign.  W_p acts on
+ * (field, spin), not on colour, so N commutes with gauge transformations.
+ * Arithmetic: BF16 weights and transported inputs on MFMA with FP32
+ * accumulation; activations stored in FP32.
+ * Weights (host, double[mpmc_net_n_params()] = 2304): for layer 0, 1, 2; for
+ * p < 9; for o < 4*f_out; for i < 4*f_in (o, i = field*4 + spin): Re then Im
+ * of W_p[o][i].  The device keeps FP32 master weights.
+ * Training loss over P pairs (r_j, e_j):
+ *   L = (1/P) sum_j ||N r_j - e_j||^2 / ||e_j||^2. */
+int mpmc_net_n_params(void);
+/* New network with the given weights (copied).  Owned by the caller; it
+ * references ctx, which must outlive it. */
+int mpmc_net_create(mpmc_ctx *ctx, const double *theta_host, mpmc_net **out);
+void mpmc_net_destroy(mpmc_net *net);
+/* Replace the weights (and reset the optimiser state).  Synchronises. */
+int mpmc_net_set_weights(mpmc_net *net, const double *theta_host);
+/* Current weights (FP32 master values widened to double).  Synchronises. */
+int mpmc_net_get_weights(const mpmc_net *net, double *theta_host);
+/* y = N x for nrhs FP32 internal-layout vectors (x and y must not alias). */
+int mpmc_net_apply(mpmc_net *net, const void *x, void *y, int nrhs);
+/* Loss L and its gradient dL/dtheta (host double[2304], same order as the
+ * weights; NULL skips) for npairs pairs given as FP32 internal-layout
+ * batches R (inputs r_j) and E (targets e_j).  Synchronises. */
+int mpmc_net_loss_grad(mpmc_net *net, const void *R, const void *E, int npairs,
+                       double *loss_host, double *grad_host);
+/* steps Adam updates (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) of
+ * the weights on the pairs (R, E); loss_host (may be NULL) receives the loss
+ * before each update, double[steps].  The optimiser state persists across
+ * calls on the same net.  Synchronises. */
+int mpmc_net_train(mpmc_net *net, const void *R, const void *E, int npairs, int steps,
+                   double lr, double *loss_host);
 
 /* ---------------------------------------------------------------- estimators */
 

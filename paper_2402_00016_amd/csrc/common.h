@@ -335,6 +335,10 @@ int defl_add(mpmc_ctx *ctx, const mpmc_defl *d, const double *c_dev, void *x, in
 //   x <- (I - Z U^H) x
 int defl_project(mpmc_ctx *ctx, const mpmc_defl *d, void *x, int nrhs);
 
+// net.hip: y = N(x) for FP32 internal-layout batches (learned preconditioner)
+int net_apply_internal(mpmc_ctx *ctx, const mpmc_net *net, const void *x, void *y, int nrhs);
+const mpmc_ctx *net_context(const mpmc_net *net);
+
 // solve.hip
 int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl, const mpmc_net *net,
                    int restart, double tol, int inner_prec, int max_outer, int *iters, double *relres_host);

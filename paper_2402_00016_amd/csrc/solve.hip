@@ -7,7 +7,9 @@
 // returns a correction e, x += e.  All right-hand sides advance together: one
 // Wilson launch, one Gram-Schmidt dot launch and one update launch per inner
 // iteration serve the whole batch, and the per-rhs Hessenberg/Givens state
-// lives on the device.  With a deflation set, x starts at Z Lambda^-1 U^H b and
+// lives on the device.  With a learned preconditioner N the inner cycle is
+// flexible GMRES (z_j = N v_j, Arnoldi on M z_j, correction sum_j y_j z_j).
+// With a deflation set, x starts at Z Lambda^-1 U^H b and
 // each restart adds Z Lambda^-1 U^H r (projection of the small eigen-components).
 #include <algorithm>
 #include <cmath>
@@ -42,7 +44,9 @@ __global__ void k_init_g(double2 *g, int m, int N, const double2 *rn2) {
 
 int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl *defl, const mpmc_net *net,
                    int m, double tol, int inner_prec, int max_outer, int *iters_out, double *relres_host) {
-    if (net) return set_err(ctx, MPMC_EINVAL, "mpmc_solve: learned preconditioner not available in this build");
+    if (net && net_context(net) != ctx) return set_err(ctx, MPMC_ESTATE, "mpmc_solve: network belongs to another context");
+    if (net && inner_prec != MPMC_FP32)
+        return set_err(ctx, MPMC_EINVAL, "mpmc_solve: the learned preconditioner runs with FP32 inner cycles only");
     if (inner_prec != MPMC_FP64 && inner_prec != MPMC_FP32)
         return set_err(ctx, MPMC_EINVAL, "mpmc_solve: inner precision must be FP64 or FP32");
     Scratch S(ctx);
@@ -51,6 +55,7 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
     const long vstride = n * N;   // complex elements between basis vectors
     double *r = (double *)S.get(vb64);
     void *V = S.get(vbi * (m + 1));
+    void *Zb = net ? S.get(vbi * m) : nullptr;   // flexible GMRES: preconditioned basis z_j = N v_j
     void *w = S.get(vbi);
     void *e = S.get(vbi);
     double *H = (double *)S.get(sizeof(double2) * (size_t)(m + 1) * (m + 1) * N);
@@ -61,7 +66,7 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
     double *res = (double *)S.get(sizeof(double) * N);
     double *sc = (double *)S.get(sizeof(double2) * 4 * N);   // [0..N) norms, [N..2N) scales
     double *dc = defl && defl->k ? (double *)S.get(sizeof(double2) * (size_t)defl->k * N) : nullptr;
-    if (!r || !V || !w || !e || !H || !h2 || !cs || !g || !y || !res || !sc || (defl && defl->k && !dc))
+    if (!r || !V || (net && !Zb) || !w || !e || !H || !h2 || !cs || !g || !y || !res || !sc || (defl && defl->k && !dc))
         return MPMC_ENOMEM;
     double *nrm = sc, *scale = sc + 2 * N;
 
@@ -96,15 +101,25 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
         return MPMC_OK;
     };
 
+    // The network is only a preconditioner: a cycle run with it that does not
+    // cut some unconverged residual by 10% switches it off for the rest of the
+    // solve, which then continues as plain (deflated) GMRES.
+    bool use_net = net != nullptr;
+    std::vector<double> rel_start;
     for (int outer = 0; outer < max_outer; ++outer) {
         RET_IF(true_residual());
         if (converged) break;
+        if (use_net && !rel_start.empty())
+            for (int i = 0; i < N; ++i)
+                if (rel[i] > tol && rel[i] > 0.9 * rel_start[i]) use_net = false;
         if (dc) {
             RET_IF(defl_coeffs(ctx, defl, r, N, dc, 1));
             RET_IF(defl_add(ctx, defl, dc, x, N, 1.0));
             RET_IF(true_residual());
             if (converged) break;
         }
+        rel_start = rel;
+        const mpmc_net *cnet = use_net ? net : nullptr;
         // inner targets: the final tolerance for an FP64 cycle; FP32 cycles
         // stop near single precision and the outer loop corrects the rest
         std::vector<double> target(N);
@@ -125,7 +140,13 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
             void *vj = (char *)V + (size_t)j * vstride * es;
             void *vj1 = (char *)V + (size_t)(j + 1) * vstride * es;
             double *Hcol = H + 2 * (size_t)j * (m + 1) * N;
-            RET_IF(wilson_launch_full(ctx, vj, nullptr, w, nullptr, N, inner_prec, make_double2(0, 0),
+            const void *opin = vj;
+            if (cnet) {
+                void *zj = (char *)Zb + (size_t)j * vstride * es;
+                RET_IF(net_apply_internal(ctx, cnet, vj, zj, N));
+                opin = zj;
+            }
+            RET_IF(wilson_launch_full(ctx, opin, nullptr, w, nullptr, N, inner_prec, make_double2(0, 0),
                                       make_double2(1, 0), make_double2(0, 0), 0, 0));
             RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, 0, 0));
             RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, N, -1.0, nullptr));
@@ -147,7 +168,7 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
         }
         RET_IF(dense_backsolve(ctx, H, m + 1, jdone, N, g, y));
         HIP_OR_RET(ctx, hipMemsetAsync(e, 0, vbi, ctx->stream));
-        RET_IF(blas_multi_axpy(ctx, V, vstride, N, jdone, e, N, inner_prec, y, N, 1.0, nullptr));
+        RET_IF(blas_multi_axpy(ctx, cnet ? Zb : V, vstride, N, jdone, e, N, inner_prec, y, N, 1.0, nullptr));
         // x += e (in FP64)
         RET_IF(blas_convert(ctx, e, inner_prec, r, MPMC_FP64, N));
         RET_IF(blas_axpby(ctx, r, x, N, MPMC_FP64, make_double2(1, 0), make_double2(1, 0)));

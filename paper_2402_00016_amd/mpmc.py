@@ -58,6 +58,14 @@ _SIGS = {
     "mpmc_defl_destroy": ([_vp], None),
     "mpmc_defl_keep": ([_vp, _i], _i),
     "mpmc_solve": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
+    "mpmc_net_n_params": ([], _i),
+    "mpmc_net_create": ([_vp, _vp, ctypes.POINTER(_vp)], _i),
+    "mpmc_net_destroy": ([_vp], None),
+    "mpmc_net_set_weights": ([_vp, _vp], _i),
+    "mpmc_net_get_weights": ([_vp, _vp], _i),
+    "mpmc_net_apply": ([_vp, _vp, _vp, _i], _i),
+    "mpmc_net_loss_grad": ([_vp, _vp, _vp, _i, _pd, _vp], _i),
+    "mpmc_net_train": ([_vp, _vp, _vp, _i, _i, _d, _vp], _i),
     "mpmc_level_estimate": ([_vp, _vp, _vp, _vp, _i, _u64, _u32, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp,
                              _pu64], _i),
 }
@@ -255,6 +263,53 @@ def mpmc_level_estimate(ctx, upper, lower, defl, theta, seed, stream, first, nno
     return samples, complex(corr[0]), mvps.value
 
 
+def mpmc_net_n_params():
+    return _L.mpmc_net_n_params()
+
+
+def mpmc_net_create(ctx, theta):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    if th.size != mpmc_net_n_params():
+        raise ValueError("network weights: %d values, expected %d" % (th.size, mpmc_net_n_params()))
+    out = _vp()
+    _check(_L.mpmc_net_create(ctx, th.ctypes.data, ctypes.byref(out)), ctx)
+    return out
+
+
+def mpmc_net_destroy(handle):
+    _L.mpmc_net_destroy(handle)
+
+
+def mpmc_net_set_weights(handle, theta):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    if th.size != mpmc_net_n_params():
+        raise ValueError("network weights: %d values, expected %d" % (th.size, mpmc_net_n_params()))
+    _check(_L.mpmc_net_set_weights(handle, th.ctypes.data), None)
+
+
+def mpmc_net_get_weights(handle):
+    th = np.zeros(mpmc_net_n_params())
+    _check(_L.mpmc_net_get_weights(handle, th.ctypes.data), None)
+    return th
+
+
+def mpmc_net_apply(handle, x, y, nrhs):
+    _check(_L.mpmc_net_apply(handle, _ptr(x), _ptr(y), int(nrhs)), None)
+
+
+def mpmc_net_loss_grad(handle, R, E, npairs):
+    loss = ctypes.c_double()
+    grad = np.zeros(mpmc_net_n_params())
+    _check(_L.mpmc_net_loss_grad(handle, _ptr(R), _ptr(E), int(npairs), ctypes.byref(loss), grad.ctypes.data), None)
+    return loss.value, grad
+
+
+def mpmc_net_train(handle, R, E, npairs, steps, lr):
+    hist = np.zeros(int(steps))
+    _check(_L.mpmc_net_train(handle, _ptr(R), _ptr(E), int(npairs), int(steps), float(lr), hist.ctypes.data), None)
+    return hist
+
+
 # ---------------------------------------------------------- object wrappers
 
 class _Handle:
@@ -297,6 +352,31 @@ class Poly(_Handle):
 
     def eval(self, lam):
         return mpmc_poly_eval(self.handle, lam)
+
+
+class Net(_Handle):
+    """Learned right preconditioner (gauge-covariant linear network)."""
+    _destroy = staticmethod(mpmc_net_destroy)
+
+    @property
+    def weights(self):
+        return mpmc_net_get_weights(self.handle)
+
+    @weights.setter
+    def weights(self, theta):
+        mpmc_net_set_weights(self.handle, theta)
+
+    def apply(self, x, nrhs, out=None):
+        """y = N(x) for FP32 internal-layout batches."""
+        y = self.owner.vector(nrhs, FP32) if out is None else out
+        mpmc_net_apply(self.handle, x, y, nrhs)
+        return y
+
+    def loss_grad(self, R, E, npairs):
+        return mpmc_net_loss_grad(self.handle, R, E, npairs)
+
+    def train(self, R, E, npairs, steps, lr):
+        return mpmc_net_train(self.handle, R, E, npairs, steps, lr)
 
 
 class Defl(_Handle):
@@ -404,12 +484,15 @@ class Context:
         return lam, Z[:defl.k], U[:defl.k]
 
     # solves and levels
-    def solve(self, b, nrhs, defl=None, restart=50, tol=1e-8, inner_prec=FP64, max_outer=100, x=None):
+    def net(self, theta):
+        return Net(mpmc_net_create(self.handle, theta), self)
+
+    def solve(self, b, nrhs, defl=None, restart=50, tol=1e-8, inner_prec=FP64, max_outer=100, x=None, net=None):
         x = self.vector(nrhs, FP64) if x is None else x
-        its, rel, rc = mpmc_solve(self.handle, b, x, nrhs, defl, None, restart, tol, inner_prec, max_outer)
+        its, rel, rc = mpmc_solve(self.handle, b, x, nrhs, defl, net, restart, tol, inner_prec, max_outer)
         return x, its, rel
 
     def level(self, upper, lower, defl, theta, seed, stream, first, nnoise, prec=FP64, max_batch=0,
-              solve_tol=1e-8, solve_restart=50, solve_inner_prec=FP64):
+              solve_tol=1e-8, solve_restart=50, solve_inner_prec=FP64, net=None):
         return mpmc_level_estimate(self.handle, upper, lower, defl, theta, seed, stream, first, nnoise, prec,
-                                   max_batch, solve_tol, solve_restart, solve_inner_prec, None)
+                                   max_batch, solve_tol, solve_restart, solve_inner_prec, net)
