@@ -12,9 +12,11 @@ accumulation and FP64 defect correction of the main solves (relative residual
 Printed metric: multi-RHS Dslash HBM GB/s = algorithmic bytes moved by all
 Wilson-kernel launches of a step / wall time of the step.  The dominant
 kernel's own rate (bytes / summed HIP-event kernel time) is the roofline
-"achieved" figure; the FP64 form of the same estimate is timed beside it for
-the time-to-fixed-standard-error comparison, and the FP64 CPU oracle is timed
-on the host as the baseline.
+"achieved" figure.  Beside it, at the same noise seeds and counts (hence the
+same standard error): the plain FP64 form of the estimate and the learned
+form (the main solves preconditioned by the trained network; its training is
+timed separately), for the time-to-fixed-standard-error comparison.  The FP64
+CPU oracle is timed on the host as the baseline.
 """
 import argparse
 import json
@@ -35,6 +37,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--noises", type=int, default=128)
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison form")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
@@ -132,6 +135,35 @@ def main():
         "time_to_error_s": {"mixed_batched": round(step_s, 4)},
         "fp64_kernel_share": {"launches": n64, "ms_per_step": round(ms64 / a.steps, 3)},
     }
+    def solve_term(e):
+        L = e.levels[0]
+        return {"s": round(L.seconds, 4), "mvps": L.mvps}
+
+    out["solve_term"] = {"mixed_batched": solve_term(est)}
+    if not a.no_learned:
+        # learned form: the network is trained once per gauge field (timed
+        # separately) and then preconditions the main solves of the estimate
+        lplan = driver.Plan(**{**plan.__dict__, "learned": True})
+        sync()
+        tl = time.perf_counter()
+        net, hist = driver.train_net(ctx, lplan)
+        sync()
+        t_train = time.perf_counter() - tl
+        driver.estimate(ctx, lplan, sync, net=net)
+        sync()
+        tl = time.perf_counter()
+        el = driver.estimate(ctx, lplan, sync, net=net)
+        sync()
+        tl = time.perf_counter() - tl
+        out["time_to_error_s"]["learned_batched"] = round(tl, 4)
+        out["time_to_error_s"]["net_training"] = round(t_train, 4)
+        out["time_to_error_s"]["learned_batched_incl_training"] = round(tl + t_train, 4)
+        out["solve_term"]["learned_batched"] = solve_term(el)
+        out["net"] = {"pairs": lplan.net_batches * lplan.net_pairs, "adam_steps": lplan.net_batches * lplan.net_steps,
+                      "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
+        comb = float(np.hypot(el.stderr, est.stderr))
+        out["trace"]["learned"] = {"value": [el.value.real, el.value.imag], "stderr": el.stderr,
+                                   "diff_in_combined_sigma": abs(est.value - el.value) / comb}
     if not a.no_plain:
         plain = driver.Plan(**{**plan.__dict__, "poly_prec": mpmc.FP64, "solve_inner_prec": mpmc.FP64})
         driver.estimate(ctx, plain, sync)
@@ -142,6 +174,11 @@ def main():
         tp = time.perf_counter() - tp
         out["time_to_error_s"]["plain_fp64"] = round(tp, 4)
         out["time_to_error_s"]["speedup_mixed_vs_plain"] = round(tp / step_s, 3)
+        if "learned_batched" in out["time_to_error_s"]:
+            out["time_to_error_s"]["speedup_learned_vs_plain"] = round(tp / out["time_to_error_s"]["learned_batched"], 3)
+            out["time_to_error_s"]["speedup_learned_incl_training_vs_plain"] = round(
+                tp / out["time_to_error_s"]["learned_batched_incl_training"], 3)
+        out["solve_term"]["plain_fp64"] = solve_term(e64)
         comb = float(np.hypot(e64.stderr, est.stderr))
         out["trace"]["plain_fp64"] = {"value": [e64.value.real, e64.value.imag], "stderr": e64.stderr,
                                       "diff_in_combined_sigma": abs(est.value - e64.value) / comb}

@@ -24,7 +24,7 @@
 //                   W'_q = (W_{q~})^H, q~ swapping +mu and -mu.
 //   k_net_wgrad  -- weight gradient dL/dW_p^* = sum_{x, rhs, c} g(x) conj(T_p a(x))
 //                   as MFMAs with the right-hand sides as the contraction
-//                   index; per-wavefront partials, reduced in a fixed order.
+//                   index; per-wavefront partials, summed in a fixed order.
 //   k_net_loss, k_net_adam, k_net_pack -- loss and output gradient, Adam,
 //                   and the BF16 operand tables built from the FP32 master
 //                   weights.
@@ -45,7 +45,7 @@ constexpr int NPARAM = 2304;
 constexpr int FIELDS[4] = {1, 2, 2, 1};
 constexpr int LAYER_OFF[4] = {0, 576, 1728, 2304};   // real parameters before layer l
 constexpr int TABLE_ELEMS = NPATH * 64 * 4;          // bf16 A-operand table of one layer op
-constexpr int WGRAD_WAVES = 2048;                    // wavefronts of the weight-gradient grid
+constexpr int WGRAD_WAVES = 1024;                    // wavefronts of the weight-gradient grid
 
 __device__ __forceinline__ short to_bf16(float f) {
     return __builtin_bit_cast(short, (__bf16)f);
@@ -299,29 +299,35 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const float2 *__restrict__ a_
         for (int r = 0; r < 4; ++r) dst[p * 256 + lane * 4 + r] = acc[p][r];
 }
 
-// Sum the per-wave partials (fixed order, FP64) and map them to the real
+// Sum the per-wave partials in a fixed order: block (p, chunk) of 256
+// threads owns 64 entries of P_p; thread slice q < 4 adds waves w = q mod 4,
+// then the four slices are combined in order.  psum[p*256 + e] (FP64).
+__global__ __launch_bounds__(256) void k_net_wgrad_sum(const float *__restrict__ partial, int nwaves,
+                                                       double *__restrict__ psum) {
+    __shared__ double red[4][64];
+    const int p = blockIdx.x >> 2, chunk = blockIdx.x & 3;
+    const int e = chunk * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+    double s = 0.0;
+    for (int w = q; w < nwaves; w += 4) s += (double)partial[((size_t)w * NPATH + p) * 256 + e];
+    red[q][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (q == 0) psum[p * 256 + e] = ((red[0][e & 63] + red[1][e & 63]) + red[2][e & 63]) + red[3][e & 63];
+}
+
+// Map P (psum, entry lane*4 + r = P[4 (lane/16) + r][lane % 16]) to the real
 // gradient of the parameters of one layer:
 //   dL/dW^* = Re: P[2o][2ci] + P[2o+1][2ci+1],  Im: P[2o+1][2ci] - P[2o][2ci+1];
 //   d loss/d Re w = 2 Re(dL/dW^*), d loss/d Im w = 2 Im(dL/dW^*).
-__global__ void k_net_wgrad_reduce(const float *__restrict__ partial, int nwaves, int layer,
-                                   double *__restrict__ grad) {
+__global__ void k_net_wgrad_map(const double *__restrict__ psum, int layer, double *__restrict__ grad) {
     const int fin = FIELDS[layer], fout = FIELDS[layer + 1];
     const int npar = LAYER_OFF[layer + 1] - LAYER_OFF[layer];
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= npar) return;
     const int part = t & 1, idx = t >> 1;
     const int ci = idx % (4 * fin), o = (idx / (4 * fin)) % (4 * fout), p = idx / (16 * fin * fout);
-    auto at = [&](int i, int b) {
-        const int lane = (i >> 2) * 16 + b, r = i & 3;
-        double s = 0.0;
-        for (int w = 0; w < nwaves; ++w) s += (double)partial[((size_t)w * NPATH + p) * 256 + lane * 4 + r];
-        return s;
-    };
-    double v;
-    if (part == 0)
-        v = at(2 * o, 2 * ci) + at(2 * o + 1, 2 * ci + 1);
-    else
-        v = at(2 * o + 1, 2 * ci) - at(2 * o, 2 * ci + 1);
+    auto at = [&](int i, int b) { return psum[p * 256 + ((i >> 2) * 16 + b) * 4 + (i & 3)]; };
+    const double v = part == 0 ? at(2 * o, 2 * ci) + at(2 * o + 1, 2 * ci + 1)
+                               : at(2 * o + 1, 2 * ci) - at(2 * o, 2 * ci + 1);
     grad[LAYER_OFF[layer] + t] = 2.0 * v;
 }
 
@@ -420,7 +426,7 @@ int launch_layer(mpmc_ctx *ctx, const mpmc_net *net, int op, const void *in, voi
 }
 
 int launch_wgrad(mpmc_ctx *ctx, mpmc_net *net, int layer, const void *a_in, const void *gout, int N,
-                 float *partial) {
+                 float *partial, double *psum) {
     const int fin = FIELDS[layer], fout = FIELDS[layer + 1];
     const int nrb = (N + 15) / 16;
     const long units = ctx->V * nrb;
@@ -438,8 +444,10 @@ int launch_wgrad(mpmc_ctx *ctx, mpmc_net *net, int layer, const void *a_in, cons
     return set_err(ctx, MPMC_EINVAL, "network: bad layer shape");
 #undef WG
     HIP_OR_RET(ctx, hipGetLastError());
+    k_net_wgrad_sum<<<NPATH * 4, 256, 0, ctx->stream>>>(partial, (int)blocks * 4, psum);
+    HIP_OR_RET(ctx, hipGetLastError());
     const int npar = LAYER_OFF[layer + 1] - LAYER_OFF[layer];
-    k_net_wgrad_reduce<<<grid_for(npar, 64), 64, 0, ctx->stream>>>(partial, (int)blocks * 4, layer, net->grad);
+    k_net_wgrad_map<<<grid_for(npar, 64), 64, 0, ctx->stream>>>(psum, layer, net->grad);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
@@ -461,7 +469,8 @@ int net_loss_grad(mpmc_net *net, const void *R, const void *E, int P) {
     double *en2 = (double *)S.get(sizeof(double2) * P);
     double *lpart = (double *)S.get(sizeof(double) * lblocks);
     float *partial = (float *)S.get(sizeof(float) * (size_t)WGRAD_WAVES * NPATH * 256);
-    if (!a1 || !a2 || !a3 || !g3 || !g2 || !g1 || !en2 || !lpart || !partial) return MPMC_ENOMEM;
+    double *psum = (double *)S.get(sizeof(double) * NPATH * 256);
+    if (!a1 || !a2 || !a3 || !g3 || !g2 || !g1 || !en2 || !lpart || !partial || !psum) return MPMC_ENOMEM;
     RET_IF(launch_layer(ctx, net, 0, R, a1, P));
     RET_IF(launch_layer(ctx, net, 2, a1, a2, P));
     RET_IF(launch_layer(ctx, net, 4, a2, a3, P));
@@ -471,11 +480,11 @@ int net_loss_grad(mpmc_net *net, const void *R, const void *E, int P) {
     HIP_OR_RET(ctx, hipGetLastError());
     k_sum_fixed<<<1, 64, 0, ctx->stream>>>(lpart, (int)lblocks, net->loss);
     HIP_OR_RET(ctx, hipGetLastError());
-    RET_IF(launch_wgrad(ctx, net, 2, a2, g3, P, partial));
+    RET_IF(launch_wgrad(ctx, net, 2, a2, g3, P, partial, psum));
     RET_IF(launch_layer(ctx, net, 5, g3, g2, P));
-    RET_IF(launch_wgrad(ctx, net, 1, a1, g2, P, partial));
+    RET_IF(launch_wgrad(ctx, net, 1, a1, g2, P, partial, psum));
     RET_IF(launch_layer(ctx, net, 3, g2, g1, P));
-    RET_IF(launch_wgrad(ctx, net, 0, R, g1, P, partial));
+    RET_IF(launch_wgrad(ctx, net, 0, R, g1, P, partial, psum));
     return MPMC_OK;
 }
 

@@ -12,6 +12,12 @@ sqrt(sum_l s_l^2 / N_l) with s_l^2 the complex sample variance.
 
 Random streams: level l uses stream l, the GMRES start vector of polynomial j
 uses stream 0x100 + j, the deflation start vector stream 0x200.
+
+Learned form (not in the paper): a gauge-covariant linear network N is trained
+on the device on residual/error pairs (r, e) = (M e, e), e a Z(4) vector drawn
+with seeds net_seed0, net_seed0 + 1, ... (stream 0), and then preconditions the
+main solves (flexible GMRES).  The solves still stop on the same FP64 true
+residual, so the estimate does not depend on N.
 """
 import math
 import time
@@ -47,6 +53,12 @@ class Plan:
     solve_restart: int = 50
     max_batch: int = 0                   # right-hand sides per launch (0: all noise of a level)
     deflate_levels: bool = True
+    learned: bool = False                # precondition the main solves with a trained network
+    net_batches: int = 8                 # training minibatches (one Z(4) seed each)
+    net_pairs: int = 64                  # (r, e) pairs per minibatch
+    net_steps: int = 10                  # Adam steps per minibatch
+    net_lr: float = 1e-2
+    net_seed0: int = 100
 
 
 @dataclass
@@ -117,13 +129,45 @@ def build_deflation(ctx, plan: Plan):
     return D
 
 
+NET_FIELDS = (1, 2, 2, 1)
+
+
+def net_identity_weights():
+    """Weights for which the network is the identity map: in every layer, path 0
+    maps spin s of field 0 to spin s of field 0.  Order: layer, path p < 9,
+    output channel o < 4 f_out, input channel i < 4 f_in, (Re, Im)."""
+    out = []
+    for l in range(3):
+        fin, fout = NET_FIELDS[l], NET_FIELDS[l + 1]
+        W = np.zeros((9, 4 * fout, 4 * fin, 2))
+        for sp in range(4):
+            W[0, sp, sp, 0] = 1.0
+        out.append(W.ravel())
+    return np.concatenate(out)
+
+
+def train_net(ctx, plan: Plan):
+    """Network trained on (M e, e) pairs; initial weights: identity plus a small
+    seeded perturbation (so that the second field receives gradient).
+    Returns (net, loss history)."""
+    rng = np.random.default_rng(plan.seed)
+    theta0 = net_identity_weights() + 0.01 * rng.standard_normal(mpmc.mpmc_net_n_params())
+    net = ctx.net(theta0)
+    hist = []
+    for b in range(plan.net_batches):
+        e = ctx.noise(plan.net_seed0 + b, 0, 0, plan.net_pairs, mpmc.FP32)
+        r = ctx.apply_M(e, plan.net_pairs, mpmc.FP32)
+        hist.extend(net.train(r, e, plan.net_pairs, plan.net_steps, plan.net_lr))
+    return net, np.array(hist)
+
+
 def combine(levels):
     est = sum((L.mean + L.corr for L in levels), 0j)
     var = sum(L.var / L.n for L in levels)
     return est, math.sqrt(var)
 
 
-def run_levels(ctx, plan: Plan, polys, defl, noises=None, first=0):
+def run_levels(ctx, plan: Plan, polys, defl, noises=None, first=0, net=None):
     """Samples of every term of the multipolynomial formula."""
     noises = plan.noises if noises is None else noises
     names = ["M^-1 - p1"] + ["p%d - p%d" % (i + 1, i + 2) for i in range(len(polys) - 1)] + ["p%d" % len(polys)]
@@ -135,29 +179,37 @@ def run_levels(ctx, plan: Plan, polys, defl, noises=None, first=0):
         t0 = time.perf_counter()
         X, T, mv = ctx.level(up, lo, d, plan.theta, plan.seed, l, first, noises, prec=plan.poly_prec,
                              max_batch=plan.max_batch, solve_tol=plan.solve_tol, solve_restart=plan.solve_restart,
-                             solve_inner_prec=plan.solve_inner_prec)
+                             solve_inner_prec=plan.solve_inner_prec, net=net if up is None else None)
         out.append(LevelResult(names[l], X, T, mv, time.perf_counter() - t0))
     return out
 
 
-def estimate(ctx, plan: Plan, sync=None) -> Estimate:
-    """Full estimate: polynomials, deflation, all levels (fixed noise counts)."""
+def estimate(ctx, plan: Plan, sync=None, net=None) -> Estimate:
+    """Full estimate: polynomials, deflation, (network training when the plan
+    is learned and no trained net is given), all levels (fixed noise counts)."""
     sync = sync or (lambda: None)
     mv0 = ctx.mvps
     t0 = time.perf_counter()
     defl = build_deflation(ctx, plan)
     polys = build_polys(ctx, plan)
+    info = {}
+    if plan.learned and net is None:
+        sync()
+        tn = time.perf_counter()
+        net, hist = train_net(ctx, plan)
+        sync()
+        info = dict(net_train_seconds=time.perf_counter() - tn, net_loss=[float(hist[0]), float(hist[-1])])
     sync()
     t1 = time.perf_counter()
-    levels = run_levels(ctx, plan, polys, defl)
+    levels = run_levels(ctx, plan, polys, defl, net=net if plan.learned else None)
     sync()
     t2 = time.perf_counter()
     est, se = combine(levels)
     return Estimate(est, se, levels, t1 - t0, t2 - t0, ctx.mvps - mv0, polys=polys,
-                    defl_k=defl.k if defl is not None else 0)
+                    defl_k=defl.k if defl is not None else 0, info=info)
 
 
-def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_every=3, max_noises=4096):
+def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_every=3, max_noises=4096, net=None):
     """Adaptive stopping (Sec. 8): each Monte Carlo term stops once its standard
     error is below eps / sqrt(#terms), with minimum counts 2 (solve term),
     3 (first difference), 6 (later terms) and checks every `check_every` noises."""
@@ -181,7 +233,8 @@ def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_e
             ts = time.perf_counter()
             Xn, corr, m = ctx.level(up, lo, d, plan.theta, plan.seed, l, len(X), want, prec=plan.poly_prec,
                                     solve_tol=plan.solve_tol, solve_restart=plan.solve_restart,
-                                    solve_inner_prec=plan.solve_inner_prec)
+                                    solve_inner_prec=plan.solve_inner_prec,
+                                    net=net if (up is None and plan.learned) else None)
             secs += time.perf_counter() - ts
             mv += m
             X = np.concatenate([X, Xn])

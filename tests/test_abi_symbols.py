@@ -1,6 +1,8 @@
 """The C-ABI library loads and exports every function include/mpmc.h declares
 (no compute calls: this runs without a GPU)."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -45,3 +47,11 @@ def test_product_path_does_not_import_the_oracle():
                 src = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", src, flags=re.M), f
                 assert "oracle/" not in src and "liboracle" not in src, f
+
+
+def test_driver_identity_weights_match_oracle():
+    from oracle import net as ON
+    from paper_2402_00016_amd import driver, mpmc
+    w = driver.net_identity_weights()
+    assert w.size == mpmc.mpmc_net_n_params() == ON.n_params()
+    assert np.array_equal(w, ON.identity_theta())
