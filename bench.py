@@ -4,7 +4,8 @@
 Workload (one "step" = one complete trace estimate): 8^4 lattice
 (n = 49152), SU(3) links U = exp(i 0.5 H) from seed 2, Wilson kappa = 0.120,
 Theta = I; GMRES polynomials of degree 128, 32 and 8; the 20 lowest eigenpairs
-of M from PP-Arnoldi; 128 Z(4) noise vectors per Monte Carlo term, each term's
+of M asked from PP-Arnoldi (112 steps on M p_in(M), p_in of degree 8; the
+pairs that pass the residual test are deflated); 128 Z(4) noise vectors per Monte Carlo term, each term's
 noise processed as one multi-RHS batch; FP32 Wilson kernels with FP64
 accumulation and FP64 defect correction of the main solves (relative residual
 1e-8).  The step includes building the polynomials and the deflation set.
@@ -85,8 +86,8 @@ def main():
     dims, eps, seed, kappa = (8, 8, 8, 8), 0.5, 2, 0.120
     links = inputs.gauge_links(dims, eps, seed)
     ctx = mpmc.Context(dims, kappa, links)
-    plan = driver.Plan(degrees=[128, 32, 8], noises=a.noises, seed=seed, nev=20, defl_candidates=40, defl_m=136,
-                       defl_pin_degree=32,
+    plan = driver.Plan(degrees=[128, 32, 8], noises=a.noises, seed=seed, nev=20, defl_candidates=40, defl_m=112,
+                       defl_pin_degree=8,
                        poly_prec=mpmc.FP32, solve_inner_prec=mpmc.FP32, solve_tol=1e-8, solve_restart=50)
     sync = torch.cuda.synchronize
 

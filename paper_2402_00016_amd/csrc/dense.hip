@@ -7,8 +7,8 @@
 //  * Ritz vectors by inverse iteration on H - mu I (deflation, Sec. 7),
 //  * per-rhs Givens updates and back substitution of restarted GMRES solves.
 // The matrices are at most a few hundred rows: one wavefront (64 lanes) works
-// on one matrix; the matrix lives in global memory (L2 resident) because it
-// does not fit in LDS for d > 90.  Every loop has a fixed iteration bound.
+// on one matrix, which lives in LDS (packed Hessenberg) up to 137 rows and in
+// global memory (L2 resident) beyond.  Every loop has a fixed iteration bound.
 #include <cfloat>
 
 #include "common.h"
@@ -38,57 +38,154 @@ __device__ __forceinline__ void st(double2 *p, long i, zd v) { p[i] = make_doubl
 // --------------------------------------------------- Hessenberg QR eigs --
 // Matrix accessors: column-major in global memory, or packed upper Hessenberg
 // in LDS (column j holds rows 0..min(j+1, n-1) at offset j(j+3)/2).
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) dvec2 lds_dvec2;
 struct GlobalMat {
     double2 *A;
     int lda;
     __device__ __forceinline__ double2 &operator()(int i, int j) const { return A[i + (long)j * lda]; }
+    __device__ __forceinline__ zd get(int i, int j) const {
+        const double2 v = A[i + (long)j * lda];
+        return mk(v.x, v.y);
+    }
+    __device__ __forceinline__ void set(int i, int j, zd v) const { A[i + (long)j * lda] = make_double2(v.re, v.im); }
 };
 struct PackedMat {
     double2 *A;
     __device__ __forceinline__ double2 &operator()(int i, int j) const { return A[j * (j + 3) / 2 + i]; }
+    // direct LDS addressing: the low 32 bits of a flat LDS address are the LDS offset
+    __device__ __forceinline__ lds_dvec2 *lds() const { return (lds_dvec2 *)(uintptr_t)(uint32_t)(uintptr_t)A; }
+    __device__ __forceinline__ zd get(int i, int j) const {
+        const dvec2 v = lds()[j * (j + 3) / 2 + i];
+        return mk(v.x, v.y);
+    }
+    __device__ __forceinline__ void set(int i, int j, zd v) const {
+        dvec2 w;
+        w.x = v.re;
+        w.y = v.im;
+        lds()[j * (j + 3) / 2 + i] = w;
+    }
 };
 __host__ __device__ inline long packed_hess_size(int n) { return (long)(n - 1) * (n + 2) / 2 + n; }
 
+// Broadcast of lane `src` (wave-uniform) of a complex double register value.
+__device__ __forceinline__ double rdlane(double v, int src) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, src), hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ zd rdlane(zd v, int src) { return mk(rdlane(v.re, src), rdlane(v.im, src)); }
+
+// 1/sqrt(z) for z > 0: hardware estimate plus one Newton step.
+__device__ __forceinline__ double rsqrt_nr(double z) {
+    const double r = __builtin_amdgcn_rsq(z);
+    const double e = fma(-z * r, r, 1.0);
+    return fma(0.5 * r, e, r);
+}
+
+// Givens rotation G = [c s; -conj(s) c] with G [x; y] = [r; 0], c real >= 0:
+// c = |x| / r, s = x conj(y) / (|x| r), r = sqrt(|x|^2 + |y|^2).
+__device__ __forceinline__ void givens(zd x, zd y, double &c, zd &sn) {
+    const double x2 = x.re * x.re + x.im * x.im, y2 = y.re * y.re + y.im * y.im;
+    if (y2 == 0.0) {
+        c = 1.0;
+        sn = mk(0.0, 0.0);
+    } else if (x2 == 0.0) {
+        const double iy = rsqrt_nr(y2);
+        c = 0.0;
+        sn = mk(y.re * iy, -y.im * iy);
+    } else {
+        const double ix = rsqrt_nr(x2), ir = rsqrt_nr(x2 + y2);
+        c = x2 * ix * ir;
+        sn = (ix * ir) * (x * cconj(y));
+    }
+}
+
+template <typename Mat>
+__device__ __forceinline__ zd ld_shift(const Mat &a, int i, int j, zd sigma) {   // element of A - sigma
+    const zd v = a.get(i, j);
+    return i == j ? v - sigma : v;
+}
+
+template <int MAXC>
+__device__ __forceinline__ zd pick(const zd (&v)[MAXC], int q) {
+    zd r = mk(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i < MAXC; ++i)
+        if (i == q) r = v[i];
+    return r;
+}
+
 // Eigenvalues of the upper Hessenberg matrix held by `a` (destroyed): shifted
 // QR with Givens rotations, Wilkinson shifts, exceptional shifts every 11
-// iterations without deflation, deflation from the bottom.  Called by all lanes
-// of one workgroup; returns 0, or -1 on non-convergence or NaN.
-template <typename Mat>
+// iterations without deflation, deflation from the bottom.  Must be called by
+// exactly one wavefront of 64 lanes (n <= 64 * MAXC); returns 0, or -1 on
+// non-convergence or NaN.
+//
+// One QR step A - sigma = QR, A' = RQ + sigma on the active window [l, hi] is
+// a single sweep over k = l .. hi-1 without barriers:
+//  * rows: lane t owns columns j = t + 64 q.  Row k (already rotated by
+//    G_{k-1}) is carried in registers and row k+1 prefetched, so the only
+//    cross-lane step is the broadcast (readlane) of the pivot pair
+//    (a(k,k), a(k+1,k)) from the lane owning column k; R's row k is stored;
+//  * columns, one step behind: lane t owns rows i = l + t + 64 r and applies
+//    G_{k-1}^H to columns k-1, k (rows <= k).  Column k is carried in
+//    registers; the R entries it needs were stored at least two steps earlier
+//    or are broadcast from the lanes that produced them in this step or the
+//    last, so no lane reads an element another lane writes in the same step.
+// The shift is subtracted when diagonal entries are loaded and added back when
+// final diagonal entries are stored.  `cs` is unused (kept for the callers'
+// workspace layout).
+template <int MAXC, typename Mat>
 __device__ int hess_eigvals(Mat a, int n, double2 *ev, double2 *cs) {
-    // cs: 2n entries of rotation storage (cosines in .x of cs[k], sines in cs[n + k])
-    const int tid = threadIdx.x, nt = blockDim.x;
+    (void)cs;
+    const int lane = threadIdx.x;
     int hi = n - 1, iter = 0, total = 0;
     const int max_total = 60 * n + 100;
     int status = 0;
     while (hi >= 0) {
         __syncthreads();
         if (hi == 0) {
-            if (tid == 0) ev[0] = a(0, 0);
+            if (lane == 0) st(ev, 0, a.get(0, 0));
             break;
         }
-        int l = hi;
-        while (l > 0) {
-            const double2 sv = a(l, l - 1), d0 = a(l - 1, l - 1), d1 = a(l, l);
-            const double sub = fabs(sv.x) + fabs(sv.y);
-            const double dia = fabs(d0.x) + fabs(d0.y) + fabs(d1.x) + fabs(d1.y);
-            if (!(sub == sub)) { status = -1; break; }
-            if (sub <= 0.5 * DBL_EPSILON * dia || sub < 1e-300) break;
-            --l;
+        // l: the largest index in [1, hi] with a negligible subdiagonal a(l, l-1), else 0;
+        // 64 subdiagonals are tested at once, from the bottom up
+        int l = 0;
+        for (int top = hi; top >= 1; top -= 64) {
+            const int i = top - lane;
+            bool small = false, bad = false;
+            if (i >= 1) {
+                const zd sv = a.get(i, i - 1), d0 = a.get(i - 1, i - 1), d1 = a.get(i, i);
+                const double sub = fabs(sv.re) + fabs(sv.im);
+                const double dia = fabs(d0.re) + fabs(d0.im) + fabs(d1.re) + fabs(d1.im);
+                bad = !(sub == sub);
+                small = sub <= 0.5 * DBL_EPSILON * dia || sub < 1e-300;
+            }
+            if (__ballot(bad)) {
+                status = -1;
+                break;
+            }
+            const unsigned long long m = __ballot(small);
+            if (m) {
+                l = top - __builtin_ctzll(m);
+                break;
+            }
         }
         if (status) break;
         if (l == hi) {
-            if (tid == 0) ev[hi] = a(hi, hi);
+            if (lane == 0) st(ev, hi, a.get(hi, hi));
             --hi;
             iter = 0;
             continue;
         }
         if (l == hi - 1) {
-            const zd p = ld(&a(hi - 1, hi - 1), 0), q = ld(&a(hi - 1, hi), 0), r = ld(&a(hi, hi - 1), 0),
-                     s = ld(&a(hi, hi), 0);
+            const zd p = a.get(hi - 1, hi - 1), q = a.get(hi - 1, hi), r = a.get(hi, hi - 1),
+                     s = a.get(hi, hi);
             const zd half_tr = 0.5 * (p + s);
             const zd det = p * s - q * r;
             const zd disc = zsqrt(half_tr * half_tr - det);
-            if (tid == 0) {
+            if (lane == 0) {
                 st(ev, hi - 1, half_tr + disc);
                 st(ev, hi, half_tr - disc);
             }
@@ -96,61 +193,99 @@ __device__ int hess_eigvals(Mat a, int n, double2 *ev, double2 *cs) {
             iter = 0;
             continue;
         }
-        if (++total > max_total) { status = -1; break; }
+        if (++total > max_total) {
+            status = -1;
+            break;
+        }
         ++iter;
-        const zd p = ld(&a(hi - 1, hi - 1), 0), q = ld(&a(hi - 1, hi), 0), r = ld(&a(hi, hi - 1), 0),
-                 s = ld(&a(hi, hi), 0);
+        const zd p = a.get(hi - 1, hi - 1), q = a.get(hi - 1, hi), r = a.get(hi, hi - 1),
+                 s = a.get(hi, hi);
         const zd half_tr = 0.5 * (p + s), det = p * s - q * r;
         const zd disc = zsqrt(half_tr * half_tr - det);
         zd e1 = half_tr + disc, e2 = half_tr - disc;
         zd sigma = zabs(e1 - s) <= zabs(e2 - s) ? e1 : e2;
         if (iter % 11 == 10) {
-            const double m = zabs(r) + zabs(ld(&a(hi - 1, hi - 2 >= l ? hi - 2 : hi - 1), 0));
+            const double m = zabs(r) + zabs(a.get(hi - 1, hi - 2 >= l ? hi - 2 : hi - 1));
             sigma = s + mk(0.75 * m, 0.4375 * m);
         }
-        for (int i = l + tid; i <= hi; i += nt) st(&a(i, i), 0, ld(&a(i, i), 0) - sigma);
-        __syncthreads();
+        __syncthreads();   // every lane has read the window before it changes
+
+        zd cur[MAXC], nxt[MAXC];    // rows k and k+1 at the lane's columns
+        zd col[MAXC], vk[MAXC];     // a(i, k-1) (rotated) and R(i, k) at the lane's rows
+#pragma unroll
+        for (int q2 = 0; q2 < MAXC; ++q2) {
+            const int j = lane + 64 * q2;
+            cur[q2] = nxt[q2] = col[q2] = vk[q2] = mk(0.0, 0.0);
+            if (j >= l && j <= hi) {
+                cur[q2] = ld_shift(a, l, j, sigma);
+                nxt[q2] = ld_shift(a, l + 1, j, sigma);
+            }
+        }
+        double cp = 1.0;            // G_{k-1}
+        zd sp = mk(0.0, 0.0);
         for (int k = l; k < hi; ++k) {
-            const zd x = ld(&a(k, k), 0), y = ld(&a(k + 1, k), 0);
-            const double x2 = x.re * x.re + x.im * x.im, y2 = y.re * y.re + y.im * y.im;
+            const int qk = k >> 6, lk = k & 63;
+            const zd x = rdlane(pick(cur, qk), lk), y = rdlane(pick(nxt, qk), lk);
             double c;
             zd sn;
-            if (y2 == 0.0) {
-                c = 1.0;
-                sn = mk(0.0, 0.0);
-            } else if (x2 == 0.0) {
-                const double iy = 1.0 / sqrt(y2);
-                c = 0.0;
-                sn = mk(y.re * iy, -y.im * iy);
-            } else {
-                // c = |x| / r, s = x conj(y) / (|x| r), with one reciprocal
-                const double ax = sqrt(x2), rr = sqrt(x2 + y2);
-                const double inv = 1.0 / (ax * rr);
-                c = ax * ax * inv;
-                sn = inv * (x * cconj(y));
+            givens(x, y, c, sn);
+            // row pass: R(k, j) for j >= k; rows k+1 carried
+            zd rkk = mk(0.0, 0.0), rkk1 = mk(0.0, 0.0);
+#pragma unroll
+            for (int q2 = 0; q2 < MAXC; ++q2) {
+                const int j = lane + 64 * q2;
+                if (j >= k && j <= hi) {
+                    const zd u = cur[q2], v = nxt[q2];
+                    const zd nr = c * u + sn * v;
+                    a.set(k, j, nr);
+                    if (j == k) rkk = nr;
+                    if (j == k + 1) rkk1 = nr;
+                    cur[q2] = j == k ? mk(0.0, 0.0) : c * v - cconj(sn) * u;
+                    if (j > k && k + 2 <= hi) nxt[q2] = ld_shift(a, k + 2, j, sigma);
+                }
             }
-            for (int j = k + tid; j <= hi; j += nt) {
-                const zd u = ld(&a(k, j), 0), v = ld(&a(k + 1, j), 0);
-                st(&a(k, j), 0, c * u + sn * v);
-                st(&a(k + 1, j), 0, c * v - cconj(sn) * u);
+            const zd Rkk = rdlane(rkk, lk);
+            const zd Rkk1 = rdlane(rkk1, (k + 1) & 63);
+            // column pass, one step behind: G_{k-1}^H on columns k-1, k, rows l..k
+#pragma unroll
+            for (int r2 = 0; r2 < MAXC; ++r2) {
+                const int i = l + lane + 64 * r2;
+                if (k > l && i <= k) {
+                    const zd u = i == k ? mk(0.0, 0.0) : col[r2];   // a(k, k-1) = 0 in R
+                    const zd v = i == k ? Rkk : vk[r2];
+                    zd o = cp * u + cconj(sp) * v;
+                    if (i == k - 1) o = o + sigma;
+                    a.set(i, k - 1, o);
+                    col[r2] = cp * v - sp * u;
+                } else if (k == l && i == l) {
+                    col[r2] = Rkk;
+                }
+                // R(i, k+1) for the next step: stored by an earlier step, or broadcast
+                if (i < k && k + 1 <= hi) vk[r2] = a.get(i, k + 1);
+                if (i == k) vk[r2] = Rkk1;
             }
-            if (tid == 0) {
-                cs[k - l] = make_double2(c, 0.0);
-                cs[n + k - l] = make_double2(sn.re, sn.im);
-            }
-            __syncthreads();
+            cp = c;
+            sp = sn;
         }
-        for (int k = l; k < hi; ++k) {
-            const double c = cs[k - l].x;
-            const zd sn = mk(cs[n + k - l].x, cs[n + k - l].y);
-            for (int i = l + tid; i <= k + 1; i += nt) {
-                const zd u = ld(&a(i, k), 0), v = ld(&a(i, k + 1), 0);
-                st(&a(i, k), 0, c * u + cconj(sn) * v);
-                st(&a(i, k + 1), 0, c * v - sn * u);
+        // last row of R, then G_{hi-1}^H on columns hi-1, hi
+        zd rhh = mk(0.0, 0.0);
+#pragma unroll
+        for (int q2 = 0; q2 < MAXC; ++q2)
+            if (lane + 64 * q2 == hi) rhh = cur[q2];
+        const zd Rhh = rdlane(rhh, hi & 63);
+#pragma unroll
+        for (int r2 = 0; r2 < MAXC; ++r2) {
+            const int i = l + lane + 64 * r2;
+            if (i <= hi) {
+                const zd u = i == hi ? mk(0.0, 0.0) : col[r2];
+                const zd v = i == hi ? Rhh : vk[r2];
+                zd o1 = cp * u + cconj(sp) * v, o2 = cp * v - sp * u;
+                if (i == hi - 1) o1 = o1 + sigma;
+                if (i == hi) o2 = o2 + sigma;
+                a.set(i, hi - 1, o1);
+                a.set(i, hi, o2);
             }
-            __syncthreads();
         }
-        for (int i = l + tid; i <= hi; i += nt) st(&a(i, i), 0, ld(&a(i, i), 0) + sigma);
     }
     __syncthreads();
     return status;
@@ -237,8 +372,9 @@ __device__ void leja_order(double2 *ev, int n, double2 *tmp, double *S, int *tak
 // rotation gives the least-squares residual |g_d|.  The eigenvalues of
 // H_d + |h_{d+1,d}|^2 f e_d^T are found in LDS (packed) when it fits.
 // work (global): >= 2*d*d + 8*d + 16 complex doubles.
+template <int use_lds>
 __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh, int d, double beta,
-                                                      double2 *work, double2 *roots, double *info, int use_lds) {
+                                                      double2 *work, double2 *roots, double *info) {
     extern __shared__ double2 lds_mat[];
     const int tid = threadIdx.x, nt = blockDim.x;
     double2 *A = work;                 // d x d (global path)
@@ -294,7 +430,7 @@ __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh,
     const double h2 = h.re * h.re + h.im * h.im;
     const bool corr = h2 > 0.0 && s_status == 0;
     int rc;
-    if (use_lds) {
+    if constexpr (use_lds != 0) {
         PackedMat M{lds_mat};
         for (int j = 0; j < d; ++j)
             for (int i = tid; i <= (j + 1 < d ? j + 1 : d - 1); i += nt) {
@@ -303,7 +439,7 @@ __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh,
                 st(&M(i, j), 0, v);
             }
         __syncthreads();
-        rc = hess_eigvals(M, d, roots, lds_mat + packed_hess_size(d));
+        rc = hess_eigvals<3>(M, d, roots, lds_mat + packed_hess_size(d));
     } else {
         GlobalMat M{A, d};
         for (long e = tid; e < (long)d * d; e += nt) {
@@ -313,7 +449,7 @@ __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh,
             st(A, e, v);
         }
         __syncthreads();
-        rc = hess_eigvals(M, d, roots, rot);   // rot/rs (2d entries) are free again
+        rc = hess_eigvals<8>(M, d, roots, rot);   // rot/rs (2d entries) are free again
     }
     if (rc && tid == 0) s_status = -1;
     __syncthreads();
@@ -350,31 +486,36 @@ int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, doub
     double2 *work = (double2 *)ws_get(ctx, WS_DENSE, ((size_t)d * d + 8 * d + 16) * sizeof(double2));
     if (!work) return MPMC_ENOMEM;
     const size_t lb = (size_t)(packed_hess_size(d) + 2 * d) * sizeof(double2);
-    const bool lds = want_lds(ctx, k_harmonic_leja, lb);
-    k_harmonic_leja<<<1, 64, lds ? lb : 0, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
-                                                          (double2 *)roots_dev, info_dev, lds ? 1 : 0);
+    const bool lds = d <= 192 && want_lds(ctx, k_harmonic_leja<1>, lb);   // LDS path: <= 3 columns per lane
+    if (lds)
+        k_harmonic_leja<1><<<1, 64, lb, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
+                                                       (double2 *)roots_dev, info_dev);
+    else
+        k_harmonic_leja<0><<<1, 64, 0, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
+                                                      (double2 *)roots_dev, info_dev);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
 
 // ------------------------------------------------- eigenvalues of H_m --
+template <int use_lds>
 __global__ __launch_bounds__(64) void k_hess_eigs(const double2 *H, int ldh, int m, double2 *work, double2 *ev,
-                                                  double *info, int use_lds) {
+                                                  double *info) {
     extern __shared__ double2 lds_mat[];
     int rc;
-    if (use_lds) {
+    if constexpr (use_lds != 0) {
         PackedMat M{lds_mat};
         for (int j = 0; j < m; ++j)
             for (int i = threadIdx.x; i <= (j + 1 < m ? j + 1 : m - 1); i += blockDim.x) M(i, j) = H[i + (long)j * ldh];
         __syncthreads();
-        rc = hess_eigvals(M, m, ev, lds_mat + packed_hess_size(m));
+        rc = hess_eigvals<3>(M, m, ev, lds_mat + packed_hess_size(m));
     } else {
         for (long e = threadIdx.x; e < (long)m * m; e += blockDim.x) {
             const int i = (int)(e % m), j = (int)(e / m);
             work[e] = (i <= j + 1) ? H[i + (long)j * ldh] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        rc = hess_eigvals(GlobalMat{work, m}, m, ev, work + (size_t)m * m);
+        rc = hess_eigvals<8>(GlobalMat{work, m}, m, ev, work + (size_t)m * m);
     }
     if (threadIdx.x == 0) info[0] = rc;
 }
@@ -384,9 +525,11 @@ int dense_hess_eigs(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, double *
     double2 *work = (double2 *)ws_get(ctx, WS_DENSE, ((size_t)m * m + 2 * m) * sizeof(double2));
     if (!work) return MPMC_ENOMEM;
     const size_t lb = (size_t)(packed_hess_size(m) + 2 * m) * sizeof(double2);
-    const bool lds = want_lds(ctx, k_hess_eigs, lb);
-    k_hess_eigs<<<1, 64, lds ? lb : 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev,
-                                                      info_dev, lds ? 1 : 0);
+    const bool lds = m <= 192 && want_lds(ctx, k_hess_eigs<1>, lb);   // LDS path: <= 3 columns per lane
+    if (lds)
+        k_hess_eigs<1><<<1, 64, lb, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev, info_dev);
+    else
+        k_hess_eigs<0><<<1, 64, 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev, info_dev);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }

@@ -45,7 +45,7 @@ constexpr int NPARAM = 2304;
 constexpr int FIELDS[4] = {1, 2, 2, 1};
 constexpr int LAYER_OFF[4] = {0, 576, 1728, 2304};   // real parameters before layer l
 constexpr int TABLE_ELEMS = NPATH * 64 * 4;          // bf16 A-operand table of one layer op
-constexpr int WGRAD_WAVES = 1024;                    // wavefronts of the weight-gradient grid
+constexpr int WGRAD_BLOCKS = 1024;                   // blocks (4 wavefronts each) of the weight-gradient grid
 
 __device__ __forceinline__ short to_bf16(float f) {
     return __builtin_bit_cast(short, (__bf16)f);
@@ -214,13 +214,15 @@ __global__ __launch_bounds__(256) void k_net_layer(const float2 *__restrict__ in
 // Weight gradient of one layer: P_p[i][b] = sum_{x, rhs, c} g_i(x, rhs, c) t_{p,b}(x, rhs, c)
 // with i = 2o + ro over the output channels (g = dL/d out^*) and b = 2 ci + ri
 // over the path's transported input channels.  Each wavefront sums its units
-// (site, 16 rhs) in registers and writes partial[wave][p][lane*4 + r] =
-// P_p[4 (lane/16) + r][lane % 16].
+// (site, 16 rhs) in registers; the four wavefronts of a block are added in LDS
+// and the block writes partial[block][p][lane*4 + r] = P_p[4 (lane/16) + r][lane % 16].
 template <int FIN, int FOUT>
 __global__ __launch_bounds__(256) void k_net_wgrad(const float2 *__restrict__ a_in, const float2 *__restrict__ gout,
                                                    const float2 *__restrict__ links, const int *__restrict__ nbr,
                                                    float *__restrict__ partial, int N, int nrb, unsigned nunits) {
-    __shared__ short lds[4][3][16][16];   // [wave][colour][b][rhs]
+    // transposition buffer [wave][colour][b][rhs] (bf16), reused for the block sum
+    __shared__ float red[4][NPATH * 256];
+    short(*lds)[3][16][16] = reinterpret_cast<short(*)[3][16][16]>(&red[0][0]);
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const unsigned wave = blockIdx.x * 4u + wv;
@@ -292,15 +294,18 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const float2 *__restrict__ a_
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
-    float *dst = partial + (size_t)wave * NPATH * 256;
+    __syncthreads();   // all transpositions done before the buffer is reused
 #pragma unroll
     for (int p = 0; p < NPATH; ++p)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) dst[p * 256 + lane * 4 + r] = acc[p][r];
+        for (int r = 0; r < 4; ++r) red[wv][p * 256 + lane * 4 + r] = acc[p][r];
+    __syncthreads();
+    float *dst = partial + (size_t)blockIdx.x * NPATH * 256;
+    for (int e = threadIdx.x; e < NPATH * 256; e += 256) dst[e] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
-// Sum the per-wave partials in a fixed order: block (p, chunk) of 256
-// threads owns 64 entries of P_p; thread slice q < 4 adds waves w = q mod 4,
+// Sum the per-block partials in a fixed order: block (p, chunk) of 256
+// threads owns 64 entries of P_p; thread slice q < 4 adds parts w = q mod 4,
 // then the four slices are combined in order.  psum[p*256 + e] (FP64).
 __global__ __launch_bounds__(256) void k_net_wgrad_sum(const float *__restrict__ partial, int nwaves,
                                                        double *__restrict__ psum) {
@@ -356,11 +361,19 @@ __global__ __launch_bounds__(256) void k_net_loss(const float2 *__restrict__ out
     if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
 }
 
-__global__ void k_sum_fixed(const double *__restrict__ part, int n, double *__restrict__ out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Deterministic sum of n partials: 256 threads add strided subsets in a fixed
+// order, then a fixed tree.
+__global__ __launch_bounds__(256) void k_sum_fixed(const double *__restrict__ part, int n, double *__restrict__ out) {
+    __shared__ double red[256];
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    *out = s;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
 }
 
 // Adam (Kingma & Ba, 2015) on the FP32 master weights.
@@ -430,7 +443,7 @@ int launch_wgrad(mpmc_ctx *ctx, mpmc_net *net, int layer, const void *a_in, cons
     const int fin = FIELDS[layer], fout = FIELDS[layer + 1];
     const int nrb = (N + 15) / 16;
     const long units = ctx->V * nrb;
-    const unsigned blocks = (unsigned)std::min<long>(WGRAD_WAVES / 4, (units + 3) / 4);
+    const unsigned blocks = (unsigned)std::min<long>(WGRAD_BLOCKS, (units + 3) / 4);
     const float2 *L = reinterpret_cast<const float2 *>(ctx->links32);
     const float2 *a = (const float2 *)a_in;
     const float2 *gg = (const float2 *)gout;
@@ -444,7 +457,7 @@ int launch_wgrad(mpmc_ctx *ctx, mpmc_net *net, int layer, const void *a_in, cons
     return set_err(ctx, MPMC_EINVAL, "network: bad layer shape");
 #undef WG
     HIP_OR_RET(ctx, hipGetLastError());
-    k_net_wgrad_sum<<<NPATH * 4, 256, 0, ctx->stream>>>(partial, (int)blocks * 4, psum);
+    k_net_wgrad_sum<<<NPATH * 4, 256, 0, ctx->stream>>>(partial, (int)blocks, psum);
     HIP_OR_RET(ctx, hipGetLastError());
     const int npar = LAYER_OFF[layer + 1] - LAYER_OFF[layer];
     k_net_wgrad_map<<<grid_for(npar, 64), 64, 0, ctx->stream>>>(psum, layer, net->grad);
@@ -468,7 +481,7 @@ int net_loss_grad(mpmc_net *net, const void *R, const void *E, int P) {
     const unsigned lblocks = grid_for(total, 256);
     double *en2 = (double *)S.get(sizeof(double2) * P);
     double *lpart = (double *)S.get(sizeof(double) * lblocks);
-    float *partial = (float *)S.get(sizeof(float) * (size_t)WGRAD_WAVES * NPATH * 256);
+    float *partial = (float *)S.get(sizeof(float) * (size_t)WGRAD_BLOCKS * NPATH * 256);
     double *psum = (double *)S.get(sizeof(double) * NPATH * 256);
     if (!a1 || !a2 || !a3 || !g3 || !g2 || !g1 || !en2 || !lpart || !partial || !psum) return MPMC_ENOMEM;
     RET_IF(launch_layer(ctx, net, 0, R, a1, P));
@@ -478,7 +491,7 @@ int net_loss_grad(mpmc_net *net, const void *R, const void *E, int P) {
     k_net_loss<<<lblocks, 256, 0, ctx->stream>>>((const float2 *)a3, (const float2 *)E, (const double2 *)en2, total,
                                                  P, 1.0 / P, (float2 *)g3, lpart);
     HIP_OR_RET(ctx, hipGetLastError());
-    k_sum_fixed<<<1, 64, 0, ctx->stream>>>(lpart, (int)lblocks, net->loss);
+    k_sum_fixed<<<1, 256, 0, ctx->stream>>>(lpart, (int)lblocks, net->loss);
     HIP_OR_RET(ctx, hipGetLastError());
     RET_IF(launch_wgrad(ctx, net, 2, a2, g3, P, partial, psum));
     RET_IF(launch_layer(ctx, net, 5, g3, g2, P));

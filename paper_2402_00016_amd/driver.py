@@ -20,6 +20,7 @@ main solves (flexible GMRES).  The solves still stop on the same FP64 true
 residual, so the estimate does not depend on N.
 """
 import math
+import threading
 import time
 from dataclasses import dataclass, field
 from typing import List, Optional
@@ -43,8 +44,8 @@ class Plan:
     seed: int = 1
     nev: int = 20                        # eigenpairs kept for deflation (0: none)
     defl_candidates: int = 40            # Ritz pairs tested for acceptance
-    defl_m: int = 136                    # PP-Arnoldi steps (the Hessenberg QR stays in LDS up to 137)
-    defl_pin_degree: int = 32            # degree of p_in for PP-Arnoldi
+    defl_m: int = 112                    # PP-Arnoldi steps (the Hessenberg QR stays in LDS up to 137)
+    defl_pin_degree: int = 8             # degree of p_in for PP-Arnoldi
     accept_tol: float = 1e-3
     real_tol: float = 2e-4
     poly_prec: int = mpmc.FP32           # precision of the polynomial levels
@@ -59,6 +60,7 @@ class Plan:
     net_steps: int = 10                  # Adam steps per minibatch
     net_lr: float = 1e-2
     net_seed0: int = 100
+    overlap_setup: bool = True           # build polynomials (and train the net) on side streams
 
 
 @dataclass
@@ -161,6 +163,69 @@ def train_net(ctx, plan: Plan):
     return net, np.array(hist)
 
 
+def rehome_poly(ctx, p, cache=None):
+    """The same polynomial (roots, inner polynomial) as a handle of ctx."""
+    cache = {} if cache is None else cache
+    if id(p) not in cache:
+        inner = rehome_poly(ctx, p.inner, cache) if p.inner is not None else None
+        q = ctx.poly_from_roots(p.roots, inner=inner)
+        q.d_eff, q.relres = p.d_eff, p.relres
+        cache[id(p)] = q
+    return cache[id(p)]
+
+
+class _SideJob:
+    """fn(side_context, *args) run by a host thread on a side context and its
+    own stream; the library calls release the interpreter lock, so the GPU
+    work of both threads overlaps."""
+
+    def __init__(self, ctx, name, fn, *args):
+        self.side, self.stream = ctx.side(name)
+        self.result, self.error = None, None
+        self.thread = threading.Thread(target=self._run, args=(fn, args), daemon=True)
+        self.thread.start()
+
+    def _run(self, fn, args):
+        try:
+            with self.side.torch.cuda.stream(self.stream):
+                self.result = fn(self.side, *args)
+                self.stream.synchronize()
+        except BaseException as e:   # re-raised in join()
+            self.error = e
+
+    def join(self):
+        self.thread.join()
+        if self.error is not None:
+            raise self.error
+        return self.result
+
+
+def total_mvps(ctx):
+    """Operator applications issued by ctx and its side contexts."""
+    return ctx.mvps + sum(c.mvps for c, _ in ctx._side.values())
+
+
+def build_setup(ctx, plan: Plan, train=False):
+    """Deflation set, polynomials and (optionally) the trained network.  With
+    plan.overlap_setup the polynomials and the training run on side streams
+    while the deflation set is built on ctx's stream."""
+    if not plan.overlap_setup:
+        defl = build_deflation(ctx, plan)
+        polys = build_polys(ctx, plan)
+        net, hist = train_net(ctx, plan) if train else (None, None)
+        return defl, polys, net, hist
+    jp = _SideJob(ctx, "polys", build_polys, plan)
+    jn = _SideJob(ctx, "net", train_net, plan) if train else None
+    defl = build_deflation(ctx, plan)
+    cache = {}
+    polys = [rehome_poly(ctx, p, cache) for p in jp.join()]
+    net, hist = None, None
+    if jn is not None:
+        snet, hist = jn.join()
+        net = ctx.net(snet.weights)
+    return defl, polys, net, hist
+
+
 def combine(levels):
     est = sum((L.mean + L.corr for L in levels), 0j)
     var = sum(L.var / L.n for L in levels)
@@ -188,24 +253,20 @@ def estimate(ctx, plan: Plan, sync=None, net=None) -> Estimate:
     """Full estimate: polynomials, deflation, (network training when the plan
     is learned and no trained net is given), all levels (fixed noise counts)."""
     sync = sync or (lambda: None)
-    mv0 = ctx.mvps
+    mv0 = total_mvps(ctx)
     t0 = time.perf_counter()
-    defl = build_deflation(ctx, plan)
-    polys = build_polys(ctx, plan)
+    defl, polys, tnet, hist = build_setup(ctx, plan, train=plan.learned and net is None)
     info = {}
-    if plan.learned and net is None:
-        sync()
-        tn = time.perf_counter()
-        net, hist = train_net(ctx, plan)
-        sync()
-        info = dict(net_train_seconds=time.perf_counter() - tn, net_loss=[float(hist[0]), float(hist[-1])])
+    if tnet is not None:
+        net = tnet
+        info = dict(net_loss=[float(hist[0]), float(hist[-1])])
     sync()
     t1 = time.perf_counter()
     levels = run_levels(ctx, plan, polys, defl, net=net if plan.learned else None)
     sync()
     t2 = time.perf_counter()
     est, se = combine(levels)
-    return Estimate(est, se, levels, t1 - t0, t2 - t0, ctx.mvps - mv0, polys=polys,
+    return Estimate(est, se, levels, t1 - t0, t2 - t0, total_mvps(ctx) - mv0, polys=polys,
                     defl_k=defl.k if defl is not None else 0, info=info)
 
 
@@ -213,10 +274,10 @@ def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_e
     """Adaptive stopping (Sec. 8): each Monte Carlo term stops once its standard
     error is below eps / sqrt(#terms), with minimum counts 2 (solve term),
     3 (first difference), 6 (later terms) and checks every `check_every` noises."""
-    mv0 = ctx.mvps
+    mv0 = total_mvps(ctx)
     t0 = time.perf_counter()
-    defl = build_deflation(ctx, plan)
-    polys = build_polys(ctx, plan)
+    defl, polys, tnet, _ = build_setup(ctx, plan, train=plan.learned and net is None)
+    net = tnet if tnet is not None else net
     t_setup = time.perf_counter() - t0
     nterms = len(polys) + 1
     target = eps / math.sqrt(nterms)
@@ -243,5 +304,5 @@ def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_e
                 break
         levels.append(LevelResult("term %d" % l, X, corr, mv, secs))
     est, se = combine(levels)
-    return Estimate(est, se, levels, t_setup, time.perf_counter() - t0, ctx.mvps - mv0, polys=polys,
+    return Estimate(est, se, levels, t_setup, time.perf_counter() - t0, total_mvps(ctx) - mv0, polys=polys,
                     defl_k=defl.k if defl is not None else 0)

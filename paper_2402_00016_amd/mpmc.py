@@ -407,9 +407,24 @@ class Context:
         self.V = int(np.prod(self.dims))
         self.n = 12 * self.V
         self.kappa = float(kappa)
+        self.links = links
+        self.t_antiperiodic = bool(t_antiperiodic)
+        self.stream = stream
         self.handle = mpmc_create(self.dims, kappa, t_antiperiodic, links, ctypes.c_void_p(stream))
+        self._side = {}
+
+    def side(self, name):
+        """A second context on the same lattice with its own HIP stream (default
+        priority), for independent work that can overlap with this context's.
+        Returns (context, torch stream); cached per name."""
+        if name not in self._side:
+            st = self.torch.cuda.Stream()
+            self._side[name] = (Context(self.dims, self.kappa, self.links, self.t_antiperiodic, st.cuda_stream), st)
+        return self._side[name]
 
     def close(self):
+        for c, _ in getattr(self, "_side", {}).values():
+            c.close()
         if getattr(self, "handle", None) is not None and self.handle.value:
             mpmc_destroy(self.handle)
         self.handle = None

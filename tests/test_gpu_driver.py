@@ -1,0 +1,48 @@
+"""GPU: the host driver's estimate is the same whether the setup runs on one
+stream or overlapped on side streams (same kernels, same inputs), and the
+learned form gives the same estimate as the plain form to solver accuracy."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2402_00016_amd import driver, inputs, mpmc  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    dims, kappa = (4, 4, 4, 4), 0.115
+    return mpmc.Context(dims, kappa, inputs.gauge_links(dims, 0.5, seed=1))
+
+
+def plan(**kw):
+    base = dict(degrees=[24, 8], noises=16, seed=3, nev=6, defl_candidates=12, defl_m=48, defl_pin_degree=4,
+                solve_tol=1e-10)
+    base.update(kw)
+    return driver.Plan(**base)
+
+
+def test_overlapped_setup_is_identical(ctx):
+    e0 = driver.estimate(ctx, plan(overlap_setup=False), torch.cuda.synchronize)
+    e1 = driver.estimate(ctx, plan(overlap_setup=True), torch.cuda.synchronize)
+    for a, b in zip(e0.polys, e1.polys):
+        assert np.array_equal(a.roots, b.roots)
+    assert e0.defl_k == e1.defl_k
+    for L0, L1 in zip(e0.levels, e1.levels):
+        assert np.allclose(L0.samples, L1.samples, rtol=0, atol=1e-9)
+    assert e0.mvps == e1.mvps
+
+
+def test_learned_form_same_estimate(ctx):
+    p = plan(solve_inner_prec=mpmc.FP32)
+    e0 = driver.estimate(ctx, p, torch.cuda.synchronize)
+    e1 = driver.estimate(ctx, plan(solve_inner_prec=mpmc.FP32, learned=True, net_batches=2, net_pairs=16,
+                                   net_steps=10), torch.cuda.synchronize)
+    assert "net_loss" in e1.info and e1.info["net_loss"][1] < e1.info["net_loss"][0]
+    # same noise, solves to 1e-10: the solve-term samples agree to ~1e-10 n
+    assert np.max(np.abs(e1.levels[0].samples - e0.levels[0].samples)) < 1e-7
+    assert abs(e1.value - e0.value) < 1e-6

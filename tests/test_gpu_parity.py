@@ -159,6 +159,18 @@ def test_gmres_poly_roots_parity(f44, d):
     assert abs(P.relres - rr) < 1e-9 * max(rr, 1e-12) + 1e-13
 
 
+def test_gmres_poly_roots_parity_high_degree():
+    """degree 47 on a slowly converging operator (kappa 0.2): many QR sweeps"""
+    dims, kappa = (4, 4, 4, 4), 0.2
+    U = inputs.gauge_links(dims, 0.5, seed=21)
+    op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    P = ctx.gmres_poly(1, 0x100, 48)
+    ref, de, rr = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 48)
+    assert P.d_eff == de == 48
+    assert _match_sets(P.roots, ref.roots) < 1e-8 * np.max(np.abs(ref.roots))
+    assert abs(P.relres - rr) < 1e-8 * rr
+
+
 def test_gmres_poly_breakdown_kappa0():
     dims = (2, 2, 2, 2)
     ctx = mpmc.Context(dims, 0.0, inputs.gauge_links(dims, 0.5, seed=1))
@@ -218,14 +230,15 @@ def test_double_poly_parity(f44):
 
 # -------------------------------------------------------------- deflation --
 
-def test_deflate_parity():
+@pytest.mark.parametrize("m", [80, 150])    # 150: the Hessenberg QR runs from global memory
+def test_deflate_parity(m):
     dims, kappa = (4, 4, 4, 4), 0.2
     U = inputs.gauge_links(dims, 0.5, seed=21)
     op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
     Pin_ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 4)
     Pin = ctx.poly_from_roots(Pin_ref.roots)
-    D = ctx.deflate(Pin, 1, 0x200, m=80, nev=10)
-    Dref, info = ODF.pp_arnoldi_eigs(op, Pin_ref.roots, z4_noise(1, 0x200, 0, op.n), 80, 10)
+    D = ctx.deflate(Pin, 1, 0x200, m=m, nev=10)
+    Dref, info = ODF.pp_arnoldi_eigs(op, Pin_ref.roots, z4_noise(1, 0x200, 0, op.n), m, 10)
     assert D.k >= 1 and abs(D.k - Dref.k) <= 2
     lam, Z, Uv = ctx.defl_vectors(D)
     assert _match_sets(lam, Dref.lam) < 1e-7
