@@ -231,6 +231,29 @@ int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl 
                const mpmc_net *net, int restart, double tol, int inner_prec,
                int max_outer, int *iters_host, double *relres_host);
 
+/* ---------------------------------------------------------------- autotuner */
+/* The multi-RHS Wilson kernel (nrhs a multiple of 64) has WILSON variants
+ * 0..3 that differ only in how the work is laid out on the GPU, never in the
+ * arithmetic (results are bit-identical):
+ *   bit 0 -- occupancy target: 1 = more wavefronts per SIMD (FP32/FP16S: 3,
+ *            FP64: register-bound), 0 = more registers per wavefront (2);
+ *   bit 1 -- traversal: 0 = site-major (a workgroup covers 256/nrhs sites x
+ *            nrhs right-hand sides), 1 = 64-wide right-hand-side chunks (a
+ *            workgroup covers 4 sites x 64 right-hand sides; all sites of a
+ *            chunk before the next chunk).
+ * Defaults: variant 1 for FP32/FP16S, 0 for FP64.
+ * mpmc_autotune times every variant on (nrhs, prec) with scratch vectors of
+ * the context (2 warm-up + 5 timed launches each, HIP events) and keeps the
+ * fastest for all later Wilson launches on ctx with that (nrhs, prec),
+ * including those inside polynomials, solves and level estimates.
+ * variant_host (may be NULL) receives the choice (-1 when nrhs is not a
+ * multiple of 64: nothing to tune); us_host (may be NULL) receives
+ * double[4] microseconds per launch per variant.  Does not count MVPs and
+ * does not enter mpmc_timing_read.  Synchronises. */
+int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host, double *us_host);
+/* Pin variant (0..3) for (nrhs, prec); -1 restores the default. */
+int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant);
+
 /* ------------------------------------------------- learned preconditioner */
 /* Not part of the paper: a small learned right preconditioner N for the main
  * solves (used by mpmc_solve / mpmc_level_estimate through their net

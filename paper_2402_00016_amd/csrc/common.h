@@ -7,7 +7,9 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mpmc.h"
@@ -47,6 +49,8 @@ struct mpmc_ctx {
         double bytes;
     };
     std::vector<TimedLaunch> timed;
+    // Wilson kernel variant per (nrhs, prec), set by mpmc_autotune / mpmc_tune_set
+    std::map<std::pair<int, int>, int> tune;
 };
 
 struct mpmc_poly {

@@ -356,16 +356,27 @@ __device__ __forceinline__ void hopping(const WIn<P> &in, long s, int r, int N, 
 // (site, rhs) of this thread.  UNI (N % 64 == 0): each wavefront covers 64
 // consecutive right-hand sides of one site, so the site follows from the
 // wavefront's first thread with scalar arithmetic.
-template <bool UNI>
+template <bool UNI, int ORDER = 0>
 __device__ __forceinline__ bool locate(long V, int N, long &s, int &r) {
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     const unsigned total = (unsigned)(V * N);
     if constexpr (UNI) {
         const unsigned w0 = tile * 256u + ((unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
         if (w0 >= total) return false;
-        const unsigned ss = w0 / (unsigned)N;
-        s = (long)ss;
-        r = (int)(w0 - ss * (unsigned)N + (threadIdx.x & 63u));
+        if constexpr (ORDER == 0) {
+            // site-major: a block holds 256/N sites x N right-hand sides
+            const unsigned ss = w0 / (unsigned)N;
+            s = (long)ss;
+            r = (int)(w0 - ss * (unsigned)N + (threadIdx.x & 63u));
+        } else {
+            // chunk-major: all sites for right-hand sides [64c, 64c + 64) before
+            // chunk c + 1; a block holds 4 sites x 64 right-hand sides, so the
+            // working set of a sweep is 64 right-hand sides wide
+            const unsigned wv = w0 >> 6, Vu = (unsigned)V;
+            const unsigned ch = wv / Vu, ss = wv - ch * Vu;
+            s = (long)ss;
+            r = (int)(ch * 64u + (threadIdx.x & 63u));
+        }
     } else {
         const unsigned t = tile * 256u + threadIdx.x;
         if (t >= total) return false;
@@ -389,15 +400,22 @@ struct WOut {
     int a_is_b;
 };
 
-// Occupancy targets: FP32/FP16S kernels fit 4 wavefronts per SIMD (<= 128
-// VGPRs), FP64 kernels 2 (<= 256 VGPRs), without scratch spills.
-template <int P, bool UNI>
+// Occupancy targets (minimum wavefronts per SIMD the register allocation must
+// allow).  The uniform kernels come in two targets chosen by the autotuner:
+// HI = 1 is the default (FP32/FP16S: 3 wavefronts, <= 168 VGPRs; FP64: no
+// target), HI = 0 trades occupancy for registers (FP32/FP16S: 2; FP64: 2).
+template <int P, bool UNI, int HI = 1>
 struct Occ {
-    static constexpr int wpe = (UNI && P != MPMC_FP64) ? 3 : 1;
+    static constexpr int wpe = !UNI ? 1 : (P == MPMC_FP64 ? (HI ? 1 : 2) : (HI ? 3 : 2));
 };
 
-template <int P, bool UNI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI>::wpe))) void k_wilson(const void *__restrict__ b, const float *__restrict__ bsc,
+// Kernel variants of the autotuner: bit 0 selects the occupancy target
+// (Occ::HI), bit 1 the traversal order of locate().
+constexpr int WILSON_VARIANTS = 4;
+static inline int default_variant(int prec) { return prec == MPMC_FP64 ? 0 : 1; }
+
+template <int P, bool UNI, int HI = 1, int ORDER = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI, HI>::wpe))) void k_wilson(const void *__restrict__ b, const float *__restrict__ bsc,
                                                 const int *__restrict__ nbr,
                                                 const typename LinkT<P>::type *__restrict__ links, WOut o, long V,
                                                 int N) {
@@ -405,7 +423,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI>
     const WIn<P> in{b, bsc, nbr, links};
     long s;
     int r;
-    if (!locate<UNI>(V, N, s, r)) return;
+    if (!locate<UNI, ORDER>(V, N, s, r)) return;
     cpx<T> acc[4][3];
     hopping<P, UNI>(in, s, r, N, o.g, acc);
     const T kap = (T)o.kappa;
@@ -570,7 +588,7 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
 // A block of 256 threads covers spb = max(1, 256/N) sites and rpb = min(N, 256)
 // right-hand sides starting at rhs (blk*256) % N.
 template <int P>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, true>::wpe))) void k_wilson_dot(const void *__restrict__ b, const int *__restrict__ nbr,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_FP64 ? 1 : 2))) void k_wilson_dot(const void *__restrict__ b, const int *__restrict__ nbr,
                                                     const typename LinkT<P>::type *__restrict__ links,
                                                     void *__restrict__ out, const uint32_t *__restrict__ codes,
                                                     double2 c, double2 cnext, double kappa, int theta,
@@ -687,6 +705,18 @@ static WIn<P> make_in(const mpmc_ctx *ctx, const void *b, int nrhs) {
     return in;
 }
 
+// Kernel variant for (nrhs, prec): pinned or tuned by the autotuner, else the default.
+static int wilson_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
+    const auto it = ctx->tune.find(std::make_pair(nrhs, prec));
+    return it == ctx->tune.end() ? default_variant(prec) : it->second;
+}
+
+template <int P, int V_>
+static void launch_uniform(mpmc_ctx *ctx, const WIn<P> &in, const WOut &o, int nrhs, unsigned grid) {
+    k_wilson<P, true, V_ & 1, (V_ >> 1) & 1><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V,
+                                                                          nrhs);
+}
+
 template <int P>
 static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs) {
     const long work = ctx->V * nrhs;
@@ -698,10 +728,16 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs) {
             return;
         }
     }
-    if (nrhs % 64 == 0)
-        k_wilson<P, true><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs);
-    else
+    if (nrhs % 64 == 0) {
+        switch (wilson_variant(ctx, nrhs, P)) {
+        case 0: launch_uniform<P, 0>(ctx, in, o, nrhs, grid); break;
+        case 1: launch_uniform<P, 1>(ctx, in, o, nrhs, grid); break;
+        case 2: launch_uniform<P, 2>(ctx, in, o, nrhs, grid); break;
+        default: launch_uniform<P, 3>(ctx, in, o, nrhs, grid); break;
+        }
+    } else {
         k_wilson<P, false><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs);
+    }
 }
 
 int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, void *y, int nrhs, int prec,
@@ -798,4 +834,72 @@ MPMC_API int mpmc_apply_M(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int p
     if (x == y) return set_err(ctx, MPMC_EINVAL, "mpmc_apply_M: x and y must not alias");
     return wilson_launch_full(ctx, x, nullptr, y, nullptr, nrhs, prec, make_double2(0, 0), make_double2(1, 0),
                               make_double2(0, 0), dagger ? 1 : 0, theta == MPMC_THETA_G5 ? 1 : 0);
+}
+
+// ------------------------------------------------------------ autotuner --
+
+MPMC_API int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant) {
+    if (!ctx) return MPMC_EINVAL;
+    if (nrhs < 1 || !prec_ok(prec) || variant < -1 || variant >= WILSON_VARIANTS)
+        return set_err(ctx, MPMC_EINVAL, "mpmc_tune_set: bad argument");
+    const auto key = std::make_pair(nrhs, prec);
+    if (variant < 0) ctx->tune.erase(key);
+    else ctx->tune[key] = variant;
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host, double *us_host) {
+    if (!ctx) return MPMC_EINVAL;
+    if (nrhs < 1 || !prec_ok(prec)) return set_err(ctx, MPMC_EINVAL, "mpmc_autotune: bad argument");
+    if (us_host)
+        for (int v = 0; v < WILSON_VARIANTS; ++v) us_host[v] = 0.0;
+    if (nrhs % 64 != 0 || ctx->V * (long)nrhs > 0x7fffff00L) {   // one kernel shape only
+        if (variant_host) *variant_host = -1;
+        return MPMC_OK;
+    }
+    Scratch S(ctx);
+    const size_t vb = vec_bytes(ctx, nrhs, prec);
+    void *x = S.get(vb), *y = S.get(vb);
+    if (!x || !y) return MPMC_ENOMEM;
+    RET_IF(launch_noise(ctx, 1, 0, 0, nrhs, prec, x));
+    hipEvent_t e0, e1;
+    HIP_OR_RET(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return set_err(ctx, MPMC_EHIP, "mpmc_autotune: event creation failed");
+    }
+    const int timing = ctx->timing;
+    const uint64_t mvps = ctx->mvps;
+    ctx->timing = 0;
+    const auto key = std::make_pair(nrhs, prec);
+    int best = default_variant(prec), rc = MPMC_OK;
+    double best_us = 1e300;
+    constexpr int warm = 2, reps = 5;
+    for (int v = 0; v < WILSON_VARIANTS && rc == MPMC_OK; ++v) {
+        ctx->tune[key] = v;
+        for (int i = 0; i < warm + reps && rc == MPMC_OK; ++i) {
+            if (i == warm && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = MPMC_EHIP;
+            if (rc == MPMC_OK)
+                rc = wilson_launch_full(ctx, x, nullptr, y, nullptr, nrhs, prec, make_double2(0, 0), make_double2(1, 0),
+                                        make_double2(0, 0), 0, 0);
+        }
+        float ms = 0.f;
+        if (rc == MPMC_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = set_err(ctx, MPMC_EHIP, "mpmc_autotune: timing failed");
+        const double us = 1e3 * ms / reps;
+        if (us_host) us_host[v] = us;
+        if (rc == MPMC_OK && us < best_us) {
+            best_us = us;
+            best = v;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->timing = timing;
+    ctx->mvps = mvps;
+    ctx->tune[key] = best;
+    if (rc != MPMC_OK) return rc;
+    if (variant_host) *variant_host = best;
+    return MPMC_OK;
 }

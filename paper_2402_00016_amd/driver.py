@@ -61,6 +61,7 @@ class Plan:
     net_lr: float = 1e-2
     net_seed0: int = 100
     overlap_setup: bool = True           # build polynomials (and train the net) on side streams
+    autotune: bool = True                # time the Wilson kernel variants for the level batches once per context
 
 
 @dataclass
@@ -200,6 +201,20 @@ class _SideJob:
         return self.result
 
 
+def autotune_levels(ctx, plan: Plan):
+    """Autotune the Wilson kernel for the batch shapes of the levels (once per
+    context and shape): the polynomial levels in plan.poly_prec, the solve
+    level's inner precision and its FP64 residuals."""
+    if not plan.autotune:
+        return
+    done = ctx.__dict__.setdefault("_tuned", set())
+    nb = plan.max_batch if plan.max_batch else plan.noises
+    for prec in {plan.poly_prec, plan.solve_inner_prec, mpmc.FP64}:
+        if (nb, prec) not in done:
+            ctx.autotune(nb, prec)
+            done.add((nb, prec))
+
+
 def total_mvps(ctx):
     """Operator applications issued by ctx and its side contexts."""
     return ctx.mvps + sum(c.mvps for c, _ in ctx._side.values())
@@ -209,6 +224,7 @@ def build_setup(ctx, plan: Plan, train=False):
     """Deflation set, polynomials and (optionally) the trained network.  With
     plan.overlap_setup the polynomials and the training run on side streams
     while the deflation set is built on ctx's stream."""
+    autotune_levels(ctx, plan)
     if not plan.overlap_setup:
         defl = build_deflation(ctx, plan)
         polys = build_polys(ctx, plan)

@@ -58,6 +58,8 @@ _SIGS = {
     "mpmc_defl_destroy": ([_vp], None),
     "mpmc_defl_keep": ([_vp, _i], _i),
     "mpmc_solve": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
+    "mpmc_autotune": ([_vp, _i, _i, _pi, _vp], _i),
+    "mpmc_tune_set": ([_vp, _i, _i, _i], _i),
     "mpmc_net_n_params": ([], _i),
     "mpmc_net_create": ([_vp, _vp, ctypes.POINTER(_vp)], _i),
     "mpmc_net_destroy": ([_vp], None),
@@ -261,6 +263,17 @@ def mpmc_level_estimate(ctx, upper, lower, defl, theta, seed, stream, first, nno
                                   int(solve_restart), int(solve_inner_prec), _h(net), samples.ctypes.data,
                                   corr.ctypes.data, ctypes.byref(mvps)), ctx)
     return samples, complex(corr[0]), mvps.value
+
+
+def mpmc_autotune(ctx, nrhs, prec):
+    v = ctypes.c_int()
+    us = np.zeros(4)
+    _check(_L.mpmc_autotune(ctx, int(nrhs), int(prec), ctypes.byref(v), us.ctypes.data), ctx)
+    return v.value, us
+
+
+def mpmc_tune_set(ctx, nrhs, prec, variant):
+    _check(_L.mpmc_tune_set(ctx, int(nrhs), int(prec), int(variant)), ctx)
 
 
 def mpmc_net_n_params():
@@ -499,6 +512,13 @@ class Context:
         return lam, Z[:defl.k], U[:defl.k]
 
     # solves and levels
+    def autotune(self, nrhs, prec=FP32):
+        """Pick the fastest Wilson kernel variant for (nrhs, prec) -> (variant, us per variant)."""
+        return mpmc_autotune(self.handle, nrhs, prec)
+
+    def tune_set(self, nrhs, prec, variant):
+        mpmc_tune_set(self.handle, nrhs, prec, variant)
+
     def net(self, theta):
         return Net(mpmc_net_create(self.handle, theta), self)
 

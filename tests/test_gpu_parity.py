@@ -401,3 +401,26 @@ def test_poly_trace_probing_exact(f44):
     # a too-coarse colouring is reported as inexact
     _, exact3, _ = ctx.poly_trace(g, period=(2, 2, 2, 2))
     assert not exact3
+
+
+# ------------------------------------------------------------- autotuner --
+
+@pytest.mark.parametrize("prec", [FP64, FP32, FP16S])
+def test_autotune_variants_bit_identical(f44, prec):
+    """every kernel variant (occupancy target, traversal order) gives the same
+    bits; the autotuner picks one of them and reports a time for each"""
+    dims, kappa, U, op, ctx = f44
+    N = 128
+    x = ctx.noise(4, 1, 0, N, prec)
+    outs = []
+    for v in range(4):
+        ctx.tune_set(N, prec, v)
+        outs.append(host(ctx.apply_M(x, N, prec)).copy())
+    ctx.tune_set(N, prec, -1)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    v, us = ctx.autotune(N, prec)
+    assert 0 <= v < 4 and np.all(us > 0) and us[v] == us.min()
+    assert np.array_equal(host(ctx.apply_M(x, N, prec)), outs[0])
+    ctx.tune_set(N, prec, -1)
+    assert ctx.autotune(20, prec)[0] == -1     # not a multiple of 64: nothing to tune
