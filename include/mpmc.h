@@ -111,7 +111,11 @@ int mpmc_mvp_reset(mpmc_ctx *ctx);
  * once and each output written once, plus the links once per site.
  * mpmc_timing_read synchronises and returns, for launches of precision prec
  * since the last enable, the count, the summed kernel time (ms) and the
- * summed algorithmic bytes; it leaves timing enabled. */
+ * summed algorithmic bytes; it leaves timing enabled.  prec may be or-ed with
+ * MPMC_TIMING_FUSED (only the fused level steps, k_wilson_dot) or
+ * MPMC_TIMING_PLAIN (only the other Wilson launches); without either flag
+ * both kinds are summed. */
+enum { MPMC_TIMING_PLAIN = 16, MPMC_TIMING_FUSED = 32 };
 int mpmc_timing_enable(mpmc_ctx *ctx, int on);
 int mpmc_timing_read(mpmc_ctx *ctx, int prec, uint64_t *launches_host, double *ms_host, double *bytes_host);
 
@@ -236,7 +240,8 @@ int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl 
  * 0..3 that differ only in how the work is laid out on the GPU, never in the
  * arithmetic (results are bit-identical):
  *   bit 0 -- occupancy target: 1 = more wavefronts per SIMD (FP32/FP16S: 3,
- *            FP64: register-bound), 0 = more registers per wavefront (2);
+ *            FP64: 2), 0 = more registers per wavefront (FP32/FP16S: 2,
+ *            FP64: 1);
  *   bit 1 -- traversal: 0 = site-major (a workgroup covers 256/nrhs sites x
  *            nrhs right-hand sides), 1 = 64-wide right-hand-side chunks (a
  *            workgroup covers 4 sites x 64 right-hand sides; all sites of a

@@ -357,7 +357,9 @@ MPMC_API int mpmc_timing_read(mpmc_ctx *ctx, int prec, uint64_t *launches, doubl
     uint64_t cnt = 0;
     double t = 0, b = 0;
     for (const auto &L : ctx->timed) {
-        if (L.prec != prec) continue;
+        // L.prec = precision | kind; prec selects a precision, optionally one kind
+        if ((L.prec & 15) != (prec & 15)) continue;
+        if ((prec & ~15) && !(L.prec & prec & ~15)) continue;
         float e = 0;
         HIP_OR_RET(ctx, hipEventElapsedTime(&e, ctx->ev_pool[L.ev0], ctx->ev_pool[L.ev1]));
         ++cnt;

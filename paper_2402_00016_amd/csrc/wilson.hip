@@ -278,10 +278,12 @@ __device__ __forceinline__ void apply(const HopData<P> &H, float g, cpx<typename
         h[0][c] = H.psi[0 * 3 + c] + sg * mulc<Pr::c0>(H.psi[Pr::j0 * 3 + c]);
         h[1][c] = H.psi[1 * 3 + c] + sg * mulc<Pr::c1>(H.psi[Pr::j1 * 3 + c]);
     }
+    // uh = U h (forward) or U^H h (backward); FP32/FP16S as explicit FMA
+    // chains (four per complex multiply-add)
     cpx<T> uh[2][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        cpx<T> t0 = mk(T(0), T(0)), t1 = mk(T(0), T(0));
+        cpx<T> t0, t1;
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb) {
             // forward: U[a][bb]; backward: conj(U[bb][a])
@@ -289,9 +291,22 @@ __device__ __forceinline__ void apply(const HopData<P> &H, float g, cpx<typename
             cpx<T> lv;
             if constexpr (UNI) lv = link_lane<P>(H.lw, li);
             else lv = H.u[li];
-            const cpx<T> u = FWD ? lv : cconj(lv);
-            t0 = t0 + u * h[0][bb];
-            t1 = t1 + u * h[1][bb];
+            const T ur = lv.re, ui = FWD ? lv.im : -lv.im;
+            if constexpr (P == MPMC_FP64) {   // FP64 keeps fewer live registers this way
+                const cpx<T> u = mk(ur, ui);
+                t0 = bb == 0 ? u * h[0][0] : t0 + u * h[0][bb];
+                t1 = bb == 0 ? u * h[1][0] : t1 + u * h[1][bb];
+                continue;
+            }
+            if (bb == 0) {
+                t0 = mk(ur * h[0][0].re, ur * h[0][0].im);
+                t1 = mk(ur * h[1][0].re, ur * h[1][0].im);
+            } else {
+                t0 = mk(fma(ur, h[0][bb].re, t0.re), fma(ur, h[0][bb].im, t0.im));
+                t1 = mk(fma(ur, h[1][bb].re, t1.re), fma(ur, h[1][bb].im, t1.im));
+            }
+            t0 = mk(fma(-ui, h[0][bb].im, t0.re), fma(ui, h[0][bb].re, t0.im));
+            t1 = mk(fma(-ui, h[1][bb].im, t1.re), fma(ui, h[1][bb].re, t1.im));
         }
         uh[0][a] = t0;
         uh[1][a] = t1;
@@ -402,11 +417,11 @@ struct WOut {
 
 // Occupancy targets (minimum wavefronts per SIMD the register allocation must
 // allow).  The uniform kernels come in two targets chosen by the autotuner:
-// HI = 1 is the default (FP32/FP16S: 3 wavefronts, <= 168 VGPRs; FP64: no
-// target), HI = 0 trades occupancy for registers (FP32/FP16S: 2; FP64: 2).
+// HI = 1 asks for more wavefronts (FP32/FP16S: 3, <= 168 VGPRs; FP64: 2),
+// HI = 0 for more registers (FP32/FP16S: 2; FP64: no target).
 template <int P, bool UNI, int HI = 1>
 struct Occ {
-    static constexpr int wpe = !UNI ? 1 : (P == MPMC_FP64 ? (HI ? 1 : 2) : (HI ? 3 : 2));
+    static constexpr int wpe = !UNI ? 1 : (P == MPMC_FP64 ? (HI ? 2 : 1) : (HI ? 3 : 2));
 };
 
 // Kernel variants of the autotuner: bit 0 selects the occupancy target
@@ -770,7 +785,7 @@ int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, v
         double per = 2 * sb;
         if (a && a != b) per += sb;
         if (y) per += 2 * sb;
-        timing_end(ctx, ev, prec, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
+        timing_end(ctx, ev, prec | MPMC_TIMING_PLAIN, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
     }
     ctx->mvps += (uint64_t)nrhs;
     return MPMC_OK;
@@ -813,7 +828,7 @@ int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *co
         // spinor read + write, 4-byte noise code, links once per site (the
         // partial sums add 16 B per 256 threads and are not counted)
         const double per = 2 * spinor_bytes(prec) + 4.0;
-        timing_end(ctx, ev, prec, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
+        timing_end(ctx, ev, prec | MPMC_TIMING_FUSED, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
     }
     ctx->mvps += (uint64_t)nrhs;
     return MPMC_OK;

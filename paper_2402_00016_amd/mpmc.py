@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("MPMC_LIB", os.path.join(HERE, "libmpmc.so"))
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32, FP16S = 0, 1, 2
 THETA_I, THETA_G5 = 0, 1
+TIMING_PLAIN, TIMING_FUSED = 16, 32     # or-ed into the precision of mpmc_timing_read
 PREC = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 THETA = {"I": THETA_I, "g5": THETA_G5}
 
