@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the Multipolynomial Monte Carlo hot path on one MI355X.
 
-Workload (one "step" = one complete trace estimate): 8^4 lattice
+Default workload (one "step" = one complete trace estimate): 8^4 lattice
 (n = 49152), SU(3) links U = exp(i 0.5 H) from seed 2, Wilson kappa = 0.120,
 Theta = I; GMRES polynomials of degree 128, 32 and 8; the 20 lowest eigenpairs
 of M asked from PP-Arnoldi (112 steps on M p_in(M), p_in of degree 8; the
@@ -18,6 +18,11 @@ same standard error): the plain FP64 form of the estimate and the learned
 form (the main solves preconditioned by the trained network; its training is
 timed separately), for the time-to-fixed-standard-error comparison.  The FP64
 CPU oracle is timed on the host as the baseline.
+
+--workload 16x4 / 24x4 run the larger configurations (16^4 double polynomial
+16x16 with 100 eigenpairs requested and 256 noises; 24^4 with four polynomials
+16x16/128/32/8 and 64 noises per term) with the same report; the default line
+is the 8^4 one.
 """
 import argparse
 import json
@@ -36,7 +41,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--noises", type=int, default=128)
+    ap.add_argument("--noises", type=int, default=None, help="noise vectors per term (default: the workload's)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="8x4",
+                    help="8x4 (default, the metric's configuration) or the larger parity configurations")
+    ap.add_argument("--theta", choices=["I", "g5"], default="I")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -45,6 +53,18 @@ def parse():
                     help="run one 256 MiB device-to-device copy first (reference for hardware byte counters)")
     return ap.parse_args()
 
+
+# Workloads: (lattice, link eps, seed, kappa, polynomial degrees ((din, dout) = double
+# polynomial), noises per term, eigenpairs kept, right-hand sides per launch (0 = all),
+# training pairs per minibatch of the learned form)
+WORKLOADS = {
+    "8x4": dict(dims=(8, 8, 8, 8), eps=0.5, seed=2, kappa=0.120, degrees=[128, 32, 8], noises=128, nev=20,
+                max_batch=0, net_pairs=64),
+    "16x4": dict(dims=(16, 16, 16, 16), eps=0.4, seed=3, kappa=0.124, degrees=[(15, 15)], noises=256, nev=100,
+                 max_batch=0, net_pairs=16),
+    "24x4": dict(dims=(24, 24, 24, 24), eps=0.4, seed=4, kappa=0.1245, degrees=[(15, 15), 128, 32, 8], noises=64,
+                 nev=20, max_batch=0, net_pairs=16),
+}
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_wilson_dot_fp32_8x4x128_traffic.md")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2402_00016_amd", "csrc", "wilson.hip")
@@ -72,9 +92,17 @@ def measured_traffic():
     return float(vals["traffic_bytes_per_launch"])
 
 
+def workload_name(key, W, noises, theta):
+    L = W["dims"]
+    degs = "/".join("%dx%d" % (d[0] + 1, d[1] + 1) if isinstance(d, tuple) else str(d) for d in W["degrees"])
+    return ("%s^4 Wilson (kappa %g, eps %g links seed %d), GMRES polynomials of degree %s, %d deflated eigenpairs "
+            "requested, %d Z(4) noises per term, Theta=%s, FP32 Dslash + FP64 refinement to 1e-8"
+            % (L[0], W["kappa"], W["eps"], W["seed"], degs, W["nev"], noises, theta))
+
+
 def cpu_baseline(dims, kappa, links, seconds):
     """FP64 oracle Dslash on the host cores, on a bounded sample: repeated
-    16-RHS applications on the same 8^4 field for about `seconds` seconds."""
+    16-RHS applications on the same field for about `seconds` seconds."""
     import numpy as np
 
     from oracle.philox import z4_noise_batch
@@ -94,8 +122,9 @@ def cpu_baseline(dims, kappa, links, seconds):
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(bytes_per_apply * reps / dt / 1e9, 3), "unit": "GB/s", "cores": cores,
             "kind": "oracle",
-            "sample": "FP64 oracle Wilson operator, 8^4 lattice, 16 Z(4) right-hand sides per call, "
-                      "%d calls in %.1f s on %d host threads; same byte formula as the GPU figure" % (reps, dt, cores)}
+            "sample": "FP64 oracle Wilson operator, %d^4 lattice, 16 Z(4) right-hand sides per call, "
+                      "%d calls in %.1f s on %d host threads; same byte formula as the GPU figure"
+                      % (dims[0], reps, dt, cores)}
 
 
 def main():
@@ -111,12 +140,16 @@ def main():
     from paper_2402_00016_amd import driver, inputs, mpmc
 
     torch.cuda.set_device(0)
-    dims, eps, seed, kappa = (8, 8, 8, 8), 0.5, 2, 0.120
+    W = WORKLOADS[a.workload]
+    dims, eps, seed, kappa = W["dims"], W["eps"], W["seed"], W["kappa"]
+    noises = a.noises or W["noises"]
     links = inputs.gauge_links(dims, eps, seed)
     ctx = mpmc.Context(dims, kappa, links)
-    plan = driver.Plan(degrees=[128, 32, 8], noises=a.noises, seed=seed, nev=20, defl_candidates=40, defl_m=112,
-                       defl_pin_degree=8,
-                       poly_prec=mpmc.FP32, solve_inner_prec=mpmc.FP32, solve_tol=1e-8, solve_restart=50)
+    plan = driver.Plan(degrees=W["degrees"], noises=noises, seed=seed, nev=W["nev"],
+                       defl_candidates=max(40, W["nev"] + 20), defl_m=112 if W["nev"] <= 40 else 136,
+                       defl_pin_degree=8, theta=mpmc.THETA[a.theta], max_batch=W["max_batch"],
+                       poly_prec=mpmc.FP32, solve_inner_prec=mpmc.FP32, solve_tol=1e-8, solve_restart=50,
+                       net_pairs=W["net_pairs"])
     sync = torch.cuda.synchronize
 
     if a.calibrate_copy:
@@ -156,14 +189,13 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": "8^4 Wilson (kappa 0.120, eps 0.5 links seed 2), 3 GMRES polynomials "
-                               "(degrees 128/32/8), 20 deflated eigenpairs, 128 Z(4) noises per term, "
-                               "FP32 Dslash + FP64 refinement to 1e-8",
-                   "lattice": list(dims), "noises_per_term": a.noises, "rhs_per_launch": a.noises},
+        "config": {"workload": workload_name(a.workload, W, noises, a.theta), "lattice": list(dims),
+                   "noises_per_term": noises, "rhs_per_launch": W["max_batch"] or noises,
+                   "degrees": [list(d) if isinstance(d, tuple) else d for d in W["degrees"]], "theta": a.theta},
         "roofline": {"bound": "hbm", "achieved": round(byd / (msd * 1e-3) / 1e9, 1) if msd > 0 else None,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(byd / (msd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if msd > 0 else None,
-                     "traffic": measured_traffic(), "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, "
+                     "traffic": measured_traffic() if a.workload == "8x4" else None, "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, "
                                                                      "scaled by a 256 MiB copy)",
                      "algorithmic_bytes_per_launch": round(byd / max(nd, 1)),
                      "kernel": "k_wilson_dot<FP32> (fused polynomial level step: w' = w - c M w, eta^H Theta w')",
@@ -185,6 +217,8 @@ def main():
 
     out["solve_term"] = {"mixed_batched": solve_term(est)}
     if not a.no_learned:
+        ctx.release_workspace()
+        torch.cuda.empty_cache()
         # learned form: the network is trained once per gauge field (timed
         # separately) and then preconditions the main solves of the estimate
         lplan = driver.Plan(**{**plan.__dict__, "learned": True})
@@ -209,6 +243,8 @@ def main():
         out["trace"]["learned"] = {"value": [el.value.real, el.value.imag], "stderr": el.stderr,
                                    "diff_in_combined_sigma": abs(est.value - el.value) / comb}
     if not a.no_plain:
+        ctx.release_workspace()
+        torch.cuda.empty_cache()
         plain = driver.Plan(**{**plan.__dict__, "poly_prec": mpmc.FP64, "solve_inner_prec": mpmc.FP64})
         driver.estimate(ctx, plain, sync)
         sync()

@@ -104,6 +104,11 @@ int mpmc_vector_bytes(const mpmc_ctx *ctx, int nrhs, int prec, size_t *bytes);
 int mpmc_mvp_count(const mpmc_ctx *ctx, uint64_t *mvps_host);
 int mpmc_mvp_reset(mpmc_ctx *ctx);
 
+/* Free the device workspace the context keeps between calls (Krylov bases,
+ * reduction partials, ...); later calls allocate again as needed.  Useful
+ * between workloads of very different sizes on a full GPU.  Synchronises. */
+int mpmc_release_workspace(mpmc_ctx *ctx);
+
 /* Launch timing of the Wilson-Dirac kernels (the multi-RHS "Dslash", alone or
  * fused into a polynomial step).  While enabled, HIP events are recorded on the
  * context stream around every such launch together with the launch's

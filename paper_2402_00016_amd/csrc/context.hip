@@ -42,6 +42,23 @@ void *ws_get(mpmc_ctx *ctx, int slot, size_t bytes) {
     return b.ptr;
 }
 
+// Frees the cached scratch buffers of stack levels >= from (none of them is
+// in use: live Scratch objects only hold levels below ctx->top).
+static void release_stack_from(mpmc_ctx *ctx, int from) {
+    bool synced = false;
+    for (int i = from; i < (int)ctx->stack.size(); ++i) {
+        WsBuf &b = ctx->stack[i];
+        if (!b.ptr) continue;
+        if (!synced) {
+            hipStreamSynchronize(ctx->stream);
+            synced = true;
+        }
+        hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+}
+
 void *stack_get(mpmc_ctx *ctx, size_t bytes) {
     if ((int)ctx->stack.size() <= ctx->top) ctx->stack.resize(ctx->top + 1);
     WsBuf &b = ctx->stack[ctx->top];
@@ -55,14 +72,32 @@ void *stack_get(mpmc_ctx *ctx, size_t bytes) {
         }
         size_t want = (bytes + 4095) & ~size_t(4095);
         if (hipMalloc(&b.ptr, want) != hipSuccess) {
-            b.ptr = nullptr;
-            set_err(ctx, MPMC_ENOMEM, "scratch: hipMalloc(%zu) failed", want);
-            return nullptr;
+            // retry once after dropping the cached buffers of deeper levels
+            (void)hipGetLastError();
+            release_stack_from(ctx, ctx->top + 1);
+            if (hipMalloc(&b.ptr, want) != hipSuccess) {
+                (void)hipGetLastError();
+                b.ptr = nullptr;
+                set_err(ctx, MPMC_ENOMEM, "scratch: hipMalloc(%zu) failed", want);
+                return nullptr;
+            }
         }
         b.bytes = want;
     }
     ctx->top++;
     return b.ptr;
+}
+
+MPMC_API int mpmc_release_workspace(mpmc_ctx *ctx) {
+    if (!ctx) return MPMC_EINVAL;
+    HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    release_stack_from(ctx, ctx->top);
+    for (auto &b : ctx->ws) {
+        if (b.ptr) hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    return MPMC_OK;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

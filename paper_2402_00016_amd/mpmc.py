@@ -60,6 +60,7 @@ _SIGS = {
     "mpmc_defl_keep": ([_vp, _i], _i),
     "mpmc_solve": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
     "mpmc_autotune": ([_vp, _i, _i, _pi, _vp], _i),
+    "mpmc_release_workspace": ([_vp], _i),
     "mpmc_tune_set": ([_vp, _i, _i, _i], _i),
     "mpmc_net_n_params": ([], _i),
     "mpmc_net_create": ([_vp, _vp, ctypes.POINTER(_vp)], _i),
@@ -513,6 +514,12 @@ class Context:
         return lam, Z[:defl.k], U[:defl.k]
 
     # solves and levels
+    def release_workspace(self):
+        """Free the library's cached device workspace of this context and its side contexts."""
+        for c, _ in self._side.values():
+            c.release_workspace()
+        _check(_L.mpmc_release_workspace(self.handle), self.handle)
+
     def autotune(self, nrhs, prec=FP32):
         """Pick the fastest Wilson kernel variant for (nrhs, prec) -> (variant, us per variant)."""
         return mpmc_autotune(self.handle, nrhs, prec)
