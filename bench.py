@@ -61,7 +61,7 @@ WORKLOADS = {
     "8x4": dict(dims=(8, 8, 8, 8), eps=0.5, seed=2, kappa=0.120, degrees=[128, 32, 8], noises=128, nev=20,
                 max_batch=0, net_pairs=64),
     "16x4": dict(dims=(16, 16, 16, 16), eps=0.4, seed=3, kappa=0.124, degrees=[(15, 15)], noises=256, nev=100,
-                 max_batch=0, net_pairs=16),
+                 max_batch=0, net_pairs=16, solve_prec="fp16s"),
     "24x4": dict(dims=(24, 24, 24, 24), eps=0.4, seed=4, kappa=0.1245, degrees=[(15, 15), 128, 32, 8], noises=64,
                  nev=20, max_batch=0, net_pairs=16),
 }
@@ -96,8 +96,9 @@ def workload_name(key, W, noises, theta):
     L = W["dims"]
     degs = "/".join("%dx%d" % (d[0] + 1, d[1] + 1) if isinstance(d, tuple) else str(d) for d in W["degrees"])
     return ("%s^4 Wilson (kappa %g, eps %g links seed %d), GMRES polynomials of degree %s, %d deflated eigenpairs "
-            "requested, %d Z(4) noises per term, Theta=%s, FP32 Dslash + FP64 refinement to 1e-8"
-            % (L[0], W["kappa"], W["eps"], W["seed"], degs, W["nev"], noises, theta))
+            "requested, %d Z(4) noises per term, Theta=%s, FP32 Dslash + FP64 refinement to 1e-8%s"
+            % (L[0], W["kappa"], W["eps"], W["seed"], degs, W["nev"], noises, theta,
+               ", FP16 Krylov basis in the solves" if W.get("solve_prec") == "fp16s" else ""))
 
 
 def cpu_baseline(dims, kappa, links, seconds):
@@ -148,8 +149,8 @@ def main():
     plan = driver.Plan(degrees=W["degrees"], noises=noises, seed=seed, nev=W["nev"],
                        defl_candidates=max(40, W["nev"] + 20), defl_m=112 if W["nev"] <= 40 else 136,
                        defl_pin_degree=8, theta=mpmc.THETA[a.theta], max_batch=W["max_batch"],
-                       poly_prec=mpmc.FP32, solve_inner_prec=mpmc.FP32, solve_tol=1e-8, solve_restart=50,
-                       net_pairs=W["net_pairs"])
+                       poly_prec=mpmc.FP32, solve_inner_prec=mpmc.PREC[W.get("solve_prec", "fp32")],
+                       solve_tol=1e-8, solve_restart=50, net_pairs=W["net_pairs"])
     sync = torch.cuda.synchronize
 
     if a.calibrate_copy:
@@ -221,7 +222,7 @@ def main():
         torch.cuda.empty_cache()
         # learned form: the network is trained once per gauge field (timed
         # separately) and then preconditions the main solves of the estimate
-        lplan = driver.Plan(**{**plan.__dict__, "learned": True})
+        lplan = driver.Plan(**{**plan.__dict__, "learned": True, "solve_inner_prec": mpmc.FP32})
         sync()
         tl = time.perf_counter()
         net, hist = driver.train_net(ctx, lplan)

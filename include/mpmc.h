@@ -227,7 +227,9 @@ int mpmc_defl_keep(mpmc_defl *d, int k);
 /* x = M^-1 b for nrhs FP64 internal-layout vectors (Sec. 1: the main expense;
  * Sec. 8: deflated GMRES).  Restarted GMRES(restart) with FP64 defect
  * correction: the outer loop forms r = b - M x in FP64, the inner cycle runs
- * in inner_prec (MPMC_FP64 or MPMC_FP32), and x += e in FP64, until every
+ * in inner_prec (MPMC_FP64; MPMC_FP32; or MPMC_FP16S = Krylov basis stored
+ * as FP16 with one FP32 scale per (site, rhs), arithmetic in FP32, each inner
+ * cycle stopped at 1e-3 of its starting residual), and x += e in FP64, until every
  * right-hand side has ||b - M x|| / ||b|| <= tol (true FP64 residual).  With
  * defl, x starts from Z Lambda^-1 U^H b and each restart adds Z Lambda^-1 U^H r.
  * net (may be NULL) is a right preconditioner inside the inner cycle

@@ -43,10 +43,13 @@ __device__ __forceinline__ cpx<double> ldd(const VecRef &v, long e, long si) {
     return mk((double)x.re, (double)x.im);
 }
 
-// partial[j][blk][r] = sum over this block's sites of conj(V_j) Theta w
-template <int P>
-__global__ __launch_bounds__(256) void k_multidot(VecRef Vb, long vstride, int vN, int nv, VecRef w, int N, long V,
-                                                  int theta, double2 *__restrict__ partial, int NB) {
+// partial[j][blk][r] = sum over this block's sites of conj(V_j) Theta w.
+// Basis vector j starts vstride_b bytes after vector j-1 and is stored in
+// precision PB (FP16S: its scales vscale_off bytes after its data); w in PW.
+template <int PB, int PW>
+__global__ __launch_bounds__(256) void k_multidot(VecRef Vb, size_t vstride_b, size_t vscale_off, int vN, int nv,
+                                                  VecRef w, int N, long V, int theta, double2 *__restrict__ partial,
+                                                  int NB) {
     __shared__ double2 red[JB][256];
     const int RT = blockDim.x, CT = blockDim.y;
     const int r = blockIdx.y * RT + threadIdx.x;
@@ -59,7 +62,7 @@ __global__ __launch_bounds__(256) void k_multidot(VecRef Vb, long vstride, int v
             cpx<double> wv[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                wv[k] = ldd<P>(w, (s * 12 + k) * N + r, s * N + r);
+                wv[k] = ldd<PW>(w, (s * 12 + k) * N + r, s * N + r);
                 if (theta && k >= 6) wv[k] = mk(-wv[k].re, -wv[k].im);
             }
 #pragma unroll
@@ -67,11 +70,12 @@ __global__ __launch_bounds__(256) void k_multidot(VecRef Vb, long vstride, int v
                 const int j = j0 + q;
                 if (j < nv) {
                     VecRef vj;
-                    vj.d = (char *)Vb.d + (size_t)j * vstride * sizeof(typename Store<P>::real) * 2;
-                    vj.sc = nullptr;
+                    vj.d = (char *)Vb.d + (size_t)j * vstride_b;
+                    vj.sc = PB == MPMC_FP16S ? (float *)((char *)vj.d + vscale_off) : nullptr;
                     const int vr = vN == 1 ? 0 : r;
 #pragma unroll
-                    for (int k = 0; k < 12; ++k) acc[q] = acc[q] + conjmul(ldd<P>(vj, (s * 12 + k) * vN + vr, 0), wv[k]);
+                    for (int k = 0; k < 12; ++k)
+                        acc[q] = acc[q] + conjmul(ldd<PB>(vj, (s * 12 + k) * vN + vr, s * vN + vr), wv[k]);
                 }
             }
         }
@@ -133,11 +137,11 @@ __global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part
 }
 
 // w += sign * sum_j h[j*N + r] V_j ; optional partial[blk][r] = sum |w|^2
-template <int P>
-__global__ __launch_bounds__(256) void k_multiaxpy(VecRef Vb, long vstride, int vN, int nv, VecRef w, int N, long V,
-                                                   const double2 *__restrict__ h, double sign,
+template <int PB, int PW>
+__global__ __launch_bounds__(256) void k_multiaxpy(VecRef Vb, size_t vstride_b, size_t vscale_off, int vN, int nv,
+                                                   VecRef w, int N, long V, const double2 *__restrict__ h, double sign,
                                                    double2 *__restrict__ partial, int NB, int ldh) {
-    using T = typename Store<P>::real;
+    using T = typename Store<PW>::real;
     __shared__ double red[256];
     const int RT = blockDim.x, CT = blockDim.y;
     const int r = blockIdx.y * RT + threadIdx.x;
@@ -147,23 +151,24 @@ __global__ __launch_bounds__(256) void k_multiaxpy(VecRef Vb, long vstride, int 
             cpx<T> acc[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                auto v = Store<P>::ld(w.d, w.sc, (s * 12 + k) * N + r, 0);
+                auto v = Store<PW>::ld(w.d, w.sc, (s * 12 + k) * N + r, 0);
                 acc[k] = mk((T)v.re, (T)v.im);
             }
             for (int j = 0; j < nv; ++j) {
                 const double2 hj = h[(long)j * ldh + r];
                 const cpx<T> c = mk((T)(sign * hj.x), (T)(sign * hj.y));
-                const void *vj = (const char *)Vb.d + (size_t)j * vstride * sizeof(T) * 2;
+                const void *vj = (const char *)Vb.d + (size_t)j * vstride_b;
+                const float *vsc = PB == MPMC_FP16S ? (const float *)((const char *)vj + vscale_off) : nullptr;
                 const int vr = vN == 1 ? 0 : r;
 #pragma unroll
                 for (int k = 0; k < 12; ++k) {
-                    auto v = Store<P>::ld(vj, nullptr, (s * 12 + k) * vN + vr, 0);
+                    auto v = Store<PB>::ld(vj, vsc, (s * 12 + k) * vN + vr, s * vN + vr);
                     acc[k] = acc[k] + c * mk((T)v.re, (T)v.im);
                 }
             }
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
-                Store<P>::st(w.d, (s * 12 + k) * N + r, acc[k]);
+                Store<PW>::st(w.d, (s * 12 + k) * N + r, acc[k]);
                 nrm += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
             }
         }
@@ -379,11 +384,31 @@ int blas_multi_dot(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv, 
     double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)nv * t.NB * nrhs * sizeof(double2));
     if (!part) return MPMC_ENOMEM;
     dim3 blk(t.RT, t.CT), grd(t.NB, t.ntile, groups);
+    const size_t es = prec == MPMC_FP64 ? 16 : 8;
     int rc = dispatch_prec(ctx, prec, [&](auto P) {
-        k_multidot<decltype(P)::value><<<grd, blk, 0, ctx->stream>>>(
-            vref(ctx, Vb, nrhs, prec), vstride, vN, nv, vref(ctx, w, nrhs, prec), nrhs, ctx->V, theta, part, t.NB);
+        k_multidot<decltype(P)::value, decltype(P)::value><<<grd, blk, 0, ctx->stream>>>(
+            vref(ctx, Vb, nrhs, prec), (size_t)vstride * es, 0, vN, nv, vref(ctx, w, nrhs, prec), nrhs, ctx->V, theta,
+            part, t.NB);
     });
     RET_IF(rc);
+    k_reduce<<<nv * nrhs, 256, 0, ctx->stream>>>(part, t.NB, nrhs, (double2 *)h_dev, accumulate, 0);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
+// FP16S basis (nrhs-wide batches vstride_b bytes apart) against an FP32 w.
+int blas_multi_dot_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, const void *w, int nrhs,
+                     double *h_dev, int accumulate) {
+    if (nv <= 0) return MPMC_OK;
+    const int groups = (nv + JB - 1) / JB;
+    Tiling t = tiling(ctx, nrhs, groups);
+    double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)nv * t.NB * nrhs * sizeof(double2));
+    if (!part) return MPMC_ENOMEM;
+    dim3 blk(t.RT, t.CT), grd(t.NB, t.ntile, groups);
+    k_multidot<MPMC_FP16S, MPMC_FP32><<<grd, blk, 0, ctx->stream>>>(
+        VecRef{const_cast<void *>(Vb), nullptr}, vstride_b, fp16s_scale_offset(ctx, nrhs), nrhs, nv,
+        vref(ctx, w, nrhs, MPMC_FP32), nrhs, ctx->V, 0, part, t.NB);
+    HIP_OR_RET(ctx, hipGetLastError());
     k_reduce<<<nv * nrhs, 256, 0, ctx->stream>>>(part, t.NB, nrhs, (double2 *)h_dev, accumulate, 0);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
@@ -426,12 +451,34 @@ int blas_multi_axpy(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv,
         if (!part) return MPMC_ENOMEM;
     }
     dim3 blk(t.RT, t.CT), grd(t.NB, t.ntile, 1);
+    const size_t es = prec == MPMC_FP64 ? 16 : 8;
     int rc = dispatch_prec(ctx, prec, [&](auto P) {
-        k_multiaxpy<decltype(P)::value><<<grd, blk, 0, ctx->stream>>>(
-            vref(ctx, Vb, nrhs, prec), vstride, vN, nv, vref(ctx, w, nrhs, prec), nrhs, ctx->V,
+        k_multiaxpy<decltype(P)::value, decltype(P)::value><<<grd, blk, 0, ctx->stream>>>(
+            vref(ctx, Vb, nrhs, prec), (size_t)vstride * es, 0, vN, nv, vref(ctx, w, nrhs, prec), nrhs, ctx->V,
             (const double2 *)h_dev, sign, part, t.NB, ldh);
     });
     RET_IF(rc);
+    if (norm2_dev) {
+        k_reduce<<<nrhs, 256, 0, ctx->stream>>>(part, t.NB, nrhs, (double2 *)norm2_dev, 0, 1);
+        HIP_OR_RET(ctx, hipGetLastError());
+    }
+    return MPMC_OK;
+}
+
+// w (FP32) += sign * sum_j h[j*ldh + r] V_j with an FP16S basis
+int blas_multi_axpy_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, void *w, int nrhs,
+                      const double *h_dev, int ldh, double sign, double *norm2_dev) {
+    Tiling t = tiling(ctx, nrhs, 1);
+    double2 *part = nullptr;
+    if (norm2_dev) {
+        part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)t.NB * nrhs * sizeof(double2));
+        if (!part) return MPMC_ENOMEM;
+    }
+    dim3 blk(t.RT, t.CT), grd(t.NB, t.ntile, 1);
+    k_multiaxpy<MPMC_FP16S, MPMC_FP32><<<grd, blk, 0, ctx->stream>>>(
+        VecRef{const_cast<void *>(Vb), nullptr}, vstride_b, fp16s_scale_offset(ctx, nrhs), nrhs, nv,
+        vref(ctx, w, nrhs, MPMC_FP32), nrhs, ctx->V, (const double2 *)h_dev, sign, part, t.NB, ldh);
+    HIP_OR_RET(ctx, hipGetLastError());
     if (norm2_dev) {
         k_reduce<<<nrhs, 256, 0, ctx->stream>>>(part, t.NB, nrhs, (double2 *)norm2_dev, 0, 1);
         HIP_OR_RET(ctx, hipGetLastError());

@@ -294,12 +294,20 @@ int blas_dot(mpmc_ctx *ctx, const void *x, const void *y, int nrhs, int prec, in
 int blas_norm2(mpmc_ctx *ctx, const void *x, int nrhs, int prec, double *out_dev);
 int blas_multi_axpy(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv, void *w, int nrhs, int prec,
                     const double *h_dev, int ldh, double sign, double *norm2_dev);
+// FP16S Krylov bases (nrhs-wide FP16S batches spaced vstride_b bytes apart)
+// against FP32 working vectors
+int blas_multi_dot_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, const void *w, int nrhs,
+                     double *h_dev, int accumulate);
+int blas_multi_axpy_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, void *w, int nrhs,
+                      const double *h_dev, int ldh, double sign, double *norm2_dev);
 int blas_axpby(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, double2 a, double2 b);
 int blas_scale_rhs(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, const double *coef_dev, int mode);
 int blas_convert(mpmc_ctx *ctx, const void *x, int px, void *y, int py, int nrhs);
 int blas_zero(mpmc_ctx *ctx, void *y, int nrhs, int prec);
 int blas_scale_acc(mpmc_ctx *ctx, const double *t, int N, double2 c, double sign, double *acc);
 
+// wilson.hip: out (FP32) = M b for an FP16S operand b
+int wilson_apply_h2f(mpmc_ctx *ctx, const void *b, void *out, int nrhs);
 // wilson.hip: out = alpha a + beta Theta op(b); y += gamma out (y may be null)
 int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, void *y, int nrhs, int prec,
                        double2 alpha, double2 beta, double2 gamma, int dagger, int theta);

@@ -47,14 +47,18 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
     if (net && net_context(net) != ctx) return set_err(ctx, MPMC_ESTATE, "mpmc_solve: network belongs to another context");
     if (net && inner_prec != MPMC_FP32)
         return set_err(ctx, MPMC_EINVAL, "mpmc_solve: the learned preconditioner runs with FP32 inner cycles only");
-    if (inner_prec != MPMC_FP64 && inner_prec != MPMC_FP32)
-        return set_err(ctx, MPMC_EINVAL, "mpmc_solve: inner precision must be FP64 or FP32");
+    if (inner_prec != MPMC_FP64 && inner_prec != MPMC_FP32 && inner_prec != MPMC_FP16S)
+        return set_err(ctx, MPMC_EINVAL, "mpmc_solve: inner precision must be FP64, FP32 or FP16S");
     Scratch S(ctx);
     const long n = ctx->n;
-    const size_t vb64 = vec_bytes(ctx, N, MPMC_FP64), vbi = vec_bytes(ctx, N, inner_prec);
-    const long vstride = n * N;   // complex elements between basis vectors
+    // basis vectors in pb (FP16S: half + per-(site, rhs) scale, storage only);
+    // working vectors (w, e) and arithmetic in pw
+    const int pb = inner_prec, pw = inner_prec == MPMC_FP64 ? MPMC_FP64 : MPMC_FP32;
+    const bool half = pb == MPMC_FP16S;
+    const size_t vb64 = vec_bytes(ctx, N, MPMC_FP64), vbi = vec_bytes(ctx, N, pw), vbb = vec_bytes(ctx, N, pb);
+    const long vstride = n * N;   // complex elements between basis vectors (FP64/FP32 bases)
     double *r = (double *)S.get(vb64);
-    void *V = S.get(vbi * (m + 1));
+    void *V = S.get(vbb * (m + 1));
     void *Zb = net ? S.get(vbi * m) : nullptr;   // flexible GMRES: preconditioned basis z_j = N v_j
     void *w = S.get(vbi);
     void *e = S.get(vbi);
@@ -127,18 +131,25 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
             const double rn = std::sqrt(std::max(rn2[2 * i], 0.0)), bn = std::sqrt(std::max(bn2[2 * i], 0.0));
             double t = 0.5 * tol * bn;
             if (inner_prec == MPMC_FP32) t = std::max(t, 2e-6 * rn);
+            if (half) t = std::max(t, 1e-3 * rn);   // FP16 basis: the Arnoldi relation holds to ~2^-11
             target[i] = t;
         }
-        RET_IF(blas_convert(ctx, r, MPMC_FP64, V, inner_prec, N));
-        RET_IF(blas_scale_rhs(ctx, V, V, N, inner_prec, nrm, 1));
+        if (half) {
+            RET_IF(blas_convert(ctx, r, MPMC_FP64, w, MPMC_FP32, N));
+            RET_IF(blas_scale_rhs(ctx, w, w, N, MPMC_FP32, nrm, 1));
+            RET_IF(blas_convert(ctx, w, MPMC_FP32, V, MPMC_FP16S, N));
+        } else {
+            RET_IF(blas_convert(ctx, r, MPMC_FP64, V, inner_prec, N));
+            RET_IF(blas_scale_rhs(ctx, V, V, N, inner_prec, nrm, 1));
+        }
         HIP_OR_RET(ctx, hipMemsetAsync(H, 0, sizeof(double2) * (size_t)(m + 1) * (m + 1) * N, ctx->stream));
         k_init_g<<<grid_for((long)(m + 1) * N, 256), 256, 0, ctx->stream>>>((double2 *)g, m, N, (const double2 *)nrm);
         HIP_OR_RET(ctx, hipGetLastError());
         const size_t es = inner_prec == MPMC_FP64 ? 16 : 8;
         int jdone = 0;
         for (int j = 0; j < m; ++j) {
-            void *vj = (char *)V + (size_t)j * vstride * es;
-            void *vj1 = (char *)V + (size_t)(j + 1) * vstride * es;
+            void *vj = half ? (void *)((char *)V + (size_t)j * vbb) : (char *)V + (size_t)j * vstride * es;
+            void *vj1 = half ? (void *)((char *)V + (size_t)(j + 1) * vbb) : (char *)V + (size_t)(j + 1) * vstride * es;
             double *Hcol = H + 2 * (size_t)j * (m + 1) * N;
             const void *opin = vj;
             if (cnet) {
@@ -146,16 +157,29 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
                 RET_IF(net_apply_internal(ctx, cnet, vj, zj, N));
                 opin = zj;
             }
-            RET_IF(wilson_launch_full(ctx, opin, nullptr, w, nullptr, N, inner_prec, make_double2(0, 0),
-                                      make_double2(1, 0), make_double2(0, 0), 0, 0));
-            RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, 0, 0));
-            RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, N, -1.0, nullptr));
-            RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, inner_prec, h2, 0, 0));
-            RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, inner_prec, h2, N, -1.0, nrm));
+            if (half) {
+                RET_IF(wilson_apply_h2f(ctx, vj, w, N));
+                RET_IF(blas_multi_dot_h(ctx, V, vbb, j + 1, w, N, Hcol, 0));
+                RET_IF(blas_multi_axpy_h(ctx, V, vbb, j + 1, w, N, Hcol, N, -1.0, nullptr));
+                RET_IF(blas_multi_dot_h(ctx, V, vbb, j + 1, w, N, h2, 0));
+                RET_IF(blas_multi_axpy_h(ctx, V, vbb, j + 1, w, N, h2, N, -1.0, nrm));
+            } else {
+                RET_IF(wilson_launch_full(ctx, opin, nullptr, w, nullptr, N, inner_prec, make_double2(0, 0),
+                                          make_double2(1, 0), make_double2(0, 0), 0, 0));
+                RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, 0, 0));
+                RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, N, -1.0, nullptr));
+                RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, inner_prec, h2, 0, 0));
+                RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, inner_prec, h2, N, -1.0, nrm));
+            }
             k_finalize_batch<<<grid_for(N, 64), 64, 0, ctx->stream>>>((double2 *)Hcol, (const double2 *)h2, j, N,
                                                                       (const double2 *)nrm, (double2 *)scale);
             HIP_OR_RET(ctx, hipGetLastError());
-            RET_IF(blas_scale_rhs(ctx, w, vj1, N, inner_prec, scale, 0));
+            if (half) {
+                RET_IF(blas_scale_rhs(ctx, w, w, N, MPMC_FP32, scale, 0));
+                RET_IF(blas_convert(ctx, w, MPMC_FP32, vj1, MPMC_FP16S, N));
+            } else {
+                RET_IF(blas_scale_rhs(ctx, w, vj1, N, inner_prec, scale, 0));
+            }
             RET_IF(dense_givens_step(ctx, H, m + 1, j, N, cs, g, res));
             jdone = j + 1;
             if ((j + 1) % 10 == 0 && j + 1 < m) {
@@ -168,9 +192,12 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
         }
         RET_IF(dense_backsolve(ctx, H, m + 1, jdone, N, g, y));
         HIP_OR_RET(ctx, hipMemsetAsync(e, 0, vbi, ctx->stream));
-        RET_IF(blas_multi_axpy(ctx, cnet ? Zb : V, vstride, N, jdone, e, N, inner_prec, y, N, 1.0, nullptr));
+        if (half)
+            RET_IF(blas_multi_axpy_h(ctx, V, vbb, jdone, e, N, y, N, 1.0, nullptr));
+        else
+            RET_IF(blas_multi_axpy(ctx, cnet ? Zb : V, vstride, N, jdone, e, N, inner_prec, y, N, 1.0, nullptr));
         // x += e (in FP64)
-        RET_IF(blas_convert(ctx, e, inner_prec, r, MPMC_FP64, N));
+        RET_IF(blas_convert(ctx, e, pw, r, MPMC_FP64, N));
         RET_IF(blas_axpby(ctx, r, x, N, MPMC_FP64, make_double2(1, 0), make_double2(1, 0)));
         total += jdone;
     }

@@ -413,6 +413,7 @@ struct WOut {
     float g;
     int theta;
     int a_is_b;
+    int out_fp32;           // FP16S kernels only: write out as FP32 (plain out = M b)
 };
 
 // Occupancy targets (minimum wavefronts per SIMD the register allocation must
@@ -460,6 +461,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI,
         res[k] = v;
     }
     if constexpr (P == MPMC_FP16S) {
+        if (o.out_fp32) {
+            const SiteAcc<MPMC_FP32, UNI> O(o.out, nullptr, s, N, (uint32_t)r);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) O.st(k, res[k]);
+            return;
+        }
         float mx = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) mx = fmaxf(mx, fmaxf(fabsf(res[k].re), fabsf(res[k].im)));
@@ -773,6 +780,7 @@ int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, v
     o.gamma = gamma;
     o.g = dagger ? -1.f : 1.f;
     o.theta = theta;
+    o.out_fp32 = 0;
     const int ev = timing_begin(ctx);
     if (prec == MPMC_FP64) launch_w<MPMC_FP64>(ctx, b, o, nrhs);
     else if (prec == MPMC_FP32) launch_w<MPMC_FP32>(ctx, b, o, nrhs);
@@ -787,6 +795,32 @@ int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, v
         if (y) per += 2 * sb;
         timing_end(ctx, ev, prec | MPMC_TIMING_PLAIN, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
     }
+    ctx->mvps += (uint64_t)nrhs;
+    return MPMC_OK;
+}
+
+int wilson_apply_h2f(mpmc_ctx *ctx, const void *b, void *out, int nrhs) {
+    WOut o;
+    o.out = out;
+    o.osc = nullptr;
+    o.a = nullptr;
+    o.asc = nullptr;
+    o.a_is_b = 0;
+    o.y = nullptr;
+    o.kappa = ctx->kappa;
+    o.alpha = make_double2(0, 0);
+    o.beta = make_double2(1, 0);
+    o.gamma = make_double2(0, 0);
+    o.g = 1.f;
+    o.theta = 0;
+    o.out_fp32 = 1;
+    const int ev = timing_begin(ctx);
+    launch_w<MPMC_FP16S>(ctx, b, o, nrhs);
+    HIP_OR_RET(ctx, hipGetLastError());
+    if (ev >= 0)
+        timing_end(ctx, ev, MPMC_FP16S | MPMC_TIMING_PLAIN,
+                   (double)ctx->V * ((double)nrhs * (spinor_bytes(MPMC_FP16S) + spinor_bytes(MPMC_FP32)) +
+                                     link_bytes(MPMC_FP16S)));
     ctx->mvps += (uint64_t)nrhs;
     return MPMC_OK;
 }

@@ -252,7 +252,7 @@ def test_deflate_parity(m):
 
 # ------------------------------------------------------------------ solve --
 
-@pytest.mark.parametrize("inner", [FP64, FP32])
+@pytest.mark.parametrize("inner", [FP64, FP32, FP16S])
 def test_solve_true_residual(f44, inner):
     dims, kappa, U, op, ctx = f44
     N = 6
@@ -424,3 +424,22 @@ def test_autotune_variants_bit_identical(f44, prec):
     assert np.array_equal(host(ctx.apply_M(x, N, prec)), outs[0])
     ctx.tune_set(N, prec, -1)
     assert ctx.autotune(20, prec)[0] == -1     # not a multiple of 64: nothing to tune
+
+
+@pytest.mark.parametrize("N", [64, 20])
+def test_solve_fp16_basis_matches_fp32(N):
+    """FP16S Krylov basis (FP32 arithmetic, FP64 defect correction): same true
+    residual bound and the same solution as the FP32-basis solve."""
+    dims, kappa = (8, 8, 8, 8), 0.120
+    U = inputs.gauge_links(dims, 0.5, seed=2)
+    ctx = mpmc.Context(dims, kappa, U)
+    op = WilsonOp(dims, kappa, U)
+    b = ctx.noise(6, 0, 0, N, FP64)
+    x16, it16, rr16 = ctx.solve(b, N, restart=50, tol=1e-9, inner_prec=FP16S)
+    x32, it32, rr32 = ctx.solve(b, N, restart=50, tol=1e-9, inner_prec=FP32)
+    assert np.all(rr16 <= 1e-9) and np.all(rr32 <= 1e-9)
+    X16, X32 = host(ctx.unpack(x16, N)), host(ctx.unpack(x32, N))
+    assert rel(X16, X32) < 5e-9
+    j = N - 1
+    bj = z4_noise(6, 0, j, op.n)
+    assert np.linalg.norm(bj - op(X16[j])) / np.linalg.norm(bj) <= 1.05e-9
