@@ -439,7 +439,8 @@ __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh,
                 st(&M(i, j), 0, v);
             }
         __syncthreads();
-        rc = hess_eigvals<3>(M, d, roots, lds_mat + packed_hess_size(d));
+        rc = d <= 128 ? hess_eigvals<2>(M, d, roots, lds_mat + packed_hess_size(d))
+                      : hess_eigvals<3>(M, d, roots, lds_mat + packed_hess_size(d));
     } else {
         GlobalMat M{A, d};
         for (long e = tid; e < (long)d * d; e += nt) {
@@ -508,7 +509,8 @@ __global__ __launch_bounds__(64) void k_hess_eigs(const double2 *H, int ldh, int
         for (int j = 0; j < m; ++j)
             for (int i = threadIdx.x; i <= (j + 1 < m ? j + 1 : m - 1); i += blockDim.x) M(i, j) = H[i + (long)j * ldh];
         __syncthreads();
-        rc = hess_eigvals<3>(M, m, ev, lds_mat + packed_hess_size(m));
+        rc = m <= 128 ? hess_eigvals<2>(M, m, ev, lds_mat + packed_hess_size(m))
+                      : hess_eigvals<3>(M, m, ev, lds_mat + packed_hess_size(m));
     } else {
         for (long e = threadIdx.x; e < (long)m * m; e += blockDim.x) {
             const int i = (int)(e % m), j = (int)(e / m);

@@ -18,16 +18,22 @@
 // After the second Gram-Schmidt pass: H(:, j) += h2, h_{j+1,j} = ||w||,
 // breakdown test against the running Frobenius norm, coefficient 1/h for the
 // new basis vector (0 after a breakdown, which keeps later vectors zero).
-__global__ void k_arnoldi_finalize(double2 *Hcol, const double2 *h2, int j, const double2 *nrm2, double *state,
-                                   double2 *scale) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One wavefront: the column update is spread over the lanes and the squared
+// norm summed with a fixed butterfly.
+__global__ __launch_bounds__(64) void k_arnoldi_finalize(double2 *Hcol, const double2 *h2, int j,
+                                                         const double2 *nrm2, double *state, double2 *scale) {
     // state[0] = running ||H||_F^2, state[1] = d_eff (or -1 while none)
-    double fro = state[0];
-    for (int i = 0; i <= j; ++i) {
-        Hcol[i].x += h2[i].x;
-        Hcol[i].y += h2[i].y;
-        fro += Hcol[i].x * Hcol[i].x + Hcol[i].y * Hcol[i].y;
+    double f = 0.0;
+    for (int i = threadIdx.x; i <= j; i += 64) {
+        double2 v = Hcol[i];
+        v.x += h2[i].x;
+        v.y += h2[i].y;
+        Hcol[i] = v;
+        f += v.x * v.x + v.y * v.y;
     }
+    for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o);
+    if (threadIdx.x != 0) return;
+    double fro = state[0] + f;
     const double hn = sqrt(fmax(nrm2[0].x, 0.0));
     fro += hn * hn;
     state[0] = fro;
@@ -97,7 +103,7 @@ int arnoldi_run(mpmc_ctx *ctx, const OpDesc &op, double *V, double *H, int d, do
         // CGS pass 2 with the norm fused into the update
         RET_IF(blas_multi_dot(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, (double *)h2, 0, 0));
         RET_IF(blas_multi_axpy(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, (double *)h2, 1, -1.0, (double *)sc));
-        k_arnoldi_finalize<<<1, 1, 0, ctx->stream>>>((double2 *)Hcol, h2, j, sc, state, sc + 1);
+        k_arnoldi_finalize<<<1, 64, 0, ctx->stream>>>((double2 *)Hcol, h2, j, sc, state, sc + 1);
         HIP_OR_RET(ctx, hipGetLastError());
         RET_IF(blas_scale_rhs(ctx, w, vj1, 1, MPMC_FP64, (double *)(sc + 1), 0));
     }
