@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="8x4",
                     help="8x4 (default, the metric's configuration) or the larger parity configurations")
     ap.add_argument("--theta", choices=["I", "g5"], default="I")
+    ap.add_argument("--net-source", choices=["random", "solve"], default="solve",
+                    help="training pairs of the learned form: (M e, e) or snapshots of training solves")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner form")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -222,7 +224,9 @@ def main():
         torch.cuda.empty_cache()
         # learned form: the network is trained once per gauge field (timed
         # separately) and then preconditions the main solves of the estimate
-        lplan = driver.Plan(**{**plan.__dict__, "learned": True, "solve_inner_prec": mpmc.FP32})
+        lplan = driver.Plan(**{**plan.__dict__, "learned": True, "solve_inner_prec": mpmc.FP32,
+                               "net_source": a.net_source,
+                               "net_batches": 2 if a.net_source == "solve" else 8})
         sync()
         tl = time.perf_counter()
         net, hist = driver.train_net(ctx, lplan)
@@ -238,7 +242,8 @@ def main():
         out["time_to_error_s"]["net_training"] = round(t_train, 4)
         out["time_to_error_s"]["learned_batched_incl_training"] = round(tl + t_train, 4)
         out["solve_term"]["learned_batched"] = solve_term(el)
-        out["net"] = {"pairs": lplan.net_batches * lplan.net_pairs, "adam_steps": lplan.net_batches * lplan.net_steps,
+        out["net"] = {"source": lplan.net_source, "minibatches": len(hist) // lplan.net_steps,
+                      "pairs": len(hist) // lplan.net_steps * lplan.net_pairs, "adam_steps": len(hist),
                       "loss_first": float(hist[0]), "loss_last": float(hist[-1])}
         comb = float(np.hypot(el.stderr, est.stderr))
         out["trace"]["learned"] = {"value": [el.value.real, el.value.imag], "stderr": el.stderr,

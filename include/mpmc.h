@@ -306,6 +306,18 @@ int mpmc_net_loss_grad(mpmc_net *net, const void *R, const void *E, int npairs,
 int mpmc_net_train(mpmc_net *net, const void *R, const void *E, int npairs, int steps,
                    double lr, double *loss_host);
 
+/* mpmc_solve (no network) that also records training pairs for the learned
+ * preconditioner from the solve itself: at the start of each outer cycle k <
+ * max_snap, batch k of R_snap receives r_k = b - M x_k and batch k of E_snap
+ * the error e_k = x - x_k of that iterate against the converged x (FP32
+ * internal layout, nrhs vectors per batch, batches spaced
+ * mpmc_vector_bytes(ctx, nrhs, MPMC_FP32) apart; caller-owned device
+ * buffers of max_snap batches).  *nsnap_host = batches written.  Synchronises. */
+int mpmc_solve_pairs(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl,
+                     int restart, double tol, int inner_prec, int max_outer, void *R_snap,
+                     void *E_snap, int max_snap, int *nsnap_host, int *iters_host,
+                     double *relres_host);
+
 /* ---------------------------------------------------------------- estimators */
 
 /* Samples of one Monte Carlo level (Sec. 2 eq. 2, Sec. 6, Sec. 7), for noise

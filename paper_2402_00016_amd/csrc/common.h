@@ -352,5 +352,13 @@ int net_apply_internal(mpmc_ctx *ctx, const mpmc_net *net, const void *x, void *
 const mpmc_ctx *net_context(const mpmc_net *net);
 
 // solve.hip
+// Optional record of (residual, error) pairs at the start of each outer cycle
+// (network training data): batches of nrhs FP32 vectors.
+struct SolveSnap {
+    void *R, *E;   // max batches each, spaced vec_bytes(ctx, nrhs, FP32) apart
+    int max;
+    int count;     // out
+};
 int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl, const mpmc_net *net,
-                   int restart, double tol, int inner_prec, int max_outer, int *iters, double *relres_host);
+                   int restart, double tol, int inner_prec, int max_outer, int *iters, double *relres_host,
+                   SolveSnap *snap = nullptr);

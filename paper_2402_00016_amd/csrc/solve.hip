@@ -43,7 +43,8 @@ __global__ void k_init_g(double2 *g, int m, int N, const double2 *rn2) {
 }  // namespace
 
 int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl *defl, const mpmc_net *net,
-                   int m, double tol, int inner_prec, int max_outer, int *iters_out, double *relres_host) {
+                   int m, double tol, int inner_prec, int max_outer, int *iters_out, double *relres_host,
+                   SolveSnap *snap) {
     if (net && net_context(net) != ctx) return set_err(ctx, MPMC_ESTATE, "mpmc_solve: network belongs to another context");
     if (net && inner_prec != MPMC_FP32)
         return set_err(ctx, MPMC_EINVAL, "mpmc_solve: the learned preconditioner runs with FP32 inner cycles only");
@@ -70,6 +71,8 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
     double *res = (double *)S.get(sizeof(double) * N);
     double *sc = (double *)S.get(sizeof(double2) * 4 * N);   // [0..N) norms, [N..2N) scales
     double *dc = defl && defl->k ? (double *)S.get(sizeof(double2) * (size_t)defl->k * N) : nullptr;
+    void *xsnap = snap ? S.get(vb64 * (size_t)snap->max) : nullptr;   // FP64 iterates x_k of the record
+    if (snap && !xsnap) return MPMC_ENOMEM;
     if (!r || !V || (net && !Zb) || !w || !e || !H || !h2 || !cs || !g || !y || !res || !sc || (defl && defl->k && !dc))
         return MPMC_ENOMEM;
     double *nrm = sc, *scale = sc + 2 * N;
@@ -124,6 +127,13 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
         }
         rel_start = rel;
         const mpmc_net *cnet = use_net ? net : nullptr;
+        if (snap && snap->count < snap->max) {   // r_k now; e_k = x* - x_k (FP64) at the end
+            const size_t vb32 = vec_bytes(ctx, N, MPMC_FP32);
+            RET_IF(blas_convert(ctx, r, MPMC_FP64, (char *)snap->R + (size_t)snap->count * vb32, MPMC_FP32, N));
+            HIP_OR_RET(ctx, hipMemcpyAsync((char *)xsnap + (size_t)snap->count * vb64, x, vb64,
+                                           hipMemcpyDeviceToDevice, ctx->stream));
+            ++snap->count;
+        }
         // inner targets: the final tolerance for an FP64 cycle; FP32 cycles
         // stop near single precision and the outer loop corrects the rest
         std::vector<double> target(N);
@@ -202,11 +212,35 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
         total += jdone;
     }
     if (!converged) RET_IF(true_residual());
+    if (snap && snap->count > 0) {
+        const size_t vb32 = vec_bytes(ctx, N, MPMC_FP32);
+        for (int k = 0; k < snap->count; ++k) {
+            void *xk = (char *)xsnap + (size_t)k * vb64;
+            RET_IF(blas_axpby(ctx, x, xk, N, MPMC_FP64, make_double2(1, 0), make_double2(-1, 0)));
+            RET_IF(blas_convert(ctx, xk, MPMC_FP64, (char *)snap->E + (size_t)k * vb32, MPMC_FP32, N));
+        }
+    }
     if (iters_out) *iters_out = total;
     if (relres_host)
         for (int i = 0; i < N; ++i) relres_host[i] = rel[i];
     if (!converged) return set_err(ctx, MPMC_ENOCONV, "mpmc_solve: not converged after %d outer cycles", max_outer);
     return MPMC_OK;
+}
+
+MPMC_API int mpmc_solve_pairs(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl, int restart,
+                              double tol, int inner_prec, int max_outer, void *R_snap, void *E_snap, int max_snap,
+                              int *nsnap_host, int *iters_host, double *relres_host) {
+    if (!ctx) return MPMC_EINVAL;
+    if (!b || !x || nrhs < 1 || restart < 1 || restart > 400 || !(tol > 0) || max_outer < 1 || !R_snap || !E_snap ||
+        max_snap < 1 || !nsnap_host)
+        return set_err(ctx, MPMC_EINVAL, "mpmc_solve_pairs: bad argument");
+    if (b == x) return set_err(ctx, MPMC_EINVAL, "mpmc_solve_pairs: b and x must not alias");
+    if (defl && defl->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "deflation set belongs to another context");
+    SolveSnap sn{R_snap, E_snap, max_snap, 0};
+    const int rc = solve_internal(ctx, b, x, nrhs, defl, nullptr, restart, tol, inner_prec, max_outer, iters_host,
+                                  relres_host, &sn);
+    *nsnap_host = sn.count;
+    return rc;
 }
 
 MPMC_API int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl, const mpmc_net *net,

@@ -14,9 +14,10 @@ Random streams: level l uses stream l, the GMRES start vector of polynomial j
 uses stream 0x100 + j, the deflation start vector stream 0x200.
 
 Learned form (not in the paper): a gauge-covariant linear network N is trained
-on the device on residual/error pairs (r, e) = (M e, e), e a Z(4) vector drawn
-with seeds net_seed0, net_seed0 + 1, ... (stream 0), and then preconditions the
-main solves (flexible GMRES).  The solves still stop on the same FP64 true
+on the device on residual/error pairs recorded by training solves of the method
+(r_k = eta - M x_k and e_k = x - x_k at the start of each outer cycle, eta a
+Z(4) vector of seed net_seed0, net_seed0 + 1, ..., stream 0), and then
+preconditions the main solves (flexible GMRES).  The solves still stop on the same FP64 true
 residual, so the estimate does not depend on N.
 """
 import math
@@ -55,11 +56,13 @@ class Plan:
     max_batch: int = 0                   # right-hand sides per launch (0: all noise of a level)
     deflate_levels: bool = True
     learned: bool = False                # precondition the main solves with a trained network
-    net_batches: int = 8                 # training minibatches (one Z(4) seed each)
+    net_batches: int = 2                 # training solves ("solve") or minibatches ("random"), one Z(4) seed each
     net_pairs: int = 64                  # (r, e) pairs per minibatch
     net_steps: int = 10                  # Adam steps per minibatch
     net_lr: float = 1e-2
     net_seed0: int = 100
+    net_source: str = "solve"            # "solve": snapshots of training solves; "random": (M e, e), e Z(4)
+    net_snaps: int = 4                   # outer cycles recorded per training solve ("solve" source)
     overlap_setup: bool = True           # build polynomials (and train the net) on side streams
     autotune: bool = True                # time the Wilson kernel variants for the level batches once per context
 
@@ -150,17 +153,32 @@ def net_identity_weights():
 
 
 def train_net(ctx, plan: Plan):
-    """Network trained on (M e, e) pairs; initial weights: identity plus a small
-    seeded perturbation (so that the second field receives gradient).
+    """Network trained on residual/error pairs; initial weights: identity plus a
+    small seeded perturbation (so that the second field receives gradient).
+
+    net_source "random": pairs (r, e) = (M e, e) with e a Z(4) vector of seed
+    net_seed0 + b (stream 0), one minibatch of net_pairs per b < net_batches.
+    net_source "solve": for b < net_batches, solve M x = eta (eta Z(4) of seed
+    net_seed0 + b, FP32 inner cycles) and train on the (r_k, e_k = x - x_k)
+    batches recorded at the start of each outer cycle (mpmc_solve_pairs).
     Returns (net, loss history)."""
     rng = np.random.default_rng(plan.seed)
     theta0 = net_identity_weights() + 0.01 * rng.standard_normal(mpmc.mpmc_net_n_params())
     net = ctx.net(theta0)
     hist = []
+    P = plan.net_pairs
     for b in range(plan.net_batches):
-        e = ctx.noise(plan.net_seed0 + b, 0, 0, plan.net_pairs, mpmc.FP32)
-        r = ctx.apply_M(e, plan.net_pairs, mpmc.FP32)
-        hist.extend(net.train(r, e, plan.net_pairs, plan.net_steps, plan.net_lr))
+        if plan.net_source == "solve":
+            eta = ctx.noise(plan.net_seed0 + b, 0, 0, P, mpmc.FP64)
+            x, R, E, ns, vb = ctx.solve_pairs(eta, P, plan.net_snaps, tol=plan.solve_tol,
+                                              restart=plan.solve_restart, inner_prec=mpmc.FP32)
+            for k in range(ns):
+                hist.extend(net.train(R[k * vb:(k + 1) * vb], E[k * vb:(k + 1) * vb], P, plan.net_steps,
+                                      plan.net_lr))
+        else:
+            e = ctx.noise(plan.net_seed0 + b, 0, 0, P, mpmc.FP32)
+            r = ctx.apply_M(e, P, mpmc.FP32)
+            hist.extend(net.train(r, e, P, plan.net_steps, plan.net_lr))
     return net, np.array(hist)
 
 

@@ -70,6 +70,7 @@ _SIGS = {
     "mpmc_net_apply": ([_vp, _vp, _vp, _i], _i),
     "mpmc_net_loss_grad": ([_vp, _vp, _vp, _i, _pd, _vp], _i),
     "mpmc_net_train": ([_vp, _vp, _vp, _i, _i, _d, _vp], _i),
+    "mpmc_solve_pairs": ([_vp, _vp, _vp, _i, _vp, _i, _d, _i, _i, _vp, _vp, _i, _pi, _pi, _vp], _i),
     "mpmc_level_estimate": ([_vp, _vp, _vp, _vp, _i, _u64, _u32, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp,
                              _pu64], _i),
 }
@@ -253,6 +254,15 @@ def mpmc_solve(ctx, b, x, nrhs, defl=None, net=None, restart=50, tol=1e-8, inner
     if rc != ENOCONV or raise_on_noconv:
         _check(rc, ctx)
     return its.value, rel, rc
+
+
+def mpmc_solve_pairs(ctx, b, x, nrhs, defl, restart, tol, inner_prec, max_outer, R, E, max_snap):
+    its, ns = ctypes.c_int(), ctypes.c_int()
+    rel = np.zeros(nrhs)
+    _check(_L.mpmc_solve_pairs(ctx, _ptr(b), _ptr(x), int(nrhs), _h(defl), int(restart), float(tol), int(inner_prec),
+                               int(max_outer), _ptr(R), _ptr(E), int(max_snap), ctypes.byref(ns), ctypes.byref(its),
+                               rel.ctypes.data), ctx)
+    return ns.value, its.value, rel
 
 
 def mpmc_level_estimate(ctx, upper, lower, defl, theta, seed, stream, first, nnoise, prec, max_batch=0,
@@ -534,6 +544,16 @@ class Context:
         x = self.vector(nrhs, FP64) if x is None else x
         its, rel, rc = mpmc_solve(self.handle, b, x, nrhs, defl, net, restart, tol, inner_prec, max_outer)
         return x, its, rel
+
+    def solve_pairs(self, b, nrhs, max_snap, defl=None, restart=50, tol=1e-8, inner_prec=FP32, max_outer=100):
+        """Solve and return (x, R, E, nsnap): R/E hold nsnap batches of (residual, error) pairs."""
+        x = self.vector(nrhs, FP64)
+        vb = mpmc_vector_bytes(self.handle, nrhs, FP32)
+        R = self.torch.empty(vb * max_snap, dtype=self.torch.uint8, device="cuda")
+        E = self.torch.empty_like(R)
+        ns, its, rel = mpmc_solve_pairs(self.handle, b, x, nrhs, defl, restart, tol, inner_prec, max_outer, R, E,
+                                        max_snap)
+        return x, R, E, ns, vb
 
     def level(self, upper, lower, defl, theta, seed, stream, first, nnoise, prec=FP64, max_batch=0,
               solve_tol=1e-8, solve_restart=50, solve_inner_prec=FP64, net=None):

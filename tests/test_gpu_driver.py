@@ -42,6 +42,9 @@ def test_learned_form_same_estimate(ctx):
     e0 = driver.estimate(ctx, p, torch.cuda.synchronize)
     e1 = driver.estimate(ctx, plan(solve_inner_prec=mpmc.FP32, learned=True, net_batches=2, net_pairs=16,
                                    net_steps=10), torch.cuda.synchronize)
+    e2 = driver.estimate(ctx, plan(solve_inner_prec=mpmc.FP32, learned=True, net_source="random", net_batches=2,
+                                   net_pairs=16, net_steps=10), torch.cuda.synchronize)
+    assert abs(e2.value - e0.value) < 1e-6
     assert "net_loss" in e1.info and e1.info["net_loss"][1] < e1.info["net_loss"][0]
     # same noise, solves to 1e-10: the solve-term samples agree to ~1e-10 n
     assert np.max(np.abs(e1.levels[0].samples - e0.levels[0].samples)) < 1e-7

@@ -191,3 +191,24 @@ def test_level_samples_unchanged_by_net(f44, trained):
                            solve_inner_prec=FP32, net=trained[0])
     # |eta| ~ sqrt(n); solution error <= 1e-10 relative, so samples agree to ~1e-10 n
     assert np.max(np.abs(X1 - X0)) < 1e-8 * op.n
+
+
+def test_solve_pairs_are_residual_error_pairs(f44):
+    """mpmc_solve_pairs: batch k holds r_k = b - M x_k and e_k = x* - x_k, so
+    M e_k = r_k up to the solve tolerance; the solution equals mpmc_solve's."""
+    dims, kappa, U, op, ctx, T = f44
+    N = 8
+    b = ctx.noise(21, 0, 0, N, FP64)
+    x, R, E, ns, vb = ctx.solve_pairs(b, N, 4, tol=1e-10, restart=20, inner_prec=FP32)
+    assert ns >= 2
+    X = host(ctx.unpack(x, N))
+    x2, _, _ = ctx.solve(b, N, restart=20, tol=1e-10, inner_prec=FP32)
+    assert rel(X, host(ctx.unpack(x2, N))) < 1e-12
+    B = z4_noise_batch(21, 0, 0, N, op.n)
+    for k in range(ns):
+        Rk = host(ctx.unpack(R[k * vb:(k + 1) * vb], N, FP32))
+        Ek = host(ctx.unpack(E[k * vb:(k + 1) * vb], N, FP32))
+        if k == 0:
+            assert rel(Rk, B) < 1e-7 and rel(Ek, X) < 1e-6
+        scale = np.linalg.norm(Rk)
+        assert np.linalg.norm(op(Ek) - Rk) < 1e-5 * scale + 1e-9 * np.linalg.norm(B)
