@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="8x4",
                     help="8x4 (default, the metric's configuration) or the larger parity configurations")
     ap.add_argument("--theta", choices=["I", "g5"], default="I")
+    ap.add_argument("--solve-pp", action="store_true",
+                    help="main solves of the mixed and plain forms as polynomial-preconditioned GMRES (p_in)")
     ap.add_argument("--net-source", choices=["random", "solve"], default="solve",
                     help="training pairs of the learned form: (M e, e) or snapshots of training solves")
     ap.add_argument("--no-plain", action="store_true", help="skip the FP64 comparison form")
@@ -152,7 +154,7 @@ def main():
                        defl_candidates=max(40, W["nev"] + 20), defl_m=112 if W["nev"] <= 40 else 136,
                        defl_pin_degree=8, theta=mpmc.THETA[a.theta], max_batch=W["max_batch"],
                        poly_prec=mpmc.FP32, solve_inner_prec=mpmc.PREC[W.get("solve_prec", "fp32")],
-                       solve_tol=1e-8, solve_restart=50, net_pairs=W["net_pairs"])
+                       solve_tol=1e-8, solve_restart=50, net_pairs=W["net_pairs"], solve_pp=a.solve_pp)
     sync = torch.cuda.synchronize
 
     if a.calibrate_copy:

@@ -306,6 +306,19 @@ int mpmc_net_loss_grad(mpmc_net *net, const void *R, const void *E, int npairs,
 int mpmc_net_train(mpmc_net *net, const void *R, const void *E, int npairs, int steps,
                    double lr, double *loss_host);
 
+/* Polynomial-preconditioned deflated solve (Sec. 8, the paper's solver):
+ * as mpmc_solve, with each inner cycle right-preconditioned GMRES on M p(M)
+ * and the correction p(M) V y, for a single or double polynomial pp of this
+ * context (typically a low-degree GMRES polynomial).  The outer loop still
+ * tests the true FP64 residual.  Synchronises. */
+int mpmc_solve_pp(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl,
+                  const mpmc_poly *pp, int restart, double tol, int inner_prec, int max_outer,
+                  int *iters_host, double *relres_host);
+/* Polynomial preconditioner used by the main solves inside mpmc_level_estimate
+ * when no network is given (NULL: none, the default).  The context keeps the
+ * pointer: the caller keeps pp alive while it is set. */
+int mpmc_set_level_solve_poly(mpmc_ctx *ctx, const mpmc_poly *pp);
+
 /* mpmc_solve (no network) that also records training pairs for the learned
  * preconditioner from the solve itself: at the start of each outer cycle k <
  * max_snap, batch k of R_snap receives r_k = b - M x_k and batch k of E_snap

@@ -51,6 +51,8 @@ struct mpmc_ctx {
     std::vector<TimedLaunch> timed;
     // Wilson kernel variant per (nrhs, prec), set by mpmc_autotune / mpmc_tune_set
     std::map<std::pair<int, int>, int> tune;
+    // polynomial right preconditioner of the solves inside mpmc_level_estimate
+    const struct mpmc_poly *level_pp = nullptr;
 };
 
 struct mpmc_poly {
@@ -361,4 +363,4 @@ struct SolveSnap {
 };
 int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl, const mpmc_net *net,
                    int restart, double tol, int inner_prec, int max_outer, int *iters, double *relres_host,
-                   SolveSnap *snap = nullptr);
+                   SolveSnap *snap = nullptr, const mpmc_poly *pp = nullptr);

@@ -97,7 +97,7 @@ MPMC_API int mpmc_level_estimate(mpmc_ctx *ctx, const mpmc_poly *upper, const mp
             std::vector<double> rr(nb);
             RET_IF(launch_noise(ctx, seed, stream, first + b0, nb, MPMC_FP64, eta64));
             RET_IF(solve_internal(ctx, eta64, yv, nb, defl, net, solve_restart, solve_tol, solve_inner_prec, 400, &its,
-                                  rr.data()));
+                                  rr.data(), nullptr, net ? nullptr : ctx->level_pp));
             RET_IF(blas_dot(ctx, eta64, yv, nb, MPMC_FP64, th, (double *)acc));
         }
         const mpmc_poly *parts[2] = {upper, lower};

@@ -9,6 +9,8 @@
 // iteration serve the whole batch, and the per-rhs Hessenberg/Givens state
 // lives on the device.  With a learned preconditioner N the inner cycle is
 // flexible GMRES (z_j = N v_j, Arnoldi on M z_j, correction sum_j y_j z_j).
+// With a polynomial preconditioner p (the paper's PP-GMRES, Sec. 8) the inner
+// cycle is right-preconditioned GMRES on M p(M) and the correction is p(M) V y.
 // With a deflation set, x starts at Z Lambda^-1 U^H b and
 // each restart adds Z Lambda^-1 U^H r (projection of the small eigen-components).
 #include <algorithm>
@@ -44,7 +46,9 @@ __global__ void k_init_g(double2 *g, int m, int N, const double2 *rn2) {
 
 int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl *defl, const mpmc_net *net,
                    int m, double tol, int inner_prec, int max_outer, int *iters_out, double *relres_host,
-                   SolveSnap *snap) {
+                   SolveSnap *snap, const mpmc_poly *pp) {
+    if (pp && net) return set_err(ctx, MPMC_EINVAL, "mpmc_solve: polynomial and learned preconditioner are exclusive");
+    if (pp && pp->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "mpmc_solve: polynomial belongs to another context");
     if (net && net_context(net) != ctx) return set_err(ctx, MPMC_ESTATE, "mpmc_solve: network belongs to another context");
     if (net && inner_prec != MPMC_FP32)
         return set_err(ctx, MPMC_EINVAL, "mpmc_solve: the learned preconditioner runs with FP32 inner cycles only");
@@ -63,6 +67,8 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
     void *Zb = net ? S.get(vbi * m) : nullptr;   // flexible GMRES: preconditioned basis z_j = N v_j
     void *w = S.get(vbi);
     void *e = S.get(vbi);
+    void *tp = pp ? S.get(vbi) : nullptr;   // p(M) v_j (polynomial right preconditioning)
+    void *tq = pp && half ? S.get(vbi) : nullptr;   // FP32 copy of an FP16S basis vector
     double *H = (double *)S.get(sizeof(double2) * (size_t)(m + 1) * (m + 1) * N);
     double *h2 = (double *)S.get(sizeof(double2) * (size_t)(m + 1) * N);
     double *cs = (double *)S.get(sizeof(double2) * (size_t)2 * m * N);
@@ -73,7 +79,7 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
     double *dc = defl && defl->k ? (double *)S.get(sizeof(double2) * (size_t)defl->k * N) : nullptr;
     void *xsnap = snap ? S.get(vb64 * (size_t)snap->max) : nullptr;   // FP64 iterates x_k of the record
     if (snap && !xsnap) return MPMC_ENOMEM;
-    if (!r || !V || (net && !Zb) || !w || !e || !H || !h2 || !cs || !g || !y || !res || !sc || (defl && defl->k && !dc))
+    if (!r || !V || (net && !Zb) || (pp && !tp) || (pp && half && !tq) || !w || !e || !H || !h2 || !cs || !g || !y || !res || !sc || (defl && defl->k && !dc))
         return MPMC_ENOMEM;
     double *nrm = sc, *scale = sc + 2 * N;
 
@@ -167,7 +173,27 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
                 RET_IF(net_apply_internal(ctx, cnet, vj, zj, N));
                 opin = zj;
             }
-            if (half) {
+            if (pp) {   // w = M p(M) v_j
+                const void *src = vj;
+                if (half) {
+                    RET_IF(blas_convert(ctx, vj, MPMC_FP16S, tq, MPMC_FP32, N));
+                    src = tq;
+                }
+                RET_IF(poly_apply_internal(ctx, pp, src, tp, N, pw));
+                RET_IF(wilson_launch_full(ctx, tp, nullptr, w, nullptr, N, pw, make_double2(0, 0),
+                                          make_double2(1, 0), make_double2(0, 0), 0, 0));
+                if (half) {
+                    RET_IF(blas_multi_dot_h(ctx, V, vbb, j + 1, w, N, Hcol, 0));
+                    RET_IF(blas_multi_axpy_h(ctx, V, vbb, j + 1, w, N, Hcol, N, -1.0, nullptr));
+                    RET_IF(blas_multi_dot_h(ctx, V, vbb, j + 1, w, N, h2, 0));
+                    RET_IF(blas_multi_axpy_h(ctx, V, vbb, j + 1, w, N, h2, N, -1.0, nrm));
+                } else {
+                    RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, pw, Hcol, 0, 0));
+                    RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, pw, Hcol, N, -1.0, nullptr));
+                    RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, pw, h2, 0, 0));
+                    RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, pw, h2, N, -1.0, nrm));
+                }
+            } else if (half) {
                 RET_IF(wilson_apply_h2f(ctx, vj, w, N));
                 RET_IF(blas_multi_dot_h(ctx, V, vbb, j + 1, w, N, Hcol, 0));
                 RET_IF(blas_multi_axpy_h(ctx, V, vbb, j + 1, w, N, Hcol, N, -1.0, nullptr));
@@ -206,6 +232,10 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
             RET_IF(blas_multi_axpy_h(ctx, V, vbb, jdone, e, N, y, N, 1.0, nullptr));
         else
             RET_IF(blas_multi_axpy(ctx, cnet ? Zb : V, vstride, N, jdone, e, N, inner_prec, y, N, 1.0, nullptr));
+        if (pp) {   // correction p(M) V y
+            RET_IF(poly_apply_internal(ctx, pp, e, tp, N, pw));
+            HIP_OR_RET(ctx, hipMemcpyAsync(e, tp, vbi, hipMemcpyDeviceToDevice, ctx->stream));
+        }
         // x += e (in FP64)
         RET_IF(blas_convert(ctx, e, pw, r, MPMC_FP64, N));
         RET_IF(blas_axpby(ctx, r, x, N, MPMC_FP64, make_double2(1, 0), make_double2(1, 0)));
@@ -238,7 +268,7 @@ MPMC_API int mpmc_solve_pairs(mpmc_ctx *ctx, const void *b, void *x, int nrhs, c
     if (defl && defl->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "deflation set belongs to another context");
     SolveSnap sn{R_snap, E_snap, max_snap, 0};
     const int rc = solve_internal(ctx, b, x, nrhs, defl, nullptr, restart, tol, inner_prec, max_outer, iters_host,
-                                  relres_host, &sn);
+                                  relres_host, &sn, nullptr);
     *nsnap_host = sn.count;
     return rc;
 }
@@ -250,5 +280,25 @@ MPMC_API int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const m
         return set_err(ctx, MPMC_EINVAL, "mpmc_solve: bad argument");
     if (b == x) return set_err(ctx, MPMC_EINVAL, "mpmc_solve: b and x must not alias");
     if (defl && defl->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "deflation set belongs to another context");
-    return solve_internal(ctx, b, x, nrhs, defl, net, restart, tol, inner_prec, max_outer, iters_host, relres_host);
+    return solve_internal(ctx, b, x, nrhs, defl, net, restart, tol, inner_prec, max_outer, iters_host, relres_host,
+                          nullptr, nullptr);
+}
+
+MPMC_API int mpmc_solve_pp(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl, const mpmc_poly *pp,
+                           int restart, double tol, int inner_prec, int max_outer, int *iters_host,
+                           double *relres_host) {
+    if (!ctx) return MPMC_EINVAL;
+    if (!b || !x || !pp || nrhs < 1 || restart < 1 || restart > 400 || !(tol > 0) || max_outer < 1)
+        return set_err(ctx, MPMC_EINVAL, "mpmc_solve_pp: bad argument");
+    if (b == x) return set_err(ctx, MPMC_EINVAL, "mpmc_solve_pp: b and x must not alias");
+    if (defl && defl->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "deflation set belongs to another context");
+    return solve_internal(ctx, b, x, nrhs, defl, nullptr, restart, tol, inner_prec, max_outer, iters_host, relres_host,
+                          nullptr, pp);
+}
+
+MPMC_API int mpmc_set_level_solve_poly(mpmc_ctx *ctx, const mpmc_poly *pp) {
+    if (!ctx) return MPMC_EINVAL;
+    if (pp && pp->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "polynomial belongs to another context");
+    ctx->level_pp = pp;
+    return MPMC_OK;
 }

@@ -64,6 +64,7 @@ class Plan:
     net_source: str = "solve"            # "solve": snapshots of training solves; "random": (M e, e), e Z(4)
     net_snaps: int = 4                   # outer cycles recorded per training solve ("solve" source)
     overlap_setup: bool = True           # build polynomials (and train the net) on side streams
+    solve_pp: bool = False               # precondition the main solves with p_in (Sec. 8's PP-GMRES)
     autotune: bool = True                # time the Wilson kernel variants for the level batches once per context
 
 
@@ -132,6 +133,7 @@ def build_deflation(ctx, plan: Plan):
     D = ctx.deflate(pin, plan.seed, 0x200, plan.defl_m, max(plan.nev, plan.defl_candidates), plan.accept_tol,
                     plan.real_tol)
     D.keep(plan.nev)
+    D.p_in = pin
     return D
 
 
@@ -233,6 +235,16 @@ def autotune_levels(ctx, plan: Plan):
             done.add((nb, prec))
 
 
+def solve_preconditioner(ctx, plan: Plan, defl):
+    """p_in of the deflation build (degree plan.defl_pin_degree), or a fresh GMRES
+    polynomial of that degree, when the plan asks for PP-GMRES main solves."""
+    if not plan.solve_pp:
+        return None
+    if defl is not None and getattr(defl, "p_in", None) is not None:
+        return defl.p_in
+    return ctx.gmres_poly(plan.seed, 0x1FF, max(plan.defl_pin_degree, 1) + 1)
+
+
 def total_mvps(ctx):
     """Operator applications issued by ctx and its side contexts."""
     return ctx.mvps + sum(c.mvps for c, _ in ctx._side.values())
@@ -296,7 +308,12 @@ def estimate(ctx, plan: Plan, sync=None, net=None) -> Estimate:
         info = dict(net_loss=[float(hist[0]), float(hist[-1])])
     sync()
     t1 = time.perf_counter()
-    levels = run_levels(ctx, plan, polys, defl, net=net if plan.learned else None)
+    pp = solve_preconditioner(ctx, plan, defl) if not plan.learned else None
+    ctx.set_level_solve_poly(pp)
+    try:
+        levels = run_levels(ctx, plan, polys, defl, net=net if plan.learned else None)
+    finally:
+        ctx.set_level_solve_poly(None)
     sync()
     t2 = time.perf_counter()
     est, se = combine(levels)

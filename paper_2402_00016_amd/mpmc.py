@@ -70,6 +70,8 @@ _SIGS = {
     "mpmc_net_apply": ([_vp, _vp, _vp, _i], _i),
     "mpmc_net_loss_grad": ([_vp, _vp, _vp, _i, _pd, _vp], _i),
     "mpmc_net_train": ([_vp, _vp, _vp, _i, _i, _d, _vp], _i),
+    "mpmc_solve_pp": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
+    "mpmc_set_level_solve_poly": ([_vp, _vp], _i),
     "mpmc_solve_pairs": ([_vp, _vp, _vp, _i, _vp, _i, _d, _i, _i, _vp, _vp, _i, _pi, _pi, _vp], _i),
     "mpmc_level_estimate": ([_vp, _vp, _vp, _vp, _i, _u64, _u32, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp,
                              _pu64], _i),
@@ -254,6 +256,18 @@ def mpmc_solve(ctx, b, x, nrhs, defl=None, net=None, restart=50, tol=1e-8, inner
     if rc != ENOCONV or raise_on_noconv:
         _check(rc, ctx)
     return its.value, rel, rc
+
+
+def mpmc_solve_pp(ctx, b, x, nrhs, defl, pp, restart=50, tol=1e-8, inner_prec=FP64, max_outer=100):
+    its = ctypes.c_int()
+    rel = np.zeros(nrhs)
+    _check(_L.mpmc_solve_pp(ctx, _ptr(b), _ptr(x), int(nrhs), _h(defl), _h(pp), int(restart), float(tol),
+                            int(inner_prec), int(max_outer), ctypes.byref(its), rel.ctypes.data), ctx)
+    return its.value, rel
+
+
+def mpmc_set_level_solve_poly(ctx, pp):
+    _check(_L.mpmc_set_level_solve_poly(ctx, _h(pp)), ctx)
 
 
 def mpmc_solve_pairs(ctx, b, x, nrhs, defl, restart, tol, inner_prec, max_outer, R, E, max_snap):
@@ -544,6 +558,16 @@ class Context:
         x = self.vector(nrhs, FP64) if x is None else x
         its, rel, rc = mpmc_solve(self.handle, b, x, nrhs, defl, net, restart, tol, inner_prec, max_outer)
         return x, its, rel
+
+    def solve_pp(self, b, nrhs, pp, defl=None, restart=50, tol=1e-8, inner_prec=FP64, max_outer=100, x=None):
+        x = self.vector(nrhs, FP64) if x is None else x
+        its, rel = mpmc_solve_pp(self.handle, b, x, nrhs, defl, pp, restart, tol, inner_prec, max_outer)
+        return x, its, rel
+
+    def set_level_solve_poly(self, pp):
+        """Polynomial preconditioner of the main solves inside level estimates (None: none)."""
+        self._level_pp = pp          # keep the handle alive while the context uses it
+        mpmc_set_level_solve_poly(self.handle, pp)
 
     def solve_pairs(self, b, nrhs, max_snap, defl=None, restart=50, tol=1e-8, inner_prec=FP32, max_outer=100):
         """Solve and return (x, R, E, nsnap): R/E hold nsnap batches of (residual, error) pairs."""

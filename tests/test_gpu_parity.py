@@ -443,3 +443,39 @@ def test_solve_fp16_basis_matches_fp32(N):
     j = N - 1
     bj = z4_noise(6, 0, j, op.n)
     assert np.linalg.norm(bj - op(X16[j])) / np.linalg.norm(bj) <= 1.05e-9
+
+
+# ------------------------------------------------- PP-GMRES main solves --
+
+@pytest.mark.parametrize("inner", [FP64, FP32, FP16S])
+def test_pp_solve_matches_plain_solve(inner):
+    """GMRES on M p(M) (right-preconditioned, correction p(M) V y) reaches the
+    same true FP64 residual and solution, in fewer inner iterations."""
+    dims, kappa = (8, 8, 8, 8), 0.120
+    U = inputs.gauge_links(dims, 0.5, seed=2)
+    ctx = mpmc.Context(dims, kappa, U)
+    op = WilsonOp(dims, kappa, U)
+    N = 20
+    pp = ctx.gmres_poly(2, 0x1FF, 9)
+    b = ctx.noise(8, 0, 0, N, FP64)
+    x0, it0, r0 = ctx.solve(b, N, restart=50, tol=1e-9, inner_prec=inner)
+    x1, it1, r1 = ctx.solve_pp(b, N, pp, restart=50, tol=1e-9, inner_prec=inner)
+    assert np.all(r0 <= 1e-9) and np.all(r1 <= 1e-9)
+    X0, X1 = host(ctx.unpack(x0, N)), host(ctx.unpack(x1, N))
+    assert rel(X1, X0) < 5e-9
+    assert it1 < it0
+    bj = z4_noise(8, 0, 7, op.n)
+    assert np.linalg.norm(bj - op(X1[7])) / np.linalg.norm(bj) <= 1.05e-9
+
+
+def test_level_with_pp_solves_unchanged(f44):
+    dims, kappa, U, op, ctx = f44
+    p = ctx.gmres_poly(1, 0x100, 9)
+    pp = ctx.gmres_poly(1, 0x1FF, 5)
+    X0, c0, m0 = ctx.level(None, p, None, mpmc.THETA_I, 3, 0, 0, 12, prec=FP64, solve_tol=1e-11)
+    ctx.set_level_solve_poly(pp)
+    try:
+        X1, c1, m1 = ctx.level(None, p, None, mpmc.THETA_I, 3, 0, 0, 12, prec=FP64, solve_tol=1e-11)
+    finally:
+        ctx.set_level_solve_poly(None)
+    assert np.max(np.abs(X1 - X0)) < 1e-9 * op.n
