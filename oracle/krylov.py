@@ -90,6 +90,35 @@ def leja_order(theta):
     return cand[chosen]
 
 
+def log10_pof(roots):
+    """log10 of the product of other factors of each root,
+    pof(k) = prod_{i != k} |1 - theta_k / theta_i|, the growth of the GMRES
+    residual polynomial with theta_k removed, evaluated at theta_k."""
+    th = np.asarray(roots, dtype=np.complex128)
+    out = np.zeros(len(th))
+    for k in range(len(th)):
+        others = np.delete(th, k)
+        out[k] = np.sum(np.log10(np.abs(1.0 - th[k] / others)))
+    return out
+
+
+def add_roots(roots, log10_threshold=4.0, digits=14.0):
+    """Stabilisation of a high-degree polynomial by added roots (Embree, Loe and
+    Morgan's rule for polynomial preconditioners): every root theta_k with
+    log10 pof(k) > threshold gets ceil((log10 pof(k) - threshold) / digits)
+    extra copies; the extended list is Leja ordered (copies go last, their
+    log-distance to an equal chosen root being -inf).  Returns (roots, added)."""
+    th = np.asarray(roots, dtype=np.complex128)
+    lp = log10_pof(th)
+    extra = []
+    for k in range(len(th)):
+        if lp[k] > log10_threshold:
+            extra.extend([th[k]] * int(np.ceil((lp[k] - log10_threshold) / digits)))
+    if not extra:
+        return leja_order(th), 0
+    return leja_order(np.concatenate([th, np.asarray(extra)])), len(extra)
+
+
 def gmres_residual(H, beta):
     """GMRES least-squares solution y and residual norm from H (d+1, d)."""
     d = H.shape[1]

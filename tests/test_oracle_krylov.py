@@ -147,3 +147,34 @@ def test_double_polynomial_identities(op44):
     op44.matvecs = 0
     poly.apply_poly(op44, D16, x)
     assert op44.matvecs == 255 == D16.degree
+
+
+def test_pof_hand_example():
+    # roots 1, 2, 4: pof(1) = (1/2)(3/4), pof(2) = 1 * (1/2), pof(4) = 3 * 1
+    lp = krylov.log10_pof([1.0, 2.0, 4.0])
+    assert np.allclose(lp, np.log10([0.375, 0.5, 3.0]), rtol=0, atol=1e-14)
+    roots, added = krylov.add_roots([1.0, 2.0, 4.0])
+    assert added == 0 and np.allclose(np.sort(roots.real), [1, 2, 4])
+
+
+def test_add_roots_outlier():
+    """20 roots on the circle |z - 1| = 1/2 and one at 50: only the outlier's
+    product of other factors is large; it is computed here directly as a
+    product (not through the oracle's log sum)."""
+    ring = 1.0 + 0.5 * np.exp(2j * np.pi * (np.arange(20) + 0.25) / 20)
+    th = np.concatenate([ring, [50.0]])
+    direct = abs(np.prod(1.0 - 50.0 / ring))
+    want = int(np.ceil((np.log10(direct) - 4.0) / 14.0))
+    assert want >= 2
+    ext, added = krylov.add_roots(th)
+    assert added == want and len(ext) == len(th) + want
+    assert np.sum(np.isclose(ext, 50.0)) == want + 1
+    assert np.all(np.isclose(ext[-want:], 50.0))      # exact copies are chosen last
+    for k in range(20):                               # ring roots stay below the threshold
+        assert np.log10(abs(np.prod(np.delete(1.0 - ring[k] / th, k)))) < 4
+    # the extended residual polynomial is pi(z) (1 - z/50)^want, and 1 - z p(z) = pi(z)
+    z = np.array([0.3 + 0.2j, 1.7 - 0.4j, 10.0])
+    pi_ext = np.prod(1.0 - z[:, None] / ext[None, :], axis=1)
+    pi_ref = np.prod(1.0 - z[:, None] / th[None, :], axis=1) * (1.0 - z / 50.0) ** want
+    assert np.allclose(pi_ext, pi_ref, rtol=1e-10)
+    assert np.allclose(1.0 - z * poly.eval_p(ext, z), pi_ext, rtol=1e-8)
