@@ -175,6 +175,16 @@ int mpmc_poly_info(const mpmc_poly *p, int *d, int *d_inner, int *degree, int *m
  * deflation coefficients p_l(lambda_i) - p_{l+1}(lambda_i) (Sec. 7). */
 int mpmc_poly_eval(const mpmc_poly *p, const double *lam_host, double *out_host, int k);
 void mpmc_poly_destroy(mpmc_poly *p);
+/* Stabilise a high-degree polynomial by added roots (for p of degree ~200 and
+ * beyond, where the product form loses accuracy): every root theta_k whose
+ * product of other factors pof(k) = prod_{i != k} |1 - theta_k/theta_i| has
+ * log10 pof(k) > log10_threshold (4 is the usual choice) gets
+ * ceil((log10 pof(k) - log10_threshold) / digits) extra copies (digits: 14);
+ * the extended list is Leja ordered (copies last) and replaces p's roots, so
+ * p's degree grows by *added_host.  The residual polynomial becomes
+ * pi(z) prod_k (1 - z/theta_k)^{copies_k} and 1 - z p(z) = pi(z) still holds
+ * for the new roots.  Computed on the device.  Synchronises. */
+int mpmc_poly_add_roots(mpmc_poly *p, double log10_threshold, double digits, int *added_host);
 
 /* y = p(M) x for nrhs internal-layout vectors of precision prec (FP64 or FP32):
  * y = sum_k w_k / theta_k, w_1 = x, w_{k+1} = w_k - M w_k / theta_k (Sec. 3,

@@ -329,6 +329,8 @@ int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, doub
 int dense_hess_eigs(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, double *ev_dev, double *info_dev);
 int dense_inverse_iteration(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, const double *mu_dev, int k,
                             double *Y_dev);
+int dense_add_roots(mpmc_ctx *ctx, const double *roots_dev, int d, double thr, double digits, int max_out,
+                    double *out_dev, int *count_dev);
 int dense_givens_step(mpmc_ctx *ctx, double *H, int ldc, int j, int N, double *cs, double *g, double *res);
 int dense_backsolve(mpmc_ctx *ctx, const double *H, int ldc, int k, int N, const double *g, double *y);
 

@@ -464,6 +464,56 @@ __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh,
     }
 }
 
+// ----------------------------------------------------- added roots --
+// Stabilisation of a high-degree polynomial (the added-roots rule for
+// polynomial preconditioners): root k with log10 pof(k) > thr, pof(k) =
+// prod_{i != k} |1 - theta_k / theta_i|, gets ceil((log10 pof(k) - thr) /
+// digits) extra copies; the extended list is Leja ordered.  One wavefront.
+// out, tmp: max_out entries; S, taken: max_out entries; count[0] = new size
+// (or -1 when it would exceed max_out).
+__global__ __launch_bounds__(64) void k_add_roots(const double2 *in, int d, double thr, double digits, int max_out,
+                                                  double2 *out, double2 *tmp, double *S, int *taken, int *count) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ int s_total;
+    for (int k = tid; k < d; k += nt) {
+        const zd tk = ld(in, k);
+        double lp = 0.0;
+        for (int i = 0; i < d; ++i) {
+            if (i == k) continue;
+            const zd q = mk(1.0, 0.0) - zdiv(tk, ld(in, i));
+            lp += log10(zabs(q));
+        }
+        taken[k] = lp > thr ? (int)ceil((lp - thr) / digits) : 0;   // copies of root k
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int total = d;
+        for (int k = 0; k < d; ++k) total += taken[k];
+        s_total = total <= max_out ? total : -1;
+        if (s_total > 0) {
+            for (int k = 0; k < d; ++k) out[k] = in[k];
+            int pos = d;
+            for (int k = 0; k < d; ++k)
+                for (int c = 0; c < taken[k]; ++c) out[pos++] = in[k];
+        }
+        count[0] = s_total;
+    }
+    __syncthreads();
+    if (s_total > 0) leja_order(out, s_total, tmp, S, taken);
+}
+
+int dense_add_roots(mpmc_ctx *ctx, const double *roots_dev, int d, double thr, double digits, int max_out,
+                    double *out_dev, int *count_dev) {
+    double2 *work = (double2 *)ws_get(ctx, WS_DENSE, (size_t)max_out * (sizeof(double2) + sizeof(double) + sizeof(int)) + 256);
+    if (!work) return MPMC_ENOMEM;
+    double *S = (double *)(work + max_out);
+    int *taken = (int *)(S + max_out);
+    k_add_roots<<<1, 64, 0, ctx->stream>>>((const double2 *)roots_dev, d, thr, digits, max_out, (double2 *)out_dev,
+                                           work, S, taken, count_dev);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
 static size_t lds_limit(mpmc_ctx *ctx) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess) v = 65536;

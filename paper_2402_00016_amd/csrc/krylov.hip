@@ -11,6 +11,8 @@
 #include <cmath>
 #include <complex>
 
+#include <algorithm>
+
 #include "common.h"
 
 // ------------------------------------------------------------ Arnoldi --
@@ -167,6 +169,32 @@ MPMC_API int mpmc_poly_create(mpmc_ctx *ctx, const double *roots_host, int d, co
     p->roots.assign(roots_host, roots_host + 2 * d);
     p->inner = inner;
     *out = p;
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_poly_add_roots(mpmc_poly *p, double log10_threshold, double digits, int *added_host) {
+    if (!p || !p->ctx) return MPMC_EINVAL;
+    mpmc_ctx *ctx = const_cast<mpmc_ctx *>(p->ctx);
+    if (!(digits > 0) || !std::isfinite(log10_threshold))
+        return set_err(ctx, MPMC_EINVAL, "mpmc_poly_add_roots: bad argument");
+    const int d = p->d, max_out = std::min(2 * d + 16, 1200);
+    Scratch S(ctx);
+    double *in = (double *)S.get(sizeof(double) * 2 * d);
+    double *out = (double *)S.get(sizeof(double) * 2 * max_out);
+    int *cnt = (int *)S.get(sizeof(int) * 4);
+    if (!in || !out || !cnt) return MPMC_ENOMEM;
+    HIP_OR_RET(ctx, hipMemcpyAsync(in, p->roots.data(), sizeof(double) * 2 * d, hipMemcpyHostToDevice, ctx->stream));
+    RET_IF(dense_add_roots(ctx, in, d, log10_threshold, digits, max_out, out, cnt));
+    int total = 0;
+    HIP_OR_RET(ctx, hipMemcpyAsync(&total, cnt, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    if (total < 0) return set_err(ctx, MPMC_EINVAL, "mpmc_poly_add_roots: more than %d roots", max_out);
+    std::vector<double> r(2 * (size_t)total);
+    HIP_OR_RET(ctx, hipMemcpyAsync(r.data(), out, sizeof(double) * 2 * total, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    if (added_host) *added_host = total - d;
+    p->roots = r;
+    p->d = total;
     return MPMC_OK;
 }
 

@@ -51,6 +51,7 @@ _SIGS = {
     "mpmc_poly_info": ([_vp, _pi, _pi, _pi, _pi], _i),
     "mpmc_poly_eval": ([_vp, _vp, _vp, _i], _i),
     "mpmc_poly_destroy": ([_vp], None),
+    "mpmc_poly_add_roots": ([_vp, _d, _d, _pi], _i),
     "mpmc_apply_poly": ([_vp, _vp, _vp, _vp, _i, _i], _i),
     "mpmc_poly_trace": ([_vp, _vp, _i, _pi, _i, _i, _vp, _pi, _pu64], _i),
     "mpmc_deflate": ([_vp, _vp, _u64, _u32, _i, _i, _d, _d, ctypes.POINTER(_vp), _pi], _i),
@@ -372,8 +373,18 @@ class _Handle:
             pass
 
 
+def mpmc_poly_add_roots(handle, log10_threshold=4.0, digits=14.0):
+    added = ctypes.c_int()
+    _check(_L.mpmc_poly_add_roots(handle, float(log10_threshold), float(digits), ctypes.byref(added)), None)
+    return added.value
+
+
 class Poly(_Handle):
     _destroy = staticmethod(mpmc_poly_destroy)
+
+    def add_roots(self, log10_threshold=4.0, digits=14.0):
+        """Added-roots stabilisation (in place); returns the number of roots added."""
+        return mpmc_poly_add_roots(self.handle, log10_threshold, digits)
 
     def __init__(self, handle, owner, inner=None, d_eff=None, relres=None):
         super().__init__(handle, owner)

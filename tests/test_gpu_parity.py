@@ -479,3 +479,39 @@ def test_level_with_pp_solves_unchanged(f44):
     finally:
         ctx.set_level_solve_poly(None)
     assert np.max(np.abs(X1 - X0)) < 1e-9 * op.n
+
+
+# ---------------------------------------------------------- added roots --
+
+def test_add_roots_matches_oracle_synthetic(f44):
+    dims, kappa, U, op, ctx = f44
+    ring = 1.0 + 0.5 * np.exp(2j * np.pi * (np.arange(20) + 0.25) / 20)
+    th = OK.leja_order(np.concatenate([ring, [50.0, 0.02 + 0.01j]]))
+    P = ctx.poly_from_roots(th)
+    added = P.add_roots()
+    ref, radded = OK.add_roots(th)
+    assert added == radded > 0
+    assert np.allclose(P.roots, ref, rtol=0, atol=1e-12)
+    assert P.info["degree"] == len(ref) - 1
+
+
+def test_add_roots_high_degree_gmres_poly():
+    """A GMRES(200) polynomial on the 8^4 field: the device rule matches the
+    oracle's on the same roots, and the stabilised p still satisfies
+    pi = 1 - M p on a vector (FP64)."""
+    dims, kappa = (8, 8, 8, 8), 0.120
+    U = inputs.gauge_links(dims, 0.5, seed=2)
+    ctx = mpmc.Context(dims, kappa, U)
+    op = WilsonOp(dims, kappa, U)
+    P = ctx.gmres_poly(2, 0x105, 200)
+    th = P.roots.copy()
+    added = P.add_roots()
+    ref, radded = OK.add_roots(th)
+    assert added == radded
+    assert _match_sets(P.roots, ref) < 1e-10 * np.abs(ref).max() and len(P.roots) == len(ref)
+    assert np.allclose(P.roots, ref, rtol=0, atol=1e-10 * np.abs(ref).max())
+    x = ctx.noise(3, 2, 0, 1, FP64)
+    y = host(ctx.unpack(ctx.apply_poly(P, x, 1, FP64), 1))[0]
+    xh = z4_noise(3, 2, 0, op.n)
+    pi_ref = OP.apply_pi(op, ref, xh)
+    assert rel(xh - op(y), pi_ref) < 1e-8 * max(1.0, np.linalg.norm(xh) / max(np.linalg.norm(pi_ref), 1e-300))
