@@ -55,3 +55,14 @@ def test_driver_identity_weights_match_oracle():
     w = driver.net_identity_weights()
     assert w.size == mpmc.mpmc_net_n_params() == ON.n_params()
     assert np.array_equal(w, ON.identity_theta())
+
+
+def test_sweep_relative_variance_definitions():
+    """eq. 3 (ratio of configuration-averaged variances) and eq. 4 (base-10
+    log average) on two configurations with hand-computed values."""
+    from paper_2402_00016_amd import sweep
+    per = [{"ns": 10.0, 4: 1.0}, {"ns": 1000.0, 4: 10.0}]
+    row = sweep.summarize(per, [4])[0]
+    assert abs(row["rel_var"] - (11.0 / 2) / (1010.0 / 2)) < 1e-15
+    assert abs(row["log_avg_rel_var"] - 10 ** -1.5) < 1e-15
+    assert abs(sweep.sample_var([1.0, 3.0]) - 2.0) < 1e-15
