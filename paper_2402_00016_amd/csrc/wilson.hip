@@ -9,14 +9,17 @@
 // [site][spin*3+colour][rhs]: the lanes of a wavefront read consecutive
 // right-hand sides of the same site, so every spinor load is one contiguous
 // 64-lane access.  When the batch size is a multiple of 64 every wavefront
-// sits on a single site ("uniform" kernels): the neighbour indices and the
-// SU(3) links are then wave-uniform and are fetched with scalar loads into
-// SGPRs, once per wavefront instead of once per lane, which also keeps them
-// out of the vector register file.  Each hop works on half spinors: the rank-2
-// projector (1 +- gamma_mu) maps the neighbour spinor to two colour vectors,
-// the link multiplies those two, and the result is expanded back.
-// Workgroups are numbered so that each XCD sweeps one contiguous range of
-// sites (stencil neighbours stay in that XCD's L2).
+// sits on a single site ("uniform" kernels): the neighbour indices are
+// wave-uniform (scalar loads), and each SU(3) link is fetched with ONE vector
+// load in which lane i holds dword i of the link, then broadcast to SGPRs
+// with v_readlane at use (one VGPR per link in flight instead of 18-36).
+// Each hop works on half spinors: the rank-2 projector (1 +- gamma_mu) maps
+// the neighbour spinor to two colour vectors, the link multiplies those two
+// (FMA chains in FP32), and the result is expanded back.  Workgroups are
+// numbered so that each XCD sweeps one contiguous range of tiles.  The
+// uniform kernel has four variants (occupancy target x traversal order) that
+// the autotuner chooses between; they compute identical bits.  FP16S operands
+// can be written out as FP32 (the FP16 Krylov bases of the solves).
 //
 // Kernels:
 //   k_wilson     out = alpha a + beta Theta op(b) [; y += gamma out]
