@@ -6,11 +6,17 @@ Device buffers are torch tensors on the current HIP device (passed as
 ``data_ptr()``), and the context runs on torch's current stream unless another
 stream is given.  If the library is missing this module raises at import time:
 there is no CPU fallback.
+
+torch is imported before the library is opened, so that the process holds one
+HIP runtime: torch's, already loaded, satisfies libmpmc.so's dependency.
+Opening libmpmc.so first would load a second HIP/HSA runtime beside torch's,
+and the one that comes second can find no device.
 """
 import ctypes
 import os
 
 import numpy as np
+import torch  # noqa: F401  (load order, see above)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MPMC_LIB", os.path.join(HERE, "libmpmc.so"))
