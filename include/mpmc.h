@@ -253,24 +253,27 @@ int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl 
                int max_outer, int *iters_host, double *relres_host);
 
 /* ---------------------------------------------------------------- autotuner */
-/* The multi-RHS Wilson kernel (nrhs a multiple of 64) has WILSON variants
- * 0..3 that differ only in how the work is laid out on the GPU, never in the
+/* The multi-RHS Wilson kernel (nrhs a multiple of 64) has six variants
+ * 0..5 that differ only in how the work is laid out on the GPU, never in the
  * arithmetic (results are bit-identical):
- *   bit 0 -- occupancy target: 1 = more wavefronts per SIMD (FP32/FP16S: 3,
- *            FP64: 2), 0 = more registers per wavefront (FP32/FP16S: 2,
- *            FP64: 1);
- *   bit 1 -- traversal: 0 = site-major (a workgroup covers 256/nrhs sites x
- *            nrhs right-hand sides), 1 = 64-wide right-hand-side chunks (a
- *            workgroup covers 4 sites x 64 right-hand sides; all sites of a
- *            chunk before the next chunk).
- * Defaults: variant 1 for FP32/FP16S, 0 for FP64.
+ *   bit 0    -- occupancy target: 1 = more wavefronts per SIMD (FP32/FP16S:
+ *               3, FP64: 2), 0 = more registers per wavefront (FP32/FP16S: 2,
+ *               FP64: 1);
+ *   bits 1-2 -- traversal: 0 = site-major (a workgroup covers 256/nrhs sites
+ *               x nrhs right-hand sides), 1 = 64-wide right-hand-side chunks
+ *               (a workgroup covers 4 sites x 64 right-hand sides; all sites
+ *               of a chunk before the next chunk), 2 = chunks as in 1 with
+ *               the sites of a chunk in 4D-blocked order (blocks of extent 4
+ *               along each direction whose length allows it, lexicographic
+ *               inside and across blocks).
+ * Defaults: variant 5 for FP32/FP16S, 4 for FP64 (blocked traversal).
  * mpmc_autotune times every variant on (nrhs, prec) with scratch vectors of
  * the context (2 warm-up + 5 timed launches each, HIP events) and keeps the
  * fastest for all later Wilson launches on ctx with that (nrhs, prec),
  * including those inside polynomials, solves and level estimates.
  * variant_host (may be NULL) receives the choice (-1 when nrhs is not a
  * multiple of 64: nothing to tune); us_host (may be NULL) receives
- * double[4] microseconds per launch per variant.  Does not count MVPs and
+ * double[6] microseconds per launch per variant.  Does not count MVPs and
  * does not enter mpmc_timing_read.  Synchronises. */
 int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host, double *us_host);
 /* Pin variant (0..3) for (nrhs, prec); -1 restores the default. */

@@ -160,11 +160,16 @@ __global__ __launch_bounds__(256) void k_multiaxpy(VecRef Vb, size_t vstride_b, 
                 const void *vj = (const char *)Vb.d + (size_t)j * vstride_b;
                 const float *vsc = PB == MPMC_FP16S ? (const float *)((const char *)vj + vscale_off) : nullptr;
                 const int vr = vN == 1 ? 0 : r;
+                // all twelve loads first: interleaved with the FMAs the
+                // scheduler reuses one register pair and waits for each load
+                cpx<T> vv[12];
 #pragma unroll
                 for (int k = 0; k < 12; ++k) {
                     auto v = Store<PB>::ld(vj, vsc, (s * 12 + k) * vN + vr, s * vN + vr);
-                    acc[k] = acc[k] + c * mk((T)v.re, (T)v.im);
+                    vv[k] = mk((T)v.re, (T)v.im);
                 }
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = acc[k] + c * vv[k];
             }
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
@@ -241,11 +246,14 @@ __global__ void k_convert(VecRef x, VecRef y, long V, int N) {
         for (int k = 0; k < 12; ++k) d[(s * 12 + k) * N + r] = __floats2half2_rn(v[k].re * inv, v[k].im * inv);
         y.sc[s * N + r] = mx;
     } else {
+        cpx<TY> v[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             auto a = Store<PX>::ld(x.d, x.sc, (s * 12 + k) * N + r, s * N + r);
-            Store<PY>::st(y.d, (s * 12 + k) * N + r, mk((TY)a.re, (TY)a.im));
+            v[k] = mk((TY)a.re, (TY)a.im);
         }
+#pragma unroll
+        for (int k = 0; k < 12; ++k) Store<PY>::st(y.d, (s * 12 + k) * N + r, v[k]);
     }
 }
 
@@ -283,16 +291,20 @@ __global__ __launch_bounds__(256) void k_multidot1(VecRef Vb, long vstride, int 
     for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)NB * 256) {
         cpx<double> wv = ldd<P>(w, e, 0);
         if (theta && (e % 12) >= 6) wv = mk(-wv.re, -wv.im);
+        // loads of the JB vectors issued together (index clamped to the last
+        // vector, its contribution masked) instead of one guarded load each
+        cpx<double> vq[JB];
 #pragma unroll
         for (int q = 0; q < JB; ++q) {
-            const int j = j0 + q;
-            if (j < nv) {
-                VecRef vj;
-                vj.d = (char *)Vb.d + (size_t)j * vstride * sizeof(T) * 2;
-                vj.sc = nullptr;
-                acc[q] = acc[q] + conjmul(ldd<P>(vj, e, 0), wv);
-            }
+            const int j = j0 + q < nv ? j0 + q : nv - 1;
+            VecRef vj;
+            vj.d = (char *)Vb.d + (size_t)j * vstride * sizeof(T) * 2;
+            vj.sc = nullptr;
+            vq[q] = ldd<P>(vj, e, 0);
         }
+#pragma unroll
+        for (int q = 0; q < JB; ++q)
+            if (j0 + q < nv) acc[q] = acc[q] + conjmul(vq[q], wv);
     }
 #pragma unroll
     for (int q = 0; q < JB; ++q) red[q][threadIdx.x] = make_double2(acc[q].re, acc[q].im);
@@ -325,7 +337,23 @@ __global__ __launch_bounds__(256) void k_multiaxpy1(VecRef Vb, long vstride, int
     for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)NB * 256) {
         auto v0 = Store<P>::ld(w.d, nullptr, e, 0);
         cpx<T> acc = mk((T)v0.re, (T)v0.im);
-        for (int j = 0; j < nv; ++j) {
+        // four basis vectors per iteration, their loads issued together
+        int j = 0;
+        for (; j + 4 <= nv; j += 4) {
+            cpx<T> vq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const void *vj = (const char *)Vb.d + (size_t)(j + q) * vstride * sizeof(T) * 2;
+                auto v = Store<P>::ld(vj, nullptr, e, 0);
+                vq[q] = mk((T)v.re, (T)v.im);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double2 hj = h[(long)(j + q) * ldh];
+                acc = acc + mk((T)(sign * hj.x), (T)(sign * hj.y)) * vq[q];
+            }
+        }
+        for (; j < nv; ++j) {
             const double2 hj = h[(long)j * ldh];
             const void *vj = (const char *)Vb.d + (size_t)j * vstride * sizeof(T) * 2;
             auto v = Store<P>::ld(vj, nullptr, e, 0);

@@ -35,6 +35,7 @@ struct mpmc_ctx {
     double *links64;   // canonical [V][4][3][3] complex double
     float *links32;    // same, complex float
     int *nbr;          // [V][8]: forward mu=0..3 then backward mu=0..3; bit 31 = time-boundary sign
+    int *site_order;   // [V]: blocked traversal order of the sites (4D blocks of 4 where the extent allows)
     uint64_t mvps;     // right-hand-side operator applications issued
     std::string err;
     std::vector<WsBuf> ws;      // fixed workspace slots (reduction partials, dense scratch)
@@ -318,7 +319,8 @@ size_t wilson_dot_partial_count(const mpmc_ctx *ctx, int nrhs);
 int wilson_noise_codes(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, uint32_t *codes);
 int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *codes, int nrhs, int prec, double2 c,
                     double2 cnext, int theta, double *partial, int first_step);
-int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, double *out, int accumulate, double sign);
+int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, int prec, double *out, int accumulate,
+                      double sign);
 // timing hooks around one launch (no-ops unless timing is enabled)
 int timing_begin(mpmc_ctx *ctx);
 void timing_end(mpmc_ctx *ctx, int ev0, int prec, double bytes);

@@ -152,6 +152,35 @@ static void build_neighbours(const int L[4], int t_anti, std::vector<int> &nbr) 
     }
 }
 
+// Traversal order of the blocked Wilson kernels: the lattice is cut into 4D
+// blocks (extent 4 along each direction whose length is a multiple of 4,
+// else 2, else 1), blocks in lexicographic order, sites lexicographic inside a
+// block.  Consecutive workgroups then work on compact 4D regions, so the
+// neighbours a wavefront reads were mostly fetched by nearby wavefronts of
+// the same XCD shortly before.
+static void build_site_order(const int L[4], std::vector<int> &order) {
+    int b[4], nb[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        b[mu] = L[mu] % 4 == 0 ? 4 : (L[mu] % 2 == 0 ? 2 : 1);
+        nb[mu] = L[mu] / b[mu];
+    }
+    const long V = (long)L[0] * L[1] * L[2] * L[3];
+    order.resize(V);
+    long q = 0;
+    for (int k3 = 0; k3 < nb[3]; ++k3)
+        for (int k2 = 0; k2 < nb[2]; ++k2)
+            for (int k1 = 0; k1 < nb[1]; ++k1)
+                for (int k0 = 0; k0 < nb[0]; ++k0)
+                    for (int i3 = 0; i3 < b[3]; ++i3)
+                        for (int i2 = 0; i2 < b[2]; ++i2)
+                            for (int i1 = 0; i1 < b[1]; ++i1)
+                                for (int i0 = 0; i0 < b[0]; ++i0) {
+                                    const long x = k0 * b[0] + i0, y = k1 * b[1] + i1, z = k2 * b[2] + i2,
+                                               t = k3 * b[3] + i3;
+                                    order[q++] = (int)(x + L[0] * (y + (long)L[1] * (z + (long)L[2] * t)));
+                                }
+}
+
 MPMC_API int mpmc_create(const int dims[4], double kappa, int t_antiperiodic, const double *links_host,
                          void *stream, mpmc_ctx **out) {
     if (!dims || !links_host || !out) return set_err(nullptr, MPMC_EINVAL, "mpmc_create: null argument");
@@ -173,6 +202,7 @@ MPMC_API int mpmc_create(const int dims[4], double kappa, int t_antiperiodic, co
     c->links64 = nullptr;
     c->links32 = nullptr;
     c->nbr = nullptr;
+    c->site_order = nullptr;
     c->mvps = 0;
     c->ws.resize(WS_NSLOTS);
     c->top = 0;
@@ -186,12 +216,16 @@ MPMC_API int mpmc_create(const int dims[4], double kappa, int t_antiperiodic, co
     for (size_t i = 0; i < nl * 2; ++i) l32[i] = (float)links_host[i];
     std::vector<int> nbr;
     build_neighbours(dims, c->t_antiperiodic, nbr);
+    std::vector<int> order;
+    build_site_order(dims, order);
     hipError_t e = hipMalloc(&c->links64, nl * 16);
     if (e == hipSuccess) e = hipMalloc(&c->links32, nl * 8);
     if (e == hipSuccess) e = hipMalloc(&c->nbr, (size_t)V * 8 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&c->site_order, (size_t)V * sizeof(int));
     if (e == hipSuccess) e = hipMemcpy(c->links64, links_host, nl * 16, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->links32, l32.data(), nl * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(c->nbr, nbr.data(), (size_t)V * 8 * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->site_order, order.data(), (size_t)V * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         set_err(nullptr, MPMC_ENOMEM, "mpmc_create: %s", hipGetErrorString(e));
         mpmc_destroy(c);
@@ -207,6 +241,7 @@ MPMC_API void mpmc_destroy(mpmc_ctx *ctx) {
     if (ctx->links64) hipFree(ctx->links64);
     if (ctx->links32) hipFree(ctx->links32);
     if (ctx->nbr) hipFree(ctx->nbr);
+    if (ctx->site_order) hipFree(ctx->site_order);
     for (auto &b : ctx->ws)
         if (b.ptr) hipFree(b.ptr);
     for (auto &b : ctx->stack)

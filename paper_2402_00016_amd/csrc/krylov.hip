@@ -373,7 +373,7 @@ static int quad_single_fused(mpmc_ctx *ctx, const std::vector<double> &roots, in
         RET_IF(wilson_dot_step(ctx, cur, nxt, codes, nrhs, prec, inv(k), inv(k + 1), theta, part, k == 0));
         cur = nxt;
     }
-    return wilson_dot_finish(ctx, part, nrhs, acc, 1, sign);
+    return wilson_dot_finish(ctx, part, nrhs, prec, acc, 1, sign);
 }
 
 int poly_quad_fused(mpmc_ctx *ctx, const mpmc_poly *p, const void *eta, const uint32_t *codes, int nrhs, int prec,

@@ -17,8 +17,9 @@
 // the neighbour spinor to two colour vectors, the link multiplies those two
 // (FMA chains in FP32), and the result is expanded back.  Workgroups are
 // numbered so that each XCD sweeps one contiguous range of tiles.  The
-// uniform kernel has four variants (occupancy target x traversal order) that
-// the autotuner chooses between; they compute identical bits.  FP16S operands
+// uniform kernel has six variants (occupancy target x three traversal orders,
+// one of them 4D-blocked through a site table) that the autotuner chooses
+// between; they compute identical bits.  FP16S operands
 // can be written out as FP32 (the FP16 Krylov bases of the solves).
 //
 // Kernels:
@@ -325,10 +326,36 @@ __device__ __forceinline__ void apply(const HopData<P> &H, float g, cpx<typename
     }
 }
 
-// acc = sum over the 8 hops (the hopping term H b at (s, r)).  Two HopData
-// buffers alternate: the loads of hop i+1 are in flight while hop i computes.
+// acc = sum over the 8 hops (the hopping term H b at (s, r)), hop i being
+// direction i/2, forward for even i.  D HopData buffers rotate: the loads of
+// hops i+1 .. i+D-1 are in flight while hop i computes.
 #define MPMC_FENCE __builtin_amdgcn_sched_barrier(0)
-template <int P, bool UNI>
+template <int P, bool UNI, int I>
+__device__ __forceinline__ void fetch_hop(const WIn<P> &in, long s, int r, int N, HopData<P> &H) {
+    fetch<P, UNI, I / 2, (I % 2) == 0>(in, s, r, N, H);
+}
+template <int P, bool UNI, int D, int I>
+__device__ __forceinline__ void hop_step(const WIn<P> &in, long s, int r, int N, float g, HopData<P> (&H)[D],
+                                         cpx<typename Store<P>::real> acc[4][3]) {
+    if constexpr (I < 8) {
+        apply<P, UNI, I / 2, (I % 2) == 0>(H[I % D], g, acc);
+        MPMC_FENCE;
+        if constexpr (I + D < 8) {
+            fetch_hop<P, UNI, I + D>(in, s, r, N, H[I % D]);
+            MPMC_FENCE;
+        }
+        hop_step<P, UNI, D, I + 1>(in, s, r, N, g, H, acc);
+    }
+}
+template <int P, bool UNI, int D, int I>
+__device__ __forceinline__ void hop_prologue(const WIn<P> &in, long s, int r, int N, HopData<P> (&H)[D]) {
+    if constexpr (I < D) {
+        fetch_hop<P, UNI, I>(in, s, r, N, H[I]);
+        MPMC_FENCE;
+        hop_prologue<P, UNI, D, I + 1>(in, s, r, N, H);
+    }
+}
+template <int P, bool UNI, int D = 2>
 __device__ __forceinline__ void hopping(const WIn<P> &in, long s, int r, int N, float g,
                                         cpx<typename Store<P>::real> acc[4][3]) {
     using T = typename Store<P>::real;
@@ -336,46 +363,29 @@ __device__ __forceinline__ void hopping(const WIn<P> &in, long s, int r, int N, 
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[sp][c] = mk(T(0), T(0));
-    HopData<P> A, B;
-    fetch<P, UNI, 0, true>(in, s, r, N, A);
-    MPMC_FENCE;
-    fetch<P, UNI, 0, false>(in, s, r, N, B);
-    MPMC_FENCE;
-    apply<P, UNI, 0, true>(A, g, acc);
-    MPMC_FENCE;
-    fetch<P, UNI, 1, true>(in, s, r, N, A);
-    MPMC_FENCE;
-    apply<P, UNI, 0, false>(B, g, acc);
-    MPMC_FENCE;
-    fetch<P, UNI, 1, false>(in, s, r, N, B);
-    MPMC_FENCE;
-    apply<P, UNI, 1, true>(A, g, acc);
-    MPMC_FENCE;
-    fetch<P, UNI, 2, true>(in, s, r, N, A);
-    MPMC_FENCE;
-    apply<P, UNI, 1, false>(B, g, acc);
-    MPMC_FENCE;
-    fetch<P, UNI, 2, false>(in, s, r, N, B);
-    MPMC_FENCE;
-    apply<P, UNI, 2, true>(A, g, acc);
-    MPMC_FENCE;
-    fetch<P, UNI, 3, true>(in, s, r, N, A);
-    MPMC_FENCE;
-    apply<P, UNI, 2, false>(B, g, acc);
-    MPMC_FENCE;
-    fetch<P, UNI, 3, false>(in, s, r, N, B);
-    MPMC_FENCE;
-    apply<P, UNI, 3, true>(A, g, acc);
-    MPMC_FENCE;
-    apply<P, UNI, 3, false>(B, g, acc);
+    HopData<P> H[D];
+    hop_prologue<P, UNI, D, 0>(in, s, r, N, H);
+    hop_step<P, UNI, D, 0>(in, s, r, N, g, H, acc);
 }
 #undef MPMC_FENCE
+
+// Materialises the hopping term before any control flow of the epilogue.
+// Without it the IR passes sink the hop arithmetic (and the loads feeding it)
+// into the epilogue's per-component blocks, where each component then waits
+// for its loads alone and the link values stay live in spilled SGPRs.
+template <typename T>
+__device__ __forceinline__ void pin_acc(cpx<T> acc[4][3]) {
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) asm volatile("" : "+v"(acc[sp][c].re), "+v"(acc[sp][c].im));
+}
 
 // (site, rhs) of this thread.  UNI (N % 64 == 0): each wavefront covers 64
 // consecutive right-hand sides of one site, so the site follows from the
 // wavefront's first thread with scalar arithmetic.
 template <bool UNI, int ORDER = 0>
-__device__ __forceinline__ bool locate(long V, int N, long &s, int &r) {
+__device__ __forceinline__ bool locate(long V, int N, long &s, int &r, const int *__restrict__ order = nullptr) {
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     const unsigned total = (unsigned)(V * N);
     if constexpr (UNI) {
@@ -389,10 +399,12 @@ __device__ __forceinline__ bool locate(long V, int N, long &s, int &r) {
         } else {
             // chunk-major: all sites for right-hand sides [64c, 64c + 64) before
             // chunk c + 1; a block holds 4 sites x 64 right-hand sides, so the
-            // working set of a sweep is 64 right-hand sides wide
+            // working set of a sweep is 64 right-hand sides wide.  ORDER 2 takes
+            // the sites of a chunk in the blocked order of the site table.
             const unsigned wv = w0 >> 6, Vu = (unsigned)V;
             const unsigned ch = wv / Vu, ss = wv - ch * Vu;
-            s = (long)ss;
+            if constexpr (ORDER == 2) s = (long)__builtin_amdgcn_readfirstlane(order[ss]);
+            else s = (long)ss;
             r = (int)(ch * 64u + (threadIdx.x & 63u));
         }
     } else {
@@ -429,39 +441,51 @@ struct Occ {
 };
 
 // Kernel variants of the autotuner: bit 0 selects the occupancy target
-// (Occ::HI), bit 1 the traversal order of locate().
-constexpr int WILSON_VARIANTS = 4;
-static inline int default_variant(int prec) { return prec == MPMC_FP64 ? 0 : 1; }
+// (Occ::HI), bits 1-2 the traversal order of locate() (0 site-major, 1
+// chunk-major, 2 chunk-major over the blocked site order).
+constexpr int WILSON_VARIANTS = 6;
+static inline int default_variant(int prec) { return prec == MPMC_FP64 ? 4 : 5; }
 
 template <int P, bool UNI, int HI = 1, int ORDER = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI, HI>::wpe))) void k_wilson(const void *__restrict__ b, const float *__restrict__ bsc,
                                                 const int *__restrict__ nbr,
                                                 const typename LinkT<P>::type *__restrict__ links, WOut o, long V,
-                                                int N) {
+                                                int N, const int *__restrict__ order) {
     using T = typename Store<P>::real;
     const WIn<P> in{b, bsc, nbr, links};
     long s;
     int r;
-    if (!locate<UNI, ORDER>(V, N, s, r)) return;
+    if (!locate<UNI, ORDER>(V, N, s, r, order)) return;
     cpx<T> acc[4][3];
     hopping<P, UNI>(in, s, r, N, o.g, acc);
+    pin_acc(acc);
+    // Epilogue without per-component control flow: all operand loads are
+    // issued together, the optional terms enter through coefficients.
     const T kap = (T)o.kappa;
-    const cpx<T> al = mk((T)o.alpha.x, (T)o.alpha.y);
+    const bool has_a = o.a_is_b || o.a;
+    const cpx<T> al = has_a ? mk((T)o.alpha.x, (T)o.alpha.y) : mk(T(0), T(0));
     const cpx<T> be = mk((T)o.beta.x, (T)o.beta.y);
-    cpx<T> res[12];
+    const cpx<T> beg5 = o.theta ? mk(-be.re, -be.im) : be;   // Theta = gamma5 flips spins 2, 3
     const SiteAcc<P, UNI> B(in.b, in.bsc, s, N, (uint32_t)r);
+    cpx<T> res[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        const cpx<T> bt = B.ld(k);
-        cpx<T> mb = bt - kap * acc[k / 3][k % 3];
-        if (o.theta && k >= 6) mb = mk(-mb.re, -mb.im);
-        cpx<T> v = be * mb;
-        if (o.a_is_b) {
-            v = v + al * bt;
-        } else if (o.a) {
-            v = v + al * SiteAcc<P, UNI>(o.a, o.asc, s, N, (uint32_t)r).ld(k);
+    for (int k = 0; k < 12; ++k) res[k] = B.ld(k);
+    if (o.a && !o.a_is_b) {
+        const SiteAcc<P, UNI> A(o.a, o.asc, s, N, (uint32_t)r);
+        cpx<T> av[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) av[k] = A.ld(k);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const cpx<T> mb = res[k] - kap * acc[k / 3][k % 3];
+            res[k] = (k >= 6 ? beg5 : be) * mb + al * av[k];
         }
-        res[k] = v;
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const cpx<T> mb = res[k] - kap * acc[k / 3][k % 3];
+            res[k] = (k >= 6 ? beg5 : be) * mb + al * res[k];
+        }
     }
     if constexpr (P == MPMC_FP16S) {
         if (o.out_fp32) {
@@ -485,8 +509,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI,
         if (o.y) {
             const cpx<T> ga = mk((T)o.gamma.x, (T)o.gamma.y);
             const SiteAcc<P, UNI> Y(o.y, nullptr, s, N, (uint32_t)r);
+            cpx<T> yv[12];
 #pragma unroll
-            for (int k = 0; k < 12; ++k) Y.st(k, Y.ld(k) + ga * res[k]);
+            for (int k = 0; k < 12; ++k) yv[k] = Y.ld(k);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) Y.st(k, yv[k] + ga * res[k]);
         }
     }
 }
@@ -581,27 +608,33 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
     const T kap = (T)o.kappa;
     const cpx<T> al = mk((T)o.alpha.x, (T)o.alpha.y);
     const cpx<T> be = mk((T)o.beta.x, (T)o.beta.y);
+    // operands loaded before any store (out may alias nothing the compiler
+    // can prove, so interleaved stores would serialise the loads)
     const typename Elem<P>::type *sp = reinterpret_cast<const typename Elem<P>::type *>(b) + s * 12;
+    const typename Elem<P>::type *ap = reinterpret_cast<const typename Elem<P>::type *>(o.a_is_b ? b : o.a) + s * 12;
+    typename Elem<P>::type *yp = reinterpret_cast<typename Elem<P>::type *>(o.y) + s * 12;
+    typename Elem<P>::type *op = reinterpret_cast<typename Elem<P>::type *>(o.out) + s * 12;
+    const bool has_a = o.a_is_b || o.a;
+    cpx<T> bt[12], av[12], yv[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) bt[k] = mk((T)sp[k].x, (T)sp[k].y);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) av[k] = has_a ? mk((T)ap[k].x, (T)ap[k].y) : mk(T(0), T(0));
+#pragma unroll
+    for (int k = 0; k < 12; ++k) yv[k] = o.y ? mk((T)yp[k].x, (T)yp[k].y) : mk(T(0), T(0));
+    const cpx<T> ga = mk((T)o.gamma.x, (T)o.gamma.y);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
-        const cpx<T> bt = mk((T)sp[k].x, (T)sp[k].y);
-        cpx<T> mb = bt - kap * c[k];
+        cpx<T> mb = bt[k] - kap * c[k];
         if (o.theta && k >= 6) mb = mk(-mb.re, -mb.im);
         cpx<T> v = be * mb;
-        if (o.a_is_b) {
-            v = v + al * bt;
-        } else if (o.a) {
-            const auto av = reinterpret_cast<const typename Elem<P>::type *>(o.a)[s * 12 + k];
-            v = v + al * mk((T)av.x, (T)av.y);
-        }
-        typename Elem<P>::type *op = reinterpret_cast<typename Elem<P>::type *>(o.out) + s * 12 + k;
-        op->x = v.re;
-        op->y = v.im;
+        if (has_a) v = v + al * av[k];
+        op[k].x = v.re;
+        op[k].y = v.im;
         if (o.y) {
-            typename Elem<P>::type *yp = reinterpret_cast<typename Elem<P>::type *>(o.y) + s * 12 + k;
-            const cpx<T> yn = mk((T)yp->x, (T)yp->y) + mk((T)o.gamma.x, (T)o.gamma.y) * v;
-            yp->x = yn.re;
-            yp->y = yn.im;
+            const cpx<T> yn = yv[k] + ga * v;
+            yp[k].x = yn.re;
+            yp[k].y = yn.im;
         }
     }
 }
@@ -612,44 +645,70 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
 // summed over the block's sites.  Requires N % 64 == 0 (uniform wavefronts).
 // A block of 256 threads covers spb = max(1, 256/N) sites and rpb = min(N, 256)
 // right-hand sides starting at rhs (blk*256) % N.
-template <int P>
+template <int P, int ORDER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_FP64 ? 1 : 2))) void k_wilson_dot(const void *__restrict__ b, const int *__restrict__ nbr,
                                                     const typename LinkT<P>::type *__restrict__ links,
                                                     void *__restrict__ out, const uint32_t *__restrict__ codes,
                                                     double2 c, double2 cnext, double kappa, int theta,
-                                                    double2 *__restrict__ partial, long V, int N, int first_step) {
+                                                    double2 *__restrict__ partial, long V, int N, int first_step,
+                                                    const int *__restrict__ order) {
     using T = typename Store<P>::real;
     const WIn<P> in{b, nullptr, nbr, links};
     __shared__ double2 red[256];
     long s;
     int r;
-    const bool live = locate<true>(V, N, s, r);
+    const bool live = locate<true, ORDER>(V, N, s, r, order);
     cpx<double> dot = mk(0.0, 0.0);
     if (live) {
         cpx<T> acc[4][3];
         hopping<P, true>(in, s, r, N, 1.0f, acc);
+        pin_acc(acc);
         const uint32_t code = codes[s * N + r];
         const T kap = (T)kappa;
         const cpx<T> cc = mk((T)c.x, (T)c.y);
         const SiteAcc<P, true> W(in.b, nullptr, s, N, (uint32_t)r), O(out, nullptr, s, N, (uint32_t)r);
+        cpx<T> wv[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) wv[k] = W.ld(k);
+        // conj(eta_k) wn with eta_k = i^sym, by selects (no per-lane branches):
+        // odd sym swaps (re, im) -> (im, -re), sym >= 2 negates; Theta = gamma5
+        // negates spins 2 and 3.
+        const double tsg = theta ? -1.0 : 1.0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            const cpx<T> w = W.ld(k);
-            const cpx<T> mw = w - kap * acc[k / 3][k % 3];
-            const cpx<T> wn = w - cc * mw;
+            const cpx<T> mw = wv[k] - kap * acc[k / 3][k % 3];
+            const cpx<T> wn = wv[k] - cc * mw;
             O.st(k, wn);
-            // conj(eta_k) * wn, eta_k = i^sym: conj(i^sym) = i^(4-sym)
             const uint32_t sym = (code >> (2 * k)) & 3u;
-            cpx<double> v = mk((double)wn.re, (double)wn.im);
-            if (sym == 1) v = times_mi(v);
-            else if (sym == 2) v = mk(-v.re, -v.im);
-            else if (sym == 3) v = times_i(v);
-            if (theta && k >= 6) v = mk(-v.re, -v.im);
-            dot = dot + v;
+            const double a = (double)wn.re, b = (double)wn.im;
+            const double sg = (sym & 2u) ? -1.0 : 1.0;
+            const double g = k >= 6 ? sg * tsg : sg;
+            dot.re += g * ((sym & 1u) ? b : a);
+            dot.im += g * ((sym & 1u) ? -a : b);
         }
     }
     red[threadIdx.x] = make_double2(dot.re, dot.im);
     __syncthreads();
+    if constexpr (ORDER != 0) {
+        // chunk-major tiles: the four wavefronts share the right-hand sides
+        // [64c, 64c + 64) of chunk c = 4 tile / V (V % 4 == 0); one partial per
+        // (tile, lane), the four sites summed in a fixed order
+        if (threadIdx.x < 64) {
+            const double2 a = red[threadIdx.x], b2 = red[threadIdx.x + 64], c2 = red[threadIdx.x + 128],
+                          d2 = red[threadIdx.x + 192];
+            const cpx<double> sum = mk(((a.x + b2.x) + c2.x) + d2.x, ((a.y + b2.y) + c2.y) + d2.y);
+            const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+            const cpx<double> term = mk(cnext.x, cnext.y) * sum;
+            double2 *pp = partial + (long)tile * 64 + threadIdx.x;
+            if (first_step) {
+                *pp = make_double2(term.re, term.im);
+            } else {
+                double2 old = *pp;
+                *pp = make_double2(old.x + term.re, old.y + term.im);
+            }
+        }
+        return;
+    }
     const int rpb = N < 256 ? N : 256;
     const int spb = 256 / rpb;
     if ((int)threadIdx.x < rpb) {
@@ -681,6 +740,39 @@ __global__ void k_dot_finish(const double2 *__restrict__ partial, int nblocks, i
     double2 a = make_double2(0, 0);
     for (int b = range + per * threadIdx.x; b < nblocks; b += per * blockDim.x) {
         const double2 v = partial[(long)b * rpb + rr];
+        a.x += v.x;
+        a.y += v.y;
+    }
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[threadIdx.x].x += red[threadIdx.x + h].x;
+            red[threadIdx.x].y += red[threadIdx.x + h].y;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (accumulate) {
+            out[r].x += sign * red[0].x;
+            out[r].y += sign * red[0].y;
+        } else {
+            out[r] = make_double2(sign * red[0].x, sign * red[0].y);
+        }
+    }
+}
+
+// out[r] = sum of partial[t*64 + r%64] over the V/4 tiles t of chunk r/64
+// (chunk-major fused steps), in a fixed order
+__global__ void k_dot_finish_chunk(const double2 *__restrict__ partial, long tiles_per_chunk, double2 *__restrict__ out,
+                                   int accumulate, double sign) {
+    __shared__ double2 red[256];
+    const int r = blockIdx.x;
+    const long t0 = (long)(r / 64) * tiles_per_chunk;
+    const int lane = r % 64;
+    double2 a = make_double2(0, 0);
+    for (long t = threadIdx.x; t < tiles_per_chunk; t += blockDim.x) {
+        const double2 v = partial[(t0 + t) * 64 + lane];
         a.x += v.x;
         a.y += v.y;
     }
@@ -736,10 +828,17 @@ static int wilson_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
     return it == ctx->tune.end() ? default_variant(prec) : it->second;
 }
 
+// The fused level step follows the traversal of the Wilson variant in use
+// for (nrhs, prec): the blocked order when that variant is blocked and the
+// chunk tiles hold one chunk each (V % 4 == 0), the site-major order otherwise.
+static bool dot_blocked(const mpmc_ctx *ctx, int nrhs, int prec) {
+    return (wilson_variant(ctx, nrhs, prec) >> 1) == 2 && ctx->V % 4 == 0;
+}
+
 template <int P, int V_>
 static void launch_uniform(mpmc_ctx *ctx, const WIn<P> &in, const WOut &o, int nrhs, unsigned grid) {
-    k_wilson<P, true, V_ & 1, (V_ >> 1) & 1><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V,
-                                                                          nrhs);
+    k_wilson<P, true, V_ & 1, (V_ >> 1)><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs,
+                                                                      ctx->site_order);
 }
 
 template <int P>
@@ -758,10 +857,12 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs) {
         case 0: launch_uniform<P, 0>(ctx, in, o, nrhs, grid); break;
         case 1: launch_uniform<P, 1>(ctx, in, o, nrhs, grid); break;
         case 2: launch_uniform<P, 2>(ctx, in, o, nrhs, grid); break;
-        default: launch_uniform<P, 3>(ctx, in, o, nrhs, grid); break;
+        case 3: launch_uniform<P, 3>(ctx, in, o, nrhs, grid); break;
+        case 4: launch_uniform<P, 4>(ctx, in, o, nrhs, grid); break;
+        default: launch_uniform<P, 5>(ctx, in, o, nrhs, grid); break;
         }
     } else {
-        k_wilson<P, false><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs);
+        k_wilson<P, false><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs, nullptr);
     }
 }
 
@@ -846,17 +947,28 @@ int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *co
         return set_err(ctx, MPMC_EINVAL, "fused level step needs nrhs %% 64 == 0 (and %% 256 above 256)");
     const long work = ctx->V * nrhs;
     const unsigned grid = grid_for(work, 256);
+    const bool blocked = dot_blocked(ctx, nrhs, prec);
     const int ev = timing_begin(ctx);
     if (prec == MPMC_FP64) {
         const WIn<MPMC_FP64> in = make_in<MPMC_FP64>(ctx, w, nrhs);
-        k_wilson_dot<MPMC_FP64><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
-                                                               ctx->kappa, theta, (double2 *)partial, ctx->V, nrhs,
-                                                               first_step);
+        if (blocked)
+            k_wilson_dot<MPMC_FP64, 2><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                                      ctx->kappa, theta, (double2 *)partial, ctx->V,
+                                                                      nrhs, first_step, ctx->site_order);
+        else
+            k_wilson_dot<MPMC_FP64, 0><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                                      ctx->kappa, theta, (double2 *)partial, ctx->V,
+                                                                      nrhs, first_step, nullptr);
     } else if (prec == MPMC_FP32) {
         const WIn<MPMC_FP32> in = make_in<MPMC_FP32>(ctx, w, nrhs);
-        k_wilson_dot<MPMC_FP32><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
-                                                               ctx->kappa, theta, (double2 *)partial, ctx->V, nrhs,
-                                                               first_step);
+        if (blocked)
+            k_wilson_dot<MPMC_FP32, 2><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                                      ctx->kappa, theta, (double2 *)partial, ctx->V,
+                                                                      nrhs, first_step, ctx->site_order);
+        else
+            k_wilson_dot<MPMC_FP32, 0><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                                      ctx->kappa, theta, (double2 *)partial, ctx->V,
+                                                                      nrhs, first_step, nullptr);
     }
     else
         return set_err(ctx, MPMC_EINVAL, "fused level step supports FP64 and FP32");
@@ -871,10 +983,15 @@ int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *co
     return MPMC_OK;
 }
 
-int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, double *out, int accumulate, double sign) {
+int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, int prec, double *out, int accumulate,
+                      double sign) {
     const long blocks = (ctx->V * nrhs + 255) / 256;
-    k_dot_finish<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, (int)blocks, nrhs, (double2 *)out,
-                                                accumulate, sign);
+    if (dot_blocked(ctx, nrhs, prec))
+        k_dot_finish_chunk<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, ctx->V / 4, (double2 *)out,
+                                                          accumulate, sign);
+    else
+        k_dot_finish<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, (int)blocks, nrhs, (double2 *)out,
+                                                    accumulate, sign);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }

@@ -298,9 +298,12 @@ def mpmc_level_estimate(ctx, upper, lower, defl, theta, seed, stream, first, nno
     return samples, complex(corr[0]), mvps.value
 
 
+WILSON_VARIANTS = 6      # kernel variants of the multi-RHS Wilson kernel (include/mpmc.h)
+
+
 def mpmc_autotune(ctx, nrhs, prec):
     v = ctypes.c_int()
-    us = np.zeros(4)
+    us = np.zeros(WILSON_VARIANTS)
     _check(_L.mpmc_autotune(ctx, int(nrhs), int(prec), ctypes.byref(v), us.ctypes.data), ctx)
     return v.value, us
 

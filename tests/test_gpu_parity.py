@@ -413,17 +413,44 @@ def test_autotune_variants_bit_identical(f44, prec):
     N = 128
     x = ctx.noise(4, 1, 0, N, prec)
     outs = []
-    for v in range(4):
+    for v in range(mpmc.WILSON_VARIANTS):
         ctx.tune_set(N, prec, v)
         outs.append(host(ctx.apply_M(x, N, prec)).copy())
     ctx.tune_set(N, prec, -1)
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     v, us = ctx.autotune(N, prec)
-    assert 0 <= v < 4 and np.all(us > 0) and us[v] == us.min()
+    assert 0 <= v < mpmc.WILSON_VARIANTS and np.all(us > 0) and us[v] == us.min()
     assert np.array_equal(host(ctx.apply_M(x, N, prec)), outs[0])
     ctx.tune_set(N, prec, -1)
     assert ctx.autotune(20, prec)[0] == -1     # not a multiple of 64: nothing to tune
+
+
+@pytest.mark.parametrize("prec,variants", [(FP32, (1, 3, 5)), (FP64, (0, 2, 4))])
+def test_fused_level_step_traversals(f44, prec, variants):
+    """The fused level step under each traversal (site-major, chunk-major,
+    4D-blocked with its per-chunk reduction): per-element arithmetic is the
+    same, so the samples differ only by the order of the FP64 sums; two
+    samples are recomputed by the oracle."""
+    dims, kappa, U, op, ctx = f44
+    P1, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 17)
+    g1 = ctx.poly_from_roots(P1.roots)
+    N = 128
+    outs = []
+    for v in variants:
+        ctx.tune_set(N, prec, v)
+        X, T, mv = ctx.level(g1, None, None, 0, 5, 1, 0, N, prec=prec)
+        assert T == 0 and mv == N * 16
+        outs.append(X)
+    ctx.tune_set(N, prec, -1)
+    for X in outs[1:]:
+        assert rel(X, outs[0]) < 1e-13
+    Xr, _ = OES.level_samples(op, P1, None, None, "I", 5, 1, 0, 2)
+    for j in range(2):
+        if prec == FP64:
+            assert abs(outs[-1][j] - Xr[j]) < 1e-10 * abs(Xr[j])
+        else:   # FP32 kernels, FP64 sums: ~1e-6 n (bound 1e-5 n)
+            assert abs(outs[-1][j] - Xr[j]) < 1e-5 * op.n
 
 
 @pytest.mark.parametrize("N", [64, 20])
