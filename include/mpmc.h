@@ -276,7 +276,11 @@ int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl 
  * double[6] microseconds per launch per variant.  Does not count MVPs and
  * does not enter mpmc_timing_read.  Synchronises. */
 int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host, double *us_host);
-/* Pin variant (0..3) for (nrhs, prec); -1 restores the default. */
+/* Pin variant (0..5) for (nrhs, prec); -1 restores the default.  The fused
+ * polynomial step of mpmc_level_estimate uses the blocked traversal when the
+ * site count is a multiple of 4, unless a variant is pinned here: then it
+ * follows that variant's traversal bits (2: blocked, else site-major).  The
+ * autotuner's choice does not change the fused step. */
 int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant);
 
 /* ------------------------------------------------- learned preconditioner */

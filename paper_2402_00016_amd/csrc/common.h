@@ -52,6 +52,7 @@ struct mpmc_ctx {
     std::vector<TimedLaunch> timed;
     // Wilson kernel variant per (nrhs, prec), set by mpmc_autotune / mpmc_tune_set
     std::map<std::pair<int, int>, int> tune;
+    std::map<std::pair<int, int>, int> tune_explicit;   // variants set by mpmc_tune_set (not by the autotuner)
     // polynomial right preconditioner of the solves inside mpmc_level_estimate
     const struct mpmc_poly *level_pp = nullptr;
 };

@@ -828,11 +828,15 @@ static int wilson_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
     return it == ctx->tune.end() ? default_variant(prec) : it->second;
 }
 
-// The fused level step follows the traversal of the Wilson variant in use
-// for (nrhs, prec): the blocked order when that variant is blocked and the
-// chunk tiles hold one chunk each (V % 4 == 0), the site-major order otherwise.
+// The fused level step takes the blocked order whenever its chunk tiles hold
+// one chunk each (V % 4 == 0), and the site-major order otherwise; a variant
+// set explicitly for (nrhs, prec) with mpmc_tune_set selects blocked (its
+// traversal bits are 2) or site-major (any other variant).  The autotuner,
+// which times the plain operator, does not change it.
 static bool dot_blocked(const mpmc_ctx *ctx, int nrhs, int prec) {
-    return (wilson_variant(ctx, nrhs, prec) >> 1) == 2 && ctx->V % 4 == 0;
+    if (ctx->V % 4 != 0) return false;
+    const auto it = ctx->tune_explicit.find(std::make_pair(nrhs, prec));
+    return it == ctx->tune_explicit.end() || (it->second >> 1) == 2;
 }
 
 template <int P, int V_>
@@ -1012,8 +1016,13 @@ MPMC_API int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant) {
     if (nrhs < 1 || !prec_ok(prec) || variant < -1 || variant >= WILSON_VARIANTS)
         return set_err(ctx, MPMC_EINVAL, "mpmc_tune_set: bad argument");
     const auto key = std::make_pair(nrhs, prec);
-    if (variant < 0) ctx->tune.erase(key);
-    else ctx->tune[key] = variant;
+    if (variant < 0) {
+        ctx->tune.erase(key);
+        ctx->tune_explicit.erase(key);
+    } else {
+        ctx->tune[key] = variant;
+        ctx->tune_explicit[key] = variant;
+    }
     return MPMC_OK;
 }
 
