@@ -324,7 +324,8 @@ def estimate(ctx, plan: Plan, sync=None, net=None) -> Estimate:
 def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_every=3, max_noises=4096, net=None):
     """Adaptive stopping (Sec. 8): each Monte Carlo term stops once its standard
     error is below eps / sqrt(#terms), with minimum counts 2 (solve term),
-    3 (first difference), 6 (later terms) and checks every `check_every` noises."""
+    3 (first difference), 6 (later terms) and checks every `check_every` noises
+    (an int, or one count per term)."""
     mv0 = total_mvps(ctx)
     t0 = time.perf_counter()
     defl, polys, tnet, _ = build_setup(ctx, plan, train=plan.learned and net is None)
@@ -335,13 +336,26 @@ def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_e
     levels = []
     uppers = [None] + polys
     lowers = polys + [None]
+    pp = solve_preconditioner(ctx, plan, defl) if not plan.learned else None
+    ctx.set_level_solve_poly(pp)
+    try:
+        _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, check_every, max_noises, levels)
+    finally:
+        ctx.set_level_solve_poly(None)
+    est, se = combine(levels)
+    return Estimate(est, se, levels, t_setup, time.perf_counter() - t0, total_mvps(ctx) - mv0, polys=polys,
+                    defl_k=defl.k if defl is not None else 0)
+
+
+def _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, check_every, max_noises, levels):
     for l, (up, lo) in enumerate(zip(uppers, lowers)):
         d = defl if (up is not None and lo is not None and plan.deflate_levels) else (defl if up is None else None)
         n0 = min_counts[min(l, len(min_counts) - 1)]
+        step = check_every if isinstance(check_every, int) else check_every[min(l, len(check_every) - 1)]
         X = np.zeros(0, dtype=np.complex128)
         corr, mv, secs = 0j, 0, 0.0
         while True:
-            want = n0 if len(X) == 0 else check_every
+            want = n0 if len(X) == 0 else step
             ts = time.perf_counter()
             Xn, corr, m = ctx.level(up, lo, d, plan.theta, plan.seed, l, len(X), want, prec=plan.poly_prec,
                                     solve_tol=plan.solve_tol, solve_restart=plan.solve_restart,
@@ -354,6 +368,3 @@ def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_e
             if math.sqrt(var / len(X)) <= target or len(X) >= max_noises:
                 break
         levels.append(LevelResult("term %d" % l, X, corr, mv, secs))
-    est, se = combine(levels)
-    return Estimate(est, se, levels, t_setup, time.perf_counter() - t0, total_mvps(ctx) - mv0, polys=polys,
-                    defl_k=defl.k if defl is not None else 0)
