@@ -6,9 +6,9 @@
 //  * Leja ordering of the roots (Sec. 3),
 //  * Ritz vectors by inverse iteration on H - mu I (deflation, Sec. 7),
 //  * per-rhs Givens updates and back substitution of restarted GMRES solves.
-// The matrices are at most a few hundred rows: one wavefront (64 lanes) works
-// on one matrix, which lives in LDS (packed Hessenberg) up to 137 rows and in
-// global memory (L2 resident) beyond.  Every loop has a fixed iteration bound.
+// The matrices are at most a few hundred rows: one workgroup works on one
+// matrix, which lives in LDS (packed Hessenberg) up to 192 rows and in global
+// memory (L2 resident) beyond.  Every loop has a fixed iteration bound.
 #include <cfloat>
 
 #include "common.h"
@@ -76,6 +76,15 @@ __device__ __forceinline__ double rdlane(double v, int src) {
 }
 __device__ __forceinline__ zd rdlane(zd v, int src) { return mk(rdlane(v.re, src), rdlane(v.im, src)); }
 
+// A value every lane holds identically, moved to scalar registers (so that
+// branches on it are uniform).
+__device__ __forceinline__ double uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ zd uniform(zd v) { return mk(uniform(v.re), uniform(v.im)); }
+
 // 1/sqrt(z) for z > 0: hardware estimate plus one Newton step.
 __device__ __forceinline__ double rsqrt_nr(double z) {
     const double r = __builtin_amdgcn_rsq(z);
@@ -119,176 +128,197 @@ __device__ __forceinline__ zd pick(const zd (&v)[MAXC], int q) {
 // Eigenvalues of the upper Hessenberg matrix held by `a` (destroyed): shifted
 // QR with Givens rotations, Wilkinson shifts, exceptional shifts every 11
 // iterations without deflation, deflation from the bottom.  Must be called by
-// exactly one wavefront of 64 lanes (n <= 64 * MAXC); returns 0, or -1 on
-// non-convergence or NaN.
+// every thread of a workgroup of QR_THREADS threads (n <= QR_THREADS * MAXC);
+// returns 0, or -1 on non-convergence or NaN.
 //
-// One QR step A - sigma = QR, A' = RQ + sigma on the active window [l, hi] is
-// a single sweep over k = l .. hi-1 without barriers:
-//  * rows: lane t owns columns j = t + 64 q.  Row k (already rotated by
-//    G_{k-1}) is carried in registers and row k+1 prefetched, so the only
-//    cross-lane step is the broadcast (readlane) of the pivot pair
-//    (a(k,k), a(k+1,k)) from the lane owning column k; R's row k is stored;
-//  * columns, one step behind: lane t owns rows i = l + t + 64 r and applies
-//    G_{k-1}^H to columns k-1, k (rows <= k).  Column k is carried in
-//    registers; the R entries it needs were stored at least two steps earlier
-//    or are broadcast from the lanes that produced them in this step or the
-//    last, so no lane reads an element another lane writes in the same step.
+// Control (deflation test, 1x1 / 2x2 blocks, shift) runs on the first
+// wavefront and reaches the others through `sh`.  One QR step A - sigma = QR,
+// A' = RQ + sigma on the active window [l, hi] is a sweep over k = l .. hi + 1
+// with one barrier per k:
+//  * rows: thread t owns columns j = t + QR_THREADS q and carries rows k and
+//    k+1 of those columns in registers.  Every thread forms G_k from the pivot
+//    pair (a(k,k), a(k+1,k)), which the owner of column k published in the
+//    previous step (double-buffered by k & 1), rotates its columns, stores
+//    row k of R and loads row k+2;
+//  * columns, two steps behind: thread t owns rows i = l + t + QR_THREADS r
+//    and applies G_{k-2}^H to columns k-2, k-1 (rows <= k-1).  Column k-2 is
+//    carried in registers; column k-1 of R was stored at least one barrier
+//    earlier.  The sets of entries the two passes touch in one step are
+//    disjoint.
 // The shift is subtracted when diagonal entries are loaded and added back when
-// final diagonal entries are stored.  `cs` is unused (kept for the callers'
-// workspace layout).
-template <int MAXC, typename Mat>
-__device__ int hess_eigvals(Mat a, int n, double2 *ev, double2 *cs) {
-    (void)cs;
-    const int lane = threadIdx.x;
-    int hi = n - 1, iter = 0, total = 0;
-    const int max_total = 60 * n + 100;
-    int status = 0;
-    while (hi >= 0) {
-        __syncthreads();
-        if (hi == 0) {
-            if (lane == 0) st(ev, 0, a.get(0, 0));
-            break;
-        }
-        // l: the largest index in [1, hi] with a negligible subdiagonal a(l, l-1), else 0;
-        // 64 subdiagonals are tested at once, from the bottom up
-        int l = 0;
-        for (int top = hi; top >= 1; top -= 64) {
-            const int i = top - lane;
-            bool small = false, bad = false;
-            if (i >= 1) {
-                const zd sv = a.get(i, i - 1), d0 = a.get(i - 1, i - 1), d1 = a.get(i, i);
-                const double sub = fabs(sv.re) + fabs(sv.im);
-                const double dia = fabs(d0.re) + fabs(d0.im) + fabs(d1.re) + fabs(d1.im);
-                bad = !(sub == sub);
-                small = sub <= 0.5 * DBL_EPSILON * dia || sub < 1e-300;
-            }
-            if (__ballot(bad)) {
-                status = -1;
-                break;
-            }
-            const unsigned long long m = __ballot(small);
-            if (m) {
-                l = top - __builtin_ctzll(m);
-                break;
-            }
-        }
-        if (status) break;
-        if (l == hi) {
-            if (lane == 0) st(ev, hi, a.get(hi, hi));
-            --hi;
-            iter = 0;
-            continue;
-        }
-        if (l == hi - 1) {
-            const zd p = a.get(hi - 1, hi - 1), q = a.get(hi - 1, hi), r = a.get(hi, hi - 1),
-                     s = a.get(hi, hi);
-            const zd half_tr = 0.5 * (p + s);
-            const zd det = p * s - q * r;
-            const zd disc = zsqrt(half_tr * half_tr - det);
-            if (lane == 0) {
-                st(ev, hi - 1, half_tr + disc);
-                st(ev, hi, half_tr - disc);
-            }
-            hi -= 2;
-            iter = 0;
-            continue;
-        }
-        if (++total > max_total) {
-            status = -1;
-            break;
-        }
-        ++iter;
-        const zd p = a.get(hi - 1, hi - 1), q = a.get(hi - 1, hi), r = a.get(hi, hi - 1),
-                 s = a.get(hi, hi);
-        const zd half_tr = 0.5 * (p + s), det = p * s - q * r;
-        const zd disc = zsqrt(half_tr * half_tr - det);
-        zd e1 = half_tr + disc, e2 = half_tr - disc;
-        zd sigma = zabs(e1 - s) <= zabs(e2 - s) ? e1 : e2;
-        if (iter % 11 == 10) {
-            const double m = zabs(r) + zabs(a.get(hi - 1, hi - 2 >= l ? hi - 2 : hi - 1));
-            sigma = s + mk(0.75 * m, 0.4375 * m);
-        }
-        __syncthreads();   // every lane has read the window before it changes
+// final diagonal entries are stored.
+constexpr int QR_THREADS = 256;
+struct QrShared {
+    double2 xy[2][2];   // pivot pair of step k in xy[k & 1]
+    double2 sigma;
+    int l, hi, go, status;
+};
 
-        zd cur[MAXC], nxt[MAXC];    // rows k and k+1 at the lane's columns
-        zd col[MAXC], vk[MAXC];     // a(i, k-1) (rotated) and R(i, k) at the lane's rows
+template <int MAXC, typename Mat>
+__device__ int hess_eigvals(Mat a, int n, double2 *ev, QrShared &sh) {
+    const int tid = threadIdx.x;
+    int hi_w = n - 1, iter = 0, total = 0;   // kept by the first wavefront
+    const int max_total = 60 * n + 100;
+    while (true) {
+        __syncthreads();   // the matrix is final for this round; sh may be rewritten
+        if (tid < 64) {
+            const int lane = tid;
+            int go = 1, l = 0, status = 0;
+            zd sigma = mk(0.0, 0.0);
+            if (hi_w < 0) {
+                go = 0;
+            } else if (hi_w == 0) {
+                if (lane == 0) st(ev, 0, a.get(0, 0));
+                go = 0;
+            } else {
+                // l: the largest index in [1, hi] with a negligible subdiagonal
+                // a(l, l-1), else 0; 64 subdiagonals tested at once from the bottom
+                for (int top = hi_w; top >= 1; top -= 64) {
+                    const int i = top - lane;
+                    bool small = false, bad = false;
+                    if (i >= 1) {
+                        const zd sv = a.get(i, i - 1), d0 = a.get(i - 1, i - 1), d1 = a.get(i, i);
+                        const double sub = fabs(sv.re) + fabs(sv.im);
+                        const double dia = fabs(d0.re) + fabs(d0.im) + fabs(d1.re) + fabs(d1.im);
+                        bad = !(sub == sub);
+                        small = sub <= 0.5 * DBL_EPSILON * dia || sub < 1e-300;
+                    }
+                    if (__ballot(bad)) {
+                        status = -1;
+                        break;
+                    }
+                    const unsigned long long m = __ballot(small);
+                    if (m) {
+                        l = top - __builtin_ctzll(m);
+                        break;
+                    }
+                }
+                if (status) {
+                    go = 0;
+                } else if (l == hi_w) {
+                    if (lane == 0) st(ev, hi_w, a.get(hi_w, hi_w));
+                    --hi_w;
+                    iter = 0;
+                    go = 2;
+                } else if (l == hi_w - 1) {
+                    const zd p = a.get(hi_w - 1, hi_w - 1), q = a.get(hi_w - 1, hi_w), r = a.get(hi_w, hi_w - 1),
+                             s = a.get(hi_w, hi_w);
+                    const zd half_tr = 0.5 * (p + s);
+                    const zd det = p * s - q * r;
+                    const zd disc = zsqrt(half_tr * half_tr - det);
+                    if (lane == 0) {
+                        st(ev, hi_w - 1, half_tr + disc);
+                        st(ev, hi_w, half_tr - disc);
+                    }
+                    hi_w -= 2;
+                    iter = 0;
+                    go = 2;
+                } else if (++total > max_total) {
+                    status = -1;
+                    go = 0;
+                } else {
+                    ++iter;
+                    const zd p = a.get(hi_w - 1, hi_w - 1), q = a.get(hi_w - 1, hi_w), r = a.get(hi_w, hi_w - 1),
+                             s = a.get(hi_w, hi_w);
+                    const zd half_tr = 0.5 * (p + s), det = p * s - q * r;
+                    const zd disc = zsqrt(half_tr * half_tr - det);
+                    const zd e1 = half_tr + disc, e2 = half_tr - disc;
+                    sigma = zabs(e1 - s) <= zabs(e2 - s) ? e1 : e2;
+                    if (iter % 11 == 10) {
+                        const double m = zabs(r) + zabs(a.get(hi_w - 1, hi_w - 2 >= l ? hi_w - 2 : hi_w - 1));
+                        sigma = s + mk(0.75 * m, 0.4375 * m);
+                    }
+                }
+            }
+            if (lane == 0) {
+                sh.go = go;
+                sh.l = l;
+                sh.hi = hi_w;
+                sh.status = status;
+                sh.sigma = make_double2(sigma.re, sigma.im);
+            }
+        }
+        __syncthreads();
+        // the control values are the same in every lane: readfirstlane keeps
+        // them (and the sweep's loop) scalar
+        const int go = __builtin_amdgcn_readfirstlane(sh.go), l = __builtin_amdgcn_readfirstlane(sh.l),
+                  hi = __builtin_amdgcn_readfirstlane(sh.hi);
+        const zd sigma = mk(sh.sigma.x, sh.sigma.y);
+        if (go == 0) break;
+        if (go == 2) continue;
+
+        // ---- one QR sweep on [l, hi]
+        zd cur[MAXC], nxt[MAXC], col[MAXC];
 #pragma unroll
-        for (int q2 = 0; q2 < MAXC; ++q2) {
-            const int j = lane + 64 * q2;
-            cur[q2] = nxt[q2] = col[q2] = vk[q2] = mk(0.0, 0.0);
+        for (int q = 0; q < MAXC; ++q) {
+            const int j = tid + QR_THREADS * q;
+            cur[q] = nxt[q] = col[q] = mk(0.0, 0.0);
             if (j >= l && j <= hi) {
-                cur[q2] = ld_shift(a, l, j, sigma);
-                nxt[q2] = ld_shift(a, l + 1, j, sigma);
+                cur[q] = ld_shift(a, l, j, sigma);
+                nxt[q] = ld_shift(a, l + 1, j, sigma);
             }
         }
-        double cp = 1.0;            // G_{k-1}
-        zd sp = mk(0.0, 0.0);
-        for (int k = l; k < hi; ++k) {
-            const int qk = k >> 6, lk = k & 63;
-            const zd x = rdlane(pick(cur, qk), lk), y = rdlane(pick(nxt, qk), lk);
-            double c;
-            zd sn;
-            givens(x, y, c, sn);
-            // row pass: R(k, j) for j >= k; rows k+1 carried
-            zd rkk = mk(0.0, 0.0), rkk1 = mk(0.0, 0.0);
+        zd x = a.get(l, l) - sigma, y = a.get(l + 1, l);
+        double c1 = 1.0, c2 = 1.0;          // G_{k-1}, G_{k-2}
+        zd s1 = mk(0.0, 0.0), s2 = mk(0.0, 0.0);
+        __syncthreads();   // every thread has read the window before row l is overwritten
+        for (int k = l; k <= hi + 1; ++k) {
+            double c = 1.0;
+            zd sn = mk(0.0, 0.0);
+            if (k < hi) {
+                if (k > l) {
+                    x = mk(sh.xy[k & 1][0].x, sh.xy[k & 1][0].y);
+                    y = mk(sh.xy[k & 1][1].x, sh.xy[k & 1][1].y);
+                }
+                givens(uniform(x), uniform(y), c, sn);
 #pragma unroll
-            for (int q2 = 0; q2 < MAXC; ++q2) {
-                const int j = lane + 64 * q2;
-                if (j >= k && j <= hi) {
-                    const zd u = cur[q2], v = nxt[q2];
-                    const zd nr = c * u + sn * v;
-                    a.set(k, j, nr);
-                    if (j == k) rkk = nr;
-                    if (j == k + 1) rkk1 = nr;
-                    cur[q2] = j == k ? mk(0.0, 0.0) : c * v - cconj(sn) * u;
-                    if (j > k && k + 2 <= hi) nxt[q2] = ld_shift(a, k + 2, j, sigma);
+                for (int q = 0; q < MAXC; ++q) {
+                    const int j = tid + QR_THREADS * q;
+                    if (j >= k && j <= hi) {
+                        const zd u = cur[q], v = nxt[q];
+                        a.set(k, j, c * u + sn * v);                        // row k of R
+                        const zd nc = j == k ? mk(0.0, 0.0) : c * v - cconj(sn) * u;
+                        const zd nn = (j > k && k + 2 <= hi) ? ld_shift(a, k + 2, j, sigma) : mk(0.0, 0.0);
+                        cur[q] = nc;
+                        nxt[q] = nn;
+                        if (j == k + 1 && k + 1 < hi) {                    // pivot pair of step k+1
+                            sh.xy[(k + 1) & 1][0] = make_double2(nc.re, nc.im);
+                            sh.xy[(k + 1) & 1][1] = make_double2(nn.re, nn.im);
+                        }
+                        if (j == hi && k == hi - 1) a.set(hi, hi, nc);     // last row of R
+                    }
                 }
             }
-            const zd Rkk = rdlane(rkk, lk);
-            const zd Rkk1 = rdlane(rkk1, (k + 1) & 63);
-            // column pass, one step behind: G_{k-1}^H on columns k-1, k, rows l..k
+            if (k - 2 >= l) {   // column pass G_{k-2}^H on columns kk, kk+1, rows l .. kk+1
+                const int kk = k - 2;
+                const bool last = kk == hi - 1;
 #pragma unroll
-            for (int r2 = 0; r2 < MAXC; ++r2) {
-                const int i = l + lane + 64 * r2;
-                if (k > l && i <= k) {
-                    const zd u = i == k ? mk(0.0, 0.0) : col[r2];   // a(k, k-1) = 0 in R
-                    const zd v = i == k ? Rkk : vk[r2];
-                    zd o = cp * u + cconj(sp) * v;
-                    if (i == k - 1) o = o + sigma;
-                    a.set(i, k - 1, o);
-                    col[r2] = cp * v - sp * u;
-                } else if (k == l && i == l) {
-                    col[r2] = Rkk;
+                for (int r = 0; r < MAXC; ++r) {
+                    const int i = l + tid + QR_THREADS * r;
+                    if (i <= kk + 1) {
+                        const zd u = i == kk + 1 ? mk(0.0, 0.0) : (kk == l ? a.get(l, l) : col[r]);
+                        const zd v = a.get(i, kk + 1);
+                        zd o = c2 * u + cconj(s2) * v;
+                        zd w = c2 * v - s2 * u;
+                        if (i == kk) o = o + sigma;
+                        a.set(i, kk, o);
+                        if (last) {
+                            if (i == hi) w = w + sigma;
+                            a.set(i, hi, w);
+                        } else {
+                            col[r] = w;
+                        }
+                    }
                 }
-                // R(i, k+1) for the next step: stored by an earlier step, or broadcast
-                if (i < k && k + 1 <= hi) vk[r2] = a.get(i, k + 1);
-                if (i == k) vk[r2] = Rkk1;
             }
-            cp = c;
-            sp = sn;
-        }
-        // last row of R, then G_{hi-1}^H on columns hi-1, hi
-        zd rhh = mk(0.0, 0.0);
-#pragma unroll
-        for (int q2 = 0; q2 < MAXC; ++q2)
-            if (lane + 64 * q2 == hi) rhh = cur[q2];
-        const zd Rhh = rdlane(rhh, hi & 63);
-#pragma unroll
-        for (int r2 = 0; r2 < MAXC; ++r2) {
-            const int i = l + lane + 64 * r2;
-            if (i <= hi) {
-                const zd u = i == hi ? mk(0.0, 0.0) : col[r2];
-                const zd v = i == hi ? Rhh : vk[r2];
-                zd o1 = cp * u + cconj(sp) * v, o2 = cp * v - sp * u;
-                if (i == hi - 1) o1 = o1 + sigma;
-                if (i == hi) o2 = o2 + sigma;
-                a.set(i, hi - 1, o1);
-                a.set(i, hi, o2);
-            }
+            c2 = c1;
+            s2 = s1;
+            c1 = c;
+            s1 = sn;
+            __syncthreads();
         }
     }
-    __syncthreads();
-    return status;
+    return sh.status;
 }
 
 // --------------------------------------------------------------- Leja --
@@ -314,8 +344,8 @@ __device__ void leja_order(double2 *ev, int n, double2 *tmp, double *S, int *tak
         taken[j] = 0;
     }
     __syncthreads();
-    __shared__ double bestv[64];
-    __shared__ int besti[64];
+    __shared__ double bestv[QR_THREADS];
+    __shared__ int besti[QR_THREADS];
     int last = -1;
     for (int step = 0; step < n; ++step) {
         double bv = -INFINITY;
@@ -334,15 +364,13 @@ __device__ void leja_order(double2 *ev, int n, double2 *tmp, double *S, int *tak
                 bi = j;
             }
         }
-        if (tid < 64) {
-            bestv[tid] = bv;
-            besti[tid] = bi;
-        }
+        bestv[tid] = bv;
+        besti[tid] = bi;
         __syncthreads();
         if (tid == 0) {
             double b = -INFINITY;
             int bj = 0x7fffffff;
-            for (int q = 0; q < (nt < 64 ? nt : 64); ++q) {
+            for (int q = 0; q < nt; ++q) {
                 if (besti[q] == 0x7fffffff) continue;
                 if (bj == 0x7fffffff || bestv[q] > b || (bestv[q] == b && besti[q] < bj)) {
                     b = bestv[q];
@@ -373,9 +401,10 @@ __device__ void leja_order(double2 *ev, int n, double2 *tmp, double *S, int *tak
 // H_d + |h_{d+1,d}|^2 f e_d^T are found in LDS (packed) when it fits.
 // work (global): >= 2*d*d + 8*d + 16 complex doubles.
 template <int use_lds>
-__global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh, int d, double beta,
-                                                      double2 *work, double2 *roots, double *info) {
+__global__ __launch_bounds__(QR_THREADS) void k_harmonic_leja(const double2 *H, int ldh, int d, double beta,
+                                                              double2 *work, double2 *roots, double *info) {
     extern __shared__ double2 lds_mat[];
+    __shared__ QrShared qsh;
     const int tid = threadIdx.x, nt = blockDim.x;
     double2 *A = work;                 // d x d (global path)
     double2 *f = work + (long)d * d;   // d
@@ -439,8 +468,7 @@ __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh,
                 st(&M(i, j), 0, v);
             }
         __syncthreads();
-        rc = d <= 128 ? hess_eigvals<2>(M, d, roots, lds_mat + packed_hess_size(d))
-                      : hess_eigvals<3>(M, d, roots, lds_mat + packed_hess_size(d));
+        rc = hess_eigvals<1>(M, d, roots, qsh);
     } else {
         GlobalMat M{A, d};
         for (long e = tid; e < (long)d * d; e += nt) {
@@ -450,7 +478,7 @@ __global__ __launch_bounds__(64) void k_harmonic_leja(const double2 *H, int ldh,
             st(A, e, v);
         }
         __syncthreads();
-        rc = hess_eigvals<8>(M, d, roots, rot);   // rot/rs (2d entries) are free again
+        rc = hess_eigvals<2>(M, d, roots, qsh);
     }
     if (rc && tid == 0) s_status = -1;
     __syncthreads();
@@ -537,12 +565,12 @@ int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, doub
     double2 *work = (double2 *)ws_get(ctx, WS_DENSE, ((size_t)d * d + 8 * d + 16) * sizeof(double2));
     if (!work) return MPMC_ENOMEM;
     const size_t lb = (size_t)(packed_hess_size(d) + 2 * d) * sizeof(double2);
-    const bool lds = d <= 192 && want_lds(ctx, k_harmonic_leja<1>, lb);   // LDS path: <= 3 columns per lane
+    const bool lds = d <= 192 && want_lds(ctx, k_harmonic_leja<1>, lb);   // LDS path: one column per thread
     if (lds)
-        k_harmonic_leja<1><<<1, 64, lb, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
+        k_harmonic_leja<1><<<1, QR_THREADS, lb, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
                                                        (double2 *)roots_dev, info_dev);
     else
-        k_harmonic_leja<0><<<1, 64, 0, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
+        k_harmonic_leja<0><<<1, QR_THREADS, 0, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
                                                       (double2 *)roots_dev, info_dev);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
@@ -550,24 +578,24 @@ int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, doub
 
 // ------------------------------------------------- eigenvalues of H_m --
 template <int use_lds>
-__global__ __launch_bounds__(64) void k_hess_eigs(const double2 *H, int ldh, int m, double2 *work, double2 *ev,
-                                                  double *info) {
+__global__ __launch_bounds__(QR_THREADS) void k_hess_eigs(const double2 *H, int ldh, int m, double2 *work,
+                                                          double2 *ev, double *info) {
     extern __shared__ double2 lds_mat[];
+    __shared__ QrShared qsh;
     int rc;
     if constexpr (use_lds != 0) {
         PackedMat M{lds_mat};
         for (int j = 0; j < m; ++j)
             for (int i = threadIdx.x; i <= (j + 1 < m ? j + 1 : m - 1); i += blockDim.x) M(i, j) = H[i + (long)j * ldh];
         __syncthreads();
-        rc = m <= 128 ? hess_eigvals<2>(M, m, ev, lds_mat + packed_hess_size(m))
-                      : hess_eigvals<3>(M, m, ev, lds_mat + packed_hess_size(m));
+        rc = hess_eigvals<1>(M, m, ev, qsh);
     } else {
         for (long e = threadIdx.x; e < (long)m * m; e += blockDim.x) {
             const int i = (int)(e % m), j = (int)(e / m);
             work[e] = (i <= j + 1) ? H[i + (long)j * ldh] : make_double2(0.0, 0.0);
         }
         __syncthreads();
-        rc = hess_eigvals<8>(GlobalMat{work, m}, m, ev, work + (size_t)m * m);
+        rc = hess_eigvals<2>(GlobalMat{work, m}, m, ev, qsh);
     }
     if (threadIdx.x == 0) info[0] = rc;
 }
@@ -577,11 +605,11 @@ int dense_hess_eigs(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, double *
     double2 *work = (double2 *)ws_get(ctx, WS_DENSE, ((size_t)m * m + 2 * m) * sizeof(double2));
     if (!work) return MPMC_ENOMEM;
     const size_t lb = (size_t)(packed_hess_size(m) + 2 * m) * sizeof(double2);
-    const bool lds = m <= 192 && want_lds(ctx, k_hess_eigs<1>, lb);   // LDS path: <= 3 columns per lane
+    const bool lds = m <= 192 && want_lds(ctx, k_hess_eigs<1>, lb);   // LDS path: one column per thread
     if (lds)
-        k_hess_eigs<1><<<1, 64, lb, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev, info_dev);
+        k_hess_eigs<1><<<1, QR_THREADS, lb, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev, info_dev);
     else
-        k_hess_eigs<0><<<1, 64, 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev, info_dev);
+        k_hess_eigs<0><<<1, QR_THREADS, 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev, info_dev);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
