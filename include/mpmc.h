@@ -253,19 +253,23 @@ int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl 
                int max_outer, int *iters_host, double *relres_host);
 
 /* ---------------------------------------------------------------- autotuner */
-/* The multi-RHS Wilson kernel (nrhs a multiple of 64) has six variants
- * 0..5 that differ only in how the work is laid out on the GPU, never in the
- * arithmetic (results are bit-identical):
+/* The multi-RHS Wilson kernel (nrhs a multiple of 64) has variants
+ * 0 .. mpmc_wilson_variant_count() - 1 (currently 10) that differ only in how
+ * the work is laid out on the GPU, never in the arithmetic (results are
+ * bit-identical):
  *   bit 0    -- occupancy target: 1 = more wavefronts per SIMD (FP32/FP16S:
  *               3, FP64: 2), 0 = more registers per wavefront (FP32/FP16S: 2,
  *               FP64: 1);
- *   bits 1-2 -- traversal: 0 = site-major (a workgroup covers 256/nrhs sites
+ *   bits 1-3 -- traversal: 0 = site-major (a workgroup covers 256/nrhs sites
  *               x nrhs right-hand sides), 1 = 64-wide right-hand-side chunks
  *               (a workgroup covers 4 sites x 64 right-hand sides; all sites
  *               of a chunk before the next chunk), 2 = chunks as in 1 with
  *               the sites of a chunk in 4D-blocked order (blocks of extent 4
  *               along each direction whose length allows it, lexicographic
- *               inside and across blocks).
+ *               inside and across blocks), 3 and 4 = blocked as in 2 with 16-
+ *               and 32-wide chunks (a wavefront covers 4 or 2 sites, links
+ *               loaded per lane); 3 and 4 need V % 16 == 0 and fall back to 2
+ *               otherwise.
  * Defaults: variant 5 for FP32/FP16S, 4 for FP64 (blocked traversal).
  * mpmc_autotune times every variant on (nrhs, prec) with scratch vectors of
  * the context (2 warm-up + 5 timed launches each, HIP events) and keeps the
@@ -273,13 +277,15 @@ int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl 
  * including those inside polynomials, solves and level estimates.
  * variant_host (may be NULL) receives the choice (-1 when nrhs is not a
  * multiple of 64: nothing to tune); us_host (may be NULL) receives
- * double[6] microseconds per launch per variant.  Does not count MVPs and
+ * double[mpmc_wilson_variant_count()] microseconds per launch per variant.  Does not count MVPs and
  * does not enter mpmc_timing_read.  Synchronises. */
 int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host, double *us_host);
-/* Pin variant (0..5) for (nrhs, prec); -1 restores the default.  The fused
+/* Number of Wilson kernel variants (the length of mpmc_autotune's us_host). */
+int mpmc_wilson_variant_count(void);
+/* Pin a variant for (nrhs, prec); -1 restores the default.  The fused
  * polynomial step of mpmc_level_estimate uses the blocked traversal when the
  * site count is a multiple of 4, unless a variant is pinned here: then it
- * follows that variant's traversal bits (2: blocked, else site-major).  The
+ * follows that variant's traversal bits (2-4: blocked, else site-major).  The
  * autotuner's choice does not change the fused step. */
 int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant);
 

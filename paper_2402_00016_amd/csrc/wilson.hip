@@ -407,6 +407,19 @@ __device__ __forceinline__ bool locate(long V, int N, long &s, int &r, const int
             else s = (long)ss;
             r = (int)(ch * 64u + (threadIdx.x & 63u));
         }
+    } else if constexpr (ORDER >= 3) {
+        // narrow chunks: a wavefront covers S = 64 / W sites x W right-hand
+        // sides of one W-wide chunk (ORDER 3: W = 16, ORDER 4: W = 32), sites
+        // in the blocked order of the site table, all sites of a chunk before
+        // the next chunk (needs N % 64 == 0 and V % S == 0)
+        constexpr unsigned W = ORDER == 3 ? 16u : 32u, S = 64u / W;
+        const unsigned w0 = tile * 256u + ((unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
+        if (w0 >= total) return false;
+        const unsigned lane = threadIdx.x & 63u;
+        const unsigned wv = w0 >> 6, wpc = (unsigned)V / S;
+        const unsigned ch = wv / wpc, q = (wv - ch * wpc) * S + lane / W;
+        s = (long)order[q];
+        r = (int)(ch * W + lane % W);
     } else {
         const unsigned t = tile * 256u + threadIdx.x;
         if (t >= total) return false;
@@ -435,19 +448,21 @@ struct WOut {
 // allow).  The uniform kernels come in two targets chosen by the autotuner:
 // HI = 1 asks for more wavefronts (FP32/FP16S: 3, <= 168 VGPRs; FP64: 2),
 // HI = 0 for more registers (FP32/FP16S: 2; FP64: no target).
-template <int P, bool UNI, int HI = 1>
+template <int P, bool UNI, int HI = 1, int ORDER = 0>
 struct Occ {
-    static constexpr int wpe = !UNI ? 1 : (P == MPMC_FP64 ? (HI ? 2 : 1) : (HI ? 3 : 2));
+    static constexpr int wpe = (!UNI && ORDER < 3) ? 1 : (P == MPMC_FP64 ? (HI ? 2 : 1) : (HI ? 3 : 2));
 };
 
 // Kernel variants of the autotuner: bit 0 selects the occupancy target
-// (Occ::HI), bits 1-2 the traversal order of locate() (0 site-major, 1
-// chunk-major, 2 chunk-major over the blocked site order).
-constexpr int WILSON_VARIANTS = 6;
+// (Occ::HI), bits 1-3 the traversal order of locate() (0 site-major, 1
+// chunk-major, 2 chunk-major over the blocked site order, 3 and 4 the same with
+// 16- and 32-wide chunks, four and two sites per wavefront and per-lane
+// links).  Orders 3 and 4 need V % 16 == 0; elsewhere they fall back to 2.
+constexpr int WILSON_VARIANTS = 10;
 static inline int default_variant(int prec) { return prec == MPMC_FP64 ? 4 : 5; }
 
 template <int P, bool UNI, int HI = 1, int ORDER = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI, HI>::wpe))) void k_wilson(const void *__restrict__ b, const float *__restrict__ bsc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI, HI, ORDER>::wpe))) void k_wilson(const void *__restrict__ b, const float *__restrict__ bsc,
                                                 const int *__restrict__ nbr,
                                                 const typename LinkT<P>::type *__restrict__ links, WOut o, long V,
                                                 int N, const int *__restrict__ order) {
@@ -653,20 +668,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_F
                                                     double2 *__restrict__ partial, long V, int N, int first_step,
                                                     const int *__restrict__ order) {
     using T = typename Store<P>::real;
+    constexpr bool U = ORDER <= 2;   // one site per wavefront (else 2 or 4, per-lane links)
     const WIn<P> in{b, nullptr, nbr, links};
     __shared__ double2 red[256];
     long s;
     int r;
-    const bool live = locate<true, ORDER>(V, N, s, r, order);
+    const bool live = locate<U, ORDER>(V, N, s, r, order);
     cpx<double> dot = mk(0.0, 0.0);
     if (live) {
         cpx<T> acc[4][3];
-        hopping<P, true>(in, s, r, N, 1.0f, acc);
+        hopping<P, U>(in, s, r, N, 1.0f, acc);
         pin_acc(acc);
         const uint32_t code = codes[s * N + r];
         const T kap = (T)kappa;
         const cpx<T> cc = mk((T)c.x, (T)c.y);
-        const SiteAcc<P, true> W(in.b, nullptr, s, N, (uint32_t)r), O(out, nullptr, s, N, (uint32_t)r);
+        const SiteAcc<P, U> W(in.b, nullptr, s, N, (uint32_t)r), O(out, nullptr, s, N, (uint32_t)r);
         cpx<T> wv[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) wv[k] = W.ld(k);
@@ -689,6 +705,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_F
     }
     red[threadIdx.x] = make_double2(dot.re, dot.im);
     __syncthreads();
+    if constexpr (ORDER >= 3) {
+        // narrow chunks: a tile holds 256 / W sites x the W right-hand sides
+        // [W c, W c + W) of chunk c (V % 16 == 0); one partial per (tile, rhs),
+        // the sites summed in a fixed order
+        constexpr int W = ORDER == 3 ? 16 : 32;
+        if ((int)threadIdx.x < W) {
+            cpx<double> sum = mk(0.0, 0.0);
+#pragma unroll
+            for (int g = 0; g < 256 / W; ++g) {
+                const double2 v = red[threadIdx.x + g * W];
+                sum = mk(sum.re + v.x, sum.im + v.y);
+            }
+            const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+            const cpx<double> term = mk(cnext.x, cnext.y) * sum;
+            double2 *pp = partial + (long)tile * W + threadIdx.x;
+            if (first_step) {
+                *pp = make_double2(term.re, term.im);
+            } else {
+                double2 old = *pp;
+                *pp = make_double2(old.x + term.re, old.y + term.im);
+            }
+        }
+        return;
+    }
     if constexpr (ORDER != 0) {
         // chunk-major tiles: the four wavefronts share the right-hand sides
         // [64c, 64c + 64) of chunk c = 4 tile / V (V % 4 == 0); one partial per
@@ -762,17 +802,17 @@ __global__ void k_dot_finish(const double2 *__restrict__ partial, int nblocks, i
     }
 }
 
-// out[r] = sum of partial[t*64 + r%64] over the V/4 tiles t of chunk r/64
-// (chunk-major fused steps), in a fixed order
-__global__ void k_dot_finish_chunk(const double2 *__restrict__ partial, long tiles_per_chunk, double2 *__restrict__ out,
-                                   int accumulate, double sign) {
+// out[r] = sum of partial[t*width + r%width] over the tiles t of chunk
+// r/width (chunk-major fused steps), in a fixed order
+__global__ void k_dot_finish_chunk(const double2 *__restrict__ partial, long tiles_per_chunk, int width,
+                                   double2 *__restrict__ out, int accumulate, double sign) {
     __shared__ double2 red[256];
     const int r = blockIdx.x;
-    const long t0 = (long)(r / 64) * tiles_per_chunk;
-    const int lane = r % 64;
+    const long t0 = (long)(r / width) * tiles_per_chunk;
+    const int lane = r % width;
     double2 a = make_double2(0, 0);
     for (long t = threadIdx.x; t < tiles_per_chunk; t += blockDim.x) {
-        const double2 v = partial[(t0 + t) * 64 + lane];
+        const double2 v = partial[(t0 + t) * width + lane];
         a.x += v.x;
         a.y += v.y;
     }
@@ -825,24 +865,30 @@ static WIn<P> make_in(const mpmc_ctx *ctx, const void *b, int nrhs) {
 // Kernel variant for (nrhs, prec): pinned or tuned by the autotuner, else the default.
 static int wilson_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
     const auto it = ctx->tune.find(std::make_pair(nrhs, prec));
-    return it == ctx->tune.end() ? default_variant(prec) : it->second;
+    const int v = it == ctx->tune.end() ? default_variant(prec) : it->second;
+    return (v >> 1) >= 3 && ctx->V % 16 != 0 ? (v & 1) | 4 : v;
 }
 
-// The fused level step takes the blocked order whenever its chunk tiles hold
-// one chunk each (V % 4 == 0), and the site-major order otherwise; a variant
-// set explicitly for (nrhs, prec) with mpmc_tune_set selects blocked (its
-// traversal bits are 2) or site-major (any other variant).  The autotuner,
-// which times the plain operator, does not change it.
-static bool dot_blocked(const mpmc_ctx *ctx, int nrhs, int prec) {
-    if (ctx->V % 4 != 0) return false;
+// The fused level step takes the 64-wide blocked order whenever its chunk
+// tiles hold one chunk each (V % 4 == 0), and the site-major order otherwise;
+// a variant set explicitly for (nrhs, prec) with mpmc_tune_set selects its
+// traversal (orders 0 and 1: site-major; 3 and 4 need V % 16 == 0).  The
+// autotuner, which times the plain operator, does not change it.
+constexpr int kDotDefaultOrder = 2;   // 64-wide blocked chunks: fastest measured
+static int dot_order(const mpmc_ctx *ctx, int nrhs, int prec) {
+    if (ctx->V % 4 != 0) return 0;
     const auto it = ctx->tune_explicit.find(std::make_pair(nrhs, prec));
-    return it == ctx->tune_explicit.end() || (it->second >> 1) == 2;
+    const int o = it == ctx->tune_explicit.end() ? kDotDefaultOrder : it->second >> 1;
+    if (o >= 3) return ctx->V % 16 == 0 ? o : 2;
+    return o == 2 ? 2 : 0;
 }
+static int dot_width(int order, int nrhs) { return order == 3 ? 16 : order == 4 ? 32 : order == 2 ? 64 : (nrhs < 256 ? nrhs : 256); }
 
 template <int P, int V_>
 static void launch_uniform(mpmc_ctx *ctx, const WIn<P> &in, const WOut &o, int nrhs, unsigned grid) {
-    k_wilson<P, true, V_ & 1, (V_ >> 1)><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs,
-                                                                      ctx->site_order);
+    constexpr int ORDER = V_ >> 1;
+    k_wilson<P, (ORDER <= 2), V_ & 1, ORDER><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V,
+                                                                          nrhs, ctx->site_order);
 }
 
 template <int P>
@@ -863,7 +909,11 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs) {
         case 2: launch_uniform<P, 2>(ctx, in, o, nrhs, grid); break;
         case 3: launch_uniform<P, 3>(ctx, in, o, nrhs, grid); break;
         case 4: launch_uniform<P, 4>(ctx, in, o, nrhs, grid); break;
-        default: launch_uniform<P, 5>(ctx, in, o, nrhs, grid); break;
+        case 5: launch_uniform<P, 5>(ctx, in, o, nrhs, grid); break;
+        case 6: launch_uniform<P, 6>(ctx, in, o, nrhs, grid); break;
+        case 7: launch_uniform<P, 7>(ctx, in, o, nrhs, grid); break;
+        case 8: launch_uniform<P, 8>(ctx, in, o, nrhs, grid); break;
+        default: launch_uniform<P, 9>(ctx, in, o, nrhs, grid); break;
         }
     } else {
         k_wilson<P, false><<<grid, 256, 0, ctx->stream>>>(in.b, in.bsc, in.nbr, in.links, o, ctx->V, nrhs, nullptr);
@@ -945,34 +995,43 @@ int wilson_noise_codes(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t f
     return MPMC_OK;
 }
 
+template <int P>
+static void launch_dot(mpmc_ctx *ctx, int dord, unsigned grid, const WIn<P> &in, void *wout, const uint32_t *codes,
+                       double2 c, double2 cnext, int theta, double2 *partial, int nrhs, int first_step) {
+    const int *ord = dord ? ctx->site_order : nullptr;
+    switch (dord) {
+    case 2:
+        k_wilson_dot<P, 2><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext, ctx->kappa,
+                                                          theta, partial, ctx->V, nrhs, first_step, ord);
+        break;
+    case 3:
+        k_wilson_dot<P, 3><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext, ctx->kappa,
+                                                          theta, partial, ctx->V, nrhs, first_step, ord);
+        break;
+    case 4:
+        k_wilson_dot<P, 4><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext, ctx->kappa,
+                                                          theta, partial, ctx->V, nrhs, first_step, ord);
+        break;
+    default:
+        k_wilson_dot<P, 0><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext, ctx->kappa,
+                                                          theta, partial, ctx->V, nrhs, first_step, nullptr);
+    }
+}
+
 int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *codes, int nrhs, int prec, double2 c,
                     double2 cnext, int theta, double *partial, int first_step) {
     if (nrhs % 64 != 0 || (nrhs > 256 && nrhs % 256 != 0))
         return set_err(ctx, MPMC_EINVAL, "fused level step needs nrhs %% 64 == 0 (and %% 256 above 256)");
     const long work = ctx->V * nrhs;
     const unsigned grid = grid_for(work, 256);
-    const bool blocked = dot_blocked(ctx, nrhs, prec);
+    const int dord = dot_order(ctx, nrhs, prec);
     const int ev = timing_begin(ctx);
     if (prec == MPMC_FP64) {
         const WIn<MPMC_FP64> in = make_in<MPMC_FP64>(ctx, w, nrhs);
-        if (blocked)
-            k_wilson_dot<MPMC_FP64, 2><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
-                                                                      ctx->kappa, theta, (double2 *)partial, ctx->V,
-                                                                      nrhs, first_step, ctx->site_order);
-        else
-            k_wilson_dot<MPMC_FP64, 0><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
-                                                                      ctx->kappa, theta, (double2 *)partial, ctx->V,
-                                                                      nrhs, first_step, nullptr);
+        launch_dot<MPMC_FP64>(ctx, dord, grid, in, wout, codes, c, cnext, theta, (double2 *)partial, nrhs, first_step);
     } else if (prec == MPMC_FP32) {
         const WIn<MPMC_FP32> in = make_in<MPMC_FP32>(ctx, w, nrhs);
-        if (blocked)
-            k_wilson_dot<MPMC_FP32, 2><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
-                                                                      ctx->kappa, theta, (double2 *)partial, ctx->V,
-                                                                      nrhs, first_step, ctx->site_order);
-        else
-            k_wilson_dot<MPMC_FP32, 0><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
-                                                                      ctx->kappa, theta, (double2 *)partial, ctx->V,
-                                                                      nrhs, first_step, nullptr);
+        launch_dot<MPMC_FP32>(ctx, dord, grid, in, wout, codes, c, cnext, theta, (double2 *)partial, nrhs, first_step);
     }
     else
         return set_err(ctx, MPMC_EINVAL, "fused level step supports FP64 and FP32");
@@ -990,10 +1049,12 @@ int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *co
 int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, int prec, double *out, int accumulate,
                       double sign) {
     const long blocks = (ctx->V * nrhs + 255) / 256;
-    if (dot_blocked(ctx, nrhs, prec))
-        k_dot_finish_chunk<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, ctx->V / 4, (double2 *)out,
-                                                          accumulate, sign);
-    else
+    const int dord = dot_order(ctx, nrhs, prec);
+    if (dord) {
+        const int wd = dot_width(dord, nrhs);
+        k_dot_finish_chunk<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, ctx->V * wd / 256, wd,
+                                                          (double2 *)out, accumulate, sign);
+    } else
         k_dot_finish<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, (int)blocks, nrhs, (double2 *)out,
                                                     accumulate, sign);
     HIP_OR_RET(ctx, hipGetLastError());
@@ -1010,6 +1071,8 @@ MPMC_API int mpmc_apply_M(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int p
 }
 
 // ------------------------------------------------------------ autotuner --
+
+MPMC_API int mpmc_wilson_variant_count(void) { return WILSON_VARIANTS; }
 
 MPMC_API int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant) {
     if (!ctx) return MPMC_EINVAL;

@@ -67,6 +67,7 @@ _SIGS = {
     "mpmc_defl_keep": ([_vp, _i], _i),
     "mpmc_solve": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
     "mpmc_autotune": ([_vp, _i, _i, _pi, _vp], _i),
+    "mpmc_wilson_variant_count": ([], _i),
     "mpmc_release_workspace": ([_vp], _i),
     "mpmc_tune_set": ([_vp, _i, _i, _i], _i),
     "mpmc_net_n_params": ([], _i),
@@ -298,7 +299,7 @@ def mpmc_level_estimate(ctx, upper, lower, defl, theta, seed, stream, first, nno
     return samples, complex(corr[0]), mvps.value
 
 
-WILSON_VARIANTS = 6      # kernel variants of the multi-RHS Wilson kernel (include/mpmc.h)
+WILSON_VARIANTS = _L.mpmc_wilson_variant_count()   # kernel variants of the multi-RHS Wilson kernel
 
 
 def mpmc_autotune(ctx, nrhs, prec):

@@ -426,10 +426,11 @@ def test_autotune_variants_bit_identical(f44, prec):
     assert ctx.autotune(20, prec)[0] == -1     # not a multiple of 64: nothing to tune
 
 
-@pytest.mark.parametrize("prec,variants", [(FP32, (1, 3, 5)), (FP64, (0, 2, 4))])
+@pytest.mark.parametrize("prec,variants", [(FP32, (1, 3, 5, 7, 9)), (FP64, (0, 2, 4, 6, 8))])
 def test_fused_level_step_traversals(f44, prec, variants):
     """The fused level step under each traversal (site-major, chunk-major,
-    4D-blocked with its per-chunk reduction): per-element arithmetic is the
+    4D-blocked with 64-, 16- and 32-wide chunks and their per-chunk
+    reductions): per-element arithmetic is the
     same, so the samples differ only by the order of the FP64 sums; two
     samples are recomputed by the oracle."""
     dims, kappa, U, op, ctx = f44
