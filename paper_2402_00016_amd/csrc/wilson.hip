@@ -80,6 +80,7 @@ struct WIn {
     const float *__restrict__ bsc;               // its FP16S scales
     const int *__restrict__ nbr;
     const typename LinkT<P>::type *__restrict__ links;
+    __amdgpu_buffer_rsrc_t vrs;                  // narrow-chunk kernels: all of b (< 4 GiB)
 };
 
 // Element k of site sn, rhs r.  The row base (sn*12 + k)*N is formed as a
@@ -215,7 +216,8 @@ struct HopData {
     using T = typename Store<P>::real;
     cpx<T> psi[12];
     cpx<T> u[9];       // generic kernels: the link, per lane
-    uint32_t lw[2];    // uniform kernels: the link spread over lanes (dword i of the link in lane i)
+    uint32_t lw[3];    // uniform kernels: the link spread over lanes (dword i of the link in lane i);
+                       // narrow-chunk kernels: over each 16-lane row (dword 16 v + i in lane i of lw[v])
     T bsign;
 };
 
@@ -250,18 +252,115 @@ __device__ __forceinline__ cpx<typename Store<P>::real> link_lane(const uint32_t
     }
 }
 
-template <int P, bool UNI, int MU, bool FWD>
+// Narrow-chunk kernels (two or four sites per wavefront, one site per group
+// of 16 or 32 lanes): every 16-lane row loads its site's link, lane i of the
+// row dword i (and 16 + i, 32 + i), and a value is broadcast within the rows
+// with DPP row_newbcast.  Spinors go through one buffer resource covering the
+// whole operand: the lane's site row is a 32-bit VGPR offset, the component a
+// scalar offset.
+template <int P>
+__device__ __forceinline__ void load_link_rows(const typename LinkT<P>::type *lk, uint32_t lw[3]) {
+    const uint32_t *d = reinterpret_cast<const uint32_t *>(lk);
+    const unsigned i = threadIdx.x & 15u;
+    lw[0] = d[i];
+    if constexpr (P == MPMC_FP64) {
+        lw[1] = d[16 + i];
+        lw[2] = d[32 + (i < 4u ? i : 0u)];
+    } else {
+        lw[1] = d[16 + (i < 2u ? i : 0u)];
+    }
+}
+template <int D>
+__device__ __forceinline__ uint32_t link_row_dword(const uint32_t lw[3]) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)lw[D / 16], 0x150 + (D % 16), 0xf, 0xf, true);
+}
+template <int P, int I>
+__device__ __forceinline__ cpx<typename Store<P>::real> link_row_t(const uint32_t lw[3]) {
+    if constexpr (P == MPMC_FP64) {
+        const uint32_t a = link_row_dword<4 * I>(lw), b = link_row_dword<4 * I + 1>(lw);
+        const uint32_t c = link_row_dword<4 * I + 2>(lw), d = link_row_dword<4 * I + 3>(lw);
+        return mk(__builtin_bit_cast(double, ((uint64_t)b << 32) | a), __builtin_bit_cast(double, ((uint64_t)d << 32) | c));
+    } else {
+        return mk(__builtin_bit_cast(float, link_row_dword<2 * I>(lw)), __builtin_bit_cast(float, link_row_dword<2 * I + 1>(lw)));
+    }
+}
+template <int P>
+__device__ __forceinline__ cpx<typename Store<P>::real> link_row(const uint32_t lw[3], int i) {
+    switch (i) {   // i is a constant after unrolling; the DPP control must be one
+    case 0: return link_row_t<P, 0>(lw);
+    case 1: return link_row_t<P, 1>(lw);
+    case 2: return link_row_t<P, 2>(lw);
+    case 3: return link_row_t<P, 3>(lw);
+    case 4: return link_row_t<P, 4>(lw);
+    case 5: return link_row_t<P, 5>(lw);
+    case 6: return link_row_t<P, 6>(lw);
+    case 7: return link_row_t<P, 7>(lw);
+    default: return link_row_t<P, 8>(lw);
+    }
+}
+
+// One operand through a single buffer resource: per-lane site row offset,
+// per-component scalar offset (FP64 / FP32 storage, operand < 4 GiB).
+template <int P>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t vec_rsrc(const void *base, long V, int N) {
+    constexpr long es = P == MPMC_FP64 ? 16 : 8;
+    const unsigned long bytes = (unsigned long)V * 12 * N * es;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0,
+                                             (int)(uint32_t)(bytes < 0xffffffffUL ? bytes : 0xffffffffUL), kBufWord3);
+}
+template <int P>
+struct VecAcc {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t vo;
+    int N;
+    __device__ __forceinline__ VecAcc(__amdgpu_buffer_rsrc_t rs_, long site, int N_, uint32_t r) : rs(rs_), N(N_) {
+        constexpr long es = P == MPMC_FP64 ? 16 : 8;
+        vo = (uint32_t)((site * 12 * N_ + r) * es);
+    }
+    __device__ __forceinline__ cpx<typename Store<P>::real> ld(int k) const {
+        if constexpr (P == MPMC_FP64) {
+            const f64x2 v = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)vo, k * N * 16, 0));
+            return mk(v.x, v.y);
+        } else {
+            const f32x2 v = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vo, k * N * 8, 0));
+            return mk(v.x, v.y);
+        }
+    }
+    __device__ __forceinline__ void st(int k, cpx<typename Store<P>::real> v) const {
+        if constexpr (P == MPMC_FP64) {
+            f64x2 d;
+            d.x = v.re;
+            d.y = v.im;
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4v, d), rs, (int)vo, k * N * 16, 0);
+        } else {
+            f32x2 d;
+            d.x = v.re;
+            d.y = v.im;
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, d), rs, (int)vo, k * N * 8, 0);
+        }
+    }
+};
+
+template <int P, bool UNI, int MU, bool FWD, bool NR = false>
 __device__ __forceinline__ void fetch(const WIn<P> &in, long s, int r, int N, HopData<P> &H) {
     using T = typename Store<P>::real;
     const int raw = in.nbr[s * 8 + (FWD ? 0 : 4) + MU];
     const long sn = (long)(raw & 0x7fffffff);
     H.bsign = raw < 0 ? T(-1) : T(1);
-    const SiteAcc<P, UNI> A(in.b, in.bsc, sn, N, (uint32_t)r);
+    if constexpr (NR && P != MPMC_FP16S) {
+        const VecAcc<P> A(in.vrs, sn, N, (uint32_t)r);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) H.psi[k] = A.ld(k);
+        for (int k = 0; k < 12; ++k) H.psi[k] = A.ld(k);
+    } else {
+        const SiteAcc<P, UNI> A(in.b, in.bsc, sn, N, (uint32_t)r);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) H.psi[k] = A.ld(k);
+    }
     const auto *lk = in.links + ((FWD ? s : sn) * 4 + MU) * 9;
     if constexpr (UNI) {
         load_link_lanes<P>(lk, H.lw);
+    } else if constexpr (NR) {
+        load_link_rows<P>(lk, H.lw);
     } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -271,7 +370,7 @@ __device__ __forceinline__ void fetch(const WIn<P> &in, long s, int r, int N, Ho
     }
 }
 
-template <int P, bool UNI, int MU, bool FWD>
+template <int P, bool UNI, int MU, bool FWD, bool NR = false>
 __device__ __forceinline__ void apply(const HopData<P> &H, float g, cpx<typename Store<P>::real> acc[4][3]) {
     using T = typename Store<P>::real;
     using Pr = Proj<MU>;
@@ -294,6 +393,7 @@ __device__ __forceinline__ void apply(const HopData<P> &H, float g, cpx<typename
             const int li = FWD ? a * 3 + bb : bb * 3 + a;
             cpx<T> lv;
             if constexpr (UNI) lv = link_lane<P>(H.lw, li);
+            else if constexpr (NR) lv = link_row<P>(H.lw, li);
             else lv = H.u[li];
             const T ur = lv.re, ui = FWD ? lv.im : -lv.im;
             if constexpr (P == MPMC_FP64) {   // FP64 keeps fewer live registers this way
@@ -330,32 +430,32 @@ __device__ __forceinline__ void apply(const HopData<P> &H, float g, cpx<typename
 // direction i/2, forward for even i.  D HopData buffers rotate: the loads of
 // hops i+1 .. i+D-1 are in flight while hop i computes.
 #define MPMC_FENCE __builtin_amdgcn_sched_barrier(0)
-template <int P, bool UNI, int I>
+template <int P, bool UNI, bool NR, int I>
 __device__ __forceinline__ void fetch_hop(const WIn<P> &in, long s, int r, int N, HopData<P> &H) {
-    fetch<P, UNI, I / 2, (I % 2) == 0>(in, s, r, N, H);
+    fetch<P, UNI, I / 2, (I % 2) == 0, NR>(in, s, r, N, H);
 }
-template <int P, bool UNI, int D, int I>
+template <int P, bool UNI, bool NR, int D, int I>
 __device__ __forceinline__ void hop_step(const WIn<P> &in, long s, int r, int N, float g, HopData<P> (&H)[D],
                                          cpx<typename Store<P>::real> acc[4][3]) {
     if constexpr (I < 8) {
-        apply<P, UNI, I / 2, (I % 2) == 0>(H[I % D], g, acc);
+        apply<P, UNI, I / 2, (I % 2) == 0, NR>(H[I % D], g, acc);
         MPMC_FENCE;
         if constexpr (I + D < 8) {
-            fetch_hop<P, UNI, I + D>(in, s, r, N, H[I % D]);
+            fetch_hop<P, UNI, NR, I + D>(in, s, r, N, H[I % D]);
             MPMC_FENCE;
         }
-        hop_step<P, UNI, D, I + 1>(in, s, r, N, g, H, acc);
+        hop_step<P, UNI, NR, D, I + 1>(in, s, r, N, g, H, acc);
     }
 }
-template <int P, bool UNI, int D, int I>
+template <int P, bool UNI, bool NR, int D, int I>
 __device__ __forceinline__ void hop_prologue(const WIn<P> &in, long s, int r, int N, HopData<P> (&H)[D]) {
     if constexpr (I < D) {
-        fetch_hop<P, UNI, I>(in, s, r, N, H[I]);
+        fetch_hop<P, UNI, NR, I>(in, s, r, N, H[I]);
         MPMC_FENCE;
-        hop_prologue<P, UNI, D, I + 1>(in, s, r, N, H);
+        hop_prologue<P, UNI, NR, D, I + 1>(in, s, r, N, H);
     }
 }
-template <int P, bool UNI, int D = 2>
+template <int P, bool UNI, bool NR = false, int D = 2>
 __device__ __forceinline__ void hopping(const WIn<P> &in, long s, int r, int N, float g,
                                         cpx<typename Store<P>::real> acc[4][3]) {
     using T = typename Store<P>::real;
@@ -364,8 +464,8 @@ __device__ __forceinline__ void hopping(const WIn<P> &in, long s, int r, int N, 
 #pragma unroll
         for (int c = 0; c < 3; ++c) acc[sp][c] = mk(T(0), T(0));
     HopData<P> H[D];
-    hop_prologue<P, UNI, D, 0>(in, s, r, N, H);
-    hop_step<P, UNI, D, 0>(in, s, r, N, g, H, acc);
+    hop_prologue<P, UNI, NR, D, 0>(in, s, r, N, H);
+    hop_step<P, UNI, NR, D, 0>(in, s, r, N, g, H, acc);
 }
 #undef MPMC_FENCE
 
@@ -467,12 +567,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI,
                                                 const typename LinkT<P>::type *__restrict__ links, WOut o, long V,
                                                 int N, const int *__restrict__ order) {
     using T = typename Store<P>::real;
-    const WIn<P> in{b, bsc, nbr, links};
+    constexpr bool NR = ORDER >= 3;   // narrow chunks: row-distributed links, whole-operand buffer
+    WIn<P> in{b, bsc, nbr, links};
+    if constexpr (NR && P != MPMC_FP16S) in.vrs = vec_rsrc<P>(b, V, N);
     long s;
     int r;
     if (!locate<UNI, ORDER>(V, N, s, r, order)) return;
     cpx<T> acc[4][3];
-    hopping<P, UNI>(in, s, r, N, o.g, acc);
+    hopping<P, UNI, NR>(in, s, r, N, o.g, acc);
     pin_acc(acc);
     // Epilogue without per-component control flow: all operand loads are
     // issued together, the optional terms enter through coefficients.
@@ -668,8 +770,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_F
                                                     double2 *__restrict__ partial, long V, int N, int first_step,
                                                     const int *__restrict__ order) {
     using T = typename Store<P>::real;
-    constexpr bool U = ORDER <= 2;   // one site per wavefront (else 2 or 4, per-lane links)
-    const WIn<P> in{b, nullptr, nbr, links};
+    constexpr bool U = ORDER <= 2;   // one site per wavefront (else 2 or 4, row-distributed links)
+    WIn<P> in{b, nullptr, nbr, links};
+    if constexpr (!U) in.vrs = vec_rsrc<P>(b, V, N);
     __shared__ double2 red[256];
     long s;
     int r;
@@ -677,7 +780,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_F
     cpx<double> dot = mk(0.0, 0.0);
     if (live) {
         cpx<T> acc[4][3];
-        hopping<P, U>(in, s, r, N, 1.0f, acc);
+        hopping<P, U, !U>(in, s, r, N, 1.0f, acc);
         pin_acc(acc);
         const uint32_t code = codes[s * N + r];
         const T kap = (T)kappa;
