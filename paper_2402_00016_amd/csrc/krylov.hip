@@ -4,7 +4,7 @@
 // classical Gram-Schmidt applied twice (two fused dot/update passes per step,
 // FP64 sums), breakdown detection on the device (no host round trip per
 // step), then the harmonic Ritz values and their Leja order in one FP64
-// single-wavefront kernel.  mpmc_apply_poly evaluates
+// one-workgroup kernel.  mpmc_apply_poly evaluates
 //     p(M) x = sum_k w_k / theta_k,  w_1 = x,  w_{k+1} = w_k - M w_k / theta_k
 // with one fused Wilson kernel per step (w update and y accumulation in the
 // same pass), and the double polynomial as p_in(M) [p_out(phi_in(M)) x].
