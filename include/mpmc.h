@@ -252,6 +252,19 @@ int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl 
                const mpmc_net *net, int restart, double tol, int inner_prec,
                int max_outer, int *iters_host, double *relres_host);
 
+/* Several lattices in ONE launch (not in the paper: batching of independent
+ * problems): y[i] = M_i x[i] for the contexts ctxs[0..count), 1 <= count <= 8,
+ * all on the device of ctxs[0] and run on ctxs[0]'s stream.  Every context
+ * keeps its own lattice, kappa and links; nrhs (a multiple of 64) right-hand
+ * sides per lattice, prec FP64 or FP32, internal layout, V % 4 == 0 for every
+ * lattice.  The grid concatenates the lattices' tile ranges (4D-blocked,
+ * 64-wide chunks), so each lattice's result is bit-identical to mpmc_apply_M
+ * with Wilson variant 4 or 5.  x[i] and y[i] must not alias.  Counts nrhs MVPs
+ * on every context; the launch's algorithmic bytes enter ctxs[0]'s timing.
+ * Asynchronous. */
+int mpmc_apply_M_batch(mpmc_ctx *const *ctxs, const void *const *x, void *const *y, int count, int nrhs,
+                       int prec, int dagger, int theta);
+
 /* ---------------------------------------------------------------- autotuner */
 /* The multi-RHS Wilson kernel (nrhs a multiple of 64) has variants
  * 0 .. mpmc_wilson_variant_count() - 1 (currently 10) that differ only in how

@@ -485,8 +485,8 @@ __device__ __forceinline__ void pin_acc(cpx<T> acc[4][3]) {
 // consecutive right-hand sides of one site, so the site follows from the
 // wavefront's first thread with scalar arithmetic.
 template <bool UNI, int ORDER = 0>
-__device__ __forceinline__ bool locate(long V, int N, long &s, int &r, const int *__restrict__ order = nullptr) {
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+__device__ __forceinline__ bool locate_at(unsigned tile, long V, int N, long &s, int &r,
+                                          const int *__restrict__ order) {
     const unsigned total = (unsigned)(V * N);
     if constexpr (UNI) {
         const unsigned w0 = tile * 256u + ((unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x) & ~63u);
@@ -529,6 +529,10 @@ __device__ __forceinline__ bool locate(long V, int N, long &s, int &r, const int
     }
     return true;
 }
+template <bool UNI, int ORDER = 0>
+__device__ __forceinline__ bool locate(long V, int N, long &s, int &r, const int *__restrict__ order = nullptr) {
+    return locate_at<UNI, ORDER>(xcd_tile(blockIdx.x, gridDim.x), V, N, s, r, order);
+}
 
 struct WOut {
     void *out;
@@ -561,18 +565,11 @@ struct Occ {
 constexpr int WILSON_VARIANTS = 10;
 static inline int default_variant(int prec) { return prec == MPMC_FP64 ? 4 : 5; }
 
-template <int P, bool UNI, int HI = 1, int ORDER = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI, HI, ORDER>::wpe))) void k_wilson(const void *__restrict__ b, const float *__restrict__ bsc,
-                                                const int *__restrict__ nbr,
-                                                const typename LinkT<P>::type *__restrict__ links, WOut o, long V,
-                                                int N, const int *__restrict__ order) {
+// Everything one thread does for (site s, rhs r) once located.
+template <int P, bool UNI, int ORDER>
+__device__ __forceinline__ void wilson_site(const WIn<P> in, const WOut o, long s, int r, int N) {
     using T = typename Store<P>::real;
     constexpr bool NR = ORDER >= 3;   // narrow chunks: row-distributed links, whole-operand buffer
-    WIn<P> in{b, bsc, nbr, links};
-    if constexpr (NR && P != MPMC_FP16S) in.vrs = vec_rsrc<P>(b, V, N);
-    long s;
-    int r;
-    if (!locate<UNI, ORDER>(V, N, s, r, order)) return;
     cpx<T> acc[4][3];
     hopping<P, UNI, NR>(in, s, r, N, o.g, acc);
     pin_acc(acc);
@@ -633,6 +630,65 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI,
             for (int k = 0; k < 12; ++k) Y.st(k, yv[k] + ga * res[k]);
         }
     }
+}
+
+template <int P, bool UNI, int HI = 1, int ORDER = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, UNI, HI, ORDER>::wpe))) void k_wilson(const void *__restrict__ b, const float *__restrict__ bsc,
+                                                const int *__restrict__ nbr,
+                                                const typename LinkT<P>::type *__restrict__ links, WOut o, long V,
+                                                int N, const int *__restrict__ order) {
+    WIn<P> in{b, bsc, nbr, links};
+    if constexpr (ORDER >= 3 && P != MPMC_FP16S) in.vrs = vec_rsrc<P>(b, V, N);
+    long s;
+    int r;
+    if (!locate<UNI, ORDER>(V, N, s, r, order)) return;
+    wilson_site<P, UNI, ORDER>(in, o, s, r, N);
+}
+
+// ------------------------------------------------ batched lattices --
+// Several lattices (contexts) in one launch: the tile range of the grid is the
+// concatenation of the lattices' tile ranges (blocked 64-wide traversal, the
+// same per-element arithmetic as k_wilson<P, true, HI, 2>); a workgroup finds
+// its lattice by a scalar scan of the first-tile offsets.
+constexpr int WILSON_BATCH_MAX = 8;
+template <int P>
+struct LatticeArgs {
+    const void *b;
+    void *out;
+    const int *nbr;
+    const typename LinkT<P>::type *links;
+    const int *order;
+    long V;
+    double kappa;
+    unsigned tile0;   // first tile of this lattice in the grid
+};
+template <int P>
+struct BatchArgs {
+    LatticeArgs<P> l[WILSON_BATCH_MAX];
+    int count;
+};
+
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, true, 1, 2>::wpe))) void k_wilson_batch(
+    BatchArgs<P> a, int N, float g, int theta) {
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    int q = 0;
+    for (int i = 1; i < a.count; ++i)
+        if (tile >= a.l[i].tile0) q = i;
+    const LatticeArgs<P> &L = a.l[q];
+    WIn<P> in{L.b, nullptr, L.nbr, L.links};
+    WOut o{};
+    o.out = L.out;
+    o.kappa = L.kappa;
+    o.alpha = make_double2(0, 0);
+    o.beta = make_double2(1, 0);
+    o.gamma = make_double2(0, 0);
+    o.g = g;
+    o.theta = theta;
+    long s;
+    int r;
+    if (!locate_at<true, 2>(tile - L.tile0, L.V, N, s, r, L.order)) return;
+    wilson_site<P, true, 2>(in, o, s, r, N);
 }
 
 // ---------------------------------------------------- single vectors --
@@ -1171,6 +1227,60 @@ MPMC_API int mpmc_apply_M(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int p
     if (x == y) return set_err(ctx, MPMC_EINVAL, "mpmc_apply_M: x and y must not alias");
     return wilson_launch_full(ctx, x, nullptr, y, nullptr, nrhs, prec, make_double2(0, 0), make_double2(1, 0),
                               make_double2(0, 0), dagger ? 1 : 0, theta == MPMC_THETA_G5 ? 1 : 0);
+}
+
+// ------------------------------------------------------ batched apply --
+
+template <int P>
+static int launch_batch(mpmc_ctx *const *ctxs, const void *const *x, void *const *y, int count, int nrhs,
+                        int dagger, int theta) {
+    mpmc_ctx *c0 = ctxs[0];
+    BatchArgs<P> a{};
+    a.count = count;
+    unsigned tiles = 0;
+    double bytes = 0;
+    for (int i = 0; i < count; ++i) {
+        const mpmc_ctx *c = ctxs[i];
+        LatticeArgs<P> &L = a.l[i];
+        L.b = vref(c, x[i], nrhs, P).d;
+        L.out = y[i];
+        L.nbr = c->nbr;
+        L.links = reinterpret_cast<const typename LinkT<P>::type *>(P == MPMC_FP64 ? (const void *)c->links64
+                                                                                   : (const void *)c->links32);
+        L.order = c->site_order;
+        L.V = c->V;
+        L.kappa = c->kappa;
+        L.tile0 = tiles;
+        tiles += (unsigned)(c->V * nrhs / 256);
+        bytes += (double)c->V * ((double)nrhs * 2 * spinor_bytes(P) + link_bytes(P));
+    }
+    const int ev = timing_begin(c0);
+    k_wilson_batch<P><<<tiles, 256, 0, c0->stream>>>(a, nrhs, dagger ? -1.f : 1.f, theta);
+    HIP_OR_RET(c0, hipGetLastError());
+    if (ev >= 0) timing_end(c0, ev, P | MPMC_TIMING_PLAIN, bytes);
+    for (int i = 0; i < count; ++i) ctxs[i]->mvps += (uint64_t)nrhs;
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_apply_M_batch(mpmc_ctx *const *ctxs, const void *const *x, void *const *y, int count, int nrhs,
+                                int prec, int dagger, int theta) {
+    if (!ctxs || !ctxs[0]) return MPMC_EINVAL;
+    mpmc_ctx *c0 = ctxs[0];
+    if (!x || !y || count < 1 || count > WILSON_BATCH_MAX)
+        return set_err(c0, MPMC_EINVAL, "mpmc_apply_M_batch: 1..%d lattices", WILSON_BATCH_MAX);
+    if (nrhs < 64 || nrhs % 64 != 0 || (prec != MPMC_FP64 && prec != MPMC_FP32) ||
+        (theta != MPMC_THETA_I && theta != MPMC_THETA_G5))
+        return set_err(c0, MPMC_EINVAL, "mpmc_apply_M_batch: nrhs must be a multiple of 64, prec FP64 or FP32");
+    long total = 0;
+    for (int i = 0; i < count; ++i) {
+        const mpmc_ctx *c = ctxs[i];
+        if (!c || !x[i] || !y[i] || x[i] == y[i] || c->device != c0->device || c->V % 4 != 0)
+            return set_err(c0, MPMC_EINVAL, "mpmc_apply_M_batch: lattice %d: null, aliasing, other device or V %% 4 != 0", i);
+        total += c->V * nrhs;
+    }
+    if (total / 256 > 0x7fffffffL) return set_err(c0, MPMC_EINVAL, "mpmc_apply_M_batch: batch too large");
+    return prec == MPMC_FP64 ? launch_batch<MPMC_FP64>(ctxs, x, y, count, nrhs, dagger, theta)
+                             : launch_batch<MPMC_FP32>(ctxs, x, y, count, nrhs, dagger, theta);
 }
 
 // ------------------------------------------------------------ autotuner --

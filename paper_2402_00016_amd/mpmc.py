@@ -68,6 +68,7 @@ _SIGS = {
     "mpmc_solve": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
     "mpmc_autotune": ([_vp, _i, _i, _pi, _vp], _i),
     "mpmc_wilson_variant_count": ([], _i),
+    "mpmc_apply_M_batch": ([_vp, _vp, _vp, _i, _i, _i, _i, _i], _i),
     "mpmc_release_workspace": ([_vp], _i),
     "mpmc_tune_set": ([_vp, _i, _i, _i], _i),
     "mpmc_net_n_params": ([], _i),
@@ -309,6 +310,14 @@ def mpmc_autotune(ctx, nrhs, prec):
     return v.value, us
 
 
+def mpmc_apply_M_batch(ctxs, xs, ys, nrhs, prec, dagger=False, theta=THETA_I):
+    n = len(ctxs)
+    ch = (ctypes.c_void_p * n)(*[c for c in ctxs])
+    xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    yp = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+    _check(_L.mpmc_apply_M_batch(ch, xp, yp, n, int(nrhs), int(prec), int(dagger), int(theta)), ctxs[0])
+
+
 def mpmc_tune_set(ctx, nrhs, prec, variant):
     _check(_L.mpmc_tune_set(ctx, int(nrhs), int(prec), int(variant)), ctx)
 
@@ -521,6 +530,14 @@ class Context:
         y = self.vector(nrhs, prec) if out is None else out
         mpmc_apply_M(self.handle, x, y, nrhs, prec, int(dagger), theta)
         return y
+
+    @staticmethod
+    def apply_M_batch(ctxs, xs, nrhs, prec=FP32, dagger=False, theta=THETA_I, outs=None):
+        """y[i] = M_i x[i] for several contexts (lattices) in one launch on the
+        first context's stream."""
+        ys = [c.vector(nrhs, prec) for c in ctxs] if outs is None else outs
+        mpmc_apply_M_batch([c.handle for c in ctxs], xs, ys, nrhs, prec, dagger, theta)
+        return ys
 
     @property
     def mvps(self):

@@ -4,7 +4,9 @@
 (field, spin) along parallel-transport paths, so the same weights apply to
 any volume.  Reported per lattice: inner GMRES iterations, MVPs and wall time
 to a true relative residual of 1e-8, with and without the network, on the
-same Z(4) right-hand sides and the same deflation set.
+same Z(4) right-hand sides and the same deflation set.  Last, the four
+fields' Wilson applications (64 right-hand sides each) run as one batched
+launch and as one launch per lattice.
 
     python -m paper_2402_00016_amd.netstudy --lattices 12,16,20,24 --rhs 16
 
@@ -58,6 +60,32 @@ def compare(dims, link_eps, kappa, seed, weights, nrhs, nev, restart, tol):
     return out
 
 
+def batch_timing(lattices, link_eps, kappa, seed, nrhs=64, reps=10):
+    """The uneven lattices' Wilson applications in one batched launch against
+    one launch per lattice (FP32, same traversal, same results)."""
+    ctxs = [mpmc.Context((L,) * 4, kappa, inputs.gauge_links((L,) * 4, link_eps, seed + i))
+            for i, L in enumerate(lattices)]
+    xs = [c.noise(seed, 7, 0, nrhs, mpmc.FP32) for c in ctxs]
+    for c in ctxs:
+        c.tune_set(nrhs, mpmc.FP32, 5)
+    ys = [c.vector(nrhs, mpmc.FP32) for c in ctxs]
+
+    def separate():
+        for c, x, y in zip(ctxs, xs, ys):
+            c.apply_M(x, nrhs, mpmc.FP32, out=y)
+
+    def batched():
+        mpmc.Context.apply_M_batch(ctxs, xs, nrhs, mpmc.FP32, outs=ys)
+
+    out = {}
+    for name, fn in (("separate", separate), ("batched", batched)):
+        fn()
+        _, secs = timed(lambda: [fn() for _ in range(reps)])
+        out[name + "_ms"] = round(secs / reps * 1e3, 3)
+    out.update(lattices=[[L] * 4 for L in lattices], nrhs=nrhs)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--lattices", default="12,16,20,24")
@@ -82,6 +110,8 @@ def main(argv=None):
         print(json.dumps(r), flush=True)
         torch.cuda.empty_cache()
     print(json.dumps(dict(summary=rows)), flush=True)
+    print(json.dumps(dict(batch=batch_timing([int(v) for v in a.lattices.split(",")], a.eps, a.kappa, a.seed))),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -454,6 +454,38 @@ def test_fused_level_step_traversals(f44, prec, variants):
             assert abs(outs[-1][j] - Xr[j]) < 1e-5 * op.n
 
 
+@pytest.mark.parametrize("prec,variant", [(FP32, 5), (FP64, 4)])
+def test_apply_batch_matches_single(prec, variant):
+    """Uneven lattices in one batched launch: every lattice's result is
+    bit-identical to its own launch of the same traversal, and one of them is
+    checked against the oracle operator."""
+    shapes = [((4, 4, 4, 4), 0.115, 1), ((4, 4, 4, 8), 0.12, 2), ((6, 6, 6, 6), 0.11, 3), ((2, 4, 6, 8), 0.1, 4)]
+    N = 64
+    ctxs, xs, refs = [], [], []
+    for dims, kappa, seed in shapes:
+        U = inputs.gauge_links(dims, 0.5, seed=seed)
+        c = mpmc.Context(dims, kappa, U)
+        x = c.noise(seed, 3, 0, N, prec)
+        c.tune_set(N, prec, variant)
+        refs.append(host(c.apply_M(x, N, prec)).copy())
+        ctxs.append(c)
+        xs.append(x)
+    mv0 = [c.mvps for c in ctxs]
+    ys = mpmc.Context.apply_M_batch(ctxs, xs, N, prec)
+    for c, y, ref, m0 in zip(ctxs, ys, refs, mv0):
+        assert np.array_equal(host(y), ref)
+        assert c.mvps == m0 + N
+    dims, kappa, seed = shapes[2]
+    op = WilsonOp(dims, kappa, inputs.gauge_links(dims, 0.5, seed=seed))
+    got = host(ctxs[2].unpack(ys[2], N, prec))
+    want = op(z4_noise(seed, 3, 17, op.n))
+    assert rel(got[17], want) < (1e-13 if prec == FP64 else 1e-6)
+    with pytest.raises(mpmc.MpmcError):
+        mpmc.Context.apply_M_batch(ctxs, xs, 20, prec)
+    with pytest.raises(mpmc.MpmcError):
+        mpmc.Context.apply_M_batch(ctxs * 3, xs * 3, N, prec)
+
+
 @pytest.mark.parametrize("N", [64, 20])
 def test_solve_fp16_basis_matches_fp32(N):
     """FP16S Krylov basis (FP32 arithmetic, FP64 defect correction): same true
