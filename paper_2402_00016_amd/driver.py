@@ -368,3 +368,81 @@ def _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, c
             if math.sqrt(var / len(X)) <= target or len(X) >= max_noises:
                 break
         levels.append(LevelResult("term %d" % l, X, corr, mv, secs))
+
+
+# ------------------------------------------------ level-cost optimisation --
+# The paper leaves the optimisation of the cost function to future work,
+# naming the multilevel Monte Carlo literature (Conclusions).  With per-noise
+# variances V_l and costs C_l of the terms, the noise counts that minimise the
+# total cost sum_l N_l C_l under the error constraint sum_l V_l / N_l <= eps^2
+# follow from a Lagrange multiplier:
+#     N_l = eps^-2 sqrt(V_l / C_l) sum_k sqrt(V_k C_k),   cost = eps^-2 (sum_k sqrt(V_k C_k))^2.
+
+def optimal_noise_counts(variances, costs, eps, min_counts=(2, 3, 6)):
+    """(noise counts per term (rounded up, at least the minimum counts),
+    predicted total cost) for target standard error eps."""
+    V = np.asarray(variances, dtype=float)
+    C = np.asarray(costs, dtype=float)
+    if V.shape != C.shape or np.any(V < 0) or np.any(C <= 0) or not eps > 0:
+        raise ValueError("variances >= 0, costs > 0 of equal length and eps > 0 are required")
+    S = float(np.sum(np.sqrt(V * C)))
+    N = np.ceil(np.sqrt(V / C) * S / eps ** 2).astype(int)
+    lo = np.array([min_counts[min(l, len(min_counts) - 1)] for l in range(len(V))])
+    N = np.maximum(N, lo)
+    return N, float(np.sum(N * C))
+
+
+def estimate_optimized(ctx, plan: Plan, eps: float, pilot: int = 16, min_counts=(2, 3, 6), net=None,
+                       rounds: int = 4):
+    """Estimate with cost-optimal noise counts: `pilot` noises per term give
+    the variances and the per-noise MVP costs, optimal_noise_counts turns them
+    into counts for standard error eps, and each term is topped up to its
+    count (noise indices continue).  The variances are re-estimated from all
+    samples after each top-up and the counts recomputed, for at most `rounds`
+    rounds.  Returns (Estimate, noise counts used, predicted MVPs of the Monte
+    Carlo part)."""
+    mv0 = total_mvps(ctx)
+    t0 = time.perf_counter()
+    defl, polys, tnet, _ = build_setup(ctx, plan, train=plan.learned and net is None)
+    net = tnet if tnet is not None else net
+    t_setup = time.perf_counter() - t0
+    uppers = [None] + polys
+    lowers = polys + [None]
+    terms = []
+    for l, (up, lo) in enumerate(zip(uppers, lowers)):
+        d = defl if (up is not None and lo is not None and plan.deflate_levels) else (defl if up is None else None)
+        terms.append((up, lo, d))
+    pp = solve_preconditioner(ctx, plan, defl) if not plan.learned else None
+    ctx.set_level_solve_poly(pp)
+
+    def run(l, first, count):
+        up, lo, d = terms[l]
+        ts = time.perf_counter()
+        X, corr, m = ctx.level(up, lo, d, plan.theta, plan.seed, l, first, count, prec=plan.poly_prec,
+                               max_batch=plan.max_batch, solve_tol=plan.solve_tol,
+                               solve_restart=plan.solve_restart, solve_inner_prec=plan.solve_inner_prec,
+                               net=net if (up is None and plan.learned) else None)
+        return X, corr, m, time.perf_counter() - ts
+
+    try:
+        st = [list(run(l, 0, max(pilot, 2))) for l in range(len(terms))]   # [X, corr, mvps, seconds]
+        predicted = 0.0
+        for _ in range(rounds):
+            V = [float(np.sum(np.abs(X - X.mean()) ** 2) / (len(X) - 1)) for X, _, _, _ in st]
+            C = [max(m / len(X), 1e-3) for X, _, m, _ in st]
+            counts, predicted = optimal_noise_counts(V, C, eps, min_counts)
+            grew = False
+            for l in range(len(terms)):
+                extra = int(counts[l]) - len(st[l][0])
+                if extra > 0:
+                    Xe, corr, me, se = run(l, len(st[l][0]), extra)
+                    st[l] = [np.concatenate([st[l][0], Xe]), corr, st[l][2] + me, st[l][3] + se]
+                    grew = True
+            if not grew:
+                break
+        levels = [LevelResult("term %d" % l, X, corr, m, secs) for l, (X, corr, m, secs) in enumerate(st)]
+    finally:
+        ctx.set_level_solve_poly(None)
+    est, se = combine(levels)
+    return (Estimate(est, se, levels, t_setup, time.perf_counter() - t0, total_mvps(ctx) - mv0, polys=polys,
+                     defl_k=defl.k if defl is not None else 0), [L.n for L in levels], predicted)
