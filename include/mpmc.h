@@ -37,7 +37,7 @@
  *            key = (seed mod 2^32, seed >> 32), counter = (c / 64, noise index,
  *            stream, 0), k = (word[(c % 64) / 16] >> 2 (c % 16)) & 3.
  *            Noise vectors are regenerated from (seed, stream, index), never
- *            stored by the caller (Sec. 1: "Z(4) noise").
+ *            stored by the caller (Z(4) noise vectors, Sec. 1).
  *
  * Memory and ownership: every pointer named x, y, b, Z, U, canon or internal
  * is a DEVICE pointer owned by the caller (e.g. a torch tensor's data_ptr()),
