@@ -148,7 +148,8 @@ int mpmc_apply_M(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec,
 /* One GMRES(d) cycle (Sec. 3): Arnoldi with CGS2 for d steps from the
  * normalised Z(4) vector (seed, stream, index 0), then the harmonic Ritz values
  * eig(H_d + |h_{d+1,d}|^2 H_d^-H e_d e_d^T) in Leja order (largest modulus
- * first, then maximal sum of log distances), all in FP64 on the device.
+ * first, then maximal sum of log distances), all in FP64 on the device (the
+ * eigenvalues by mpmc_set_dense_method's solver).
  * The polynomial p has degree d-1 and satisfies pi(M) = 1 - M p(M) with
  * pi(M) = prod_i (1 - M/theta_i).
  * inner == NULL: the cycle runs on M.  inner != NULL: it runs on
@@ -211,8 +212,9 @@ int mpmc_poly_trace(mpmc_ctx *ctx, const mpmc_poly *p, int theta, const int peri
 
 /* Eigenpairs for deflation (Sec. 7, acceptance rule of Sec. 8): m steps of
  * polynomial-preconditioned Arnoldi on phi_in(M) = M p_in(M) (on M itself if
- * p_in == NULL) from the Z(4) vector (seed, stream, 0); Ritz pairs of H_m by
- * an FP64 Hessenberg QR + inverse iteration on the device; the nev Ritz values
+ * p_in == NULL) from the Z(4) vector (seed, stream, 0); Ritz values of H_m by
+ * mpmc_set_dense_method's FP64 solver on the device, Ritz vectors by inverse
+ * iteration; the nev Ritz values
  * of smallest modulus give z = V_m s (unit norm) and lambda = z^H M z; left
  * vectors u_i = g5 z_j with lambda_j the conjugate partner of lambda_i (j = i
  * when |Im lambda_i| < real_tol), scaled to u_i^H z_i = 1; a pair is accepted
@@ -350,6 +352,17 @@ int mpmc_net_train(mpmc_net *net, const void *R, const void *E, int npairs, int 
 int mpmc_solve_pp(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl,
                   const mpmc_poly *pp, int restart, double tol, int inner_prec, int max_outer,
                   int *iters_host, double *relres_host);
+/* Eigenvalue solver of the small dense FP64 problems (the harmonic Ritz
+ * values of mpmc_gmres_poly, Sec. 3, and the Ritz values of mpmc_deflate,
+ * Sec. 7).  method 0 (default): Aberth-Ehrlich simultaneous iteration on the
+ * Hessenberg matrix (Newton ratios by Hyman's determinant recurrence), one
+ * 16-lane group per eigenvalue across the GPU, for matrices up to 256 rows;
+ * if it has not converged after 40 sweeps (or for larger matrices) the
+ * shifted Hessenberg QR runs instead.  method 1: the shifted QR only.  The
+ * eigenvalues agree to rounding; they come out in a different order before
+ * the Leja ordering.  Returns MPMC_EINVAL for another method. */
+int mpmc_set_dense_method(mpmc_ctx *ctx, int method);
+
 /* Polynomial preconditioner used by the main solves inside mpmc_level_estimate
  * when no network is given (NULL: none, the default).  The context keeps the
  * pointer: the caller keeps pp alive while it is set. */

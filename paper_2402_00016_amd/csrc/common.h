@@ -55,6 +55,8 @@ struct mpmc_ctx {
     std::map<std::pair<int, int>, int> tune_explicit;   // variants set by mpmc_tune_set (not by the autotuner)
     // polynomial right preconditioner of the solves inside mpmc_level_estimate
     const struct mpmc_poly *level_pp = nullptr;
+    // small eigenproblems: 0 = Aberth-Ehrlich with the QR as fallback, 1 = QR only
+    int dense_qr_only = 0;
 };
 
 struct mpmc_poly {

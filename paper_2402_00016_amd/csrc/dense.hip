@@ -1,15 +1,19 @@
 // Small dense FP64 problems of the method, solved on the device:
 //  * harmonic Ritz values of a GMRES(d) cycle, eig(H_d + |h|^2 H_d^-H e_d e_d^T)
 //    (Sec. 3), with the GMRES least-squares residual,
-//  * eigenvalues of an upper Hessenberg matrix by shifted QR with Givens
-//    rotations (Wilkinson shift, exceptional shifts, bottom deflation),
+//  * eigenvalues of an upper Hessenberg matrix by the Aberth-Ehrlich
+//    simultaneous iteration (one 16-lane group per eigenvalue, spread over
+//    the GPU, one launch per sweep) and, when that has not converged, by
+//    shifted QR with Givens rotations (Wilkinson shift, exceptional shifts,
+//    bottom deflation) in one workgroup,
 //  * Leja ordering of the roots (Sec. 3),
 //  * Ritz vectors by inverse iteration on H - mu I (deflation, Sec. 7),
 //  * per-rhs Givens updates and back substitution of restarted GMRES solves.
-// The matrices are at most a few hundred rows: one workgroup works on one
-// matrix, which lives in LDS (packed Hessenberg) up to 192 rows and in global
-// memory (L2 resident) beyond.  Every loop has a fixed iteration bound.
+// The matrices are at most a few hundred rows; the QR's matrix lives in LDS
+// (packed Hessenberg) up to 192 rows and in global memory (L2 resident)
+// beyond.  Every loop has a fixed iteration bound.
 #include <cfloat>
+#include <climits>
 
 #include "common.h"
 
@@ -322,73 +326,354 @@ __device__ int hess_eigvals(Mat a, int n, double2 *ev, QrShared &sh) {
 }
 
 // --------------------------------------------------------------- Leja --
-// Orders ev[0..n) in place: candidates sorted by (Re, Im), first the largest
-// modulus, then the maximiser of sum log|theta - chosen| (lowest index on ties).
-__device__ void leja_order(double2 *ev, int n, double2 *tmp, double *S, int *taken) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    __syncthreads();
-    if (tid == 0) {   // insertion sort by (Re, Im); n <= a few hundred
-        for (int i = 1; i < n; ++i) {
-            double2 v = ev[i];
-            int j = i - 1;
-            while (j >= 0 && (ev[j].x > v.x || (ev[j].x == v.x && ev[j].y > v.y))) {
-                ev[j + 1] = ev[j];
-                --j;
-            }
-            ev[j + 1] = v;
-        }
-    }
-    __syncthreads();
+// Orders ev[0..n) in place: candidates sorted by (Re, Im) (stable), first the
+// largest modulus, then the maximiser of sum log|theta - chosen| (lowest index
+// on ties; an exact duplicate, log = -inf, comes last).  Called by every
+// thread of a workgroup of nt = blockDim.x threads (a multiple of 64,
+// n <= SLOTS nt).  The sort is by rank (each candidate counts those that
+// precede it); thread t keeps candidates j = t + nt q and their log sums in
+// registers; each step is a workgroup argmax: a wavefront butterfly, then the
+// per-wavefront winners through LDS (double-buffered by step parity, one
+// barrier per step).  Returns false, leaving ev as it was, when a value is not
+// finite.
+__device__ __forceinline__ bool leja_better(double v1, int i1, double v2, int i2) {
+    if (i1 == INT_MAX) return false;
+    if (i2 == INT_MAX) return true;
+    return v1 > v2 || (v1 == v2 && i1 < i2);
+}
+__device__ __forceinline__ bool key_before(double2 a, int ia, double2 b, int ib) {   // (Re, Im), then index
+    return a.x < b.x || (a.x == b.x && (a.y < b.y || (a.y == b.y && ia < ib)));
+}
+template <int SLOTS>
+__device__ bool leja_order(double2 *ev, int n) {
+    constexpr int MAXN = SLOTS * QR_THREADS;
+    __shared__ double2 lin[MAXN], lso[MAXN];
+    __shared__ double wv[2][QR_THREADS / 64];
+    __shared__ int wi[2][QR_THREADS / 64];
+    const int tid = threadIdx.x, nt = blockDim.x, nw = nt / 64;
+    int bad = 0;
     for (int j = tid; j < n; j += nt) {
-        S[j] = 0.0;
-        taken[j] = 0;
+        const double2 v = ev[j];
+        lin[j] = v;
+        bad |= !isfinite(v.x) || !isfinite(v.y);
+    }
+    if (__syncthreads_or(bad)) return false;
+    for (int j = tid; j < n; j += nt) {
+        const double2 v = lin[j];
+        int rank = 0;
+        for (int i = 0; i < n; ++i) rank += key_before(lin[i], i, v, j) ? 1 : 0;
+        lso[rank] = v;
     }
     __syncthreads();
-    __shared__ double bestv[QR_THREADS];
-    __shared__ int besti[QR_THREADS];
+    zd c[SLOTS];
+    double S[SLOTS];
+    bool taken[SLOTS];
+#pragma unroll
+    for (int q = 0; q < SLOTS; ++q) {
+        const int j = tid + nt * q;
+        c[q] = j < n ? mk(lso[j].x, lso[j].y) : mk(0.0, 0.0);
+        S[q] = 0.0;
+        taken[q] = j >= n;
+    }
     int last = -1;
     for (int step = 0; step < n; ++step) {
         double bv = -INFINITY;
-        int bi = 0x7fffffff;
-        for (int j = tid; j < n; j += nt) {
-            if (taken[j]) continue;
+        int bi = INT_MAX;
+        const double2 tl = last >= 0 ? lso[last] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q) {
+            if (taken[q]) continue;
             double v;
             if (step == 0) {
-                v = hypot(ev[j].x, ev[j].y);
+                v = hypot(c[q].re, c[q].im);
             } else {
-                S[j] += log(hypot(ev[j].x - ev[last].x, ev[j].y - ev[last].y));
-                v = S[j];
+                S[q] += log(hypot(c[q].re - tl.x, c[q].im - tl.y));
+                v = S[q];
             }
-            if (bi == 0x7fffffff || v > bv) {   // j increases: ties keep the lower index
+            if (leja_better(v, tid + nt * q, bv, bi)) {
                 bv = v;
-                bi = j;
+                bi = tid + nt * q;
             }
         }
-        bestv[tid] = bv;
-        besti[tid] = bi;
-        __syncthreads();
-        if (tid == 0) {
-            double b = -INFINITY;
-            int bj = 0x7fffffff;
-            for (int q = 0; q < nt; ++q) {
-                if (besti[q] == 0x7fffffff) continue;
-                if (bj == 0x7fffffff || bestv[q] > b || (bestv[q] == b && besti[q] < bj)) {
-                    b = bestv[q];
-                    bj = besti[q];
-                }
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) {
+            const double ov = __shfl_xor(bv, m, 64);
+            const int oi = __shfl_xor(bi, m, 64);
+            if (leja_better(ov, oi, bv, bi)) {
+                bv = ov;
+                bi = oi;
             }
-            besti[0] = bj;
+        }
+        if ((tid & 63) == 0) {
+            wv[step & 1][tid >> 6] = bv;
+            wi[step & 1][tid >> 6] = bi;
         }
         __syncthreads();
-        last = besti[0];
-        if (tid == 0) {
-            taken[last] = 1;
-            tmp[step] = ev[last];
+        bv = wv[step & 1][0];
+        bi = wi[step & 1][0];
+        for (int w = 1; w < nw; ++w)
+            if (leja_better(wv[step & 1][w], wi[step & 1][w], bv, bi)) {
+                bv = wv[step & 1][w];
+                bi = wi[step & 1][w];
+            }
+        last = bi;
+#pragma unroll
+        for (int q = 0; q < SLOTS; ++q)
+            if (tid + nt * q == last) taken[q] = true;
+        if (tid == 0) lin[step] = lso[last];
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += nt) ev[j] = lin[j];
+    __syncthreads();
+    return true;
+}
+
+// ------------------------------------------- Aberth-Ehrlich eigenvalues --
+// All eigenvalues of an unreduced upper Hessenberg A (n x n) at once by the
+// Aberth-Ehrlich simultaneous iteration (O. Aberth, Math. Comp. 27 (1973);
+// L. W. Ehrlich, Comm. ACM 10 (1967)):
+//   z_k <- z_k - N_k / (1 - N_k sum_{j != k} 1 / (z_k - z_j)),
+// N_k = det(A - z_k) / det'(A - z_k).  The Newton ratio comes from Hyman's
+// method: for B = A - z, x_{n-1} = 1 and B(i, i-1) x_{i-1} = -sum_{j >= i}
+// B(i, j) x_j for i = n-1 .. 1; then det B is f = sum_j B(0, j) x_j times a
+// product of subdiagonal entries that does not depend on z, so N = f / f'
+// with x' from the derivative of the same recurrence.  Each root takes one
+// 16-lane DPP row of a wavefront, the lanes splitting the columns
+// j = lane + 16 q (x_j, x'_j in registers), so the roots of a sweep run on many
+// compute units; one launch is one Jacobi sweep.  A root whose correction has
+// fallen below tol |z| (or stopped shrinking below 1e-11 |z|) is frozen.
+// Launches after the last root froze return at once; if roots are still
+// moving after AB_SWEEPS sweeps, the QR kernels take over.
+constexpr int AB_G = 16;         // lanes per root: one DPP row
+constexpr int AB_MAXN = 256;     // larger matrices go to the QR kernels directly
+constexpr int AB_SWEEPS = 40;    // sweeps before the QR kernels take over
+constexpr double AB_TOL = 1e-15;
+
+struct AberthWs {
+    double2 *arow;   // n x n row-major copy of A (zero below the subdiagonal)
+    double2 *rsub;   // rsub[i] = -1 / A(i, i-1), i >= 1
+    double2 *z;      // 2 n estimates: sweep t reads half t & 1, writes the other
+    double *wprev;   // n: modulus of each root's last correction
+    int *conv;       // n: frozen roots
+    int *left;       // AB_SWEEPS + 1: left[t + 1] = roots still moving after sweep t
+};
+static size_t aberth_bytes(int n) {
+    return sizeof(double2) * ((size_t)n * n + 3 * (size_t)n) + sizeof(double) * n + sizeof(int) * ((size_t)n + AB_SWEEPS + 1);
+}
+static AberthWs aberth_carve(void *base, int n) {
+    AberthWs w;
+    double2 *p = (double2 *)base;
+    w.arow = p;
+    p += (size_t)n * n;
+    w.rsub = p;
+    p += n;
+    w.z = p;
+    p += 2 * (size_t)n;
+    w.wprev = (double *)p;
+    w.conv = (int *)(w.wprev + n);
+    w.left = w.conv + n;
+    return w;
+}
+__host__ __device__ inline const double2 *aberth_result(const AberthWs &w, int n) {
+    return w.z + (size_t)(AB_SWEEPS & 1) * n;
+}
+
+// Sum over the 16 lanes of a DPP row with the same bits in every lane: an
+// inclusive scan with row_shr 1, 2, 4, 8 (zero fill), then lane 15 broadcast
+// with row_newbcast.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double row_sum16(double v) {
+    v += dpp_d<0x111>(v);
+    v += dpp_d<0x112>(v);
+    v += dpp_d<0x114>(v);
+    v += dpp_d<0x118>(v);
+    return dpp_d<0x15F>(v);
+}
+__device__ __forceinline__ zd row_sum16(zd v) { return mk(row_sum16(v.re), row_sum16(v.im)); }
+
+// Centre = trace / n, radius = ||A - centre||_F / sqrt(n); initial estimates
+// on that circle, rotated off the real axis.
+__global__ __launch_bounds__(256) void k_aberth_init(const double2 *A, int lda, int n, AberthWs w) {
+    __shared__ double red[3][256];
+    const int tid = threadIdx.x;
+    for (long e = tid; e < (long)n * n; e += 256) {
+        const int i = (int)(e / n), j = (int)(e - (long)i * n);
+        w.arow[e] = i <= j + 1 ? A[i + (long)j * lda] : make_double2(0.0, 0.0);
+    }
+    double tr = 0.0, ti = 0.0;
+    int reducible = 0;
+    for (int i = tid; i < n; i += 256) {
+        const zd a = ld(A, i + (long)i * lda);
+        tr += a.re;
+        ti += a.im;
+        const zd sub = i > 0 ? ld(A, i + (long)(i - 1) * lda) : mk(1.0, 0.0);
+        reducible |= sub.re == 0.0 && sub.im == 0.0;
+        st(w.rsub, i, i > 0 ? zdiv(mk(-1.0, 0.0), sub) : mk(0.0, 0.0));
+        w.conv[i] = 0;
+        w.wprev[i] = INFINITY;
+    }
+    for (int t = tid; t <= AB_SWEEPS; t += 256) w.left[t] = t == 0 ? n : 0;
+    // A zero subdiagonal entry splits the determinant, which Hyman's
+    // recurrence does not see: no sweep runs and the QR takes the matrix.
+    if (__syncthreads_or(reducible) && tid == 0) {
+        w.left[0] = 0;
+        w.left[AB_SWEEPS] = 1;
+    }
+    red[0][tid] = tr;
+    red[1][tid] = ti;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+            red[0][tid] += red[0][tid + h];
+            red[1][tid] += red[1][tid + h];
         }
         __syncthreads();
     }
-    for (int j = tid; j < n; j += nt) ev[j] = tmp[j];
+    const zd c = mk(red[0][0] / n, red[1][0] / n);
+    double f2 = 0.0;
+    for (long e = tid; e < (long)n * n; e += 256) {
+        const int i = (int)(e / n), j = (int)(e - (long)i * n);
+        if (i > j + 1) continue;
+        zd a = ld(A, i + (long)j * lda);
+        if (i == j) a = a - c;
+        f2 += a.re * a.re + a.im * a.im;
+    }
+    red[2][tid] = f2;
     __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) red[2][tid] += red[2][tid + h];
+        __syncthreads();
+    }
+    double R = sqrt(red[2][0] / n);
+    if (!(R > 0.0) || !isfinite(R)) R = 1.0;
+    for (int k = tid; k < n; k += 256) {
+        const double th = 6.283185307179586 * k / n + 0.4;
+        w.z[k] = make_double2(c.re + R * cos(th), c.im + R * sin(th));
+    }
+}
+
+// s = sum_{j >= i} B(i, j) x_j and its derivative, B = A - z, for this lane's
+// columns (row i of A in a[]).
+template <int Q>
+__device__ __forceinline__ void hyman_row(const zd (&a)[Q], const zd (&x)[Q], const zd (&xp)[Q], int i, int n, int g,
+                                          zd z, zd &s, zd &sp) {
+    s = mk(0.0, 0.0);
+    sp = mk(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (AB_G * q + AB_G - 1 < i || AB_G * q >= n) continue;   // uniform: no column >= i here
+        const int j = g + AB_G * q;
+        zd b = j >= i ? a[q] : mk(0.0, 0.0);
+        if (j == i) b = b - z;
+        s = s + b * x[q];
+        sp = sp + b * xp[q];
+        if (j == i) sp = sp - x[q];
+    }
+    s = row_sum16(s);
+    sp = row_sum16(sp);
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void k_aberth_sweep(AberthWs w, int n, int t, double tol) {
+    const double2 *zin = w.z + (size_t)(t & 1) * n;
+    double2 *zout = w.z + (size_t)((t + 1) & 1) * n;
+    const int g = threadIdx.x & (AB_G - 1);
+    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) / AB_G);   // the same in all 16 lanes of a row
+    if (k >= n) return;
+    const zd zk = ld(zin, k);
+    if (w.left[t] == 0 || w.conv[k]) {
+        if (g == 0) st(zout, k, zk);
+        return;
+    }
+    zd x[Q], xp[Q], a[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int j = g + AB_G * q;
+        x[q] = mk(j == n - 1 ? 1.0 : 0.0, 0.0);
+        xp[q] = mk(0.0, 0.0);
+        a[q] = j < n ? ld(w.arow, (long)(n - 1) * n + j) : mk(0.0, 0.0);
+    }
+    zd rs = ld(w.rsub, n - 1);
+    for (int i = n - 1; i >= 1; --i) {
+        zd an[Q];   // row i - 1, in flight while row i is summed
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int j = g + AB_G * q;
+            an[q] = (AB_G * q < n && j < n) ? ld(w.arow, (long)(i - 1) * n + j) : mk(0.0, 0.0);
+        }
+        const zd rsn = ld(w.rsub, i - 1);
+        zd s, sp;
+        hyman_row<Q>(a, x, xp, i, n, g, zk, s, sp);
+        const zd xn = rs * s, xpn = rs * sp;   // x_{i-1}, x'_{i-1}: the same bits in every lane
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (g + AB_G * q == i - 1) {
+                x[q] = xn;
+                xp[q] = xpn;
+            }
+        const double mx = fmax(fmax(fabs(xn.re), fabs(xn.im)), fmax(fabs(xpn.re), fabs(xpn.im)));
+        if (mx > 0x1p400) {   // a common power-of-two scale leaves f / f' unchanged
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                x[q] = 0x1p-400 * x[q];
+                xp[q] = 0x1p-400 * xp[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) a[q] = an[q];
+        rs = rsn;
+    }
+    zd f, fp;
+    hyman_row<Q>(a, x, xp, 0, n, g, zk, f, fp);
+    const bool flat = fp.re == 0.0 && fp.im == 0.0;
+    const zd N = flat ? mk((double)NAN, (double)NAN) : zdiv(f, fp);   // NaN: no Newton step; the QR takes over
+    zd S = mk(0.0, 0.0);
+    for (int j = g; j < n; j += AB_G)
+        if (j != k) S = S + zdiv(mk(1.0, 0.0), zk - ld(zin, j));
+    S = row_sum16(S);
+    const zd den = mk(1.0, 0.0) - N * S;
+    const zd wk = (den.re == 0.0 && den.im == 0.0) ? N : zdiv(N, den);
+    if (g == 0) {
+        const double aw = hypot(wk.re, wk.im), az = hypot(zk.re, zk.im);
+        const bool done = aw <= tol * az || (aw <= 1e-11 * az && aw >= w.wprev[k]);
+        st(zout, k, zk - wk);
+        w.wprev[k] = aw;
+        if (done) w.conv[k] = 1;
+        else atomicAdd(&w.left[t + 1], 1);
+    }
+}
+
+// Runs the iteration on A (n x n, column-major, leading dimension lda) on the
+// context stream.  Afterwards w.left[AB_SWEEPS] == 0 means every root froze,
+// with the eigenvalues at aberth_result(w, n).
+static int aberth_run(mpmc_ctx *ctx, const double2 *A, int lda, int n, const AberthWs &w) {
+    k_aberth_init<<<1, 256, 0, ctx->stream>>>(A, lda, n, w);
+    const unsigned blocks = (unsigned)((n + 15) / 16);
+    for (int t = 0; t < AB_SWEEPS; ++t) {
+        if (n <= 32) k_aberth_sweep<2><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+        else if (n <= 64) k_aberth_sweep<4><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+        else if (n <= 128) k_aberth_sweep<8><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+        else if (n <= 192) k_aberth_sweep<12><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+        else k_aberth_sweep<16><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+    }
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
+// The QR kernels' hand-over: when the iteration converged, its eigenvalues
+// are copied to ev and the QR is skipped (uniform: every thread reads the same
+// flag).
+__device__ __forceinline__ bool take_aberth(const int *left, const double2 *zab, int n, double2 *ev) {
+    if (!left) return false;
+    if (__builtin_amdgcn_readfirstlane(left[AB_SWEEPS]) != 0) return false;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) ev[k] = zab[k];
+    return true;
 }
 
 // ------------------------------------------------ harmonic Ritz + Leja --
@@ -397,24 +682,21 @@ __device__ void leja_order(double2 *ev, int n, double2 *tmp, double *S, int *tak
 // Lane 0 runs the Givens QR of Hbar column by column: the first d-1 rotations
 // are also the QR of H_d, so r = R_d(d-1, d-1) and f = H_d^-H e_d = Q e_d / conj(r)
 // (R_d^H is lower triangular, so R_d^H g = e_d has g = e_d / conj(r)); the last
-// rotation gives the least-squares residual |g_d|.  The eigenvalues of
-// H_d + |h_{d+1,d}|^2 f e_d^T are found in LDS (packed) when it fits.
-// work (global): >= 2*d*d + 8*d + 16 complex doubles.
-template <int use_lds>
-__global__ __launch_bounds__(QR_THREADS) void k_harmonic_leja(const double2 *H, int ldh, int d, double beta,
-                                                              double2 *work, double2 *roots, double *info) {
-    extern __shared__ double2 lds_mat[];
-    __shared__ QrShared qsh;
+// rotation gives the least-squares residual |g_d|.  Then the workgroup writes
+// A = H_d + |h_{d+1,d}|^2 f e_d^T (d x d, column-major) for the eigensolvers.
+// info[0] = residual / beta, info[1] = 0 or -2 (H_d singular: A = H_d).
+struct HarmWs {
+    double2 *A;     // d x d
+    double2 *f;     // d
+    double2 *rot;   // d rotations: (c, 0)
+    double2 *rs;    // d: s
+    void *ab;       // Aberth workspace (d <= AB_MAXN)
+};
+__global__ __launch_bounds__(256) void k_harmonic_build(const double2 *H, int ldh, int d, double beta, HarmWs w,
+                                                        double *info) {
     const int tid = threadIdx.x, nt = blockDim.x;
-    double2 *A = work;                 // d x d (global path)
-    double2 *f = work + (long)d * d;   // d
-    double2 *rot = f + d;              // d rotations: (c, 0) then s
-    double2 *rs = rot + d;             // d
-    double2 *tmp = rs + d;             // d
-    double *S = (double *)(tmp + d);   // d doubles
-    int *taken = (int *)(S + d);       // d ints
+    double2 *f = w.f, *rot = w.rot, *rs = w.rs;
     __shared__ int s_status;
-    __shared__ double s_res;
     if (tid == 0) {
         s_status = 0;
         zd gk = mk(beta, 0.0);
@@ -439,7 +721,6 @@ __global__ __launch_bounds__(QR_THREADS) void k_harmonic_leja(const double2 *H, 
             st(rs, j, sn);
             gk = mk(0.0, 0.0) - cconj(sn) * gk;
         }
-        s_res = beta > 0 ? zabs(gk) / beta : 0.0;
         // f = Q e_{d-1} / conj(rdd), Q = G_0^H ... G_{d-2}^H
         for (int i = 0; i < d; ++i) f[i] = make_double2(0.0, 0.0);
         f[d - 1] = make_double2(1.0, 0.0);
@@ -453,42 +734,53 @@ __global__ __launch_bounds__(QR_THREADS) void k_harmonic_leja(const double2 *H, 
         if (zabs(rdd) == 0.0) s_status = -2;
         const zd inv = zdiv(mk(1.0, 0.0), cconj(rdd));
         for (int i = 0; i < d; ++i) st(f, i, ld(f, i) * inv);
+        info[0] = beta > 0 ? zabs(gk) / beta : 0.0;
+        info[1] = (double)s_status;
     }
     __syncthreads();
     const zd h = ld(H, d + (long)(d - 1) * ldh);
     const double h2 = h.re * h.re + h.im * h.im;
     const bool corr = h2 > 0.0 && s_status == 0;
+    for (long e = tid; e < (long)d * d; e += nt) {
+        const int i = (int)(e % d), j = (int)(e / d);
+        zd v = (i <= j + 1) ? ld(H, i + (long)j * ldh) : mk(0.0, 0.0);
+        if (corr && j == d - 1) v = v + h2 * ld(f, i);
+        st(w.A, e, v);
+    }
+}
+
+// Eigenvalues of A when the Aberth iteration did not converge (or was not
+// run): shifted QR in LDS (packed) when it fits, else in place in global
+// memory.  info[1] = -1 on QR failure.
+template <int use_lds>
+__global__ __launch_bounds__(QR_THREADS) void k_harmonic_qr(HarmWs w, int d, const int *ab_left,
+                                                            const double2 *ab_z, double2 *roots, double *info) {
+    extern __shared__ double2 lds_mat[];
+    __shared__ QrShared qsh;
+    if (take_aberth(ab_left, ab_z, d, roots)) return;
     int rc;
     if constexpr (use_lds != 0) {
         PackedMat M{lds_mat};
         for (int j = 0; j < d; ++j)
-            for (int i = tid; i <= (j + 1 < d ? j + 1 : d - 1); i += nt) {
-                zd v = ld(H, i + (long)j * ldh);
-                if (corr && j == d - 1) v = v + h2 * ld(f, i);
-                st(&M(i, j), 0, v);
-            }
+            for (int i = threadIdx.x; i <= (j + 1 < d ? j + 1 : d - 1); i += blockDim.x) M(i, j) = w.A[i + (long)j * d];
         __syncthreads();
         rc = hess_eigvals<1>(M, d, roots, qsh);
     } else {
-        GlobalMat M{A, d};
-        for (long e = tid; e < (long)d * d; e += nt) {
-            const int i = (int)(e % d), j = (int)(e / d);
-            zd v = (i <= j + 1) ? ld(H, i + (long)j * ldh) : mk(0.0, 0.0);
-            if (corr && j == d - 1) v = v + h2 * ld(f, i);
-            st(A, e, v);
-        }
-        __syncthreads();
-        rc = hess_eigvals<2>(M, d, roots, qsh);
+        rc = hess_eigvals<2>(GlobalMat{w.A, d}, d, roots, qsh);
     }
-    if (rc && tid == 0) s_status = -1;
-    __syncthreads();
-    leja_order(roots, d, tmp, S, taken);
-    if (tid == 0) {
+    if (rc && threadIdx.x == 0) info[1] = -1.0;
+}
+
+// Leja order of the roots, then the checks: info[1] = -1 if a root is not
+// finite or zero.
+template <int SLOTS>
+__global__ __launch_bounds__(QR_THREADS) void k_leja(double2 *roots, int d, double *info) {
+    const bool ok = leja_order<SLOTS>(roots, d);
+    if (threadIdx.x == 0) {
+        bool bad = !ok;
         for (int i = 0; i < d; ++i)
-            if (!(roots[i].x == roots[i].x) || !(roots[i].y == roots[i].y) || (roots[i].x == 0 && roots[i].y == 0))
-                s_status = -1;
-        info[0] = s_res;
-        info[1] = (double)s_status;
+            if (roots[i].x == 0 && roots[i].y == 0) bad = true;
+        if (bad) info[1] = -1.0;
     }
 }
 
@@ -496,11 +788,13 @@ __global__ __launch_bounds__(QR_THREADS) void k_harmonic_leja(const double2 *H, 
 // Stabilisation of a high-degree polynomial (the added-roots rule for
 // polynomial preconditioners): root k with log10 pof(k) > thr, pof(k) =
 // prod_{i != k} |1 - theta_k / theta_i|, gets ceil((log10 pof(k) - thr) /
-// digits) extra copies; the extended list is Leja ordered.  One wavefront.
-// out, tmp: max_out entries; S, taken: max_out entries; count[0] = new size
+// digits) extra copies; the extended list is Leja ordered.  One workgroup.
+// out: max_out entries (<= ADD_ROOTS_MAX); taken: d ints; count[0] = new size
 // (or -1 when it would exceed max_out).
-__global__ __launch_bounds__(64) void k_add_roots(const double2 *in, int d, double thr, double digits, int max_out,
-                                                  double2 *out, double2 *tmp, double *S, int *taken, int *count) {
+constexpr int ADD_ROOTS_SLOTS = 5;
+constexpr int ADD_ROOTS_MAX = ADD_ROOTS_SLOTS * QR_THREADS;
+__global__ __launch_bounds__(QR_THREADS) void k_add_roots(const double2 *in, int d, double thr, double digits,
+                                                          int max_out, double2 *out, int *taken, int *count) {
     const int tid = threadIdx.x, nt = blockDim.x;
     __shared__ int s_total;
     for (int k = tid; k < d; k += nt) {
@@ -527,17 +821,16 @@ __global__ __launch_bounds__(64) void k_add_roots(const double2 *in, int d, doub
         count[0] = s_total;
     }
     __syncthreads();
-    if (s_total > 0) leja_order(out, s_total, tmp, S, taken);
+    if (s_total > 0) leja_order<ADD_ROOTS_SLOTS>(out, s_total);
 }
 
 int dense_add_roots(mpmc_ctx *ctx, const double *roots_dev, int d, double thr, double digits, int max_out,
                     double *out_dev, int *count_dev) {
-    double2 *work = (double2 *)ws_get(ctx, WS_DENSE, (size_t)max_out * (sizeof(double2) + sizeof(double) + sizeof(int)) + 256);
-    if (!work) return MPMC_ENOMEM;
-    double *S = (double *)(work + max_out);
-    int *taken = (int *)(S + max_out);
-    k_add_roots<<<1, 64, 0, ctx->stream>>>((const double2 *)roots_dev, d, thr, digits, max_out, (double2 *)out_dev,
-                                           work, S, taken, count_dev);
+    if (max_out > ADD_ROOTS_MAX) return set_err(ctx, MPMC_EINVAL, "added roots: at most %d roots", ADD_ROOTS_MAX);
+    int *taken = (int *)ws_get(ctx, WS_DENSE, (size_t)d * sizeof(int) + 256);
+    if (!taken) return MPMC_ENOMEM;
+    k_add_roots<<<1, QR_THREADS, 0, ctx->stream>>>((const double2 *)roots_dev, d, thr, digits, max_out,
+                                                   (double2 *)out_dev, taken, count_dev);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
@@ -559,19 +852,37 @@ static bool want_lds(mpmc_ctx *ctx, K kernel, size_t bytes) {
     return true;
 }
 
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, double beta, double *roots_dev,
                         double *info_dev) {
     if (d < 1 || d > 500) return set_err(ctx, MPMC_EINVAL, "harmonic Ritz: d=%d out of range [1, 500]", d);
-    double2 *work = (double2 *)ws_get(ctx, WS_DENSE, ((size_t)d * d + 8 * d + 16) * sizeof(double2));
+    const bool aberth = d <= AB_MAXN && !ctx->dense_qr_only;
+    const size_t ba = align256(sizeof(double2) * (size_t)d * d), bv = align256(sizeof(double2) * (size_t)d);
+    char *work = (char *)ws_get(ctx, WS_DENSE, ba + 3 * bv + (aberth ? aberth_bytes(d) : 0) + 256);
     if (!work) return MPMC_ENOMEM;
-    const size_t lb = (size_t)(packed_hess_size(d) + 2 * d) * sizeof(double2);
-    const bool lds = d <= 192 && want_lds(ctx, k_harmonic_leja<1>, lb);   // LDS path: one column per thread
+    HarmWs w;
+    w.A = (double2 *)work;
+    w.f = (double2 *)(work + ba);
+    w.rot = (double2 *)(work + ba + bv);
+    w.rs = (double2 *)(work + ba + 2 * bv);
+    w.ab = work + ba + 3 * bv;
+    k_harmonic_build<<<1, 256, 0, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, w, info_dev);
+    const int *ab_left = nullptr;
+    const double2 *ab_z = nullptr;
+    if (aberth) {
+        const AberthWs aw = aberth_carve(w.ab, d);
+        RET_IF(aberth_run(ctx, w.A, d, d, aw));
+        ab_left = aw.left;
+        ab_z = aberth_result(aw, d);
+    }
+    const size_t lb = (size_t)packed_hess_size(d) * sizeof(double2);
+    const bool lds = d <= 192 && want_lds(ctx, k_harmonic_qr<1>, lb);   // LDS path: one column per thread
     if (lds)
-        k_harmonic_leja<1><<<1, QR_THREADS, lb, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
-                                                       (double2 *)roots_dev, info_dev);
+        k_harmonic_qr<1><<<1, QR_THREADS, lb, ctx->stream>>>(w, d, ab_left, ab_z, (double2 *)roots_dev, info_dev);
     else
-        k_harmonic_leja<0><<<1, QR_THREADS, 0, ctx->stream>>>((const double2 *)H_dev, ldh, d, beta, work,
-                                                      (double2 *)roots_dev, info_dev);
+        k_harmonic_qr<0><<<1, QR_THREADS, 0, ctx->stream>>>(w, d, ab_left, ab_z, (double2 *)roots_dev, info_dev);
+    k_leja<2><<<1, QR_THREADS, 0, ctx->stream>>>((double2 *)roots_dev, d, info_dev);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
@@ -579,9 +890,14 @@ int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, doub
 // ------------------------------------------------- eigenvalues of H_m --
 template <int use_lds>
 __global__ __launch_bounds__(QR_THREADS) void k_hess_eigs(const double2 *H, int ldh, int m, double2 *work,
-                                                          double2 *ev, double *info) {
+                                                          const int *ab_left, const double2 *ab_z, double2 *ev,
+                                                          double *info) {
     extern __shared__ double2 lds_mat[];
     __shared__ QrShared qsh;
+    if (take_aberth(ab_left, ab_z, m, ev)) {
+        if (threadIdx.x == 0) info[0] = 0.0;
+        return;
+    }
     int rc;
     if constexpr (use_lds != 0) {
         PackedMat M{lds_mat};
@@ -602,14 +918,26 @@ __global__ __launch_bounds__(QR_THREADS) void k_hess_eigs(const double2 *H, int 
 
 int dense_hess_eigs(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, double *ev_dev, double *info_dev) {
     if (m < 1 || m > 500) return set_err(ctx, MPMC_EINVAL, "Hessenberg eigenproblem: m=%d out of range", m);
-    double2 *work = (double2 *)ws_get(ctx, WS_DENSE, ((size_t)m * m + 2 * m) * sizeof(double2));
+    const bool aberth = m <= AB_MAXN && !ctx->dense_qr_only;
+    const size_t bq = align256(((size_t)m * m + 2 * m) * sizeof(double2));
+    char *work = (char *)ws_get(ctx, WS_DENSE, bq + (aberth ? aberth_bytes(m) : 0) + 256);
     if (!work) return MPMC_ENOMEM;
+    const int *ab_left = nullptr;
+    const double2 *ab_z = nullptr;
+    if (aberth) {
+        const AberthWs aw = aberth_carve(work + bq, m);
+        RET_IF(aberth_run(ctx, (const double2 *)H_dev, ldh, m, aw));
+        ab_left = aw.left;
+        ab_z = aberth_result(aw, m);
+    }
     const size_t lb = (size_t)(packed_hess_size(m) + 2 * m) * sizeof(double2);
     const bool lds = m <= 192 && want_lds(ctx, k_hess_eigs<1>, lb);   // LDS path: one column per thread
     if (lds)
-        k_hess_eigs<1><<<1, QR_THREADS, lb, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev, info_dev);
+        k_hess_eigs<1><<<1, QR_THREADS, lb, ctx->stream>>>((const double2 *)H_dev, ldh, m, (double2 *)work, ab_left,
+                                                           ab_z, (double2 *)ev_dev, info_dev);
     else
-        k_hess_eigs<0><<<1, QR_THREADS, 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, work, (double2 *)ev_dev, info_dev);
+        k_hess_eigs<0><<<1, QR_THREADS, 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, (double2 *)work, ab_left,
+                                                          ab_z, (double2 *)ev_dev, info_dev);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
@@ -783,5 +1111,12 @@ int dense_backsolve(mpmc_ctx *ctx, const double *H, int ldc, int k, int N, const
     k_backsolve<<<grid_for(N, 64), 64, 0, ctx->stream>>>((const double2 *)H, ldc, k, N, (const double2 *)g,
                                                         (double2 *)y);
     HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_set_dense_method(mpmc_ctx *ctx, int method) {
+    if (!ctx) return MPMC_EINVAL;
+    if (method != 0 && method != 1) return set_err(ctx, MPMC_EINVAL, "mpmc_set_dense_method: method %d", method);
+    ctx->dense_qr_only = method;
     return MPMC_OK;
 }

@@ -22,6 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("MPMC_LIB", os.path.join(HERE, "libmpmc.so"))
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
+DENSE_ABERTH, DENSE_QR = 0, 1   # eigenvalue solvers of the small dense problems
 FP64, FP32, FP16S = 0, 1, 2
 THETA_I, THETA_G5 = 0, 1
 TIMING_PLAIN, TIMING_FUSED = 16, 32     # or-ed into the precision of mpmc_timing_read
@@ -81,6 +82,7 @@ _SIGS = {
     "mpmc_net_train": ([_vp, _vp, _vp, _i, _i, _d, _vp], _i),
     "mpmc_solve_pp": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
     "mpmc_set_level_solve_poly": ([_vp, _vp], _i),
+    "mpmc_set_dense_method": ([_vp, _i], _i),
     "mpmc_solve_pairs": ([_vp, _vp, _vp, _i, _vp, _i, _d, _i, _i, _vp, _vp, _i, _pi, _pi, _vp], _i),
     "mpmc_level_estimate": ([_vp, _vp, _vp, _vp, _i, _u64, _u32, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp,
                              _pu64], _i),
@@ -277,6 +279,10 @@ def mpmc_solve_pp(ctx, b, x, nrhs, defl, pp, restart=50, tol=1e-8, inner_prec=FP
 
 def mpmc_set_level_solve_poly(ctx, pp):
     _check(_L.mpmc_set_level_solve_poly(ctx, _h(pp)), ctx)
+
+
+def mpmc_set_dense_method(ctx, method):
+    _check(_L.mpmc_set_dense_method(ctx, int(method)), ctx)
 
 
 def mpmc_solve_pairs(ctx, b, x, nrhs, defl, restart, tol, inner_prec, max_outer, R, E, max_snap):
@@ -601,6 +607,10 @@ class Context:
         x = self.vector(nrhs, FP64) if x is None else x
         its, rel = mpmc_solve_pp(self.handle, b, x, nrhs, defl, pp, restart, tol, inner_prec, max_outer)
         return x, its, rel
+
+    def set_dense_method(self, method):
+        """Small eigenproblems: DENSE_ABERTH (default, QR fallback) or DENSE_QR."""
+        mpmc_set_dense_method(self.handle, method)
 
     def set_level_solve_poly(self, pp):
         """Polynomial preconditioner of the main solves inside level estimates (None: none)."""

@@ -171,6 +171,29 @@ def test_gmres_poly_roots_parity_high_degree():
     assert abs(P.relres - rr) < 1e-8 * rr
 
 
+@pytest.mark.parametrize("dims,kappa,seed,d", [((4, 4, 4, 4), 0.2, 21, 48), ((8, 8, 8, 8), 0.12, 2, 129),
+                                               ((8, 8, 8, 8), 0.12, 2, 33), ((4, 4, 4, 4), 0.115, 1, 300)])
+def test_dense_eigensolvers_agree(dims, kappa, seed, d):
+    """Harmonic Ritz values by the Aberth-Ehrlich iteration (the default) and by
+    the shifted QR agree to rounding, and each set comes out in the oracle's
+    Leja order of its own values.  d = 300 (more than 256 rows) takes the QR
+    in both settings."""
+    U = inputs.gauge_links(dims, 0.5, seed=seed)
+    ctx = mpmc.Context(dims, kappa, U)
+    P_ab = ctx.gmres_poly(1, 0x100, d)
+    ctx.set_dense_method(mpmc.DENSE_QR)
+    P_qr = ctx.gmres_poly(1, 0x100, d)
+    ctx.set_dense_method(mpmc.DENSE_ABERTH)
+    assert P_ab.d_eff == P_qr.d_eff == d
+    scale = np.max(np.abs(P_qr.roots))
+    assert _match_sets(P_ab.roots, P_qr.roots) < 1e-11 * scale
+    assert abs(P_ab.relres - P_qr.relres) <= 1e-12 * P_qr.relres
+    for P in (P_ab, P_qr):
+        assert np.max(np.abs(OK.leja_order(P.roots) - P.roots)) <= 1e-13 * scale
+    with pytest.raises(mpmc.MpmcError):
+        ctx.set_dense_method(2)
+
+
 def test_gmres_poly_breakdown_kappa0():
     dims = (2, 2, 2, 2)
     ctx = mpmc.Context(dims, 0.0, inputs.gauge_links(dims, 0.5, seed=1))
@@ -230,11 +253,13 @@ def test_double_poly_parity(f44):
 
 # -------------------------------------------------------------- deflation --
 
-@pytest.mark.parametrize("m", [80, 150])    # 150: the Hessenberg QR runs from global memory
-def test_deflate_parity(m):
+@pytest.mark.parametrize("m,method", [(80, mpmc.DENSE_ABERTH), (150, mpmc.DENSE_ABERTH), (80, mpmc.DENSE_QR),
+                                      (150, mpmc.DENSE_QR)])   # QR at 150: from global memory
+def test_deflate_parity(m, method):
     dims, kappa = (4, 4, 4, 4), 0.2
     U = inputs.gauge_links(dims, 0.5, seed=21)
     op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    ctx.set_dense_method(method)
     Pin_ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 4)
     Pin = ctx.poly_from_roots(Pin_ref.roots)
     D = ctx.deflate(Pin, 1, 0x200, m=m, nev=10)
