@@ -214,7 +214,8 @@ def main():
                              for L in est.levels],
                   "deflated": est.defl_k, "setup_s": round(est.setup_seconds, 4), "mvps": est.mvps},
         "time_to_error_s": {"mixed_batched": round(step_s, 4)},
-        "fp64_kernel_share": {"launches": n64, "ms_per_step": round(ms64 / a.steps, 3)},
+        "fp64_kernel_share": {"launches": n64, "multi_rhs_ms_per_step": round(ms64 / a.steps, 3),
+                              "note": "single-vector launches are counted (bytes, launches) without events"},
     }
     def solve_term(e):
         L = e.levels[0]

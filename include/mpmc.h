@@ -111,16 +111,19 @@ int mpmc_release_workspace(mpmc_ctx *ctx);
 
 /* Launch timing of the Wilson-Dirac kernels (the multi-RHS "Dslash", alone or
  * fused into a polynomial step).  While enabled, HIP events are recorded on the
- * context stream around every such launch together with the launch's
+ * context stream around every multi-RHS launch together with the launch's
  * algorithmic HBM bytes: spinor bytes per (site, rhs) for each operand read
  * once and each output written once, plus the links once per site.
- * mpmc_timing_read synchronises and returns, for launches of precision prec
- * since the last enable, the count, the summed kernel time (ms) and the
- * summed algorithmic bytes; it leaves timing enabled.  prec may be or-ed with
- * MPMC_TIMING_FUSED (only the fused level steps, k_wilson_dot) or
- * MPMC_TIMING_PLAIN (only the other Wilson launches); without either flag
- * both kinds are summed. */
-enum { MPMC_TIMING_PLAIN = 16, MPMC_TIMING_FUSED = 32 };
+ * Single-vector launches (nrhs = 1, the Arnoldi cycles) are counted with their
+ * bytes but get no events (two event records would cost about as much as the
+ * launch).  mpmc_timing_read synchronises and returns, for launches of
+ * precision prec since the last enable, the count, the summed kernel time (ms,
+ * multi-RHS launches only) and the summed algorithmic bytes; it leaves timing
+ * enabled.  prec may be or-ed with MPMC_TIMING_FUSED (only the fused level
+ * steps, k_wilson_dot), MPMC_TIMING_PLAIN (only the other multi-RHS Wilson
+ * launches) or MPMC_TIMING_SINGLE (only single-vector launches: time 0);
+ * without a flag every kind is summed. */
+enum { MPMC_TIMING_PLAIN = 16, MPMC_TIMING_FUSED = 32, MPMC_TIMING_SINGLE = 64 };
 int mpmc_timing_enable(mpmc_ctx *ctx, int on);
 int mpmc_timing_read(mpmc_ctx *ctx, int prec, uint64_t *launches_host, double *ms_host, double *bytes_host);
 

@@ -49,7 +49,8 @@ struct mpmc_ctx {
         int ev0, ev1, prec;
         double bytes;
     };
-    std::vector<TimedLaunch> timed;
+    std::vector<TimedLaunch> timed;   // ev0 < 0: counted without events
+    int timed_events = 0;             // events of ev_pool in use since the last enable
     // Wilson kernel variant per (nrhs, prec), set by mpmc_autotune / mpmc_tune_set
     std::map<std::pair<int, int>, int> tune;
     std::map<std::pair<int, int>, int> tune_explicit;   // variants set by mpmc_tune_set (not by the autotuner)
@@ -327,6 +328,7 @@ int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, int prec, 
 // timing hooks around one launch (no-ops unless timing is enabled)
 int timing_begin(mpmc_ctx *ctx);
 void timing_end(mpmc_ctx *ctx, int ev0, int prec, double bytes);
+void timing_count(mpmc_ctx *ctx, int prec, double bytes);   // a launch without events
 
 // dense.hip
 int dense_harmonic_leja(mpmc_ctx *ctx, const double *H_dev, int ldh, int d, double beta, double *roots_dev,

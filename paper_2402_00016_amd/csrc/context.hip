@@ -397,7 +397,8 @@ MPMC_API int mpmc_noise(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t 
 
 int timing_begin(mpmc_ctx *ctx) {
     if (!ctx->timing) return -1;
-    const int i = (int)ctx->timed.size() * 2;
+    const int i = ctx->timed_events;
+    ctx->timed_events += 2;
     while ((int)ctx->ev_pool.size() < i + 2) {
         hipEvent_t e;
         if (hipEventCreate(&e) != hipSuccess) return -1;
@@ -413,11 +414,16 @@ void timing_end(mpmc_ctx *ctx, int ev0, int prec, double bytes) {
     ctx->timed.push_back({ev0, ev0 + 1, prec, bytes});
 }
 
+void timing_count(mpmc_ctx *ctx, int prec, double bytes) {
+    if (ctx->timing) ctx->timed.push_back({-1, -1, prec, bytes});
+}
+
 MPMC_API int mpmc_timing_enable(mpmc_ctx *ctx, int on) {
     if (!ctx) return MPMC_EINVAL;
     HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
     ctx->timing = on ? 1 : 0;
     ctx->timed.clear();
+    ctx->timed_events = 0;
     return MPMC_OK;
 }
 
@@ -431,7 +437,7 @@ MPMC_API int mpmc_timing_read(mpmc_ctx *ctx, int prec, uint64_t *launches, doubl
         if ((L.prec & 15) != (prec & 15)) continue;
         if ((prec & ~15) && !(L.prec & prec & ~15)) continue;
         float e = 0;
-        HIP_OR_RET(ctx, hipEventElapsedTime(&e, ctx->ev_pool[L.ev0], ctx->ev_pool[L.ev1]));
+        if (L.ev0 >= 0) HIP_OR_RET(ctx, hipEventElapsedTime(&e, ctx->ev_pool[L.ev0], ctx->ev_pool[L.ev1]));
         ++cnt;
         t += e;
         b += L.bytes;

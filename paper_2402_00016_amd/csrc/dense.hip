@@ -444,7 +444,6 @@ __device__ bool leja_order(double2 *ev, int n) {
 // fallen below tol |z| (or stopped shrinking below 1e-11 |z|) is frozen.
 // Launches after the last root froze return at once; if roots are still
 // moving after AB_SWEEPS sweeps, the QR kernels take over.
-constexpr int AB_G = 16;         // lanes per root: one DPP row
 constexpr int AB_MAXN = 256;     // larger matrices go to the QR kernels directly
 constexpr int AB_SWEEPS = 40;    // sweeps before the QR kernels take over
 constexpr double AB_TOL = 1e-15;
@@ -496,6 +495,16 @@ __device__ __forceinline__ double row_sum16(double v) {
     return dpp_d<0x15F>(v);
 }
 __device__ __forceinline__ zd row_sum16(zd v) { return mk(row_sum16(v.re), row_sum16(v.im)); }
+// Sum over a group of G = 16 or 32 lanes (two DPP rows joined by a lane-16
+// exchange; the same bits in every lane: a + b == b + a).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+    v = row_sum16(v);
+    if constexpr (G == 32) v += __shfl_xor(v, 16, 64);
+    return v;
+}
+template <int G>
+__device__ __forceinline__ zd group_sum(zd v) { return mk(group_sum<G>(v.re), group_sum<G>(v.im)); }
 
 // Centre = trace / n, radius = ||A - centre||_F / sqrt(n); initial estimates
 // on that circle, rotated off the real axis.
@@ -558,33 +567,32 @@ __global__ __launch_bounds__(256) void k_aberth_init(const double2 *A, int lda, 
     }
 }
 
-// s = sum_{j >= i} B(i, j) x_j and its derivative, B = A - z, for this lane's
-// columns (row i of A in a[]).
-template <int Q>
-__device__ __forceinline__ void hyman_row(const zd (&a)[Q], const zd (&x)[Q], const zd (&xp)[Q], int i, int n, int g,
-                                          zd z, zd &s, zd &sp) {
+// Row sums of Hyman's recurrence for row i of A (in a[], this lane's
+// columns): s = sum_j A(i, j) x_j - z x_i and s' = sum_j A(i, j) x'_j - z x'_i
+// - x_i, over the slots p0 .. Q-1.  Columns below i hold x_j = 0 (not computed
+// yet), so the sums need no mask.
+template <int G, int Q>
+__device__ __forceinline__ void hyman_row(const zd (&a)[Q], const zd (&x)[Q], const zd (&xp)[Q], int p0, int n, zd z,
+                                          zd xi, zd xpi, zd &s, zd &sp) {
     s = mk(0.0, 0.0);
     sp = mk(0.0, 0.0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        if (AB_G * q + AB_G - 1 < i || AB_G * q >= n) continue;   // uniform: no column >= i here
-        const int j = g + AB_G * q;
-        zd b = j >= i ? a[q] : mk(0.0, 0.0);
-        if (j == i) b = b - z;
-        s = s + b * x[q];
-        sp = sp + b * xp[q];
-        if (j == i) sp = sp - x[q];
+        if (q < p0) continue;    // a constant once the caller's slot loop is unrolled
+        if (G * q >= n) break;   // uniform
+        s = s + a[q] * x[q];
+        sp = sp + a[q] * xp[q];
     }
-    s = row_sum16(s);
-    sp = row_sum16(sp);
+    s = group_sum<G>(s) - z * xi;
+    sp = group_sum<G>(sp) - z * xpi - xi;
 }
 
-template <int Q>
+template <int G, int Q>
 __global__ __launch_bounds__(256) void k_aberth_sweep(AberthWs w, int n, int t, double tol) {
     const double2 *zin = w.z + (size_t)(t & 1) * n;
     double2 *zout = w.z + (size_t)((t + 1) & 1) * n;
-    const int g = threadIdx.x & (AB_G - 1);
-    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) / AB_G);   // the same in all 16 lanes of a row
+    const int g = threadIdx.x & (G - 1);
+    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) / G);   // the same in all G lanes of the group
     if (k >= n) return;
     const zd zk = ld(zin, k);
     if (w.left[t] == 0 || w.conv[k]) {
@@ -594,49 +602,59 @@ __global__ __launch_bounds__(256) void k_aberth_sweep(AberthWs w, int n, int t, 
     zd x[Q], xp[Q], a[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int j = g + AB_G * q;
+        const int j = g + G * q;
         x[q] = mk(j == n - 1 ? 1.0 : 0.0, 0.0);
         xp[q] = mk(0.0, 0.0);
         a[q] = j < n ? ld(w.arow, (long)(n - 1) * n + j) : mk(0.0, 0.0);
     }
+    zd xi = mk(1.0, 0.0), xpi = mk(0.0, 0.0);   // x_i, x'_i of the current row (uniform)
     zd rs = ld(w.rsub, n - 1);
-    for (int i = n - 1; i >= 1; --i) {
-        zd an[Q];   // row i - 1, in flight while row i is summed
+    int i = n - 1;
+    // Rows in descending order, grouped by the slot QS of their new column
+    // i - 1 (unrolled: every register index is a constant); slots below QS
+    // hold no computed column yet and are neither summed nor loaded.
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            const int j = g + AB_G * q;
-            an[q] = (AB_G * q < n && j < n) ? ld(w.arow, (long)(i - 1) * n + j) : mk(0.0, 0.0);
-        }
-        const zd rsn = ld(w.rsub, i - 1);
-        zd s, sp;
-        hyman_row<Q>(a, x, xp, i, n, g, zk, s, sp);
-        const zd xn = rs * s, xpn = rs * sp;   // x_{i-1}, x'_{i-1}: the same bits in every lane
+    for (int QS = Q - 1; QS >= 0; --QS) {
+        for (; i >= 1 && i - 1 >= G * QS; --i) {
+            zd an[Q];   // row i - 1, in flight while row i is summed
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
-            if (g + AB_G * q == i - 1) {
-                x[q] = xn;
-                xp[q] = xpn;
+            for (int q = QS; q < Q; ++q) {
+                const int j = g + G * q;
+                an[q] = (G * q < n && j < n) ? ld(w.arow, (long)(i - 1) * n + j) : mk(0.0, 0.0);
             }
-        const double mx = fmax(fmax(fabs(xn.re), fabs(xn.im)), fmax(fabs(xpn.re), fabs(xpn.im)));
-        if (mx > 0x1p400) {   // a common power-of-two scale leaves f / f' unchanged
+            const zd rsn = ld(w.rsub, i - 1);
+            zd s, sp;
+            hyman_row<G, Q>(a, x, xp, QS, n, zk, xi, xpi, s, sp);
+            xi = rs * s;    // x_{i-1}, x'_{i-1}: the same bits in every lane
+            xpi = rs * sp;
+            const bool own = g == i - 1 - G * QS;
+            x[QS].re = own ? xi.re : x[QS].re;
+            x[QS].im = own ? xi.im : x[QS].im;
+            xp[QS].re = own ? xpi.re : xp[QS].re;
+            xp[QS].im = own ? xpi.im : xp[QS].im;
+            const double mx = fmax(fmax(fabs(xi.re), fabs(xi.im)), fmax(fabs(xpi.re), fabs(xpi.im)));
+            if (mx > 0x1p400) {   // a common power-of-two scale leaves f / f' unchanged
 #pragma unroll
-            for (int q = 0; q < Q; ++q) {
-                x[q] = 0x1p-400 * x[q];
-                xp[q] = 0x1p-400 * xp[q];
+                for (int q = QS; q < Q; ++q) {
+                    x[q] = 0x1p-400 * x[q];
+                    xp[q] = 0x1p-400 * xp[q];
+                }
+                xi = 0x1p-400 * xi;
+                xpi = 0x1p-400 * xpi;
             }
-        }
 #pragma unroll
-        for (int q = 0; q < Q; ++q) a[q] = an[q];
-        rs = rsn;
+            for (int q = QS; q < Q; ++q) a[q] = an[q];
+            rs = rsn;
+        }
     }
     zd f, fp;
-    hyman_row<Q>(a, x, xp, 0, n, g, zk, f, fp);
+    hyman_row<G, Q>(a, x, xp, 0, n, zk, xi, xpi, f, fp);
     const bool flat = fp.re == 0.0 && fp.im == 0.0;
     const zd N = flat ? mk((double)NAN, (double)NAN) : zdiv(f, fp);   // NaN: no Newton step; the QR takes over
     zd S = mk(0.0, 0.0);
-    for (int j = g; j < n; j += AB_G)
+    for (int j = g; j < n; j += G)
         if (j != k) S = S + zdiv(mk(1.0, 0.0), zk - ld(zin, j));
-    S = row_sum16(S);
+    S = group_sum<G>(S);
     const zd den = mk(1.0, 0.0) - N * S;
     const zd wk = (den.re == 0.0 && den.im == 0.0) ? N : zdiv(N, den);
     if (g == 0) {
@@ -654,13 +672,14 @@ __global__ __launch_bounds__(256) void k_aberth_sweep(AberthWs w, int n, int t, 
 // with the eigenvalues at aberth_result(w, n).
 static int aberth_run(mpmc_ctx *ctx, const double2 *A, int lda, int n, const AberthWs &w) {
     k_aberth_init<<<1, 256, 0, ctx->stream>>>(A, lda, n, w);
-    const unsigned blocks = (unsigned)((n + 15) / 16);
+    // 16 lanes per root up to 128 rows, 32 beyond; at most 8 columns per lane
+    const unsigned b16 = (unsigned)((n + 15) / 16), b32 = (unsigned)((n + 7) / 8);
     for (int t = 0; t < AB_SWEEPS; ++t) {
-        if (n <= 32) k_aberth_sweep<2><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
-        else if (n <= 64) k_aberth_sweep<4><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
-        else if (n <= 128) k_aberth_sweep<8><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
-        else if (n <= 192) k_aberth_sweep<12><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
-        else k_aberth_sweep<16><<<blocks, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+        if (n <= 32) k_aberth_sweep<16, 2><<<b16, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+        else if (n <= 64) k_aberth_sweep<16, 4><<<b16, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+        else if (n <= 128) k_aberth_sweep<16, 8><<<b16, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+        else if (n <= 160) k_aberth_sweep<32, 5><<<b32, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
+        else k_aberth_sweep<32, 8><<<b32, 256, 0, ctx->stream>>>(w, n, t, AB_TOL);
     }
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
@@ -943,115 +962,143 @@ int dense_hess_eigs(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, double *
 }
 
 // ------------------------------------------- inverse iteration vectors --
-// One workgroup (one wavefront) per eigenvalue mu_q: three solves of
-// (H_m - mu I) y = y_prev by Hessenberg LU with adjacent-row pivoting, the row
-// operations spread over the lanes; y normalised after each solve.
-// Y: m x k column-major.  The factor lives in LDS (packed) when it fits.
-template <typename Mat>
-__device__ void inverse_iteration(Mat A, const double2 *H, int ldh, int m, zd mq, double hn, double2 *y) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    __shared__ int s_swap;
-    __shared__ double2 s_red[64];
-    for (int i = tid; i < m; i += nt) y[i] = make_double2(1.0, 0.0);
+// One wavefront per eigenvalue mu_q: three solves of (H_m - mu I) y = y_prev by
+// Hessenberg LU with adjacent-row pivoting, y normalised after each solve.
+// The factor lives in LDS (packed) when it fits, else in global memory; y
+// stays in registers, y_j in lane j % 64 of slot j / 64.  Every lane takes the
+// same pivot decision from the factor, row operations run over the lanes, and
+// the back substitution's row sums are wavefront butterflies (the same bits
+// in every lane).  Y: m x k column-major.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+template <int YS>
+__device__ __forceinline__ zd y_get(const zd (&y)[YS], int j) {   // j uniform
+    zd v = mk(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < YS; ++q)
+        if (q == (j >> 6)) v = y[q];
+    return rdlane(v, j & 63);
+}
+template <int YS>
+__device__ __forceinline__ void y_set(zd (&y)[YS], int j, zd v) {   // j uniform, v the same in every lane
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < YS; ++q)
+        if (q == (j >> 6) && lane == (j & 63)) y[q] = v;
+}
+
+template <int YS, typename Mat>
+__device__ void inverse_iteration(Mat A, const double2 *H, int ldh, int m, zd mq, double hn, double2 *yout) {
+    const int lane = threadIdx.x & 63;
+    zd y[YS];
+#pragma unroll
+    for (int q = 0; q < YS; ++q) y[q] = mk(lane + 64 * q < m ? 1.0 : 0.0, 0.0);
     for (int it = 0; it < 3; ++it) {
         __syncthreads();
         for (int j = 0; j < m; ++j)
-            for (int i = tid; i <= (j + 1 < m ? j + 1 : m - 1); i += nt) {
+            for (int i = lane; i <= (j + 1 < m ? j + 1 : m - 1); i += 64) {
                 zd v = ld(H, i + (long)j * ldh);
                 if (i == j) v = v - mq;
                 st(&A(i, j), 0, v);
             }
         __syncthreads();
         for (int k = 0; k < m; ++k) {
-            if (tid == 0) {
-                s_swap = (k + 1 < m && zabs(ld(&A(k + 1, k), 0)) > zabs(ld(&A(k, k), 0))) ? 1 : 0;
-            }
-            __syncthreads();
-            if (s_swap) {
-                for (int j = k + tid; j < m; j += nt) {
+            const zd akk = ld(&A(k, k), 0);
+            const zd ak1 = k + 1 < m ? ld(&A(k + 1, k), 0) : mk(0.0, 0.0);
+            if (k + 1 < m && zabs(ak1) > zabs(akk)) {   // uniform: every lane reads the same entries
+                __syncthreads();
+                for (int j = k + lane; j < m; j += 64) {
                     const double2 t = A(k, j);
                     A(k, j) = A(k + 1, j);
                     A(k + 1, j) = t;
                 }
-                if (tid == 0) {
-                    const double2 t = y[k];
-                    y[k] = y[k + 1];
-                    y[k + 1] = t;
-                }
+                const zd yk = y_get(y, k), yk1 = y_get(y, k + 1);
+                y_set(y, k, yk1);
+                y_set(y, k + 1, yk);
             }
             __syncthreads();
-            if (tid == 0 && zabs(ld(&A(k, k), 0)) < DBL_EPSILON * hn) A(k, k) = make_double2(DBL_EPSILON * hn, 0.0);
+            zd piv = ld(&A(k, k), 0);
+            if (zabs(piv) < DBL_EPSILON * hn) piv = mk(DBL_EPSILON * hn, 0.0);
             __syncthreads();
+            if (lane == 0) st(&A(k, k), 0, piv);
             if (k + 1 < m) {
-                const zd l = zdiv(ld(&A(k + 1, k), 0), ld(&A(k, k), 0));
-                for (int j = k + 1 + tid; j < m; j += nt)
+                const zd l = zdiv(ld(&A(k + 1, k), 0), piv);
+                for (int j = k + 1 + lane; j < m; j += 64)
                     st(&A(k + 1, j), 0, ld(&A(k + 1, j), 0) - l * ld(&A(k, j), 0));
-                if (tid == 0) st(y, k + 1, ld(y, k + 1) - l * ld(y, k));
+                y_set(y, k + 1, y_get(y, k + 1) - l * y_get(y, k));
             }
             __syncthreads();
         }
-        // back substitution, one row at a time with a lane reduction
         for (int i = m - 1; i >= 0; --i) {
             zd part = mk(0.0, 0.0);
-            for (int j = i + 1 + tid; j < m; j += nt) part = part + ld(&A(i, j), 0) * ld(y, j);
-            s_red[tid] = make_double2(part.re, part.im);
-            __syncthreads();
-            if (tid == 0) {
-                zd acc = ld(y, i);
-                for (int q = 0; q < nt; ++q) acc = acc - ld(s_red, q);
-                st(y, i, zdiv(acc, ld(&A(i, i), 0)));
+#pragma unroll
+            for (int q = 0; q < YS; ++q) {
+                const int j = lane + 64 * q;
+                if (j > i && j < m) part = part + ld(&A(i, j), 0) * y[q];
             }
-            __syncthreads();
+            const zd sum = mk(wave_sum(part.re), wave_sum(part.im));
+            y_set(y, i, zdiv(y_get(y, i) - sum, ld(&A(i, i), 0)));
         }
-        zd part = mk(0.0, 0.0);
-        for (int i = tid; i < m; i += nt) part.re += y[i].x * y[i].x + y[i].y * y[i].y;
-        s_red[tid] = make_double2(part.re, 0.0);
-        __syncthreads();
-        double nr = 0;
-        for (int q = 0; q < nt; ++q) nr += s_red[q].x;
-        nr = sqrt(nr);
+        double nr = 0.0;
+#pragma unroll
+        for (int q = 0; q < YS; ++q) nr += y[q].re * y[q].re + y[q].im * y[q].im;
+        nr = sqrt(wave_sum(nr));
         const double inv = nr > 0 ? 1.0 / nr : 0.0;
-        __syncthreads();
-        for (int i = tid; i < m; i += nt) y[i] = make_double2(y[i].x * inv, y[i].y * inv);
+#pragma unroll
+        for (int q = 0; q < YS; ++q) y[q] = inv * y[q];
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < YS; ++q)
+        if (lane + 64 * q < m) st(yout, lane + 64 * q, y[q]);
 }
 
+template <int YS>
 __global__ __launch_bounds__(64) void k_inverse_iteration(const double2 *H, int ldh, int m, const double2 *mu,
                                                           double2 *work, double2 *Y, int use_lds) {
     extern __shared__ double2 lds_mat[];
     const int q = blockIdx.x;
-    __shared__ double s_hn;
-    if (threadIdx.x == 0) {
-        double mx = 0;
-        for (int j = 0; j < m; ++j)
-            for (int i = 0; i <= (j + 1 < m ? j + 1 : m - 1); ++i) {
-                const double2 v = H[i + (long)j * ldh];
-                mx = fmax(mx, hypot(v.x, v.y));
-            }
-        s_hn = mx;
-    }
-    __syncthreads();
+    double mx = 0.0;
+    for (int j = 0; j < m; ++j)
+        for (int i = threadIdx.x; i <= (j + 1 < m ? j + 1 : m - 1); i += 64) {
+            const double2 v = H[i + (long)j * ldh];
+            mx = fmax(mx, hypot(v.x, v.y));
+        }
+    const double hn = wave_max(mx);
     double2 *y = Y + (long)q * m;
     if (use_lds) {
-        inverse_iteration(PackedMat{lds_mat}, H, ldh, m, ld(mu, q), s_hn, y);
+        inverse_iteration<YS>(PackedMat{lds_mat}, H, ldh, m, ld(mu, q), hn, y);
     } else {
-        inverse_iteration(GlobalMat{work + (size_t)q * m * m, m}, H, ldh, m, ld(mu, q), s_hn, y);
+        inverse_iteration<YS>(GlobalMat{work + (size_t)q * m * m, m}, H, ldh, m, ld(mu, q), hn, y);
     }
 }
 
 int dense_inverse_iteration(mpmc_ctx *ctx, const double *H_dev, int ldh, int m, const double *mu_dev, int k,
                             double *Y_dev) {
     if (k < 1) return MPMC_OK;
+    if (m > 512) return set_err(ctx, MPMC_EINVAL, "inverse iteration: m=%d above 512", m);
     const size_t lb = (size_t)packed_hess_size(m) * sizeof(double2);
-    const bool lds = want_lds(ctx, k_inverse_iteration, lb);
+    const int ys = m <= 128 ? 2 : (m <= 256 ? 4 : 8);
+    const bool lds = ys == 2 ? want_lds(ctx, k_inverse_iteration<2>, lb)
+                             : (ys == 4 ? want_lds(ctx, k_inverse_iteration<4>, lb) : want_lds(ctx, k_inverse_iteration<8>, lb));
     double2 *work = nullptr;
     if (!lds) {
         work = (double2 *)ws_get(ctx, WS_DENSE, (size_t)k * m * m * sizeof(double2));
         if (!work) return MPMC_ENOMEM;
     }
-    k_inverse_iteration<<<k, 64, lds ? lb : 0, ctx->stream>>>((const double2 *)H_dev, ldh, m, (const double2 *)mu_dev,
-                                                              work, (double2 *)Y_dev, lds ? 1 : 0);
+    const double2 *Hd = (const double2 *)H_dev, *mud = (const double2 *)mu_dev;
+    double2 *Yd = (double2 *)Y_dev;
+    const size_t sh = lds ? lb : 0;
+    if (ys == 2) k_inverse_iteration<2><<<k, 64, sh, ctx->stream>>>(Hd, ldh, m, mud, work, Yd, lds ? 1 : 0);
+    else if (ys == 4) k_inverse_iteration<4><<<k, 64, sh, ctx->stream>>>(Hd, ldh, m, mud, work, Yd, lds ? 1 : 0);
+    else k_inverse_iteration<8><<<k, 64, sh, ctx->stream>>>(Hd, ldh, m, mud, work, Yd, lds ? 1 : 0);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }

@@ -694,7 +694,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, true
 // ---------------------------------------------------- single vectors --
 // nrhs == 1 (GMRES-polynomial and deflation Arnoldi cycles): eight lanes per
 // site, one hop each, so a single-vector matvec occupies 8x more wavefronts;
-// the eight 12-component contributions are summed with lane shuffles.
+// the eight 12-component contributions are summed with DPP (quad xor 1 and 2,
+// then row_shr 4, which leaves the site's total in lane 4 of its group), and
+// lane 4 loads the epilogue operands before the hop, so they arrive while
+// the hop computes.
 template <typename T>
 __device__ __forceinline__ cpx<T> mulc_rt(cpx<T> z, int code) {
     T a = z.re, b = z.im;
@@ -710,6 +713,29 @@ __device__ __forceinline__ cpx<T> mulc_rt(cpx<T> z, int code) {
     return mk(a, b);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_t(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_t(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+// Sum over the 8-lane group: quad_perm [1,0,3,2] and [2,3,0,1] (every lane of
+// a quad holds the quad's sum), then row_shr 4: lanes 4..7 of the group (and
+// 12..15 of the next, within the same 16-lane row) add the first quad.
+template <typename T>
+__device__ __forceinline__ T group8_sum1(T v) {
+    v += dpp_t<0xB1>(v);
+    v += dpp_t<0x4E>(v);
+    return v + dpp_t<0x114>(v);
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> group8_sum(cpx<T> v) { return mk(group8_sum1(v.re), group8_sum1(v.im)); }
+
 template <int P>
 __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, const int *__restrict__ nbr,
                                                  const typename LinkT<P>::type *__restrict__ links, WOut o, long V) {
@@ -718,6 +744,19 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
     const long s = t >> 3;
     const int h = (int)(t & 7);
     const bool live = s < V;
+    const bool epi = live && h == 4;   // the lane that finishes the site
+    const typename Elem<P>::type *sp = reinterpret_cast<const typename Elem<P>::type *>(b) + s * 12;
+    const typename Elem<P>::type *ap = reinterpret_cast<const typename Elem<P>::type *>(o.a_is_b ? b : o.a) + s * 12;
+    typename Elem<P>::type *yp = reinterpret_cast<typename Elem<P>::type *>(o.y) + s * 12;
+    typename Elem<P>::type *op = reinterpret_cast<typename Elem<P>::type *>(o.out) + s * 12;
+    const bool has_a = o.a_is_b || o.a;
+    cpx<T> bt[12], av[12], yv[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        bt[k] = epi ? mk((T)sp[k].x, (T)sp[k].y) : mk(T(0), T(0));
+        av[k] = epi && has_a ? mk((T)ap[k].x, (T)ap[k].y) : mk(T(0), T(0));
+        yv[k] = epi && o.y ? mk((T)yp[k].x, (T)yp[k].y) : mk(T(0), T(0));
+    }
     cpx<T> c[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) c[k] = mk(T(0), T(0));
@@ -768,33 +807,13 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
             c[9 + a] = sg * mulc_rt(k3 ? uh[1][a] : uh[0][a], d3);
         }
     }
-    // sum the eight hops of a site (lanes 8q .. 8q+7)
+    // sum the eight hops of a site (lanes 8q .. 8q+7) into lane 8q + 4
 #pragma unroll
-    for (int off = 1; off < 8; off <<= 1) {
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            c[k].re += __shfl_xor(c[k].re, off);
-            c[k].im += __shfl_xor(c[k].im, off);
-        }
-    }
-    if (!live || h != 0) return;
+    for (int k = 0; k < 12; ++k) c[k] = group8_sum(c[k]);
+    if (!epi) return;
     const T kap = (T)o.kappa;
     const cpx<T> al = mk((T)o.alpha.x, (T)o.alpha.y);
     const cpx<T> be = mk((T)o.beta.x, (T)o.beta.y);
-    // operands loaded before any store (out may alias nothing the compiler
-    // can prove, so interleaved stores would serialise the loads)
-    const typename Elem<P>::type *sp = reinterpret_cast<const typename Elem<P>::type *>(b) + s * 12;
-    const typename Elem<P>::type *ap = reinterpret_cast<const typename Elem<P>::type *>(o.a_is_b ? b : o.a) + s * 12;
-    typename Elem<P>::type *yp = reinterpret_cast<typename Elem<P>::type *>(o.y) + s * 12;
-    typename Elem<P>::type *op = reinterpret_cast<typename Elem<P>::type *>(o.out) + s * 12;
-    const bool has_a = o.a_is_b || o.a;
-    cpx<T> bt[12], av[12], yv[12];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) bt[k] = mk((T)sp[k].x, (T)sp[k].y);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) av[k] = has_a ? mk((T)ap[k].x, (T)ap[k].y) : mk(T(0), T(0));
-#pragma unroll
-    for (int k = 0; k < 12; ++k) yv[k] = o.y ? mk((T)yp[k].x, (T)yp[k].y) : mk(T(0), T(0));
     const cpx<T> ga = mk((T)o.gamma.x, (T)o.gamma.y);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -1098,19 +1117,21 @@ int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, v
     o.g = dagger ? -1.f : 1.f;
     o.theta = theta;
     o.out_fp32 = 0;
-    const int ev = timing_begin(ctx);
+    const int ev = nrhs > 1 ? timing_begin(ctx) : -1;   // single vectors: counted, no events
     if (prec == MPMC_FP64) launch_w<MPMC_FP64>(ctx, b, o, nrhs);
     else if (prec == MPMC_FP32) launch_w<MPMC_FP32>(ctx, b, o, nrhs);
     else launch_w<MPMC_FP16S>(ctx, b, o, nrhs);
     HIP_OR_RET(ctx, hipGetLastError());
-    if (ev >= 0) {
+    if (ctx->timing) {
         // algorithmic bytes: operand read once, a read once if distinct,
         // out written once, y read and written, links once per site
         const double sb = spinor_bytes(prec);
         double per = 2 * sb;
         if (a && a != b) per += sb;
         if (y) per += 2 * sb;
-        timing_end(ctx, ev, prec | MPMC_TIMING_PLAIN, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
+        const double bytes = (double)ctx->V * ((double)nrhs * per + link_bytes(prec));
+        if (ev >= 0) timing_end(ctx, ev, prec | MPMC_TIMING_PLAIN, bytes);
+        else timing_count(ctx, prec | MPMC_TIMING_SINGLE, bytes);
     }
     ctx->mvps += (uint64_t)nrhs;
     return MPMC_OK;

@@ -25,7 +25,7 @@ OK, EINVAL, ENOMEM, EHIP, ENOCONV, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -6
 DENSE_ABERTH, DENSE_QR = 0, 1   # eigenvalue solvers of the small dense problems
 FP64, FP32, FP16S = 0, 1, 2
 THETA_I, THETA_G5 = 0, 1
-TIMING_PLAIN, TIMING_FUSED = 16, 32     # or-ed into the precision of mpmc_timing_read
+TIMING_PLAIN, TIMING_FUSED, TIMING_SINGLE = 16, 32, 64   # or-ed into the precision of mpmc_timing_read
 PREC = {"fp64": FP64, "fp32": FP32, "fp16s": FP16S}
 THETA = {"I": THETA_I, "g5": THETA_G5}
 

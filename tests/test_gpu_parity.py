@@ -511,6 +511,24 @@ def test_apply_batch_matches_single(prec, variant):
         mpmc.Context.apply_M_batch(ctxs * 3, xs * 3, N, prec)
 
 
+def test_timing_counts_single_vectors_without_events(f44):
+    """Launch timing: multi-RHS launches carry event times, single-vector
+    launches are counted with their algorithmic bytes only."""
+    dims, kappa, U, op, ctx = f44
+    V = op.n // 12
+    x1, x64 = ctx.noise(3, 0, 0, 1, FP64), ctx.noise(3, 0, 0, 64, FP64)
+    mpmc.mpmc_timing_enable(ctx.handle, 1)
+    ctx.apply_M(x1, 1, FP64)
+    ctx.apply_M(x64, 64, FP64)
+    n1, ms1, b1 = mpmc.mpmc_timing_read(ctx.handle, FP64 | mpmc.TIMING_SINGLE)
+    n64, ms64, b64 = mpmc.mpmc_timing_read(ctx.handle, FP64 | mpmc.TIMING_PLAIN)
+    na, msa, ba = mpmc.mpmc_timing_read(ctx.handle, FP64)
+    mpmc.mpmc_timing_enable(ctx.handle, 0)
+    assert (n1, ms1, b1) == (1, 0.0, V * (2 * 192.0 + 576.0))
+    assert n64 == 1 and ms64 > 0 and b64 == V * (64 * 2 * 192.0 + 576.0)
+    assert (na, msa, ba) == (2, ms64, b1 + b64)
+
+
 @pytest.mark.parametrize("N", [64, 20])
 def test_solve_fp16_basis_matches_fp32(N):
     """FP16S Krylov basis (FP32 arithmetic, FP64 defect correction): same true
