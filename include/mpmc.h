@@ -407,6 +407,28 @@ int mpmc_level_estimate(mpmc_ctx *ctx, const mpmc_poly *upper, const mpmc_poly *
                         const mpmc_net *net, double *samples_host, double *corr_host,
                         uint64_t *mvps_host);
 
+/* The polynomial levels of the multipolynomial formula (Sec. 6) together:
+ * term t has the samples, correction and precision semantics of
+ * mpmc_level_estimate(ctx, upper[t], lower[t], defl, theta, seed, streams[t],
+ * first, nnoise, prec, 0, ...) -- bit for bit -- with upper[t] != NULL (the
+ * solve term stays with mpmc_level_estimate) and lower[t] possibly NULL.
+ * Every single-polynomial recurrence of the batch (the upper and the lower
+ * polynomial of each term, on that term's noise) occupies its own run of
+ * nnoise right-hand sides of one operand, runs ordered by decreasing degree,
+ * and step s of all recurrences still running is ONE fused launch; the
+ * per-chunk coefficients come from a table uploaded once.  Terms with a
+ * double polynomial, and all terms when nnoise % 64 != 0 or V % 4 != 0, run
+ * one by one through mpmc_level_estimate.  nterms <= 64.
+ * samples_host: complex double [nterms][nnoise]; corr_host (may be NULL):
+ * complex double [nterms]; mvps_host (may be NULL): MVPs used.  Device
+ * memory: 3 operands of nterms*2*nnoise right-hand sides in precision prec
+ * plus 4 bytes per (site, rhs) of noise codes.  Synchronises. */
+int mpmc_level_estimate_multi(mpmc_ctx *ctx, int nterms, const mpmc_poly *const *upper,
+                              const mpmc_poly *const *lower, const mpmc_defl *defl, int theta,
+                              uint64_t seed, const uint32_t *streams, uint64_t first, int nnoise,
+                              int prec, double *samples_host, double *corr_host,
+                              uint64_t *mvps_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -290,7 +290,8 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned bid, unsigned nblocks) {
 
 // ---------------------------------------------------- cross-file host API --
 // context.hip
-int launch_noise(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, int prec, void *internal);
+int launch_noise(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, int prec, void *internal,
+                 int ld = 0, int off = 0);   // columns off .. off+nrhs-1 of an operand of ld right-hand sides
 
 // blas.hip.  Basis vectors Vb[j] are spaced vstride complex elements apart and
 // hold vN right-hand sides (vN == nrhs, or vN == 1 for single vectors that are
@@ -320,7 +321,13 @@ int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, v
                        double2 alpha, double2 beta, double2 gamma, int dagger, int theta);
 // fused level step (see wilson.hip): w' = w - c M w; partial += cnext eta^H Theta w'
 size_t wilson_dot_partial_count(const mpmc_ctx *ctx, int nrhs);
-int wilson_noise_codes(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, uint32_t *codes);
+// codes of noise vectors first .. first+nrhs-1 into columns off .. of rows of
+// ld entries (ld = 0: ld = nrhs)
+int wilson_noise_codes(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, uint32_t *codes,
+                       int ld = 0, int off = 0);
+int wilson_dot_step_multi(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *codes, int nrhs, int nact,
+                          int prec, const double *coef_dev, int theta, double *partial, int first_step);
+int wilson_dot_finish_chunks(mpmc_ctx *ctx, const double *partial, int nrhs, double *out);
 int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *codes, int nrhs, int prec, double2 c,
                     double2 cnext, int theta, double *partial, int first_step);
 int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, int prec, double *out, int accumulate,

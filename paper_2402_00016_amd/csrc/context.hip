@@ -353,7 +353,8 @@ MPMC_API int mpmc_unpack(mpmc_ctx *ctx, const void *internal, void *canon, int n
 // -------------------------------------------------------------- noise --
 
 template <int P>
-__global__ void k_noise(uint64_t seed, uint32_t stream, uint64_t first, VecRef out, long V, int N) {
+// N noise vectors into columns off .. off+N-1 of an operand of ld right-hand sides
+__global__ void k_noise(uint64_t seed, uint32_t stream, uint64_t first, VecRef out, long V, int N, int ld, int off) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= V * N) return;
     const long s = t / N;
@@ -365,22 +366,28 @@ __global__ void k_noise(uint64_t seed, uint32_t stream, uint64_t first, VecRef o
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             cpx<float> v = z4_value<float>((sym >> (2 * k)) & 3u);
-            d[(s * 12 + k) * N + r] = __floats2half2_rn(v.re, v.im);
+            d[(s * 12 + k) * ld + off + r] = __floats2half2_rn(v.re, v.im);
         }
-        out.sc[s * N + r] = 1.0f;
+        out.sc[s * ld + off + r] = 1.0f;
     } else {
 #pragma unroll
-        for (int k = 0; k < 12; ++k) Store<P>::st(out.d, (s * 12 + k) * N + r, z4_value<R>((sym >> (2 * k)) & 3u));
+        for (int k = 0; k < 12; ++k)
+            Store<P>::st(out.d, (s * 12 + k) * ld + off + r, z4_value<R>((sym >> (2 * k)) & 3u));
     }
 }
 
-int launch_noise(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, int prec, void *internal) {
+int launch_noise(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, int prec, void *internal,
+                 int ld, int off) {
+    if (ld <= 0) ld = nrhs;
     const long work = ctx->V * nrhs;
-    VecRef o = vref(ctx, internal, nrhs, prec);
+    VecRef o = vref(ctx, internal, ld, prec);
     const int B = 256;
-    if (prec == MPMC_FP64) k_noise<MPMC_FP64><<<grid_for(work, B), B, 0, ctx->stream>>>(seed, stream, first, o, ctx->V, nrhs);
-    else if (prec == MPMC_FP32) k_noise<MPMC_FP32><<<grid_for(work, B), B, 0, ctx->stream>>>(seed, stream, first, o, ctx->V, nrhs);
-    else k_noise<MPMC_FP16S><<<grid_for(work, B), B, 0, ctx->stream>>>(seed, stream, first, o, ctx->V, nrhs);
+    if (prec == MPMC_FP64)
+        k_noise<MPMC_FP64><<<grid_for(work, B), B, 0, ctx->stream>>>(seed, stream, first, o, ctx->V, nrhs, ld, off);
+    else if (prec == MPMC_FP32)
+        k_noise<MPMC_FP32><<<grid_for(work, B), B, 0, ctx->stream>>>(seed, stream, first, o, ctx->V, nrhs, ld, off);
+    else
+        k_noise<MPMC_FP16S><<<grid_for(work, B), B, 0, ctx->stream>>>(seed, stream, first, o, ctx->V, nrhs, ld, off);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }

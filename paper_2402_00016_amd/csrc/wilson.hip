@@ -837,13 +837,20 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
 // summed over the block's sites.  Requires N % 64 == 0 (uniform wavefronts).
 // A block of 256 threads covers spb = max(1, 256/N) sites and rpb = min(N, 256)
 // right-hand sides starting at rhs (blk*256) % N.
-template <int P, int ORDER>
+//
+// MULTI (blocked 64-wide chunks only): several recurrences side by side, each
+// a run of 64-wide chunks of the right-hand-side axis (stride N); the launch
+// covers the first nact right-hand sides, and chunk q takes its (c, cnext)
+// from coef[2q], coef[2q + 1].
+template <int P, int ORDER, bool MULTI = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_FP64 ? 1 : 2))) void k_wilson_dot(const void *__restrict__ b, const int *__restrict__ nbr,
                                                     const typename LinkT<P>::type *__restrict__ links,
                                                     void *__restrict__ out, const uint32_t *__restrict__ codes,
                                                     double2 c, double2 cnext, double kappa, int theta,
                                                     double2 *__restrict__ partial, long V, int N, int first_step,
-                                                    const int *__restrict__ order) {
+                                                    const int *__restrict__ order, int nact = 0,
+                                                    const double2 *__restrict__ coef = nullptr) {
+    static_assert(!MULTI || ORDER == 2, "several recurrences need the blocked 64-wide traversal");
     using T = typename Store<P>::real;
     constexpr bool U = ORDER <= 2;   // one site per wavefront (else 2 or 4, row-distributed links)
     WIn<P> in{b, nullptr, nbr, links};
@@ -851,7 +858,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_F
     __shared__ double2 red[256];
     long s;
     int r;
-    const bool live = locate<U, ORDER>(V, N, s, r, order);
+    const bool live = locate<U, ORDER>(V, MULTI ? nact : N, s, r, order);
+    if constexpr (MULTI) {
+        const unsigned q = live ? (unsigned)r >> 6 : 0u;   // the wavefront's chunk
+        c = coef[2 * q];
+        cnext = coef[2 * q + 1];
+    }
     cpx<double> dot = mk(0.0, 0.0);
     if (live) {
         cpx<T> acc[4][3];
@@ -1014,13 +1026,14 @@ __global__ void k_dot_finish_chunk(const double2 *__restrict__ partial, long til
 }
 
 // codes[s*N + r] = Z(4) symbols of noise vector first + r at site s
+// (noise vectors first .. first+N-1 in columns off .. off+N-1 of rows of ld)
 __global__ void k_noise_codes(uint64_t seed, uint32_t stream, uint64_t first, uint32_t *__restrict__ codes, long V,
-                              int N) {
+                              int N, int ld, int off) {
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= V * N) return;
     const long s = t / N;
     const int r = (int)(t - s * N);
-    codes[t] = z4_site_symbols(seed, stream, (uint32_t)(first + r), s);
+    codes[s * ld + off + r] = z4_site_symbols(seed, stream, (uint32_t)(first + r), s);
 }
 
 // ------------------------------------------------------------- launch --
@@ -1168,9 +1181,11 @@ size_t wilson_dot_partial_count(const mpmc_ctx *ctx, int nrhs) {
     return (size_t)blocks * (nrhs < 256 ? nrhs : 256);
 }
 
-int wilson_noise_codes(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, uint32_t *codes) {
+int wilson_noise_codes(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t first, int nrhs, uint32_t *codes,
+                       int ld, int off) {
     const long work = ctx->V * nrhs;
-    k_noise_codes<<<grid_for(work, 256), 256, 0, ctx->stream>>>(seed, stream, first, codes, ctx->V, nrhs);
+    k_noise_codes<<<grid_for(work, 256), 256, 0, ctx->stream>>>(seed, stream, first, codes, ctx->V, nrhs,
+                                                                ld > 0 ? ld : nrhs, off);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
@@ -1223,6 +1238,48 @@ int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *co
         timing_end(ctx, ev, prec | MPMC_TIMING_FUSED, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
     }
     ctx->mvps += (uint64_t)nrhs;
+    return MPMC_OK;
+}
+
+// Fused step over several recurrences side by side (the blocked 64-wide
+// traversal): right-hand sides [0, nact) of operands with stride nrhs, chunk
+// q's coefficients at coef_dev[2q], coef_dev[2q + 1]; partial as for
+// wilson_dot_step with nrhs (chunks at or beyond nact keep their sums).
+int wilson_dot_step_multi(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *codes, int nrhs, int nact,
+                          int prec, const double *coef_dev, int theta, double *partial, int first_step) {
+    if (ctx->V % 4 != 0 || nrhs % 64 != 0 || nact % 64 != 0 || nact < 64 || nact > nrhs)
+        return set_err(ctx, MPMC_EINVAL, "several recurrences need V %% 4 == 0 and 64-wide chunks");
+    const unsigned grid = (unsigned)(ctx->V * nact / 256);
+    const double2 *cf = (const double2 *)coef_dev;
+    const int ev = timing_begin(ctx);
+    if (prec == MPMC_FP64) {
+        const WIn<MPMC_FP64> in = make_in<MPMC_FP64>(ctx, w, nrhs);
+        k_wilson_dot<MPMC_FP64, 2, true><<<grid, 256, 0, ctx->stream>>>(
+            in.b, in.nbr, in.links, wout, codes, make_double2(0, 0), make_double2(0, 0), ctx->kappa, theta,
+            (double2 *)partial, ctx->V, nrhs, first_step, ctx->site_order, nact, cf);
+    } else if (prec == MPMC_FP32) {
+        const WIn<MPMC_FP32> in = make_in<MPMC_FP32>(ctx, w, nrhs);
+        k_wilson_dot<MPMC_FP32, 2, true><<<grid, 256, 0, ctx->stream>>>(
+            in.b, in.nbr, in.links, wout, codes, make_double2(0, 0), make_double2(0, 0), ctx->kappa, theta,
+            (double2 *)partial, ctx->V, nrhs, first_step, ctx->site_order, nact, cf);
+    } else {
+        return set_err(ctx, MPMC_EINVAL, "fused level step supports FP64 and FP32");
+    }
+    HIP_OR_RET(ctx, hipGetLastError());
+    if (ev >= 0) {
+        const double per = 2 * spinor_bytes(prec) + 4.0;
+        timing_end(ctx, ev, prec | MPMC_TIMING_FUSED, (double)ctx->V * ((double)nact * per + link_bytes(prec)));
+    }
+    ctx->mvps += (uint64_t)nact;
+    return MPMC_OK;
+}
+
+// Sums of the blocked 64-wide partials for right-hand sides [0, nrhs) (the
+// several-recurrence step's layout).
+int wilson_dot_finish_chunks(mpmc_ctx *ctx, const double *partial, int nrhs, double *out) {
+    k_dot_finish_chunk<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, ctx->V * 64 / 256, 64, (double2 *)out,
+                                                      0, 1.0);
+    HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
 

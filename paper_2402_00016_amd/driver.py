@@ -66,6 +66,8 @@ class Plan:
     overlap_setup: bool = True           # build polynomials (and train the net) on side streams
     solve_pp: bool = False               # precondition the main solves with p_in (Sec. 8's PP-GMRES)
     autotune: bool = True                # time the Wilson kernel variants for the level batches once per context
+    batch_levels: bool = False           # polynomial terms in shared launches (mpmc_level_estimate_multi);
+                                         # off: one term's operand pair stays in the 256 MB Infinity Cache
 
 
 @dataclass
@@ -284,6 +286,8 @@ def run_levels(ctx, plan: Plan, polys, defl, noises=None, first=0, net=None):
     names = ["M^-1 - p1"] + ["p%d - p%d" % (i + 1, i + 2) for i in range(len(polys) - 1)] + ["p%d" % len(polys)]
     uppers = [None] + polys
     lowers = polys + [None]
+    if plan.batch_levels and len(polys) > 0 and (not plan.max_batch or plan.max_batch >= noises):
+        return _run_levels_batched(ctx, plan, polys, defl, noises, first, net, names, uppers, lowers)
     out = []
     for l, (up, lo) in enumerate(zip(uppers, lowers)):
         d = defl if (up is not None and lo is not None and plan.deflate_levels) else (defl if up is None else None)
@@ -292,6 +296,28 @@ def run_levels(ctx, plan: Plan, polys, defl, noises=None, first=0, net=None):
                              max_batch=plan.max_batch, solve_tol=plan.solve_tol, solve_restart=plan.solve_restart,
                              solve_inner_prec=plan.solve_inner_prec, net=net if up is None else None)
         out.append(LevelResult(names[l], X, T, mv, time.perf_counter() - t0))
+    return out
+
+
+def _run_levels_batched(ctx, plan, polys, defl, noises, first, net, names, uppers, lowers):
+    """The solve term alone, the polynomial terms in shared launches (same
+    samples as one term at a time).  The batch's time and MVPs are shared out
+    over its terms in proportion to their recurrence lengths."""
+    t0 = time.perf_counter()
+    X, T, mv = ctx.level(None, lowers[0], defl, plan.theta, plan.seed, 0, first, noises, prec=plan.poly_prec,
+                         solve_tol=plan.solve_tol, solve_restart=plan.solve_restart,
+                         solve_inner_prec=plan.solve_inner_prec, net=net)
+    out = [LevelResult(names[0], X, T, mv, time.perf_counter() - t0)]
+    t0 = time.perf_counter()
+    ups, los = uppers[1:], lowers[1:]
+    Xs, Ts, mv = ctx.levels_multi(ups, los, defl if plan.deflate_levels else None, plan.theta, plan.seed,
+                                  list(range(1, len(ups) + 1)), first, noises, prec=plan.poly_prec)
+    secs = time.perf_counter() - t0
+    work = [sum(p.info["matvecs"] for p in (u, l) if p is not None) for u, l in zip(ups, los)]
+    tot = max(sum(work), 1)
+    for l in range(len(ups)):
+        share = work[l] / tot
+        out.append(LevelResult(names[l + 1], Xs[l], complex(Ts[l]), int(round(mv * share)), secs * share))
     return out
 
 

@@ -86,6 +86,7 @@ _SIGS = {
     "mpmc_solve_pairs": ([_vp, _vp, _vp, _i, _vp, _i, _d, _i, _i, _vp, _vp, _i, _pi, _pi, _vp], _i),
     "mpmc_level_estimate": ([_vp, _vp, _vp, _vp, _i, _u64, _u32, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp,
                              _pu64], _i),
+    "mpmc_level_estimate_multi": ([_vp, _i, _vp, _vp, _vp, _i, _u64, _vp, _u64, _i, _i, _vp, _vp, _vp], _i),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_L, _name)
@@ -292,6 +293,20 @@ def mpmc_solve_pairs(ctx, b, x, nrhs, defl, restart, tol, inner_prec, max_outer,
                                int(max_outer), _ptr(R), _ptr(E), int(max_snap), ctypes.byref(ns), ctypes.byref(its),
                                rel.ctypes.data), ctx)
     return ns.value, its.value, rel
+
+
+def mpmc_level_estimate_multi(ctx, uppers, lowers, defl, theta, seed, streams, first, nnoise, prec):
+    """Polynomial terms (upper non-None) in shared launches: (samples [nterms, nnoise], corr [nterms], mvps)."""
+    T = len(uppers)
+    up = (ctypes.c_void_p * T)(*[_h(p) for p in uppers])
+    lo = (ctypes.c_void_p * T)(*[_h(p) for p in lowers])
+    st = (ctypes.c_uint32 * T)(*[int(x) for x in streams])
+    samples = np.zeros((T, nnoise), dtype=np.complex128)
+    corr = np.zeros(T, dtype=np.complex128)
+    mvps = ctypes.c_uint64()
+    _check(_L.mpmc_level_estimate_multi(ctx, T, up, lo, _h(defl), int(theta), int(seed), st, int(first), int(nnoise),
+                                        int(prec), samples.ctypes.data, corr.ctypes.data, ctypes.byref(mvps)), ctx)
+    return samples, corr, mvps.value
 
 
 def mpmc_level_estimate(ctx, upper, lower, defl, theta, seed, stream, first, nnoise, prec, max_batch=0,
@@ -626,6 +641,9 @@ class Context:
         ns, its, rel = mpmc_solve_pairs(self.handle, b, x, nrhs, defl, restart, tol, inner_prec, max_outer, R, E,
                                         max_snap)
         return x, R, E, ns, vb
+
+    def levels_multi(self, uppers, lowers, defl, theta, seed, streams, first, nnoise, prec=FP64):
+        return mpmc_level_estimate_multi(self.handle, uppers, lowers, defl, theta, seed, streams, first, nnoise, prec)
 
     def level(self, upper, lower, defl, theta, seed, stream, first, nnoise, prec=FP64, max_batch=0,
               solve_tol=1e-8, solve_restart=50, solve_inner_prec=FP64, net=None):

@@ -37,6 +37,17 @@ def test_overlapped_setup_is_identical(ctx):
     assert e0.mvps == e1.mvps
 
 
+def test_batched_levels_same_estimate(ctx):
+    """Polynomial terms in shared launches: the same samples bit for bit, so
+    the same estimate."""
+    e0 = driver.estimate(ctx, plan(noises=64, batch_levels=False), torch.cuda.synchronize)
+    e1 = driver.estimate(ctx, plan(noises=64, batch_levels=True), torch.cuda.synchronize)
+    for L0, L1 in zip(e0.levels[1:], e1.levels[1:]):
+        assert np.array_equal(L0.samples, L1.samples) and L0.corr == L1.corr
+    assert np.allclose(e0.levels[0].samples, e1.levels[0].samples, rtol=0, atol=1e-9)
+    assert abs(e0.value - e1.value) < 1e-8 and e0.mvps == e1.mvps
+
+
 def test_learned_form_same_estimate(ctx):
     p = plan(solve_inner_prec=mpmc.FP32)
     e0 = driver.estimate(ctx, p, torch.cuda.synchronize)

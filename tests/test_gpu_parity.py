@@ -335,6 +335,51 @@ def test_level_samples_parity(f44):
         assert np.max(np.abs(X - Xr)) < 2 * op.n * 10 * 1e-12
 
 
+@pytest.mark.parametrize("prec,theta", [(FP64, 0), (FP32, 0), (FP32, 1)])
+def test_levels_multi_equal_one_at_a_time(f44, prec, theta):
+    """mpmc_level_estimate_multi gives the samples, corrections and MVPs of
+    mpmc_level_estimate term by term, bit for bit: single polynomials of
+    degrees 16, 8, 3 and 0 share launches (the degree-0 one needs no step), a
+    double polynomial term falls back to one term at a time, and one term has
+    no lower polynomial.  Against the oracle on the first term as well."""
+    dims, kappa, U, op, ctx = f44
+    b = z4_noise(1, 0x100, 0, op.n)
+    P1, _, _ = OK.gmres_poly(op, b, 17)
+    P2, _, _ = OK.gmres_poly(op, b, 9)
+    P3, _, _ = OK.gmres_poly(op, b, 4)
+    Pin, _, _ = OK.gmres_poly(op, b, 4)
+    Dref, _ = ODF.pp_arnoldi_eigs(op, Pin.roots, z4_noise(1, 0x200, 0, op.n), 60, 8)
+    D = ctx.defl_from_arrays(Dref.lam, torch.from_numpy(Dref.Z).cuda(), torch.from_numpy(Dref.U).cuda())
+    g1, g2, g3 = (ctx.poly_from_roots(P.roots) for P in (P1, P2, P3))
+    g0 = ctx.poly_from_roots(P1.roots[:1])
+    gin = ctx.poly_from_roots(P3.roots)
+    gd = ctx.poly_from_roots(P3.roots[:3], inner=gin)
+    ups = [g1, g2, g3, gd, g0]
+    los = [g2, g3, g0, g3, None]
+    streams = [1, 2, 3, 4, 5]
+    N = 64
+    Xs, Ts, mv = ctx.levels_multi(ups, los, D, theta, 3, streams, 7, N, prec=prec)
+    mv_one = 0
+    for t, (u, l) in enumerate(zip(ups, los)):
+        X, T, m = ctx.level(u, l, D if l is not None else None, theta, 3, streams[t], 7, N, prec=prec)
+        assert np.array_equal(Xs[t], X), t
+        assert Ts[t] == T
+        mv_one += m
+    assert mv == mv_one
+    Xr, Tr = OES.level_samples(op, P1, P2, Dref, "g5" if theta else "I", 3, 1, 7, N)
+    assert abs(Ts[0] - Tr) < 1e-10 * max(1, abs(Tr))
+    if prec == FP64:
+        assert rel(Xs[0], Xr) < 1e-10
+    # 20 noises: no 64-wide chunks, every term one at a time (same values)
+    Xs20, _, _ = ctx.levels_multi(ups[:2], los[:2], D, theta, 3, streams[:2], 7, 20, prec=prec)
+    for t in range(2):
+        assert np.array_equal(Xs20[t], ctx.level(ups[t], los[t], D, theta, 3, streams[t], 7, 20, prec=prec)[0])
+    with pytest.raises(mpmc.MpmcError):
+        ctx.levels_multi([None], [g1], D, theta, 3, [1], 0, N, prec=prec)
+    with pytest.raises(mpmc.MpmcError):
+        ctx.levels_multi(ups[:1], los[:1], D, theta, 3, [1], 0, N, prec=mpmc.FP16S)
+
+
 def test_plain_4444_estimate_vs_dense_exact(f44):
     """4^4, kappa 0.115: 32 Z(4) noises, Hutchinson and the subtracted level
     against the dense exact traces of M^-1 and M^-1 - p(M)."""
