@@ -37,6 +37,17 @@ def test_overlapped_setup_is_identical(ctx):
     assert e0.mvps == e1.mvps
 
 
+def test_overlapped_levels_same_samples(ctx):
+    """Polynomial terms on a side stream while the solve term runs: every
+    sample as with all terms on one stream."""
+    e0 = driver.estimate(ctx, plan(overlap_levels=False), torch.cuda.synchronize)
+    e1 = driver.estimate(ctx, plan(overlap_levels=True), torch.cuda.synchronize)
+    assert [L.name for L in e0.levels] == [L.name for L in e1.levels]
+    for L0, L1 in zip(e0.levels, e1.levels):
+        assert np.array_equal(L0.samples, L1.samples) and L0.corr == L1.corr and L0.mvps == L1.mvps
+    assert e0.value == e1.value and e0.mvps == e1.mvps
+
+
 def test_batched_levels_same_estimate(ctx):
     """Polynomial terms in shared launches: the same samples bit for bit, so
     the same estimate."""
