@@ -189,6 +189,74 @@ __global__ __launch_bounds__(256) void k_multiaxpy(VecRef Vb, size_t vstride_b, 
     if (threadIdx.y == 0 && r < N) partial[(long)blockIdx.x * N + r] = make_double2(red[threadIdx.x], 0.0);
 }
 
+// The middle of a CGS2 step in one pass over the basis: w += sign * sum_j
+// h[j*ldh + r] V_j, then partial[j][blk][r] = sum over the block's sites of
+// conj(V_j) w (the second pass's dot products, summed by k_reduce).  Component
+// by component, the nv <= NVMAX basis values stay in registers between the
+// update and the dot, so the basis is read once instead of twice.
+template <int P, int NVMAX>
+__global__ __launch_bounds__(256) void k_multiaxpy_dot(VecRef Vb, size_t vstride_b, int nv, VecRef w, int N, long V,
+                                                       const double2 *__restrict__ h, double sign, int ldh,
+                                                       double2 *__restrict__ partial, int NB) {
+    using T = typename Store<P>::real;
+    __shared__ double2 red[NVMAX][256];
+    const int RT = blockDim.x, CT = blockDim.y;
+    const int r = blockIdx.y * RT + threadIdx.x;
+    cpx<double> d[NVMAX];
+#pragma unroll
+    for (int j = 0; j < NVMAX; ++j) d[j] = mk(0.0, 0.0);
+    if (r < N) {
+        cpx<T> c[NVMAX];
+#pragma unroll
+        for (int j = 0; j < NVMAX; ++j) {
+            const double2 hj = j < nv ? h[(long)j * ldh + r] : make_double2(0.0, 0.0);
+            c[j] = mk((T)(sign * hj.x), (T)(sign * hj.y));
+        }
+        for (long s = (long)blockIdx.x * CT + threadIdx.y; s < V; s += (long)NB * CT) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const long e = (s * 12 + k) * N + r;
+                const auto wv = Store<P>::ld(w.d, nullptr, e, 0);
+                cpx<T> acc = mk((T)wv.re, (T)wv.im);
+                cpx<T> vv[NVMAX];
+#pragma unroll
+                for (int j = 0; j < NVMAX; ++j) {
+                    if (j < nv) {
+                        const auto v = Store<P>::ld((const char *)Vb.d + (size_t)j * vstride_b, nullptr, e, 0);
+                        vv[j] = mk((T)v.re, (T)v.im);
+                    } else {
+                        vv[j] = mk(T(0), T(0));
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < NVMAX; ++j)
+                    if (j < nv) acc = acc + c[j] * vv[j];
+                Store<P>::st(w.d, e, acc);
+                const cpx<double> wd = mk((double)acc.re, (double)acc.im);
+#pragma unroll
+                for (int j = 0; j < NVMAX; ++j)
+                    if (j < nv) d[j] = d[j] + conjmul(mk((double)vv[j].re, (double)vv[j].im), wd);
+            }
+        }
+    }
+    // the block's sums over its site rows (threadIdx.y), in a fixed order;
+    // thread row y writes the partials of vectors j = y, y + CT, ...
+    const int tid = threadIdx.y * RT + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < NVMAX; ++j) red[j][tid] = make_double2(d[j].re, d[j].im);
+    __syncthreads();
+    if (r < N) {
+        for (int j = threadIdx.y; j < nv; j += CT) {
+            double2 a = red[j][threadIdx.x];
+            for (int y = 1; y < CT; ++y) {
+                a.x += red[j][y * RT + threadIdx.x].x;
+                a.y += red[j][y * RT + threadIdx.x].y;
+            }
+            partial[((long)j * NB + blockIdx.x) * N + r] = a;
+        }
+    }
+}
+
 // y = a * x + b * y   (uniform complex coefficients)
 template <int P>
 __global__ void k_axpby(VecRef x, VecRef y, long total, double2 a, double2 b) {
@@ -511,6 +579,31 @@ int blas_multi_axpy_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, v
         k_reduce<<<nrhs, 256, 0, ctx->stream>>>(part, t.NB, nrhs, (double2 *)norm2_dev, 0, 1);
         HIP_OR_RET(ctx, hipGetLastError());
     }
+    return MPMC_OK;
+}
+
+// w += sign * sum_j h[j*ldh + r] V_j, then h2[j*nrhs + r] = V_j^H w (j < nv):
+// one pass over the basis for FP32 storage and nv <= 16 (one basis vector per
+// right-hand side), blas_multi_axpy + blas_multi_dot otherwise (an FP64
+// version would need twice the registers and spills).
+int blas_multi_axpy_dot(mpmc_ctx *ctx, const void *Vb, long vstride, int nv, void *w, int nrhs, int prec,
+                        const double *h_dev, int ldh, double sign, double *h2_dev) {
+    constexpr int NVMAX = 16;
+    if (nv > NVMAX || nrhs < 2 || prec != MPMC_FP32) {
+        RET_IF(blas_multi_axpy(ctx, Vb, vstride, nrhs, nv, w, nrhs, prec, h_dev, ldh, sign, nullptr));
+        return blas_multi_dot(ctx, Vb, vstride, nrhs, nv, w, nrhs, prec, h2_dev, 0, 0);
+    }
+    if (nv <= 0) return MPMC_OK;
+    Tiling t = tiling(ctx, nrhs, 1);
+    double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)nv * t.NB * nrhs * sizeof(double2));
+    if (!part) return MPMC_ENOMEM;
+    dim3 blk(t.RT, t.CT), grd(t.NB, t.ntile, 1);
+    k_multiaxpy_dot<MPMC_FP32, NVMAX><<<grd, blk, 0, ctx->stream>>>(
+        vref(ctx, Vb, nrhs, prec), (size_t)vstride * 8, nv, vref(ctx, w, nrhs, prec), nrhs, ctx->V,
+        (const double2 *)h_dev, sign, ldh, part, t.NB);
+    HIP_OR_RET(ctx, hipGetLastError());
+    k_reduce<<<nv * nrhs, 256, 0, ctx->stream>>>(part, t.NB, nrhs, (double2 *)h2_dev, 0, 0);
+    HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
 

@@ -302,6 +302,8 @@ int blas_dot(mpmc_ctx *ctx, const void *x, const void *y, int nrhs, int prec, in
 int blas_norm2(mpmc_ctx *ctx, const void *x, int nrhs, int prec, double *out_dev);
 int blas_multi_axpy(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv, void *w, int nrhs, int prec,
                     const double *h_dev, int ldh, double sign, double *norm2_dev);
+int blas_multi_axpy_dot(mpmc_ctx *ctx, const void *Vb, long vstride, int nv, void *w, int nrhs, int prec,
+                        const double *h_dev, int ldh, double sign, double *h2_dev);
 // FP16S Krylov bases (nrhs-wide FP16S batches spaced vstride_b bytes apart)
 // against FP32 working vectors
 int blas_multi_dot_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, const void *w, int nrhs,

@@ -189,8 +189,7 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
                     RET_IF(blas_multi_axpy_h(ctx, V, vbb, j + 1, w, N, h2, N, -1.0, nrm));
                 } else {
                     RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, pw, Hcol, 0, 0));
-                    RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, pw, Hcol, N, -1.0, nullptr));
-                    RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, pw, h2, 0, 0));
+                    RET_IF(blas_multi_axpy_dot(ctx, V, vstride, j + 1, w, N, pw, Hcol, N, -1.0, h2));
                     RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, pw, h2, N, -1.0, nrm));
                 }
             } else if (half) {
@@ -203,8 +202,7 @@ int solve_internal(mpmc_ctx *ctx, const void *b, void *x, int N, const mpmc_defl
                 RET_IF(wilson_launch_full(ctx, opin, nullptr, w, nullptr, N, inner_prec, make_double2(0, 0),
                                           make_double2(1, 0), make_double2(0, 0), 0, 0));
                 RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, 0, 0));
-                RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, inner_prec, Hcol, N, -1.0, nullptr));
-                RET_IF(blas_multi_dot(ctx, V, vstride, N, j + 1, w, N, inner_prec, h2, 0, 0));
+                RET_IF(blas_multi_axpy_dot(ctx, V, vstride, j + 1, w, N, inner_prec, Hcol, N, -1.0, h2));
                 RET_IF(blas_multi_axpy(ctx, V, vstride, N, j + 1, w, N, inner_prec, h2, N, -1.0, nrm));
             }
             k_finalize_batch<<<grid_for(N, 64), 64, 0, ctx->stream>>>((double2 *)Hcol, (const double2 *)h2, j, N,
