@@ -45,7 +45,7 @@ class Plan:
     seed: int = 1
     nev: int = 20                        # eigenpairs kept for deflation (0: none)
     defl_candidates: int = 40            # Ritz pairs tested for acceptance
-    defl_m: int = 112                    # PP-Arnoldi steps (the Hessenberg QR stays in LDS up to 137)
+    defl_m: int = 112                    # PP-Arnoldi steps (Aberth sweeps up to 256; the QR fallback in LDS up to 137)
     defl_pin_degree: int = 8             # degree of p_in for PP-Arnoldi
     accept_tol: float = 1e-3
     real_tol: float = 2e-4
