@@ -167,14 +167,19 @@ __device__ __forceinline__ cpx<typename Store<P>::real> ldbuf(__amdgpu_buffer_rs
     }
 }
 
+// A store of more than 64 bits of data has a hazard: a VALU write to its data
+// registers in the next cycle can replace the data before the store reads it.
+// The compiler guards global stores but not buffer stores whose scalar offset
+// is a register (it assumes the hazard away), and such writes follow these
+// stores in the generated code; a complex double is therefore stored as two
+// 64-bit halves.
 template <int P>
 __device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t rs, int k, int N, uint32_t r,
                                       cpx<typename Store<P>::real> v) {
     if constexpr (P == MPMC_FP64) {
-        f64x2 d;
-        d.x = v.re;
-        d.y = v.im;
-        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4v, d), rs, (int)(r * 16u), k * N * 16, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.re), rs, (int)(r * 16u), k * N * 16, 0);
+        __builtin_amdgcn_sched_barrier(0);   // keeps the halves from being merged back into one store
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.im), rs, (int)(r * 16u + 8u), k * N * 16, 0);
     } else {
         f32x2 d;
         d.x = v.re;
@@ -327,11 +332,10 @@ struct VecAcc {
         }
     }
     __device__ __forceinline__ void st(int k, cpx<typename Store<P>::real> v) const {
-        if constexpr (P == MPMC_FP64) {
-            f64x2 d;
-            d.x = v.re;
-            d.y = v.im;
-            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4v, d), rs, (int)vo, k * N * 16, 0);
+        if constexpr (P == MPMC_FP64) {   // two 64-bit halves: see stbuf
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.re), rs, (int)vo, k * N * 16, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v.im), rs, (int)(vo + 8u), k * N * 16, 0);
         } else {
             f32x2 d;
             d.x = v.re;
