@@ -166,7 +166,11 @@ def main():
         del src, dst
     for _ in range(a.warmup):
         driver.estimate(ctx, plan, sync)
-    mpmc.mpmc_timing_enable(ctx.handle, 1)
+    # the side contexts (setup work on other streams) exist after the warm-up;
+    # their Wilson launches count in value as well
+    sides = [c for c, _ in ctx._side.values()]
+    for c in [ctx] + sides:
+        mpmc.mpmc_timing_enable(c.handle, 1)
     sync()
     t0 = time.perf_counter()
     ests = [driver.estimate(ctx, plan, sync) for _ in range(a.steps)]
@@ -176,9 +180,11 @@ def main():
     n64, ms64, by64 = mpmc.mpmc_timing_read(ctx.handle, mpmc.FP64)
     nd, msd, byd = mpmc.mpmc_timing_read(ctx.handle, mpmc.FP32 | mpmc.TIMING_FUSED)   # dominant kernel
     na, msa, bya = mpmc.mpmc_timing_read(ctx.handle, mpmc.FP32 | mpmc.TIMING_PLAIN)
-    mpmc.mpmc_timing_enable(ctx.handle, 0)
+    side_bytes = sum(mpmc.mpmc_timing_read(c.handle, p)[2] for c in sides for p in (mpmc.FP32, mpmc.FP64))
+    for c in [ctx] + sides:
+        mpmc.mpmc_timing_enable(c.handle, 0)
     step_s = (t1 - t0) / a.steps
-    bytes_step = (by32 + by64) / a.steps
+    bytes_step = (by32 + by64 + side_bytes) / a.steps
     est = ests[-1]
 
     out = {
