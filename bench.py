@@ -135,7 +135,7 @@ def cpu_baseline(dims, kappa, links, seconds):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the method's noise vectors "
+        print("bench.py runs on one GPU only: there is no multi-GPU path (the method's noise vectors "
               "shard across GPUs with one final all-reduce, which is not implemented); use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)

@@ -9,7 +9,7 @@ Tolerances (derived from the arithmetic):
   terms per component).
 * FP16S operator output: <= 1.5e-3 (half storage, 2^-11 relative to the
   per-(site, rhs) maximum).
-* FP64 polynomials / solves / level samples: 1e-10 relative (spec bound).
+* FP64 polynomials / solves / level samples: 1e-10 relative (the FP64-mode parity bound).
 """
 import numpy as np
 import pytest
