@@ -701,7 +701,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occ<P, true
 // the eight 12-component contributions are summed with DPP (quad xor 1 and 2,
 // then row_shr 4, which leaves the site's total in lane 4 of its group), and
 // lane 4 loads the epilogue operands before the hop, so they arrive while
-// the hop computes.
+// the hop computes.  Workgroups are one wavefront: an 8^4 vector is 32,768
+// threads, which 256-thread workgroups would put on half the compute units.
 template <typename T>
 __device__ __forceinline__ cpx<T> mulc_rt(cpx<T> z, int code) {
     T a = z.re, b = z.im;
@@ -1093,7 +1094,7 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs) {
     WIn<P> in = make_in<P>(ctx, b, nrhs);
     if constexpr (P != MPMC_FP16S) {
         if (nrhs == 1) {
-            k_wilson1<P><<<grid_for(ctx->V * 8, 256), 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, o, ctx->V);
+            k_wilson1<P><<<grid_for(ctx->V * 8, 64), 64, 0, ctx->stream>>>(in.b, in.nbr, in.links, o, ctx->V);
             return;
         }
     }
