@@ -103,27 +103,35 @@ __global__ __launch_bounds__(256) void k_multidot(VecRef Vb, size_t vstride_b, s
     }
 }
 
-// out[j*N + r] (+)= sum_b partial[j][b][r]; one workgroup per (j, r).
-__global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ partial, int NB, int N,
-                                                double2 *__restrict__ out, int accumulate, int only_real) {
-    __shared__ double2 red[256];
-    const int jr = blockIdx.x;
-    const int j = jr / N, r = jr % N;
+// sum_b partial[j][b][r] by a 256-thread workgroup in a fixed order (thread t
+// adds b = t, t + 256, ..., then a halving tree); the result is in red[0]
+// for every thread after the return.
+__device__ __forceinline__ void block_sum_partials(const double2 *__restrict__ partial, int NB, int N, int j, int r,
+                                                   double2 *red) {
     double2 a = make_double2(0, 0);
-    for (int b = threadIdx.x; b < NB; b += blockDim.x) {
+    for (int b = threadIdx.x; b < NB; b += 256) {
         double2 v = partial[((long)j * NB + b) * N + r];
         a.x += v.x;
         a.y += v.y;
     }
     red[threadIdx.x] = a;
     __syncthreads();
-    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    for (int h = 128; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
             red[threadIdx.x].x += red[threadIdx.x + h].x;
             red[threadIdx.x].y += red[threadIdx.x + h].y;
         }
         __syncthreads();
     }
+}
+
+// out[j*N + r] (+)= sum_b partial[j][b][r]; one workgroup per (j, r).
+__global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ partial, int NB, int N,
+                                                double2 *__restrict__ out, int accumulate, int only_real) {
+    __shared__ double2 red[256];
+    const int jr = blockIdx.x;
+    const int j = jr / N, r = jr % N;
+    block_sum_partials(partial, NB, N, j, r, red);
     if (threadIdx.x == 0) {
         double2 v = red[0];
         if (only_real) v.y = 0;
@@ -440,6 +448,43 @@ __global__ __launch_bounds__(256) void k_multiaxpy1(VecRef Vb, long vstride, int
     if (threadIdx.x == 0) partial[blockIdx.x] = make_double2(red[0], 0.0);
 }
 
+// End of one single-vector FP64 Arnoldi step, one workgroup: ||w||^2 from the
+// partials of the second update (the same sum as k_reduce), then on the first
+// wavefront H(:, j) += h2, h_{j+1,j} = ||w||, the breakdown test against the
+// running Frobenius norm and the coefficient 1/h of the new basis vector (0
+// after a breakdown, which keeps later vectors zero).
+__global__ __launch_bounds__(256) void k_arnoldi_finish(const double2 *__restrict__ partial, int NB, double2 *Hcol,
+                                                        const double2 *h2, int j, double *state, double2 *scale) {
+    // state[0] = running ||H||_F^2, state[1] = d_eff (or -1 while none)
+    __shared__ double2 red[256];
+    block_sum_partials(partial, NB, 1, 0, 0, red);
+    const double wn2 = red[0].x;
+    if (threadIdx.x >= 64) return;
+    double f = 0.0;
+    for (int i = threadIdx.x; i <= j; i += 64) {
+        double2 v = Hcol[i];
+        v.x += h2[i].x;
+        v.y += h2[i].y;
+        Hcol[i] = v;
+        f += v.x * v.x + v.y * v.y;
+    }
+    for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o);
+    if (threadIdx.x != 0) return;
+    double fro = state[0] + f;
+    const double hn = sqrt(fmax(wn2, 0.0));
+    fro += hn * hn;
+    state[0] = fro;
+    const bool broken = state[1] >= 0;
+    if (broken || hn <= 1e-14 * sqrt(fro) || !(hn == hn)) {
+        Hcol[j + 1] = make_double2(0.0, 0.0);
+        if (!broken) state[1] = j + 1;
+        scale[0] = make_double2(0.0, 0.0);
+    } else {
+        Hcol[j + 1] = make_double2(hn, 0.0);
+        scale[0] = make_double2(1.0 / hn, 0.0);
+    }
+}
+
 int nb_single(const mpmc_ctx *ctx, long n, int groups) {
     long nb = (long)ctx->num_cu * 8 / (groups > 0 ? groups : 1);
     const long maxnb = (n + 255) / 256;
@@ -516,6 +561,21 @@ int blas_dot(mpmc_ctx *ctx, const void *x, const void *y, int nrhs, int prec, in
 
 int blas_norm2(mpmc_ctx *ctx, const void *x, int nrhs, int prec, double *out_dev) {
     return blas_multi_dot(ctx, x, 0, nrhs, 1, x, nrhs, prec, out_dev, 0, 0);
+}
+
+int blas_arnoldi_update(mpmc_ctx *ctx, const void *V, long vstride, int nv, void *w, const double *h2, double *Hcol,
+                        int j, double *state, double *scale) {
+    const int NB = nb_single(ctx, ctx->n, 1);
+    double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)NB * sizeof(double2));
+    if (!part) return MPMC_ENOMEM;
+    k_multiaxpy1<MPMC_FP64><<<NB, 256, 0, ctx->stream>>>(vref(ctx, V, 1, MPMC_FP64), vstride, nv,
+                                                         vref(ctx, w, 1, MPMC_FP64), ctx->n, (const double2 *)h2, 1,
+                                                         -1.0, part, NB);
+    HIP_OR_RET(ctx, hipGetLastError());
+    k_arnoldi_finish<<<1, 256, 0, ctx->stream>>>(part, NB, (double2 *)Hcol, (const double2 *)h2, j, state,
+                                                 (double2 *)scale);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
 }
 
 // w += sign * sum_j h[j*ldh + r] V_j ; if norm2_dev: norm2_dev[r] = ||w_r||^2 (after update)

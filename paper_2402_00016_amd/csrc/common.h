@@ -304,6 +304,12 @@ int blas_multi_axpy(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv,
                     const double *h_dev, int ldh, double sign, double *norm2_dev);
 int blas_multi_axpy_dot(mpmc_ctx *ctx, const void *Vb, long vstride, int nv, void *w, int nrhs, int prec,
                         const double *h_dev, int ldh, double sign, double *h2_dev);
+// Second Gram-Schmidt pass of one single-vector FP64 Arnoldi step: w -= V h2,
+// then H(:, j) += h2, h_{j+1,j} = ||w|| with the breakdown test against the
+// running Frobenius norm in state[0] (state[1] = d_eff or -1), and scale[0] =
+// 1 / h_{j+1,j} (0 after a breakdown).  Two launches.
+int blas_arnoldi_update(mpmc_ctx *ctx, const void *V, long vstride, int nv, void *w, const double *h2, double *Hcol,
+                        int j, double *state, double *scale);
 // FP16S Krylov bases (nrhs-wide FP16S batches spaced vstride_b bytes apart)
 // against FP32 working vectors
 int blas_multi_dot_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, const void *w, int nrhs,
@@ -318,9 +324,11 @@ int blas_scale_acc(mpmc_ctx *ctx, const double *t, int N, double2 c, double sign
 
 // wilson.hip: out (FP32) = M b for an FP16S operand b
 int wilson_apply_h2f(mpmc_ctx *ctx, const void *b, void *out, int nrhs);
-// wilson.hip: out = alpha a + beta Theta op(b); y += gamma out (y may be null)
+// wilson.hip: out = alpha a + beta Theta op(b); y += gamma out (y may be null);
+// yinit_on (single vectors, a == b): y = yinit b + gamma out, y not read
 int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, void *y, int nrhs, int prec,
-                       double2 alpha, double2 beta, double2 gamma, int dagger, int theta);
+                       double2 alpha, double2 beta, double2 gamma, int dagger, int theta,
+                       double2 yinit = double2{0.0, 0.0}, int yinit_on = 0);
 // fused level step (see wilson.hip): w' = w - c M w; partial += cnext eta^H Theta w'
 size_t wilson_dot_partial_count(const mpmc_ctx *ctx, int nrhs);
 // codes of noise vectors first .. first+nrhs-1 into columns off .. of rows of

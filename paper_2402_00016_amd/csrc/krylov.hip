@@ -17,39 +17,6 @@
 
 // ------------------------------------------------------------ Arnoldi --
 
-// After the second Gram-Schmidt pass: H(:, j) += h2, h_{j+1,j} = ||w||,
-// breakdown test against the running Frobenius norm, coefficient 1/h for the
-// new basis vector (0 after a breakdown, which keeps later vectors zero).
-// One wavefront: the column update is spread over the lanes and the squared
-// norm summed with a fixed butterfly.
-__global__ __launch_bounds__(64) void k_arnoldi_finalize(double2 *Hcol, const double2 *h2, int j,
-                                                         const double2 *nrm2, double *state, double2 *scale) {
-    // state[0] = running ||H||_F^2, state[1] = d_eff (or -1 while none)
-    double f = 0.0;
-    for (int i = threadIdx.x; i <= j; i += 64) {
-        double2 v = Hcol[i];
-        v.x += h2[i].x;
-        v.y += h2[i].y;
-        Hcol[i] = v;
-        f += v.x * v.x + v.y * v.y;
-    }
-    for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o);
-    if (threadIdx.x != 0) return;
-    double fro = state[0] + f;
-    const double hn = sqrt(fmax(nrm2[0].x, 0.0));
-    fro += hn * hn;
-    state[0] = fro;
-    const bool broken = state[1] >= 0;
-    if (broken || hn <= 1e-14 * sqrt(fro) || !(hn == hn)) {
-        Hcol[j + 1] = make_double2(0.0, 0.0);
-        if (!broken) state[1] = j + 1;
-        scale[0] = make_double2(0.0, 0.0);
-    } else {
-        Hcol[j + 1] = make_double2(hn, 0.0);
-        scale[0] = make_double2(1.0 / hn, 0.0);
-    }
-}
-
 __global__ void k_arnoldi_init(double *state, double2 *scale, const double2 *nrm2) {
     state[0] = 0.0;
     state[1] = -1.0;
@@ -102,11 +69,9 @@ int arnoldi_run(mpmc_ctx *ctx, const OpDesc &op, double *V, double *H, int d, do
         // CGS pass 1: H(:, j) = V^H w ; w -= V H(:, j)
         RET_IF(blas_multi_dot(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, Hcol, 0, 0));
         RET_IF(blas_multi_axpy(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, Hcol, 1, -1.0, nullptr));
-        // CGS pass 2 with the norm fused into the update
+        // CGS pass 2; the norm's reduction also finishes the column (breakdown test, 1/h)
         RET_IF(blas_multi_dot(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, (double *)h2, 0, 0));
-        RET_IF(blas_multi_axpy(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, (double *)h2, 1, -1.0, (double *)sc));
-        k_arnoldi_finalize<<<1, 64, 0, ctx->stream>>>((double2 *)Hcol, h2, j, sc, state, sc + 1);
-        HIP_OR_RET(ctx, hipGetLastError());
+        RET_IF(blas_arnoldi_update(ctx, V, n, j + 1, w, (double *)h2, Hcol, j, state, (double *)(sc + 1)));
         RET_IF(blas_scale_rhs(ctx, w, vj1, 1, MPMC_FP64, (double *)(sc + 1), 0));
     }
     return MPMC_OK;
@@ -280,11 +245,9 @@ static int apply_single(mpmc_ctx *ctx, const std::vector<double> &roots, int d, 
         std::complex<double> v = 1.0 / th(k);
         return make_double2(v.real(), v.imag());
     };
-    // y = x / theta_1
-    {
-        double2 c = inv(0);
-        RET_IF(blas_axpby(ctx, x, y, nrhs, prec, c, make_double2(0, 0)));
-    }
+    // y = x / theta_1 (single vectors: inside the first step's launch)
+    const bool fold = nrhs == 1 && d > 1;
+    if (!fold) RET_IF(blas_axpby(ctx, x, y, nrhs, prec, inv(0), make_double2(0, 0)));
     if (d == 1) return MPMC_OK;
     void *wa = S.get(vec_bytes(ctx, nrhs, prec));
     void *wb = S.get(vec_bytes(ctx, nrhs, prec));
@@ -294,7 +257,7 @@ static int apply_single(mpmc_ctx *ctx, const std::vector<double> &roots, int d, 
         void *nxt = (cur == wa) ? wb : wa;
         double2 c = inv(k);
         RET_IF(wilson_launch_full(ctx, cur, cur, nxt, y, nrhs, prec, make_double2(1, 0), make_double2(-c.x, -c.y),
-                                  inv(k + 1), 0, 0));
+                                  inv(k + 1), 0, 0, inv(0), fold && k == 0));
         cur = nxt;
     }
     return MPMC_OK;

@@ -741,9 +741,13 @@ __device__ __forceinline__ T group8_sum1(T v) {
 template <typename T>
 __device__ __forceinline__ cpx<T> group8_sum(cpx<T> v) { return mk(group8_sum1(v.re), group8_sum1(v.im)); }
 
+// yinit_on: y = yinit * b + gamma * out instead of y += gamma * out (the
+// first step of a polynomial, whose accumulator starts at b / theta_1; needs
+// a == b), y is then not read.
 template <int P>
 __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, const int *__restrict__ nbr,
-                                                 const typename LinkT<P>::type *__restrict__ links, WOut o, long V) {
+                                                 const typename LinkT<P>::type *__restrict__ links, WOut o, long V,
+                                                 double2 yinit, int yinit_on) {
     using T = typename Store<P>::real;
     const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     const long s = t >> 3;
@@ -760,7 +764,7 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
     for (int k = 0; k < 12; ++k) {
         bt[k] = epi ? mk((T)sp[k].x, (T)sp[k].y) : mk(T(0), T(0));
         av[k] = epi && has_a ? mk((T)ap[k].x, (T)ap[k].y) : mk(T(0), T(0));
-        yv[k] = epi && o.y ? mk((T)yp[k].x, (T)yp[k].y) : mk(T(0), T(0));
+        yv[k] = epi && o.y && !yinit_on ? mk((T)yp[k].x, (T)yp[k].y) : mk(T(0), T(0));
     }
     cpx<T> c[12];
 #pragma unroll
@@ -820,6 +824,7 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
     const cpx<T> al = mk((T)o.alpha.x, (T)o.alpha.y);
     const cpx<T> be = mk((T)o.beta.x, (T)o.beta.y);
     const cpx<T> ga = mk((T)o.gamma.x, (T)o.gamma.y);
+    const cpx<T> yi = mk((T)yinit.x, (T)yinit.y);
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
         cpx<T> mb = bt[k] - kap * c[k];
@@ -829,7 +834,7 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
         op[k].x = v.re;
         op[k].y = v.im;
         if (o.y) {
-            const cpx<T> yn = yv[k] + ga * v;
+            const cpx<T> yn = (yinit_on ? yi * av[k] : yv[k]) + ga * v;
             yp[k].x = yn.re;
             yp[k].y = yn.im;
         }
@@ -1088,13 +1093,14 @@ static void launch_uniform(mpmc_ctx *ctx, const WIn<P> &in, const WOut &o, int n
 }
 
 template <int P>
-static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs) {
+static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs, double2 yinit, int yinit_on) {
     const long work = ctx->V * nrhs;
     const unsigned grid = grid_for(work, 256);
     WIn<P> in = make_in<P>(ctx, b, nrhs);
     if constexpr (P != MPMC_FP16S) {
         if (nrhs == 1) {
-            k_wilson1<P><<<grid_for(ctx->V * 8, 64), 64, 0, ctx->stream>>>(in.b, in.nbr, in.links, o, ctx->V);
+            k_wilson1<P><<<grid_for(ctx->V * 8, 64), 64, 0, ctx->stream>>>(in.b, in.nbr, in.links, o, ctx->V,
+                                                                            yinit, yinit_on);
             return;
         }
     }
@@ -1117,8 +1123,11 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs) {
 }
 
 int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, void *y, int nrhs, int prec,
-                       double2 alpha, double2 beta, double2 gamma, int dagger, int theta) {
+                       double2 alpha, double2 beta, double2 gamma, int dagger, int theta, double2 yinit,
+                       int yinit_on) {
     if (prec == MPMC_FP16S && y) return set_err(ctx, MPMC_EINVAL, "FP16S output cannot accumulate");
+    if (yinit_on && (nrhs != 1 || !y || a != b))
+        return set_err(ctx, MPMC_EINVAL, "accumulator start from the operand: single vectors with a == b only");
     WOut o;
     VecRef vo = vref(ctx, out, nrhs, prec);
     o.out = vo.d;
@@ -1136,17 +1145,18 @@ int wilson_launch_full(mpmc_ctx *ctx, const void *b, const void *a, void *out, v
     o.theta = theta;
     o.out_fp32 = 0;
     const int ev = nrhs > 1 ? timing_begin(ctx) : -1;   // single vectors: counted, no events
-    if (prec == MPMC_FP64) launch_w<MPMC_FP64>(ctx, b, o, nrhs);
-    else if (prec == MPMC_FP32) launch_w<MPMC_FP32>(ctx, b, o, nrhs);
-    else launch_w<MPMC_FP16S>(ctx, b, o, nrhs);
+    if (prec == MPMC_FP64) launch_w<MPMC_FP64>(ctx, b, o, nrhs, yinit, yinit_on);
+    else if (prec == MPMC_FP32) launch_w<MPMC_FP32>(ctx, b, o, nrhs, yinit, yinit_on);
+    else launch_w<MPMC_FP16S>(ctx, b, o, nrhs, yinit, yinit_on);
     HIP_OR_RET(ctx, hipGetLastError());
     if (ctx->timing) {
         // algorithmic bytes: operand read once, a read once if distinct,
-        // out written once, y read and written, links once per site
+        // out written once, y read (unless it starts from b) and written,
+        // links once per site
         const double sb = spinor_bytes(prec);
         double per = 2 * sb;
         if (a && a != b) per += sb;
-        if (y) per += 2 * sb;
+        if (y) per += yinit_on ? sb : 2 * sb;
         const double bytes = (double)ctx->V * ((double)nrhs * per + link_bytes(prec));
         if (ev >= 0) timing_end(ctx, ev, prec | MPMC_TIMING_PLAIN, bytes);
         else timing_count(ctx, prec | MPMC_TIMING_SINGLE, bytes);
@@ -1171,7 +1181,7 @@ int wilson_apply_h2f(mpmc_ctx *ctx, const void *b, void *out, int nrhs) {
     o.theta = 0;
     o.out_fp32 = 1;
     const int ev = timing_begin(ctx);
-    launch_w<MPMC_FP16S>(ctx, b, o, nrhs);
+    launch_w<MPMC_FP16S>(ctx, b, o, nrhs, make_double2(0, 0), 0);
     HIP_OR_RET(ctx, hipGetLastError());
     if (ev >= 0)
         timing_end(ctx, ev, MPMC_FP16S | MPMC_TIMING_PLAIN,
