@@ -202,12 +202,14 @@ def test_gmres_poly_breakdown_kappa0():
     assert np.allclose(P.roots, [1.0])
 
 
+@pytest.mark.parametrize("N", [1, 5])
 @pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (FP32, 2e-5)])
-def test_apply_poly_parity(f44, prec, tol):
+def test_apply_poly_parity(f44, prec, tol, N):
+    """N = 1 is the single-vector kernel, whose first step also starts the
+    accumulator at x / theta_1."""
     dims, kappa, U, op, ctx = f44
     ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 16)
     P = ctx.poly_from_roots(ref.roots)
-    N = 5
     eta = ctx.noise(4, 1, 0, N, prec)
     got = host(ctx.unpack(ctx.apply_poly(P, eta, N, prec), N, prec))
     E = z4_noise_batch(4, 1, 0, N, op.n)
@@ -445,6 +447,25 @@ def test_apply_poly_fp32_ignores_garbage_output(f44):
     assert np.all(np.isfinite(got))
     want = np.stack([OP.apply_p(op, ref.roots, e) for e in z4_noise_batch(4, 1, 0, 2, op.n)])
     assert rel(got[:2], want) < 2e-5
+
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-12), (FP32, 2e-5)])
+def test_apply_poly_single_vector_ignores_garbage_output(f44, prec, tol):
+    """Regression: a single vector's accumulator starts inside the first Wilson
+    launch, which never reads the output's old contents (here NaN); a degree-1
+    polynomial (no Wilson launch) still gives x / theta_1."""
+    dims, kappa, U, op, ctx = f44
+    ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 9)
+    x = ctx.noise(6, 3, 0, 1, prec)
+    xh = z4_noise(6, 3, 0, op.n)
+    for roots in (ref.roots, np.array([2.0 + 0.5j])):
+        P = ctx.poly_from_roots(roots)
+        y = ctx.vector(1, prec)
+        y.view(torch.float64 if prec == FP64 else torch.float32).fill_(float("nan"))
+        ctx.apply_poly(P, x, 1, prec, out=y)
+        got = host(ctx.unpack(y, 1, prec))[0]
+        assert np.all(np.isfinite(got))
+        assert rel(got, OP.apply_p(op, roots, xh)) < tol
 
 
 # ---------------------------------------------------------------- probing --
