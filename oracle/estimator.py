@@ -12,6 +12,13 @@
                               sum_i c_i (eta^H Theta z_i)(u_i^H eta),
                               c_i = p_l(lambda_i) - p_{l+1}(lambda_i), and add
                               back T_l = sum_i c_i u_i^H Theta z_i.
+* Deflated solve level:       when p_1 is the deflated double polynomial it
+                              does not approximate 1/lambda on the deflated
+                              eigenvalues, so the first level M^-1 - p_1 is
+                              deflated the same way with c_i = 1/lambda_i -
+                              p_1(lambda_i) (Sec. 7's level formula with M^-1
+                              in place of the upper polynomial; exact for any
+                              eigen-triples, like every deflated level).
 
 Reading of the error bookkeeping (Sec. 8 only gives the total tolerance):
 samples are complex; a level's variance is s^2 = sum |X - mean|^2 / (N-1);
@@ -41,11 +48,12 @@ def quad(eta, theta_spin, y):
 
 
 def level_samples(op, upper, lower, D, theta, seed, stream, first, N,
-                  solve_tol=1e-10, solve_m=50, eta=None, X_solved=None):
+                  solve_tol=1e-10, solve_m=50, eta=None, X_solved=None, deflate_solve=False):
     """Samples of one level and its exact correction T.
 
     upper: GmresPoly or None (None = M^-1 via a solve); lower: GmresPoly or
-    None (None = 0).  Deflation is applied only when both are polynomials.
+    None (None = 0).  Deflation is applied when both are polynomials, and on
+    the solve level (upper None, lower a polynomial) when deflate_solve.
     """
     S = theta_matrix(theta)
     if eta is None:
@@ -61,6 +69,10 @@ def level_samples(op, upper, lower, D, theta, seed, stream, first, N,
     T = 0j
     if upper is not None and lower is not None and D is not None and D.k:
         c = eval_poly(upper, D.lam) - eval_poly(lower, D.lam)
+        X = X - deflated_term(D, c, eta, S)
+        T = exact_correction(D, c, S)
+    elif deflate_solve and upper is None and lower is not None and D is not None and D.k:
+        c = 1.0 / D.lam - eval_poly(lower, D.lam)
         X = X - deflated_term(D, c, eta, S)
         T = exact_correction(D, c, S)
     return X, T

@@ -8,6 +8,10 @@ not define, harmonic Ritz values and Leja ordering; readings used here:
 * Arnoldi with classical Gram-Schmidt applied twice (CGS2), started from the
   normalised vector b.  Breakdown (h_{j+1,j} <= 1e-14 ||H||_F) truncates the
   cycle to d_eff = j+1 steps: the Krylov space is then invariant.
+* Deflated cycle (Sec. 7 names a deflated double polynomial, its mechanism is
+  left to a reference): with a projector Q = I - Z U^H the start vector is Qb
+  and every new vector is Q applied to the operator's output, i.e. Arnoldi on
+  Q op from Qb.  The polynomial then fits the spectrum that deflation leaves.
 * Harmonic Ritz values: eigenvalues of H_d + |h_{d+1,d}|^2 H_d^{-H} e_d e_d^T,
   which are the roots of the GMRES residual polynomial.
 * Leja order: first the value of largest modulus, then repeatedly the value
@@ -23,13 +27,17 @@ the Leja choice rule and permutation property.
 import numpy as np
 
 
-def arnoldi(op, b, d, breakdown_rtol=1e-14):
-    """d steps of Arnoldi (CGS2) on op from b.
+def arnoldi(op, b, d, breakdown_rtol=1e-14, proj=None):
+    """d steps of Arnoldi (CGS2) on op from b; with proj (a callable Q), on
+    Q op from Q b.
 
     Returns (V, H, beta, d_eff): V is (d_eff+1, n) with orthonormal rows (the
-    last row is zero on breakdown), H is (d_eff+1, d_eff), beta = ||b||.
+    last row is zero on breakdown), H is (d_eff+1, d_eff), beta = ||b|| (of
+    Q b when projected).
     """
     b = np.asarray(b, dtype=np.complex128)
+    if proj is not None:
+        b = proj(b)
     n = b.size
     V = np.zeros((d + 1, n), dtype=np.complex128)
     H = np.zeros((d + 1, d), dtype=np.complex128)
@@ -38,6 +46,8 @@ def arnoldi(op, b, d, breakdown_rtol=1e-14):
     d_eff = d
     for j in range(d):
         w = op(V[j])
+        if proj is not None:
+            w = proj(w)
         Vj = V[: j + 1]
         h = Vj.conj() @ w
         w = w - Vj.T @ h
@@ -146,9 +156,11 @@ class GmresPoly:
         return self.inner.d * self.d - 1
 
 
-def gmres_poly(op, b, d):
-    """One GMRES(d) cycle on op from b -> (GmresPoly, d_eff, relative residual)."""
-    V, H, beta, d_eff = arnoldi(op, b, d)
+def gmres_poly(op, b, d, proj=None):
+    """One GMRES(d) cycle on op from b -> (GmresPoly, d_eff, relative residual).
+    With proj the cycle is the deflated one (on Q op from Q b; the residual is
+    relative to ||Q b||)."""
+    V, H, beta, d_eff = arnoldi(op, b, d, proj=proj)
     _, res = gmres_residual(H, beta)
     roots = leja_order(harmonic_ritz(H))
     return GmresPoly(roots), d_eff, res / beta

@@ -16,10 +16,25 @@ Sec. 5: the double polynomial.  p_in comes from GMRES on M, p_out from GMRES
 on phi_in(M) = M p_in(M); p_double(M) = p_in(M) p_out(phi_in(M)), of degree
 (d_in)(d_out) - 1 when p_in, p_out come from GMRES(d_in), GMRES(d_out).
 
+Deflated double polynomial (Sec. 7 and the conclusions name it; the
+mechanism is deferred to a reference).  Reading: p_in as above (GMRES on M,
+not deflated); the outer cycle is GMRES on Q phi_in(M) started from Q b,
+Q = I - Z U^H the oblique projector of the deflation set, so every Arnoldi
+vector lies in the range of Q and p_out fits phi_in only on the spectrum that
+deflation leaves.  p_double(M) = p_in(M) p_out(phi_in(M)) is applied as before
+(it is a polynomial of M; the deflated eigen-components are handled by the
+deflation of the Monte Carlo levels).
+
 Pins (tests/test_oracle_krylov.py): pi(M) = 1 - M p(M) on random vectors to
 1e-12 (two different formulas); pi(M) b equals the GMRES residual; scalar
 p(lambda) equals the vector action on free-field plane waves; the double
-polynomial's outer residual identity and its matvec count.
+polynomial's outer residual identity and its matvec count.  Deflated double
+polynomial: pi_out(Q phi_in) Q b equals the least-squares residual on an
+explicit monomial basis of the projected Krylov space, and with exact
+eigenvectors also pi_out(phi_in) Q b; every Arnoldi vector is annihilated by
+U^H; with exact eigenvectors deflated, no harmonic Ritz value of the outer
+cycle comes near phi_in(lambda_i) of a deflated eigenvalue, which the
+undeflated cycle does resolve.
 """
 import numpy as np
 
@@ -77,10 +92,25 @@ def eval_poly(P, lam):
     return pin * eval_p(P.roots, np.asarray(lam) * pin)
 
 
-def double_poly(op, b, d_in, d_out):
-    """GMRES(d_in) on M, then GMRES(d_out) on phi_in(M) from the same b."""
+def projector(Z, U):
+    """Q x = x - sum_i z_i (u_i^H x): the oblique projector of a deflation set
+    (Z, U of shape (k, n)), on vectors of shape (n,) or (N, n)."""
+    Z = np.asarray(Z, dtype=np.complex128)
+    U = np.asarray(U, dtype=np.complex128)
+
+    def Q(x):
+        x = np.asarray(x, dtype=np.complex128)
+        c = x @ U.conj().T                  # (..., k): u_i^H x
+        return x - c @ Z
+    return Q
+
+
+def double_poly(op, b, d_in, d_out, proj=None):
+    """GMRES(d_in) on M, then GMRES(d_out) on phi_in(M) from the same b; with
+    proj (the deflation projector Q) the outer cycle is the deflated one, on
+    Q phi_in(M) from Q b."""
     P_in, din_eff, res_in = gmres_poly(op, b, d_in)
-    P_out, dout_eff, res_out = gmres_poly(phi(op, P_in.roots), b, d_out)
+    P_out, dout_eff, res_out = gmres_poly(phi(op, P_in.roots), b, d_out, proj=proj)
     return GmresPoly(P_out.roots, inner=P_in), (din_eff, dout_eff), (res_in, res_out)
 
 

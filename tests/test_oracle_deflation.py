@@ -86,9 +86,42 @@ def test_deflated_level_is_unbiased_exactly(small_field):
             term = DF.deflated_term(Dx, c, eta, S)
             dense_term = np.einsum("rn,nm,rm->r", eta.conj(), A - A_defl, eta)
             assert np.allclose(term, dense_term, atol=1e-9)
+        # the deflated solve level: A = Theta (M^-1 - Pa(M)), c = 1/lambda - Pa(lambda)
+        Minv = np.linalg.inv(M)
+        A0 = G @ (Minv - Ia)
+        c0 = 1.0 / D.lam - poly.eval_poly(Pa, D.lam)
+        A0_defl = A0 - sum(c0[i] * np.outer(G @ D.Z[i], D.U[i].conj()) for i in range(D.k))
+        T0 = DF.exact_correction(D, c0, S)
+        assert abs(np.trace(A0_defl) + T0 - np.trace(A0)) < 1e-9 * max(1, abs(np.trace(A0)))
         # Whether deflation lowers the variance is an empirical property of the
         # field and the polynomials (non-normality can raise it, Sec. 7); only
         # the unbiasedness above is an identity.
+
+
+def test_deflated_solve_level_samples_match_dense(small_field):
+    """Per-sample values of the deflated solve level against the dense
+    quadratic forms eta^H Theta (M^-1 - p(M) - sum_i c_i z_i u_i^H) eta."""
+    dims, kappa, op, M = small_field
+    from oracle import estimator as ES
+    b = z4_noise(2, 0x200, 0, op.n)
+    P, _, _ = krylov.gmres_poly(op, b, 6)
+    P_in, _, _ = krylov.gmres_poly(op, b, 4)
+    D, _ = DF.pp_arnoldi_eigs(op, P_in.roots, b, m=120, nev=12)
+    n = op.n
+    Minv = np.linalg.inv(M)
+    Pm = poly.apply_poly(op, P, np.eye(n)).T
+    c = 1.0 / D.lam - poly.eval_poly(P, D.lam)
+    for theta in ("I", "g5"):
+        S = LT.theta_matrix(theta)
+        G = np.kron(np.eye(LT.volume(dims)), np.kron(S, np.eye(3)))
+        A = G @ (Minv - Pm - sum(c[i] * np.outer(D.Z[i], D.U[i].conj()) for i in range(D.k)))
+        X, T = ES.level_samples(op, None, P, D, theta, 5, 0, 0, 4, solve_tol=1e-12, deflate_solve=True)
+        eta = ES.noise_batch(5, 0, 0, 4, n)
+        ref = np.einsum("rn,nm,rm->r", eta.conj(), A, eta)
+        assert np.allclose(X, ref, rtol=1e-9, atol=1e-9)
+        assert abs(T - DF.exact_correction(D, c, S)) < 1e-12
+        X0, T0 = ES.level_samples(op, None, P, D, theta, 5, 0, 0, 4, solve_tol=1e-12)
+        assert T0 == 0 and not np.allclose(X0, X)
 
 
 def test_gmres_solve_true_residual_and_dense(small_field):

@@ -178,3 +178,77 @@ def test_add_roots_outlier():
     pi_ref = np.prod(1.0 - z[:, None] / th[None, :], axis=1) * (1.0 - z / 50.0) ** want
     assert np.allclose(pi_ext, pi_ref, rtol=1e-10)
     assert np.allclose(1.0 - z * poly.eval_p(ext, z), pi_ext, rtol=1e-8)
+
+
+@pytest.fixture(scope="module")
+def exact_defl():
+    """A 2^3 x 4 field near criticality with its exact smallest eigen-triples:
+    right vectors from dense eig, left vectors from the inverse eigenvector
+    matrix, so U^H Z = I and Q = I - Z U^H is the spectral projector."""
+    dims, kappa = (2, 2, 2, 4), 0.2
+    U = inputs.gauge_links(dims, 0.4, seed=7)
+    op = WilsonOp(dims, kappa, U)
+    M = LT.dense_wilson(dims, kappa, U)
+    lam, R = np.linalg.eig(M)
+    sel = np.argsort(np.abs(lam))[:6]
+    Z = R[:, sel].T
+    Uv = np.linalg.inv(R)[sel, :].conj()
+    assert np.abs(Uv.conj() @ Z.T - np.eye(6)).max() < 1e-10
+    return op, lam[sel], Z, Uv
+
+
+@pytest.mark.parametrize("dout", [4, 7])
+def test_deflated_double_poly_is_projected_gmres(exact_defl, dout):
+    """Sec. 7's deflated double polynomial: the outer cycle is GMRES on
+    Q phi_in from Q b, so pi_out(Q phi_in) Q b is the least-squares residual
+    over an explicit monomial basis of that projected Krylov space; with the
+    spectral projector Q commutes with phi_in and pi_out(phi_in) Q b is the
+    same vector."""
+    op, lam, Z, Uv = exact_defl
+    Q = poly.projector(Z, Uv)
+    b = z4_noise(1, 0x100, 0, op.n)
+    D, (di, do), (ri, ro) = poly.double_poly(op, b, 4, dout, proj=Q)
+    assert do == dout and D.degree == 4 * dout - 1 and poly.matvec_count(D) == D.degree
+    phi = poly.phi(op, D.inner.roots)
+
+    def A(v):
+        return Q(phi(v))
+    c = Q(b)
+    r_ls = _krylov_lstsq_residual(A, c, dout)
+    r_pi = poly.apply_pi(A, D.roots, c)
+    assert np.linalg.norm(r_pi - r_ls) < 1e-10 * np.linalg.norm(c)
+    assert abs(np.linalg.norm(r_pi) / np.linalg.norm(c) - ro) < 1e-10
+    assert np.linalg.norm(poly.apply_pi(phi, D.roots, c) - r_ls) < 1e-10 * np.linalg.norm(c)
+    # the unprojected start vector gives a different (wrong) residual
+    assert np.linalg.norm(poly.apply_pi(A, D.roots, b) - r_ls) > 1e-3 * np.linalg.norm(c)
+
+
+def test_deflated_arnoldi_basis_is_annihilated_by_left_vectors(exact_defl):
+    op, lam, Z, Uv = exact_defl
+    Q = poly.projector(Z, Uv)
+    b = z4_noise(1, 0x100, 0, op.n)
+    Pin, _, _ = krylov.gmres_poly(op, b, 4)
+    V, H, beta, d_eff = krylov.arnoldi(poly.phi(op, Pin.roots), b, 12, proj=Q)
+    assert d_eff == 12
+    assert np.abs(V @ Uv.conj().T).max() < 1e-12
+    assert np.allclose(V.conj() @ V.T, np.eye(13), atol=1e-13)
+    assert abs(beta - np.linalg.norm(Q(b))) < 1e-12 * beta
+
+
+def test_deflated_outer_cycle_avoids_deflated_eigenvalues(exact_defl):
+    """With exact eigenvectors deflated, the outer cycle never sees their
+    eigenvalues: no harmonic Ritz value comes within 30% of phi_in(lambda_i),
+    while the undeflated cycle of the same length resolves every one of them
+    to 1%."""
+    op, lam, Z, Uv = exact_defl
+    Q = poly.projector(Z, Uv)
+    b = z4_noise(1, 0x100, 0, op.n)
+    Pin, _, _ = krylov.gmres_poly(op, b, 4)
+    phl = lam * poly.eval_p(Pin.roots, lam)
+    phi = poly.phi(op, Pin.roots)
+    P0, _, _ = krylov.gmres_poly(phi, b, 48)
+    P1, _, _ = krylov.gmres_poly(phi, b, 48, proj=Q)
+    d0 = np.array([np.min(np.abs(P0.roots - v)) / abs(v) for v in phl])
+    d1 = np.array([np.min(np.abs(P1.roots - v)) / abs(v) for v in phl])
+    assert d0.max() < 1e-2
+    assert d1.min() > 0.3
