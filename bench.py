@@ -1,34 +1,40 @@
 #!/usr/bin/env python3
 """Benchmark of the Multipolynomial Monte Carlo hot path on one MI355X.
 
-Default workload (one "step" = one complete trace estimate): 8^4 lattice
-(n = 49152), SU(3) links U = exp(i 0.5 H) from seed 2, Wilson kappa = 0.120,
-Theta = I; GMRES polynomials of degree 128, 32 and 8; the 20 lowest eigenpairs
-of M asked from PP-Arnoldi (112 steps on M p_in(M), p_in of degree 8; the
-pairs that pass the residual test are deflated); 128 Z(4) noise vectors per Monte Carlo term, each term's
-noise processed as one multi-RHS batch; FP32 Wilson kernels with FP64
-accumulation and FP64 defect correction of the main solves (relative residual
-1e-8).  The step includes building the polynomials and the deflation set.
+Default workload (one "step" = one complete trace estimate, setup included):
+the 24^4 lattice (V = 331776, n = 3981312, the paper's lattice shape), SU(3)
+links U = exp(i 0.4 H) from seed 4, Wilson kappa = 0.1245, Theta = I; four
+polynomials: a 16x16 double polynomial (degree 255) and GMRES polynomials of
+degree 128, 32 and 8; the 20 lowest eigenpairs of M asked from PP-Arnoldi
+(p_in of degree 8, the pairs that pass the residual test are deflated); 64
+Z(4) noise vectors per Monte Carlo term, each term's noise one multi-RHS
+batch; FP32 Wilson kernels with FP64 sums, main solves deflated GMRES(50) with
+FP32 inner cycles and FP64 defect correction to a true relative residual of
+1e-8.
 
-Printed metric: multi-RHS Dslash HBM GB/s = algorithmic bytes moved by all
-Wilson-kernel launches of a step / wall time of the step.  The dominant
-kernel's own rate (bytes / summed HIP-event kernel time) is the roofline
+Printed metric: multi-RHS Dslash GB/s = algorithmic HBM bytes of every
+multi-right-hand-side Wilson launch of the timed steps (spinor operands read
+once, outputs written once, links once per site) / the summed HIP-event
+durations of those launches.  The dominant kernel's own rate is the roofline
 "achieved" figure.  Beside it, at the same noise seeds and counts (hence the
-same standard error): the plain FP64 form of the estimate and the learned
-form (the main solves preconditioned by the trained network; its training is
-timed separately), for the time-to-fixed-standard-error comparison.  The FP64
-CPU oracle is timed on the host as the baseline.
+same standard error): the plain FP64 form of the estimate and the learned form
+(the main solves preconditioned by the trained network, training timed too),
+for the time-to-fixed-standard-error comparison; the per-term differences of
+the mixed-precision means from the FP64 ones in units of the FP64 standard
+errors; the FP64 CPU oracle timed on the host as the baseline.
 
---workload 16x4 / 24x4 run the larger configurations (16^4 double polynomial
-16x16 with 100 eigenpairs requested and 256 noises; 24^4 with four polynomials
-16x16/128/32/8 and 64 noises per term) with the same report; the default line
-is the 8^4 one.
+--workload 16x4 runs the 16^4 configuration (the deflated 16x16 double
+polynomial with 100 eigenpairs requested, 256 noises, FP16 Krylov basis in the
+solves; the undeflated double polynomial's level variance is reported beside
+it) and --workload 8x4 the 8^4 one (degrees 128/32/8, 128 noises).
 """
 import argparse
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -42,8 +48,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--noises", type=int, default=None, help="noise vectors per term (default: the workload's)")
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="8x4",
-                    help="8x4 (default, the metric's configuration) or the larger parity configurations")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="24x4",
+                    help="24x4 (default, the largest single-GPU configuration), 16x4 or 8x4")
+    ap.add_argument("--compare-runs", type=int, default=3,
+                    help="estimates of the learned and of the plain form timed (median reported)")
     ap.add_argument("--theta", choices=["I", "g5"], default="I")
     ap.add_argument("--solve-pp", action="store_true",
                     help="main solves of the mixed and plain forms as polynomial-preconditioned GMRES (p_in)")
@@ -65,71 +73,101 @@ WORKLOADS = {
     "8x4": dict(dims=(8, 8, 8, 8), eps=0.5, seed=2, kappa=0.120, degrees=[128, 32, 8], noises=128, nev=20,
                 max_batch=0, net_pairs=64),
     "16x4": dict(dims=(16, 16, 16, 16), eps=0.4, seed=3, kappa=0.124, degrees=[(15, 15)], noises=256, nev=100,
-                 max_batch=0, net_pairs=16, solve_prec="fp16s"),
+                 max_batch=0, net_pairs=16, solve_prec="fp16s", deflate_double=True),
     "24x4": dict(dims=(24, 24, 24, 24), eps=0.4, seed=4, kappa=0.1245, degrees=[(15, 15), 128, 32, 8], noises=64,
                  nev=20, max_batch=0, net_pairs=16),
 }
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_wilson_dot_fp32_8x4x128_traffic.md")
+TRAFFIC_FILES = {"8x4": os.path.join(ROOT, "profiles", "k_wilson_dot_fp32_8x4x128_traffic.md"),
+                 "24x4": os.path.join(ROOT, "profiles", "wilson_fp32_24x4x64_traffic.md")}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2402_00016_amd", "csrc", "wilson.hip")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when the summary is missing or the kernel source changed
-    since the counters were taken (the summary records the source's SHA-256)."""
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` ("fused" or "plain") from the committed
+    counter summary of the workload, or None when the summary is missing or the
+    kernel source changed since the counters were taken (the summary records
+    the source's SHA-256)."""
     import hashlib
     try:
-        txt = open(TRAFFIC_FILE).read()
-    except OSError:
+        txt = open(TRAFFIC_FILES[workload]).read()
+    except (OSError, KeyError):
         return None
+    key = "traffic_bytes_per_launch" if workload == "8x4" else "traffic_bytes_per_launch_" + kernel
     vals = {}
     for line in txt.splitlines():
         line = line.strip().strip("`")
-        if ":" in line and line.split(":", 1)[0] in ("kernel_source_sha256", "traffic_bytes_per_launch"):
+        if ":" in line and line.split(":", 1)[0] in ("kernel_source_sha256", key):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
-    if "traffic_bytes_per_launch" not in vals:
+    if key not in vals:
         return None
     if vals.get("kernel_source_sha256") != hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest():
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return float(vals[key])
 
 
 def workload_name(key, W, noises, theta):
     L = W["dims"]
     degs = "/".join("%dx%d" % (d[0] + 1, d[1] + 1) if isinstance(d, tuple) else str(d) for d in W["degrees"])
-    return ("%s^4 Wilson (kappa %g, eps %g links seed %d), GMRES polynomials of degree %s, %d deflated eigenpairs "
+    return ("%s^4 Wilson (kappa %g, eps %g links seed %d), GMRES polynomials of degree %s%s, %d deflated eigenpairs "
             "requested, %d Z(4) noises per term, Theta=%s, FP32 Dslash + FP64 refinement to 1e-8%s"
-            % (L[0], W["kappa"], W["eps"], W["seed"], degs, W["nev"], noises, theta,
-               ", FP16 Krylov basis in the solves" if W.get("solve_prec") == "fp16s" else ""))
+            % (L[0], W["kappa"], W["eps"], W["seed"], degs, " (deflated double)" if W.get("deflate_double") else "",
+               W["nev"], noises, theta, ", FP16 Krylov basis in the solves" if W.get("solve_prec") == "fp16s" else ""))
 
 
-def cpu_baseline(dims, kappa, links, seconds):
-    """FP64 oracle Dslash on the host cores, on a bounded sample: repeated
-    16-RHS applications on the same field for about `seconds` seconds."""
-    import numpy as np
-
-    from oracle.philox import z4_noise_batch
+def cpu_baseline(dims, kappa, links, seconds, step_mvps):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload: repeated 16-RHS operator applications on the same field for
+    about `seconds` seconds on all threads, then a quarter of that on one
+    thread, and one degree-8 polynomial application to one vector.  The
+    oracle's time for a whole estimate is extrapolated from its per-MVP time
+    and the estimate's MVP count (labelled as such)."""
+    from oracle import krylov as OK
+    from oracle import poly as OP
+    from oracle.philox import z4_noise, z4_noise_batch
     from oracle.wilson import WilsonOp
     op = WilsonOp(dims, kappa, links)
+    threads = WilsonOp.max_threads()
     N = 16
     X = z4_noise_batch(2, 0, 0, N, op.n)
-    op(X)
-    t0 = time.perf_counter()
-    reps = 0
-    while time.perf_counter() - t0 < seconds:
+    bytes_per_apply = op.V * (N * 384.0 + 576.0)     # FP64: 12 complex in + out per site per rhs, links once
+
+    def rate(secs):
         op(X)
-        reps += 1
-    dt = time.perf_counter() - t0
-    V = op.V
-    bytes_per_apply = V * (N * 384.0 + 576.0)      # FP64: 12 complex in + out per site per rhs, links once
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(bytes_per_apply * reps / dt / 1e9, 3), "unit": "GB/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "FP64 oracle Wilson operator, %d^4 lattice, 16 Z(4) right-hand sides per call, "
-                      "%d calls in %.1f s on %d host threads; same byte formula as the GPU figure"
-                      % (dims[0], reps, dt, cores)}
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < secs:
+            op(X)
+            reps += 1
+        dt = time.perf_counter() - t0
+        return bytes_per_apply * reps / dt / 1e9, dt / (reps * N), reps, dt
+
+    gbs, s_per_mvp, reps, dt = rate(seconds)
+    WilsonOp.set_threads(1)
+    gbs1, s_per_mvp1, reps1, dt1 = rate(seconds / 4)
+    WilsonOp.set_threads(threads)
+    roots = OK.leja_order(np.array([1.0 + 0.05j * k for k in range(9)]))
+    v = z4_noise(2, 1, 0, op.n)
+    t0 = time.perf_counter()
+    OP.apply_p(op, roots, v)
+    t_poly8 = time.perf_counter() - t0
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle Wilson operator on the %s lattice, 16 Z(4) right-hand sides per call: "
+                      "%d calls in %.1f s on %d threads, %d calls in %.1f s on 1 thread; one degree-8 polynomial "
+                      "application to one vector; same byte formula as the GPU figure"
+                      % ("x".join(map(str, dims)), reps, dt, threads, reps1, dt1),
+            "one_core_GBs": round(gbs1, 3),
+            "s_per_rhs_mvp": s_per_mvp, "s_per_rhs_mvp_one_core": s_per_mvp1,
+            "degree8_poly_one_vector_s": round(t_poly8, 3),
+            "estimate_s_extrapolated": round(s_per_mvp * step_mvps, 1),
+            "estimate_note": "extrapolated: the oracle's per-MVP time x the MVPs of one GPU estimate "
+                             "(Gram-Schmidt and dense work not included)"}
+
+
+def level_report(est):
+    return [{"name": L.name, "mean": [L.mean.real, L.mean.imag], "var": L.var, "n": L.n,
+             "corr": [L.corr.real, L.corr.imag], "mvps": L.mvps, "s": round(L.seconds, 4)} for L in est.levels]
 
 
 def main():
@@ -139,7 +177,6 @@ def main():
               "shard across GPUs with one final all-reduce, which is not implemented); use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2402_00016_amd import driver, inputs, mpmc
@@ -154,7 +191,8 @@ def main():
                        defl_candidates=max(40, W["nev"] + 20), defl_m=112 if W["nev"] <= 40 else 136,
                        defl_pin_degree=8, theta=mpmc.THETA[a.theta], max_batch=W["max_batch"],
                        poly_prec=mpmc.FP32, solve_inner_prec=mpmc.PREC[W.get("solve_prec", "fp32")],
-                       solve_tol=1e-8, solve_restart=50, net_pairs=W["net_pairs"], solve_pp=a.solve_pp)
+                       solve_tol=1e-8, solve_restart=50, net_pairs=W["net_pairs"], solve_pp=a.solve_pp,
+                       deflate_double=W.get("deflate_double", False))
     sync = torch.cuda.synchronize
 
     if a.calibrate_copy:
@@ -166,8 +204,7 @@ def main():
         del src, dst
     for _ in range(a.warmup):
         driver.estimate(ctx, plan, sync)
-    # the side contexts (setup work on other streams) exist after the warm-up;
-    # their Wilson launches count in value as well
+    # the side contexts (setup work on other streams) exist after the warm-up
     sides = [c for c, _ in ctx._side.values()]
     for c in [ctx] + sides:
         mpmc.mpmc_timing_enable(c.handle, 1)
@@ -176,20 +213,40 @@ def main():
     ests = [driver.estimate(ctx, plan, sync) for _ in range(a.steps)]
     sync()
     t1 = time.perf_counter()
-    n32, ms32, by32 = mpmc.mpmc_timing_read(ctx.handle, mpmc.FP32)
-    n64, ms64, by64 = mpmc.mpmc_timing_read(ctx.handle, mpmc.FP64)
-    nd, msd, byd = mpmc.mpmc_timing_read(ctx.handle, mpmc.FP32 | mpmc.TIMING_FUSED)   # dominant kernel
-    na, msa, bya = mpmc.mpmc_timing_read(ctx.handle, mpmc.FP32 | mpmc.TIMING_PLAIN)
-    side_bytes = sum(mpmc.mpmc_timing_read(c.handle, p)[2] for c in sides for p in (mpmc.FP32, mpmc.FP64))
+
+    def timing(prec):
+        n = ms = by = 0.0
+        for c in [ctx] + sides:
+            cn, cms, cby = mpmc.mpmc_timing_read(c.handle, prec)
+            n, ms, by = n + cn, ms + cms, by + cby
+        return int(n), ms, by
+
+    fused = timing(mpmc.FP32 | mpmc.TIMING_FUSED)
+    plain32 = timing(mpmc.FP32 | mpmc.TIMING_PLAIN)
+    fused64 = timing(mpmc.FP64 | mpmc.TIMING_FUSED)
+    plain64 = timing(mpmc.FP64 | mpmc.TIMING_PLAIN)
+    single = timing(mpmc.FP64 | mpmc.TIMING_SINGLE)
+    single32 = timing(mpmc.FP32 | mpmc.TIMING_SINGLE)
     for c in [ctx] + sides:
         mpmc.mpmc_timing_enable(c.handle, 0)
     step_s = (t1 - t0) / a.steps
-    bytes_step = (by32 + by64 + side_bytes) / a.steps
+    multi = [fused, plain32, fused64, plain64]
+    dslash_ms = sum(k[1] for k in multi)
+    dslash_bytes = sum(k[2] for k in multi)
     est = ests[-1]
 
+    def kern(name, k):
+        n, ms, by = k
+        return {"kernel": name, "launches": n, "avg_launch_us": round(ms * 1e3 / max(n, 1), 2),
+                "algorithmic_bytes_per_launch": round(by / max(n, 1)),
+                "GBs": round(by / (ms * 1e-3) / 1e9, 1) if ms > 0 else None, "ms_per_step": round(ms / a.steps, 2)}
+
+    kf = kern("k_wilson_dot<FP32> (fused polynomial level step: w' = w - c M w, eta^H Theta w')", fused)
+    kp = kern("k_wilson<FP32> (multi-RHS apply: solves, polynomial applications)", plain32)
+    dom, dom_key = (kf, "fused") if fused[1] >= plain32[1] else (kp, "plain")
     out = {
         "metric": "multi-RHS Dslash HBM GB/s; time to fixed trace std-error, learned vs plain",
-        "value": round(bytes_step / step_s / 1e9, 3),
+        "value": round(dslash_bytes / (dslash_ms * 1e-3) / 1e9, 3) if dslash_ms > 0 else None,
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -203,31 +260,43 @@ def main():
         "config": {"workload": workload_name(a.workload, W, noises, a.theta), "lattice": list(dims),
                    "noises_per_term": noises, "rhs_per_launch": W["max_batch"] or noises,
                    "degrees": [list(d) if isinstance(d, tuple) else d for d in W["degrees"]], "theta": a.theta},
-        "roofline": {"bound": "hbm", "achieved": round(byd / (msd * 1e-3) / 1e9, 1) if msd > 0 else None,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(byd / (msd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if msd > 0 else None,
-                     "traffic": measured_traffic() if a.workload == "8x4" else None, "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, "
-                                                                     "scaled by a 256 MiB copy)",
-                     "algorithmic_bytes_per_launch": round(byd / max(nd, 1)),
-                     "kernel": "k_wilson_dot<FP32> (fused polynomial level step: w' = w - c M w, eta^H Theta w')",
-                     "launches": nd, "avg_launch_us": round(msd * 1e3 / max(nd, 1), 2),
-                     "other_fp32_wilson": {"kernel": "k_wilson<FP32>", "launches": na,
-                                           "avg_launch_us": round(msa * 1e3 / max(na, 1), 2),
-                                           "GBs": round(bya / (msa * 1e-3) / 1e9, 1) if msa > 0 else None}},
-        "trace": {"value": [est.value.real, est.value.imag], "stderr": est.stderr,
-                  "levels": [{"name": L.name, "mean": [L.mean.real, L.mean.imag], "var": L.var, "n": L.n,
-                              "corr": [L.corr.real, L.corr.imag], "mvps": L.mvps, "s": round(L.seconds, 4)}
-                             for L in est.levels],
+        "value_def": "algorithmic bytes of all multi-RHS Wilson launches of the timed steps / their summed "
+                     "HIP-event durations (inputs resident in HBM)",
+        "dslash": {"bytes_per_step": round(dslash_bytes / a.steps), "kernel_ms_per_step": round(dslash_ms / a.steps, 2),
+                   "bytes_per_wall_s_GBs": round(dslash_bytes / a.steps / step_s / 1e9, 1),
+                   "kernels": [kf, kp, kern("k_wilson_dot<FP64>", fused64), kern("k_wilson<FP64>", plain64)],
+                   "single_vector_launches": {"fp64": single[0], "fp32": single32[0],
+                                              "note": "nrhs = 1 (Arnoldi cycles): counted, not timed, not in value"}},
+        "roofline": {"bound": "hbm", "achieved": dom["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(dom["GBs"] / HBM_PEAK_GBS, 4) if dom["GBs"] else None,
+                     "traffic": measured_traffic(a.workload, dom_key),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy)",
+                     **{k: dom[k] for k in ("kernel", "launches", "avg_launch_us", "algorithmic_bytes_per_launch")}},
+        "trace": {"value": [est.value.real, est.value.imag], "stderr": est.stderr, "levels": level_report(est),
                   "deflated": est.defl_k, "setup_s": round(est.setup_seconds, 4), "mvps": est.mvps},
         "time_to_error_s": {"mixed_batched": round(step_s, 4)},
-        "fp64_kernel_share": {"launches": n64, "multi_rhs_ms_per_step": round(ms64 / a.steps, 3),
-                              "note": "single-vector launches are counted (bytes, launches) without events"},
     }
+
     def solve_term(e):
         L = e.levels[0]
         return {"s": round(L.seconds, 4), "mvps": L.mvps}
 
+    def timed_runs(fn, runs):
+        ts, last = [], None
+        for _ in range(max(1, runs)):
+            sync()
+            t = time.perf_counter()
+            last = fn()
+            sync()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)), ts, last
+
     out["solve_term"] = {"mixed_batched": solve_term(est)}
+    if W.get("deflate_double"):
+        # the same estimate with the undeflated double polynomial: its level variances beside the deflated ones
+        und = driver.estimate(ctx, driver.Plan(**{**plan.__dict__, "deflate_double": False}), sync)
+        out["trace"]["undeflated_double"] = {"value": [und.value.real, und.value.imag], "stderr": und.stderr,
+                                             "levels": level_report(und)}
     if not a.no_learned:
         ctx.release_workspace()
         torch.cuda.empty_cache()
@@ -242,12 +311,9 @@ def main():
         sync()
         t_train = time.perf_counter() - tl
         driver.estimate(ctx, lplan, sync, net=net)
-        sync()
-        tl = time.perf_counter()
-        el = driver.estimate(ctx, lplan, sync, net=net)
-        sync()
-        tl = time.perf_counter() - tl
+        tl, tls, el = timed_runs(lambda: driver.estimate(ctx, lplan, sync, net=net), a.compare_runs)
         out["time_to_error_s"]["learned_batched"] = round(tl, 4)
+        out["time_to_error_s"]["learned_runs"] = [round(t, 4) for t in tls]
         out["time_to_error_s"]["net_training"] = round(t_train, 4)
         out["time_to_error_s"]["learned_batched_incl_training"] = round(tl + t_train, 4)
         out["solve_term"]["learned_batched"] = solve_term(el)
@@ -262,23 +328,25 @@ def main():
         torch.cuda.empty_cache()
         plain = driver.Plan(**{**plan.__dict__, "poly_prec": mpmc.FP64, "solve_inner_prec": mpmc.FP64})
         driver.estimate(ctx, plain, sync)
-        sync()
-        tp = time.perf_counter()
-        e64 = driver.estimate(ctx, plain, sync)
-        sync()
-        tp = time.perf_counter() - tp
-        out["time_to_error_s"]["plain_fp64"] = round(tp, 4)
-        out["time_to_error_s"]["speedup_mixed_vs_plain"] = round(tp / step_s, 3)
-        if "learned_batched" in out["time_to_error_s"]:
-            out["time_to_error_s"]["speedup_learned_vs_plain"] = round(tp / out["time_to_error_s"]["learned_batched"], 3)
-            out["time_to_error_s"]["speedup_learned_incl_training_vs_plain"] = round(
-                tp / out["time_to_error_s"]["learned_batched_incl_training"], 3)
+        tp, tps, e64 = timed_runs(lambda: driver.estimate(ctx, plain, sync), a.compare_runs)
+        tt = out["time_to_error_s"]
+        tt["plain_fp64"] = round(tp, 4)
+        tt["plain_runs"] = [round(t, 4) for t in tps]
+        tt["speedup_mixed_vs_plain"] = round(tp / step_s, 3)
+        if "learned_batched" in tt:
+            tt["speedup_learned_vs_plain"] = round(tp / tt["learned_batched"], 3)
+            tt["speedup_learned_incl_training_vs_plain"] = round(tp / tt["learned_batched_incl_training"], 3)
         out["solve_term"]["plain_fp64"] = solve_term(e64)
         comb = float(np.hypot(e64.stderr, est.stderr))
         out["trace"]["plain_fp64"] = {"value": [e64.value.real, e64.value.imag], "stderr": e64.stderr,
                                       "diff_in_combined_sigma": abs(est.value - e64.value) / comb}
+        # per term: (mixed mean - FP64 mean) / FP64 standard error of the mean, same noise
+        out["trace"]["fp32_bias_in_fp64_sigma"] = [
+            {"name": Lm.name, "ratio": float(abs((Lm.mean + Lm.corr) - (Lp.mean + Lp.corr)) /
+                                             max(np.sqrt(Lp.var / Lp.n), 1e-300)),
+             "fp64_sigma": float(np.sqrt(Lp.var / Lp.n))} for Lm, Lp in zip(est.levels, e64.levels)]
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(dims, kappa, links, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(dims, kappa, links, a.cpu_seconds, est.mvps)
     print(json.dumps(out))
 
 

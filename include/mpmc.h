@@ -211,6 +211,36 @@ int mpmc_apply_poly(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y,
 int mpmc_poly_trace(mpmc_ctx *ctx, const mpmc_poly *p, int theta, const int period[4], int prec,
                     int max_batch, double *trace_host, int *exact_host, uint64_t *mvps_host);
 
+/* Distance colouring for exact probing (host only, no device work).  Sites x
+ * of the periodic lattice dims get colours from k <= 4 linear forms
+ *   c_i(x) = (sum_mu W[4 i + mu] x_mu) mod moduli[i],
+ *   colour(x) = sum_i c_i(x) prod_{l < i} moduli[l],
+ * such that two distinct sites at taxicab distance <= distance on the torus
+ * never share a colour (every modulus divides every extent, so each form is
+ * defined on the torus; the colouring is translation invariant).  The forms
+ * are searched by increasing colour count with a fixed pseudo-random sequence
+ * (the result depends on dims and distance only); without a valid candidate
+ * every site gets its own colour (forms x_mu mod L_mu).  Outputs (host):
+ * *k_host, moduli_host[4] (unused entries 1), W_host[16] (row-major k x 4,
+ * unused rows 0), *ncolours_host = prod moduli.  EINVAL for a null pointer,
+ * distance < 0 or an extent outside 1 .. 1024. */
+int mpmc_probe_colouring(const int dims[4], int distance, int *k_host, int *moduli_host, int *W_host,
+                         long *ncolours_host);
+
+/* Exact Tr(Theta p(M)) by probing with the distance colouring (Sec. 6: the
+ * last term of the multipolynomial formula is computed exactly by probing).
+ * p(M) of degree D couples only sites at taxicab distance <= D, so with the
+ * colouring of mpmc_probe_colouring(dims, D) the probe vectors v_{c,alpha}
+ * (1 on spin-colour component alpha of every site of colour c) satisfy
+ * sum_{c,alpha} v^H Theta p(M) v = Tr(Theta p(M)) exactly.  12 * ncolours
+ * probes, processed max_batch (rounded down to a multiple of 12; 0 = 192) at
+ * a time; each costs the MVPs of one mpmc_apply_poly.  prec: FP64 or FP32
+ * (quadratic forms accumulated in FP64).  Outputs (host): trace_host (complex
+ * double), *nprobe_host (may be NULL), *mvps_host (may be NULL).  The
+ * colouring is cached in the context per degree.  Synchronises. */
+int mpmc_poly_trace_probe(mpmc_ctx *ctx, const mpmc_poly *p, int theta, int prec, int max_batch,
+                          double *trace_host, long *nprobe_host, uint64_t *mvps_host);
+
 /* ---------------------------------------------------------------- deflation */
 
 /* Eigenpairs for deflation (Sec. 7, acceptance rule of Sec. 8): m steps of
@@ -307,6 +337,16 @@ int mpmc_wilson_variant_count(void);
  * autotuner's choice does not change the fused step. */
 int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant);
 
+/* Traversal order of the blocked multi-RHS Wilson kernels (variants 4-9 and
+ * the fused level step): order_host[i] is the i-th site visited (int[V], a
+ * permutation of 0 .. V-1, host memory, copied); workgroups take consecutive
+ * entries and each XCD one contiguous eighth of them.  NULL restores the
+ * default (4D blocks of extent 4, lexicographic).  Operator results do not
+ * depend on the order; the fused level step sums its per-workgroup partials
+ * in a different grouping (FP64 rounding only).  EINVAL if not a
+ * permutation.  Synchronises. */
+int mpmc_set_site_order(mpmc_ctx *ctx, const int *order_host);
+
 /* ------------------------------------------------- learned preconditioner */
 /* Not part of the paper: a small learned right preconditioner N for the main
  * solves (used by mpmc_solve / mpmc_level_estimate through their net
@@ -394,7 +434,10 @@ int mpmc_solve_pairs(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc
  * When both are polynomials and defl is given, the deflation term is
  *   sum_i c_i (eta^H Theta z_i)(u_i^H eta), c_i = upper(lambda_i) - lower(lambda_i),
  * and *corr_host = sum_i c_i u_i^H Theta z_i (the exact trace of the removed
- * part); otherwise *corr_host = 0.
+ * part).  The solve level (upper NULL, lower a polynomial) with defl uses the
+ * set inside its solves and, when mpmc_set_solve_level_deflation(ctx, 1) is
+ * in effect, is deflated the same way with c_i = 1/lambda_i - lower(lambda_i).
+ * Otherwise *corr_host = 0.
  * prec: precision of the polynomial applications (MPMC_FP64 or MPMC_FP32);
  * dot products and samples are accumulated in FP64.  Noise vectors are
  * processed in batches of at most max_batch right-hand sides (0 = all).
@@ -406,6 +449,16 @@ int mpmc_level_estimate(mpmc_ctx *ctx, const mpmc_poly *upper, const mpmc_poly *
                         double solve_tol, int solve_restart, int solve_inner_prec,
                         const mpmc_net *net, double *samples_host, double *corr_host,
                         uint64_t *mvps_host);
+
+/* Deflation of the solve level M^-1 - p_1 in mpmc_level_estimate (Sec. 7's
+ * level deflation with M^-1 as the upper operator): on = 1 subtracts
+ * sum_i (1/lambda_i - p_1(lambda_i)) (eta^H Theta z_i)(u_i^H eta) from every
+ * sample and returns the exact trace of the removed part as the correction;
+ * needed when p_1 is the deflated double polynomial (mpmc_gmres_poly with a
+ * deflation set), which does not approximate 1/lambda on the deflated
+ * eigenvalues.  on = 0 (the default): no subtraction.  The estimate is
+ * unbiased either way; only its variance changes.  EINVAL unless on is 0 or 1. */
+int mpmc_set_solve_level_deflation(mpmc_ctx *ctx, int on);
 
 /* The polynomial levels of the multipolynomial formula (Sec. 6) together:
  * term t has the samples, correction and precision semantics of

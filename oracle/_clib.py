@@ -32,5 +32,9 @@ def lib():
             ctypes.POINTER(ctypes.c_int), ctypes.c_double, ctypes.c_int,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long, ctypes.c_int]
         L.oracle_wilson_apply.restype = None
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
     return _lib

@@ -23,7 +23,12 @@
  *   spinor psi[r][s][spin][colour] complex double, r = right-hand side
  */
 #include <complex.h>
+#include <omp.h>
 #include <stddef.h>
+
+/* OpenMP team size of the operator (the baseline timing reports it). */
+void oracle_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 typedef double complex cplx;
 

@@ -39,6 +39,15 @@ class WilsonOp:
         self.matvecs += X.shape[0]
         return Y.reshape(-1) if single else Y
 
+    @staticmethod
+    def set_threads(n):
+        """OpenMP threads of the C operator (all calls in this process)."""
+        _clib.lib().oracle_set_threads(int(n))
+
+    @staticmethod
+    def max_threads():
+        return int(_clib.lib().oracle_max_threads())
+
     def __call__(self, x):
         return self._apply(x, False)
 

@@ -58,6 +58,10 @@ struct mpmc_ctx {
     const struct mpmc_poly *level_pp = nullptr;
     // small eigenproblems: 0 = Aberth-Ehrlich with the QR as fallback, 1 = QR only
     int dense_qr_only = 0;
+    // deflate the solve level M^-1 - p_1 of mpmc_level_estimate (mpmc_set_solve_level_deflation)
+    int solve_level_defl = 0;
+    // distance colourings of mpmc_poly_trace_probe by polynomial degree: k, m[4], W[4][4]
+    std::map<int, std::vector<int>> colourings;
 };
 
 struct mpmc_poly {
@@ -339,7 +343,8 @@ int wilson_dot_step_multi(mpmc_ctx *ctx, const void *w, void *wout, const uint32
                           int prec, const double *coef_dev, int theta, double *partial, int first_step);
 int wilson_dot_finish_chunks(mpmc_ctx *ctx, const double *partial, int nrhs, double *out);
 int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *codes, int nrhs, int prec, double2 c,
-                    double2 cnext, int theta, double *partial, int first_step);
+                    double2 cnext, int theta, double *partial, int first_step, const void *a = nullptr,
+                    double2 alpha = double2{0, 0}, double2 beta = double2{1, 0});
 int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, int prec, double *out, int accumulate,
                       double sign);
 // timing hooks around one launch (no-ops unless timing is enabled)
@@ -360,6 +365,9 @@ int dense_backsolve(mpmc_ctx *ctx, const double *H, int ldc, int k, int N, const
 
 // krylov.hip
 int poly_apply_internal(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec);
+int poly_work_vectors(const mpmc_poly *p);
+int poly_apply_buf(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec, void *const *buf);
+int poly_validate(const mpmc_ctx *ctx, const mpmc_poly *p);
 // acc[r] += sign * eta_r^H Theta p(M) eta_r without forming p(M) eta (fused steps)
 int poly_quad_fused(mpmc_ctx *ctx, const mpmc_poly *p, const void *eta, const uint32_t *codes, int nrhs, int prec,
                     int theta, double *acc, double sign);

@@ -181,6 +181,28 @@ static void build_site_order(const int L[4], std::vector<int> &order) {
                                 }
 }
 
+// Replace the traversal order of the blocked kernels (NULL: the default
+// blocked order).  The order must be a permutation of the sites.
+MPMC_API int mpmc_set_site_order(mpmc_ctx *ctx, const int *order_host) {
+    if (!ctx) return MPMC_EINVAL;
+    std::vector<int> order;
+    if (order_host) {
+        order.assign(order_host, order_host + ctx->V);
+        std::vector<char> seen(ctx->V, 0);
+        for (long i = 0; i < ctx->V; ++i) {
+            const int s = order[i];
+            if (s < 0 || s >= ctx->V || seen[s])
+                return set_err(ctx, MPMC_EINVAL, "mpmc_set_site_order: entry %ld (%d) is not a permutation", i, s);
+            seen[s] = 1;
+        }
+    } else {
+        build_site_order(ctx->dims, order);
+    }
+    HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_OR_RET(ctx, hipMemcpy(ctx->site_order, order.data(), (size_t)ctx->V * sizeof(int), hipMemcpyHostToDevice));
+    return MPMC_OK;
+}
+
 MPMC_API int mpmc_create(const int dims[4], double kappa, int t_antiperiodic, const double *links_host,
                          void *stream, mpmc_ctx **out) {
     if (!dims || !links_host || !out) return set_err(nullptr, MPMC_EINVAL, "mpmc_create: null argument");

@@ -86,6 +86,8 @@ static int validate_poly(const mpmc_ctx *ctx, const mpmc_poly *p) {
     return MPMC_OK;
 }
 
+int poly_validate(const mpmc_ctx *ctx, const mpmc_poly *p) { return validate_poly(ctx, p); }
+
 int poly_matvecs(const mpmc_poly *p) {
     if (!p->inner) return p->d - 1;
     return (p->d - 1) * p->inner->d + (p->inner->d - 1);
@@ -237,9 +239,10 @@ MPMC_API int mpmc_gmres_poly(mpmc_ctx *ctx, const mpmc_poly *inner, const mpmc_d
 
 // ------------------------------------------------------ apply_poly --
 
-static int apply_single(mpmc_ctx *ctx, const std::vector<double> &roots, int d, const void *x, void *y, int nrhs,
-                        int prec) {
-    Scratch S(ctx);
+// y = p(M) x for a single polynomial with caller-provided work vectors wa, wb
+// (each vec_bytes(ctx, nrhs, prec), distinct from x and y).
+static int apply_single_buf(mpmc_ctx *ctx, const std::vector<double> &roots, int d, const void *x, void *y,
+                            int nrhs, int prec, void *wa, void *wb) {
     auto th = [&](int k) { return std::complex<double>(roots[2 * k], roots[2 * k + 1]); };
     auto inv = [&](int k) {
         std::complex<double> v = 1.0 / th(k);
@@ -249,9 +252,6 @@ static int apply_single(mpmc_ctx *ctx, const std::vector<double> &roots, int d, 
     const bool fold = nrhs == 1 && d > 1;
     if (!fold) RET_IF(blas_axpby(ctx, x, y, nrhs, prec, inv(0), make_double2(0, 0)));
     if (d == 1) return MPMC_OK;
-    void *wa = S.get(vec_bytes(ctx, nrhs, prec));
-    void *wb = S.get(vec_bytes(ctx, nrhs, prec));
-    if (!wa || !wb) return MPMC_ENOMEM;
     const void *cur = x;
     for (int k = 0; k + 1 < d; ++k) {
         void *nxt = (cur == wa) ? wb : wa;
@@ -263,18 +263,24 @@ static int apply_single(mpmc_ctx *ctx, const std::vector<double> &roots, int d, 
     return MPMC_OK;
 }
 
-int poly_apply_internal(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec) {
+static int apply_single(mpmc_ctx *ctx, const std::vector<double> &roots, int d, const void *x, void *y, int nrhs,
+                        int prec) {
+    Scratch S(ctx);
+    void *wa = S.get(vec_bytes(ctx, nrhs, prec));
+    void *wb = S.get(vec_bytes(ctx, nrhs, prec));
+    if (!wa || !wb) return MPMC_ENOMEM;
+    return apply_single_buf(ctx, roots, d, x, y, nrhs, prec, wa, wb);
+}
+
+int poly_work_vectors(const mpmc_poly *p) { return p->inner ? 6 : 2; }
+
+// y = p(M) x with the poly_work_vectors(p) work vectors buf[i] supplied by the caller.
+int poly_apply_buf(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec, void *const *buf) {
     if (prec != MPMC_FP64 && prec != MPMC_FP32)
         return set_err(ctx, MPMC_EINVAL, "polynomial application supports FP64 and FP32 storage");
-    Scratch S(ctx);
-    if (!p->inner) return apply_single(ctx, p->roots, p->d, x, y, nrhs, prec);
+    if (!p->inner) return apply_single_buf(ctx, p->roots, p->d, x, y, nrhs, prec, buf[0], buf[1]);
     // u = p_out(phi_in) x : u = x/v_1, w_{k+1} = w_k - phi(w_k)/v_k, phi(w) = M p_in(M) w
-    const size_t vb = vec_bytes(ctx, nrhs, prec);
-    void *u = S.get(vb);
-    void *t = S.get(vb);
-    void *wa = S.get(vb);
-    void *wb = S.get(vb);
-    if (!u || !t || !wa || !wb) return MPMC_ENOMEM;
+    void *u = buf[0], *t = buf[1], *wa = buf[2], *wb = buf[3];
     auto inv = [&](int k) {
         std::complex<double> v = 1.0 / std::complex<double>(p->roots[2 * k], p->roots[2 * k + 1]);
         return make_double2(v.real(), v.imag());
@@ -283,13 +289,24 @@ int poly_apply_internal(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *
     const void *cur = x;
     for (int k = 0; k + 1 < p->d; ++k) {
         void *nxt = (cur == wa) ? wb : wa;
-        RET_IF(apply_single(ctx, p->inner->roots, p->inner->d, cur, t, nrhs, prec));
+        RET_IF(apply_single_buf(ctx, p->inner->roots, p->inner->d, cur, t, nrhs, prec, buf[4], buf[5]));
         double2 c = inv(k);
         RET_IF(wilson_launch_full(ctx, t, cur, nxt, u, nrhs, prec, make_double2(1, 0), make_double2(-c.x, -c.y),
                                   inv(k + 1), 0, 0));
         cur = nxt;
     }
-    return apply_single(ctx, p->inner->roots, p->inner->d, u, y, nrhs, prec);
+    return apply_single_buf(ctx, p->inner->roots, p->inner->d, u, y, nrhs, prec, buf[4], buf[5]);
+}
+
+int poly_apply_internal(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec) {
+    if (prec != MPMC_FP64 && prec != MPMC_FP32)
+        return set_err(ctx, MPMC_EINVAL, "polynomial application supports FP64 and FP32 storage");
+    Scratch S(ctx);
+    const size_t vb = vec_bytes(ctx, nrhs, prec);
+    void *buf[6];
+    for (int i = 0; i < poly_work_vectors(p); ++i)
+        if (!(buf[i] = S.get(vb))) return MPMC_ENOMEM;
+    return poly_apply_buf(ctx, p, x, y, nrhs, prec, buf);
 }
 
 MPMC_API int mpmc_apply_poly(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec) {
@@ -343,26 +360,55 @@ int poly_quad_fused(mpmc_ctx *ctx, const mpmc_poly *p, const void *eta, const ui
                     int theta, double *acc, double sign) {
     if (!poly_quad_fusable(nrhs)) return set_err(ctx, MPMC_EINVAL, "fused quadratic form needs nrhs %% 64 == 0");
     if (!p->inner) return quad_single_fused(ctx, p->roots, p->d, eta, eta, codes, nrhs, prec, theta, acc, sign);
+    // Double polynomial (Sec. 5): p(M) = p_in(M) p_out(phi(M)), phi = M p_in(M) = 1 - pi_in(M).
+    // With the outer recurrence w_0 = eta, w_{k+1} = w_k - phi(w_k) / th_k^out and the
+    // inner one v_0 = w_k, v_{j+1} = v_j - M v_j / th_j^in:
+    //   eta^H Theta p(M) eta = sum_k (1/th_k^out) sum_{j < d_in} (1/th_j^in) eta^H Theta v_{k,j},
+    //   phi(w_k) = w_k - v_{k,d_in},  so  w_{k+1} = (1 - 1/th_k^out) w_k + (1/th_k^out) v_{k,d_in}.
+    // Every step is one fused launch (one spinor read and write; the step that
+    // yields v_{k,d_in} also reads w_k and writes w_{k+1} directly), and every
+    // term of the quadratic form is accumulated inside those launches.
     Scratch S(ctx);
     const size_t vb = vec_bytes(ctx, nrhs, prec);
-    void *u = S.get(vb);
-    void *t = S.get(vb);
-    void *wa = S.get(vb);
-    void *wb = S.get(vb);
-    if (!u || !t || !wa || !wb) return MPMC_ENOMEM;
-    auto inv = [&](int k) {
-        std::complex<double> v = 1.0 / std::complex<double>(p->roots[2 * k], p->roots[2 * k + 1]);
-        return make_double2(v.real(), v.imag());
-    };
-    RET_IF(blas_axpby(ctx, eta, u, nrhs, prec, inv(0), make_double2(0, 0)));
-    const void *cur = eta;
-    for (int k = 0; k + 1 < p->d; ++k) {
-        void *nxt = (cur == wa) ? wb : wa;
-        RET_IF(apply_single(ctx, p->inner->roots, p->inner->d, cur, t, nrhs, prec));
-        double2 c = inv(k);
-        RET_IF(wilson_launch_full(ctx, t, cur, nxt, u, nrhs, prec, make_double2(1, 0), make_double2(-c.x, -c.y),
-                                  inv(k + 1), 0, 0));
-        cur = nxt;
+    void *buf[3] = {S.get(vb), S.get(vb), S.get(vb)};
+    double2 *t = (double2 *)S.get(sizeof(double2) * nrhs * 2);
+    double *part = (double *)S.get(sizeof(double2) * wilson_dot_partial_count(ctx, nrhs));
+    if (!buf[0] || !buf[1] || !buf[2] || !t || !part) return MPMC_ENOMEM;
+    const mpmc_poly *pin = p->inner;
+    const int din = pin->d, dout = p->d;
+    auto cx = [](const std::vector<double> &r, int k) { return std::complex<double>(r[2 * k], r[2 * k + 1]); };
+    auto d2 = [](std::complex<double> v) { return make_double2(v.real(), v.imag()); };
+    auto io = [&](int k) { return 1.0 / cx(p->roots, k); };
+    auto ii = [&](int j) { return 1.0 / cx(pin->roots, j); };
+    // first term (k = 0, j = 0): eta^H Theta eta / (th_0^out th_0^in)
+    RET_IF(blas_dot(ctx, eta, eta, nrhs, prec, theta, (double *)t));
+    RET_IF(blas_scale_acc(ctx, (double *)t, nrhs, d2(io(0) * ii(0)), sign, acc));
+    const void *w = eta;   // w_k
+    bool first = true;
+    for (int k = 0; k < dout; ++k) {
+        const bool last_outer = k == dout - 1;
+        const int nsteps = last_outer ? din - 1 : din;
+        const void *v = w;
+        for (int j = 0; j < nsteps; ++j) {
+            void *dst = nullptr;
+            for (void *c : buf)
+                if (c != w && c != v) {
+                    dst = c;
+                    break;
+                }
+            const double2 c = d2(ii(j));
+            if (!last_outer && j == din - 1) {
+                // v_{k,d_in} combined into w_{k+1}; accumulates the first term of step k + 1
+                RET_IF(wilson_dot_step(ctx, v, dst, codes, nrhs, prec, c, d2(io(k + 1) * ii(0)), theta, part, first,
+                                       w, d2(1.0 - io(k)), d2(io(k))));
+                w = dst;
+            } else {
+                RET_IF(wilson_dot_step(ctx, v, dst, codes, nrhs, prec, c, d2(io(k) * ii(j + 1)), theta, part, first));
+                v = dst;
+            }
+            first = false;
+        }
     }
-    return quad_single_fused(ctx, p->inner->roots, p->inner->d, eta, u, codes, nrhs, prec, theta, acc, sign);
+    if (!first) RET_IF(wilson_dot_finish(ctx, part, nrhs, prec, acc, 1, sign));
+    return MPMC_OK;
 }

@@ -29,13 +29,22 @@ __global__ void k_defl_term(double2 *acc, const double2 *a, const double2 *b, co
 }
 
 // Deflated level (Sec. 7): coefficients c_i = upper(lambda_i) - lower(lambda_i)
-// on the device (dcf, k entries) and the exact correction
-// corr = sum_i c_i u_i^H Theta z_i.  Synchronises.
+// (upper == nullptr: M^-1, upper(lambda) = 1/lambda) on the device (dcf, k
+// entries) and the exact correction corr = sum_i c_i u_i^H Theta z_i.
+// Synchronises.
 int defl_setup(mpmc_ctx *ctx, const mpmc_poly *upper, const mpmc_poly *lower, const mpmc_defl *defl, int th,
                double2 *dcf, double2 *uz, std::complex<double> &corr) {
     const int k = defl->k;
     std::vector<double> pu(2 * k), pl(2 * k), c(2 * k);
-    poly_eval_host(upper, defl->lam.data(), pu.data(), k);
+    if (upper) {
+        poly_eval_host(upper, defl->lam.data(), pu.data(), k);
+    } else {
+        for (int i = 0; i < k; ++i) {
+            const std::complex<double> v = 1.0 / std::complex<double>(defl->lam[2 * i], defl->lam[2 * i + 1]);
+            pu[2 * i] = v.real();
+            pu[2 * i + 1] = v.imag();
+        }
+    }
     poly_eval_host(lower, defl->lam.data(), pl.data(), k);
     for (int i = 0; i < 2 * k; ++i) c[i] = pu[i] - pl[i];
     HIP_OR_RET(ctx, hipMemcpyAsync(dcf, c.data(), sizeof(double2) * k, hipMemcpyHostToDevice, ctx->stream));
@@ -66,6 +75,13 @@ int defl_samples(mpmc_ctx *ctx, const mpmc_defl *defl, const double2 *dcf, uint6
 
 }  // namespace
 
+MPMC_API int mpmc_set_solve_level_deflation(mpmc_ctx *ctx, int on) {
+    if (!ctx) return MPMC_EINVAL;
+    if (on != 0 && on != 1) return set_err(ctx, MPMC_EINVAL, "mpmc_set_solve_level_deflation: on must be 0 or 1");
+    ctx->solve_level_defl = on;
+    return MPMC_OK;
+}
+
 MPMC_API int mpmc_level_estimate(mpmc_ctx *ctx, const mpmc_poly *upper, const mpmc_poly *lower,
                                  const mpmc_defl *defl, int theta, uint64_t seed, uint32_t stream, uint64_t first,
                                  int nnoise, int prec, int max_batch, double solve_tol, int solve_restart,
@@ -82,7 +98,9 @@ MPMC_API int mpmc_level_estimate(mpmc_ctx *ctx, const mpmc_poly *upper, const mp
     const uint64_t mvp0 = ctx->mvps;
     const int th = theta == MPMC_THETA_G5 ? 1 : 0;
     const int B = (max_batch > 0 && max_batch < nnoise) ? max_batch : nnoise;
-    const bool use_defl = upper && lower && defl && defl->k > 0;
+    // polynomial-difference levels are deflated (Sec. 7); the solve level
+    // M^-1 - p_1 too when the context asks for it (a deflated p_1)
+    const bool use_defl = lower && defl && defl->k > 0 && (upper || ctx->solve_level_defl);
     const int k = use_defl ? defl->k : 0;
 
     Scratch S(ctx);

@@ -852,15 +852,22 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
 // a run of 64-wide chunks of the right-hand-side axis (stride N); the launch
 // covers the first nact right-hand sides, and chunk q takes its (c, cnext)
 // from coef[2q], coef[2q + 1].
-template <int P, int ORDER, bool MULTI = false>
+//
+// CMB: the step ends a double polynomial's inner product form and combines,
+// w' = alpha a + beta (w - c M w) with a second operand a (the outer
+// recurrence's current vector); the quadratic form then accumulates on w'.
+template <int P, int ORDER, bool MULTI = false, bool CMB = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_FP64 ? 1 : 2))) void k_wilson_dot(const void *__restrict__ b, const int *__restrict__ nbr,
                                                     const typename LinkT<P>::type *__restrict__ links,
                                                     void *__restrict__ out, const uint32_t *__restrict__ codes,
                                                     double2 c, double2 cnext, double kappa, int theta,
                                                     double2 *__restrict__ partial, long V, int N, int first_step,
                                                     const int *__restrict__ order, int nact = 0,
-                                                    const double2 *__restrict__ coef = nullptr) {
+                                                    const double2 *__restrict__ coef = nullptr,
+                                                    const void *__restrict__ a = nullptr,
+                                                    double2 alpha = double2{0, 0}, double2 beta = double2{1, 0}) {
     static_assert(!MULTI || ORDER == 2, "several recurrences need the blocked 64-wide traversal");
+    static_assert(!(MULTI && CMB), "the combining step runs one recurrence");
     using T = typename Store<P>::real;
     constexpr bool U = ORDER <= 2;   // one site per wavefront (else 2 or 4, row-distributed links)
     WIn<P> in{b, nullptr, nbr, links};
@@ -883,9 +890,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_F
         const T kap = (T)kappa;
         const cpx<T> cc = mk((T)c.x, (T)c.y);
         const SiteAcc<P, U> W(in.b, nullptr, s, N, (uint32_t)r), O(out, nullptr, s, N, (uint32_t)r);
-        cpx<T> wv[12];
+        cpx<T> wv[12], av[12];
 #pragma unroll
         for (int k = 0; k < 12; ++k) wv[k] = W.ld(k);
+        if constexpr (CMB) {
+            const SiteAcc<P, U> A(a, nullptr, s, N, (uint32_t)r);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) av[k] = A.ld(k);
+        }
+        const cpx<T> al = mk((T)alpha.x, (T)alpha.y), be = mk((T)beta.x, (T)beta.y);
         // conj(eta_k) wn with eta_k = i^sym, by selects (no per-lane branches):
         // odd sym swaps (re, im) -> (im, -re), sym >= 2 negates; Theta = gamma5
         // negates spins 2 and 3.
@@ -893,7 +906,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_F
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const cpx<T> mw = wv[k] - kap * acc[k / 3][k % 3];
-            const cpx<T> wn = wv[k] - cc * mw;
+            cpx<T> wn = wv[k] - cc * mw;
+            if constexpr (CMB) wn = al * av[k] + be * wn;
             O.st(k, wn);
             const uint32_t sym = (code >> (2 * k)) & 3u;
             const double a = (double)wn.re, b = (double)wn.im;
@@ -1205,51 +1219,70 @@ int wilson_noise_codes(mpmc_ctx *ctx, uint64_t seed, uint32_t stream, uint64_t f
     return MPMC_OK;
 }
 
-template <int P>
+template <int P, bool CMB>
 static void launch_dot(mpmc_ctx *ctx, int dord, unsigned grid, const WIn<P> &in, void *wout, const uint32_t *codes,
-                       double2 c, double2 cnext, int theta, double2 *partial, int nrhs, int first_step) {
+                       double2 c, double2 cnext, int theta, double2 *partial, int nrhs, int first_step,
+                       const void *a, double2 alpha, double2 beta) {
     const int *ord = dord ? ctx->site_order : nullptr;
     switch (dord) {
     case 2:
-        k_wilson_dot<P, 2><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext, ctx->kappa,
-                                                          theta, partial, ctx->V, nrhs, first_step, ord);
+        k_wilson_dot<P, 2, false, CMB><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                                      ctx->kappa, theta, partial, ctx->V, nrhs,
+                                                                      first_step, ord, 0, nullptr, a, alpha, beta);
         break;
     case 3:
-        k_wilson_dot<P, 3><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext, ctx->kappa,
-                                                          theta, partial, ctx->V, nrhs, first_step, ord);
+        k_wilson_dot<P, 3, false, CMB><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                                      ctx->kappa, theta, partial, ctx->V, nrhs,
+                                                                      first_step, ord, 0, nullptr, a, alpha, beta);
         break;
     case 4:
-        k_wilson_dot<P, 4><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext, ctx->kappa,
-                                                          theta, partial, ctx->V, nrhs, first_step, ord);
+        k_wilson_dot<P, 4, false, CMB><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                                      ctx->kappa, theta, partial, ctx->V, nrhs,
+                                                                      first_step, ord, 0, nullptr, a, alpha, beta);
         break;
     default:
-        k_wilson_dot<P, 0><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext, ctx->kappa,
-                                                          theta, partial, ctx->V, nrhs, first_step, nullptr);
+        k_wilson_dot<P, 0, false, CMB><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
+                                                                      ctx->kappa, theta, partial, ctx->V, nrhs,
+                                                                      first_step, nullptr, 0, nullptr, a, alpha, beta);
     }
 }
 
+// One fused step; with a != nullptr the combining form
+// wout = alpha a + beta (w - c M w) (a may be w, must not be wout).
 int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *codes, int nrhs, int prec, double2 c,
-                    double2 cnext, int theta, double *partial, int first_step) {
+                    double2 cnext, int theta, double *partial, int first_step, const void *a, double2 alpha,
+                    double2 beta) {
     if (nrhs % 64 != 0 || (nrhs > 256 && nrhs % 256 != 0))
         return set_err(ctx, MPMC_EINVAL, "fused level step needs nrhs %% 64 == 0 (and %% 256 above 256)");
+    if (a && a == wout) return set_err(ctx, MPMC_EINVAL, "fused level step: a aliases the output");
     const long work = ctx->V * nrhs;
     const unsigned grid = grid_for(work, 256);
     const int dord = dot_order(ctx, nrhs, prec);
     const int ev = timing_begin(ctx);
     if (prec == MPMC_FP64) {
         const WIn<MPMC_FP64> in = make_in<MPMC_FP64>(ctx, w, nrhs);
-        launch_dot<MPMC_FP64>(ctx, dord, grid, in, wout, codes, c, cnext, theta, (double2 *)partial, nrhs, first_step);
+        if (a)
+            launch_dot<MPMC_FP64, true>(ctx, dord, grid, in, wout, codes, c, cnext, theta, (double2 *)partial, nrhs,
+                                        first_step, a, alpha, beta);
+        else
+            launch_dot<MPMC_FP64, false>(ctx, dord, grid, in, wout, codes, c, cnext, theta, (double2 *)partial, nrhs,
+                                         first_step, nullptr, alpha, beta);
     } else if (prec == MPMC_FP32) {
         const WIn<MPMC_FP32> in = make_in<MPMC_FP32>(ctx, w, nrhs);
-        launch_dot<MPMC_FP32>(ctx, dord, grid, in, wout, codes, c, cnext, theta, (double2 *)partial, nrhs, first_step);
+        if (a)
+            launch_dot<MPMC_FP32, true>(ctx, dord, grid, in, wout, codes, c, cnext, theta, (double2 *)partial, nrhs,
+                                        first_step, a, alpha, beta);
+        else
+            launch_dot<MPMC_FP32, false>(ctx, dord, grid, in, wout, codes, c, cnext, theta, (double2 *)partial, nrhs,
+                                         first_step, nullptr, alpha, beta);
     }
     else
         return set_err(ctx, MPMC_EINVAL, "fused level step supports FP64 and FP32");
     HIP_OR_RET(ctx, hipGetLastError());
     if (ev >= 0) {
-        // spinor read + write, 4-byte noise code, links once per site (the
-        // partial sums add 16 B per 256 threads and are not counted)
-        const double per = 2 * spinor_bytes(prec) + 4.0;
+        // spinor read + write (+ the read of a), 4-byte noise code, links once
+        // per site (the partial sums add 16 B per 256 threads and are not counted)
+        const double per = (a ? 3 : 2) * spinor_bytes(prec) + 4.0;
         timing_end(ctx, ev, prec | MPMC_TIMING_FUSED, (double)ctx->V * ((double)nrhs * per + link_bytes(prec)));
     }
     ctx->mvps += (uint64_t)nrhs;

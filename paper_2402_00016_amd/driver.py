@@ -70,6 +70,10 @@ class Plan:
                                          # off: one term's operand pair stays in the 256 MB Infinity Cache
     overlap_levels: bool = False         # polynomial terms on a side stream while the solve term runs
                                          # (8^4: 56.5 vs 58.0 ms per estimate; both streams bandwidth-bound)
+    deflate_double: bool = False         # double polynomials from a deflated outer cycle (Sec. 7); the
+                                         # solve level is then deflated as well when p_1 is one of them
+    probe_last: bool = False             # last term Tr(Theta p_K) exactly by probing (Sec. 6) instead of sampling
+    probe_batch: int = 192               # probe vectors per batch
 
 
 @dataclass
@@ -79,6 +83,7 @@ class LevelResult:
     corr: complex
     mvps: int
     seconds: float
+    exact: bool = False                  # one exact value (probing), no sampling variance
 
     @property
     def n(self):
@@ -90,6 +95,8 @@ class LevelResult:
 
     @property
     def var(self):
+        if self.exact:
+            return 0.0
         X = self.samples
         return float(np.sum(np.abs(X - X.mean()) ** 2) / (len(X) - 1)) if len(X) > 1 else math.inf
 
@@ -116,18 +123,38 @@ class Estimate:
             **self.info)
 
 
-def build_polys(ctx, plan: Plan, defl=None):
-    """GMRES polynomials of the plan (highest degree first)."""
+def build_polys(ctx, plan: Plan, defl=None, defer_deflated=False):
+    """GMRES polynomials of the plan (highest degree first).  A double
+    polynomial's outer cycle is the deflated one (Sec. 7) when
+    plan.deflate_double and defl holds eigenpairs.  defer_deflated: such an
+    outer cycle is not run; its entry is (j, p_in) for build_deferred."""
     polys = []
     for j, deg in enumerate(plan.degrees):
         if isinstance(deg, (tuple, list)):
             din, dout = deg
             pin = ctx.gmres_poly(plan.seed, 0x100 + j, din + 1)
-            p = ctx.gmres_poly(plan.seed, 0x100 + j, dout + 1, inner=pin, defl=defl)
+            if plan.deflate_double and defer_deflated:
+                p = (j, pin)
+            else:
+                d = defl if plan.deflate_double else None
+                p = ctx.gmres_poly(plan.seed, 0x100 + j, dout + 1, inner=pin, defl=d)
         else:
             p = ctx.gmres_poly(plan.seed, 0x100 + j, int(deg) + 1)
         polys.append(p)
     return polys
+
+
+def build_deferred(ctx, plan: Plan, polys, defl):
+    """Outer cycles left by build_polys(defer_deflated=True), now on the
+    deflation set (GMRES on Q phi_in(M) from Q b)."""
+    out = []
+    for p in polys:
+        if isinstance(p, tuple):
+            j, pin = p
+            dout = plan.degrees[j][1]
+            p = ctx.gmres_poly(plan.seed, 0x100 + j, dout + 1, inner=pin, defl=defl)
+        out.append(p)
+    return out
 
 
 def build_deflation(ctx, plan: Plan):
@@ -194,7 +221,7 @@ def rehome_poly(ctx, p, cache=None):
     if id(p) not in cache:
         inner = rehome_poly(ctx, p.inner, cache) if p.inner is not None else None
         q = ctx.poly_from_roots(p.roots, inner=inner)
-        q.d_eff, q.relres = p.d_eff, p.relres
+        q.d_eff, q.relres, q.deflated = p.d_eff, p.relres, p.deflated
         cache[id(p)] = q
     return cache[id(p)]
 
@@ -261,19 +288,28 @@ def build_setup(ctx, plan: Plan, train=False):
     autotune_levels(ctx, plan)
     if not plan.overlap_setup:
         defl = build_deflation(ctx, plan)
-        polys = build_polys(ctx, plan)
+        polys = build_polys(ctx, plan, defl)
         net, hist = train_net(ctx, plan) if train else (None, None)
         return defl, polys, net, hist
-    jp = _SideJob(ctx, "polys", build_polys, plan)
+    jp = _SideJob(ctx, "polys", build_polys, plan, None, True)
     jn = _SideJob(ctx, "net", train_net, plan) if train else None
     defl = build_deflation(ctx, plan)
     cache = {}
-    polys = [rehome_poly(ctx, p, cache) for p in jp.join()]
+    polys = [(p[0], rehome_poly(ctx, p[1], cache)) if isinstance(p, tuple) else rehome_poly(ctx, p, cache)
+             for p in jp.join()]
+    polys = build_deferred(ctx, plan, polys, defl)
     net, hist = None, None
     if jn is not None:
         snet, hist = jn.join()
         net = ctx.net(snet.weights)
     return defl, polys, net, hist
+
+
+def solve_level_deflated(polys, defl):
+    """The solve level M^-1 - p_1 is deflated (c_i = 1/lambda_i - p_1(lambda_i))
+    when p_1 comes from a deflated outer cycle: p_1 then does not approximate
+    1/lambda on the deflated eigenvalues."""
+    return int(bool(polys) and getattr(polys[0], "deflated", False) and defl is not None and defl.k > 0)
 
 
 def combine(levels):
@@ -295,6 +331,9 @@ def run_levels(ctx, plan: Plan, polys, defl, noises=None, first=0, net=None, ski
     for l, (up, lo) in enumerate(zip(uppers, lowers)):
         if skip_solve and up is None:
             continue
+        if plan.probe_last and up is not None and lo is None:
+            out.append(probe_term(ctx, plan, up, names[l]))
+            continue
         d = defl if (up is not None and lo is not None and plan.deflate_levels) else (defl if up is None else None)
         t0 = time.perf_counter()
         X, T, mv = ctx.level(up, lo, d, plan.theta, plan.seed, l, first, noises, prec=plan.poly_prec,
@@ -302,6 +341,14 @@ def run_levels(ctx, plan: Plan, polys, defl, noises=None, first=0, net=None, ski
                              solve_inner_prec=plan.solve_inner_prec, net=net if up is None else None)
         out.append(LevelResult(names[l], X, T, mv, time.perf_counter() - t0))
     return out
+
+
+def probe_term(ctx, plan: Plan, p, name):
+    """Tr(Theta p(M)) exactly by probing with the distance colouring (Sec. 6)."""
+    t0 = time.perf_counter()
+    tr, nprobe, mv = ctx.poly_trace_probe(p, theta=plan.theta, prec=plan.poly_prec, max_batch=plan.probe_batch)
+    return LevelResult(name + " (probed, %d probes)" % nprobe, np.array([tr]), 0j, mv, time.perf_counter() - t0,
+                       exact=True)
 
 
 def run_levels_overlapped(ctx, plan: Plan, polys, defl, net=None):
@@ -368,6 +415,7 @@ def estimate(ctx, plan: Plan, sync=None, net=None) -> Estimate:
     t1 = time.perf_counter()
     pp = solve_preconditioner(ctx, plan, defl) if not plan.learned else None
     ctx.set_level_solve_poly(pp)
+    ctx.set_solve_level_deflation(solve_level_deflated(polys, defl))
     try:
         if plan.overlap_levels and plan.overlap_setup and len(polys) > 0:
             levels = run_levels_overlapped(ctx, plan, polys, defl, net=net if plan.learned else None)
@@ -375,6 +423,7 @@ def estimate(ctx, plan: Plan, sync=None, net=None) -> Estimate:
             levels = run_levels(ctx, plan, polys, defl, net=net if plan.learned else None)
     finally:
         ctx.set_level_solve_poly(None)
+        ctx.set_solve_level_deflation(0)
     sync()
     t2 = time.perf_counter()
     est, se = combine(levels)
@@ -392,17 +441,19 @@ def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_e
     defl, polys, tnet, _ = build_setup(ctx, plan, train=plan.learned and net is None)
     net = tnet if tnet is not None else net
     t_setup = time.perf_counter() - t0
-    nterms = len(polys) + 1
+    nterms = len(polys) + (0 if plan.probe_last and polys else 1)
     target = eps / math.sqrt(nterms)
     levels = []
     uppers = [None] + polys
     lowers = polys + [None]
     pp = solve_preconditioner(ctx, plan, defl) if not plan.learned else None
     ctx.set_level_solve_poly(pp)
+    ctx.set_solve_level_deflation(solve_level_deflated(polys, defl))
     try:
         _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, check_every, max_noises, levels)
     finally:
         ctx.set_level_solve_poly(None)
+        ctx.set_solve_level_deflation(0)
     est, se = combine(levels)
     return Estimate(est, se, levels, t_setup, time.perf_counter() - t0, total_mvps(ctx) - mv0, polys=polys,
                     defl_k=defl.k if defl is not None else 0)
@@ -410,6 +461,9 @@ def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_e
 
 def _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, check_every, max_noises, levels):
     for l, (up, lo) in enumerate(zip(uppers, lowers)):
+        if plan.probe_last and up is not None and lo is None:
+            levels.append(probe_term(ctx, plan, up, "term %d" % l))
+            continue
         d = defl if (up is not None and lo is not None and plan.deflate_levels) else (defl if up is None else None)
         n0 = min_counts[min(l, len(min_counts) - 1)]
         step = check_every if isinstance(check_every, int) else check_every[min(l, len(check_every) - 1)]
@@ -469,12 +523,16 @@ def estimate_optimized(ctx, plan: Plan, eps: float, pilot: int = 16, min_counts=
     t_setup = time.perf_counter() - t0
     uppers = [None] + polys
     lowers = polys + [None]
+    probed = plan.probe_last and len(polys) > 0   # the last term is then exact, outside the allocation
     terms = []
     for l, (up, lo) in enumerate(zip(uppers, lowers)):
+        if probed and lo is None:
+            continue
         d = defl if (up is not None and lo is not None and plan.deflate_levels) else (defl if up is None else None)
         terms.append((up, lo, d))
     pp = solve_preconditioner(ctx, plan, defl) if not plan.learned else None
     ctx.set_level_solve_poly(pp)
+    ctx.set_solve_level_deflation(solve_level_deflated(polys, defl))
 
     def run(l, first, count):
         up, lo, d = terms[l]
@@ -502,8 +560,11 @@ def estimate_optimized(ctx, plan: Plan, eps: float, pilot: int = 16, min_counts=
             if not grew:
                 break
         levels = [LevelResult("term %d" % l, X, corr, m, secs) for l, (X, corr, m, secs) in enumerate(st)]
+        if probed:
+            levels.append(probe_term(ctx, plan, polys[-1], "term %d" % len(polys)))
     finally:
         ctx.set_level_solve_poly(None)
+        ctx.set_solve_level_deflation(0)
     est, se = combine(levels)
     return (Estimate(est, se, levels, t_setup, time.perf_counter() - t0, total_mvps(ctx) - mv0, polys=polys,
                      defl_k=defl.k if defl is not None else 0), [L.n for L in levels], predicted)

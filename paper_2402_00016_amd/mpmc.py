@@ -83,6 +83,10 @@ _SIGS = {
     "mpmc_solve_pp": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
     "mpmc_set_level_solve_poly": ([_vp, _vp], _i),
     "mpmc_set_dense_method": ([_vp, _i], _i),
+    "mpmc_set_solve_level_deflation": ([_vp, _i], _i),
+    "mpmc_set_site_order": ([_vp, _vp], _i),
+    "mpmc_probe_colouring": ([_pi, _i, _pi, _pi, _pi, ctypes.POINTER(ctypes.c_long)], _i),
+    "mpmc_poly_trace_probe": ([_vp, _vp, _i, _i, _i, _vp, ctypes.POINTER(ctypes.c_long), _pu64], _i),
     "mpmc_solve_pairs": ([_vp, _vp, _vp, _i, _vp, _i, _d, _i, _i, _vp, _vp, _i, _pi, _pi, _vp], _i),
     "mpmc_level_estimate": ([_vp, _vp, _vp, _vp, _i, _u64, _u32, _u64, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp,
                              _pu64], _i),
@@ -228,6 +232,25 @@ def mpmc_poly_trace(ctx, poly, theta, period, prec, max_batch=0):
     return complex(tr[0]), bool(exact.value), mvps.value
 
 
+def mpmc_probe_colouring(dims, distance):
+    """(k, moduli[k], W[k][4], number of colours) of the distance colouring (host only)."""
+    d = (ctypes.c_int * 4)(*[int(v) for v in dims])
+    k, m, W, nc = ctypes.c_int(), (ctypes.c_int * 4)(), (ctypes.c_int * 16)(), ctypes.c_long()
+    rc = _L.mpmc_probe_colouring(d, int(distance), ctypes.byref(k), m, W, ctypes.byref(nc))
+    if rc != OK:
+        raise MpmcError(rc, "mpmc_probe_colouring: bad argument")
+    kk = k.value
+    return kk, list(m)[:kk], [list(W)[4 * i:4 * i + 4] for i in range(kk)], nc.value
+
+
+def mpmc_poly_trace_probe(ctx, poly, theta, prec, max_batch=0):
+    tr = np.zeros(1, dtype=np.complex128)
+    npr, mvps = ctypes.c_long(), ctypes.c_uint64()
+    _check(_L.mpmc_poly_trace_probe(ctx, _h(poly), int(theta), int(prec), int(max_batch), tr.ctypes.data,
+                                    ctypes.byref(npr), ctypes.byref(mvps)), ctx)
+    return complex(tr[0]), npr.value, mvps.value
+
+
 def mpmc_deflate(ctx, p_in, seed, stream, m, nev, accept_tol=1e-3, real_tol=2e-4):
     out, k = _vp(), ctypes.c_int()
     _check(_L.mpmc_deflate(ctx, _h(p_in), int(seed), int(stream), int(m), int(nev), float(accept_tol),
@@ -280,6 +303,18 @@ def mpmc_solve_pp(ctx, b, x, nrhs, defl, pp, restart=50, tol=1e-8, inner_prec=FP
 
 def mpmc_set_level_solve_poly(ctx, pp):
     _check(_L.mpmc_set_level_solve_poly(ctx, _h(pp)), ctx)
+
+
+def mpmc_set_site_order(ctx, order):
+    if order is None:
+        _check(_L.mpmc_set_site_order(ctx, None), ctx)
+        return
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    _check(_L.mpmc_set_site_order(ctx, o.ctypes.data), ctx)
+
+
+def mpmc_set_solve_level_deflation(ctx, on):
+    _check(_L.mpmc_set_solve_level_deflation(ctx, int(on)), ctx)
 
 
 def mpmc_set_dense_method(ctx, method):
@@ -431,6 +466,7 @@ class Poly(_Handle):
         self.inner = inner
         self.d_eff = d_eff
         self.relres = relres
+        self.deflated = False      # outer cycle built with a deflation set
 
     @property
     def roots(self):
@@ -567,7 +603,9 @@ class Context:
     # polynomials
     def gmres_poly(self, seed, stream, d, inner=None, defl=None):
         h, de, rr = mpmc_gmres_poly(self.handle, inner, defl, seed, stream, d)
-        return Poly(h, (self, inner, defl), inner=inner, d_eff=de, relres=rr)
+        P = Poly(h, (self, inner, defl), inner=inner, d_eff=de, relres=rr)
+        P.deflated = defl is not None and defl.k > 0
+        return P
 
     def poly_from_roots(self, roots, inner=None):
         return Poly(mpmc_poly_create(self.handle, roots, inner), (self, inner), inner=inner)
@@ -583,6 +621,11 @@ class Context:
         return mpmc_poly_trace(self.handle, poly, theta, period, prec, max_batch)
 
     # deflation
+    def poly_trace_probe(self, poly, theta=THETA_I, prec=FP64, max_batch=0):
+        """Exact Tr(Theta p(M)) with the distance-(deg p + 1) colouring:
+        (trace, probe vectors, MVPs)."""
+        return mpmc_poly_trace_probe(self.handle, poly, theta, prec, max_batch)
+
     def deflate(self, p_in, seed, stream, m, nev, accept_tol=1e-3, real_tol=2e-4):
         h, k = mpmc_deflate(self.handle, p_in, seed, stream, m, nev, accept_tol, real_tol)
         return Defl(h, (self, p_in), k)
@@ -626,6 +669,14 @@ class Context:
     def set_dense_method(self, method):
         """Small eigenproblems: DENSE_ABERTH (default, QR fallback) or DENSE_QR."""
         mpmc_set_dense_method(self.handle, method)
+
+    def set_site_order(self, order):
+        """Traversal order of the blocked Wilson kernels (None: the default)."""
+        mpmc_set_site_order(self.handle, order)
+
+    def set_solve_level_deflation(self, on):
+        """Deflate the solve level M^-1 - p_1 of level estimates (for a deflated p_1)."""
+        mpmc_set_solve_level_deflation(self.handle, on)
 
     def set_level_solve_poly(self, pp):
         """Polynomial preconditioner of the main solves inside level estimates (None: none)."""

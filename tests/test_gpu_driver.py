@@ -89,3 +89,53 @@ def test_multilevel_estimate_within_3_sigma_of_dense_exact(ctx, poly_prec, solve
     assert 0 < e.stderr < np.inf
     assert abs(e.value - exact) < 3 * e.stderr
     assert e.levels[0].var < 1e-3 * e.levels[-1].var
+
+
+@pytest.fixture(scope="module")
+def dense44():
+    from oracle import lattice as OLT
+    dims, kappa = (4, 4, 4, 4), 0.115
+    U = inputs.gauge_links(dims, 0.5, seed=1)
+    return np.linalg.inv(OLT.dense_wilson(dims, kappa, U))
+
+
+def test_probed_last_term_estimate(ctx, dense44):
+    """Sec. 6 with the last term by probing: the probed term equals the dense
+    Tr p_K(M) of the GPU's own roots, carries no variance, and the estimate is
+    within 3 standard errors of the dense Tr M^-1 with a far smaller error than
+    the all-sampled estimate."""
+    from oracle import poly as OP
+    from oracle.wilson import WilsonOp
+    dims, kappa = (4, 4, 4, 4), 0.115
+    op = WilsonOp(dims, kappa, inputs.gauge_links(dims, 0.5, seed=1))
+    e_s = driver.estimate(ctx, plan(noises=64, seed=11), torch.cuda.synchronize)
+    e_p = driver.estimate(ctx, plan(noises=64, seed=11, probe_last=True), torch.cuda.synchronize)
+    last = e_p.levels[-1]
+    assert last.exact and last.var == 0.0 and "probed" in last.name
+    Pm = OP.apply_p(op, e_p.polys[-1].roots, np.eye(op.n)).T
+    assert abs(last.mean - np.trace(Pm)) < 1e-9 * abs(np.trace(Pm))
+    exact = np.trace(dense44)
+    assert 0 < e_p.stderr < 0.1 * e_s.stderr
+    assert abs(e_p.value - exact) < 3 * e_p.stderr + 1e-9 * abs(exact)
+    for L0, L1 in zip(e_s.levels[:-1], e_p.levels[:-1]):
+        assert np.array_equal(L0.samples, L1.samples)
+
+
+@pytest.mark.parametrize("probe", [False, True])
+def test_estimate_to_error_stops_at_target(ctx, dense44, probe):
+    """Sec. 8's adaptive stopping: every sampled term stops once its standard
+    error is at most eps / sqrt(#sampled terms) (or at the noise cap), the
+    minimum counts 2 / 3 / 6 hold, counts grow in steps of check_every, and the
+    estimate is within 3 standard errors of the dense trace."""
+    eps = 1.0
+    p = plan(seed=5, probe_last=probe)
+    e = driver.estimate_to_error(ctx, p, eps, check_every=3, max_noises=4096)
+    sampled = [L for L in e.levels if not L.exact]
+    target = eps / np.sqrt(len(sampled))
+    for l, L in enumerate(sampled):
+        assert L.n >= (2, 3, 6)[min(l, 2)]
+        assert (L.n - (2, 3, 6)[min(l, 2)]) % 3 == 0
+        assert np.sqrt(L.var / L.n) <= target or L.n >= 4096
+    assert e.stderr <= eps * 1.0000001
+    assert len(e.levels) == 3 and (e.levels[-1].exact == probe)
+    assert abs(e.value - np.trace(dense44)) < 3 * max(e.stderr, 1e-9)

@@ -494,6 +494,45 @@ def test_poly_trace_probing_exact(f44):
     assert not exact3
 
 
+@pytest.mark.parametrize("d", [4, 9])
+def test_poly_trace_distance_colouring_exact(f44, d):
+    """Exact Tr(Theta p(M)) with the distance-(deg + 1) colouring (Sec. 6)
+    against the oracle's dense trace, FP64 and FP32 (FP64 sums)."""
+    dims, kappa, U, op, ctx = f44
+    P, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), d)
+    Pm = OP.apply_p(op, P.roots, np.eye(op.n)).T
+    g = ctx.poly_from_roots(P.roots)
+    k, m, W, nc = mpmc.mpmc_probe_colouring(dims, d - 1)
+    for theta, th in (("I", 0), ("g5", 1)):
+        G = np.kron(np.eye(OLT.volume(dims)), np.kron(OLT.theta_matrix(theta), np.eye(3)))
+        ref = np.trace(G @ Pm)
+        tr, nprobe, mv = ctx.poly_trace_probe(g, theta=th, prec=FP64, max_batch=96)
+        assert nprobe == 12 * nc and mv == nprobe * (d - 1)
+        assert abs(tr - ref) < 1e-10 * max(1.0, abs(ref))
+        tr32, _, _ = ctx.poly_trace_probe(g, theta=th, prec=FP32)
+        assert abs(tr32 - ref) < 1e-5 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("d", [5, 9])
+def test_poly_trace_probe_vs_sampled_8x4(d):
+    """8^4, degrees 4 and 8: the probed trace agrees with a 256-noise
+    Hutchinson estimate of the same term within 3.5 standard errors.  Degree
+    4 takes a 64-colour code (768 probes); for degree 8 the 8^4 torus admits
+    no code of at most 512 colours, so every site is its own colour."""
+    dims, kappa = (8, 8, 8, 8), 0.12
+    U = inputs.gauge_links(dims, 0.5, seed=2)
+    ctx = mpmc.Context(dims, kappa, U)
+    g = ctx.gmres_poly(2, 0x103, d)
+    tr, nprobe, mv = ctx.poly_trace_probe(g, prec=FP32)
+    X, T, _ = ctx.level(g, None, None, 0, 2, 3, 0, 256, prec=FP64)
+    m, v = OES.level_stats(X)
+    assert abs(tr - m) < 3.5 * np.sqrt(v / 256)
+    k, mods, W, nc = mpmc.mpmc_probe_colouring(dims, d - 1)
+    assert nprobe == 12 * nc and mv == nprobe * (d - 1)
+    if d == 5:
+        assert nc == 64
+
+
 # ------------------------------------------------------------- autotuner --
 
 @pytest.mark.parametrize("prec", [FP64, FP32, FP16S])
@@ -684,3 +723,75 @@ def test_add_roots_high_degree_gmres_poly():
     xh = z4_noise(3, 2, 0, op.n)
     pi_ref = OP.apply_pi(op, ref, xh)
     assert rel(xh - op(y), pi_ref) < 1e-8 * max(1.0, np.linalg.norm(xh) / max(np.linalg.norm(pi_ref), 1e-300))
+
+
+# ---------------------------------------------- deflated double polynomial --
+
+@pytest.fixture(scope="module")
+def f44c():
+    """4^4 field at kappa 0.2 (small eigenvalues) with an oracle deflation set
+    imported to the GPU."""
+    dims, kappa = (4, 4, 4, 4), 0.2
+    U = inputs.gauge_links(dims, 0.5, seed=21)
+    op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    Pin4, _, _ = OK.gmres_poly(op, z4_noise(1, 0x1FF, 0, op.n), 5)
+    Dref, _ = ODF.pp_arnoldi_eigs(op, Pin4.roots, z4_noise(1, 0x200, 0, op.n), 80, 12)
+    assert Dref.k >= 6
+    D = ctx.defl_from_arrays(Dref.lam, torch.from_numpy(Dref.Z).cuda(), torch.from_numpy(Dref.U).cuda())
+    return op, ctx, Dref, D
+
+
+@pytest.mark.parametrize("din,dout", [(5, 4), (16, 16)])
+def test_deflated_double_poly_parity(f44c, din, dout):
+    """mpmc_gmres_poly(inner, defl) (Sec. 7: the deflated double polynomial)
+    against the oracle's projected outer cycle on Q phi_in from Q b, with the
+    same imported deflation set: inner and outer roots, relres, and the
+    GMRES residual identity under the oracle operator with the GPU's roots."""
+    op, ctx, Dref, D = f44c
+    b = z4_noise(1, 0x100, 0, op.n)
+    Q = OP.projector(Dref.Z, Dref.U)
+    ref, (di, do), (ri, ro) = OP.double_poly(op, b, din, dout, proj=Q)
+    Pin = ctx.gmres_poly(1, 0x100, din)
+    Pd = ctx.gmres_poly(1, 0x100, dout, inner=Pin, defl=D)
+    assert Pd.d_eff == do == dout
+    scale = np.max(np.abs(ref.roots))
+    assert _match_sets(Pin.roots, ref.inner.roots) < 1e-9 * np.max(np.abs(ref.inner.roots))
+    assert _match_sets(Pd.roots, ref.roots) < 1e-8 * scale
+    assert abs(Pd.relres - ro) < 1e-8 * ro
+    assert Pd.info["degree"] == din * dout - 1
+    # with the GPU's own roots: ||pi_out(Q phi_in) Q b|| / ||Q b|| is the reported relres
+    phi = OP.phi(op, Pin.roots)
+    c = Q(b)
+    r = OP.apply_pi(lambda v: Q(phi(v)), Pd.roots, c)
+    assert abs(np.linalg.norm(r) / np.linalg.norm(c) - Pd.relres) < 1e-9 * Pd.relres
+    # the undeflated outer cycle is a different polynomial
+    Pu = ctx.gmres_poly(1, 0x100, dout, inner=Pin)
+    assert _match_sets(Pu.roots, Pd.roots) > 1e-6 * scale
+
+
+def test_deflated_solve_level_parity(f44c):
+    """Solve level with mpmc_set_solve_level_deflation(1): per-sample values
+    and the exact correction against the oracle's deflated solve level, for a
+    deflated double polynomial p_1 (imported roots), Theta = I and g5."""
+    op, ctx, Dref, D = f44c
+    b = z4_noise(1, 0x100, 0, op.n)
+    ref, _, _ = OP.double_poly(op, b, 5, 4, proj=OP.projector(Dref.Z, Dref.U))
+    gi = ctx.poly_from_roots(ref.inner.roots)
+    gd = ctx.poly_from_roots(ref.roots, inner=gi)
+    N = 6
+    ctx.set_solve_level_deflation(1)
+    try:
+        for theta, th in (("I", 0), ("g5", 1)):
+            X, T, _ = ctx.level(None, gd, D, th, 3, 0, 0, N, solve_tol=1e-12, solve_restart=30)
+            Xr, Tr = OES.level_samples(op, None, ref, Dref, theta, 3, 0, 0, N, solve_tol=1e-12, deflate_solve=True)
+            # solves to 1e-12 on both sides: |eta^H (x - x*)| <= n ||M^-1|| 1e-12 per
+            # side, ||M^-1|| = 11.3 on this field (smallest singular value, dense)
+            assert np.max(np.abs(X - Xr)) < 2 * op.n * 12 * 1e-12
+            assert abs(T - Tr) < 1e-10 * max(1, abs(Tr))
+            assert abs(Tr) > 0
+    finally:
+        ctx.set_solve_level_deflation(0)
+    X0, T0, _ = ctx.level(None, gd, D, 0, 3, 0, 0, N, solve_tol=1e-12, solve_restart=30)
+    assert T0 == 0
+    with pytest.raises(mpmc.MpmcError):
+        ctx.set_solve_level_deflation(2)
