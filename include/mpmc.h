@@ -406,6 +406,17 @@ int mpmc_solve_pp(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_de
  * the Leja ordering.  Returns MPMC_EINVAL for another method. */
 int mpmc_set_dense_method(mpmc_ctx *ctx, int method);
 
+/* Storage precision of the single-vector Arnoldi cycles behind
+ * mpmc_gmres_poly (Sec. 3, Sec. 5) and mpmc_deflate (Sec. 7): MPMC_FP64 (the
+ * default) or MPMC_FP32 (vectors and operator applications in FP32, every
+ * inner product, the Hessenberg matrix, the harmonic Ritz / Ritz values, Leja
+ * ordering, the Ritz vectors, Rayleigh quotients and acceptance residuals in
+ * FP64).  FP32 halves the traffic of the setup; the polynomials then differ
+ * from the FP64 ones at the level of FP32 rounding, which leaves the
+ * multipolynomial estimate unbiased (any polynomials telescope).  EINVAL for
+ * another precision. */
+int mpmc_set_setup_precision(mpmc_ctx *ctx, int prec);
+
 /* Polynomial preconditioner used by the main solves inside mpmc_level_estimate
  * when no network is given (NULL: none, the default).  The context keeps the
  * pointer: the caller keeps pp alive while it is set. */

@@ -564,13 +564,18 @@ int blas_norm2(mpmc_ctx *ctx, const void *x, int nrhs, int prec, double *out_dev
 }
 
 int blas_arnoldi_update(mpmc_ctx *ctx, const void *V, long vstride, int nv, void *w, const double *h2, double *Hcol,
-                        int j, double *state, double *scale) {
+                        int j, double *state, double *scale, int prec) {
     const int NB = nb_single(ctx, ctx->n, 1);
     double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)NB * sizeof(double2));
     if (!part) return MPMC_ENOMEM;
-    k_multiaxpy1<MPMC_FP64><<<NB, 256, 0, ctx->stream>>>(vref(ctx, V, 1, MPMC_FP64), vstride, nv,
-                                                         vref(ctx, w, 1, MPMC_FP64), ctx->n, (const double2 *)h2, 1,
-                                                         -1.0, part, NB);
+    if (prec == MPMC_FP64)
+        k_multiaxpy1<MPMC_FP64><<<NB, 256, 0, ctx->stream>>>(vref(ctx, V, 1, prec), vstride, nv, vref(ctx, w, 1, prec),
+                                                             ctx->n, (const double2 *)h2, 1, -1.0, part, NB);
+    else if (prec == MPMC_FP32)
+        k_multiaxpy1<MPMC_FP32><<<NB, 256, 0, ctx->stream>>>(vref(ctx, V, 1, prec), vstride, nv, vref(ctx, w, 1, prec),
+                                                             ctx->n, (const double2 *)h2, 1, -1.0, part, NB);
+    else
+        return set_err(ctx, MPMC_EINVAL, "Arnoldi vectors are FP64 or FP32");
     HIP_OR_RET(ctx, hipGetLastError());
     k_arnoldi_finish<<<1, 256, 0, ctx->stream>>>(part, NB, (double2 *)Hcol, (const double2 *)h2, j, state,
                                                  (double2 *)scale);

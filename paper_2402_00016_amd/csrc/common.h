@@ -60,6 +60,8 @@ struct mpmc_ctx {
     int dense_qr_only = 0;
     // deflate the solve level M^-1 - p_1 of mpmc_level_estimate (mpmc_set_solve_level_deflation)
     int solve_level_defl = 0;
+    // storage precision of the single-vector Arnoldi cycles (mpmc_gmres_poly, mpmc_deflate)
+    int setup_prec = MPMC_FP64;
     // distance colourings of mpmc_poly_trace_probe by polynomial degree: k, m[4], W[4][4]
     std::map<int, std::vector<int>> colourings;
 };
@@ -313,7 +315,7 @@ int blas_multi_axpy_dot(mpmc_ctx *ctx, const void *Vb, long vstride, int nv, voi
 // running Frobenius norm in state[0] (state[1] = d_eff or -1), and scale[0] =
 // 1 / h_{j+1,j} (0 after a breakdown).  Two launches.
 int blas_arnoldi_update(mpmc_ctx *ctx, const void *V, long vstride, int nv, void *w, const double *h2, double *Hcol,
-                        int j, double *state, double *scale);
+                        int j, double *state, double *scale, int prec);
 // FP16S Krylov bases (nrhs-wide FP16S batches spaced vstride_b bytes apart)
 // against FP32 working vectors
 int blas_multi_dot_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, const void *w, int nrhs,
@@ -382,6 +384,7 @@ int defl_coeffs(mpmc_ctx *ctx, const mpmc_defl *d, const void *x, int nrhs, doub
 int defl_add(mpmc_ctx *ctx, const mpmc_defl *d, const double *c_dev, void *x, int nrhs, double sign);
 //   x <- (I - Z U^H) x
 int defl_project(mpmc_ctx *ctx, const mpmc_defl *d, void *x, int nrhs);
+int project_any(mpmc_ctx *ctx, const mpmc_defl *d, void *x, int prec);   // one vector in FP64 or FP32
 
 // net.hip: y = N(x) for FP32 internal-layout batches (learned preconditioner)
 int net_apply_internal(mpmc_ctx *ctx, const mpmc_net *net, const void *x, void *y, int nrhs);

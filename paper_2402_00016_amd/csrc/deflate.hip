@@ -43,6 +43,17 @@ int defl_add(mpmc_ctx *ctx, const mpmc_defl *d, const double *c_dev, void *x, in
     return blas_multi_axpy(ctx, d->Z, ctx->n, 1, d->k, x, nrhs, MPMC_FP64, c_dev, nrhs, sign, nullptr);
 }
 
+// Q x for one vector stored in prec (FP64 directly; FP32 through an FP64 copy).
+int project_any(mpmc_ctx *ctx, const mpmc_defl *d, void *x, int prec) {
+    if (prec == MPMC_FP64) return defl_project(ctx, d, x, 1);
+    Scratch S(ctx);
+    void *t = S.get(vec_bytes(ctx, 1, MPMC_FP64));
+    if (!t) return MPMC_ENOMEM;
+    RET_IF(blas_convert(ctx, x, prec, t, MPMC_FP64, 1));
+    RET_IF(defl_project(ctx, d, t, 1));
+    return blas_convert(ctx, t, MPMC_FP64, x, prec, 1);
+}
+
 int defl_project(mpmc_ctx *ctx, const mpmc_defl *d, void *x, int nrhs) {
     Scratch S(ctx);
     double *c = (double *)S.get(sizeof(double2) * (size_t)d->k * nrhs);
@@ -116,7 +127,8 @@ MPMC_API int mpmc_defl_export(const mpmc_defl *d, double *lam_host, void *Z, voi
     return MPMC_OK;
 }
 
-int arnoldi_run_ext(mpmc_ctx *ctx, const mpmc_poly *inner, double *V, double *H, int d, double *state, Scratch &S);
+int arnoldi_run_ext(mpmc_ctx *ctx, const mpmc_poly *inner, void *V, double *H, int d, double *state, Scratch &S,
+                    int prec);
 
 MPMC_API int mpmc_deflate(mpmc_ctx *ctx, const mpmc_poly *p_in, uint64_t seed, uint32_t stream, int m, int nev,
                           double accept_tol, double real_tol, mpmc_defl **out, int *k_out) {
@@ -129,14 +141,15 @@ MPMC_API int mpmc_deflate(mpmc_ctx *ctx, const mpmc_poly *p_in, uint64_t seed, u
     Scratch S(ctx);
     const long n = ctx->n;
     const size_t vb = sizeof(double2) * (size_t)n;
-    double *V = (double *)S.get(vb * (m + 1));
+    const int bprec = ctx->setup_prec;   // storage of the Arnoldi basis; Ritz vectors are FP64
+    void *V = S.get(vec_bytes(ctx, 1, bprec) * (size_t)(m + 1));
     double *H = (double *)S.get(sizeof(double2) * (size_t)(m + 1) * m);
     double *state = (double *)S.get(sizeof(double) * 8);
     double *mu = (double *)S.get(sizeof(double2) * (m + 2));
     double *info = (double *)S.get(sizeof(double) * 4);
     if (!V || !H || !state || !mu || !info) return MPMC_ENOMEM;
-    RET_IF(launch_noise(ctx, seed, stream, 0, 1, MPMC_FP64, V));
-    RET_IF(arnoldi_run_ext(ctx, p_in, V, H, m, state, S));
+    RET_IF(launch_noise(ctx, seed, stream, 0, 1, bprec, V));
+    RET_IF(arnoldi_run_ext(ctx, p_in, V, H, m, state, S, bprec));
     double hs[3];
     HIP_OR_RET(ctx, hipMemcpyAsync(hs, state, sizeof hs, hipMemcpyDeviceToHost, ctx->stream));
     HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
@@ -167,7 +180,8 @@ MPMC_API int mpmc_deflate(mpmc_ctx *ctx, const mpmc_poly *p_in, uint64_t seed, u
     double *MZ = (double *)S.get(vb * ns);
     double *tmp = (double *)S.get(vb);
     double *scal = (double *)S.get(sizeof(double2) * 8);
-    if (!mus || !Y || !Zc || !MZ || !tmp || !scal) return MPMC_ENOMEM;
+    void *z32 = bprec == MPMC_FP64 ? nullptr : S.get(vec_bytes(ctx, 1, bprec));
+    if (!mus || !Y || !Zc || !MZ || !tmp || !scal || (bprec != MPMC_FP64 && !z32)) return MPMC_ENOMEM;
     HIP_OR_RET(ctx, hipMemcpyAsync(mus, musel.data(), sizeof(double2) * ns, hipMemcpyHostToDevice, ctx->stream));
     RET_IF(dense_inverse_iteration(ctx, H, m + 1, me, mus, ns, Y));
 
@@ -176,8 +190,15 @@ MPMC_API int mpmc_deflate(mpmc_ctx *ctx, const mpmc_poly *p_in, uint64_t seed, u
     std::vector<double> rres(ns);
     for (int q = 0; q < ns; ++q) {
         double *z = Zc + 2 * (size_t)q * n, *mz = MZ + 2 * (size_t)q * n;
-        HIP_OR_RET(ctx, hipMemsetAsync(z, 0, vb, ctx->stream));
-        RET_IF(blas_multi_axpy(ctx, V, n, 1, me, z, 1, MPMC_FP64, Y + 2 * (size_t)q * me, 1, 1.0, nullptr));
+        if (bprec == MPMC_FP64) {
+            HIP_OR_RET(ctx, hipMemsetAsync(z, 0, vb, ctx->stream));
+            RET_IF(blas_multi_axpy(ctx, V, n, 1, me, z, 1, MPMC_FP64, Y + 2 * (size_t)q * me, 1, 1.0, nullptr));
+        } else {
+            // z = V y in the basis precision (FP64 coefficients), then widened
+            HIP_OR_RET(ctx, hipMemsetAsync(z32, 0, vec_bytes(ctx, 1, bprec), ctx->stream));
+            RET_IF(blas_multi_axpy(ctx, V, n, 1, me, z32, 1, bprec, Y + 2 * (size_t)q * me, 1, 1.0, nullptr));
+            RET_IF(blas_convert(ctx, z32, bprec, z, MPMC_FP64, 1));
+        }
         RET_IF(blas_norm2(ctx, z, 1, MPMC_FP64, scal));
         RET_IF(blas_scale_rhs(ctx, z, z, 1, MPMC_FP64, scal, 1));
         RET_IF(wilson_launch_full(ctx, z, nullptr, mz, nullptr, 1, MPMC_FP64, make_double2(0, 0), make_double2(1, 0),

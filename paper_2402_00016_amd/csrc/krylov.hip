@@ -28,51 +28,53 @@ __global__ void k_arnoldi_init(double *state, double2 *scale, const double2 *nrm
 struct OpDesc {
     const mpmc_poly *inner;   // nullptr: M; else phi_in(M) = M p_in(M)
     const mpmc_defl *defl;    // project each new vector with Q = I - Z U^H
+    int prec;                 // storage of the Arnoldi vectors (FP64 or FP32; scalars are FP64)
 };
 
 static int apply_op(mpmc_ctx *ctx, const OpDesc &op, const void *x, void *y) {
     Scratch S(ctx);
     if (!op.inner) {
-        RET_IF(wilson_launch_full(ctx, x, nullptr, y, nullptr, 1, MPMC_FP64, make_double2(0, 0),
+        RET_IF(wilson_launch_full(ctx, x, nullptr, y, nullptr, 1, op.prec, make_double2(0, 0),
                                   make_double2(1, 0), make_double2(0, 0), 0, 0));
     } else {
-        void *t = S.get(vec_bytes(ctx, 1, MPMC_FP64));
+        void *t = S.get(vec_bytes(ctx, 1, op.prec));
         if (!t) return MPMC_ENOMEM;
-        RET_IF(poly_apply_internal(ctx, op.inner, x, t, 1, MPMC_FP64));
-        RET_IF(wilson_launch_full(ctx, t, nullptr, y, nullptr, 1, MPMC_FP64, make_double2(0, 0),
+        RET_IF(poly_apply_internal(ctx, op.inner, x, t, 1, op.prec));
+        RET_IF(wilson_launch_full(ctx, t, nullptr, y, nullptr, 1, op.prec, make_double2(0, 0),
                                   make_double2(1, 0), make_double2(0, 0), 0, 0));
     }
-    if (op.defl) RET_IF(defl_project(ctx, op.defl, y, 1));
+    if (op.defl) RET_IF(project_any(ctx, op.defl, y, op.prec));
     return MPMC_OK;
 }
 
-// d Arnoldi steps (FP64, one rhs) from b (overwritten by v_0).  V: (d+1) vectors
-// of n complex doubles, H: column-major (d+1) x d, ld = d+1.  state (device):
-// [0] ||H||_F^2, [1] d_eff or -1, [2] ||b||.
-int arnoldi_run(mpmc_ctx *ctx, const OpDesc &op, double *V, double *H, int d, double *state, Scratch &S) {
+// d Arnoldi steps (one rhs) from b (overwritten by v_0), vectors stored in
+// op.prec.  V: (d+1) vectors of n complex elements, H: column-major (d+1) x d
+// FP64, ld = d+1.  state (device): [0] ||H||_F^2, [1] d_eff or -1, [2] ||b||.
+int arnoldi_run(mpmc_ctx *ctx, const OpDesc &op, void *V, double *H, int d, double *state, Scratch &S) {
     const long n = ctx->n;
+    const size_t vstep = vec_bytes(ctx, 1, op.prec);
     double2 *sc = (double2 *)S.get(sizeof(double2) * (d + 8));
     double2 *h2 = (double2 *)S.get(sizeof(double2) * (d + 8));
-    void *w = S.get(vec_bytes(ctx, 1, MPMC_FP64));
+    void *w = S.get(vstep);
     if (!sc || !h2 || !w) return MPMC_ENOMEM;
     HIP_OR_RET(ctx, hipMemsetAsync(H, 0, sizeof(double2) * (size_t)(d + 1) * d, ctx->stream));
-    if (op.defl) RET_IF(defl_project(ctx, op.defl, V, 1));
-    RET_IF(blas_norm2(ctx, V, 1, MPMC_FP64, (double *)sc));
+    if (op.defl) RET_IF(project_any(ctx, op.defl, V, op.prec));
+    RET_IF(blas_norm2(ctx, V, 1, op.prec, (double *)sc));
     k_arnoldi_init<<<1, 1, 0, ctx->stream>>>(state, sc + 1, sc);
     HIP_OR_RET(ctx, hipGetLastError());
-    RET_IF(blas_scale_rhs(ctx, V, V, 1, MPMC_FP64, (double *)(sc + 1), 0));
+    RET_IF(blas_scale_rhs(ctx, V, V, 1, op.prec, (double *)(sc + 1), 0));
     for (int j = 0; j < d; ++j) {
-        double *vj = V + 2 * (size_t)j * n;
-        double *vj1 = V + 2 * (size_t)(j + 1) * n;
+        void *vj = (char *)V + (size_t)j * vstep;
+        void *vj1 = (char *)V + (size_t)(j + 1) * vstep;
         double *Hcol = H + 2 * (size_t)j * (d + 1);
         RET_IF(apply_op(ctx, op, vj, w));
         // CGS pass 1: H(:, j) = V^H w ; w -= V H(:, j)
-        RET_IF(blas_multi_dot(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, Hcol, 0, 0));
-        RET_IF(blas_multi_axpy(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, Hcol, 1, -1.0, nullptr));
+        RET_IF(blas_multi_dot(ctx, V, n, 1, j + 1, w, 1, op.prec, Hcol, 0, 0));
+        RET_IF(blas_multi_axpy(ctx, V, n, 1, j + 1, w, 1, op.prec, Hcol, 1, -1.0, nullptr));
         // CGS pass 2; the norm's reduction also finishes the column (breakdown test, 1/h)
-        RET_IF(blas_multi_dot(ctx, V, n, 1, j + 1, w, 1, MPMC_FP64, (double *)h2, 0, 0));
-        RET_IF(blas_arnoldi_update(ctx, V, n, j + 1, w, (double *)h2, Hcol, j, state, (double *)(sc + 1)));
-        RET_IF(blas_scale_rhs(ctx, w, vj1, 1, MPMC_FP64, (double *)(sc + 1), 0));
+        RET_IF(blas_multi_dot(ctx, V, n, 1, j + 1, w, 1, op.prec, (double *)h2, 0, 0));
+        RET_IF(blas_arnoldi_update(ctx, V, n, j + 1, w, (double *)h2, Hcol, j, state, (double *)(sc + 1), op.prec));
+        RET_IF(blas_scale_rhs(ctx, w, vj1, 1, op.prec, (double *)(sc + 1), 0));
     }
     return MPMC_OK;
 }
@@ -204,14 +206,16 @@ MPMC_API int mpmc_gmres_poly(mpmc_ctx *ctx, const mpmc_poly *inner, const mpmc_d
     *out = nullptr;
     Scratch S(ctx);
     const long n = ctx->n;
-    double *V = (double *)S.get(sizeof(double2) * (size_t)(d + 1) * n);
+    const int prec = ctx->setup_prec;
+    void *V = S.get(vec_bytes(ctx, 1, prec) * (size_t)(d + 1));
     double *H = (double *)S.get(sizeof(double2) * (size_t)(d + 1) * d);
     double *state = (double *)S.get(sizeof(double) * 8);
     double *roots = (double *)S.get(sizeof(double2) * (d + 2));
     double *info = (double *)S.get(sizeof(double) * 4);
     if (!V || !H || !state || !roots || !info) return MPMC_ENOMEM;
-    RET_IF(launch_noise(ctx, seed, stream, 0, 1, MPMC_FP64, V));
-    OpDesc op{inner, (defl && defl->k > 0) ? defl : nullptr};
+    (void)n;
+    RET_IF(launch_noise(ctx, seed, stream, 0, 1, prec, V));
+    OpDesc op{inner, (defl && defl->k > 0) ? defl : nullptr, prec};
     RET_IF(arnoldi_run(ctx, op, V, H, d, state, S));
     double hs[3];
     HIP_OR_RET(ctx, hipMemcpyAsync(hs, state, sizeof hs, hipMemcpyDeviceToHost, ctx->stream));
@@ -318,9 +322,18 @@ MPMC_API int mpmc_apply_poly(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, v
 }
 
 // Arnoldi on M (inner == nullptr) or on phi_in(M) = M p_in(M), for the deflation build.
-int arnoldi_run_ext(mpmc_ctx *ctx, const mpmc_poly *inner, double *V, double *H, int d, double *state, Scratch &S) {
-    OpDesc op{inner, nullptr};
+int arnoldi_run_ext(mpmc_ctx *ctx, const mpmc_poly *inner, void *V, double *H, int d, double *state, Scratch &S,
+                    int prec) {
+    OpDesc op{inner, nullptr, prec};
     return arnoldi_run(ctx, op, V, H, d, state, S);
+}
+
+MPMC_API int mpmc_set_setup_precision(mpmc_ctx *ctx, int prec) {
+    if (!ctx) return MPMC_EINVAL;
+    if (prec != MPMC_FP64 && prec != MPMC_FP32)
+        return set_err(ctx, MPMC_EINVAL, "mpmc_set_setup_precision: FP64 or FP32");
+    ctx->setup_prec = prec;
+    return MPMC_OK;
 }
 
 // ------------------------------------------------- fused quadratic form --

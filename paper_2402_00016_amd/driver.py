@@ -72,6 +72,7 @@ class Plan:
                                          # (8^4: 56.5 vs 58.0 ms per estimate; both streams bandwidth-bound)
     deflate_double: bool = False         # double polynomials from a deflated outer cycle (Sec. 7); the
                                          # solve level is then deflated as well when p_1 is one of them
+    setup_prec: int = mpmc.FP64          # Arnoldi vectors of the polynomial and deflation builds (scalars FP64)
     probe_last: bool = False             # last term Tr(Theta p_K) exactly by probing (Sec. 6) instead of sampling
     probe_batch: int = 192               # probe vectors per batch
 
@@ -286,6 +287,8 @@ def build_setup(ctx, plan: Plan, train=False):
     plan.overlap_setup the polynomials and the training run on side streams
     while the deflation set is built on ctx's stream."""
     autotune_levels(ctx, plan)
+    for c in [ctx] + [c for c, _ in ctx._side.values()] + ([ctx.side("polys")[0]] if plan.overlap_setup else []):
+        c.set_setup_precision(plan.setup_prec)
     if not plan.overlap_setup:
         defl = build_deflation(ctx, plan)
         polys = build_polys(ctx, plan, defl)

@@ -85,6 +85,7 @@ _SIGS = {
     "mpmc_set_dense_method": ([_vp, _i], _i),
     "mpmc_set_solve_level_deflation": ([_vp, _i], _i),
     "mpmc_set_site_order": ([_vp, _vp], _i),
+    "mpmc_set_setup_precision": ([_vp, _i], _i),
     "mpmc_probe_colouring": ([_pi, _i, _pi, _pi, _pi, ctypes.POINTER(ctypes.c_long)], _i),
     "mpmc_poly_trace_probe": ([_vp, _vp, _i, _i, _i, _vp, ctypes.POINTER(ctypes.c_long), _pu64], _i),
     "mpmc_solve_pairs": ([_vp, _vp, _vp, _i, _vp, _i, _d, _i, _i, _vp, _vp, _i, _pi, _pi, _vp], _i),
@@ -311,6 +312,10 @@ def mpmc_set_site_order(ctx, order):
         return
     o = np.ascontiguousarray(order, dtype=np.int32)
     _check(_L.mpmc_set_site_order(ctx, o.ctypes.data), ctx)
+
+
+def mpmc_set_setup_precision(ctx, prec):
+    _check(_L.mpmc_set_setup_precision(ctx, int(prec)), ctx)
 
 
 def mpmc_set_solve_level_deflation(ctx, on):
@@ -673,6 +678,10 @@ class Context:
     def set_site_order(self, order):
         """Traversal order of the blocked Wilson kernels (None: the default)."""
         mpmc_set_site_order(self.handle, order)
+
+    def set_setup_precision(self, prec):
+        """Storage of the Arnoldi vectors of gmres_poly and deflate (FP64 or FP32)."""
+        mpmc_set_setup_precision(self.handle, prec)
 
     def set_solve_level_deflation(self, on):
         """Deflate the solve level M^-1 - p_1 of level estimates (for a deflated p_1)."""

@@ -795,3 +795,40 @@ def test_deflated_solve_level_parity(f44c):
     assert T0 == 0
     with pytest.raises(mpmc.MpmcError):
         ctx.set_solve_level_deflation(2)
+
+
+# ------------------------------------------------- FP32 setup precision --
+
+def test_fp32_setup_polynomials_and_deflation():
+    """mpmc_set_setup_precision(FP32): Arnoldi vectors in FP32, every scalar
+    in FP64.  The GMRES polynomial's roots stay within FP32 rounding of the
+    FP64 ones, its relres is the residual of its own roots under the oracle
+    operator, and the deflation set passes the same acceptance test with
+    eigenvalues matching the FP64 build."""
+    dims, kappa = (4, 4, 4, 4), 0.2
+    U = inputs.gauge_links(dims, 0.5, seed=21)
+    op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    b = z4_noise(1, 0x100, 0, op.n)
+    P64 = ctx.gmres_poly(1, 0x100, 12)
+    ctx.set_setup_precision(FP32)
+    try:
+        P32 = ctx.gmres_poly(1, 0x100, 12)
+        assert P32.d_eff == 12
+        assert _match_sets(P32.roots, P64.roots) < 1e-4 * np.max(np.abs(P64.roots))
+        r = OP.apply_pi(op, P32.roots, b)
+        assert abs(np.linalg.norm(r) / np.linalg.norm(b) - P32.relres) < 1e-4 * P32.relres + 1e-7
+        Pin = ctx.poly_from_roots(P64.roots[:5])
+        D32 = ctx.deflate(Pin, 1, 0x200, m=60, nev=10)
+        lam32, Z32, U32 = ctx.defl_vectors(D32)
+    finally:
+        ctx.set_setup_precision(FP64)
+    D64 = ctx.deflate(Pin, 1, 0x200, m=60, nev=10)
+    lam64, _, _ = ctx.defl_vectors(D64)
+    assert D32.k >= 1 and abs(D32.k - D64.k) <= 1
+    assert _match_sets(lam32, lam64) < 1e-5
+    Zh, Uh = Z32.cpu().numpy(), U32.cpu().numpy()
+    for i in range(D32.k):
+        assert abs(np.vdot(Uh[i], Zh[i]) - 1) < 1e-10
+        assert np.linalg.norm(op(Zh[i]) - lam32[i] * Zh[i]) < 1e-3
+    with pytest.raises(mpmc.MpmcError):
+        ctx.set_setup_precision(FP16S)
