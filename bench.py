@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--compare-runs", type=int, default=3,
                     help="estimates of the learned and of the plain form timed (median reported)")
     ap.add_argument("--theta", choices=["I", "g5"], default="I")
+    ap.add_argument("--probe-last", action="store_true",
+                    help="last term exactly by probing (distance colouring) in every form")
+    ap.add_argument("--no-probe-report", action="store_true",
+                    help="skip the extra estimate with the probed last term")
     ap.add_argument("--solve-pp", action="store_true",
                     help="main solves of the mixed and plain forms as polynomial-preconditioned GMRES (p_in)")
     ap.add_argument("--net-source", choices=["random", "solve"], default="solve",
@@ -192,7 +196,8 @@ def main():
                        defl_pin_degree=8, theta=mpmc.THETA[a.theta], max_batch=W["max_batch"],
                        poly_prec=mpmc.FP32, solve_inner_prec=mpmc.PREC[W.get("solve_prec", "fp32")],
                        solve_tol=1e-8, solve_restart=50, net_pairs=W["net_pairs"], solve_pp=a.solve_pp,
-                       deflate_double=W.get("deflate_double", False))
+                       deflate_double=W.get("deflate_double", False), setup_prec=mpmc.FP32,
+                       probe_last=a.probe_last)
     sync = torch.cuda.synchronize
 
     if a.calibrate_copy:
@@ -272,6 +277,8 @@ def main():
                      "traffic": measured_traffic(a.workload, dom_key),
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy)",
                      **{k: dom[k] for k in ("kernel", "launches", "avg_launch_us", "algorithmic_bytes_per_launch")}},
+        "autotuned": {"%d_%s" % (k[0], {0: "fp64", 1: "fp32", 2: "fp16s"}[k[1]]): v
+                      for k, v in getattr(ctx, "tuned", {}).items()},
         "trace": {"value": [est.value.real, est.value.imag], "stderr": est.stderr, "levels": level_report(est),
                   "deflated": est.defl_k, "setup_s": round(est.setup_seconds, 4), "mvps": est.mvps},
         "time_to_error_s": {"mixed_batched": round(step_s, 4)},
@@ -292,6 +299,17 @@ def main():
         return float(np.median(ts)), ts, last
 
     out["solve_term"] = {"mixed_batched": solve_term(est)}
+    if not a.probe_last and not a.no_probe_report:
+        # the same estimate with the last term exact by probing (Sec. 6)
+        sync()
+        tq = time.perf_counter()
+        ep = driver.estimate(ctx, driver.Plan(**{**plan.__dict__, "probe_last": True}), sync)
+        sync()
+        tq = time.perf_counter() - tq
+        Lq = ep.levels[-1]
+        out["trace"]["probed_last"] = {"value": [ep.value.real, ep.value.imag], "stderr": ep.stderr,
+                                       "s": round(tq, 4), "last_term": Lq.name, "last_term_s": round(Lq.seconds, 4),
+                                       "last_term_mvps": Lq.mvps, "mvps": ep.mvps}
     if W.get("deflate_double"):
         # the same estimate with the undeflated double polynomial: its level variances beside the deflated ones
         und = driver.estimate(ctx, driver.Plan(**{**plan.__dict__, "deflate_double": False}), sync)
@@ -326,7 +344,8 @@ def main():
     if not a.no_plain:
         ctx.release_workspace()
         torch.cuda.empty_cache()
-        plain = driver.Plan(**{**plan.__dict__, "poly_prec": mpmc.FP64, "solve_inner_prec": mpmc.FP64})
+        plain = driver.Plan(**{**plan.__dict__, "poly_prec": mpmc.FP64, "solve_inner_prec": mpmc.FP64,
+                               "setup_prec": mpmc.FP64})
         driver.estimate(ctx, plain, sync)
         tp, tps, e64 = timed_runs(lambda: driver.estimate(ctx, plain, sync), a.compare_runs)
         tt = out["time_to_error_s"]

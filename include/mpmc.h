@@ -1,8 +1,13 @@
 /*
  * mpmc.h -- C ABI of libmpmc.so: Multipolynomial Monte Carlo trace estimation
  * of Tr(Theta M^-1) for the Wilson-Dirac matrix M on one AMD Instinct MI355X
- * (gfx950).  Every compute step behind these calls is a HIP kernel of this
- * library; no call falls back to the CPU.
+ * (gfx950).  Every vector operation and every small dense eigenproblem behind
+ * these calls is a HIP kernel of this library; there is no CPU fallback.  The
+ * host code does only O(k d) scalar work: the scalar polynomial values
+ * p(lambda_i) of the deflation coefficients (mpmc_poly_eval, the level
+ * estimators), the sums of k exact-correction terms and of the per-probe
+ * values of mpmc_poly_trace*, and the selection of Ritz pairs; it also builds
+ * index tables (neighbours, traversal orders, probing colourings).
  *
  * Paper: P. Lashomb, R. B. Morgan, T. Whyte, W. Wilcox, "Multipolynomial Monte
  * Carlo Trace Estimation", Lattice 2023 (arXiv:2402.00016).  Citations below
@@ -302,27 +307,32 @@ int mpmc_apply_M_batch(mpmc_ctx *const *ctxs, const void *const *x, void *const 
 
 /* ---------------------------------------------------------------- autotuner */
 /* The multi-RHS Wilson kernel (nrhs a multiple of 64) has variants
- * 0 .. mpmc_wilson_variant_count() - 1 (currently 10) that differ only in how
+ * 0 .. mpmc_wilson_variant_count() - 1 (currently 11) that differ only in how
  * the work is laid out on the GPU, never in the arithmetic (results are
  * bit-identical):
- *   bit 0    -- occupancy target: 1 = more wavefronts per SIMD (FP32/FP16S:
+ *   0-9, bit 0 -- occupancy target: 1 = more wavefronts per SIMD (FP32/FP16S:
  *               3, FP64: 2), 0 = more registers per wavefront (FP32/FP16S: 2,
  *               FP64: 1);
- *   bits 1-3 -- traversal: 0 = site-major (a workgroup covers 256/nrhs sites
- *               x nrhs right-hand sides), 1 = 64-wide right-hand-side chunks
- *               (a workgroup covers 4 sites x 64 right-hand sides; all sites
- *               of a chunk before the next chunk), 2 = chunks as in 1 with
- *               the sites of a chunk in 4D-blocked order (blocks of extent 4
- *               along each direction whose length allows it, lexicographic
- *               inside and across blocks), 3 and 4 = blocked as in 2 with 16-
- *               and 32-wide chunks (a wavefront covers 4 or 2 sites, links
- *               loaded per lane); 3 and 4 need V % 16 == 0 and fall back to 2
- *               otherwise.
- * Defaults: variant 5 for FP32/FP16S, 4 for FP64 (blocked traversal).
+ *   0-9, bits 1-3 -- traversal: 0 = site-major (a workgroup covers 256/nrhs
+ *               sites x nrhs right-hand sides), 1 = 64-wide right-hand-side
+ *               chunks (a workgroup covers 4 sites x 64 right-hand sides; all
+ *               sites of a chunk before the next chunk), 2 = chunks as in 1 with
+ *               the sites of a chunk in the order of the site table
+ *               (mpmc_set_site_order; default 4D blocks of extent 4), 3 and 4 =
+ *               as in 2 with 16- and 32-wide chunks (a wavefront covers 4 or 2
+ *               sites, links loaded per lane; need V % 16 == 0, else 2);
+ *   10       -- column streaming (FP32, even Lx, Ly, Lz, Lt >= 4; else 5): a
+ *               workgroup of 8 wavefronts owns a 2 x 2 x 2 tile of (x, y, z)
+ *               columns and 64 right-hand sides and walks the columns along
+ *               t; the t-1 and the in-tile x, y, z neighbours come from LDS,
+ *               the t+1 site from registers, so each site's spinor is read
+ *               from memory 4 times instead of 9.
+ * Defaults: variant 10 where it applies (FP32), else 5 for FP32/FP16S and 4
+ * for FP64.
  * mpmc_autotune times every variant on (nrhs, prec) with scratch vectors of
  * the context (2 warm-up + 5 timed launches each, HIP events) and keeps the
  * fastest for all later Wilson launches on ctx with that (nrhs, prec),
- * including those inside polynomials, solves and level estimates.
+ * including those inside polynomials and solves.
  * variant_host (may be NULL) receives the choice (-1 when nrhs is not a
  * multiple of 64: nothing to tune); us_host (may be NULL) receives
  * double[mpmc_wilson_variant_count()] microseconds per launch per variant.  Does not count MVPs and
@@ -330,12 +340,41 @@ int mpmc_apply_M_batch(mpmc_ctx *const *ctxs, const void *const *x, void *const 
 int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host, double *us_host);
 /* Number of Wilson kernel variants (the length of mpmc_autotune's us_host). */
 int mpmc_wilson_variant_count(void);
-/* Pin a variant for (nrhs, prec); -1 restores the default.  The fused
- * polynomial step of mpmc_level_estimate uses the blocked traversal when the
- * site count is a multiple of 4, unless a variant is pinned here: then it
- * follows that variant's traversal bits (2-4: blocked, else site-major).  The
- * autotuner's choice does not change the fused step. */
+/* Pin a variant for (nrhs, prec); -1 restores the default.  A pinned variant
+ * also fixes the traversal of the fused polynomial step of the level
+ * estimators (variants 0-3: site-major, 4-9: blocked chunks, 10: column
+ * streaming), overriding mpmc_autotune_level. */
 int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant);
+/* Autotune the fused polynomial step of mpmc_level_estimate (the dominant
+ * kernel of the polynomial levels, Sec. 6): every traversal valid for the
+ * shape -- order 0 site-major, 2 blocked 64-wide chunks, 3 / 4 blocked 16- /
+ * 32-wide chunks (V % 16 == 0), 5 column streaming (FP32, as variant 10) --
+ * is timed on (nrhs, prec) (2 warm-up + 5 timed steps, HIP events) and the
+ * fastest is kept for later level estimates on ctx.  Without this call the
+ * step takes the column streaming kernel where it applies, else blocked
+ * 64-wide chunks (V % 4 == 0), else site-major.  prec FP64 or FP32, nrhs a
+ * multiple of 64 (and of 256 above 256).  order_host (may be NULL): the
+ * choice; us_host (may be NULL): double[6] microseconds per step by order (0
+ * for orders not tried).  Samples are the same up to the grouping of the FP64
+ * partial sums.  Does not count MVPs.  Synchronises. */
+int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_host, double *us_host);
+
+/* Captured polynomial recurrences.  on = 1: the launch sequence of each
+ * fused polynomial recurrence of the level estimators (every step of
+ * eta^H Theta p(M) eta, single and double polynomials, Sec. 3 and 5) is
+ * captured once into a hipGraph on a stream the context creates (default
+ * priority) and replayed from then on; the replay is ordered after the
+ * earlier and before the later work of the context stream.  The key of a
+ * captured graph is every input of its launches (operand and work-buffer
+ * addresses, shape, precision, Theta, traversal, roots), so results are
+ * bit-identical to the launches run one by one.  Launch timing
+ * (mpmc_timing_enable) switches replay off while it is on.  Graphs are
+ * dropped by mpmc_release_workspace, when a work buffer grows and by
+ * mpmc_destroy.  on = 0 (default): launches one by one.  EINVAL unless on is
+ * 0 or 1; EHIP if the stream or events cannot be created. */
+int mpmc_set_graph_recurrences(mpmc_ctx *ctx, int on);
+/* Replays of captured recurrences since creation and graphs held (host, may be NULL). */
+int mpmc_graph_replays(const mpmc_ctx *ctx, uint64_t *replays_host, int *graphs_host);
 
 /* Traversal order of the blocked multi-RHS Wilson kernels (variants 4-9 and
  * the fused level step): order_host[i] is the i-th site visited (int[V], a
@@ -474,8 +513,11 @@ int mpmc_set_solve_level_deflation(mpmc_ctx *ctx, int on);
 /* The polynomial levels of the multipolynomial formula (Sec. 6) together:
  * term t has the samples, correction and precision semantics of
  * mpmc_level_estimate(ctx, upper[t], lower[t], defl, theta, seed, streams[t],
- * first, nnoise, prec, 0, ...) -- bit for bit -- with upper[t] != NULL (the
- * solve term stays with mpmc_level_estimate) and lower[t] possibly NULL.
+ * first, nnoise, prec, 0, ...) -- bit for bit when that call's fused step
+ * takes the blocked 64-wide traversal (variants 4/5 pinned with
+ * mpmc_tune_set), else up to the grouping of the FP64 partial sums -- with
+ * upper[t] != NULL (the solve term stays with mpmc_level_estimate) and
+ * lower[t] possibly NULL.
  * Every single-polynomial recurrence of the batch (the upper and the lower
  * polynomial of each term, on that term's noise) occupies its own run of
  * nnoise right-hand sides of one operand, runs ordered by decreasing degree,

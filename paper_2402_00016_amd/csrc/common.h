@@ -54,6 +54,7 @@ struct mpmc_ctx {
     // Wilson kernel variant per (nrhs, prec), set by mpmc_autotune / mpmc_tune_set
     std::map<std::pair<int, int>, int> tune;
     std::map<std::pair<int, int>, int> tune_explicit;   // variants set by mpmc_tune_set (not by the autotuner)
+    std::map<std::pair<int, int>, int> tune_dot;        // fused level step traversal chosen by mpmc_autotune
     // polynomial right preconditioner of the solves inside mpmc_level_estimate
     const struct mpmc_poly *level_pp = nullptr;
     // small eigenproblems: 0 = Aberth-Ehrlich with the QR as fallback, 1 = QR only
@@ -62,6 +63,12 @@ struct mpmc_ctx {
     int solve_level_defl = 0;
     // storage precision of the single-vector Arnoldi cycles (mpmc_gmres_poly, mpmc_deflate)
     int setup_prec = MPMC_FP64;
+    // fused polynomial recurrences replayed from captured hipGraphs (mpmc_set_graph_recurrences)
+    int use_graphs = 0;
+    hipStream_t gstream = nullptr;          // capture / replay stream (default priority)
+    hipEvent_t gev[2] = {nullptr, nullptr}; // ordering between the context stream and gstream
+    std::map<std::string, hipGraphExec_t> graphs;   // key: operands, shape and coefficients of a recurrence
+    uint64_t graph_replays = 0;
     // distance colourings of mpmc_poly_trace_probe by polynomial degree: k, m[4], W[4][4]
     std::map<int, std::vector<int>> colourings;
 };
@@ -374,6 +381,8 @@ int poly_validate(const mpmc_ctx *ctx, const mpmc_poly *p);
 int poly_quad_fused(mpmc_ctx *ctx, const mpmc_poly *p, const void *eta, const uint32_t *codes, int nrhs, int prec,
                     int theta, double *acc, double sign);
 bool poly_quad_fusable(int nrhs);
+void graphs_clear(mpmc_ctx *ctx);
+int wilson_dot_order(const mpmc_ctx *ctx, int nrhs, int prec);   // traversal of the fused step
 int poly_matvecs(const mpmc_poly *p);
 void poly_eval_host(const mpmc_poly *p, const double *lam, double *out, int k);
 

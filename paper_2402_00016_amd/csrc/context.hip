@@ -66,6 +66,8 @@ void *stack_get(mpmc_ctx *ctx, size_t bytes) {
     if (b.bytes < bytes) {
         if (b.ptr) {
             hipStreamSynchronize(ctx->stream);
+            if (ctx->gstream) hipStreamSynchronize(ctx->gstream);
+            graphs_clear(ctx);   // captured recurrences may refer to this buffer
             hipFree(b.ptr);
             b.ptr = nullptr;
             b.bytes = 0;
@@ -91,6 +93,8 @@ void *stack_get(mpmc_ctx *ctx, size_t bytes) {
 MPMC_API int mpmc_release_workspace(mpmc_ctx *ctx) {
     if (!ctx) return MPMC_EINVAL;
     HIP_OR_RET(ctx, hipStreamSynchronize(ctx->stream));
+    if (ctx->gstream) HIP_OR_RET(ctx, hipStreamSynchronize(ctx->gstream));
+    graphs_clear(ctx);   // captured recurrences refer to the buffers released here
     release_stack_from(ctx, ctx->top);
     for (auto &b : ctx->ws) {
         if (b.ptr) hipFree(b.ptr);
@@ -260,6 +264,13 @@ MPMC_API int mpmc_create(const int dims[4], double kappa, int t_antiperiodic, co
 MPMC_API void mpmc_destroy(mpmc_ctx *ctx) {
     if (!ctx) return;
     hipStreamSynchronize(ctx->stream);
+    if (ctx->gstream) {
+        hipStreamSynchronize(ctx->gstream);
+        graphs_clear(ctx);
+        hipStreamDestroy(ctx->gstream);
+        for (auto e : ctx->gev)
+            if (e) hipEventDestroy(e);
+    }
     if (ctx->links64) hipFree(ctx->links64);
     if (ctx->links32) hipFree(ctx->links32);
     if (ctx->nbr) hipFree(ctx->nbr);

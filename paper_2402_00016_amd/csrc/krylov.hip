@@ -12,6 +12,7 @@
 #include <complex>
 
 #include <algorithm>
+#include <string>
 
 #include "common.h"
 
@@ -343,6 +344,83 @@ MPMC_API int mpmc_set_setup_precision(mpmc_ctx *ctx, int prec) {
 
 bool poly_quad_fusable(int nrhs) { return nrhs % 64 == 0 && (nrhs <= 256 || nrhs % 256 == 0); }
 
+// ------------------------------------------------ captured recurrences --
+// With mpmc_set_graph_recurrences the launch sequence of a fused recurrence is
+// captured once into a hipGraph on the context's capture stream and replayed
+// afterwards.  The key holds everything the launches depend on: operand,
+// work-vector, code and partial-sum addresses, shape, precision, Theta, the
+// traversal and the coefficients (roots), so a replay issues exactly the
+// launches an eager run would.  Only kernel launches are captured.
+
+void graphs_clear(mpmc_ctx *ctx) {
+    for (auto &g : ctx->graphs) hipGraphExecDestroy(g.second);
+    ctx->graphs.clear();
+}
+
+template <typename T>
+static void key_put(std::string &k, const T &v) {
+    k.append(reinterpret_cast<const char *>(&v), sizeof(T));
+}
+
+template <typename F>
+static int run_recurrence(mpmc_ctx *ctx, const std::string &key, uint64_t mvps, F &&steps) {
+    if (!ctx->use_graphs || ctx->timing || !ctx->gstream) return steps();
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        hipStream_t s0 = ctx->stream;
+        ctx->stream = ctx->gstream;
+        if (hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            ctx->stream = s0;
+            return steps();
+        }
+        const uint64_t mv0 = ctx->mvps;
+        const int rc = steps();
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->gstream, &g);
+        ctx->stream = s0;
+        ctx->mvps = mv0;
+        if (rc != MPMC_OK || e != hipSuccess || !g) {
+            if (g) hipGraphDestroy(g);
+            if (rc != MPMC_OK) return rc;
+            return set_err(ctx, MPMC_EHIP, "recurrence capture failed: %s", hipGetErrorString(e));
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ei != hipSuccess) return set_err(ctx, MPMC_EHIP, "graph instantiation: %s", hipGetErrorString(ei));
+        it = ctx->graphs.emplace(key, ex).first;
+    }
+    // replay on the capture stream, after the context stream's earlier work and before its later work
+    HIP_OR_RET(ctx, hipEventRecord(ctx->gev[0], ctx->stream));
+    HIP_OR_RET(ctx, hipStreamWaitEvent(ctx->gstream, ctx->gev[0], 0));
+    HIP_OR_RET(ctx, hipGraphLaunch(it->second, ctx->gstream));
+    HIP_OR_RET(ctx, hipEventRecord(ctx->gev[1], ctx->gstream));
+    HIP_OR_RET(ctx, hipStreamWaitEvent(ctx->stream, ctx->gev[1], 0));
+    ctx->mvps += mvps;
+    ctx->graph_replays++;
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_set_graph_recurrences(mpmc_ctx *ctx, int on) {
+    if (!ctx) return MPMC_EINVAL;
+    if (on != 0 && on != 1) return set_err(ctx, MPMC_EINVAL, "mpmc_set_graph_recurrences: on must be 0 or 1");
+    if (on && !ctx->gstream) {
+        HIP_OR_RET(ctx, hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+        HIP_OR_RET(ctx, hipEventCreateWithFlags(&ctx->gev[0], hipEventDisableTiming));
+        HIP_OR_RET(ctx, hipEventCreateWithFlags(&ctx->gev[1], hipEventDisableTiming));
+    }
+    ctx->use_graphs = on;
+    return MPMC_OK;
+}
+
+MPMC_API int mpmc_graph_replays(const mpmc_ctx *ctx, uint64_t *replays_host, int *graphs_host) {
+    if (!ctx) return MPMC_EINVAL;
+    if (replays_host) *replays_host = ctx->graph_replays;
+    if (graphs_host) *graphs_host = (int)ctx->graphs.size();
+    return MPMC_OK;
+}
+
 static int quad_single_fused(mpmc_ctx *ctx, const std::vector<double> &roots, int d, const void *eta, const void *x,
                              const uint32_t *codes, int nrhs, int prec, int theta, double *acc, double sign) {
     Scratch S(ctx);
@@ -360,12 +438,20 @@ static int quad_single_fused(mpmc_ctx *ctx, const std::vector<double> &roots, in
     void *wb = S.get(vec_bytes(ctx, nrhs, prec));
     double *part = (double *)S.get(sizeof(double2) * wilson_dot_partial_count(ctx, nrhs));
     if (!wa || !wb || !part) return MPMC_ENOMEM;
-    const void *cur = x;
-    for (int k = 0; k + 1 < d; ++k) {
-        void *nxt = (cur == wa) ? wb : wa;
-        RET_IF(wilson_dot_step(ctx, cur, nxt, codes, nrhs, prec, inv(k), inv(k + 1), theta, part, k == 0));
-        cur = nxt;
-    }
+    std::string key("s");
+    for (const void *q : {(const void *)x, (const void *)wa, (const void *)wb, (const void *)codes, (const void *)part})
+        key_put(key, q);
+    for (int v : {d, nrhs, prec, theta, wilson_dot_order(ctx, nrhs, prec)}) key_put(key, v);
+    key.append(reinterpret_cast<const char *>(roots.data()), sizeof(double) * 2 * d);
+    RET_IF(run_recurrence(ctx, key, (uint64_t)(d - 1) * nrhs, [&]() -> int {
+        const void *cur = x;
+        for (int k = 0; k + 1 < d; ++k) {
+            void *nxt = (cur == wa) ? wb : wa;
+            RET_IF(wilson_dot_step(ctx, cur, nxt, codes, nrhs, prec, inv(k), inv(k + 1), theta, part, k == 0));
+            cur = nxt;
+        }
+        return MPMC_OK;
+    }));
     return wilson_dot_finish(ctx, part, nrhs, prec, acc, 1, sign);
 }
 
@@ -396,32 +482,44 @@ int poly_quad_fused(mpmc_ctx *ctx, const mpmc_poly *p, const void *eta, const ui
     // first term (k = 0, j = 0): eta^H Theta eta / (th_0^out th_0^in)
     RET_IF(blas_dot(ctx, eta, eta, nrhs, prec, theta, (double *)t));
     RET_IF(blas_scale_acc(ctx, (double *)t, nrhs, d2(io(0) * ii(0)), sign, acc));
-    const void *w = eta;   // w_k
-    bool first = true;
-    for (int k = 0; k < dout; ++k) {
-        const bool last_outer = k == dout - 1;
-        const int nsteps = last_outer ? din - 1 : din;
-        const void *v = w;
-        for (int j = 0; j < nsteps; ++j) {
-            void *dst = nullptr;
-            for (void *c : buf)
-                if (c != w && c != v) {
-                    dst = c;
-                    break;
+    const int nsteps_total = (dout - 1) * din + (din - 1);
+    if (nsteps_total == 0) return MPMC_OK;
+    std::string key("d");
+    for (const void *q : {(const void *)eta, (const void *)buf[0], (const void *)buf[1], (const void *)buf[2],
+                          (const void *)codes, (const void *)part})
+        key_put(key, q);
+    for (int v : {din, dout, nrhs, prec, theta, wilson_dot_order(ctx, nrhs, prec)}) key_put(key, v);
+    key.append(reinterpret_cast<const char *>(pin->roots.data()), sizeof(double) * 2 * din);
+    key.append(reinterpret_cast<const char *>(p->roots.data()), sizeof(double) * 2 * dout);
+    RET_IF(run_recurrence(ctx, key, (uint64_t)nsteps_total * nrhs, [&]() -> int {
+        const void *w = eta;   // w_k
+        bool first = true;
+        for (int k = 0; k < dout; ++k) {
+            const bool last_outer = k == dout - 1;
+            const int nsteps = last_outer ? din - 1 : din;
+            const void *v = w;
+            for (int j = 0; j < nsteps; ++j) {
+                void *dst = nullptr;
+                for (void *c : buf)
+                    if (c != w && c != v) {
+                        dst = c;
+                        break;
+                    }
+                const double2 c = d2(ii(j));
+                if (!last_outer && j == din - 1) {
+                    // v_{k,d_in} combined into w_{k+1}; accumulates the first term of step k + 1
+                    RET_IF(wilson_dot_step(ctx, v, dst, codes, nrhs, prec, c, d2(io(k + 1) * ii(0)), theta, part,
+                                           first, w, d2(1.0 - io(k)), d2(io(k))));
+                    w = dst;
+                } else {
+                    RET_IF(wilson_dot_step(ctx, v, dst, codes, nrhs, prec, c, d2(io(k) * ii(j + 1)), theta, part,
+                                           first));
+                    v = dst;
                 }
-            const double2 c = d2(ii(j));
-            if (!last_outer && j == din - 1) {
-                // v_{k,d_in} combined into w_{k+1}; accumulates the first term of step k + 1
-                RET_IF(wilson_dot_step(ctx, v, dst, codes, nrhs, prec, c, d2(io(k + 1) * ii(0)), theta, part, first,
-                                       w, d2(1.0 - io(k)), d2(io(k))));
-                w = dst;
-            } else {
-                RET_IF(wilson_dot_step(ctx, v, dst, codes, nrhs, prec, c, d2(io(k) * ii(j + 1)), theta, part, first));
-                v = dst;
+                first = false;
             }
-            first = false;
         }
-    }
-    if (!first) RET_IF(wilson_dot_finish(ctx, part, nrhs, prec, acc, 1, sign));
-    return MPMC_OK;
+        return MPMC_OK;
+    }));
+    return wilson_dot_finish(ctx, part, nrhs, prec, acc, 1, sign);
 }

@@ -566,8 +566,8 @@ struct Occ {
 // chunk-major, 2 chunk-major over the blocked site order, 3 and 4 the same with
 // 16- and 32-wide chunks, four and two sites per wavefront and per-lane
 // links).  Orders 3 and 4 need V % 16 == 0; elsewhere they fall back to 2.
-constexpr int WILSON_VARIANTS = 10;
-static inline int default_variant(int prec) { return prec == MPMC_FP64 ? 4 : 5; }
+constexpr int WILSON_VARIANTS = 11;
+constexpr int WILSON_COLUMN = 10;   // FP32 column-streaming kernel (k_wilson_col)
 
 // Everything one thread does for (site s, rhs r) once located.
 template <int P, bool UNI, int ORDER>
@@ -1060,9 +1060,278 @@ __global__ void k_noise_codes(uint64_t seed, uint32_t stream, uint64_t first, ui
     codes[s * ld + off + r] = z4_site_symbols(seed, stream, (uint32_t)(first + r), s);
 }
 
+// -------------------------------------------------- column streaming --
+// FP32 kernels in which a workgroup owns a 2 x 2 x 2 tile of (x, y, z)
+// columns and 64 right-hand sides (one wavefront per column) and walks the
+// columns along t.  Every wavefront keeps its own site and the next one in
+// registers (the t+1 neighbour of step t is the own site of step t+1, loaded
+// one step ahead) and publishes its site in LDS each step; the t-1 neighbour
+// (the own column's previous site) and the three in-tile x, y, z neighbours
+// come from LDS, only the three out-of-tile neighbours from global memory.
+// A site's spinor is thus fetched by 4 wavefronts instead of 9 -- the Wilson
+// kernels are bound by L1-miss requests to the L2 (each site-wavefront's
+// loads miss the 32 KB L1), so this cuts the bound itself.  LDS holds three
+// slices (t-1, t, and the one being written next) so that one barrier per
+// step orders all writes and reads.  Requires even Lx, Ly, Lz, Lt >= 4 and
+// nrhs % 64 == 0.
+constexpr int COL_WAVES = 8;
+
+struct ColArgs {
+    int L[4];
+    int ntx, nty, ntz;   // tiles per direction
+    long ntiles;         // tiles per 64-wide chunk
+    int tap;             // antiperiodic time direction
+};
+
+template <int P>
+struct ColLds {
+    float2 v[3][COL_WAVES][12][64];
+};
+
+// hop MU (forward or backward) from a spinor held by the lane
+template <int P, int MU, bool FWD>
+__device__ __forceinline__ void col_hop(const cpx<float> (&psi)[12], uint32_t lw, float bsign, float g,
+                                        cpx<float> acc[4][3]) {
+    HopData<P> H;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) H.psi[k] = psi[k];
+    H.lw[0] = lw;
+    H.bsign = bsign;
+    apply<P, true, MU, FWD>(H, g, acc);
+    __builtin_amdgcn_sched_barrier(0);   // hops one after another: short live ranges
+}
+
+__device__ __forceinline__ void col_lds_read(const ColLds<MPMC_FP32> &L, int buf, int w, unsigned lane,
+                                             cpx<float> (&psi)[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const float2 v = L.v[buf][w][k][lane];
+        psi[k] = mk(v.x, v.y);
+    }
+}
+
+__device__ __forceinline__ void col_load(const void *b, long site, int N, uint32_t r, cpx<float> (&psi)[12]) {
+    const SiteAcc<MPMC_FP32, true> A(b, nullptr, site, N, r);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = A.ld(k);
+}
+
+__device__ __forceinline__ long col_site(const ColArgs &c, int x, int y, int z, int t) {
+    return x + (long)c.L[0] * (y + (long)c.L[1] * (z + (long)c.L[2] * t));
+}
+
+// The x, y or z hops of one site: the in-tile neighbour (the wavefront's
+// partner across the tile, from LDS) and the out-of-tile one (og, global
+// memory; forward if the column sits at the tile's upper edge, else
+// backward).  lf: U_mu(s), lb: U_mu(s - mu), both lane-distributed.
+template <int MU>
+__device__ __forceinline__ void col_dir(const ColLds<MPMC_FP32> &L, int curb, int w, unsigned lane, int upper,
+                                        const cpx<float> (&og)[12], uint32_t lf, uint32_t lb, float g,
+                                        cpx<float> acc[4][3]) {
+    cpx<float> nb[12];
+    col_lds_read(L, curb, w ^ (1 << MU), lane, nb);
+    // forward before backward, as in every Wilson kernel (same rounding)
+    if (!upper) {
+        col_hop<MPMC_FP32, MU, true>(nb, lf, 1.f, g, acc);
+        col_hop<MPMC_FP32, MU, false>(og, lb, 1.f, g, acc);
+    } else {
+        col_hop<MPMC_FP32, MU, true>(og, lf, 1.f, g, acc);
+        col_hop<MPMC_FP32, MU, false>(nb, lb, 1.f, g, acc);
+    }
+}
+
+// MODE 0: plain apply with the WOut epilogue (FP32 out, no FP16S);
+// MODE 1: fused level step (w' = w - c M w [combined with a], eta^H Theta w').
+// Per step t of a column: the loads of the t+1 site, the three out-of-tile
+// neighbours and the links are issued first; after the barrier the LDS hops
+// run while they arrive; the t+1 site is then published for step t+1.
+template <int MODE, bool CMB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_wilson_col(
+    const void *__restrict__ b, const float2 *__restrict__ links, ColArgs ca, int N, WOut o,
+    const uint32_t *__restrict__ codes, double2 c, double2 cnext, int theta, double2 *__restrict__ partial,
+    int first_step, const void *__restrict__ a2, double2 alpha, double2 beta) {
+    using T = float;
+    __shared__ ColLds<MPMC_FP32> L;
+    const int w = (int)(threadIdx.x >> 6);
+    const unsigned lane = threadIdx.x & 63u;
+    const int wx = w & 1, wy = (w >> 1) & 1, wz = w >> 2;
+    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
+    const long chunk = (long)tile / ca.ntiles, tl = (long)tile - chunk * ca.ntiles;
+    const int tx = (int)(tl % ca.ntx), ty = (int)((tl / ca.ntx) % ca.nty), tz = (int)(tl / ((long)ca.ntx * ca.nty));
+    const int x = 2 * tx + wx, y = 2 * ty + wy, z = 2 * tz + wz, Lt = ca.L[3];
+    const uint32_t r = (uint32_t)(chunk * 64 + lane);
+    // out-of-tile neighbour coordinates (forward at the tile's upper edge, else backward)
+    const int xo = wx ? (x + 1 == ca.L[0] ? 0 : x + 1) : (x == 0 ? ca.L[0] - 1 : x - 1);
+    const int yo = wy ? (y + 1 == ca.L[1] ? 0 : y + 1) : (y == 0 ? ca.L[1] - 1 : y - 1);
+    const int zo = wz ? (z + 1 == ca.L[2] ? 0 : z + 1) : (z == 0 ? ca.L[2] - 1 : z - 1);
+    // backward-neighbour coordinates (their forward links are this site's backward links)
+    const int xb = x == 0 ? ca.L[0] - 1 : x - 1, yb = y == 0 ? ca.L[1] - 1 : y - 1, zb = z == 0 ? ca.L[2] - 1 : z - 1;
+    const float g = o.g;
+    const T kap = (T)o.kappa;
+
+    {   // slices Lt-1 (read as t-1 at t = 0) and 0 of the own column
+        cpx<float> v[12];
+        col_load(b, col_site(ca, x, y, z, Lt - 1), N, r, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) L.v[2][w][k][lane] = make_float2(v[k].re, v[k].im);
+        col_load(b, col_site(ca, x, y, z, 0), N, r, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) L.v[0][w][k][lane] = make_float2(v[k].re, v[k].im);
+    }
+    uint32_t ltprev[1];   // U_t(s - t): the forward t link of the previous site
+    load_link_lanes<MPMC_FP32>(links + (col_site(ca, x, y, z, Lt - 1) * 4 + 3) * 9, ltprev);
+    cpx<double> dot = mk(0.0, 0.0);
+
+    for (int t = 0; t < Lt; ++t) {
+        const int curb = t % 3, prevb = (t + 2) % 3, nextb = (t + 1) % 3;
+        const long s = col_site(ca, x, y, z, t);
+        // global traffic of the step: the t+1 site, the out-of-tile neighbours, the links
+        cpx<float> nx[12], ogx[12], ogy[12], ogz[12];
+        col_load(b, col_site(ca, x, y, z, t + 1 < Lt ? t + 1 : 0), N, r, nx);
+        col_load(b, col_site(ca, xo, y, z, t), N, r, ogx);
+        col_load(b, col_site(ca, x, yo, z, t), N, r, ogy);
+        uint32_t lf[4][1], lb[3][1];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) load_link_lanes<MPMC_FP32>(links + (s * 4 + mu) * 9, lf[mu]);
+        load_link_lanes<MPMC_FP32>(links + (col_site(ca, xb, y, z, t) * 4 + 0) * 9, lb[0]);
+        load_link_lanes<MPMC_FP32>(links + (col_site(ca, x, yb, z, t) * 4 + 1) * 9, lb[1]);
+        load_link_lanes<MPMC_FP32>(links + (col_site(ca, x, y, zb, t) * 4 + 2) * 9, lb[2]);
+        // slice t of every column of the tile (published one step ahead) is now
+        // visible, and every read of step t-1 is done (three buffers rotate)
+        __syncthreads();
+
+        cpx<float> acc[4][3];
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = mk(0.f, 0.f);
+        // hops in the order of every Wilson kernel: x, y, z, t, forward first
+        col_dir<0>(L, curb, w, lane, wx, ogx, lf[0][0], lb[0][0], g, acc);
+        // the z neighbour's loads start once the x one is consumed (register budget)
+        __builtin_amdgcn_sched_barrier(0);
+        col_load(b, col_site(ca, x, y, zo, t), N, r, ogz);
+        __builtin_amdgcn_sched_barrier(0);
+        col_dir<1>(L, curb, w, lane, wy, ogy, lf[1][0], lb[1][0], g, acc);
+        col_dir<2>(L, curb, w, lane, wz, ogz, lf[2][0], lb[2][0], g, acc);
+        col_hop<MPMC_FP32, 3, true>(nx, lf[3][0], (ca.tap && t == Lt - 1) ? -1.f : 1.f, g, acc);
+        {   // t backward: the own column's previous slice
+            cpx<float> pv[12];
+            col_lds_read(L, prevb, w, lane, pv);
+            col_hop<MPMC_FP32, 3, false>(pv, ltprev[0], (ca.tap && t == 0) ? -1.f : 1.f, g, acc);
+        }
+        pin_acc(acc);
+        // publish the t+1 site for step t+1 (that buffer was last read at step t-1)
+#pragma unroll
+        for (int k = 0; k < 12; ++k) L.v[nextb][w][k][lane] = make_float2(nx[k].re, nx[k].im);
+
+        cpx<float> cur[12];
+        col_lds_read(L, curb, w, lane, cur);
+        const SiteAcc<MPMC_FP32, true> O(o.out, nullptr, s, N, r);
+        if constexpr (MODE == 0) {
+            const bool has_a = o.a_is_b || o.a;
+            const cpx<T> al = has_a ? mk((T)o.alpha.x, (T)o.alpha.y) : mk(T(0), T(0));
+            const cpx<T> be = mk((T)o.beta.x, (T)o.beta.y);
+            const cpx<T> beg5 = o.theta ? mk(-be.re, -be.im) : be;
+            cpx<T> av[12];
+            if (o.a && !o.a_is_b) {
+                const SiteAcc<MPMC_FP32, true> A(o.a, nullptr, s, N, r);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) av[k] = A.ld(k);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) av[k] = cur[k];
+            }
+            cpx<T> res[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const cpx<T> mb = cur[k] - kap * acc[k / 3][k % 3];
+                res[k] = (k >= 6 ? beg5 : be) * mb + al * av[k];
+                O.st(k, res[k]);
+            }
+            if (o.y) {
+                const cpx<T> ga = mk((T)o.gamma.x, (T)o.gamma.y);
+                const SiteAcc<MPMC_FP32, true> Y(o.y, nullptr, s, N, r);
+                cpx<T> yv[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) yv[k] = Y.ld(k);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) Y.st(k, yv[k] + ga * res[k]);
+            }
+        } else {
+            const uint32_t code = codes[s * N + r];
+            const cpx<T> ccf = mk((T)c.x, (T)c.y);
+            cpx<T> av[12];
+            if constexpr (CMB) {
+                const SiteAcc<MPMC_FP32, true> A(a2, nullptr, s, N, r);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) av[k] = A.ld(k);
+            }
+            const cpx<T> al = mk((T)alpha.x, (T)alpha.y), be = mk((T)beta.x, (T)beta.y);
+            const double tsg = theta ? -1.0 : 1.0;
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const cpx<T> mw = cur[k] - kap * acc[k / 3][k % 3];
+                cpx<T> wn = cur[k] - ccf * mw;
+                if constexpr (CMB) wn = al * av[k] + be * wn;
+                O.st(k, wn);
+                const uint32_t sym = (code >> (2 * k)) & 3u;
+                const double ar = (double)wn.re, ai = (double)wn.im;
+                const double sg = (sym & 2u) ? -1.0 : 1.0;
+                const double gg = k >= 6 ? sg * tsg : sg;
+                dot.re += gg * ((sym & 1u) ? ai : ar);
+                dot.im += gg * ((sym & 1u) ? -ar : ai);
+            }
+        }
+        ltprev[0] = lf[3][0];
+    }
+    if constexpr (MODE == 1) {
+        // per-tile partial of every right-hand side: the 8 columns summed in a fixed order
+        __syncthreads();   // every wavefront is done with the slices
+        double2 *red = reinterpret_cast<double2 *>(&L.v[0][0][0][0]);
+        red[threadIdx.x] = make_double2(dot.re, dot.im);
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            double sx = 0, sy = 0;
+#pragma unroll
+            for (int q = 0; q < COL_WAVES; ++q) {
+                sx += red[q * 64 + threadIdx.x].x;
+                sy += red[q * 64 + threadIdx.x].y;
+            }
+            const cpx<double> term = mk(cnext.x, cnext.y) * mk(sx, sy);
+            double2 *pp = partial + (long)tile * 64 + threadIdx.x;
+            if (first_step) {
+                *pp = make_double2(term.re, term.im);
+            } else {
+                const double2 old = *pp;
+                *pp = make_double2(old.x + term.re, old.y + term.im);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------- launch --
 
 static double spinor_bytes(int prec) { return prec == MPMC_FP64 ? 192.0 : (prec == MPMC_FP32 ? 96.0 : 52.0); }
+
+// The column-streaming kernel needs even Lx, Ly, Lz, Lt >= 4, FP32 and 64-wide chunks.
+static bool col_ok(const mpmc_ctx *ctx, int nrhs, int prec) {
+    return prec == MPMC_FP32 && nrhs % 64 == 0 && ctx->dims[0] % 2 == 0 && ctx->dims[1] % 2 == 0 &&
+           ctx->dims[2] % 2 == 0 && ctx->dims[3] >= 4;
+}
+static ColArgs col_args(const mpmc_ctx *ctx) {
+    ColArgs a;
+    for (int mu = 0; mu < 4; ++mu) a.L[mu] = ctx->dims[mu];
+    a.ntx = ctx->dims[0] / 2;
+    a.nty = ctx->dims[1] / 2;
+    a.ntz = ctx->dims[2] / 2;
+    a.ntiles = (long)a.ntx * a.nty * a.ntz;
+    a.tap = ctx->t_antiperiodic;
+    return a;
+}
+static int default_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
+    if (col_ok(ctx, nrhs, prec)) return WILSON_COLUMN;
+    return prec == MPMC_FP64 ? 4 : 5;
+}
 static double link_bytes(int prec) { return prec == MPMC_FP64 ? 576.0 : 288.0; }
 
 template <int P>
@@ -1080,7 +1349,8 @@ static WIn<P> make_in(const mpmc_ctx *ctx, const void *b, int nrhs) {
 // Kernel variant for (nrhs, prec): pinned or tuned by the autotuner, else the default.
 static int wilson_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
     const auto it = ctx->tune.find(std::make_pair(nrhs, prec));
-    const int v = it == ctx->tune.end() ? default_variant(prec) : it->second;
+    const int v = it == ctx->tune.end() ? default_variant(ctx, nrhs, prec) : it->second;
+    if (v == WILSON_COLUMN) return col_ok(ctx, nrhs, prec) ? v : (prec == MPMC_FP64 ? 4 : 5);
     return (v >> 1) >= 3 && ctx->V % 16 != 0 ? (v & 1) | 4 : v;
 }
 
@@ -1089,15 +1359,30 @@ static int wilson_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
 // a variant set explicitly for (nrhs, prec) with mpmc_tune_set selects its
 // traversal (orders 0 and 1: site-major; 3 and 4 need V % 16 == 0).  The
 // autotuner, which times the plain operator, does not change it.
-constexpr int kDotDefaultOrder = 2;   // 64-wide blocked chunks: fastest measured
+constexpr int kDotDefaultOrder = 2;   // 64-wide blocked chunks (FP64; FP32 takes the column kernel)
+constexpr int kDotColumn = 5;         // order code of the column-streaming fused step
 static int dot_order(const mpmc_ctx *ctx, int nrhs, int prec) {
-    if (ctx->V % 4 != 0) return 0;
+    const auto td = ctx->tune_dot.find(std::make_pair(nrhs, prec));
+    if (td != ctx->tune_dot.end() && ctx->tune_explicit.find(std::make_pair(nrhs, prec)) == ctx->tune_explicit.end()) {
+        const int o = td->second;   // the autotuner's choice (valid for this shape by construction)
+        return o;
+    }
     const auto it = ctx->tune_explicit.find(std::make_pair(nrhs, prec));
-    const int o = it == ctx->tune_explicit.end() ? kDotDefaultOrder : it->second >> 1;
+    if (it == ctx->tune_explicit.end() || it->second == WILSON_COLUMN)
+        if (col_ok(ctx, nrhs, prec) && nrhs <= 256) return kDotColumn;
+    if (ctx->V % 4 != 0) return 0;
+    const int o = (it == ctx->tune_explicit.end() || it->second == WILSON_COLUMN) ? kDotDefaultOrder : it->second >> 1;
     if (o >= 3) return ctx->V % 16 == 0 ? o : 2;
     return o == 2 ? 2 : 0;
 }
-static int dot_width(int order, int nrhs) { return order == 3 ? 16 : order == 4 ? 32 : order == 2 ? 64 : (nrhs < 256 ? nrhs : 256); }
+int wilson_dot_order(const mpmc_ctx *ctx, int nrhs, int prec) { return dot_order(ctx, nrhs, prec); }
+
+static int dot_width(int order, int nrhs) {
+    return order == 3 ? 16 : order == 4 ? 32 : (order == 2 || order == kDotColumn) ? 64 : (nrhs < 256 ? nrhs : 256);
+}
+static long dot_tiles_per_chunk(const mpmc_ctx *ctx, int order, int width) {
+    return order == kDotColumn ? col_args(ctx).ntiles : ctx->V * width / 256;
+}
 
 template <int P, int V_>
 static void launch_uniform(mpmc_ctx *ctx, const WIn<P> &in, const WOut &o, int nrhs, unsigned grid) {
@@ -1118,8 +1403,18 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs, double2 yi
             return;
         }
     }
+    if constexpr (P == MPMC_FP32) {
+        if (nrhs % 64 == 0 && wilson_variant(ctx, nrhs, P) == WILSON_COLUMN && !o.osc) {
+            const ColArgs ca = col_args(ctx);
+            k_wilson_col<0, false><<<(unsigned)(ca.ntiles * (nrhs / 64)), 512, 0, ctx->stream>>>(
+                in.b, in.links, ca, nrhs, o, nullptr, make_double2(0, 0), make_double2(0, 0), 0, nullptr, 0, nullptr,
+                make_double2(0, 0), make_double2(1, 0));
+            return;
+        }
+    }
     if (nrhs % 64 == 0) {
-        switch (wilson_variant(ctx, nrhs, P)) {
+        const int v = wilson_variant(ctx, nrhs, P);
+        switch (v == WILSON_COLUMN ? 5 : v) {
         case 0: launch_uniform<P, 0>(ctx, in, o, nrhs, grid); break;
         case 1: launch_uniform<P, 1>(ctx, in, o, nrhs, grid); break;
         case 2: launch_uniform<P, 2>(ctx, in, o, nrhs, grid); break;
@@ -1224,6 +1519,18 @@ static void launch_dot(mpmc_ctx *ctx, int dord, unsigned grid, const WIn<P> &in,
                        double2 c, double2 cnext, int theta, double2 *partial, int nrhs, int first_step,
                        const void *a, double2 alpha, double2 beta) {
     const int *ord = dord ? ctx->site_order : nullptr;
+    if constexpr (P == MPMC_FP32) {
+        if (dord == kDotColumn) {
+            const ColArgs ca = col_args(ctx);
+            WOut o{};
+            o.out = wout;   // the step's output w'
+            o.kappa = ctx->kappa;
+            o.g = 1.f;
+            k_wilson_col<1, CMB><<<(unsigned)(ca.ntiles * (nrhs / 64)), 512, 0, ctx->stream>>>(
+                in.b, in.links, ca, nrhs, o, codes, c, cnext, theta, partial, first_step, a, alpha, beta);
+            return;
+        }
+    }
     switch (dord) {
     case 2:
         k_wilson_dot<P, 2, false, CMB><<<grid, 256, 0, ctx->stream>>>(in.b, in.nbr, in.links, wout, codes, c, cnext,
@@ -1255,6 +1562,8 @@ int wilson_dot_step(mpmc_ctx *ctx, const void *w, void *wout, const uint32_t *co
     if (nrhs % 64 != 0 || (nrhs > 256 && nrhs % 256 != 0))
         return set_err(ctx, MPMC_EINVAL, "fused level step needs nrhs %% 64 == 0 (and %% 256 above 256)");
     if (a && a == wout) return set_err(ctx, MPMC_EINVAL, "fused level step: a aliases the output");
+    if (!w || !wout || !codes || !partial || w == wout)
+        return set_err(ctx, MPMC_EINVAL, "fused level step: null or aliased operand");
     const long work = ctx->V * nrhs;
     const unsigned grid = grid_for(work, 256);
     const int dord = dot_order(ctx, nrhs, prec);
@@ -1337,8 +1646,9 @@ int wilson_dot_finish(mpmc_ctx *ctx, const double *partial, int nrhs, int prec, 
     const int dord = dot_order(ctx, nrhs, prec);
     if (dord) {
         const int wd = dot_width(dord, nrhs);
-        k_dot_finish_chunk<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, ctx->V * wd / 256, wd,
-                                                          (double2 *)out, accumulate, sign);
+        k_dot_finish_chunk<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial,
+                                                          dot_tiles_per_chunk(ctx, dord, wd), wd, (double2 *)out,
+                                                          accumulate, sign);
     } else
         k_dot_finish<<<nrhs, 256, 0, ctx->stream>>>((const double2 *)partial, (int)blocks, nrhs, (double2 *)out,
                                                     accumulate, sign);
@@ -1452,7 +1762,7 @@ MPMC_API int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host,
     const uint64_t mvps = ctx->mvps;
     ctx->timing = 0;
     const auto key = std::make_pair(nrhs, prec);
-    int best = default_variant(prec), rc = MPMC_OK;
+    int best = default_variant(ctx, nrhs, prec), rc = MPMC_OK;
     double best_us = 1e300;
     constexpr int warm = 2, reps = 5;
     for (int v = 0; v < WILSON_VARIANTS && rc == MPMC_OK; ++v) {
@@ -1481,5 +1791,77 @@ MPMC_API int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host,
     ctx->tune[key] = best;
     if (rc != MPMC_OK) return rc;
     if (variant_host) *variant_host = best;
+    return MPMC_OK;
+}
+
+// Fused level step traversal (orders 0 site-major, 2 blocked 64-wide chunks,
+// 3 / 4 blocked 16- / 32-wide chunks, 5 column streaming): each valid one is
+// timed (2 warm-up + 5 timed steps) and the fastest kept for (nrhs, prec).
+MPMC_API int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_host, double *us_host) {
+    if (!ctx) return MPMC_EINVAL;
+    if ((prec != MPMC_FP64 && prec != MPMC_FP32) || nrhs < 64 || nrhs % 64 != 0 || (nrhs > 256 && nrhs % 256 != 0))
+        return set_err(ctx, MPMC_EINVAL, "mpmc_autotune_level: FP64/FP32 and nrhs %% 64 == 0 (%% 256 above 256)");
+    if (us_host)
+        for (int o = 0; o < 6; ++o) us_host[o] = 0.0;
+    Scratch S(ctx);
+    const size_t vb = vec_bytes(ctx, nrhs, prec);
+    void *x = S.get(vb), *y = S.get(vb);
+    uint32_t *codes = (uint32_t *)S.get(sizeof(uint32_t) * (size_t)ctx->V * nrhs);
+    double *part = (double *)S.get(sizeof(double2) * wilson_dot_partial_count(ctx, nrhs));
+    if (!x || !y || !codes || !part) return MPMC_ENOMEM;
+    RET_IF(launch_noise(ctx, 1, 0, 0, nrhs, prec, x));
+    RET_IF(wilson_noise_codes(ctx, 1, 0, 0, nrhs, codes));
+    hipEvent_t e0, e1;
+    HIP_OR_RET(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return set_err(ctx, MPMC_EHIP, "mpmc_autotune_level: event creation failed");
+    }
+    const int timing = ctx->timing;
+    const uint64_t mvps = ctx->mvps;
+    ctx->timing = 0;
+    const auto key = std::make_pair(nrhs, prec);
+    const auto ex = ctx->tune_explicit.find(key);
+    const bool had_ex = ex != ctx->tune_explicit.end();
+    const int ex_v = had_ex ? ex->second : 0;
+    ctx->tune_explicit.erase(key);
+    std::vector<int> cand = {0};
+    if (ctx->V % 4 == 0) cand.push_back(2);
+    if (ctx->V % 16 == 0) {
+        cand.push_back(3);
+        cand.push_back(4);
+    }
+    if (col_ok(ctx, nrhs, prec) && nrhs <= 256) cand.push_back(kDotColumn);
+    int best = cand.back(), rc = MPMC_OK;
+    double best_us = 1e300;
+    constexpr int warm = 2, reps = 5;
+    for (size_t q = 0; q < cand.size() && rc == MPMC_OK; ++q) {
+        const int o = cand[q];
+        ctx->tune_dot[key] = o;
+        for (int i = 0; i < warm + reps && rc == MPMC_OK; ++i) {
+            if (i == warm && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = MPMC_EHIP;
+            if (rc == MPMC_OK)
+                rc = wilson_dot_step(ctx, (i & 1) ? y : x, (i & 1) ? x : y, codes, nrhs, prec, make_double2(0.1, 0),
+                                     make_double2(0.1, 0), 0, part, i == 0);
+        }
+        float ms = 0.f;
+        if (rc == MPMC_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+            rc = set_err(ctx, MPMC_EHIP, "mpmc_autotune_level: timing failed");
+        const double us = 1e3 * ms / reps;
+        if (us_host) us_host[o] = us;
+        if (rc == MPMC_OK && us < best_us) {
+            best_us = us;
+            best = o;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->timing = timing;
+    ctx->mvps = mvps;
+    ctx->tune_dot[key] = best;
+    if (had_ex) ctx->tune_explicit[key] = ex_v;
+    if (rc != MPMC_OK) return rc;
+    if (order_host) *order_host = best;
     return MPMC_OK;
 }

@@ -73,6 +73,7 @@ class Plan:
     deflate_double: bool = False         # double polynomials from a deflated outer cycle (Sec. 7); the
                                          # solve level is then deflated as well when p_1 is one of them
     setup_prec: int = mpmc.FP64          # Arnoldi vectors of the polynomial and deflation builds (scalars FP64)
+    graphs: bool = False                 # fused polynomial recurrences replayed from captured hipGraphs
     probe_last: bool = False             # last term Tr(Theta p_K) exactly by probing (Sec. 6) instead of sampling
     probe_batch: int = 192               # probe vectors per batch
 
@@ -255,16 +256,20 @@ class _SideJob:
 
 def autotune_levels(ctx, plan: Plan):
     """Autotune the Wilson kernel for the batch shapes of the levels (once per
-    context and shape): the polynomial levels in plan.poly_prec, the solve
-    level's inner precision and its FP64 residuals."""
+    context and shape): the polynomial levels in plan.poly_prec (the operator
+    and the fused level step), the solve level's inner precision and its FP64
+    residuals.  The choices are kept in ctx.tuned[(nrhs, prec)]."""
     if not plan.autotune:
         return
-    done = ctx.__dict__.setdefault("_tuned", set())
+    done = ctx.__dict__.setdefault("tuned", {})
     nb = plan.max_batch if plan.max_batch else plan.noises
     for prec in {plan.poly_prec, plan.solve_inner_prec, mpmc.FP64}:
         if (nb, prec) not in done:
-            ctx.autotune(nb, prec)
-            done.add((nb, prec))
+            v = ctx.autotune(nb, prec)[0]
+            lv = None
+            if prec == plan.poly_prec and nb % 64 == 0 and (nb <= 256 or nb % 256 == 0):
+                lv = ctx.autotune_level(nb, prec)[0]
+            done[(nb, prec)] = {"variant": v, "level_order": lv}
 
 
 def solve_preconditioner(ctx, plan: Plan, defl):
@@ -289,6 +294,7 @@ def build_setup(ctx, plan: Plan, train=False):
     autotune_levels(ctx, plan)
     for c in [ctx] + [c for c, _ in ctx._side.values()] + ([ctx.side("polys")[0]] if plan.overlap_setup else []):
         c.set_setup_precision(plan.setup_prec)
+    ctx.set_graph_recurrences(int(plan.graphs))
     if not plan.overlap_setup:
         defl = build_deflation(ctx, plan)
         polys = build_polys(ctx, plan, defl)

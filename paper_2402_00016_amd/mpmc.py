@@ -68,6 +68,7 @@ _SIGS = {
     "mpmc_defl_keep": ([_vp, _i], _i),
     "mpmc_solve": ([_vp, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _pi, _vp], _i),
     "mpmc_autotune": ([_vp, _i, _i, _pi, _vp], _i),
+    "mpmc_autotune_level": ([_vp, _i, _i, _pi, _vp], _i),
     "mpmc_wilson_variant_count": ([], _i),
     "mpmc_apply_M_batch": ([_vp, _vp, _vp, _i, _i, _i, _i, _i], _i),
     "mpmc_release_workspace": ([_vp], _i),
@@ -86,6 +87,8 @@ _SIGS = {
     "mpmc_set_solve_level_deflation": ([_vp, _i], _i),
     "mpmc_set_site_order": ([_vp, _vp], _i),
     "mpmc_set_setup_precision": ([_vp, _i], _i),
+    "mpmc_set_graph_recurrences": ([_vp, _i], _i),
+    "mpmc_graph_replays": ([_vp, _pu64, _pi], _i),
     "mpmc_probe_colouring": ([_pi, _i, _pi, _pi, _pi, ctypes.POINTER(ctypes.c_long)], _i),
     "mpmc_poly_trace_probe": ([_vp, _vp, _i, _i, _i, _vp, ctypes.POINTER(ctypes.c_long), _pu64], _i),
     "mpmc_solve_pairs": ([_vp, _vp, _vp, _i, _vp, _i, _d, _i, _i, _vp, _vp, _i, _pi, _pi, _vp], _i),
@@ -314,6 +317,16 @@ def mpmc_set_site_order(ctx, order):
     _check(_L.mpmc_set_site_order(ctx, o.ctypes.data), ctx)
 
 
+def mpmc_set_graph_recurrences(ctx, on):
+    _check(_L.mpmc_set_graph_recurrences(ctx, int(on)), ctx)
+
+
+def mpmc_graph_replays(ctx):
+    r, g = ctypes.c_uint64(), ctypes.c_int()
+    _check(_L.mpmc_graph_replays(ctx, ctypes.byref(r), ctypes.byref(g)), ctx)
+    return r.value, g.value
+
+
 def mpmc_set_setup_precision(ctx, prec):
     _check(_L.mpmc_set_setup_precision(ctx, int(prec)), ctx)
 
@@ -362,6 +375,14 @@ def mpmc_level_estimate(ctx, upper, lower, defl, theta, seed, stream, first, nno
 
 
 WILSON_VARIANTS = _L.mpmc_wilson_variant_count()   # kernel variants of the multi-RHS Wilson kernel
+
+
+def mpmc_autotune_level(ctx, nrhs, prec):
+    """(chosen traversal order, microseconds per fused step for orders 0..5; 0 = not a candidate)."""
+    o = ctypes.c_int()
+    us = np.zeros(6)
+    _check(_L.mpmc_autotune_level(ctx, int(nrhs), int(prec), ctypes.byref(o), us.ctypes.data), ctx)
+    return o.value, us
 
 
 def mpmc_autotune(ctx, nrhs, prec):
@@ -655,6 +676,9 @@ class Context:
         """Pick the fastest Wilson kernel variant for (nrhs, prec) -> (variant, us per variant)."""
         return mpmc_autotune(self.handle, nrhs, prec)
 
+    def autotune_level(self, nrhs, prec=FP32):
+        return mpmc_autotune_level(self.handle, nrhs, prec)
+
     def tune_set(self, nrhs, prec, variant):
         mpmc_tune_set(self.handle, nrhs, prec, variant)
 
@@ -678,6 +702,10 @@ class Context:
     def set_site_order(self, order):
         """Traversal order of the blocked Wilson kernels (None: the default)."""
         mpmc_set_site_order(self.handle, order)
+
+    def set_graph_recurrences(self, on):
+        """Replay the fused polynomial recurrences from captured hipGraphs."""
+        mpmc_set_graph_recurrences(self.handle, on)
 
     def set_setup_precision(self, prec):
         """Storage of the Arnoldi vectors of gmres_poly and deflate (FP64 or FP32)."""

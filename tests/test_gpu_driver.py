@@ -49,10 +49,15 @@ def test_overlapped_levels_same_samples(ctx):
 
 
 def test_batched_levels_same_estimate(ctx):
-    """Polynomial terms in shared launches: the same samples bit for bit, so
-    the same estimate."""
-    e0 = driver.estimate(ctx, plan(noises=64, batch_levels=False), torch.cuda.synchronize)
-    e1 = driver.estimate(ctx, plan(noises=64, batch_levels=True), torch.cuda.synchronize)
+    """Polynomial terms in shared launches: the same samples bit for bit as the
+    terms one at a time with the same (blocked 64-wide) traversal, so the same
+    estimate."""
+    ctx.tune_set(64, mpmc.FP32, 5)
+    try:
+        e0 = driver.estimate(ctx, plan(noises=64, batch_levels=False), torch.cuda.synchronize)
+        e1 = driver.estimate(ctx, plan(noises=64, batch_levels=True), torch.cuda.synchronize)
+    finally:
+        ctx.tune_set(64, mpmc.FP32, -1)
     for L0, L1 in zip(e0.levels[1:], e1.levels[1:]):
         assert np.array_equal(L0.samples, L1.samples) and L0.corr == L1.corr
     assert np.allclose(e0.levels[0].samples, e1.levels[0].samples, rtol=0, atol=1e-9)
@@ -113,7 +118,8 @@ def test_probed_last_term_estimate(ctx, dense44):
     last = e_p.levels[-1]
     assert last.exact and last.var == 0.0 and "probed" in last.name
     Pm = OP.apply_p(op, e_p.polys[-1].roots, np.eye(op.n)).T
-    assert abs(last.mean - np.trace(Pm)) < 1e-9 * abs(np.trace(Pm))
+    # the default plan probes in FP32 arithmetic (FP64 sums): FP32 rounding per probe
+    assert abs(last.mean - np.trace(Pm)) < 1e-6 * abs(np.trace(Pm))
     exact = np.trace(dense44)
     assert 0 < e_p.stderr < 0.1 * e_s.stderr
     assert abs(e_p.value - exact) < 3 * e_p.stderr + 1e-9 * abs(exact)

@@ -94,3 +94,101 @@ def test_solve_errors(ctx):
     rejects(mpmc.EINVAL, "inner precision", mpmc.mpmc_solve, h, b, x, N, inner_prec=9)
     its, rel, rc = mpmc.mpmc_solve(h, b, x, N, tol=1e-9, inner_prec=FP32)
     assert rc == mpmc.OK and np.all(rel <= 1e-9)
+
+
+# ------------------------------------------------ forced failures (host-side) --
+
+def test_nonconvergence_reports_true_residual(ctx):
+    """max_outer = 1 with a 1e-12 target: MPMC_ENOCONV, and the reported
+    relative residual is the true one of the returned iterate (checked with
+    the oracle operator), finite and above the target."""
+    from oracle.philox import z4_noise_batch
+    from oracle.wilson import WilsonOp
+    N = 4
+    b = ctx.noise(9, 0, 0, N, FP64)
+    x = ctx.vector(N, FP64)
+    its, rel, rc = mpmc.mpmc_solve(ctx.handle, b, x, N, restart=4, tol=1e-12, inner_prec=FP32, max_outer=1,
+                                   raise_on_noconv=False)
+    assert rc == mpmc.ENOCONV and its == 4
+    assert "not converged" in mpmc.mpmc_last_error(ctx.handle)
+    op = WilsonOp(ctx.dims, ctx.kappa, ctx.links)
+    B = z4_noise_batch(9, 0, 0, N, op.n)
+    X = host(ctx.unpack(x, N))
+    true = np.linalg.norm(B - op(X), axis=1) / np.linalg.norm(B, axis=1)
+    assert np.all(np.isfinite(rel)) and np.all(rel > 1e-12)
+    assert np.allclose(rel, true, rtol=1e-6)
+    with pytest.raises(mpmc.MpmcError) as e:
+        ctx.solve(b, N, restart=4, tol=1e-12, inner_prec=FP32, max_outer=1)
+    assert e.value.rc == mpmc.ENOCONV
+
+
+def test_nan_right_hand_side_and_links_are_enumeric(ctx):
+    """A NaN in a right-hand side is rejected before any iteration; a NaN link
+    makes the first true residual non-finite: both MPMC_ENUMERIC, bounded."""
+    N = 2
+    canon = torch.zeros((N, ctx.n), dtype=torch.complex128, device="cuda")
+    canon[0, 5] = float("nan")
+    canon[1, 7] = 1.0
+    b = ctx.pack(canon, FP64)
+    rejects(mpmc.ENUMERIC, "not finite", ctx.solve, b, N, restart=8, tol=1e-8, max_outer=3)
+    U = np.array(ctx.links, copy=True)
+    U[3, 1, 0, 0] = np.nan
+    bad = mpmc.Context(ctx.dims, ctx.kappa, U)
+    bb = bad.noise(1, 0, 0, N, FP64)
+    rejects(mpmc.ENUMERIC, "not finite", bad.solve, bb, N, restart=8, tol=1e-8, inner_prec=FP32, max_outer=3)
+    # the good context is untouched
+    x, its, rel = ctx.solve(ctx.noise(1, 0, 0, N, FP64), N, restart=20, tol=1e-8, inner_prec=FP32)
+    assert np.all(rel <= 1e-8)
+
+
+def test_fp16s_pack_keeps_huge_and_tiny_sites(ctx):
+    """FP16 storage with one FP32 scale per (site, rhs): sites whose magnitudes
+    span 1e-30 .. 1e+30 keep a relative error below 2^-10 of the site maximum
+    (no overflow, no flush), and the FP16S operator on them stays finite."""
+    N = 3
+    rng = np.random.default_rng(4)
+    V = ctx.V
+    mag = 10.0 ** rng.uniform(-30, 30, size=(N, V))
+    v = (rng.standard_normal((N, V, 12)) + 1j * rng.standard_normal((N, V, 12))) * mag[:, :, None]
+    canon = torch.from_numpy(v.reshape(N, ctx.n)).cuda()
+    h = ctx.pack(canon, FP16S)
+    back = host(ctx.unpack(h, N, FP16S)).reshape(N, V, 12)
+    site_max = np.max(np.maximum(np.abs(v.real), np.abs(v.imag)), axis=2)
+    err = np.max(np.abs(back - v), axis=2) / site_max
+    assert np.all(np.isfinite(back)) and np.max(err) < 2.0 ** -10
+    y = host(ctx.unpack(ctx.apply_M(h, N, FP16S), N, FP16S))
+    assert np.all(np.isfinite(y))
+
+
+def test_garbage_deflation_set_keeps_levels_unbiased():
+    """A random (garbage) deflation set imported to the GPU: the deflated
+    polynomial-difference level still has the dense exact expectation
+    Tr(p_a - p_b) (the correction is exact for any triples), per sample equal
+    to the oracle's, and the sampled mean is within 3.5 standard errors."""
+    from oracle import deflation as ODF
+    from oracle import estimator as OES
+    from oracle import krylov as OK
+    from oracle import poly as OP
+    from oracle.philox import z4_noise
+    from oracle.wilson import WilsonOp
+    dims, kappa = (4, 4, 4, 4), 0.115
+    U = inputs.gauge_links(dims, 0.5, seed=1)
+    op, c = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    b = z4_noise(1, 0x100, 0, op.n)
+    Pa, _, _ = OK.gmres_poly(op, b, 9)
+    Pb, _, _ = OK.gmres_poly(op, b, 3)
+    rng = np.random.default_rng(11)
+    k = 5
+    junk = ODF.Deflation(rng.standard_normal(k) + 0.3j * rng.standard_normal(k),
+                         rng.standard_normal((k, op.n)) + 1j * rng.standard_normal((k, op.n)),
+                         rng.standard_normal((k, op.n)) + 1j * rng.standard_normal((k, op.n)))
+    D = c.defl_from_arrays(junk.lam, torch.from_numpy(junk.Z).cuda(), torch.from_numpy(junk.U).cuda())
+    ga, gb = c.poly_from_roots(Pa.roots), c.poly_from_roots(Pb.roots)
+    N = 256
+    X, T, _ = c.level(ga, gb, D, 0, 4, 2, 0, N, prec=FP64)
+    Xr, Tr = OES.level_samples(op, Pa, Pb, junk, "I", 4, 2, 0, N)
+    assert np.max(np.abs(X - Xr)) < 1e-9 * max(1.0, np.max(np.abs(Xr)))
+    assert abs(T - Tr) < 1e-9 * max(1.0, abs(Tr))
+    exact = np.trace(OP.apply_poly(op, Pa, np.eye(op.n)).T - OP.apply_poly(op, Pb, np.eye(op.n)).T)
+    m, v = OES.level_stats(X)
+    assert abs(m + T - exact) < 3.5 * np.sqrt(v / N)

@@ -360,13 +360,22 @@ def test_levels_multi_equal_one_at_a_time(f44, prec, theta):
     los = [g2, g3, g0, g3, None]
     streams = [1, 2, 3, 4, 5]
     N = 64
-    Xs, Ts, mv = ctx.levels_multi(ups, los, D, theta, 3, streams, 7, N, prec=prec)
-    mv_one = 0
-    for t, (u, l) in enumerate(zip(ups, los)):
-        X, T, m = ctx.level(u, l, D if l is not None else None, theta, 3, streams[t], 7, N, prec=prec)
-        assert np.array_equal(Xs[t], X), t
-        assert Ts[t] == T
-        mv_one += m
+    ctx.tune_set(N, prec, 5)   # the blocked 64-wide traversal of the shared launches, also for the fallbacks
+    try:
+        Xs, Ts, mv = ctx.levels_multi(ups, los, D, theta, 3, streams, 7, N, prec=prec)
+        mv_one = 0
+        for t, (u, l) in enumerate(zip(ups, los)):
+            X, T, m = ctx.level(u, l, D if l is not None else None, theta, 3, streams[t], 7, N, prec=prec)
+            assert np.array_equal(Xs[t], X), t
+            assert Ts[t] == T
+            mv_one += m
+        # any other traversal groups the FP64 partial sums differently: the
+        # sample (a difference of two forms of size ~n) moves by ~1e-16 n
+        ctx.tune_set(N, prec, -1)
+        X, _, _ = ctx.level(ups[0], los[0], D, theta, 3, streams[0], 7, N, prec=prec)
+        assert np.max(np.abs(X - Xs[0])) < 1e-12 * op.n
+    finally:
+        ctx.tune_set(N, prec, -1)
     assert mv == mv_one
     Xr, Tr = OES.level_samples(op, P1, P2, Dref, "g5" if theta else "I", 3, 1, 7, N)
     assert abs(Ts[0] - Tr) < 1e-10 * max(1, abs(Tr))
@@ -556,7 +565,7 @@ def test_autotune_variants_bit_identical(f44, prec):
     assert ctx.autotune(20, prec)[0] == -1     # not a multiple of 64: nothing to tune
 
 
-@pytest.mark.parametrize("prec,variants", [(FP32, (1, 3, 5, 7, 9)), (FP64, (0, 2, 4, 6, 8))])
+@pytest.mark.parametrize("prec,variants", [(FP32, (1, 3, 5, 7, 9, 10)), (FP64, (0, 2, 4, 6, 8))])
 def test_fused_level_step_traversals(f44, prec, variants):
     """The fused level step under each traversal (site-major, chunk-major,
     4D-blocked with 64-, 16- and 32-wide chunks and their per-chunk
@@ -810,6 +819,7 @@ def test_fp32_setup_polynomials_and_deflation():
     op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
     b = z4_noise(1, 0x100, 0, op.n)
     P64 = ctx.gmres_poly(1, 0x100, 12)
+    Pin = ctx.gmres_poly(1, 0x100, 5)   # FP64 p_in for both deflation builds
     ctx.set_setup_precision(FP32)
     try:
         P32 = ctx.gmres_poly(1, 0x100, 12)
@@ -817,14 +827,14 @@ def test_fp32_setup_polynomials_and_deflation():
         assert _match_sets(P32.roots, P64.roots) < 1e-4 * np.max(np.abs(P64.roots))
         r = OP.apply_pi(op, P32.roots, b)
         assert abs(np.linalg.norm(r) / np.linalg.norm(b) - P32.relres) < 1e-4 * P32.relres + 1e-7
-        Pin = ctx.poly_from_roots(P64.roots[:5])
-        D32 = ctx.deflate(Pin, 1, 0x200, m=60, nev=10)
+        # m = 120: ten pairs converged far below the 1e-3 acceptance (oracle: residuals <= 2e-7)
+        D32 = ctx.deflate(Pin, 1, 0x200, m=120, nev=10)
         lam32, Z32, U32 = ctx.defl_vectors(D32)
     finally:
         ctx.set_setup_precision(FP64)
-    D64 = ctx.deflate(Pin, 1, 0x200, m=60, nev=10)
+    D64 = ctx.deflate(Pin, 1, 0x200, m=120, nev=10)
     lam64, _, _ = ctx.defl_vectors(D64)
-    assert D32.k >= 1 and abs(D32.k - D64.k) <= 1
+    assert D32.k >= 8 and abs(D32.k - D64.k) <= 1
     assert _match_sets(lam32, lam64) < 1e-5
     Zh, Uh = Z32.cpu().numpy(), U32.cpu().numpy()
     for i in range(D32.k):
@@ -832,3 +842,45 @@ def test_fp32_setup_polynomials_and_deflation():
         assert np.linalg.norm(op(Zh[i]) - lam32[i] * Zh[i]) < 1e-3
     with pytest.raises(mpmc.MpmcError):
         ctx.set_setup_precision(FP16S)
+
+
+# ------------------------------------------------ captured recurrences --
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_graph_recurrences_bit_identical(prec):
+    """mpmc_set_graph_recurrences: the fused recurrences of the polynomial
+    levels (single and double polynomials, deflated level) replayed from
+    captured hipGraphs give the samples of the launches run one by one, bit
+    for bit, on every one of several replays with unrelated eager work and
+    synchronisations in between, and again after the workspace is released."""
+    dims, kappa = (4, 4, 4, 4), 0.115
+    U = inputs.gauge_links(dims, 0.5, seed=1)
+    op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    b = z4_noise(1, 0x100, 0, op.n)
+    P1, _, _ = OK.gmres_poly(op, b, 9)
+    Dp, _, _ = OP.double_poly(op, b, 3, 4)
+    Pin, _, _ = OK.gmres_poly(op, b, 4)
+    Dref, _ = ODF.pp_arnoldi_eigs(op, Pin.roots, z4_noise(1, 0x200, 0, op.n), 60, 8)
+    D = ctx.defl_from_arrays(Dref.lam, torch.from_numpy(Dref.Z).cuda(), torch.from_numpy(Dref.U).cuda())
+    g1 = ctx.poly_from_roots(P1.roots)
+    gd = ctx.poly_from_roots(Dp.roots, inner=ctx.poly_from_roots(Dp.inner.roots))
+    N = 64
+    cases = [(gd, g1, D), (g1, None, None)]
+    want = [ctx.level(u, l, d, 1, 5, 2, 0, N, prec=prec) for u, l, d in cases]
+    ctx.set_graph_recurrences(1)
+    try:
+        for rep in range(4):
+            for (u, l, d), (Xw, Tw, mw) in zip(cases, want):
+                X, T, mv = ctx.level(u, l, d, 1, 5, 2, 0, N, prec=prec)
+                assert np.array_equal(X, Xw) and T == Tw and mv == mw, rep
+            y = ctx.apply_M(ctx.noise(3, 0, 0, 8, prec), 8, prec)          # eager work in between
+            float(torch.sum(y.view(torch.float32)).item())
+            if rep == 1:
+                ctx.release_workspace()
+                assert mpmc.mpmc_graph_replays(ctx.handle)[1] == 0
+        replays, graphs = mpmc.mpmc_graph_replays(ctx.handle)
+        assert replays >= 6 and graphs >= 1
+    finally:
+        ctx.set_graph_recurrences(0)
+    X, _, _ = ctx.level(g1, None, None, 1, 5, 2, 0, N, prec=prec)
+    assert np.array_equal(X, want[1][0])
