@@ -202,6 +202,24 @@ int mpmc_poly_add_roots(mpmc_poly *p, double log10_threshold, double digits, int
 int mpmc_apply_poly(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y,
                     int nrhs, int prec);
 
+/* mpmc_apply_poly for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result bit for bit, with its work vectors (2 for a
+ * single polynomial, 6 for a double one, each mpmc_vector_bytes(nrhs, prec)
+ * rounded up to 256 bytes) in one fixed 64 MiB device array of the library
+ * that every GPU it runs on holds until the process ends (its address is
+ * taken in mpmc_create).  No hipMalloc, hipFree or event creation happens in
+ * the call.  Every call on one GPU shares that GPU's array, from every context
+ * and thread: calls that overlap on one GPU (two streams, two threads, a
+ * second call before the first has finished on the device) race and give
+ * undefined results; calls ordered on one stream are safe.  The array keeps
+ * the last call's contents; no part of it needs to start at zero.  Errors:
+ * MPMC_EINVAL for bad arguments, aliasing x and y, precisions other than FP64
+ * and FP32, and work vectors beyond 64 MiB (message names the limit);
+ * MPMC_ESTATE while launch timing is on (it creates events). */
+int mpmc_apply_poly_noalloc(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y,
+                            int nrhs, int prec);
+
 /* Exact Tr(Theta p(M)) by probing (Sec. 6: the last term of the
  * multipolynomial formula is computed exactly with probing).  Sites are
  * coloured by c(x) = sum_mu (x_mu mod period[mu]) prod_{nu<mu} period[nu]

@@ -377,6 +377,9 @@ int poly_apply_internal(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *
 int poly_work_vectors(const mpmc_poly *p);
 int poly_apply_buf(mpmc_ctx *ctx, const mpmc_poly *p, const void *x, void *y, int nrhs, int prec, void *const *buf);
 int poly_validate(const mpmc_ctx *ctx, const mpmc_poly *p);
+// Device address of `device`'s copy of the fixed scratch array of
+// mpmc_apply_poly_noalloc (looked up once per device); nullptr on failure.
+void *noalloc_scratch(int device);
 // acc[r] += sign * eta_r^H Theta p(M) eta_r without forming p(M) eta (fused steps)
 int poly_quad_fused(mpmc_ctx *ctx, const mpmc_poly *p, const void *eta, const uint32_t *codes, int nrhs, int prec,
                     int theta, double *acc, double sign);

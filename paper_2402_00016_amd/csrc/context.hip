@@ -257,6 +257,13 @@ MPMC_API int mpmc_create(const int dims[4], double kappa, int t_antiperiodic, co
         mpmc_destroy(c);
         return MPMC_ENOMEM;
     }
+    // the device address of this device's copy of the fixed no-allocation
+    // scratch array, taken once with the device current
+    if (!noalloc_scratch(c->device)) {
+        set_err(nullptr, MPMC_EHIP, "mpmc_create: no device address for the scratch array of mpmc_apply_poly_noalloc");
+        mpmc_destroy(c);
+        return MPMC_EHIP;
+    }
     *out = c;
     return MPMC_OK;
 }

@@ -60,6 +60,7 @@ _SIGS = {
     "mpmc_poly_destroy": ([_vp], None),
     "mpmc_poly_add_roots": ([_vp, _d, _d, _pi], _i),
     "mpmc_apply_poly": ([_vp, _vp, _vp, _vp, _i, _i], _i),
+    "mpmc_apply_poly_noalloc": ([_vp, _vp, _vp, _vp, _i, _i], _i),
     "mpmc_poly_trace": ([_vp, _vp, _i, _pi, _i, _i, _vp, _pi, _pu64], _i),
     "mpmc_deflate": ([_vp, _vp, _u64, _u32, _i, _i, _d, _d, ctypes.POINTER(_vp), _pi], _i),
     "mpmc_defl_create": ([_vp, _vp, _vp, _vp, _i, ctypes.POINTER(_vp)], _i),
@@ -225,6 +226,10 @@ def mpmc_poly_destroy(handle):
 
 def mpmc_apply_poly(ctx, poly, x, y, nrhs, prec):
     _check(_L.mpmc_apply_poly(ctx, _h(poly), _ptr(x), _ptr(y), int(nrhs), int(prec)), ctx)
+
+
+def mpmc_apply_poly_noalloc(ctx, poly, x, y, nrhs, prec):
+    _check(_L.mpmc_apply_poly_noalloc(ctx, _h(poly), _ptr(x), _ptr(y), int(nrhs), int(prec)), ctx)
 
 
 def mpmc_poly_trace(ctx, poly, theta, period, prec, max_batch=0):
