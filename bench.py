@@ -57,6 +57,8 @@ def parse():
                     help="last term exactly by probing (distance colouring) in every form")
     ap.add_argument("--no-probe-report", action="store_true",
                     help="skip the extra estimate with the probed last term")
+    ap.add_argument("--solve-prec", choices=["fp32", "fp16s"], default=None,
+                    help="Krylov basis storage of the mixed form's main solves (default: the workload's)")
     ap.add_argument("--solve-pp", action="store_true",
                     help="main solves of the mixed and plain forms as polynomial-preconditioned GMRES (p_in)")
     ap.add_argument("--net-source", choices=["random", "solve"], default="solve",
@@ -174,6 +176,10 @@ def level_report(est):
              "corr": [L.corr.real, L.corr.imag], "mvps": L.mvps, "s": round(L.seconds, 4)} for L in est.levels]
 
 
+def progress(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -186,7 +192,9 @@ def main():
     from paper_2402_00016_amd import driver, inputs, mpmc
 
     torch.cuda.set_device(0)
-    W = WORKLOADS[a.workload]
+    W = dict(WORKLOADS[a.workload])
+    if a.solve_prec:
+        W["solve_prec"] = a.solve_prec
     dims, eps, seed, kappa = W["dims"], W["eps"], W["seed"], W["kappa"]
     noises = a.noises or W["noises"]
     links = inputs.gauge_links(dims, eps, seed)
@@ -207,8 +215,9 @@ def main():
         dst.copy_(src)
         sync()
         del src, dst
-    for _ in range(a.warmup):
+    for i in range(a.warmup):
         driver.estimate(ctx, plan, sync)
+        progress("warm-up step %d done" % (i + 1))
     # the side contexts (setup work on other streams) exist after the warm-up
     sides = [c for c, _ in ctx._side.values()]
     for c in [ctx] + sides:
@@ -218,6 +227,7 @@ def main():
     ests = [driver.estimate(ctx, plan, sync) for _ in range(a.steps)]
     sync()
     t1 = time.perf_counter()
+    progress("%d timed steps done (%.3f s/step)" % (a.steps, (t1 - t0) / a.steps))
 
     def timing(prec):
         n = ms = by = 0.0
@@ -307,6 +317,7 @@ def main():
         sync()
         tq = time.perf_counter() - tq
         Lq = ep.levels[-1]
+        progress("probed-last estimate done")
         out["trace"]["probed_last"] = {"value": [ep.value.real, ep.value.imag], "stderr": ep.stderr,
                                        "s": round(tq, 4), "last_term": Lq.name, "last_term_s": round(Lq.seconds, 4),
                                        "last_term_mvps": Lq.mvps, "mvps": ep.mvps}
@@ -328,12 +339,22 @@ def main():
         net, hist = driver.train_net(ctx, lplan)
         sync()
         t_train = time.perf_counter() - tl
+        progress("network trained (%.3f s)" % t_train)
         driver.estimate(ctx, lplan, sync, net=net)
         tl, tls, el = timed_runs(lambda: driver.estimate(ctx, lplan, sync, net=net), a.compare_runs)
         out["time_to_error_s"]["learned_batched"] = round(tl, 4)
         out["time_to_error_s"]["learned_runs"] = [round(t, 4) for t in tls]
         out["time_to_error_s"]["net_training"] = round(t_train, 4)
-        out["time_to_error_s"]["learned_batched_incl_training"] = round(tl + t_train, 4)
+        out["time_to_error_s"]["learned_plus_separate_training"] = round(tl + t_train, 4)
+        # from scratch: each estimate trains its own network inside its set-up
+        # (side stream, overlapped with the deflation and polynomial builds)
+        ctx.release_workspace()
+        torch.cuda.empty_cache()
+        driver.estimate(ctx, lplan, sync)
+        ti, tis, ei = timed_runs(lambda: driver.estimate(ctx, lplan, sync), a.compare_runs)
+        progress("learned estimates with in-setup training done (%.3f s)" % ti)
+        out["time_to_error_s"]["learned_batched_incl_training"] = round(ti, 4)
+        out["time_to_error_s"]["learned_incl_training_runs"] = [round(t, 4) for t in tis]
         out["solve_term"]["learned_batched"] = solve_term(el)
         out["net"] = {"source": lplan.net_source, "minibatches": len(hist) // lplan.net_steps,
                       "pairs": len(hist) // lplan.net_steps * lplan.net_pairs, "adam_steps": len(hist),
@@ -360,10 +381,13 @@ def main():
         out["trace"]["plain_fp64"] = {"value": [e64.value.real, e64.value.imag], "stderr": e64.stderr,
                                       "diff_in_combined_sigma": abs(est.value - e64.value) / comb}
         # per term: (mixed mean - FP64 mean) / FP64 standard error of the mean, same noise
+        # and against the FP64 estimate's total standard error (what the bias adds to the result)
         out["trace"]["fp32_bias_in_fp64_sigma"] = [
             {"name": Lm.name, "ratio": float(abs((Lm.mean + Lm.corr) - (Lp.mean + Lp.corr)) /
                                              max(np.sqrt(Lp.var / Lp.n), 1e-300)),
-             "fp64_sigma": float(np.sqrt(Lp.var / Lp.n))} for Lm, Lp in zip(est.levels, e64.levels)]
+             "fp64_sigma": float(np.sqrt(Lp.var / Lp.n)),
+             "ratio_to_total_sigma": float(abs((Lm.mean + Lm.corr) - (Lp.mean + Lp.corr)) / max(e64.stderr, 1e-300))}
+            for Lm, Lp in zip(est.levels, e64.levels)]
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(dims, kappa, links, a.cpu_seconds, est.mvps)
     print(json.dumps(out))

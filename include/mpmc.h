@@ -323,9 +323,27 @@ int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl 
 int mpmc_apply_M_batch(mpmc_ctx *const *ctxs, const void *const *x, void *const *y, int count, int nrhs,
                        int prec, int dagger, int theta);
 
+/* mpmc_solve for several lattices at once (not in the paper: batching of
+ * independent problems, e.g. uneven lattices that share one network): the
+ * contexts ctxs[0..count), 1 <= count <= 8, distinct, on one device and one
+ * stream, each with its own b[i], x[i] (nrhs FP64 internal-layout vectors,
+ * nrhs a multiple of 64, the same for all), deflation set defl[i] and network
+ * net[i] (defl, net or their entries may be NULL).  The solves advance in
+ * lockstep: every inner iteration applies M on all lattices still iterating
+ * with ONE mpmc_apply_M_batch launch; Gram-Schmidt, Givens steps and the
+ * outer loop stay per lattice.  inner_prec FP64 or FP32.  Each lattice's
+ * iterates equal those of its own mpmc_solve with Wilson variant 4/5 (the
+ * batched launch's traversal; every variant gives the same bits).  Outputs
+ * (host, may be NULL): iters_host[count], relres_host[count * nrhs].
+ * Returns the first failing lattice's code (MPMC_ENOCONV when one did not
+ * converge; every lattice still runs to its end).  Synchronises. */
+int mpmc_solve_batch(mpmc_ctx *const *ctxs, int count, const void *const *b, void *const *x, int nrhs,
+                     const mpmc_defl *const *defl, const mpmc_net *const *net, int restart, double tol,
+                     int inner_prec, int max_outer, int *iters_host, double *relres_host);
+
 /* ---------------------------------------------------------------- autotuner */
 /* The multi-RHS Wilson kernel (nrhs a multiple of 64) has variants
- * 0 .. mpmc_wilson_variant_count() - 1 (currently 11) that differ only in how
+ * 0 .. mpmc_wilson_variant_count() - 1 (currently 12) that differ only in how
  * the work is laid out on the GPU, never in the arithmetic (results are
  * bit-identical):
  *   0-9, bit 0 -- occupancy target: 1 = more wavefronts per SIMD (FP32/FP16S:
@@ -344,7 +362,11 @@ int mpmc_apply_M_batch(mpmc_ctx *const *ctxs, const void *const *x, void *const 
  *               columns and 64 right-hand sides and walks the columns along
  *               t; the t-1 and the in-tile x, y, z neighbours come from LDS,
  *               the t+1 site from registers, so each site's spinor is read
- *               from memory 4 times instead of 9.
+ *               from memory 4 times instead of 9;
+ *   11       -- column streaming with 2 x 2 x 1 tiles (FP32, even Lx, Ly,
+ *               Lt >= 4; else 5): 4 wavefronts per workgroup and half the
+ *               LDS, so two workgroups share a compute unit; both z
+ *               neighbours come from memory (5 reads per site).
  * Defaults: variant 10 where it applies (FP32), else 5 for FP32/FP16S and 4
  * for FP64.
  * mpmc_autotune times every variant on (nrhs, prec) with scratch vectors of
@@ -360,19 +382,23 @@ int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host, double *
 int mpmc_wilson_variant_count(void);
 /* Pin a variant for (nrhs, prec); -1 restores the default.  A pinned variant
  * also fixes the traversal of the fused polynomial step of the level
- * estimators (variants 0-3: site-major, 4-9: blocked chunks, 10: column
- * streaming), overriding mpmc_autotune_level. */
+ * estimators (variants 0-3: site-major, 4-9: blocked chunks, 10 and 11:
+ * column streaming with 2x2x2 and 2x2x1 tiles), overriding
+ * mpmc_autotune_level.  For nrhs = 1 (single vectors) variant 0 selects
+ * eight lanes per site (one hop each), 1 one site per lane; the default is 0
+ * up to 12^4 sites and 1 above. */
 int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant);
 /* Autotune the fused polynomial step of mpmc_level_estimate (the dominant
  * kernel of the polynomial levels, Sec. 6): every traversal valid for the
  * shape -- order 0 site-major, 2 blocked 64-wide chunks, 3 / 4 blocked 16- /
- * 32-wide chunks (V % 16 == 0), 5 column streaming (FP32, as variant 10) --
+ * 32-wide chunks (V % 16 == 0), 5 / 6 column streaming (FP32, as variants
+ * 10 / 11) --
  * is timed on (nrhs, prec) (2 warm-up + 5 timed steps, HIP events) and the
  * fastest is kept for later level estimates on ctx.  Without this call the
  * step takes the column streaming kernel where it applies, else blocked
  * 64-wide chunks (V % 4 == 0), else site-major.  prec FP64 or FP32, nrhs a
  * multiple of 64 (and of 256 above 256).  order_host (may be NULL): the
- * choice; us_host (may be NULL): double[6] microseconds per step by order (0
+ * choice; us_host (may be NULL): double[7] microseconds per step by order (0
  * for orders not tried).  Samples are the same up to the grouping of the FP64
  * partial sums.  Does not count MVPs.  Synchronises. */
 int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_host, double *us_host);

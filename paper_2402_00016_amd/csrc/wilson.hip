@@ -566,8 +566,9 @@ struct Occ {
 // chunk-major, 2 chunk-major over the blocked site order, 3 and 4 the same with
 // 16- and 32-wide chunks, four and two sites per wavefront and per-lane
 // links).  Orders 3 and 4 need V % 16 == 0; elsewhere they fall back to 2.
-constexpr int WILSON_VARIANTS = 11;
-constexpr int WILSON_COLUMN = 10;   // FP32 column-streaming kernel (k_wilson_col)
+constexpr int WILSON_VARIANTS = 12;
+constexpr int WILSON_COLUMN = 10;    // FP32 column-streaming kernel (k_wilson_col), 2x2x2 tiles
+constexpr int WILSON_COLUMN1 = 11;   // the same with 2x2x1 tiles (two workgroups per compute unit)
 
 // Everything one thread does for (site s, rhs r) once located.
 template <int P, bool UNI, int ORDER>
@@ -1074,18 +1075,20 @@ __global__ void k_noise_codes(uint64_t seed, uint32_t stream, uint64_t first, ui
 // slices (t-1, t, and the one being written next) so that one barrier per
 // step orders all writes and reads.  Requires even Lx, Ly, Lz, Lt >= 4 and
 // nrhs % 64 == 0.
-constexpr int COL_WAVES = 8;
+template <int TZ>
+constexpr int col_waves() { return 4 * TZ; }
 
 struct ColArgs {
     int L[4];
     int ntx, nty, ntz;   // tiles per direction
+    int bx, by, bz;      // tiles per block of the traversal (each divides its extent)
     long ntiles;         // tiles per 64-wide chunk
     int tap;             // antiperiodic time direction
 };
 
-template <int P>
+template <int TZ>
 struct ColLds {
-    float2 v[3][COL_WAVES][12][64];
+    float2 v[3][col_waves<TZ>()][12][64];
 };
 
 // hop MU (forward or backward) from a spinor held by the lane
@@ -1101,7 +1104,8 @@ __device__ __forceinline__ void col_hop(const cpx<float> (&psi)[12], uint32_t lw
     __builtin_amdgcn_sched_barrier(0);   // hops one after another: short live ranges
 }
 
-__device__ __forceinline__ void col_lds_read(const ColLds<MPMC_FP32> &L, int buf, int w, unsigned lane,
+template <int TZ>
+__device__ __forceinline__ void col_lds_read(const ColLds<TZ> &L, int buf, int w, unsigned lane,
                                              cpx<float> (&psi)[12]) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) {
@@ -1124,8 +1128,8 @@ __device__ __forceinline__ long col_site(const ColArgs &c, int x, int y, int z, 
 // partner across the tile, from LDS) and the out-of-tile one (og, global
 // memory; forward if the column sits at the tile's upper edge, else
 // backward).  lf: U_mu(s), lb: U_mu(s - mu), both lane-distributed.
-template <int MU>
-__device__ __forceinline__ void col_dir(const ColLds<MPMC_FP32> &L, int curb, int w, unsigned lane, int upper,
+template <int MU, int TZ>
+__device__ __forceinline__ void col_dir(const ColLds<TZ> &L, int curb, int w, unsigned lane, int upper,
                                         const cpx<float> (&og)[12], uint32_t lf, uint32_t lb, float g,
                                         cpx<float> acc[4][3]) {
     cpx<float> nb[12];
@@ -1142,28 +1146,46 @@ __device__ __forceinline__ void col_dir(const ColLds<MPMC_FP32> &L, int curb, in
 
 // MODE 0: plain apply with the WOut epilogue (FP32 out, no FP16S);
 // MODE 1: fused level step (w' = w - c M w [combined with a], eta^H Theta w').
-// Per step t of a column: the loads of the t+1 site, the three out-of-tile
+// Per step t of a column: the loads of the t+1 site, the out-of-tile
 // neighbours and the links are issued first; after the barrier the LDS hops
 // run while they arrive; the t+1 site is then published for step t+1.
-template <int MODE, bool CMB>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_wilson_col(
+// TZ = 2: 2x2x2 tiles, eight wavefronts, 144 KB of LDS (one workgroup per
+// compute unit; every step of a compute unit waits on one barrier).  TZ = 1:
+// 2x2x1 tiles, four wavefronts, 72 KB, both z neighbours from global memory
+// (five reads per site instead of four) but two independent workgroups per
+// compute unit, so one's loads overlap the other's arithmetic.
+template <int MODE, bool CMB, int TZ>
+__global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) void k_wilson_col(
     const void *__restrict__ b, const float2 *__restrict__ links, ColArgs ca, int N, WOut o,
     const uint32_t *__restrict__ codes, double2 c, double2 cnext, int theta, double2 *__restrict__ partial,
     int first_step, const void *__restrict__ a2, double2 alpha, double2 beta) {
     using T = float;
-    __shared__ ColLds<MPMC_FP32> L;
-    const int w = (int)(threadIdx.x >> 6);
+    __shared__ ColLds<TZ> L;
+    // the wavefront index as a scalar: every site index below is then uniform,
+    // and the buffer descriptors built from it stay in SGPRs (a per-lane
+    // descriptor would make the compiler loop over lanes for each load)
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const unsigned lane = threadIdx.x & 63u;
-    const int wx = w & 1, wy = (w >> 1) & 1, wz = w >> 2;
+    const int wx = w & 1, wy = (w >> 1) & 1, wz = TZ == 2 ? w >> 2 : 0;
+    // an XCD's contiguous tile range walks blocks of bx x by x bz tiles, so
+    // the workgroups it runs at once hold a compact 3D region whose columns
+    // advance along t together: most out-of-tile neighbours were just
+    // fetched into the XCD's L2 by the workgroup that owns them
     const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
     const long chunk = (long)tile / ca.ntiles, tl = (long)tile - chunk * ca.ntiles;
-    const int tx = (int)(tl % ca.ntx), ty = (int)((tl / ca.ntx) % ca.nty), tz = (int)(tl / ((long)ca.ntx * ca.nty));
-    const int x = 2 * tx + wx, y = 2 * ty + wy, z = 2 * tz + wz, Lt = ca.L[3];
+    const int bsz = ca.bx * ca.by * ca.bz, nbx = ca.ntx / ca.bx, nby = ca.nty / ca.by;
+    const long blk = tl / bsz;
+    const int in = (int)(tl - blk * bsz);
+    const int tx = (int)(blk % nbx) * ca.bx + in % ca.bx;
+    const int ty = (int)((blk / nbx) % nby) * ca.by + (in / ca.bx) % ca.by;
+    const int tz = (int)(blk / ((long)nbx * nby)) * ca.bz + in / (ca.bx * ca.by);
+    const int x = 2 * tx + wx, y = 2 * ty + wy, z = TZ * tz + wz, Lt = ca.L[3];
     const uint32_t r = (uint32_t)(chunk * 64 + lane);
-    // out-of-tile neighbour coordinates (forward at the tile's upper edge, else backward)
+    // out-of-tile neighbour coordinates (forward at the tile's upper edge, else
+    // backward; TZ = 1: zo is the forward z neighbour, zb the backward one)
     const int xo = wx ? (x + 1 == ca.L[0] ? 0 : x + 1) : (x == 0 ? ca.L[0] - 1 : x - 1);
     const int yo = wy ? (y + 1 == ca.L[1] ? 0 : y + 1) : (y == 0 ? ca.L[1] - 1 : y - 1);
-    const int zo = wz ? (z + 1 == ca.L[2] ? 0 : z + 1) : (z == 0 ? ca.L[2] - 1 : z - 1);
+    const int zo = (TZ == 1 || wz) ? (z + 1 == ca.L[2] ? 0 : z + 1) : (z == 0 ? ca.L[2] - 1 : z - 1);
     // backward-neighbour coordinates (their forward links are this site's backward links)
     const int xb = x == 0 ? ca.L[0] - 1 : x - 1, yb = y == 0 ? ca.L[1] - 1 : y - 1, zb = z == 0 ? ca.L[2] - 1 : z - 1;
     const float g = o.g;
@@ -1182,20 +1204,30 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     load_link_lanes<MPMC_FP32>(links + (col_site(ca, x, y, z, Lt - 1) * 4 + 3) * 9, ltprev);
     cpx<double> dot = mk(0.0, 0.0);
 
+    // The out-of-tile neighbours of step t+1 are fetched during step t, each
+    // into the registers its step-t value has just left (loop-carried): they
+    // then travel to the L2 together with the neighbouring tiles' own loads
+    // of slice t+1 (which those tiles issue during step t as well), so most of
+    // them are served by the XCD's L2 instead of memory.
+    cpx<float> ogx[12], ogy[12], ogz[12];
+    col_load(b, col_site(ca, xo, y, z, 0), N, r, ogx);
+    col_load(b, col_site(ca, x, yo, z, 0), N, r, ogy);
+    col_load(b, col_site(ca, x, y, zo, 0), N, r, ogz);
+
     for (int t = 0; t < Lt; ++t) {
         const int curb = t % 3, prevb = (t + 2) % 3, nextb = (t + 1) % 3;
         const long s = col_site(ca, x, y, z, t);
-        // global traffic of the step: the t+1 site, the out-of-tile neighbours, the links
-        cpx<float> nx[12], ogx[12], ogy[12], ogz[12];
-        col_load(b, col_site(ca, x, y, z, t + 1 < Lt ? t + 1 : 0), N, r, nx);
-        col_load(b, col_site(ca, xo, y, z, t), N, r, ogx);
-        col_load(b, col_site(ca, x, yo, z, t), N, r, ogy);
+        const bool more = t + 1 < Lt;
+        // global traffic of the step: the t+1 site, the links and the noise code
+        cpx<float> nx[12];
+        col_load(b, col_site(ca, x, y, z, more ? t + 1 : 0), N, r, nx);
         uint32_t lf[4][1], lb[3][1];
 #pragma unroll
         for (int mu = 0; mu < 4; ++mu) load_link_lanes<MPMC_FP32>(links + (s * 4 + mu) * 9, lf[mu]);
         load_link_lanes<MPMC_FP32>(links + (col_site(ca, xb, y, z, t) * 4 + 0) * 9, lb[0]);
         load_link_lanes<MPMC_FP32>(links + (col_site(ca, x, yb, z, t) * 4 + 1) * 9, lb[1]);
         load_link_lanes<MPMC_FP32>(links + (col_site(ca, x, y, zb, t) * 4 + 2) * 9, lb[2]);
+        const uint32_t code = MODE == 1 ? codes[s * N + r] : 0u;
         // slice t of every column of the tile (published one step ahead) is now
         // visible, and every read of step t-1 is done (three buffers rotate)
         __syncthreads();
@@ -1207,12 +1239,33 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
             for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = mk(0.f, 0.f);
         // hops in the order of every Wilson kernel: x, y, z, t, forward first
         col_dir<0>(L, curb, w, lane, wx, ogx, lf[0][0], lb[0][0], g, acc);
-        // the z neighbour's loads start once the x one is consumed (register budget)
         __builtin_amdgcn_sched_barrier(0);
-        col_load(b, col_site(ca, x, y, zo, t), N, r, ogz);
+        if constexpr (TZ == 2) {
+            if (more) col_load(b, col_site(ca, xo, y, z, t + 1), N, r, ogx);
+        } else {
+            // the backward z neighbour (both z neighbours are outside a 2x2x1 tile)
+            col_load(b, col_site(ca, x, y, zb, t), N, r, ogx);
+        }
         __builtin_amdgcn_sched_barrier(0);
         col_dir<1>(L, curb, w, lane, wy, ogy, lf[1][0], lb[1][0], g, acc);
-        col_dir<2>(L, curb, w, lane, wz, ogz, lf[2][0], lb[2][0], g, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) col_load(b, col_site(ca, x, yo, z, t + 1), N, r, ogy);
+        __builtin_amdgcn_sched_barrier(0);
+        if constexpr (TZ == 2) {
+            col_dir<2>(L, curb, w, lane, wz, ogz, lf[2][0], lb[2][0], g, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) col_load(b, col_site(ca, x, y, zo, t + 1), N, r, ogz);
+            __builtin_amdgcn_sched_barrier(0);
+        } else {
+            col_hop<MPMC_FP32, 2, true>(ogz, lf[2][0], 1.f, g, acc);
+            col_hop<MPMC_FP32, 2, false>(ogx, lb[2][0], 1.f, g, acc);
+            __builtin_amdgcn_sched_barrier(0);
+            if (more) {
+                col_load(b, col_site(ca, x, y, zo, t + 1), N, r, ogz);
+                col_load(b, col_site(ca, xo, y, z, t + 1), N, r, ogx);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
         col_hop<MPMC_FP32, 3, true>(nx, lf[3][0], (ca.tap && t == Lt - 1) ? -1.f : 1.f, g, acc);
         {   // t backward: the own column's previous slice
             cpx<float> pv[12];
@@ -1258,7 +1311,6 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                 for (int k = 0; k < 12; ++k) Y.st(k, yv[k] + ga * res[k]);
             }
         } else {
-            const uint32_t code = codes[s * N + r];
             const cpx<T> ccf = mk((T)c.x, (T)c.y);
             cpx<T> av[12];
             if constexpr (CMB) {
@@ -1293,7 +1345,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
         if (threadIdx.x < 64) {
             double sx = 0, sy = 0;
 #pragma unroll
-            for (int q = 0; q < COL_WAVES; ++q) {
+            for (int q = 0; q < col_waves<TZ>(); ++q) {
                 sx += red[q * 64 + threadIdx.x].x;
                 sy += red[q * 64 + threadIdx.x].y;
             }
@@ -1313,17 +1365,27 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
 
 static double spinor_bytes(int prec) { return prec == MPMC_FP64 ? 192.0 : (prec == MPMC_FP32 ? 96.0 : 52.0); }
 
-// The column-streaming kernel needs even Lx, Ly, Lz, Lt >= 4, FP32 and 64-wide chunks.
-static bool col_ok(const mpmc_ctx *ctx, int nrhs, int prec) {
+// The column-streaming kernel needs even Lx, Ly (and Lz for 2x2x2 tiles),
+// Lt >= 4, FP32 and 64-wide chunks.
+static bool col_ok(const mpmc_ctx *ctx, int nrhs, int prec, int tz = 2) {
     return prec == MPMC_FP32 && nrhs % 64 == 0 && ctx->dims[0] % 2 == 0 && ctx->dims[1] % 2 == 0 &&
-           ctx->dims[2] % 2 == 0 && ctx->dims[3] >= 4;
+           ctx->dims[2] % tz == 0 && ctx->dims[3] >= 4;
 }
-static ColArgs col_args(const mpmc_ctx *ctx) {
+static ColArgs col_args(const mpmc_ctx *ctx, int tz = 2) {
     ColArgs a;
     for (int mu = 0; mu < 4; ++mu) a.L[mu] = ctx->dims[mu];
     a.ntx = ctx->dims[0] / 2;
     a.nty = ctx->dims[1] / 2;
-    a.ntz = ctx->dims[2] / 2;
+    a.ntz = ctx->dims[2] / tz;
+    // blocks of 8 x 8 x 4 sites where the extents allow (32 tiles of 2x2x2,
+    // 64 of 2x2x1: one round of workgroups of an XCD)
+    auto ext = [](int n, int want) {
+        while (want > 1 && n % want != 0) want /= 2;
+        return want;
+    };
+    a.bx = ext(a.ntx, 4);
+    a.by = ext(a.nty, 4);
+    a.bz = ext(a.ntz, tz == 2 ? 2 : 4);
     a.ntiles = (long)a.ntx * a.nty * a.ntz;
     a.tap = ctx->t_antiperiodic;
     return a;
@@ -1351,6 +1413,7 @@ static int wilson_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
     const auto it = ctx->tune.find(std::make_pair(nrhs, prec));
     const int v = it == ctx->tune.end() ? default_variant(ctx, nrhs, prec) : it->second;
     if (v == WILSON_COLUMN) return col_ok(ctx, nrhs, prec) ? v : (prec == MPMC_FP64 ? 4 : 5);
+    if (v == WILSON_COLUMN1) return col_ok(ctx, nrhs, prec, 1) ? v : (prec == MPMC_FP64 ? 4 : 5);
     return (v >> 1) >= 3 && ctx->V % 16 != 0 ? (v & 1) | 4 : v;
 }
 
@@ -1360,7 +1423,10 @@ static int wilson_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
 // traversal (orders 0 and 1: site-major; 3 and 4 need V % 16 == 0).  The
 // autotuner, which times the plain operator, does not change it.
 constexpr int kDotDefaultOrder = 2;   // 64-wide blocked chunks (FP64; FP32 takes the column kernel)
-constexpr int kDotColumn = 5;         // order code of the column-streaming fused step
+constexpr int kDotColumn = 5;         // order code of the column-streaming fused step (2x2x2 tiles)
+constexpr int kDotColumn1 = 6;        // the same with 2x2x1 tiles
+constexpr int kDotOrders = 7;
+static bool is_col_order(int o) { return o == kDotColumn || o == kDotColumn1; }
 static int dot_order(const mpmc_ctx *ctx, int nrhs, int prec) {
     const auto td = ctx->tune_dot.find(std::make_pair(nrhs, prec));
     if (td != ctx->tune_dot.end() && ctx->tune_explicit.find(std::make_pair(nrhs, prec)) == ctx->tune_explicit.end()) {
@@ -1368,20 +1434,23 @@ static int dot_order(const mpmc_ctx *ctx, int nrhs, int prec) {
         return o;
     }
     const auto it = ctx->tune_explicit.find(std::make_pair(nrhs, prec));
-    if (it == ctx->tune_explicit.end() || it->second == WILSON_COLUMN)
+    if (it != ctx->tune_explicit.end() && it->second == WILSON_COLUMN1 && col_ok(ctx, nrhs, prec, 1) && nrhs <= 256)
+        return kDotColumn1;
+    if (it == ctx->tune_explicit.end() || it->second == WILSON_COLUMN || it->second == WILSON_COLUMN1)
         if (col_ok(ctx, nrhs, prec) && nrhs <= 256) return kDotColumn;
     if (ctx->V % 4 != 0) return 0;
-    const int o = (it == ctx->tune_explicit.end() || it->second == WILSON_COLUMN) ? kDotDefaultOrder : it->second >> 1;
+    const int o = (it == ctx->tune_explicit.end() || it->second >= WILSON_COLUMN) ? kDotDefaultOrder : it->second >> 1;
     if (o >= 3) return ctx->V % 16 == 0 ? o : 2;
     return o == 2 ? 2 : 0;
 }
 int wilson_dot_order(const mpmc_ctx *ctx, int nrhs, int prec) { return dot_order(ctx, nrhs, prec); }
 
 static int dot_width(int order, int nrhs) {
-    return order == 3 ? 16 : order == 4 ? 32 : (order == 2 || order == kDotColumn) ? 64 : (nrhs < 256 ? nrhs : 256);
+    return order == 3 ? 16 : order == 4 ? 32 : (order == 2 || is_col_order(order)) ? 64 : (nrhs < 256 ? nrhs : 256);
 }
 static long dot_tiles_per_chunk(const mpmc_ctx *ctx, int order, int width) {
-    return order == kDotColumn ? col_args(ctx).ntiles : ctx->V * width / 256;
+    if (is_col_order(order)) return col_args(ctx, order == kDotColumn1 ? 1 : 2).ntiles;
+    return ctx->V * width / 256;
 }
 
 template <int P, int V_>
@@ -1391,6 +1460,18 @@ static void launch_uniform(mpmc_ctx *ctx, const WIn<P> &in, const WOut &o, int n
                                                                           nrhs, ctx->site_order);
 }
 
+// Single vectors: k_wilson1 (eight lanes per site, one hop each, one
+// wavefront per workgroup) keeps a small lattice's dependent chain of
+// launches short; on large lattices its scattered per-lane loads dominate and
+// the generic kernel with one site per lane (all eight hops in the lane) is
+// faster.  mpmc_tune_set(ctx, 1, prec, 0 or 1) pins one (1 = site per lane).
+constexpr long kWilson1MaxV = 20736;   // 12^4 sites
+static bool single_site_per_lane(const mpmc_ctx *ctx, int prec) {
+    const auto it = ctx->tune.find(std::make_pair(1, prec));
+    if (it != ctx->tune.end()) return it->second == 1;
+    return ctx->V > kWilson1MaxV;
+}
+
 template <int P>
 static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs, double2 yinit, int yinit_on) {
     const long work = ctx->V * nrhs;
@@ -1398,15 +1479,28 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs, double2 yi
     WIn<P> in = make_in<P>(ctx, b, nrhs);
     if constexpr (P != MPMC_FP16S) {
         if (nrhs == 1) {
-            k_wilson1<P><<<grid_for(ctx->V * 8, 64), 64, 0, ctx->stream>>>(in.b, in.nbr, in.links, o, ctx->V,
-                                                                            yinit, yinit_on);
-            return;
+            if (!single_site_per_lane(ctx, P)) {
+                k_wilson1<P><<<grid_for(ctx->V * 8, 64), 64, 0, ctx->stream>>>(in.b, in.nbr, in.links, o, ctx->V,
+                                                                                yinit, yinit_on);
+                return;
+            }
+            // site per lane (the generic kernel below); the accumulator start
+            // y = yinit b is its own pass
+            if (yinit_on) blas_axpby(ctx, b, o.y, 1, P, yinit, make_double2(0, 0));
         }
     }
     if constexpr (P == MPMC_FP32) {
-        if (nrhs % 64 == 0 && wilson_variant(ctx, nrhs, P) == WILSON_COLUMN && !o.osc) {
-            const ColArgs ca = col_args(ctx);
-            k_wilson_col<0, false><<<(unsigned)(ca.ntiles * (nrhs / 64)), 512, 0, ctx->stream>>>(
+        const int cv = nrhs % 64 == 0 && !o.osc ? wilson_variant(ctx, nrhs, P) : -1;
+        if (cv == WILSON_COLUMN) {
+            const ColArgs ca = col_args(ctx, 2);
+            k_wilson_col<0, false, 2><<<(unsigned)(ca.ntiles * (nrhs / 64)), 512, 0, ctx->stream>>>(
+                in.b, in.links, ca, nrhs, o, nullptr, make_double2(0, 0), make_double2(0, 0), 0, nullptr, 0, nullptr,
+                make_double2(0, 0), make_double2(1, 0));
+            return;
+        }
+        if (cv == WILSON_COLUMN1) {
+            const ColArgs ca = col_args(ctx, 1);
+            k_wilson_col<0, false, 1><<<(unsigned)(ca.ntiles * (nrhs / 64)), 256, 0, ctx->stream>>>(
                 in.b, in.links, ca, nrhs, o, nullptr, make_double2(0, 0), make_double2(0, 0), 0, nullptr, 0, nullptr,
                 make_double2(0, 0), make_double2(1, 0));
             return;
@@ -1414,7 +1508,7 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs, double2 yi
     }
     if (nrhs % 64 == 0) {
         const int v = wilson_variant(ctx, nrhs, P);
-        switch (v == WILSON_COLUMN ? 5 : v) {
+        switch (v >= WILSON_COLUMN ? 5 : v) {
         case 0: launch_uniform<P, 0>(ctx, in, o, nrhs, grid); break;
         case 1: launch_uniform<P, 1>(ctx, in, o, nrhs, grid); break;
         case 2: launch_uniform<P, 2>(ctx, in, o, nrhs, grid); break;
@@ -1520,14 +1614,19 @@ static void launch_dot(mpmc_ctx *ctx, int dord, unsigned grid, const WIn<P> &in,
                        const void *a, double2 alpha, double2 beta) {
     const int *ord = dord ? ctx->site_order : nullptr;
     if constexpr (P == MPMC_FP32) {
-        if (dord == kDotColumn) {
-            const ColArgs ca = col_args(ctx);
+        if (is_col_order(dord)) {
+            const int tz = dord == kDotColumn1 ? 1 : 2;
+            const ColArgs ca = col_args(ctx, tz);
             WOut o{};
             o.out = wout;   // the step's output w'
             o.kappa = ctx->kappa;
             o.g = 1.f;
-            k_wilson_col<1, CMB><<<(unsigned)(ca.ntiles * (nrhs / 64)), 512, 0, ctx->stream>>>(
-                in.b, in.links, ca, nrhs, o, codes, c, cnext, theta, partial, first_step, a, alpha, beta);
+            if (tz == 2)
+                k_wilson_col<1, CMB, 2><<<(unsigned)(ca.ntiles * (nrhs / 64)), 512, 0, ctx->stream>>>(
+                    in.b, in.links, ca, nrhs, o, codes, c, cnext, theta, partial, first_step, a, alpha, beta);
+            else
+                k_wilson_col<1, CMB, 1><<<(unsigned)(ca.ntiles * (nrhs / 64)), 256, 0, ctx->stream>>>(
+                    in.b, in.links, ca, nrhs, o, codes, c, cnext, theta, partial, first_step, a, alpha, beta);
             return;
         }
     }
@@ -1795,14 +1894,15 @@ MPMC_API int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host,
 }
 
 // Fused level step traversal (orders 0 site-major, 2 blocked 64-wide chunks,
-// 3 / 4 blocked 16- / 32-wide chunks, 5 column streaming): each valid one is
+// 3 / 4 blocked 16- / 32-wide chunks, 5 / 6 column streaming with 2x2x2 /
+// 2x2x1 tiles): each valid one is
 // timed (2 warm-up + 5 timed steps) and the fastest kept for (nrhs, prec).
 MPMC_API int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_host, double *us_host) {
     if (!ctx) return MPMC_EINVAL;
     if ((prec != MPMC_FP64 && prec != MPMC_FP32) || nrhs < 64 || nrhs % 64 != 0 || (nrhs > 256 && nrhs % 256 != 0))
         return set_err(ctx, MPMC_EINVAL, "mpmc_autotune_level: FP64/FP32 and nrhs %% 64 == 0 (%% 256 above 256)");
     if (us_host)
-        for (int o = 0; o < 6; ++o) us_host[o] = 0.0;
+        for (int o = 0; o < kDotOrders; ++o) us_host[o] = 0.0;
     Scratch S(ctx);
     const size_t vb = vec_bytes(ctx, nrhs, prec);
     void *x = S.get(vb), *y = S.get(vb);
@@ -1832,6 +1932,7 @@ MPMC_API int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_h
         cand.push_back(4);
     }
     if (col_ok(ctx, nrhs, prec) && nrhs <= 256) cand.push_back(kDotColumn);
+    if (col_ok(ctx, nrhs, prec, 1) && nrhs <= 256) cand.push_back(kDotColumn1);
     int best = cand.back(), rc = MPMC_OK;
     double best_us = 1e300;
     constexpr int warm = 2, reps = 5;

@@ -63,6 +63,8 @@ class Plan:
     net_seed0: int = 100
     net_source: str = "solve"            # "solve": snapshots of training solves; "random": (M e, e), e Z(4)
     net_snaps: int = 4                   # outer cycles recorded per training solve ("solve" source)
+    net_restart: int = 20                # GMRES restart of the training solves (their basis is the
+                                         # training's memory: 21 vectors of net_pairs right-hand sides)
     overlap_setup: bool = True           # build polynomials (and train the net) on side streams
     solve_pp: bool = False               # precondition the main solves with p_in (Sec. 8's PP-GMRES)
     autotune: bool = True                # time the Wilson kernel variants for the level batches once per context
@@ -206,7 +208,7 @@ def train_net(ctx, plan: Plan):
         if plan.net_source == "solve":
             eta = ctx.noise(plan.net_seed0 + b, 0, 0, P, mpmc.FP64)
             x, R, E, ns, vb = ctx.solve_pairs(eta, P, plan.net_snaps, tol=plan.solve_tol,
-                                              restart=plan.solve_restart, inner_prec=mpmc.FP32)
+                                              restart=plan.net_restart, inner_prec=mpmc.FP32)
             for k in range(ns):
                 hist.extend(net.train(R[k * vb:(k + 1) * vb], E[k * vb:(k + 1) * vb], P, plan.net_steps,
                                       plan.net_lr))

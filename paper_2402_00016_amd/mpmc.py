@@ -72,6 +72,7 @@ _SIGS = {
     "mpmc_autotune_level": ([_vp, _i, _i, _pi, _vp], _i),
     "mpmc_wilson_variant_count": ([], _i),
     "mpmc_apply_M_batch": ([_vp, _vp, _vp, _i, _i, _i, _i, _i], _i),
+    "mpmc_solve_batch": ([_vp, _i, _vp, _vp, _i, _vp, _vp, _i, _d, _i, _i, _vp, _vp], _i),
     "mpmc_release_workspace": ([_vp], _i),
     "mpmc_tune_set": ([_vp, _i, _i, _i], _i),
     "mpmc_net_n_params": ([], _i),
@@ -383,9 +384,9 @@ WILSON_VARIANTS = _L.mpmc_wilson_variant_count()   # kernel variants of the mult
 
 
 def mpmc_autotune_level(ctx, nrhs, prec):
-    """(chosen traversal order, microseconds per fused step for orders 0..5; 0 = not a candidate)."""
+    """(chosen traversal order, microseconds per fused step for orders 0..6; 0 = not a candidate)."""
     o = ctypes.c_int()
-    us = np.zeros(6)
+    us = np.zeros(7)
     _check(_L.mpmc_autotune_level(ctx, int(nrhs), int(prec), ctypes.byref(o), us.ctypes.data), ctx)
     return o.value, us
 
@@ -403,6 +404,22 @@ def mpmc_apply_M_batch(ctxs, xs, ys, nrhs, prec, dagger=False, theta=THETA_I):
     xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
     yp = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
     _check(_L.mpmc_apply_M_batch(ch, xp, yp, n, int(nrhs), int(prec), int(dagger), int(theta)), ctxs[0])
+
+
+def mpmc_solve_batch(ctxs, bs, xs, nrhs, defls=None, nets=None, restart=50, tol=1e-8, inner_prec=FP32,
+                     max_outer=100):
+    """Lockstep solves of several contexts; returns (iterations per context, relres [count, nrhs])."""
+    n = len(ctxs)
+    vp = ctypes.c_void_p * n
+    its = np.zeros(n, dtype=np.int32)
+    rel = np.zeros((n, nrhs))
+    dl = vp(*[_h(d) for d in defls]) if defls is not None else None
+    nl = vp(*[_h(t) for t in nets]) if nets is not None else None
+    rc = _L.mpmc_solve_batch(vp(*ctxs), n, vp(*[b.data_ptr() for b in bs]), vp(*[x.data_ptr() for x in xs]),
+                             int(nrhs), dl, nl, int(restart), float(tol), int(inner_prec), int(max_outer),
+                             its.ctypes.data, rel.ctypes.data)
+    _check(rc, ctxs[0])
+    return its, rel
 
 
 def mpmc_tune_set(ctx, nrhs, prec, variant):
@@ -694,6 +711,15 @@ class Context:
         x = self.vector(nrhs, FP64) if x is None else x
         its, rel, rc = mpmc_solve(self.handle, b, x, nrhs, defl, net, restart, tol, inner_prec, max_outer)
         return x, its, rel
+
+    @staticmethod
+    def solve_batch(ctxs, bs, nrhs, defls=None, nets=None, restart=50, tol=1e-8, inner_prec=FP32, max_outer=100):
+        """Solves of several contexts in lockstep, one batched Wilson launch per
+        inner iteration; returns (xs, iterations per context, relres)."""
+        xs = [c.vector(nrhs, FP64) for c in ctxs]
+        its, rel = mpmc_solve_batch([c.handle for c in ctxs], bs, xs, nrhs, defls, nets, restart, tol, inner_prec,
+                                    max_outer)
+        return xs, its, rel
 
     def solve_pp(self, b, nrhs, pp, defl=None, restart=50, tol=1e-8, inner_prec=FP64, max_outer=100, x=None):
         x = self.vector(nrhs, FP64) if x is None else x

@@ -9,6 +9,8 @@ fields' Wilson applications (64 right-hand sides each) run as one batched
 launch and as one launch per lattice.
 
     python -m paper_2402_00016_amd.netstudy --lattices 12,16,20,24 --rhs 16
+    python -m paper_2402_00016_amd.netstudy --train-seeds 64 --train-rhs 16 --train-snaps 4 --train-restart 10
+        (4096 training pairs from the solves of noise seeds 100-163)
 
 Host bookkeeping only; every vector operation runs in libmpmc.so.
 """
@@ -96,13 +98,23 @@ def main(argv=None):
     ap.add_argument("--rhs", type=int, default=16)
     ap.add_argument("--nev", type=int, default=20)
     ap.add_argument("--restart", type=int, default=50)
+    ap.add_argument("--train-seeds", type=int, default=2,
+                    help="training solves, Z(4) noise seeds 100, 101, ... (64: seeds 100-163)")
+    ap.add_argument("--train-rhs", type=int, default=16, help="right-hand sides per training solve")
+    ap.add_argument("--train-snaps", type=int, default=4, help="(r, e) batches recorded per training solve")
+    ap.add_argument("--train-restart", type=int, default=20,
+                    help="GMRES restart of the training solves (shorter: more outer cycles, more snapshots)")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     Lt = a.train_lattice
-    plan = driver.Plan(degrees=[], seed=a.seed, net_pairs=16, net_batches=2, net_steps=10, net_source="solve")
+    plan = driver.Plan(degrees=[], seed=a.seed, net_pairs=a.train_rhs, net_batches=a.train_seeds, net_steps=10,
+                       net_source="solve", net_snaps=a.train_snaps, net_seed0=100, net_restart=a.train_restart)
     w, hist, t_train = train((Lt,) * 4, a.eps, a.kappa, a.seed, plan)
+    # each recorded batch of right-hand sides is one minibatch of net_steps Adam steps
+    pairs = len(hist) // plan.net_steps * plan.net_pairs
     print(json.dumps(dict(trained_on=[Lt] * 4, seconds=round(t_train, 3), loss_first=float(hist[0]),
-                          loss_last=float(hist[-1]), adam_steps=len(hist))), flush=True)
+                          loss_last=float(hist[-1]), adam_steps=len(hist), training_pairs=pairs,
+                          noise_seeds=[100, 100 + a.train_seeds - 1])), flush=True)
     rows = []
     for L in (int(v) for v in a.lattices.split(",")):
         r = compare((L,) * 4, a.eps, a.kappa, a.seed, w, a.rhs, a.nev, a.restart, 1e-8)

@@ -218,6 +218,31 @@ def test_apply_poly_parity(f44, prec, tol, N):
     assert P.info["degree"] == 15 and P.info["matvecs"] == 15
 
 
+@pytest.mark.parametrize("prec,tol_m,tol_p", [(FP64, 1e-13, 1e-12), (FP32, 2e-6, 2e-5)])
+def test_single_vector_site_per_lane(f44, prec, tol_m, tol_p):
+    """Single vectors with one site per lane (the default above 12^4 sites;
+    pinned here with mpmc_tune_set(ctx, 1, prec, 1)): M, M^H and gamma5 M
+    against the oracle, and a polynomial on one vector, whose accumulator
+    start y = x / theta_1 is then a separate pass."""
+    dims, kappa, U, op, ctx = f44
+    xh = z4_noise(9, 1, 0, op.n)
+    ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 16)
+    ctx.tune_set(1, prec, 1)
+    try:
+        x = ctx.noise(9, 1, 0, 1, prec)
+        for dagger, theta in ((False, 0), (True, 0), (False, 1)):
+            y = host(ctx.unpack(ctx.apply_M(x, 1, prec, dagger=dagger, theta=theta), 1, prec))[0]
+            want = op.dagger(xh) if dagger else op(xh)
+            if theta:
+                want = OLT.spin_op(want[None, :], OLT.theta_matrix("g5"))[0]
+            assert rel(y, want) < tol_m, (dagger, theta)
+        P = ctx.poly_from_roots(ref.roots)
+        got = host(ctx.unpack(ctx.apply_poly(P, x, 1, prec), 1, prec))[0]
+        assert rel(got, OP.apply_p(op, ref.roots, xh)) < tol_p
+    finally:
+        ctx.tune_set(1, prec, -1)
+
+
 def test_pi_equals_one_minus_M_p_on_gpu(f44):
     """pi(M) = 1 - M p(M) with the GPU's own roots: residual of the GMRES cycle."""
     dims, kappa, U, op, ctx = f44
@@ -565,7 +590,7 @@ def test_autotune_variants_bit_identical(f44, prec):
     assert ctx.autotune(20, prec)[0] == -1     # not a multiple of 64: nothing to tune
 
 
-@pytest.mark.parametrize("prec,variants", [(FP32, (1, 3, 5, 7, 9, 10)), (FP64, (0, 2, 4, 6, 8))])
+@pytest.mark.parametrize("prec,variants", [(FP32, (1, 3, 5, 7, 9, 10, 11)), (FP64, (0, 2, 4, 6, 8))])
 def test_fused_level_step_traversals(f44, prec, variants):
     """The fused level step under each traversal (site-major, chunk-major,
     4D-blocked with 64-, 16- and 32-wide chunks and their per-chunk
