@@ -189,7 +189,7 @@ def net_identity_weights():
     return np.concatenate(out)
 
 
-def train_net(ctx, plan: Plan):
+def train_net(ctx, plan: Plan, progress=None):
     """Network trained on residual/error pairs; initial weights: identity plus a
     small seeded perturbation (so that the second field receives gradient).
 
@@ -198,7 +198,7 @@ def train_net(ctx, plan: Plan):
     net_source "solve": for b < net_batches, solve M x = eta (eta Z(4) of seed
     net_seed0 + b, FP32 inner cycles) and train on the (r_k, e_k = x - x_k)
     batches recorded at the start of each outer cycle (mpmc_solve_pairs).
-    Returns (net, loss history)."""
+    progress(b, history) is called after each seed.  Returns (net, loss history)."""
     rng = np.random.default_rng(plan.seed)
     theta0 = net_identity_weights() + 0.01 * rng.standard_normal(mpmc.mpmc_net_n_params())
     net = ctx.net(theta0)
@@ -216,6 +216,8 @@ def train_net(ctx, plan: Plan):
             e = ctx.noise(plan.net_seed0 + b, 0, 0, P, mpmc.FP32)
             r = ctx.apply_M(e, P, mpmc.FP32)
             hist.extend(net.train(r, e, P, plan.net_steps, plan.net_lr))
+        if progress is not None:
+            progress(b, hist)
     return net, np.array(hist)
 
 

@@ -6,7 +6,9 @@ any volume.  Reported per lattice: inner GMRES iterations, MVPs and wall time
 to a true relative residual of 1e-8, with and without the network, on the
 same Z(4) right-hand sides and the same deflation set.  Last, the four
 fields' Wilson applications (64 right-hand sides each) run as one batched
-launch and as one launch per lattice.
+launch and as one launch per lattice, and their deflated solves run one
+after another and in lockstep with one batched Wilson launch per inner
+iteration (mpmc_solve_batch), plain and with the network.
 
     python -m paper_2402_00016_amd.netstudy --lattices 12,16,20,24 --rhs 16
     python -m paper_2402_00016_amd.netstudy --train-seeds 64 --train-rhs 16 --train-snaps 4 --train-restart 10
@@ -34,7 +36,12 @@ def timed(fn):
 
 def train(dims, link_eps, kappa, seed, plan):
     ctx = mpmc.Context(dims, kappa, inputs.gauge_links(dims, link_eps, seed))
-    (net, hist), secs = timed(lambda: driver.train_net(ctx, plan))
+    def report(b, hist):
+        if (b + 1) % 8 == 0 or b + 1 == plan.net_batches:
+            print(json.dumps(dict(training_seeds_done=b + 1, adam_steps=len(hist),
+                                  loss=float(hist[-1]) if hist else None)), flush=True)
+
+    (net, hist), secs = timed(lambda: driver.train_net(ctx, plan, report))
     w = net.weights.copy()
     del net
     ctx.release_workspace()
@@ -59,6 +66,39 @@ def compare(dims, link_eps, kappa, seed, weights, nrhs, nev, restart, tol):
     out["speedup"] = round(out["plain"]["seconds"] / out["learned"]["seconds"], 3)
     out["iteration_ratio"] = round(out["plain"]["inner_iterations"] / max(out["learned"]["inner_iterations"], 1), 3)
     ctx.release_workspace()
+    return out
+
+
+def batch_solves(lattices, link_eps, kappa, seed, weights, nrhs, nev, restart, tol):
+    """The lattices' deflated solves (nrhs right-hand sides each) one lattice
+    after another and in lockstep with one batched Wilson launch per inner
+    iteration (mpmc_solve_batch), plain and with the network; same iterates
+    either way, so the same iteration counts."""
+    ctxs = [mpmc.Context((L,) * 4, kappa, inputs.gauge_links((L,) * 4, link_eps, seed)) for L in lattices]
+    defls = [driver.build_deflation(c, driver.Plan(degrees=[], nev=nev, seed=seed)) for c in ctxs]
+    nets = [c.net(weights) for c in ctxs]
+    bs = [c.noise(seed, 5, 0, nrhs, mpmc.FP64) for c in ctxs]
+    out = dict(lattices=[[L] * 4 for L in lattices], nrhs=nrhs, deflated=[int(d.k) for d in defls])
+    for name, nn in (("plain", None), ("learned", nets)):
+        def sequential():
+            return [c.solve(b, nrhs, defl=d, restart=restart, tol=tol, inner_prec=mpmc.FP32,
+                            net=None if nn is None else nn[i])[1] for i, (c, b, d) in enumerate(zip(ctxs, bs, defls))]
+
+        def batched():
+            xs, its, rel = mpmc.Context.solve_batch(ctxs, bs, nrhs, defls=defls, nets=nn, restart=restart, tol=tol,
+                                                    inner_prec=mpmc.FP32)
+            assert float(np.max(rel)) <= tol
+            return [int(v) for v in its]
+
+        sequential()   # warm-up (workspace)
+        its_s, t_s = timed(sequential)
+        batched()
+        its_b, t_b = timed(batched)
+        out[name] = dict(inner_iterations=[int(v) for v in its_s], sequential_s=round(t_s, 4),
+                         batched_s=round(t_b, 4), batched_iterations=its_b)
+        for c in ctxs:
+            c.release_workspace()
+    out["learned_vs_plain_batched"] = round(out["plain"]["batched_s"] / out["learned"]["batched_s"], 3)
     return out
 
 
@@ -104,6 +144,9 @@ def main(argv=None):
     ap.add_argument("--train-snaps", type=int, default=4, help="(r, e) batches recorded per training solve")
     ap.add_argument("--train-restart", type=int, default=20,
                     help="GMRES restart of the training solves (shorter: more outer cycles, more snapshots)")
+    ap.add_argument("--batch-rhs", type=int, default=64,
+                    help="right-hand sides per lattice of the lockstep solves (0: skip them)")
+    ap.add_argument("--batch-restart", type=int, default=25)
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     Lt = a.train_lattice
@@ -122,8 +165,11 @@ def main(argv=None):
         print(json.dumps(r), flush=True)
         torch.cuda.empty_cache()
     print(json.dumps(dict(summary=rows)), flush=True)
-    print(json.dumps(dict(batch=batch_timing([int(v) for v in a.lattices.split(",")], a.eps, a.kappa, a.seed))),
-          flush=True)
+    lat = [int(v) for v in a.lattices.split(",")]
+    print(json.dumps(dict(batch=batch_timing(lat, a.eps, a.kappa, a.seed))), flush=True)
+    if a.batch_rhs:
+        print(json.dumps(dict(batch_solves=batch_solves(lat, a.eps, a.kappa, a.seed, w, a.batch_rhs, a.nev,
+                                                          a.batch_restart, 1e-8))), flush=True)
 
 
 if __name__ == "__main__":
