@@ -59,6 +59,8 @@ def parse():
                     help="skip the extra estimate with the probed last term")
     ap.add_argument("--solve-prec", choices=["fp32", "fp16s"], default=None,
                     help="Krylov basis storage of the mixed form's main solves (default: the workload's)")
+    ap.add_argument("--defl-m", type=int, default=0,
+                    help="PP-Arnoldi steps of the deflation build (0: 2 x eigenpairs + 40, at least 112, at most 256)")
     ap.add_argument("--solve-pp", action="store_true",
                     help="main solves of the mixed and plain forms as polynomial-preconditioned GMRES (p_in)")
     ap.add_argument("--net-source", choices=["random", "solve"], default="solve",
@@ -81,7 +83,7 @@ WORKLOADS = {
     "16x4": dict(dims=(16, 16, 16, 16), eps=0.4, seed=3, kappa=0.124, degrees=[(15, 15)], noises=256, nev=100,
                  max_batch=0, net_pairs=16, solve_prec="fp16s", deflate_double=True),
     "24x4": dict(dims=(24, 24, 24, 24), eps=0.4, seed=4, kappa=0.1245, degrees=[(15, 15), 128, 32, 8], noises=64,
-                 nev=20, max_batch=0, net_pairs=16),
+                 nev=20, max_batch=0, net_pairs=16, solve_prec="fp16s"),
 }
 
 TRAFFIC_FILES = {"8x4": os.path.join(ROOT, "profiles", "k_wilson_dot_fp32_8x4x128_traffic.md"),
@@ -200,7 +202,7 @@ def main():
     links = inputs.gauge_links(dims, eps, seed)
     ctx = mpmc.Context(dims, kappa, links)
     plan = driver.Plan(degrees=W["degrees"], noises=noises, seed=seed, nev=W["nev"],
-                       defl_candidates=max(40, W["nev"] + 20), defl_m=112 if W["nev"] <= 40 else 136,
+                       defl_candidates=max(40, W["nev"] + 20), defl_m=a.defl_m or min(256, max(112, 2 * W["nev"] + 40)),
                        defl_pin_degree=8, theta=mpmc.THETA[a.theta], max_batch=W["max_batch"],
                        poly_prec=mpmc.FP32, solve_inner_prec=mpmc.PREC[W.get("solve_prec", "fp32")],
                        solve_tol=1e-8, solve_restart=50, net_pairs=W["net_pairs"], solve_pp=a.solve_pp,
@@ -290,7 +292,9 @@ def main():
         "autotuned": {"%d_%s" % (k[0], {0: "fp64", 1: "fp32", 2: "fp16s"}[k[1]]): v
                       for k, v in getattr(ctx, "tuned", {}).items()},
         "trace": {"value": [est.value.real, est.value.imag], "stderr": est.stderr, "levels": level_report(est),
-                  "deflated": est.defl_k, "setup_s": round(est.setup_seconds, 4), "mvps": est.mvps},
+                  "deflated": est.defl_k, "eigenpairs_requested": W["nev"], "pp_arnoldi_steps": plan.defl_m,
+                  "ritz_pairs_tested": plan.defl_candidates,
+                  "setup_s": round(est.setup_seconds, 4), "mvps": est.mvps},
         "time_to_error_s": {"mixed_batched": round(step_s, 4)},
     }
 

@@ -375,7 +375,8 @@ int mpmc_solve_batch(mpmc_ctx *const *ctxs, int count, const void *const *b, voi
  * including those inside polynomials and solves.
  * variant_host (may be NULL) receives the choice (-1 when nrhs is not a
  * multiple of 64: nothing to tune); us_host (may be NULL) receives
- * double[mpmc_wilson_variant_count()] microseconds per launch per variant.  Does not count MVPs and
+ * double[mpmc_wilson_variant_count()] microseconds per launch per variant
+ * (0 for a variant that does not apply to the shape and is not timed).  Does not count MVPs and
  * does not enter mpmc_timing_read.  Synchronises. */
 int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host, double *us_host);
 /* Number of Wilson kernel variants (the length of mpmc_autotune's us_host). */

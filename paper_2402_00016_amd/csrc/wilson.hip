@@ -1866,6 +1866,7 @@ MPMC_API int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host,
     constexpr int warm = 2, reps = 5;
     for (int v = 0; v < WILSON_VARIANTS && rc == MPMC_OK; ++v) {
         ctx->tune[key] = v;
+        if (wilson_variant(ctx, nrhs, prec) != v) continue;   // falls back to another variant on this shape
         for (int i = 0; i < warm + reps && rc == MPMC_OK; ++i) {
             if (i == warm && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = MPMC_EHIP;
             if (rc == MPMC_OK)

@@ -584,7 +584,9 @@ def test_autotune_variants_bit_identical(f44, prec):
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     v, us = ctx.autotune(N, prec)
-    assert 0 <= v < mpmc.WILSON_VARIANTS and np.all(us > 0) and us[v] == us.min()
+    tried = us > 0   # variants that fall back to another one on this shape are not timed
+    assert 0 <= v < mpmc.WILSON_VARIANTS and tried[v] and us[v] == us[tried].min()
+    assert tried.sum() >= 10 - 2 * (prec != FP32)   # the column kernels are FP32 only
     assert np.array_equal(host(ctx.apply_M(x, N, prec)), outs[0])
     ctx.tune_set(N, prec, -1)
     assert ctx.autotune(20, prec)[0] == -1     # not a multiple of 64: nothing to tune
