@@ -50,8 +50,9 @@ def parse():
     ap.add_argument("--noises", type=int, default=None, help="noise vectors per term (default: the workload's)")
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="24x4",
                     help="24x4 (default, the largest single-GPU configuration), 16x4 or 8x4")
-    ap.add_argument("--compare-runs", type=int, default=3,
-                    help="estimates of the learned and of the plain form timed (median reported)")
+    ap.add_argument("--compare-runs", type=int, default=0,
+                    help="estimates of the learned and of the plain form timed (median reported); "
+                         "0 = as many as --steps, at most 5")
     ap.add_argument("--theta", choices=["I", "g5"], default="I")
     ap.add_argument("--probe-last", action="store_true",
                     help="last term exactly by probing (distance colouring) in every form")
@@ -160,6 +161,22 @@ def cpu_baseline(dims, kappa, links, seconds, step_mvps):
     t0 = time.perf_counter()
     OP.apply_p(op, roots, v)
     t_poly8 = time.perf_counter() - t0
+    # one GMRES(8) cycle (8 Arnoldi steps with CGS2) on one vector of this lattice
+    t0 = time.perf_counter()
+    OK.arnoldi(op, v, 8)
+    t_arn8 = time.perf_counter() - t0
+    # the whole plain-method estimate of the 4^4 configuration on the oracle:
+    # GMRES(16) polynomial, 32 noises, solves to 1e-8, with and without subtraction
+    from oracle import estimator as OES
+    from paper_2402_00016_amd import inputs as _inputs
+    d4, k4 = (4, 4, 4, 4), 0.115
+    op4 = WilsonOp(d4, k4, _inputs.gauge_links(d4, 0.5, seed=1))
+    t0 = time.perf_counter()
+    P4, _, _ = OK.gmres_poly(op4, z4_noise(1, 0x100, 0, op4.n), 16)
+    X0, _ = OES.level_samples(op4, None, None, None, "I", 1, 0, 0, 32, solve_tol=1e-8)
+    X1, _ = OES.level_samples(op4, None, P4, None, "I", 1, 1, 0, 32, solve_tol=1e-8)
+    X2, _ = OES.level_samples(op4, P4, None, None, "I", 1, 2, 0, 32)
+    t_est4 = time.perf_counter() - t0
     return {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": "FP64 oracle Wilson operator on the %s lattice, 16 Z(4) right-hand sides per call: "
                       "%d calls in %.1f s on %d threads, %d calls in %.1f s on 1 thread; one degree-8 polynomial "
@@ -168,6 +185,10 @@ def cpu_baseline(dims, kappa, links, seconds, step_mvps):
             "one_core_GBs": round(gbs1, 3),
             "s_per_rhs_mvp": s_per_mvp, "s_per_rhs_mvp_one_core": s_per_mvp1,
             "degree8_poly_one_vector_s": round(t_poly8, 3),
+            "gmres8_cycle_one_vector_s": round(t_arn8, 3),
+            "estimate_4x4_plain_method_s": round(t_est4, 3),
+            "estimate_4x4_note": "the 4^4 configuration's whole estimate on the oracle (GMRES(16) polynomial, "
+                                 "32 noises, solves to 1e-8, with and without subtraction)",
             "estimate_s_extrapolated": round(s_per_mvp * step_mvps, 1),
             "estimate_note": "extrapolated: the oracle's per-MVP time x the MVPs of one GPU estimate "
                              "(Gram-Schmidt and dense work not included)"}
@@ -184,6 +205,8 @@ def progress(msg):
 
 def main():
     a = parse()
+    if a.compare_runs <= 0:
+        a.compare_runs = max(1, min(a.steps, 5))
     if a.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path (the method's noise vectors "
               "shard across GPUs with one final all-reduce, which is not implemented); use --gpus 1.",
@@ -335,6 +358,9 @@ def main():
         torch.cuda.empty_cache()
         # learned form: the network is trained once per gauge field (timed
         # separately) and then preconditions the main solves of the estimate
+        # (FP32 inner cycles: with an FP16 basis each inner cycle ends at 1e-3 of
+        # its start, and the network's restarts then cost more than they save:
+        # 24^4 learned solve term 0.87 s with FP32, 1.16 s with FP16S)
         lplan = driver.Plan(**{**plan.__dict__, "learned": True, "solve_inner_prec": mpmc.FP32,
                                "net_source": a.net_source,
                                "net_batches": 2 if a.net_source == "solve" else 8})

@@ -301,7 +301,9 @@ int mpmc_defl_keep(mpmc_defl *d, int k);
  * right-hand side has ||b - M x|| / ||b|| <= tol (true FP64 residual).  With
  * defl, x starts from Z Lambda^-1 U^H b and each restart adds Z Lambda^-1 U^H r.
  * net (may be NULL) is a right preconditioner inside the inner cycle
- * (flexible GMRES, requires inner_prec = MPMC_FP32); it changes cost, never
+ * (flexible GMRES with the preconditioned vectors z_j = N v_j kept in FP32;
+ * requires inner_prec = MPMC_FP32 or MPMC_FP16S, whose FP16 basis vectors are
+ * widened to FP32 before N); it changes cost, never
  * the converged x.  Outputs (host):
  * iters_host = total inner iterations, relres_host[nrhs] = final true
  * relative residuals.  Returns MPMC_ENOCONV after max_outer cycles.

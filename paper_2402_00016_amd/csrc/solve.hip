@@ -115,8 +115,9 @@ int Gmres::init() {
     if (pp_ && pp_->ctx != ctx) return set_err(ctx, MPMC_ESTATE, "mpmc_solve: polynomial belongs to another context");
     if (net_ && net_context(net_) != ctx)
         return set_err(ctx, MPMC_ESTATE, "mpmc_solve: network belongs to another context");
-    if (net_ && inner_prec_ != MPMC_FP32)
-        return set_err(ctx, MPMC_EINVAL, "mpmc_solve: the learned preconditioner runs with FP32 inner cycles only");
+    if (net_ && inner_prec_ != MPMC_FP32 && inner_prec_ != MPMC_FP16S)
+        return set_err(ctx, MPMC_EINVAL, "mpmc_solve: the learned preconditioner runs with FP32 arithmetic "
+                                         "(FP32 or FP16S inner cycles) only");
     if (inner_prec_ != MPMC_FP64 && inner_prec_ != MPMC_FP32 && inner_prec_ != MPMC_FP16S)
         return set_err(ctx, MPMC_EINVAL, "mpmc_solve: inner precision must be FP64, FP32 or FP16S");
     // basis vectors in pb (FP16S: half + per-(site, rhs) scale, storage only);
@@ -135,7 +136,7 @@ int Gmres::init() {
     w_ = S_.get(vbi_);
     corr_ = S_.get(vbi_);
     tp_ = pp_ ? S_.get(vbi_) : nullptr;          // p(M) v_j (polynomial right preconditioning)
-    tq_ = pp_ && half_ ? S_.get(vbi_) : nullptr;  // FP32 copy of an FP16S basis vector
+    tq_ = (pp_ || net_) && half_ ? S_.get(vbi_) : nullptr;  // FP32 copy of an FP16S basis vector
     H_ = (double *)S_.get(sizeof(double2) * (size_t)(m + 1) * (m + 1) * N);
     h2_ = (double *)S_.get(sizeof(double2) * (size_t)(m + 1) * N);
     cs_ = (double *)S_.get(sizeof(double2) * (size_t)2 * m * N);
@@ -146,7 +147,7 @@ int Gmres::init() {
     dc_ = defl_ && defl_->k ? (double *)S_.get(sizeof(double2) * (size_t)defl_->k * N) : nullptr;
     xsnap_ = snap_ ? S_.get(vb64_ * (size_t)snap_->max) : nullptr;   // FP64 iterates x_k of the record
     if (snap_ && !xsnap_) return MPMC_ENOMEM;
-    if (!r_ || !V_ || (net_ && !Zb_) || (pp_ && !tp_) || (pp_ && half_ && !tq_) || !w_ || !corr_ || !H_ || !h2_ ||
+    if (!r_ || !V_ || (net_ && !Zb_) || (pp_ && !tp_) || ((pp_ || net_) && half_ && !tq_) || !w_ || !corr_ || !H_ || !h2_ ||
         !cs_ || !g_ || !y_ || !res_ || !sc_ || (defl_ && defl_->k && !dc_))
         return MPMC_ENOMEM;
     nrm_ = sc_;
@@ -245,9 +246,14 @@ int Gmres::begin_cycle(bool *go) {
 
 int Gmres::operand(int j, const void **opin) {
     *opin = basis(j);
-    if (cnet_) {
-        void *zj = (char *)Zb_ + (size_t)j * vstride_ * es_;
-        RET_IF(net_apply_internal(ctx_, cnet_, basis(j), zj, N_));
+    if (cnet_) {   // z_j = N v_j (FP32; an FP16S basis vector is widened first)
+        const void *vj = basis(j);
+        if (half_) {
+            RET_IF(blas_convert(ctx_, vj, MPMC_FP16S, tq_, MPMC_FP32, N_));
+            vj = tq_;
+        }
+        void *zj = (char *)Zb_ + (size_t)j * vbi_;
+        RET_IF(net_apply_internal(ctx_, cnet_, vj, zj, N_));
         *opin = zj;
     }
     return MPMC_OK;
@@ -266,8 +272,8 @@ int Gmres::matvec(int j, const void *opin) {
         return wilson_launch_full(ctx, tp_, nullptr, w_, nullptr, N, pw_, make_double2(0, 0), make_double2(1, 0),
                                   make_double2(0, 0), 0, 0);
     }
-    if (half_) return wilson_apply_h2f(ctx, basis(j), w_, N);
-    return wilson_launch_full(ctx, opin, nullptr, w_, nullptr, N, inner_prec_, make_double2(0, 0), make_double2(1, 0),
+    if (half_ && !cnet_) return wilson_apply_h2f(ctx, basis(j), w_, N);
+    return wilson_launch_full(ctx, opin, nullptr, w_, nullptr, N, pw_, make_double2(0, 0), make_double2(1, 0),
                               make_double2(0, 0), 0, 0);
 }
 
@@ -312,10 +318,12 @@ int Gmres::end_cycle() {
     const int N = N_, m = m_;
     RET_IF(dense_backsolve(ctx, H_, m + 1, jdone_, N, g_, y_));
     HIP_OR_RET(ctx, hipMemsetAsync(corr_, 0, vbi_, ctx->stream));
-    if (half_)
+    if (cnet_)   // flexible GMRES: e = Z y (FP32)
+        RET_IF(blas_multi_axpy(ctx, Zb_, vstride_, N, jdone_, corr_, N, pw_, y_, N, 1.0, nullptr));
+    else if (half_)
         RET_IF(blas_multi_axpy_h(ctx, V_, vbb_, jdone_, corr_, N, y_, N, 1.0, nullptr));
     else
-        RET_IF(blas_multi_axpy(ctx, cnet_ ? Zb_ : V_, vstride_, N, jdone_, corr_, N, inner_prec_, y_, N, 1.0, nullptr));
+        RET_IF(blas_multi_axpy(ctx, V_, vstride_, N, jdone_, corr_, N, inner_prec_, y_, N, 1.0, nullptr));
     if (pp_) {   // correction p(M) V y
         RET_IF(poly_apply_internal(ctx, pp_, corr_, tp_, N, pw_));
         HIP_OR_RET(ctx, hipMemcpyAsync(corr_, tp_, vbi_, hipMemcpyDeviceToDevice, ctx->stream));

@@ -175,6 +175,23 @@ def test_sabotaged_net_keeps_solution(f44, kind):
     assert rel(x1, x0) < 1e-7
 
 
+def test_solve_with_net_and_fp16_basis(f44, trained):
+    """Flexible GMRES with an FP16 Krylov basis (FP16S inner cycles): the
+    network sees each basis vector widened to FP32; the solve reaches the FP64
+    true residual and the solution of the FP32-basis solve with the network."""
+    dims, kappa, U, op, ctx, T = f44
+    net = trained[0]
+    N = 24
+    b = ctx.noise(11, 5, 0, N, FP64)
+    x32, it32, rel32 = ctx.solve(b, N, restart=20, tol=1e-8, inner_prec=FP32, net=net)
+    x16, it16, rel16 = ctx.solve(b, N, restart=20, tol=1e-8, inner_prec=mpmc.FP16S, net=net)
+    assert np.all(rel16 <= 1e-8)
+    assert rel(host(ctx.unpack(x16, N, FP64)), host(ctx.unpack(x32, N, FP64))) < 1e-7
+    X = host(ctx.unpack(x16, N, FP64))
+    B = z4_noise_batch(11, 5, 0, N, op.n)
+    assert np.all(np.linalg.norm(B - op(X), axis=1) / np.linalg.norm(B, axis=1) <= 1.05e-8)
+
+
 def test_net_requires_fp32_inner(f44, trained):
     dims, kappa, U, op, ctx, T = f44
     b = ctx.noise(1, 5, 0, 2, FP64)
