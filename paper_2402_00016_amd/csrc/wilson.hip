@@ -1083,6 +1083,7 @@ struct ColArgs {
     int ntx, nty, ntz;   // tiles per direction
     int bx, by, bz;      // tiles per block of the traversal (each divides its extent)
     long ntiles;         // tiles per 64-wide chunk
+    long nblk;           // blocks over all chunks of the launch (col_grid)
     int tap;             // antiperiodic time direction
 };
 
@@ -1167,15 +1168,23 @@ __global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) v
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const unsigned lane = threadIdx.x & 63u;
     const int wx = w & 1, wy = (w >> 1) & 1, wz = TZ == 2 ? w >> 2 : 0;
-    // an XCD's contiguous tile range walks blocks of bx x by x bz tiles, so
-    // the workgroups it runs at once hold a compact 3D region whose columns
-    // advance along t together: most out-of-tile neighbours were just
-    // fetched into the XCD's L2 by the workgroup that owns them
-    const unsigned tile = xcd_tile(blockIdx.x, gridDim.x);
-    const long chunk = (long)tile / ca.ntiles, tl = (long)tile - chunk * ca.ntiles;
+    // Whole blocks of bx x by x bz tiles go to the XCDs (workgroup b runs on
+    // XCD b % 8, in the order b / 8), each XCD taking a contiguous range of
+    // blocks: a round of the workgroups an XCD runs at once is one compact 3D
+    // block whose columns advance along t together, so most out-of-tile
+    // neighbours were just fetched into the XCD's L2 by the workgroup that
+    // owns them.  The grid is padded to 8 x (most blocks per XCD) x block
+    // size; padding workgroups return at once.
     const int bsz = ca.bx * ca.by * ca.bz, nbx = ca.ntx / ca.bx, nby = ca.nty / ca.by;
-    const long blk = tl / bsz;
-    const int in = (int)(tl - blk * bsz);
+    const long xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
+    const long per = ca.nblk / 8, rem = ca.nblk % 8;
+    const long lb = slot / bsz;
+    if (lb >= per + (xcd < rem ? 1 : 0)) return;
+    const long gb = xcd * per + (xcd < rem ? xcd : rem) + lb;   // block over all chunks
+    const long nbc = ca.ntiles / bsz;                          // blocks per 64-wide chunk
+    const long chunk = gb / nbc, blk = gb - chunk * nbc;
+    const int in = (int)(slot - lb * bsz);
+    const unsigned tile = (unsigned)(chunk * ca.ntiles + blk * bsz + in);
     const int tx = (int)(blk % nbx) * ca.bx + in % ca.bx;
     const int ty = (int)((blk / nbx) % nby) * ca.by + (in / ca.bx) % ca.by;
     const int tz = (int)(blk / ((long)nbx * nby)) * ca.bz + in / (ca.bx * ca.by);
@@ -1387,8 +1396,15 @@ static ColArgs col_args(const mpmc_ctx *ctx, int tz = 2) {
     a.by = ext(a.nty, 4);
     a.bz = ext(a.ntz, tz == 2 ? 2 : 4);
     a.ntiles = (long)a.ntx * a.nty * a.ntz;
+    a.nblk = 0;
     a.tap = ctx->t_antiperiodic;
     return a;
+}
+// Grid of a column launch over nrhs / 64 chunks (sets ca.nblk).
+static unsigned col_grid(ColArgs &ca, int nrhs) {
+    const long bsz = (long)ca.bx * ca.by * ca.bz;
+    ca.nblk = ca.ntiles / bsz * (nrhs / 64);
+    return (unsigned)(8 * ((ca.nblk + 7) / 8) * bsz);
 }
 static int default_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
     if (col_ok(ctx, nrhs, prec)) return WILSON_COLUMN;
@@ -1492,15 +1508,15 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs, double2 yi
     if constexpr (P == MPMC_FP32) {
         const int cv = nrhs % 64 == 0 && !o.osc ? wilson_variant(ctx, nrhs, P) : -1;
         if (cv == WILSON_COLUMN) {
-            const ColArgs ca = col_args(ctx, 2);
-            k_wilson_col<0, false, 2><<<(unsigned)(ca.ntiles * (nrhs / 64)), 512, 0, ctx->stream>>>(
+            ColArgs ca = col_args(ctx, 2);
+            k_wilson_col<0, false, 2><<<col_grid(ca, nrhs), 512, 0, ctx->stream>>>(
                 in.b, in.links, ca, nrhs, o, nullptr, make_double2(0, 0), make_double2(0, 0), 0, nullptr, 0, nullptr,
                 make_double2(0, 0), make_double2(1, 0));
             return;
         }
         if (cv == WILSON_COLUMN1) {
-            const ColArgs ca = col_args(ctx, 1);
-            k_wilson_col<0, false, 1><<<(unsigned)(ca.ntiles * (nrhs / 64)), 256, 0, ctx->stream>>>(
+            ColArgs ca = col_args(ctx, 1);
+            k_wilson_col<0, false, 1><<<col_grid(ca, nrhs), 256, 0, ctx->stream>>>(
                 in.b, in.links, ca, nrhs, o, nullptr, make_double2(0, 0), make_double2(0, 0), 0, nullptr, 0, nullptr,
                 make_double2(0, 0), make_double2(1, 0));
             return;
@@ -1616,16 +1632,17 @@ static void launch_dot(mpmc_ctx *ctx, int dord, unsigned grid, const WIn<P> &in,
     if constexpr (P == MPMC_FP32) {
         if (is_col_order(dord)) {
             const int tz = dord == kDotColumn1 ? 1 : 2;
-            const ColArgs ca = col_args(ctx, tz);
+            ColArgs ca = col_args(ctx, tz);
+            const unsigned grid_c = col_grid(ca, nrhs);
             WOut o{};
             o.out = wout;   // the step's output w'
             o.kappa = ctx->kappa;
             o.g = 1.f;
             if (tz == 2)
-                k_wilson_col<1, CMB, 2><<<(unsigned)(ca.ntiles * (nrhs / 64)), 512, 0, ctx->stream>>>(
+                k_wilson_col<1, CMB, 2><<<grid_c, 512, 0, ctx->stream>>>(
                     in.b, in.links, ca, nrhs, o, codes, c, cnext, theta, partial, first_step, a, alpha, beta);
             else
-                k_wilson_col<1, CMB, 1><<<(unsigned)(ca.ntiles * (nrhs / 64)), 256, 0, ctx->stream>>>(
+                k_wilson_col<1, CMB, 1><<<grid_c, 256, 0, ctx->stream>>>(
                     in.b, in.links, ca, nrhs, o, codes, c, cnext, theta, partial, first_step, a, alpha, beta);
             return;
         }
