@@ -502,6 +502,16 @@ int mpmc_set_dense_method(mpmc_ctx *ctx, int method);
  * multipolynomial estimate unbiased (any polynomials telescope).  EINVAL for
  * another precision. */
 int mpmc_set_setup_precision(mpmc_ctx *ctx, int prec);
+/* Gram-Schmidt of those Arnoldi cycles.  Both are classical Gram-Schmidt
+ * applied twice (the Hessenberg matrices agree to rounding).  on = 0: the
+ * second projection of each vector is delayed to the next step (the operator
+ * is applied to the once-projected candidate u, one pass over the basis gives
+ * V^H u, V^H (A u), u^H u and u^H A u, one more pass writes the finished
+ * vector and the next candidate): two basis passes and four launches per step
+ * besides the operator.  on = 1: the two projections in sequence (four basis
+ * passes, eight shorter launches).  on = -1 (the default): 1 below 16^4
+ * sites, where the steps are launch-bound, else 0.  EINVAL otherwise. */
+int mpmc_set_arnoldi_cgs2(mpmc_ctx *ctx, int on);
 
 /* Polynomial preconditioner used by the main solves inside mpmc_level_estimate
  * when no network is given (NULL: none, the default).  The context keeps the

@@ -63,6 +63,9 @@ struct mpmc_ctx {
     int solve_level_defl = 0;
     // storage precision of the single-vector Arnoldi cycles (mpmc_gmres_poly, mpmc_deflate)
     int setup_prec = MPMC_FP64;
+    // their Gram-Schmidt: 0 = CGS2 with the second projection delayed one step, 1 = plain CGS2,
+    // -1 = by lattice size (plain below 16^4 sites)
+    int gs_cgs2 = -1;
     // fused polynomial recurrences replayed from captured hipGraphs (mpmc_set_graph_recurrences)
     int use_graphs = 0;
     hipStream_t gstream = nullptr;          // capture / replay stream (default priority)

@@ -48,10 +48,316 @@ static int apply_op(mpmc_ctx *ctx, const OpDesc &op, const void *x, void *y) {
     return MPMC_OK;
 }
 
+// ------------------------------------ delayed reorthogonalisation --
+// Classical Gram-Schmidt applied twice, with the second projection of each
+// Arnoldi vector delayed by one step (the low-synchronisation "DCGS2" form of
+// Swirydowicz, Langou, Ananthan, Yang and Thomas, and of Bielich et al.): at
+// step j the operator is applied to the not yet reorthogonalised candidate u
+// (z = A u), one pass over the basis V_j gives every inner product of the
+// step (s = V_j^H u, t = V_j^H z, u^H u, u^H z), a one-workgroup kernel turns
+// them into the final column j-1 of H, the single-projection column j and the
+// coefficients of
+//     v_j    = (u - V_j s) / nu,                nu = sqrt(u^H u - |s|^2),
+//     u_next = (z - V_j (t - s c / nu) - u c / nu) / nu,   c = (u^H z - s^H t) / nu,
+// and one more pass over V_j writes both vectors.  In exact arithmetic this is
+// the CGS2 Arnoldi process (A V_j = V_{j+1} H_j gives A v_j from z without a
+// second operator application); each step reads the basis twice instead of
+// four times and issues four launches besides the operator instead of eight.
+
+constexpr int kDcgsJB = 8;   // basis vectors per workgroup row of the dot pass
+
+__device__ __forceinline__ double2 wave_sum2(double2 v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o);
+        v.y += __shfl_xor(v.y, o);
+    }
+    return v;
+}
+
+// partial[q * NB + blk]: q < nv: V_q^H u; nv <= q < 2 nv: V_{q-nv}^H z (z may be
+// null: zero); q = 2 nv: u^H u; q = 2 nv + 1: u^H z.  Row g = blockIdx.y of the
+// grid takes basis vectors [g JB, g JB + JB); row 0 also the two u products.
+template <int P>
+__global__ __launch_bounds__(256) void k_dcgs_dots(const void *__restrict__ V, size_t vstep, int nv,
+                                                   const void *__restrict__ u, const void *__restrict__ z, long n,
+                                                   double2 *__restrict__ partial, int NB) {
+    __shared__ double2 red[2 * kDcgsJB + 2][4];
+    const int j0 = blockIdx.y * kDcgsJB;
+    cpx<double> sa[kDcgsJB], ta[kDcgsJB], aa = mk(0.0, 0.0), ba = mk(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < kDcgsJB; ++q) sa[q] = ta[q] = mk(0.0, 0.0);
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)NB * 256) {
+        const auto u0 = Store<P>::ld(u, nullptr, e, 0);
+        const cpx<double> uv = mk((double)u0.re, (double)u0.im);
+        cpx<double> zv = mk(0.0, 0.0);
+        if (z) {
+            const auto z0 = Store<P>::ld(z, nullptr, e, 0);
+            zv = mk((double)z0.re, (double)z0.im);
+        }
+        if (blockIdx.y == 0) {
+            aa = aa + conjmul(uv, uv);
+            ba = ba + conjmul(uv, zv);
+        }
+        cpx<double> vq[kDcgsJB];
+#pragma unroll
+        for (int q = 0; q < kDcgsJB; ++q) {   // loads issued together, index clamped, masked below
+            const int i = j0 + q < nv ? j0 + q : (nv > 0 ? nv - 1 : 0);
+            const auto v = nv > 0 ? Store<P>::ld((const char *)V + (size_t)i * vstep, nullptr, e, 0)
+                                  : Store<P>::ld(u, nullptr, e, 0);
+            vq[q] = mk((double)v.re, (double)v.im);
+        }
+#pragma unroll
+        for (int q = 0; q < kDcgsJB; ++q)
+            if (j0 + q < nv) {
+                sa[q] = sa[q] + conjmul(vq[q], uv);
+                ta[q] = ta[q] + conjmul(vq[q], zv);
+            }
+    }
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < kDcgsJB; ++q) {
+        const double2 a = wave_sum2(make_double2(sa[q].re, sa[q].im));
+        const double2 b = wave_sum2(make_double2(ta[q].re, ta[q].im));
+        if (ln == 0) {
+            red[q][wv] = a;
+            red[kDcgsJB + q][wv] = b;
+        }
+    }
+    const double2 a2 = wave_sum2(make_double2(aa.re, aa.im)), b2 = wave_sum2(make_double2(ba.re, ba.im));
+    if (ln == 0) {
+        red[2 * kDcgsJB][wv] = a2;
+        red[2 * kDcgsJB + 1][wv] = b2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kDcgsJB + 2) {
+        const int q = threadIdx.x;
+        double2 acc = red[q][0];
+        for (int w = 1; w < 4; ++w) {
+            acc.x += red[q][w].x;
+            acc.y += red[q][w].y;
+        }
+        long out = -1;
+        if (q < kDcgsJB) {
+            if (j0 + q < nv) out = j0 + q;
+        } else if (q < 2 * kDcgsJB) {
+            if (j0 + q - kDcgsJB < nv) out = nv + j0 + q - kDcgsJB;
+        } else if (blockIdx.y == 0) {
+            out = 2L * nv + (q - 2 * kDcgsJB);
+        }
+        if (out >= 0) partial[out * NB + blockIdx.x] = acc;
+    }
+}
+
+// D[q] = sum_b partial[q * NB + b] (fixed order), one workgroup per q.
+__global__ __launch_bounds__(256) void k_dcgs_reduce(const double2 *__restrict__ partial, int NB,
+                                                     double2 *__restrict__ D) {
+    __shared__ double2 red[4];
+    const int q = blockIdx.x;
+    double2 a = make_double2(0.0, 0.0);
+    for (int b = threadIdx.x; b < NB; b += 256) {
+        const double2 v = partial[(long)q * NB + b];
+        a.x += v.x;
+        a.y += v.y;
+    }
+    a = wave_sum2(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double2 t = red[0];
+        for (int w = 1; w < 4; ++w) {
+            t.x += red[w].x;
+            t.y += red[w].y;
+        }
+        D[q] = t;
+    }
+}
+
+__device__ __forceinline__ double block_sum1(double v, double *red4) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return red4[0] + red4[1] + red4[2] + red4[3];
+}
+
+// Coefficients of step j from D (k_dcgs_reduce; nv = j basis vectors): the
+// final column j-1 of H (H(0:j-1, j-1) += s, H(j, j-1) = nu, breakdown test as
+// in CGS2: nu <= 1e-14 ||H||_F), then (unless last) the single-projection
+// column j and C = [1/nu, -c/nu^2, 1/nu, -s_i/nu (i < j), -(t_i - s_i c/nu)/nu
+// (i < j)].  After a breakdown every coefficient is 0 (later vectors stay 0).
+// j = 0 also records ||b|| = nu in state[2].  ldh = d + 1; j <= d <= 500.
+__global__ __launch_bounds__(256) void k_dcgs_coef(const double2 *__restrict__ D, int j, int ldh,
+                                                   double2 *__restrict__ H, double *__restrict__ state,
+                                                   double2 *__restrict__ C, int last) {
+    __shared__ double2 sv[512], tv[512];
+    __shared__ double red4[4];
+    __shared__ double sh_nu;
+    __shared__ int sh_bad;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < j; i += 256) {
+        sv[i] = D[i];
+        tv[i] = D[j + i];
+    }
+    __syncthreads();
+    const double2 a = D[2 * j], b = D[2 * j + 1];
+    double ss = 0.0, stre = 0.0, stim = 0.0;
+    for (int i = tid; i < j; i += 256) {
+        ss += sv[i].x * sv[i].x + sv[i].y * sv[i].y;
+        stre += sv[i].x * tv[i].x + sv[i].y * tv[i].y;   // s^H t
+        stim += sv[i].x * tv[i].y - sv[i].y * tv[i].x;
+    }
+    ss = block_sum1(ss, red4);
+    stre = block_sum1(stre, red4);
+    stim = block_sum1(stim, red4);
+    const double nu = sqrt(fmax(a.x - ss, 0.0));
+    // the final column j-1 and its share of the running Frobenius norm
+    double col = 0.0;
+    if (j > 0) {
+        double2 *Hc = H + (size_t)(j - 1) * ldh;
+        for (int i = tid; i < j; i += 256) {
+            double2 h = Hc[i];
+            h.x += sv[i].x;
+            h.y += sv[i].y;
+            Hc[i] = h;
+            col += h.x * h.x + h.y * h.y;
+        }
+    }
+    col = block_sum1(col, red4);
+    if (tid == 0) {
+        bool bad = state[1] >= 0 || !(nu == nu);
+        if (j == 0) {
+            state[2] = nu;
+            if (!(nu > 0)) bad = true;
+        } else {
+            const double fro = state[0] + col + nu * nu;
+            state[0] = fro;
+            if (!bad && nu <= 1e-14 * sqrt(fro)) bad = true;
+            if (bad && state[1] < 0) state[1] = j;
+            H[(size_t)(j - 1) * ldh + j] = make_double2(bad ? 0.0 : nu, 0.0);
+        }
+        if (bad && j == 0 && state[1] < 0) state[1] = 0;
+        sh_nu = nu;
+        sh_bad = bad ? 1 : 0;
+    }
+    __syncthreads();
+    const bool bad = sh_bad != 0;
+    const double inu = bad ? 0.0 : 1.0 / sh_nu;
+    // c = v_j^H z = (u^H z - s^H t) / nu
+    const cpx<double> c = mk((b.x - stre) * inu, (b.y - stim) * inu);
+    if (tid == 0) {
+        C[0] = make_double2(inu, 0.0);
+        C[1] = make_double2(-c.re * inu * inu, -c.im * inu * inu);
+        C[2] = make_double2(last ? 0.0 : inu, 0.0);
+    }
+    for (int i = tid; i < j; i += 256) {
+        C[3 + i] = make_double2(-sv[i].x * inu, -sv[i].y * inu);
+        // t_i - s_i c / nu
+        const double r = tv[i].x - (sv[i].x * c.re - sv[i].y * c.im) * inu;
+        const double m = tv[i].y - (sv[i].x * c.im + sv[i].y * c.re) * inu;
+        C[3 + j + i] = make_double2(last ? 0.0 : -r * inu, last ? 0.0 : -m * inu);
+    }
+    if (last) return;
+    // single-projection column j: h_i = (t_i - g_i) / nu (i < j), h_j = (c - g_j) / nu,
+    // g = H(0:j, 0:j-1) s.  Row i per thread, all k: the entries below the
+    // subdiagonal are zero (H starts zeroed), so the loop bound is uniform and
+    // the loads of one k are one coalesced column segment.
+    double2 *Hj = H + (size_t)j * ldh;
+    for (int i = tid; i <= j; i += 256) {
+        double gr = 0.0, gi = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < j; ++k) {
+            const double2 h = H[(size_t)k * ldh + i];
+            gr += h.x * sv[k].x - h.y * sv[k].y;
+            gi += h.x * sv[k].y + h.y * sv[k].x;
+        }
+        const double2 tt = i < j ? tv[i] : make_double2(c.re, c.im);
+        Hj[i] = make_double2((tt.x - gr) * inu, (tt.y - gi) * inu);
+    }
+}
+
+// vout = C0 u + sum_i C[3+i] V_i ; un = C1 u + C2 z + sum_i C[3+nv+i] V_i (un may
+// alias u, vout may alias u; z and un may be null).
+template <int P>
+__global__ __launch_bounds__(256) void k_dcgs_update(const void *__restrict__ V, size_t vstep, int nv, const void *u,
+                                                     const void *__restrict__ z, void *un, void *vout,
+                                                     const double2 *__restrict__ C, long n) {
+    using T = typename Store<P>::real;
+    const cpx<T> cu = mk((T)C[0].x, (T)C[0].y), bu = mk((T)C[1].x, (T)C[1].y), bz = mk((T)C[2].x, (T)C[2].y);
+    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+        const auto u0 = Store<P>::ld(u, nullptr, e, 0);
+        const cpx<T> uv = mk((T)u0.re, (T)u0.im);
+        cpx<T> v = cu * uv, w = bu * uv;
+        if (z) {
+            const auto z0 = Store<P>::ld(z, nullptr, e, 0);
+            w = w + bz * mk((T)z0.re, (T)z0.im);
+        }
+        int i = 0;
+        for (; i + 4 <= nv; i += 4) {   // four basis vectors per iteration, loads issued together
+            cpx<T> vq[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const auto x = Store<P>::ld((const char *)V + (size_t)(i + q) * vstep, nullptr, e, 0);
+                vq[q] = mk((T)x.re, (T)x.im);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double2 a = C[3 + i + q], bb = C[3 + nv + i + q];
+                v = v + mk((T)a.x, (T)a.y) * vq[q];
+                w = w + mk((T)bb.x, (T)bb.y) * vq[q];
+            }
+        }
+        for (; i < nv; ++i) {
+            const auto x = Store<P>::ld((const char *)V + (size_t)i * vstep, nullptr, e, 0);
+            const cpx<T> vx = mk((T)x.re, (T)x.im);
+            const double2 a = C[3 + i], bb = C[3 + nv + i];
+            v = v + mk((T)a.x, (T)a.y) * vx;
+            w = w + mk((T)bb.x, (T)bb.y) * vx;
+        }
+        if (un) Store<P>::st(un, e, w);
+        Store<P>::st(vout, e, v);
+    }
+}
+
+static int dcgs_launch_dots(mpmc_ctx *ctx, int prec, const void *V, size_t vstep, int nv, const void *u,
+                            const void *z, double2 *D) {
+    const long n = ctx->n;
+    const int groups = nv > 0 ? (nv + kDcgsJB - 1) / kDcgsJB : 1;
+    long nb = (long)ctx->num_cu * 8 / groups;
+    const long maxnb = (n + 255) / 256;
+    if (nb < 8) nb = 8;
+    if (nb > maxnb) nb = maxnb;
+    if (nb > 2048) nb = 2048;
+    const int NB = (int)nb;
+    double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)(2 * nv + 2) * NB * sizeof(double2));
+    if (!part) return MPMC_ENOMEM;
+    if (prec == MPMC_FP64)
+        k_dcgs_dots<MPMC_FP64><<<dim3(NB, groups), 256, 0, ctx->stream>>>(V, vstep, nv, u, z, n, part, NB);
+    else
+        k_dcgs_dots<MPMC_FP32><<<dim3(NB, groups), 256, 0, ctx->stream>>>(V, vstep, nv, u, z, n, part, NB);
+    HIP_OR_RET(ctx, hipGetLastError());
+    k_dcgs_reduce<<<2 * nv + 2, 256, 0, ctx->stream>>>(part, NB, D);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
+static int dcgs_launch_update(mpmc_ctx *ctx, int prec, const void *V, size_t vstep, int nv, const void *u,
+                              const void *z, void *un, void *vout, const double2 *C) {
+    const long n = ctx->n;
+    long nb = (n + 255) / 256;
+    if (nb > (long)ctx->num_cu * 8) nb = (long)ctx->num_cu * 8;
+    if (prec == MPMC_FP64)
+        k_dcgs_update<MPMC_FP64><<<(unsigned)nb, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, un, vout, C, n);
+    else
+        k_dcgs_update<MPMC_FP32><<<(unsigned)nb, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, un, vout, C, n);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
+}
+
 // d Arnoldi steps (one rhs) from b (overwritten by v_0), vectors stored in
 // op.prec.  V: (d+1) vectors of n complex elements, H: column-major (d+1) x d
 // FP64, ld = d+1.  state (device): [0] ||H||_F^2, [1] d_eff or -1, [2] ||b||.
-int arnoldi_run(mpmc_ctx *ctx, const OpDesc &op, void *V, double *H, int d, double *state, Scratch &S) {
+static int arnoldi_run_cgs2(mpmc_ctx *ctx, const OpDesc &op, void *V, double *H, int d, double *state,
+                            Scratch &S) {
     const long n = ctx->n;
     const size_t vstep = vec_bytes(ctx, 1, op.prec);
     double2 *sc = (double2 *)S.get(sizeof(double2) * (d + 8));
@@ -77,6 +383,60 @@ int arnoldi_run(mpmc_ctx *ctx, const OpDesc &op, void *V, double *H, int d, doub
         RET_IF(blas_arnoldi_update(ctx, V, n, j + 1, w, (double *)h2, Hcol, j, state, (double *)(sc + 1), op.prec));
         RET_IF(blas_scale_rhs(ctx, w, vj1, 1, op.prec, (double *)(sc + 1), 0));
     }
+    return MPMC_OK;
+}
+
+__global__ void k_dcgs_init(double *state) {
+    state[0] = 0.0;
+    state[1] = -1.0;
+    state[2] = 0.0;
+}
+
+// The same process with the delayed second projection (see k_dcgs_dots): per
+// step the operator on the candidate u, one dot pass, the coefficient kernel,
+// one update pass; after the last step the candidate's delayed projection
+// completes column d-1 and v_d.
+static int arnoldi_run_dcgs2(mpmc_ctx *ctx, const OpDesc &op, void *V, double *H, int d, double *state,
+                             Scratch &S) {
+    const size_t vstep = vec_bytes(ctx, 1, op.prec);
+    void *u = S.get(vstep), *z = S.get(vstep);
+    double2 *D = (double2 *)S.get(sizeof(double2) * (size_t)(2 * d + 4));
+    double2 *C = (double2 *)S.get(sizeof(double2) * (size_t)(2 * d + 4));
+    if (!u || !z || !D || !C) return MPMC_ENOMEM;
+    if (d > 500) return set_err(ctx, MPMC_EINVAL, "Arnoldi: at most 500 steps");
+    HIP_OR_RET(ctx, hipMemsetAsync(H, 0, sizeof(double2) * (size_t)(d + 1) * d, ctx->stream));
+    k_dcgs_init<<<1, 1, 0, ctx->stream>>>(state);
+    HIP_OR_RET(ctx, hipGetLastError());
+    if (op.defl) RET_IF(project_any(ctx, op.defl, V, op.prec));
+    for (int j = 0; j < d; ++j) {
+        const void *cur = j == 0 ? V : u;   // the candidate for v_j (the start vector at j = 0)
+        RET_IF(apply_op(ctx, op, cur, z));
+        RET_IF(dcgs_launch_dots(ctx, op.prec, V, vstep, j, cur, z, D));
+        k_dcgs_coef<<<1, 256, 0, ctx->stream>>>(D, j, d + 1, (double2 *)H, state, C, 0);
+        HIP_OR_RET(ctx, hipGetLastError());
+        RET_IF(dcgs_launch_update(ctx, op.prec, V, vstep, j, cur, z, u, (char *)V + (size_t)j * vstep, C));
+    }
+    RET_IF(dcgs_launch_dots(ctx, op.prec, V, vstep, d, u, nullptr, D));
+    k_dcgs_coef<<<1, 256, 0, ctx->stream>>>(D, d, d + 1, (double2 *)H, state, C, 1);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return dcgs_launch_update(ctx, op.prec, V, vstep, d, u, nullptr, nullptr, (char *)V + (size_t)d * vstep, C);
+}
+
+// Automatic choice: on small lattices the step is launch-bound and the
+// shorter kernels of plain CGS2 win (8^4: GMRES(129) 9.3 against 11.7 ms);
+// from 16^4 sites on the step is bound by the basis passes and the delayed
+// form wins (24^4 FP32: 217 against 160 ms).
+constexpr long kDelayedGsMinV = 65536;
+
+int arnoldi_run(mpmc_ctx *ctx, const OpDesc &op, void *V, double *H, int d, double *state, Scratch &S) {
+    const bool plain = ctx->gs_cgs2 == 1 || (ctx->gs_cgs2 < 0 && ctx->V < kDelayedGsMinV);
+    return plain ? arnoldi_run_cgs2(ctx, op, V, H, d, state, S) : arnoldi_run_dcgs2(ctx, op, V, H, d, state, S);
+}
+
+MPMC_API int mpmc_set_arnoldi_cgs2(mpmc_ctx *ctx, int on) {
+    if (!ctx) return MPMC_EINVAL;
+    if (on < -1 || on > 1) return set_err(ctx, MPMC_EINVAL, "mpmc_set_arnoldi_cgs2: -1, 0 or 1");
+    ctx->gs_cgs2 = on;
     return MPMC_OK;
 }
 

@@ -777,18 +777,25 @@ def f44c():
     return op, ctx, Dref, D
 
 
+@pytest.mark.parametrize("cgs2", [-1, 0])
 @pytest.mark.parametrize("din,dout", [(5, 4), (16, 16)])
-def test_deflated_double_poly_parity(f44c, din, dout):
+def test_deflated_double_poly_parity(f44c, din, dout, cgs2):
     """mpmc_gmres_poly(inner, defl) (Sec. 7: the deflated double polynomial)
     against the oracle's projected outer cycle on Q phi_in from Q b, with the
     same imported deflation set: inner and outer roots, relres, and the
-    GMRES residual identity under the oracle operator with the GPU's roots."""
+    GMRES residual identity under the oracle operator with the GPU's roots;
+    with the default Gram-Schmidt of this size (plain CGS2) and the delayed one."""
     op, ctx, Dref, D = f44c
     b = z4_noise(1, 0x100, 0, op.n)
     Q = OP.projector(Dref.Z, Dref.U)
     ref, (di, do), (ri, ro) = OP.double_poly(op, b, din, dout, proj=Q)
-    Pin = ctx.gmres_poly(1, 0x100, din)
-    Pd = ctx.gmres_poly(1, 0x100, dout, inner=Pin, defl=D)
+    ctx.set_arnoldi_cgs2(cgs2)
+    try:
+        Pin = ctx.gmres_poly(1, 0x100, din)
+        Pd = ctx.gmres_poly(1, 0x100, dout, inner=Pin, defl=D)
+        Pu = ctx.gmres_poly(1, 0x100, dout, inner=Pin)
+    finally:
+        ctx.set_arnoldi_cgs2(-1)
     assert Pd.d_eff == do == dout
     scale = np.max(np.abs(ref.roots))
     assert _match_sets(Pin.roots, ref.inner.roots) < 1e-9 * np.max(np.abs(ref.inner.roots))
@@ -801,7 +808,6 @@ def test_deflated_double_poly_parity(f44c, din, dout):
     r = OP.apply_pi(lambda v: Q(phi(v)), Pd.roots, c)
     assert abs(np.linalg.norm(r) / np.linalg.norm(c) - Pd.relres) < 1e-9 * Pd.relres
     # the undeflated outer cycle is a different polynomial
-    Pu = ctx.gmres_poly(1, 0x100, dout, inner=Pin)
     assert _match_sets(Pu.roots, Pd.roots) > 1e-6 * scale
 
 
@@ -831,6 +837,58 @@ def test_deflated_solve_level_parity(f44c):
     assert T0 == 0
     with pytest.raises(mpmc.MpmcError):
         ctx.set_solve_level_deflation(2)
+
+
+# ------------------------------------------- set-up Gram-Schmidt variants --
+
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-9), (FP32, 1e-4)])
+def test_delayed_and_plain_cgs2_agree(f44, prec, tol):
+    """The set-up Arnoldi with the second projection delayed by one step (the
+    default) and with plain CGS2: the same GMRES roots and relres and the same
+    deflation eigenvalues, to rounding of the storage precision (both forms are
+    held to the oracle by the other tests, which run the default)."""
+    dims, kappa, U, op, ctx = f44
+    ctx.set_setup_precision(prec)
+    out = []
+    try:
+        for cgs2 in (1, 0):
+            ctx.set_arnoldi_cgs2(cgs2)
+            P = ctx.gmres_poly(1, 0x100, 16)
+            Pin = ctx.gmres_poly(1, 0x1FF, 5)
+            D = ctx.deflate(Pin, 1, 0x200, m=60, nev=8)
+            lam, _, _ = ctx.defl_vectors(D)
+            out.append((P, np.asarray(lam)[:D.k], D.k))
+    finally:
+        ctx.set_arnoldi_cgs2(-1)
+        ctx.set_setup_precision(FP64)
+    (P1, l1, k1), (P0, l0, k0) = out
+    assert P0.d_eff == P1.d_eff == 16
+    assert _match_sets(P0.roots, P1.roots) < tol * np.max(np.abs(P1.roots))
+    assert abs(P0.relres - P1.relres) < tol * P1.relres
+    assert k0 == k1 >= 1 and _match_sets(l0, l1) < tol * np.max(np.abs(l1))
+    with pytest.raises(mpmc.MpmcError):
+        ctx.set_arnoldi_cgs2(2)
+
+
+@pytest.mark.parametrize("cgs2", [0, 1])
+@pytest.mark.parametrize("kappa,seed,d", [(0.115, 1, 9), (0.2, 21, 48)])
+def test_delayed_cgs2_roots_parity(cgs2, kappa, seed, d):
+    """GMRES(d) roots and relres of both Gram-Schmidt forms against the oracle
+    (plain CGS2) on the same Z(4) start vector (kappa 0.2: slow convergence,
+    many steps); the kappa = 0 breakdown gives d_eff = 1 in both forms."""
+    dims = (4, 4, 4, 4)
+    U = inputs.gauge_links(dims, 0.5, seed=seed)
+    op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    ctx.set_arnoldi_cgs2(cgs2)
+    P = ctx.gmres_poly(1, 0x100, d)
+    ref, de, rr = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), d)
+    assert P.d_eff == de == d
+    assert _match_sets(P.roots, ref.roots) < 1e-8 * np.max(np.abs(ref.roots))
+    assert abs(P.relres - rr) < 1e-8 * rr
+    c0 = mpmc.Context((2, 2, 2, 2), 0.0, inputs.gauge_links((2, 2, 2, 2), 0.5, seed=1))
+    c0.set_arnoldi_cgs2(cgs2)
+    P0 = c0.gmres_poly(1, 0x100, 16)
+    assert P0.d_eff == 1 and np.allclose(P0.roots, [1.0])
 
 
 # ------------------------------------------------- FP32 setup precision --
