@@ -111,8 +111,9 @@ struct PathSrc {
     bool dag;
 };
 
-__device__ __forceinline__ PathSrc path_src(const int *__restrict__ nbr, const float2 *__restrict__ links, long site,
-                                            int p) {
+// nbw: the site's eight neighbour words, lane i holding entry i & 7 (one load
+// per wavefront instead of one dependent load per path).
+__device__ __forceinline__ PathSrc path_src(int nbw, const float2 *__restrict__ links, long site, int p) {
     PathSrc ps;
     ps.src = site;
     ps.sgn = 1.f;
@@ -120,7 +121,7 @@ __device__ __forceinline__ PathSrc path_src(const int *__restrict__ nbr, const f
     ps.dag = false;
     if (p > 0) {
         const int mu = (p - 1) & 3;
-        const int v = uni(nbr[site * 8 + (p - 1)]);   // forward entries 0..3, backward 4..7
+        const int v = __builtin_amdgcn_readlane(nbw, p - 1);   // forward entries 0..3, backward 4..7
         ps.src = v & 0x7fffffff;
         ps.sgn = v < 0 ? -1.f : 1.f;
         ps.dag = p > 4;
@@ -179,11 +180,12 @@ __global__ __launch_bounds__(256) void k_net_layer(const float2 *__restrict__ in
     f32x4 acc[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nbw = nbr[site * 8 + (lane & 7)];
 
-#pragma unroll 1
+#pragma unroll 3
     for (int p = 0; p < NPATH; ++p) {
         const bf16x4 A = table[p * 64 + lane];
-        const PathSrc ps = path_src(nbr, links, site, p);
+        const PathSrc ps = path_src(nbw, links, site, p);
         float2 a[2][3];
         const float2 *src = in + (ps.src * CIN + f * 12 + s0 * 3) * (long)N + rhs;
 #pragma unroll
@@ -261,9 +263,10 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const float2 *__restrict__ a_
         }
         const int rhs = rb * 16 + n;
         const bool act = rhs < N && f < FIN;
+        const int nbw = nbr[site * 8 + (lane & 7)];
 #pragma unroll 1
         for (int p = 0; p < NPATH; ++p) {
-            const PathSrc ps = path_src(nbr, links, site, p);
+            const PathSrc ps = path_src(nbw, links, site, p);
             float2 a[2][3];
             const float2 *src = a_in + (ps.src * CIN + f * 12 + s0 * 3) * (long)N + rhs;
 #pragma unroll
