@@ -512,6 +512,18 @@ int mpmc_set_setup_precision(mpmc_ctx *ctx, int prec);
  * passes, eight shorter launches).  on = -1 (the default): 1 below 16^4
  * sites, where the steps are launch-bound, else 0.  EINVAL otherwise. */
 int mpmc_set_arnoldi_cgs2(mpmc_ctx *ctx, int on);
+/* Gram-Schmidt of the inner GMRES cycles of mpmc_solve, mpmc_solve_pp,
+ * mpmc_solve_batch and the solves inside mpmc_level_estimate (Sec. 3's GMRES
+ * used as the solver of the M^-1 level): passes = 2 projects each new Krylov
+ * vector twice (classical Gram-Schmidt twice, orthogonal to working
+ * precision); passes = 1 projects it once, which halves the basis traffic of
+ * a step; passes = 0 (the default) takes 1 for FP32 and FP16S inner cycles,
+ * whose targets (2e-6 and 1e-3 of the cycle's start) lie far above the loss
+ * of orthogonality of one projection, and 2 for FP64 inner cycles, which run
+ * to the final tolerance.  The outer FP64 defect correction checks the true
+ * residual either way, so the choice changes iteration counts and time, never
+ * the tolerance met.  EINVAL otherwise. */
+int mpmc_set_solve_gs_passes(mpmc_ctx *ctx, int passes);
 
 /* Polynomial preconditioner used by the main solves inside mpmc_level_estimate
  * when no network is given (NULL: none, the default).  The context keeps the

@@ -66,6 +66,9 @@ struct mpmc_ctx {
     // their Gram-Schmidt: 0 = CGS2 with the second projection delayed one step, 1 = plain CGS2,
     // -1 = by lattice size (plain below 16^4 sites)
     int gs_cgs2 = -1;
+    // projections per inner GMRES step of mpmc_solve / mpmc_solve_batch: 1, 2, or 0 = one for
+    // FP32 and FP16S inner cycles, two for FP64 ones
+    int solve_gs_passes = 0;
     // fused polynomial recurrences replayed from captured hipGraphs (mpmc_set_graph_recurrences)
     int use_graphs = 0;
     hipStream_t gstream = nullptr;          // capture / replay stream (default priority)

@@ -29,10 +29,11 @@ __global__ void k_finalize_batch(double2 *Hcol, const double2 *h2, int j, int N,
                                  double2 *scale) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= N) return;
-    for (int i = 0; i <= j; ++i) {
-        Hcol[(long)i * N + r].x += h2[(long)i * N + r].x;
-        Hcol[(long)i * N + r].y += h2[(long)i * N + r].y;
-    }
+    if (h2)
+        for (int i = 0; i <= j; ++i) {
+            Hcol[(long)i * N + r].x += h2[(long)i * N + r].x;
+            Hcol[(long)i * N + r].y += h2[(long)i * N + r].y;
+        }
     const double hn = sqrt(fmax(nrm2[r].x, 0.0));
     Hcol[(long)(j + 1) * N + r] = make_double2(hn, 0.0);
     scale[r] = make_double2(hn > 1e-290 ? 1.0 / hn : 0.0, 0.0);
@@ -281,7 +282,17 @@ int Gmres::orthogonalize(int j, bool *more) {
     mpmc_ctx *ctx = ctx_;
     const int N = N_, m = m_;
     double *Hcol = H_ + 2 * (size_t)j * (m + 1) * N;
-    if (half_) {
+    // FP32 and FP16S cycles stop at 2e-6 and 1e-3 of their start, far above
+    // the loss of orthogonality of one classical projection in FP32
+    // arithmetic; FP64 cycles run to the final tolerance and project twice
+    const bool once = ctx->solve_gs_passes == 1 || (ctx->solve_gs_passes == 0 && inner_prec_ != MPMC_FP64);
+    if (once && half_) {
+        RET_IF(blas_multi_dot_h(ctx, V_, vbb_, j + 1, w_, N, Hcol, 0));
+        RET_IF(blas_multi_axpy_h(ctx, V_, vbb_, j + 1, w_, N, Hcol, N, -1.0, nrm_));
+    } else if (once) {
+        RET_IF(blas_multi_dot(ctx, V_, vstride_, N, j + 1, w_, N, pw_, Hcol, 0, 0));
+        RET_IF(blas_multi_axpy(ctx, V_, vstride_, N, j + 1, w_, N, pw_, Hcol, N, -1.0, nrm_));
+    } else if (half_) {
         RET_IF(blas_multi_dot_h(ctx, V_, vbb_, j + 1, w_, N, Hcol, 0));
         RET_IF(blas_multi_axpy_h(ctx, V_, vbb_, j + 1, w_, N, Hcol, N, -1.0, nullptr));
         RET_IF(blas_multi_dot_h(ctx, V_, vbb_, j + 1, w_, N, h2_, 0));
@@ -291,8 +302,8 @@ int Gmres::orthogonalize(int j, bool *more) {
         RET_IF(blas_multi_axpy_dot(ctx, V_, vstride_, j + 1, w_, N, pw_, Hcol, N, -1.0, h2_));
         RET_IF(blas_multi_axpy(ctx, V_, vstride_, N, j + 1, w_, N, pw_, h2_, N, -1.0, nrm_));
     }
-    k_finalize_batch<<<grid_for(N, 64), 64, 0, ctx->stream>>>((double2 *)Hcol, (const double2 *)h2_, j, N,
-                                                              (const double2 *)nrm_, (double2 *)scale_);
+    k_finalize_batch<<<grid_for(N, 64), 64, 0, ctx->stream>>>((double2 *)Hcol, once ? nullptr : (const double2 *)h2_,
+                                                              j, N, (const double2 *)nrm_, (double2 *)scale_);
     HIP_OR_RET(ctx, hipGetLastError());
     if (half_) {
         RET_IF(blas_scale_rhs(ctx, w_, w_, N, MPMC_FP32, scale_, 0));
@@ -463,6 +474,13 @@ MPMC_API int mpmc_solve_pairs(mpmc_ctx *ctx, const void *b, void *x, int nrhs, c
                                   relres_host, &sn, nullptr);
     *nsnap_host = sn.count;
     return rc;
+}
+
+MPMC_API int mpmc_set_solve_gs_passes(mpmc_ctx *ctx, int passes) {
+    if (!ctx) return MPMC_EINVAL;
+    if (passes < 0 || passes > 2) return set_err(ctx, MPMC_EINVAL, "mpmc_set_solve_gs_passes: 0, 1 or 2");
+    ctx->solve_gs_passes = passes;
+    return MPMC_OK;
 }
 
 MPMC_API int mpmc_solve(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc_defl *defl, const mpmc_net *net,

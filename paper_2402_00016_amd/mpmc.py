@@ -90,6 +90,7 @@ _SIGS = {
     "mpmc_set_site_order": ([_vp, _vp], _i),
     "mpmc_set_setup_precision": ([_vp, _i], _i),
     "mpmc_set_arnoldi_cgs2": ([_vp, _i], _i),
+    "mpmc_set_solve_gs_passes": ([_vp, _i], _i),
     "mpmc_set_graph_recurrences": ([_vp, _i], _i),
     "mpmc_graph_replays": ([_vp, _pu64, _pi], _i),
     "mpmc_probe_colouring": ([_pi, _i, _pi, _pi, _pi, ctypes.POINTER(ctypes.c_long)], _i),
@@ -743,6 +744,11 @@ class Context:
         """1: plain CGS2 in the set-up Arnoldi cycles; 0: CGS2 with the second projection delayed;
         -1 (default): by lattice size."""
         _check(_L.mpmc_set_arnoldi_cgs2(self.handle, int(on)), self.handle)
+
+    def set_solve_gs_passes(self, passes):
+        """Projections per inner GMRES step of the solves: 1, 2, or 0 (default: 1 for FP32/FP16S
+        inner cycles, 2 for FP64)."""
+        _check(_L.mpmc_set_solve_gs_passes(self.handle, int(passes)), self.handle)
 
     def set_setup_precision(self, prec):
         """Storage of the Arnoldi vectors of gmres_poly and deflate (FP64 or FP32)."""

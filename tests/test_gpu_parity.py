@@ -689,6 +689,36 @@ def test_solve_fp16_basis_matches_fp32(N):
     assert np.linalg.norm(bj - op(X16[j])) / np.linalg.norm(bj) <= 1.05e-9
 
 
+@pytest.mark.parametrize("inner", [FP64, FP32, FP16S])
+def test_solve_gram_schmidt_passes(inner):
+    """One or two classical projections per inner GMRES step: both reach the
+    true FP64 residual (checked under the oracle operator on a sampled
+    right-hand side) and the same solution; one projection costs at most one
+    more 10-step convergence check of inner iterations; the default (0) is one
+    projection for FP32/FP16S inner cycles and two for FP64."""
+    dims, kappa = (8, 8, 8, 8), 0.120
+    U = inputs.gauge_links(dims, 0.5, seed=2)
+    ctx = mpmc.Context(dims, kappa, U)
+    op = WilsonOp(dims, kappa, U)
+    N, tol = 20, 1e-9
+    b = ctx.noise(9, 0, 0, N, FP64)
+    out = {}
+    for passes in (2, 1, 0):
+        ctx.set_solve_gs_passes(passes)
+        out[passes] = ctx.solve(b, N, restart=50, tol=tol, inner_prec=inner)
+    X = {p: host(ctx.unpack(x, N)) for p, (x, _, _) in out.items()}
+    for p in (1, 2):
+        assert np.all(out[p][2] <= tol)
+        bj = z4_noise(9, 0, 11, op.n)
+        assert np.linalg.norm(bj - op(X[p][11])) / np.linalg.norm(bj) <= 1.05 * tol
+    assert rel(X[1], X[2]) < 5 * tol
+    assert out[1][1] <= out[2][1] + 10
+    dflt = 2 if inner == FP64 else 1
+    assert out[0][1] == out[dflt][1] and torch.equal(out[0][0], out[dflt][0])
+    with pytest.raises(mpmc.MpmcError):
+        ctx.set_solve_gs_passes(3)
+
+
 # ------------------------------------------------- PP-GMRES main solves --
 
 @pytest.mark.parametrize("inner", [FP64, FP32, FP16S])
