@@ -20,7 +20,10 @@ Z(4) vector of seed net_seed0, net_seed0 + 1, ..., stream 0), and then
 preconditions the main solves (flexible GMRES).  The solves still stop on the same FP64 true
 residual, so the estimate does not depend on N.
 """
+import hashlib
+import json
 import math
+import os
 import threading
 import time
 from dataclasses import dataclass, field
@@ -444,16 +447,162 @@ def estimate(ctx, plan: Plan, sync=None, net=None) -> Estimate:
                     defl_k=defl.k if defl is not None else 0, info=info)
 
 
-def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_every=3, max_noises=4096, net=None):
+# ------------------------------------------------------ checkpoint / resume --
+# The state of an adaptive estimate is its set-up (polynomial roots, the
+# deflation set, the network weights) and the samples of every term so far.
+# Noise vector i of term l is regenerated from (seed, l, i), so a resumed run
+# continues each term at its next index and reproduces the samples of an
+# uninterrupted run.  Files: <dir>/setup.npz (written once) and <dir>/mc.npz
+# (rewritten after every batch), each replaced atomically; both hold only
+# numeric and string arrays (read with allow_pickle=False).
+
+CHECKPOINT_VERSION = 1
+
+
+def _links_digest(ctx):
+    d = getattr(ctx, "_links_sha256", None)
+    if d is None:
+        a = ctx.links
+        a = a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+        d = hashlib.sha256(memoryview(np.ascontiguousarray(a).reshape(-1).view(np.uint8))).hexdigest()
+        ctx._links_sha256 = d
+    return d
+
+
+def plan_identity(ctx, plan: Plan):
+    """JSON text naming the lattice (extents, kappa, boundary, SHA-256 of the
+    links) and every plan field: a checkpoint is only resumed under the
+    identical configuration."""
+    fields = {k: (list(v) if isinstance(v, tuple) else v) for k, v in sorted(plan.__dict__.items())}
+    return json.dumps({"version": CHECKPOINT_VERSION, "dims": list(ctx.dims), "kappa": float(ctx.kappa),
+                       "t_antiperiodic": bool(ctx.t_antiperiodic), "links_sha256": _links_digest(ctx),
+                       "plan": fields}, sort_keys=True, default=lambda v: list(v) if isinstance(v, tuple) else str(v))
+
+
+def _atomic_savez(path, arrays):
+    tmp = path + ".tmp"
+    with open(tmp, "wb") as f:
+        np.savez(f, **arrays)
+    os.replace(tmp, path)
+
+
+def _check_identity(z, ident, path):
+    if str(z["identity"]) != ident:
+        raise ValueError("checkpoint %s was written for another lattice or plan" % path)
+
+
+def save_setup(path, ctx, plan: Plan, polys, defl, net=None):
+    """Polynomials (roots, inner polynomials, d_eff, relres, deflated flag), the
+    deflation set (eigenvalues, right and left vectors, p_in) and the network
+    weights."""
+    arrays = {"identity": np.array(plan_identity(ctx, plan))}
+    handles, index = [], {}
+
+    def reg(p):
+        if p is None:
+            return -1
+        if id(p) not in index:
+            inner = reg(p.inner)
+            index[id(p)] = len(handles)
+            handles.append((p, inner))
+        return index[id(p)]
+
+    top = [reg(p) for p in polys]
+    pin = reg(getattr(defl, "p_in", None)) if defl is not None else -1
+    meta = []
+    for i, (p, inner) in enumerate(handles):
+        arrays["poly%d_roots" % i] = np.asarray(p.roots, dtype=np.complex128)
+        meta.append({"inner": inner, "d_eff": p.d_eff, "relres": p.relres, "deflated": bool(p.deflated)})
+    arrays["polys"] = np.array(json.dumps({"handles": meta, "top": top, "defl_p_in": pin,
+                                           "defl_k": -1 if defl is None else int(defl.k)}))
+    if defl is not None and defl.k > 0:
+        lam, Z, U = ctx.defl_vectors(defl)
+        arrays["defl_lam"] = np.asarray(lam, dtype=np.complex128)[:defl.k]
+        arrays["defl_Z"] = Z.cpu().numpy()
+        arrays["defl_U"] = U.cpu().numpy()
+    if net is not None:
+        arrays["net_weights"] = np.asarray(net.weights, dtype=np.float64)
+    _atomic_savez(path, arrays)
+
+
+def load_setup(path, ctx, plan: Plan):
+    """(polys, defl, net) of save_setup as handles of ctx."""
+    with np.load(path, allow_pickle=False) as z:
+        _check_identity(z, plan_identity(ctx, plan), path)
+        info = json.loads(str(z["polys"]))
+        handles = []
+        for i, m in enumerate(info["handles"]):
+            inner = handles[m["inner"]] if m["inner"] >= 0 else None
+            q = ctx.poly_from_roots(z["poly%d_roots" % i], inner=inner)
+            q.d_eff, q.relres, q.deflated = m["d_eff"], m["relres"], m["deflated"]
+            handles.append(q)
+        polys = [handles[i] for i in info["top"]]
+        defl = None
+        if info["defl_k"] >= 0:
+            if info["defl_k"] > 0:
+                t = ctx.torch
+                defl = ctx.defl_from_arrays(z["defl_lam"], t.from_numpy(z["defl_Z"]).cuda(),
+                                            t.from_numpy(z["defl_U"]).cuda())
+            else:   # an empty set keeps the deflated code paths of the original run
+                t = ctx.torch
+                e = t.zeros((0, ctx.n), dtype=t.complex128, device="cuda")
+                defl = ctx.defl_from_arrays(np.zeros(0, dtype=np.complex128), e, e)
+            defl.p_in = handles[info["defl_p_in"]] if info["defl_p_in"] >= 0 else None
+        net = ctx.net(z["net_weights"]) if "net_weights" in z else None
+    return polys, defl, net
+
+
+def save_mc(path, ctx, plan: Plan, terms):
+    """terms: one record per term begun, in order: (LevelResult, done)."""
+    arrays = {"identity": np.array(plan_identity(ctx, plan))}
+    meta = []
+    for l, (L, done) in enumerate(terms):
+        arrays["term%d_samples" % l] = np.asarray(L.samples, dtype=np.complex128)
+        meta.append({"name": L.name, "corr": [L.corr.real, L.corr.imag], "mvps": int(L.mvps),
+                     "seconds": float(L.seconds), "exact": bool(L.exact), "done": bool(done)})
+    arrays["terms"] = np.array(json.dumps(meta))
+    _atomic_savez(path, arrays)
+
+
+def load_mc(path, ctx, plan: Plan):
+    with np.load(path, allow_pickle=False) as z:
+        _check_identity(z, plan_identity(ctx, plan), path)
+        out = []
+        for l, m in enumerate(json.loads(str(z["terms"]))):
+            L = LevelResult(m["name"], z["term%d_samples" % l].copy(), complex(*m["corr"]), m["mvps"], m["seconds"],
+                            exact=m["exact"])
+            out.append((L, m["done"]))
+    return out
+
+
+def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_every=3, max_noises=4096, net=None,
+                      checkpoint=None, on_batch=None):
     """Adaptive stopping (Sec. 8): each Monte Carlo term stops once its standard
     error is below eps / sqrt(#terms), with minimum counts 2 (solve term),
     3 (first difference), 6 (later terms) and checks every `check_every` noises
-    (an int, or one count per term)."""
+    (an int, or one count per term).
+
+    checkpoint: a directory; the set-up is saved there once and the samples
+    after every batch, and a run given a directory that holds them resumes
+    (same lattice and plan) instead of starting over.  on_batch(term, count) is
+    called after each batch has been saved."""
     mv0 = total_mvps(ctx)
     t0 = time.perf_counter()
-    defl, polys, tnet, _ = build_setup(ctx, plan, train=plan.learned and net is None)
+    setup_file = mc_file = None
+    if checkpoint is not None:
+        os.makedirs(checkpoint, exist_ok=True)
+        setup_file, mc_file = os.path.join(checkpoint, "setup.npz"), os.path.join(checkpoint, "mc.npz")
+    if setup_file is not None and os.path.exists(setup_file):
+        polys, defl, tnet = load_setup(setup_file, ctx, plan)
+        if plan.learned and net is None and tnet is None:
+            raise ValueError("checkpoint %s holds no network for a learned plan" % setup_file)
+    else:
+        defl, polys, tnet, _ = build_setup(ctx, plan, train=plan.learned and net is None)
+        if setup_file is not None:
+            save_setup(setup_file, ctx, plan, polys, defl, tnet)
     net = tnet if tnet is not None else net
     t_setup = time.perf_counter() - t0
+    resume = load_mc(mc_file, ctx, plan) if mc_file is not None and os.path.exists(mc_file) else []
     nterms = len(polys) + (0 if plan.probe_last and polys else 1)
     target = eps / math.sqrt(nterms)
     levels = []
@@ -462,8 +611,20 @@ def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_e
     pp = solve_preconditioner(ctx, plan, defl) if not plan.learned else None
     ctx.set_level_solve_poly(pp)
     ctx.set_solve_level_deflation(solve_level_deflated(polys, defl))
+    terms = []
+
+    def saved(l, L, done):
+        if l == len(terms):
+            terms.append(None)
+        terms[l] = (L, done)
+        if mc_file is not None:
+            save_mc(mc_file, ctx, plan, terms)
+        if on_batch is not None:
+            on_batch(l, L.n)
+
     try:
-        _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, check_every, max_noises, levels)
+        _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, check_every, max_noises, levels,
+                         resume, saved)
     finally:
         ctx.set_level_solve_poly(None)
         ctx.set_solve_level_deflation(0)
@@ -472,16 +633,27 @@ def estimate_to_error(ctx, plan: Plan, eps: float, min_counts=(2, 3, 6), check_e
                     defl_k=defl.k if defl is not None else 0)
 
 
-def _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, check_every, max_noises, levels):
+def _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, check_every, max_noises, levels,
+                     resume=(), saved=None):
+    """resume: (LevelResult, done) per term begun by an earlier run; saved(l,
+    LevelResult, done) after every batch."""
+    saved = saved or (lambda l, L, done: None)
     for l, (up, lo) in enumerate(zip(uppers, lowers)):
+        if l < len(resume) and resume[l][1]:
+            levels.append(resume[l][0])
+            saved(l, resume[l][0], True)
+            continue
         if plan.probe_last and up is not None and lo is None:
             levels.append(probe_term(ctx, plan, up, "term %d" % l))
+            saved(l, levels[-1], True)
             continue
         d = defl if (up is not None and lo is not None and plan.deflate_levels) else (defl if up is None else None)
         n0 = min_counts[min(l, len(min_counts) - 1)]
         step = check_every if isinstance(check_every, int) else check_every[min(l, len(check_every) - 1)]
         X = np.zeros(0, dtype=np.complex128)
         corr, mv, secs = 0j, 0, 0.0
+        if l < len(resume):   # a term interrupted after some batches
+            X, corr, mv, secs = resume[l][0].samples, resume[l][0].corr, resume[l][0].mvps, resume[l][0].seconds
         while True:
             want = n0 if len(X) == 0 else step
             ts = time.perf_counter()
@@ -493,7 +665,9 @@ def _levels_to_error(ctx, plan, defl, uppers, lowers, net, target, min_counts, c
             mv += m
             X = np.concatenate([X, Xn])
             var = np.sum(np.abs(X - X.mean()) ** 2) / (len(X) - 1) if len(X) > 1 else math.inf
-            if math.sqrt(var / len(X)) <= target or len(X) >= max_noises:
+            done = math.sqrt(var / len(X)) <= target or len(X) >= max_noises
+            saved(l, LevelResult("term %d" % l, X, corr, mv, secs), done)
+            if done:
                 break
         levels.append(LevelResult("term %d" % l, X, corr, mv, secs))
 

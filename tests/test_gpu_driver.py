@@ -145,3 +145,40 @@ def test_estimate_to_error_stops_at_target(ctx, dense44, probe):
     assert e.stderr <= eps * 1.0000001
     assert len(e.levels) == 3 and (e.levels[-1].exact == probe)
     assert abs(e.value - np.trace(dense44)) < 3 * max(e.stderr, 1e-9)
+
+
+class _Stop(Exception):
+    pass
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_estimate_to_error_resumes_from_checkpoint(ctx, tmp_path, learned):
+    """An adaptive estimate interrupted after its fourth batch and resumed from
+    its checkpoint directory gives every term's samples, counts and the
+    estimate of the same run left uninterrupted (noise i of term l comes from
+    (seed, l, i); the set-up is reloaded from its roots, eigenpairs and
+    weights)."""
+    p = plan(seed=7, degrees=[(3, 3), 24, 8], learned=learned, net_batches=1, net_pairs=16)
+    eps = 1.0
+    full = driver.estimate_to_error(ctx, p, eps, check_every=3, checkpoint=str(tmp_path / "a"))
+    seen = []
+
+    def stop(l, n):
+        seen.append((l, n))
+        if len(seen) == 4:
+            raise _Stop()
+
+    with pytest.raises(_Stop):
+        driver.estimate_to_error(ctx, p, eps, check_every=3, checkpoint=str(tmp_path / "b"), on_batch=stop)
+    state = driver.load_mc(str(tmp_path / "b" / "mc.npz"), ctx, p)
+    assert state[seen[-1][0]][0].n == seen[-1][1] and len(state) == seen[-1][0] + 1
+    resumed = driver.estimate_to_error(ctx, p, eps, check_every=3, checkpoint=str(tmp_path / "b"))
+    assert [L.name for L in resumed.levels] == [L.name for L in full.levels]
+    for L0, L1 in zip(full.levels, resumed.levels):
+        assert L0.n == L1.n and np.array_equal(L0.samples, L1.samples) and L0.corr == L1.corr
+    assert resumed.value == full.value and resumed.stderr == full.stderr
+    # a finished checkpoint resumes to the same result without new samples
+    again = driver.estimate_to_error(ctx, p, eps, check_every=3, checkpoint=str(tmp_path / "b"))
+    assert again.value == full.value
+    with pytest.raises(ValueError):   # another plan on the same directory
+        driver.estimate_to_error(ctx, plan(seed=8, degrees=[(3, 3), 24, 8]), eps, checkpoint=str(tmp_path / "b"))
