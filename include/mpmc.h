@@ -388,8 +388,10 @@ int mpmc_wilson_variant_count(void);
  * estimators (variants 0-3: site-major, 4-9: blocked chunks, 10 and 11:
  * column streaming with 2x2x2 and 2x2x1 tiles), overriding
  * mpmc_autotune_level.  For nrhs = 1 (single vectors) variant 0 selects
- * eight lanes per site (one hop each), 1 one site per lane; the default is 0
- * up to 12^4 sites and 1 above. */
+ * eight lanes per site (one hop each), 1 the generic kernel with one site per
+ * lane, 2 the single-vector kernel with one site per lane (coordinate-derived
+ * neighbours; the same results as 1 bit for bit); the default is 0 up to 12^4
+ * sites and 2 above. */
 int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant);
 /* Autotune the fused polynomial step of mpmc_level_estimate (the dominant
  * kernel of the polynomial levels, Sec. 6): every traversal valid for the

@@ -842,6 +842,198 @@ __global__ __launch_bounds__(256) void k_wilson1(const void *__restrict__ b, con
     }
 }
 
+// ---------------------------------------- single vectors, large lattices --
+// One site per lane, lexicographic sites (consecutive lanes, consecutive x).
+// Against the generic kernel at one right-hand side: the neighbour index and
+// the antiperiodic sign follow from the site's coordinates (no table load in
+// each hop's dependency chain), the neighbour's 12 components arrive as
+// 16-byte loads, and an FP32 link as four 16-byte loads and one 8-byte load
+// (link mu of a site starts 72 mu bytes into the site's 288, so its 16-byte
+// alignment is known from mu at compile time).  The hop arithmetic is the
+// generic kernel's (apply), so M b is the same bit for bit; the accumulator
+// start y = yinit b of a polynomial's first step is fused into the epilogue.
+// Site indices are 32-bit here (the library keeps V below 2^31): the
+// neighbour offset is a select between two constants, so no branch splits the
+// hops (a branch would let the compiler sink each hop's arithmetic below the
+// next hops' loads and hold all eight neighbours in registers at once).
+struct SvGeom {
+    int L[4];
+    int st[4];     // site strides 1, Lx, Lx Ly, Lx Ly Lz
+    int wrap[4];   // (L_mu - 1) st_mu
+    int anti;      // antiperiodic in t
+};
+
+template <int P, int MU, bool FWD>
+__device__ __forceinline__ void fetch_sv(const void *__restrict__ b, const typename LinkT<P>::type *__restrict__ links,
+                                         const SvGeom &G, int s, const int c[4], HopData<P> &H) {
+    using T = typename Store<P>::real;
+    const bool edge = FWD ? c[MU] == G.L[MU] - 1 : c[MU] == 0;
+    const int off = FWD ? (edge ? -G.wrap[MU] : G.st[MU]) : (edge ? G.wrap[MU] : -G.st[MU]);
+    const int sn = s + off;
+    H.bsign = (MU == 3 && G.anti && edge) ? T(-1) : T(1);
+    if constexpr (P == MPMC_FP32) {
+        const float4 *p4 = reinterpret_cast<const float4 *>(b) + (long)sn * 6;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const float4 v = p4[i];
+            H.psi[2 * i] = mk(v.x, v.y);
+            H.psi[2 * i + 1] = mk(v.z, v.w);
+        }
+        const float2 *lk = links + ((long)(FWD ? s : sn) * 4 + MU) * 9;
+        if constexpr ((MU & 1) == 0) {   // 16-byte aligned: elements 0-7 as pairs, then 8
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float4 v = reinterpret_cast<const float4 *>(lk)[i];
+                H.u[2 * i] = mk(v.x, v.y);
+                H.u[2 * i + 1] = mk(v.z, v.w);
+            }
+            const float2 v8 = lk[8];
+            H.u[8] = mk(v8.x, v8.y);
+        } else {                          // 8 bytes past alignment: element 0, then 1-8 as pairs
+            const float2 v0 = lk[0];
+            H.u[0] = mk(v0.x, v0.y);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float4 v = reinterpret_cast<const float4 *>(lk + 1)[i];
+                H.u[2 * i + 1] = mk(v.x, v.y);
+                H.u[2 * i + 2] = mk(v.z, v.w);
+            }
+        }
+    } else {
+        const double2 *p = reinterpret_cast<const double2 *>(b) + (long)sn * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) H.psi[k] = mk(p[k].x, p[k].y);
+        const double2 *lk = links + ((long)(FWD ? s : sn) * 4 + MU) * 9;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) H.u[i] = mk(lk[i].x, lk[i].y);
+    }
+}
+
+#define MPMC_FENCE __builtin_amdgcn_sched_barrier(0)
+template <int P, int D, int I>
+__device__ __forceinline__ void sv_step(const void *__restrict__ b, const typename LinkT<P>::type *__restrict__ links,
+                                        const SvGeom &G, int s, const int c[4], float g, HopData<P> (&H)[D],
+                                        cpx<typename Store<P>::real> acc[4][3]) {
+    if constexpr (I < 8) {
+        apply<P, false, I / 2, (I % 2) == 0, false>(H[I % D], g, acc);
+        MPMC_FENCE;
+        if constexpr (I + D < 8) {
+            fetch_sv<P, (I + D) / 2, ((I + D) % 2) == 0>(b, links, G, s, c, H[I % D]);
+            MPMC_FENCE;
+        }
+        sv_step<P, D, I + 1>(b, links, G, s, c, g, H, acc);
+    }
+}
+template <int P, int D, int I>
+__device__ __forceinline__ void sv_prologue(const void *__restrict__ b,
+                                            const typename LinkT<P>::type *__restrict__ links, const SvGeom &G,
+                                            int s, const int c[4], HopData<P> (&H)[D]) {
+    if constexpr (I < D) {
+        fetch_sv<P, I / 2, (I % 2) == 0>(b, links, G, s, c, H[I]);
+        MPMC_FENCE;
+        sv_prologue<P, D, I + 1>(b, links, G, s, c, H);
+    }
+}
+#undef MPMC_FENCE
+
+template <int P>
+__device__ __forceinline__ void sv_load12(const void *p, int s, cpx<typename Store<P>::real> v[12]) {
+    if constexpr (P == MPMC_FP32) {
+        const float4 *p4 = reinterpret_cast<const float4 *>(p) + (long)s * 6;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const float4 w = p4[i];
+            v[2 * i] = mk(w.x, w.y);
+            v[2 * i + 1] = mk(w.z, w.w);
+        }
+    } else {
+        const double2 *p2 = reinterpret_cast<const double2 *>(p) + (long)s * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = mk(p2[k].x, p2[k].y);
+    }
+}
+template <int P>
+__device__ __forceinline__ void sv_store12(void *p, int s, const cpx<typename Store<P>::real> v[12]) {
+    if constexpr (P == MPMC_FP32) {
+        float4 *p4 = reinterpret_cast<float4 *>(p) + (long)s * 6;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) p4[i] = make_float4(v[2 * i].re, v[2 * i].im, v[2 * i + 1].re, v[2 * i + 1].im);
+    } else {
+        double2 *p2 = reinterpret_cast<double2 *>(p) + (long)s * 12;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) p2[k] = make_double2(v[k].re, v[k].im);
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_FP64 ? 2 : 3))) void k_wilson_sv(const void *__restrict__ b,
+                                                   const typename LinkT<P>::type *__restrict__ links, WOut o,
+                                                   SvGeom G, long V, double2 yinit, int yinit_on) {
+    using T = typename Store<P>::real;
+    const unsigned su = xcd_tile(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+    if (su >= (unsigned)V) return;
+    const int s = (int)su;
+    int c[4];
+    {
+        unsigned q = su;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            const unsigned qn = q / (unsigned)G.L[mu];
+            c[mu] = (int)(q - qn * (unsigned)G.L[mu]);
+            q = qn;
+        }
+    }
+    cpx<T> acc[4][3];
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) acc[sp][cc] = mk(T(0), T(0));
+    {
+        HopData<P> H[2];
+        sv_prologue<P, 2, 0>(b, links, G, s, c, H);
+        sv_step<P, 2, 0>(b, links, G, s, c, o.g, H, acc);
+    }
+    pin_acc(acc);
+    // epilogue: the generic kernel's arithmetic (wilson_site)
+    const T kap = (T)o.kappa;
+    const bool has_a = o.a_is_b || o.a;
+    const cpx<T> al = has_a ? mk((T)o.alpha.x, (T)o.alpha.y) : mk(T(0), T(0));
+    const cpx<T> be = mk((T)o.beta.x, (T)o.beta.y);
+    const cpx<T> beg5 = o.theta ? mk(-be.re, -be.im) : be;
+    cpx<T> bv[12], res[12];
+    sv_load12<P>(b, s, bv);
+    if (o.a && !o.a_is_b) {
+        cpx<T> av[12];
+        sv_load12<P>(o.a, s, av);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const cpx<T> mb = bv[k] - kap * acc[k / 3][k % 3];
+            res[k] = (k >= 6 ? beg5 : be) * mb + al * av[k];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const cpx<T> mb = bv[k] - kap * acc[k / 3][k % 3];
+            res[k] = (k >= 6 ? beg5 : be) * mb + al * bv[k];
+        }
+    }
+    sv_store12<P>(o.out, s, res);
+    if (o.y) {
+        const cpx<T> ga = mk((T)o.gamma.x, (T)o.gamma.y);
+        cpx<T> yv[12];
+        if (yinit_on) {   // y = yinit b + gamma out (b is also the additive operand here)
+            const cpx<T> yi = mk((T)yinit.x, (T)yinit.y);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) yv[k] = yi * bv[k] + ga * res[k];
+        } else {
+            sv_load12<P>(o.y, s, yv);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) yv[k] = yv[k] + ga * res[k];
+        }
+        sv_store12<P>(o.y, s, yv);
+    }
+}
+
 // ------------------------------------------------- fused level step --
 // w' = w - c M w for a batch whose rhs r is noise vector eta_r (2-bit codes in
 // codes[s*N + r]); partial[blk][rl] += cnext * sum_k conj(eta_k) (Theta w')_k
@@ -1479,13 +1671,26 @@ static void launch_uniform(mpmc_ctx *ctx, const WIn<P> &in, const WOut &o, int n
 // Single vectors: k_wilson1 (eight lanes per site, one hop each, one
 // wavefront per workgroup) keeps a small lattice's dependent chain of
 // launches short; on large lattices its scattered per-lane loads dominate and
-// the generic kernel with one site per lane (all eight hops in the lane) is
-// faster.  mpmc_tune_set(ctx, 1, prec, 0 or 1) pins one (1 = site per lane).
+// one site per lane (all eight hops in the lane) is faster: k_wilson_sv, or
+// the generic kernel at one right-hand side.  mpmc_tune_set(ctx, 1, prec, v)
+// pins one: v = 0 k_wilson1, 1 the generic kernel, 2 k_wilson_sv.
 constexpr long kWilson1MaxV = 20736;   // 12^4 sites
-static bool single_site_per_lane(const mpmc_ctx *ctx, int prec) {
+static int single_vector_kernel(const mpmc_ctx *ctx, int prec) {
     const auto it = ctx->tune.find(std::make_pair(1, prec));
-    if (it != ctx->tune.end()) return it->second == 1;
-    return ctx->V > kWilson1MaxV;
+    if (it != ctx->tune.end() && it->second <= 2) return it->second;
+    return ctx->V > kWilson1MaxV ? 2 : 0;
+}
+static SvGeom sv_geom(const mpmc_ctx *ctx) {
+    SvGeom G;
+    int st = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        G.L[mu] = ctx->dims[mu];
+        G.st[mu] = st;
+        G.wrap[mu] = (ctx->dims[mu] - 1) * st;
+        st *= ctx->dims[mu];
+    }
+    G.anti = ctx->t_antiperiodic;
+    return G;
 }
 
 template <int P>
@@ -1495,9 +1700,15 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs, double2 yi
     WIn<P> in = make_in<P>(ctx, b, nrhs);
     if constexpr (P != MPMC_FP16S) {
         if (nrhs == 1) {
-            if (!single_site_per_lane(ctx, P)) {
+            const int sv = single_vector_kernel(ctx, P);
+            if (sv == 0) {
                 k_wilson1<P><<<grid_for(ctx->V * 8, 64), 64, 0, ctx->stream>>>(in.b, in.nbr, in.links, o, ctx->V,
                                                                                 yinit, yinit_on);
+                return;
+            }
+            if (sv == 2) {
+                k_wilson_sv<P><<<grid_for(ctx->V, 256), 256, 0, ctx->stream>>>(in.b, in.links, o, sv_geom(ctx),
+                                                                               ctx->V, yinit, yinit_on);
                 return;
             }
             // site per lane (the generic kernel below); the accumulator start
@@ -1871,7 +2082,7 @@ MPMC_API int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host,
     hipEvent_t e0, e1;
     HIP_OR_RET(ctx, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return set_err(ctx, MPMC_EHIP, "mpmc_autotune: event creation failed");
     }
     const int timing = ctx->timing;
@@ -1901,8 +2112,8 @@ MPMC_API int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host,
             best = v;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     ctx->timing = timing;
     ctx->mvps = mvps;
     ctx->tune[key] = best;
@@ -1932,7 +2143,7 @@ MPMC_API int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_h
     hipEvent_t e0, e1;
     HIP_OR_RET(ctx, hipEventCreate(&e0));
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return set_err(ctx, MPMC_EHIP, "mpmc_autotune_level: event creation failed");
     }
     const int timing = ctx->timing;
@@ -1974,8 +2185,8 @@ MPMC_API int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_h
             best = o;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     ctx->timing = timing;
     ctx->mvps = mvps;
     ctx->tune_dot[key] = best;

@@ -218,16 +218,19 @@ def test_apply_poly_parity(f44, prec, tol, N):
     assert P.info["degree"] == 15 and P.info["matvecs"] == 15
 
 
+@pytest.mark.parametrize("variant", [1, 2])
 @pytest.mark.parametrize("prec,tol_m,tol_p", [(FP64, 1e-13, 1e-12), (FP32, 2e-6, 2e-5)])
-def test_single_vector_site_per_lane(f44, prec, tol_m, tol_p):
-    """Single vectors with one site per lane (the default above 12^4 sites;
-    pinned here with mpmc_tune_set(ctx, 1, prec, 1)): M, M^H and gamma5 M
-    against the oracle, and a polynomial on one vector, whose accumulator
-    start y = x / theta_1 is then a separate pass."""
+def test_single_vector_site_per_lane(f44, prec, tol_m, tol_p, variant):
+    """Single vectors with one site per lane, pinned with mpmc_tune_set(ctx, 1,
+    prec, v): v = 2 the single-vector kernel (the default above 12^4 sites),
+    v = 1 the generic kernel at one right-hand side.  M, M^H and gamma5 M
+    against the oracle, and a polynomial on one vector (its accumulator start
+    y = x / theta_1 fused into the first step for v = 2, a separate pass for
+    v = 1)."""
     dims, kappa, U, op, ctx = f44
     xh = z4_noise(9, 1, 0, op.n)
     ref, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 16)
-    ctx.tune_set(1, prec, 1)
+    ctx.tune_set(1, prec, variant)
     try:
         x = ctx.noise(9, 1, 0, 1, prec)
         for dagger, theta in ((False, 0), (True, 0), (False, 1)):
@@ -241,6 +244,32 @@ def test_single_vector_site_per_lane(f44, prec, tol_m, tol_p):
         assert rel(got, OP.apply_p(op, ref.roots, xh)) < tol_p
     finally:
         ctx.tune_set(1, prec, -1)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (3, 5, 4, 6)])
+def test_single_vector_kernel_matches_generic(prec, dims):
+    """The single-vector kernel computes each hop with the generic kernel's
+    arithmetic from coordinate-derived neighbours: M, M^H and gamma5 M equal
+    the generic kernel's bit for bit on a lattice with odd extents (every
+    boundary wraps, antiperiodic in t), and against the oracle."""
+    kappa = 0.12
+    U = inputs.gauge_links(dims, 0.5, seed=4)
+    op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    x = ctx.noise(11, 2, 0, 1, prec)
+    xh = z4_noise(11, 2, 0, op.n)
+    tol = 1e-13 if prec == FP64 else 2e-6
+    for dagger, theta in ((False, 0), (True, 0), (False, 1), (True, 1)):
+        out = {}
+        for v in (1, 2):
+            ctx.tune_set(1, prec, v)
+            out[v] = ctx.apply_M(x, 1, prec, dagger=dagger, theta=theta)
+        ctx.tune_set(1, prec, -1)
+        assert torch.equal(out[1], out[2]), (dagger, theta)
+        want = op.dagger(xh) if dagger else op(xh)
+        if theta:
+            want = OLT.spin_op(want[None, :], OLT.theta_matrix("g5"))[0]
+        assert rel(host(ctx.unpack(out[2], 1, prec))[0], want) < tol
 
 
 def test_pi_equals_one_minus_M_p_on_gpu(f44):
