@@ -77,6 +77,7 @@ __device__ __forceinline__ double2 wave_sum2(double2 v) {
 // partial[q * NB + blk]: q < nv: V_q^H u; nv <= q < 2 nv: V_{q-nv}^H z (z may be
 // null: zero); q = 2 nv: u^H u; q = 2 nv + 1: u^H z.  Row g = blockIdx.y of the
 // grid takes basis vectors [g JB, g JB + JB); row 0 also the two u products.
+// Used above kDcgsRunMaxV basis vectors; the run form below otherwise.
 template <int P>
 __global__ __launch_bounds__(256) void k_dcgs_dots(const void *__restrict__ V, size_t vstep, int nv,
                                                    const void *__restrict__ u, const void *__restrict__ z, long n,
@@ -145,6 +146,97 @@ __global__ __launch_bounds__(256) void k_dcgs_dots(const void *__restrict__ V, s
             out = 2L * nv + (q - 2 * kDcgsJB);
         }
         if (out >= 0) partial[out * NB + blockIdx.x] = acc;
+    }
+}
+
+// The same products with the element range split instead of the basis: a
+// workgroup owns S 16-byte slots per thread (slot k of thread i at k*256 + i
+// of the workgroup's run, so every load instruction is contiguous over the
+// wavefront), holds its run of u and z in registers, and streams all nv basis
+// vectors over it.  u and z are read once per step (the row form above reads
+// them once per group of kDcgsJB vectors); per-wavefront sums wait in LDS
+// until one barrier at the end.  A 16-byte slot holds two FP32 or one FP64
+// complex element.
+constexpr int kDcgsRunMaxV = 256;   // basis vectors the LDS of the run form holds
+
+template <int P>
+struct Slot;
+template <>
+struct Slot<MPMC_FP32> {   // two complex elements, kept as stored, widened at use
+    using raw = float4;
+    static constexpr int per = 2;
+    __device__ static cpx<double> el(const float4 &w, int e) {
+        return e == 0 ? mk((double)w.x, (double)w.y) : mk((double)w.z, (double)w.w);
+    }
+};
+template <>
+struct Slot<MPMC_FP64> {
+    using raw = double2;
+    static constexpr int per = 1;
+    __device__ static cpx<double> el(const double2 &w, int) { return mk(w.x, w.y); }
+};
+
+template <int P, int S>
+__global__ __launch_bounds__(256) void k_dcgs_dots_run(const void *__restrict__ V, size_t vstep, int nv,
+                                                       const void *__restrict__ u, const void *__restrict__ z,
+                                                       long nslots, double2 *__restrict__ partial, int NB) {
+    using R = typename Slot<P>::raw;
+    constexpr int E = Slot<P>::per;
+    __shared__ double2 red[2 * kDcgsRunMaxV + 2][4];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const long base = (long)blockIdx.x * 256 * S + threadIdx.x;
+    R ur[S], zr[S];
+    cpx<double> aa = mk(0.0, 0.0), ba = mk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        const long sl = base + (long)k * 256;
+        const bool in = sl < nslots;
+        ur[k] = in ? reinterpret_cast<const R *>(u)[sl] : R{};
+        zr[k] = in && z ? reinterpret_cast<const R *>(z)[sl] : R{};
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const cpx<double> ue = Slot<P>::el(ur[k], e), ze = Slot<P>::el(zr[k], e);
+            aa = aa + conjmul(ue, ue);
+            ba = ba + conjmul(ue, ze);
+        }
+    }
+    for (int q = 0; q < nv; ++q) {
+        const R *vq = reinterpret_cast<const R *>((const char *)V + (size_t)q * vstep);
+        R vr[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) {   // loads issued together
+            const long sl = base + (long)k * 256;
+            vr[k] = sl < nslots ? vq[sl] : R{};
+        }
+        cpx<double> sa = mk(0.0, 0.0), ta = mk(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < S; ++k)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const cpx<double> ve = Slot<P>::el(vr[k], e);
+                sa = sa + conjmul(ve, Slot<P>::el(ur[k], e));
+                ta = ta + conjmul(ve, Slot<P>::el(zr[k], e));
+            }
+        const double2 a = wave_sum2(make_double2(sa.re, sa.im));
+        const double2 b = wave_sum2(make_double2(ta.re, ta.im));
+        if (ln == 0) {
+            red[q][wv] = a;
+            red[nv + q][wv] = b;
+        }
+    }
+    const double2 a2 = wave_sum2(make_double2(aa.re, aa.im)), b2 = wave_sum2(make_double2(ba.re, ba.im));
+    if (ln == 0) {
+        red[2 * nv][wv] = a2;
+        red[2 * nv + 1][wv] = b2;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * nv + 2; q += 256) {
+        double2 acc = red[q][0];
+        for (int w = 1; w < 4; ++w) {
+            acc.x += red[q][w].x;
+            acc.y += red[q][w].y;
+        }
+        partial[(long)q * NB + blockIdx.x] = acc;
     }
 }
 
@@ -321,6 +413,27 @@ __global__ __launch_bounds__(256) void k_dcgs_update(const void *__restrict__ V,
 static int dcgs_launch_dots(mpmc_ctx *ctx, int prec, const void *V, size_t vstep, int nv, const void *u,
                             const void *z, double2 *D) {
     const long n = ctx->n;
+    if (nv <= kDcgsRunMaxV) {
+        // run form: 8 (FP64) or 4 (FP32) slots per thread where that still gives
+        // two workgroups per compute unit (126 and 112 VGPRs), else 2
+        const long nslots = prec == MPMC_FP64 ? n : n / 2;   // n = 12 V is even
+        const int Sbig = prec == MPMC_FP64 ? 8 : 4;
+        const int S = (nslots + 256L * Sbig - 1) / (256L * Sbig) >= 2L * ctx->num_cu ? Sbig : 2;
+        const int NB = (int)((nslots + 256L * S - 1) / (256L * S));
+        double2 *part = (double2 *)ws_get(ctx, WS_PARTIAL, (size_t)(2 * nv + 2) * NB * sizeof(double2));
+        if (!part) return MPMC_ENOMEM;
+        if (prec == MPMC_FP64) {
+            if (S == 8) k_dcgs_dots_run<MPMC_FP64, 8><<<NB, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, nslots, part, NB);
+            else k_dcgs_dots_run<MPMC_FP64, 2><<<NB, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, nslots, part, NB);
+        } else {
+            if (S == 4) k_dcgs_dots_run<MPMC_FP32, 4><<<NB, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, nslots, part, NB);
+            else k_dcgs_dots_run<MPMC_FP32, 2><<<NB, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, nslots, part, NB);
+        }
+        HIP_OR_RET(ctx, hipGetLastError());
+        k_dcgs_reduce<<<2 * nv + 2, 256, 0, ctx->stream>>>(part, NB, D);
+        HIP_OR_RET(ctx, hipGetLastError());
+        return MPMC_OK;
+    }
     const int groups = nv > 0 ? (nv + kDcgsJB - 1) / kDcgsJB : 1;
     long nb = (long)ctx->num_cu * 8 / groups;
     const long maxnb = (n + 255) / 256;

@@ -68,6 +68,28 @@ def test_24_gmres_roots(f24):
     assert abs(P.relres - rr) < 1e-9 * rr
 
 
+@pytest.mark.parametrize("prec,tol", [(FP64, 1e-9), (FP32, 1e-4)])
+def test_24_delayed_gram_schmidt_matches_plain(f24, prec, tol):
+    """At 24^4 the delayed Gram-Schmidt's dot pass runs with 8 (FP64) or 4
+    (FP32) 16-byte slots per thread: GMRES(33) roots and relres equal plain
+    CGS2's to rounding of the storage precision."""
+    dims, kappa, U, op, ctx = f24
+    ctx.set_setup_precision(prec)
+    out = []
+    try:
+        for cgs2 in (1, 0):
+            ctx.set_arnoldi_cgs2(cgs2)
+            out.append(ctx.gmres_poly(4, 0x104, 33))
+    finally:
+        ctx.set_arnoldi_cgs2(-1)
+        ctx.set_setup_precision(FP64)
+    P1, P0 = out
+    assert P0.d_eff == P1.d_eff == 33
+    d = np.abs(np.subtract.outer(P0.roots, P1.roots)).min(axis=1).max()
+    assert d < tol * np.abs(P1.roots).max()
+    assert abs(P0.relres - P1.relres) < tol * P1.relres
+
+
 @pytest.mark.parametrize("theta", [mpmc.THETA_I, mpmc.THETA_G5])
 def test_24_fused_level_step_sampled(f24, theta):
     """Tr(Theta p(M)) samples of 64 noise vectors in one FP32 fused batch; two
