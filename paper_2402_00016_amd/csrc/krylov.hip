@@ -368,45 +368,76 @@ __global__ __launch_bounds__(256) void k_dcgs_coef(const double2 *__restrict__ D
 }
 
 // vout = C0 u + sum_i C[3+i] V_i ; un = C1 u + C2 z + sum_i C[3+nv+i] V_i (un may
-// alias u, vout may alias u; z and un may be null).
+// alias u, vout may alias u; z and un may be null), over 16-byte slots (two
+// FP32 or one FP64 complex element per load), eight basis vectors' loads in
+// flight per iteration.
 template <int P>
-__global__ __launch_bounds__(256) void k_dcgs_update(const void *__restrict__ V, size_t vstep, int nv, const void *u,
-                                                     const void *__restrict__ z, void *un, void *vout,
-                                                     const double2 *__restrict__ C, long n) {
+__device__ __forceinline__ void slot_cpx(const typename Slot<P>::raw &w, cpx<typename Store<P>::real> x[Slot<P>::per]) {
+    if constexpr (P == MPMC_FP32) {
+        x[0] = mk(w.x, w.y);
+        x[1] = mk(w.z, w.w);
+    } else {
+        x[0] = mk(w.x, w.y);
+    }
+}
+template <int P>
+__device__ __forceinline__ typename Slot<P>::raw cpx_slot(const cpx<typename Store<P>::real> x[Slot<P>::per]) {
+    if constexpr (P == MPMC_FP32) return make_float4(x[0].re, x[0].im, x[1].re, x[1].im);
+    else return make_double2(x[0].re, x[0].im);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_dcgs_update_run(const void *__restrict__ V, size_t vstep, int nv,
+                                                         const void *u, const void *__restrict__ z, void *un,
+                                                         void *vout, const double2 *__restrict__ C, long nslots) {
     using T = typename Store<P>::real;
+    using R = typename Slot<P>::raw;
+    constexpr int E = Slot<P>::per;
+    constexpr int G = 8;
     const cpx<T> cu = mk((T)C[0].x, (T)C[0].y), bu = mk((T)C[1].x, (T)C[1].y), bz = mk((T)C[2].x, (T)C[2].y);
-    for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
-        const auto u0 = Store<P>::ld(u, nullptr, e, 0);
-        const cpx<T> uv = mk((T)u0.re, (T)u0.im);
-        cpx<T> v = cu * uv, w = bu * uv;
+    for (long sl = (long)blockIdx.x * 256 + threadIdx.x; sl < nslots; sl += (long)gridDim.x * 256) {
+        cpx<T> uv[E], v[E], w[E];
+        slot_cpx<P>(reinterpret_cast<const R *>(u)[sl], uv);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            v[e] = cu * uv[e];
+            w[e] = bu * uv[e];
+        }
         if (z) {
-            const auto z0 = Store<P>::ld(z, nullptr, e, 0);
-            w = w + bz * mk((T)z0.re, (T)z0.im);
+            cpx<T> zv[E];
+            slot_cpx<P>(reinterpret_cast<const R *>(z)[sl], zv);
+#pragma unroll
+            for (int e = 0; e < E; ++e) w[e] = w[e] + bz * zv[e];
         }
         int i = 0;
-        for (; i + 4 <= nv; i += 4) {   // four basis vectors per iteration, loads issued together
-            cpx<T> vq[4];
+        for (; i + G <= nv; i += G) {
+            R vr[G];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const auto x = Store<P>::ld((const char *)V + (size_t)(i + q) * vstep, nullptr, e, 0);
-                vq[q] = mk((T)x.re, (T)x.im);
-            }
+            for (int q = 0; q < G; ++q) vr[q] = reinterpret_cast<const R *>((const char *)V + (size_t)(i + q) * vstep)[sl];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < G; ++q) {
+                cpx<T> x[E];
+                slot_cpx<P>(vr[q], x);
                 const double2 a = C[3 + i + q], bb = C[3 + nv + i + q];
-                v = v + mk((T)a.x, (T)a.y) * vq[q];
-                w = w + mk((T)bb.x, (T)bb.y) * vq[q];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    v[e] = v[e] + mk((T)a.x, (T)a.y) * x[e];
+                    w[e] = w[e] + mk((T)bb.x, (T)bb.y) * x[e];
+                }
             }
         }
         for (; i < nv; ++i) {
-            const auto x = Store<P>::ld((const char *)V + (size_t)i * vstep, nullptr, e, 0);
-            const cpx<T> vx = mk((T)x.re, (T)x.im);
+            cpx<T> x[E];
+            slot_cpx<P>(reinterpret_cast<const R *>((const char *)V + (size_t)i * vstep)[sl], x);
             const double2 a = C[3 + i], bb = C[3 + nv + i];
-            v = v + mk((T)a.x, (T)a.y) * vx;
-            w = w + mk((T)bb.x, (T)bb.y) * vx;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                v[e] = v[e] + mk((T)a.x, (T)a.y) * x[e];
+                w[e] = w[e] + mk((T)bb.x, (T)bb.y) * x[e];
+            }
         }
-        if (un) Store<P>::st(un, e, w);
-        Store<P>::st(vout, e, v);
+        if (un) reinterpret_cast<R *>(un)[sl] = cpx_slot<P>(w);
+        reinterpret_cast<R *>(vout)[sl] = cpx_slot<P>(v);
     }
 }
 
@@ -456,12 +487,13 @@ static int dcgs_launch_dots(mpmc_ctx *ctx, int prec, const void *V, size_t vstep
 static int dcgs_launch_update(mpmc_ctx *ctx, int prec, const void *V, size_t vstep, int nv, const void *u,
                               const void *z, void *un, void *vout, const double2 *C) {
     const long n = ctx->n;
-    long nb = (n + 255) / 256;
+    const long nslots = prec == MPMC_FP64 ? n : n / 2;   // 16-byte slots; n = 12 V is even
+    long nb = (nslots + 255) / 256;
     if (nb > (long)ctx->num_cu * 8) nb = (long)ctx->num_cu * 8;
     if (prec == MPMC_FP64)
-        k_dcgs_update<MPMC_FP64><<<(unsigned)nb, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, un, vout, C, n);
+        k_dcgs_update_run<MPMC_FP64><<<(unsigned)nb, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, un, vout, C, nslots);
     else
-        k_dcgs_update<MPMC_FP32><<<(unsigned)nb, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, un, vout, C, n);
+        k_dcgs_update_run<MPMC_FP32><<<(unsigned)nb, 256, 0, ctx->stream>>>(V, vstep, nv, u, z, un, vout, C, nslots);
     HIP_OR_RET(ctx, hipGetLastError());
     return MPMC_OK;
 }
