@@ -333,6 +333,30 @@ __global__ void k_convert(VecRef x, VecRef y, long V, int N) {
     }
 }
 
+// y (FP16S) = coef[r] * x (FP32): k_scale_rhs followed by k_convert in one
+// pass, with the same arithmetic (the product in FP32, then the per-(site,
+// rhs) scale and the half-precision values).
+__global__ void k_convert_scaled_h(VecRef x, VecRef y, long V, int N, const double2 *__restrict__ coef) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= V * N) return;
+    const long s = t / N;
+    const int r = (int)(t - s * N);
+    const double2 c = coef[r];
+    cpx<float> v[12];
+    float mx = 0.f;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const auto a = Store<MPMC_FP32>::ld(x.d, nullptr, (s * 12 + k) * N + r, 0);
+        v[k] = mk((float)c.x, (float)c.y) * mk(a.re, a.im);
+        mx = fmaxf(mx, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+    }
+    const float inv = mx > 0.f ? 1.0f / mx : 0.f;
+    __half2 *d = reinterpret_cast<__half2 *>(y.d);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) d[(s * 12 + k) * N + r] = __floats2half2_rn(v[k].re * inv, v[k].im * inv);
+    y.sc[s * N + r] = mx;
+}
+
 template <typename F>
 int dispatch_prec(mpmc_ctx *ctx, int prec, F &&f) {
     switch (prec) {
@@ -687,6 +711,13 @@ int blas_scale_rhs(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, co
         k_scale_rhs<decltype(P)::value><<<grid_for(total, 256), 256, 0, ctx->stream>>>(
             vref(ctx, x, nrhs, prec), vref(ctx, y, nrhs, prec), total, nrhs, (const double2 *)coef_dev, mode);
     });
+}
+
+int blas_convert_scaled_h(mpmc_ctx *ctx, const void *x, void *y, int nrhs, const double *coef_dev) {
+    k_convert_scaled_h<<<grid_for(ctx->V * nrhs, 256), 256, 0, ctx->stream>>>(
+        vref(ctx, x, nrhs, MPMC_FP32), vref(ctx, y, nrhs, MPMC_FP16S), ctx->V, nrhs, (const double2 *)coef_dev);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
 }
 
 int blas_convert(mpmc_ctx *ctx, const void *x, int px, void *y, int py, int nrhs) {

@@ -338,6 +338,8 @@ int blas_multi_axpy_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, v
 int blas_axpby(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, double2 a, double2 b);
 int blas_scale_rhs(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, const double *coef_dev, int mode);
 int blas_convert(mpmc_ctx *ctx, const void *x, int px, void *y, int py, int nrhs);
+// y (FP16S) = coef[r] x (FP32), coef per rhs (complex FP64, device)
+int blas_convert_scaled_h(mpmc_ctx *ctx, const void *x, void *y, int nrhs, const double *coef_dev);
 int blas_zero(mpmc_ctx *ctx, void *y, int nrhs, int prec);
 int blas_scale_acc(mpmc_ctx *ctx, const double *t, int N, double2 c, double sign, double *acc);
 

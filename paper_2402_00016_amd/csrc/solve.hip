@@ -305,9 +305,8 @@ int Gmres::orthogonalize(int j, bool *more) {
     k_finalize_batch<<<grid_for(N, 64), 64, 0, ctx->stream>>>((double2 *)Hcol, once ? nullptr : (const double2 *)h2_,
                                                               j, N, (const double2 *)nrm_, (double2 *)scale_);
     HIP_OR_RET(ctx, hipGetLastError());
-    if (half_) {
-        RET_IF(blas_scale_rhs(ctx, w_, w_, N, MPMC_FP32, scale_, 0));
-        RET_IF(blas_convert(ctx, w_, MPMC_FP32, basis(j + 1), MPMC_FP16S, N));
+    if (half_) {   // v_{j+1} = w / h_{j+1,j} straight into the FP16S basis (w is not needed after)
+        RET_IF(blas_convert_scaled_h(ctx, w_, basis(j + 1), N, scale_));
     } else {
         RET_IF(blas_scale_rhs(ctx, w_, basis(j + 1), N, inner_prec_, scale_, 0));
     }
