@@ -339,7 +339,20 @@ def main():
         return float(np.median(ts)), ts, last
 
     out["solve_term"] = {"mixed_batched": solve_term(est)}
-    if not a.probe_last and not a.no_probe_report:
+    probe_cost = None
+    if not a.probe_last and not a.no_probe_report and est.polys:
+        # probes x degree of the exact last term against the sampled estimate's MVPs: a
+        # last polynomial whose distance colouring leaves (nearly) every site its own
+        # colour (the 16^4 workload's degree-255 double polynomial) is not reported
+        deg = est.polys[-1].info["degree"]
+        nc = mpmc.mpmc_probe_colouring(dims, deg)[3]
+        probe_cost = 12 * nc * deg
+        if probe_cost > 20 * est.mvps:
+            out["trace"]["probed_last"] = {"skipped": "the last polynomial (degree %d) needs %d probe vectors "
+                                                      "(%d MVPs, %.0fx the sampled estimate's)"
+                                                      % (deg, 12 * nc, probe_cost, probe_cost / max(est.mvps, 1))}
+            progress("probed-last estimate skipped (%d probes)" % (12 * nc))
+    if not a.probe_last and not a.no_probe_report and "probed_last" not in out["trace"]:
         # the same estimate with the last term exact by probing (Sec. 6)
         sync()
         tq = time.perf_counter()

@@ -11,7 +11,9 @@
 // a_mu < L_mu, so the sum is the exact trace when every such a_mu satisfies
 // D < a_mu <= L_mu / 2 (a_mu = L_mu gives every site its own colour).
 #include <algorithm>
+#include <cmath>
 #include <complex>
+#include <new>
 #include <vector>
 
 #include "common.h"
@@ -68,9 +70,29 @@ struct LinCol {
     int W[4][4];
 };
 
-// displacements 0 < |d|_1 <= D that are not periods of the lattice
+// Displacements 0 < |d|_1 <= D that are not periods of the lattice.  A colour
+// W x mod m with m dividing every L_mu depends on d only modulo L, so when the
+// ball is larger than the lattice the residues r with torus distance
+// sum_mu min(r_mu, L_mu - r_mu) <= D stand for it (the same conditions, at
+// most V - 1 of them; the ball of radius 256 alone would hold ~10^9).
 static void ball_displacements(const int L[4], int D, std::vector<int> &out) {
     out.clear();
+    const double ball = std::pow(2.0 * D + 1.0, 4.0);
+    const long V = (long)L[0] * L[1] * L[2] * L[3];
+    if (ball > 4.0 * (double)V) {
+        for (long q = 0; q < V; ++q) {
+            int r[4];
+            long t = q;
+            int dist = 0;
+            for (int mu = 0; mu < 4; ++mu) {
+                r[mu] = (int)(t % L[mu]);
+                t /= L[mu];
+                dist += std::min(r[mu], L[mu] - r[mu]);
+            }
+            if (q != 0 && dist <= D) out.insert(out.end(), r, r + 4);
+        }
+        return;
+    }
     for (int a = -D; a <= D; ++a)
         for (int b = -(D - std::abs(a)); b <= D - std::abs(a); ++b)
             for (int c = -(D - std::abs(a) - std::abs(b)); c <= D - std::abs(a) - std::abs(b); ++c) {
@@ -111,8 +133,16 @@ static LinCol identity_colouring(const int L[4]) {
     return c;
 }
 
+// Largest residue set the search enumerates (16 bytes each); beyond it, and
+// whenever D reaches across the whole torus, every site is its own colour.
+constexpr long kColourSearchMaxV = 1L << 24;
+
 static LinCol find_colouring(const int L[4], int D) {
     const long V = (long)L[0] * L[1] * L[2] * L[3];
+    int diameter = 0;
+    for (int mu = 0; mu < 4; ++mu) diameter += L[mu] / 2;
+    if (D >= diameter && V > 1) return identity_colouring(L);   // every pair of sites conflicts
+    if (std::pow(2.0 * D + 1.0, 4.0) > 4.0 * (double)V && V > kColourSearchMaxV) return identity_colouring(L);
     std::vector<int> disp;
     ball_displacements(L, D, disp);
     if (disp.empty()) {   // D = 0: one colour
@@ -211,7 +241,12 @@ MPMC_API int mpmc_probe_colouring(const int dims[4], int distance, int *k_host, 
     if (!dims || distance < 0 || !k_host || !moduli_host || !W_host || !ncolours_host) return MPMC_EINVAL;
     for (int mu = 0; mu < 4; ++mu)
         if (dims[mu] < 1 || dims[mu] > 1024) return MPMC_EINVAL;
-    const LinCol c = find_colouring(dims, distance);
+    LinCol c;
+    try {
+        c = find_colouring(dims, distance);
+    } catch (const std::bad_alloc &) {
+        return MPMC_ENOMEM;
+    }
     *k_host = c.k;
     long nc = 1;
     for (int i = 0; i < 4; ++i) {
@@ -234,7 +269,12 @@ MPMC_API int mpmc_poly_trace_probe(mpmc_ctx *ctx, const mpmc_poly *p, int theta,
     mpmc_poly_info(p, nullptr, nullptr, &degree, nullptr);
     auto it = ctx->colourings.find(degree);
     if (it == ctx->colourings.end()) {
-        const LinCol c = find_colouring(ctx->dims, degree);
+        LinCol c;
+        try {
+            c = find_colouring(ctx->dims, degree);
+        } catch (const std::bad_alloc &) {
+            return set_err(ctx, MPMC_ENOMEM, "mpmc_poly_trace_probe: colouring search out of host memory");
+        }
         std::vector<int> enc(1 + 4 + 16, 0);
         enc[0] = c.k;
         for (int i = 0; i < c.k; ++i) {

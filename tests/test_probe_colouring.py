@@ -66,3 +66,14 @@ def test_large_lattice_colouring_is_compact():
             assert np.any((W @ np.array(d)) % np.array(m) != 0), d
     with pytest.raises(mpmc.MpmcError):
         mpmc.mpmc_probe_colouring(dims, -1)
+
+
+@pytest.mark.parametrize("dims,D", [((16, 16, 16, 16), 255), ((16, 16, 16, 16), 32), ((24, 24, 24, 24), 129)])
+def test_distance_beyond_the_torus_is_every_site(dims, D):
+    """A distance at or beyond the torus diameter (sum of L_mu / 2; 255 is the
+    degree of the 16x16 double polynomial) puts every pair of sites within
+    reach, so every site is its own colour; found without enumerating the
+    ball of radius D (about 10^9 displacements at D = 255)."""
+    k, m, W, nc = mpmc.mpmc_probe_colouring(dims, D)
+    assert nc == int(np.prod(dims)) and k == 4
+    assert sorted(m) == sorted(dims)
