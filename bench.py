@@ -376,8 +376,7 @@ def main():
         # separately) and then preconditions the main solves of the estimate
         # (FP32 inner cycles: with an FP16 basis each inner cycle ends at 1e-3 of
         # its start, and the network's restarts then cost more than they save:
-        # 24^4 learned solve term 0.87 s with FP32, 1.16 s with FP16S, both with two
-        # Gram-Schmidt projections per step)
+        # 24^4 learned solve term 0.81 s with FP32, 1.01 s with FP16S)
         lplan = driver.Plan(**{**plan.__dict__, "learned": True, "solve_inner_prec": mpmc.FP32,
                                "net_source": a.net_source, "net_steps": a.net_steps,
                                "net_batches": 2 if a.net_source == "solve" else 8})
