@@ -161,16 +161,23 @@ __device__ __forceinline__ void transport(const PathSrc &ps, const float2 (&a)[2
 }
 
 // One layer (or its adjoint): out = sum_p W_p T_p in.  Wave = (site, 16 rhs).
+// Sites are taken in the blocked order of the site table (4^4 blocks where the
+// extents allow): the neighbours of a block's sites are mostly in the block,
+// whose inputs stay in the L2 of the XCD that runs it, where the lexicographic
+// order put the z and t neighbours (576 and 13824 sites away at 24^4) out of
+// any L2's reach.  Each wave writes only its own site, so the order does not
+// change the result.
 template <int FIN, int FOUT>
 __global__ __launch_bounds__(256) void k_net_layer(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                    const float2 *__restrict__ links, const int *__restrict__ nbr,
                                                    const bf16x4 *__restrict__ table, int N, int nrb,
-                                                   unsigned nunits) {
+                                                   unsigned nunits, const int *__restrict__ order) {
     const int lane = threadIdx.x & 63;
     const unsigned unit = uni(xcd_tile(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6));
     if (unit >= nunits) return;
-    const long site = unit / nrb;
-    const int rb = (int)(unit - site * nrb);
+    const unsigned q = unit / (unsigned)nrb;
+    const long site = uni(order[q]);
+    const int rb = (int)(unit - q * (unsigned)nrb);
     const int n = lane & 15, g = lane >> 4;
     const int rhs = rb * 16 + n;
     const int f = g >> 1, s0 = 2 * (g & 1);
@@ -221,7 +228,8 @@ __global__ __launch_bounds__(256) void k_net_layer(const float2 *__restrict__ in
 template <int FIN, int FOUT>
 __global__ __launch_bounds__(256) void k_net_wgrad(const float2 *__restrict__ a_in, const float2 *__restrict__ gout,
                                                    const float2 *__restrict__ links, const int *__restrict__ nbr,
-                                                   float *__restrict__ partial, int N, int nrb, unsigned nunits) {
+                                                   float *__restrict__ partial, int N, int nrb, unsigned nunits,
+                                                   const int *__restrict__ order) {
     // transposition buffer [wave][colour][b][rhs] (bf16), reused for the block sum
     __shared__ float red[4][NPATH * 256];
     short(*lds)[3][16][16] = reinterpret_cast<short(*)[3][16][16]>(&red[0][0]);
@@ -241,8 +249,9 @@ __global__ __launch_bounds__(256) void k_net_wgrad(const float2 *__restrict__ a_
 
     for (unsigned unit = wave; unit < nunits; unit += nwaves) {
         const unsigned u = uni(unit);
-        const long site = u / nrb;
-        const int rb = (int)(u - site * nrb);
+        const unsigned q = u / (unsigned)nrb;
+        const long site = uni(order[q]);   // blocked site order, as in k_net_layer
+        const int rb = (int)(u - q * (unsigned)nrb);
         // A operands: g_i at rhs rb*16 + 4g + j, one per colour
         bf16x4 Ag[3];
         {
@@ -430,7 +439,8 @@ int launch_layer(mpmc_ctx *ctx, const mpmc_net *net, int op, const void *in, voi
     float2 *y = (float2 *)out;
 #define LAYER(A, B)                                                                                       \
     if (fin == A && fout == B)                                                                            \
-        k_net_layer<A, B><<<blocks, 256, 0, ctx->stream>>>(x, y, L, ctx->nbr, tab, N, nrb, (unsigned)units); \
+        k_net_layer<A, B><<<blocks, 256, 0, ctx->stream>>>(x, y, L, ctx->nbr, tab, N, nrb, (unsigned)units, \
+                                                           ctx->site_order);                                 \
     else
     LAYER(1, 2)
     LAYER(2, 2)
@@ -452,7 +462,8 @@ int launch_wgrad(mpmc_ctx *ctx, mpmc_net *net, int layer, const void *a_in, cons
     const float2 *gg = (const float2 *)gout;
 #define WG(A, B)                                                                                              \
     if (fin == A && fout == B)                                                                                \
-        k_net_wgrad<A, B><<<blocks, 256, 0, ctx->stream>>>(a, gg, L, ctx->nbr, partial, N, nrb, (unsigned)units); \
+        k_net_wgrad<A, B><<<blocks, 256, 0, ctx->stream>>>(a, gg, L, ctx->nbr, partial, N, nrb, (unsigned)units, \
+                                                           ctx->site_order);                                      \
     else
     WG(1, 2)
     WG(2, 2)
