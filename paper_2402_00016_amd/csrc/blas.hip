@@ -145,10 +145,15 @@ __global__ __launch_bounds__(256) void k_reduce(const double2 *__restrict__ part
 }
 
 // w += sign * sum_j h[j*N + r] V_j ; optional partial[blk][r] = sum |w|^2
-template <int PB, int PW>
+// OUTH (FP16S basis, FP32 w): the result is not written back to w but to the
+// FP16S vector hout (half values and per-(site, rhs) scales), for a caller
+// that needs it only in that form; partial still receives the norms of the
+// FP32 result.
+template <int PB, int PW, bool OUTH = false>
 __global__ __launch_bounds__(256) void k_multiaxpy(VecRef Vb, size_t vstride_b, size_t vscale_off, int vN, int nv,
                                                    VecRef w, int N, long V, const double2 *__restrict__ h, double sign,
-                                                   double2 *__restrict__ partial, int NB, int ldh) {
+                                                   double2 *__restrict__ partial, int NB, int ldh,
+                                                   VecRef hout = VecRef{nullptr, nullptr}) {
     using T = typename Store<PW>::real;
     __shared__ double red[256];
     const int RT = blockDim.x, CT = blockDim.y;
@@ -179,10 +184,25 @@ __global__ __launch_bounds__(256) void k_multiaxpy(VecRef Vb, size_t vstride_b, 
 #pragma unroll
                 for (int k = 0; k < 12; ++k) acc[k] = acc[k] + c * vv[k];
             }
+            if constexpr (OUTH) {
+                float mx = 0.f;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) {
-                Store<PW>::st(w.d, (s * 12 + k) * N + r, acc[k]);
-                nrm += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
+                for (int k = 0; k < 12; ++k) {
+                    mx = fmaxf(mx, fmaxf(fabsf(acc[k].re), fabsf(acc[k].im)));
+                    nrm += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
+                }
+                const float inv = mx > 0.f ? 1.0f / mx : 0.f;
+                __half2 *d = reinterpret_cast<__half2 *>(hout.d);
+#pragma unroll
+                for (int k = 0; k < 12; ++k)
+                    d[(s * 12 + k) * N + r] = __floats2half2_rn(acc[k].re * inv, acc[k].im * inv);
+                hout.sc[s * N + r] = mx;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) {
+                    Store<PW>::st(w.d, (s * 12 + k) * N + r, acc[k]);
+                    nrm += (double)acc[k].re * acc[k].re + (double)acc[k].im * acc[k].im;
+                }
             }
         }
     }
@@ -652,7 +672,7 @@ int blas_multi_axpy(mpmc_ctx *ctx, const void *Vb, long vstride, int vN, int nv,
 
 // w (FP32) += sign * sum_j h[j*ldh + r] V_j with an FP16S basis
 int blas_multi_axpy_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, void *w, int nrhs,
-                      const double *h_dev, int ldh, double sign, double *norm2_dev) {
+                      const double *h_dev, int ldh, double sign, double *norm2_dev, void *out_h) {
     Tiling t = tiling(ctx, nrhs, 1);
     double2 *part = nullptr;
     if (norm2_dev) {
@@ -660,9 +680,15 @@ int blas_multi_axpy_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, v
         if (!part) return MPMC_ENOMEM;
     }
     dim3 blk(t.RT, t.CT), grd(t.NB, t.ntile, 1);
-    k_multiaxpy<MPMC_FP16S, MPMC_FP32><<<grd, blk, 0, ctx->stream>>>(
-        VecRef{const_cast<void *>(Vb), nullptr}, vstride_b, fp16s_scale_offset(ctx, nrhs), nrhs, nv,
-        vref(ctx, w, nrhs, MPMC_FP32), nrhs, ctx->V, (const double2 *)h_dev, sign, part, t.NB, ldh);
+    if (out_h)
+        k_multiaxpy<MPMC_FP16S, MPMC_FP32, true><<<grd, blk, 0, ctx->stream>>>(
+            VecRef{const_cast<void *>(Vb), nullptr}, vstride_b, fp16s_scale_offset(ctx, nrhs), nrhs, nv,
+            vref(ctx, w, nrhs, MPMC_FP32), nrhs, ctx->V, (const double2 *)h_dev, sign, part, t.NB, ldh,
+            vref(ctx, out_h, nrhs, MPMC_FP16S));
+    else
+        k_multiaxpy<MPMC_FP16S, MPMC_FP32><<<grd, blk, 0, ctx->stream>>>(
+            VecRef{const_cast<void *>(Vb), nullptr}, vstride_b, fp16s_scale_offset(ctx, nrhs), nrhs, nv,
+            vref(ctx, w, nrhs, MPMC_FP32), nrhs, ctx->V, (const double2 *)h_dev, sign, part, t.NB, ldh);
     HIP_OR_RET(ctx, hipGetLastError());
     if (norm2_dev) {
         k_reduce<<<nrhs, 256, 0, ctx->stream>>>(part, t.NB, nrhs, (double2 *)norm2_dev, 0, 1);
@@ -711,6 +737,21 @@ int blas_scale_rhs(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, co
         k_scale_rhs<decltype(P)::value><<<grid_for(total, 256), 256, 0, ctx->stream>>>(
             vref(ctx, x, nrhs, prec), vref(ctx, y, nrhs, prec), total, nrhs, (const double2 *)coef_dev, mode);
     });
+}
+
+// y's per-(site, rhs) scales *= Re coef[r] (FP16S y; its half values stay)
+__global__ void k_scale_h(float *__restrict__ sc, long total, int N, const double2 *__restrict__ coef) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    sc[t] = sc[t] * (float)coef[t % N].x;
+}
+
+int blas_scale_h(mpmc_ctx *ctx, void *y, int nrhs, const double *coef_dev) {
+    const long total = ctx->V * nrhs;
+    k_scale_h<<<grid_for(total, 256), 256, 0, ctx->stream>>>(vref(ctx, y, nrhs, MPMC_FP16S).sc, total, nrhs,
+                                                            (const double2 *)coef_dev);
+    HIP_OR_RET(ctx, hipGetLastError());
+    return MPMC_OK;
 }
 
 int blas_convert_scaled_h(mpmc_ctx *ctx, const void *x, void *y, int nrhs, const double *coef_dev) {

@@ -333,8 +333,11 @@ int blas_arnoldi_update(mpmc_ctx *ctx, const void *V, long vstride, int nv, void
 // against FP32 working vectors
 int blas_multi_dot_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, const void *w, int nrhs,
                      double *h_dev, int accumulate);
+// out_h (FP16S, may be null): write the result there instead of back to w
 int blas_multi_axpy_h(mpmc_ctx *ctx, const void *Vb, size_t vstride_b, int nv, void *w, int nrhs,
-                      const double *h_dev, int ldh, double sign, double *norm2_dev);
+                      const double *h_dev, int ldh, double sign, double *norm2_dev, void *out_h = nullptr);
+// the per-(site, rhs) scales of FP16S y *= Re coef[r] (coef per rhs, complex FP64, device)
+int blas_scale_h(mpmc_ctx *ctx, void *y, int nrhs, const double *coef_dev);
 int blas_axpby(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, double2 a, double2 b);
 int blas_scale_rhs(mpmc_ctx *ctx, const void *x, void *y, int nrhs, int prec, const double *coef_dev, int mode);
 int blas_convert(mpmc_ctx *ctx, const void *x, int px, void *y, int py, int nrhs);

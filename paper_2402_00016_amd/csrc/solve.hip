@@ -293,9 +293,9 @@ int Gmres::orthogonalize(int j, bool *more) {
     // the loss of orthogonality of one classical projection in FP32
     // arithmetic; FP64 cycles run to the final tolerance and project twice
     const bool once = ctx->solve_gs_passes == 1 || (ctx->solve_gs_passes == 0 && inner_prec_ != MPMC_FP64);
-    if (once && half_) {
+    if (once && half_) {   // w - V h goes straight into the FP16S basis slot j+1 (unnormalised)
         RET_IF(blas_multi_dot_h(ctx, V_, vbb_, j + 1, w_, N, Hcol, 0));
-        RET_IF(blas_multi_axpy_h(ctx, V_, vbb_, j + 1, w_, N, Hcol, N, -1.0, nrm_));
+        RET_IF(blas_multi_axpy_h(ctx, V_, vbb_, j + 1, w_, N, Hcol, N, -1.0, nrm_, basis(j + 1)));
     } else if (once) {
         RET_IF(blas_multi_dot(ctx, V_, vstride_, N, j + 1, w_, N, pw_, Hcol, 0, 0));
         RET_IF(blas_multi_axpy(ctx, V_, vstride_, N, j + 1, w_, N, pw_, Hcol, N, -1.0, nrm_));
@@ -312,7 +312,9 @@ int Gmres::orthogonalize(int j, bool *more) {
     k_finalize_batch<<<grid_for(N, 64), 64, 0, ctx->stream>>>((double2 *)Hcol, once ? nullptr : (const double2 *)h2_,
                                                               j, N, (const double2 *)nrm_, (double2 *)scale_);
     HIP_OR_RET(ctx, hipGetLastError());
-    if (half_) {   // v_{j+1} = w / h_{j+1,j} straight into the FP16S basis (w is not needed after)
+    if (once && half_) {   // v_{j+1} = (w - V h) / h_{j+1,j}: only the per-(site, rhs) scales change
+        RET_IF(blas_scale_h(ctx, basis(j + 1), N, scale_));
+    } else if (half_) {    // v_{j+1} = w / h_{j+1,j} straight into the FP16S basis (w is not needed after)
         RET_IF(blas_convert_scaled_h(ctx, w_, basis(j + 1), N, scale_));
     } else {
         RET_IF(blas_scale_rhs(ctx, w_, basis(j + 1), N, inner_prec_, scale_, 0));
