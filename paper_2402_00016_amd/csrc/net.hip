@@ -51,13 +51,15 @@ __device__ __forceinline__ short to_bf16(float f) {
     return __builtin_bit_cast(short, (__bf16)f);
 }
 
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+
+// two packed conversions (round to nearest even, as to_bf16), no permutes
 __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d) {
-    bf16x4 r;
-    r[0] = to_bf16(a);
-    r[1] = to_bf16(b);
-    r[2] = to_bf16(c);
-    r[3] = to_bf16(d);
-    return r;
+    const bf16x2v lo = __builtin_convertvector((f32x2v){a, b}, bf16x2v);
+    const bf16x2v hi = __builtin_convertvector((f32x2v){c, d}, bf16x2v);
+    const uint64_t u = (uint64_t)__builtin_bit_cast(uint32_t, lo) | ((uint64_t)__builtin_bit_cast(uint32_t, hi) << 32);
+    return __builtin_bit_cast(bf16x4, u);
 }
 
 // A-operand tables.  Op 2l is the forward map of layer l, op 2l+1 its adjoint.
@@ -138,23 +140,34 @@ __device__ __forceinline__ void transport(const PathSrc &ps, const float2 (&a)[2
             for (int c = 0; c < 3; ++c) t[s][c] = a[s][c];
         return;
     }
-    float2 u[9];
+    // w[c][d] = sgn U[c][d], or sgn conj(U[d][c]) for the backward path: the
+    // signs are flipped as bits of wave-uniform values (scalar instructions),
+    // so the lanes run only the 72 FMAs of the two 3x3 complex products
+    const uint32_t sm = ps.sgn < 0.f ? 0x80000000u : 0u;
+    const uint32_t cm = ps.dag ? 0x80000000u : 0u;
+    float wr[9], wi[9], nwi[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        const float2 w = ps.U[e];
-        u[e] = make_float2(ps.sgn * w.x, ps.sgn * w.y);
-    }
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float2 x = ps.U[ps.dag ? d * 3 + c : c * 3 + d];
+            wr[c * 3 + d] = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x.x) ^ sm);
+            wi[c * 3 + d] = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x.y) ^ sm ^ cm);
+            nwi[c * 3 + d] = __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, x.y) ^ sm ^ cm ^ 0x80000000u);
+        }
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            float re = 0.f, im = 0.f;
+            float re = wr[c * 3] * a[s][0].x, im = wr[c * 3] * a[s][0].y;
+            re = fmaf(nwi[c * 3], a[s][0].y, re);
+            im = fmaf(wi[c * 3], a[s][0].x, im);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                // U[c][d] a[d], or conj(U[d][c]) a[d] for the backward path
-                const float2 w = ps.dag ? make_float2(u[d * 3 + c].x, -u[d * 3 + c].y) : u[c * 3 + d];
-                re += w.x * a[s][d].x - w.y * a[s][d].y;
-                im += w.x * a[s][d].y + w.y * a[s][d].x;
+            for (int d = 1; d < 3; ++d) {
+                re = fmaf(wr[c * 3 + d], a[s][d].x, re);
+                re = fmaf(nwi[c * 3 + d], a[s][d].y, re);
+                im = fmaf(wr[c * 3 + d], a[s][d].y, im);
+                im = fmaf(wi[c * 3 + d], a[s][d].x, im);
             }
             t[s][c] = make_float2(re, im);
         }
@@ -534,12 +547,12 @@ MPMC_API int mpmc_net_n_params(void) { return NPARAM; }
 
 MPMC_API void mpmc_net_destroy(mpmc_net *net) {
     if (!net) return;
-    hipFree(net->theta);
-    hipFree(net->adam_m);
-    hipFree(net->adam_v);
-    hipFree(net->grad);
-    hipFree(net->tables);
-    hipFree(net->loss);
+    (void)hipFree(net->theta);
+    (void)hipFree(net->adam_m);
+    (void)hipFree(net->adam_v);
+    (void)hipFree(net->grad);
+    (void)hipFree(net->tables);
+    (void)hipFree(net->loss);
     delete net;
 }
 
