@@ -339,7 +339,6 @@ def main():
         return float(np.median(ts)), ts, last
 
     out["solve_term"] = {"mixed_batched": solve_term(est)}
-    probe_cost = None
     if not a.probe_last and not a.no_probe_report and est.polys:
         # probes x degree of the exact last term against the sampled estimate's MVPs: a
         # last polynomial whose distance colouring leaves (nearly) every site its own

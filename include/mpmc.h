@@ -304,7 +304,10 @@ int mpmc_defl_keep(mpmc_defl *d, int k);
  * (flexible GMRES with the preconditioned vectors z_j = N v_j kept in FP32;
  * requires inner_prec = MPMC_FP32 or MPMC_FP16S, whose FP16 basis vectors are
  * widened to FP32 before N); it changes cost, never
- * the converged x.  Outputs (host):
+ * the converged x.  An inner cycle ends when every right-hand side's
+ * residual estimate meets its target, tested after every inner step when
+ * V * nrhs >= 2^22 and every 10 steps otherwise (a test waits for the
+ * stream).  Gram-Schmidt: see mpmc_set_solve_gs_passes.  Outputs (host):
  * iters_host = total inner iterations, relres_host[nrhs] = final true
  * relative residuals.  Returns MPMC_ENOCONV after max_outer cycles.
  * Synchronises. */
