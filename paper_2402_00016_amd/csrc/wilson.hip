@@ -1361,25 +1361,31 @@ __global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) v
     const unsigned lane = threadIdx.x & 63u;
     const int wx = w & 1, wy = (w >> 1) & 1, wz = TZ == 2 ? w >> 2 : 0;
     // Whole blocks of bx x by x bz tiles go to the XCDs (workgroup b runs on
-    // XCD b % 8, in the order b / 8), each XCD taking a contiguous range of
-    // blocks: a round of the workgroups an XCD runs at once is one compact 3D
-    // block whose columns advance along t together, so most out-of-tile
-    // neighbours were just fetched into the XCD's L2 by the workgroup that
-    // owns them.  The grid is padded to 8 x (most blocks per XCD) x block
-    // size; padding workgroups return at once.
-    const int bsz = ca.bx * ca.by * ca.bz, nbx = ca.ntx / ca.bx, nby = ca.nty / ca.by;
+    // XCD b % 8, in the order b / 8): a round of the workgroups an XCD runs at
+    // once is one compact 3D block whose columns advance along t together, so
+    // most out-of-tile neighbours were just fetched into the XCD's L2 by the
+    // workgroup that owns them.  At each round the eight XCDs take eight
+    // consecutive blocks of a snake that runs along z first (then x, then y),
+    // so blocks that run at the same time share faces: the second read of a
+    // face, from the neighbouring XCD at the same t, finds it in the
+    // memory-side cache instead of HBM.  The grid is padded to a multiple of 8
+    // blocks; padding workgroups return at once.
+    const int bsz = ca.bx * ca.by * ca.bz, nbx = ca.ntx / ca.bx, nbz = ca.ntz / ca.bz;
     const long xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
-    const long per = ca.nblk / 8, rem = ca.nblk % 8;
     const long lb = slot / bsz;
-    if (lb >= per + (xcd < rem ? 1 : 0)) return;
-    const long gb = xcd * per + (xcd < rem ? xcd : rem) + lb;   // block over all chunks
+    const long gb = lb * 8 + xcd;                              // block over all chunks
+    if (gb >= ca.nblk) return;
     const long nbc = ca.ntiles / bsz;                          // blocks per 64-wide chunk
     const long chunk = gb / nbc, blk = gb - chunk * nbc;
     const int in = (int)(slot - lb * bsz);
     const unsigned tile = (unsigned)(chunk * ca.ntiles + blk * bsz + in);
-    const int tx = (int)(blk % nbx) * ca.bx + in % ca.bx;
-    const int ty = (int)((blk / nbx) % nby) * ca.by + (in / ca.bx) % ca.by;
-    const int tz = (int)(blk / ((long)nbx * nby)) * ca.bz + in / (ca.bx * ca.by);
+    const long zrow = blk / nbz;                               // (x, y) block column of the snake
+    const int bzi = (int)(zrow & 1 ? nbz - 1 - (blk - zrow * nbz) : blk - zrow * nbz);
+    const int xrow = (int)(zrow / nbx);
+    const int bxi = (int)(xrow & 1 ? nbx - 1 - (zrow - (long)xrow * nbx) : zrow - (long)xrow * nbx);
+    const int tx = bxi * ca.bx + in % ca.bx;
+    const int ty = xrow * ca.by + (in / ca.bx) % ca.by;
+    const int tz = bzi * ca.bz + in / (ca.bx * ca.by);
     const int x = 2 * tx + wx, y = 2 * ty + wy, z = TZ * tz + wz, Lt = ca.L[3];
     const uint32_t r = (uint32_t)(chunk * 64 + lane);
     // out-of-tile neighbour coordinates (forward at the tile's upper edge, else
