@@ -180,13 +180,22 @@ __device__ __forceinline__ void transport(const PathSrc &ps, const float2 (&a)[2
 // order put the z and t neighbours (576 and 13824 sites away at 24^4) out of
 // any L2's reach.  Each wave writes only its own site, so the order does not
 // change the result.
+// Workgroups (4 units each) are dealt to the XCDs by whole site blocks: at
+// each round XCD k works on block 8 i + k, so every XCD's L2 sees one compact
+// block at a time while the eight XCDs work on consecutive, mostly adjacent
+// blocks (face reads that cross to a neighbouring XCD's block at the same time
+// are served by the memory-side cache).  wpb = workgroups per site block; the
+// grid is padded to whole rounds and padding workgroups return.
 template <int FIN, int FOUT>
 __global__ __launch_bounds__(256) void k_net_layer(const float2 *__restrict__ in, float2 *__restrict__ out,
                                                    const float2 *__restrict__ links, const int *__restrict__ nbr,
                                                    const bf16x4 *__restrict__ table, int N, int nrb,
-                                                   unsigned nunits, const int *__restrict__ order) {
+                                                   unsigned nunits, const int *__restrict__ order, unsigned wpb) {
     const int lane = threadIdx.x & 63;
-    const unsigned unit = uni(xcd_tile(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6));
+    const unsigned xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
+    const unsigned round = slot / wpb;
+    const unsigned wg = (round * 8u + xcd) * wpb + (slot - round * wpb);
+    const unsigned unit = uni(wg * 4u + (threadIdx.x >> 6));
     if (unit >= nunits) return;
     const unsigned q = unit / (unsigned)nrb;
     const long site = uni(order[q]);
@@ -445,7 +454,14 @@ int launch_layer(mpmc_ctx *ctx, const mpmc_net *net, int op, const void *in, voi
     const int nrb = (N + 15) / 16;
     const long units = ctx->V * nrb;
     if (units > 0xFFFFFFFFL - 4) return set_err(ctx, MPMC_EINVAL, "network: batch too large");
-    const unsigned blocks = grid_for(units, 4);
+    // sites per block of the default site order (extent 4, 2 or 1 per direction)
+    long bsites = 1;
+    for (int mu = 0; mu < 4; ++mu) bsites *= ctx->dims[mu] % 4 == 0 ? 4 : (ctx->dims[mu] % 2 == 0 ? 2 : 1);
+    const long wpb = std::max<long>(1, bsites * nrb / 4);          // workgroups per site block
+    const long nwg = (units + 3) / 4;
+    const long rounds = (nwg + 8 * wpb - 1) / (8 * wpb);
+    if (rounds * 8 * wpb > 0x7FFFFFFFL) return set_err(ctx, MPMC_EINVAL, "network: batch too large");
+    const unsigned blocks = (unsigned)(rounds * 8 * wpb);
     const bf16x4 *tab = reinterpret_cast<const bf16x4 *>(net->tables + (size_t)op * TABLE_ELEMS);
     const float2 *L = reinterpret_cast<const float2 *>(ctx->links32);
     const float2 *x = (const float2 *)in;
@@ -453,7 +469,7 @@ int launch_layer(mpmc_ctx *ctx, const mpmc_net *net, int op, const void *in, voi
 #define LAYER(A, B)                                                                                       \
     if (fin == A && fout == B)                                                                            \
         k_net_layer<A, B><<<blocks, 256, 0, ctx->stream>>>(x, y, L, ctx->nbr, tab, N, nrb, (unsigned)units, \
-                                                           ctx->site_order);                                 \
+                                                           ctx->site_order, (unsigned)wpb);                  \
     else
     LAYER(1, 2)
     LAYER(2, 2)
