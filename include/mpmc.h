@@ -243,10 +243,14 @@ int mpmc_poly_trace(mpmc_ctx *ctx, const mpmc_poly *p, int theta, const int peri
  * defined on the torus; the colouring is translation invariant).  The forms
  * are searched by increasing colour count with a fixed pseudo-random sequence
  * (the result depends on dims and distance only); without a valid candidate
- * every site gets its own colour (forms x_mu mod L_mu).  Outputs (host):
+ * every site gets its own colour (forms x_mu mod L_mu), and so without a
+ * search when distance reaches the torus diameter (sum of L_mu / 2) or when
+ * the distance ball exceeds 4 V displacements on a lattice of more than 2^24
+ * sites.  Outputs (host):
  * *k_host, moduli_host[4] (unused entries 1), W_host[16] (row-major k x 4,
  * unused rows 0), *ncolours_host = prod moduli.  EINVAL for a null pointer,
- * distance < 0 or an extent outside 1 .. 1024. */
+ * distance < 0 or an extent outside 1 .. 1024; ENOMEM if the host search
+ * cannot allocate. */
 int mpmc_probe_colouring(const int dims[4], int distance, int *k_host, int *moduli_host, int *W_host,
                          long *ncolours_host);
 
