@@ -48,7 +48,9 @@
  * is a DEVICE pointer owned by the caller (e.g. a torch tensor's data_ptr()),
  * unless its name ends in _host.  Handles (mpmc_ctx, mpmc_poly, mpmc_defl,
  * mpmc_net) are owned by the library and released only by their _destroy
- * call.  The library allocates its own device workspace inside the context.
+ * call.  The library allocates its own device workspace inside the context;
+ * mpmc_apply_poly_noalloc instead carves its work vectors from a fixed
+ * 64 MiB device array per GPU and allocates nothing.
  *
  * Ordering: work is enqueued on the context's HIP stream.  Calls that return
  * values through _host pointers or through d_eff/relres/iters outputs
