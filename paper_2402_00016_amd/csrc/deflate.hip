@@ -29,6 +29,36 @@ __global__ void k_gamma5_scale(const double2 *x, double2 *y, long n, double2 coe
     y[e] = make_double2(coef.x * v.x - coef.y * v.y, coef.x * v.y + coef.y * v.x);
 }
 
+// Ritz vectors z_q = V y_q for q in [q0, q0 + QC) (q < ns), one thread per
+// complex element: each basis vector is read once for QC Ritz vectors instead
+// of once per vector.  Per z_q the arithmetic is that of forming it alone with
+// the single-vector update from a zero start (same order, basis precision), so
+// the vectors are the same bit for bit; they are written widened to FP64.
+template <int PB, int QC>
+__global__ __launch_bounds__(256) void k_ritz_vectors(const void *__restrict__ V, size_t vstep, int me,
+                                                      const double2 *__restrict__ Y, int ns, int q0,
+                                                      double2 *__restrict__ Z, long n) {
+    using T = typename Store<PB>::real;
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    cpx<T> acc[QC];
+#pragma unroll
+    for (int q = 0; q < QC; ++q) acc[q] = mk(T(0), T(0));
+    for (int j = 0; j < me; ++j) {
+        const auto v0 = Store<PB>::ld((const char *)V + (size_t)j * vstep, nullptr, e, 0);
+        const cpx<T> v = mk((T)v0.re, (T)v0.im);
+#pragma unroll
+        for (int q = 0; q < QC; ++q)
+            if (q0 + q < ns) {
+                const double2 y = Y[(size_t)(q0 + q) * me + j];
+                acc[q] = acc[q] + mk((T)y.x, (T)y.y) * v;
+            }
+    }
+#pragma unroll
+    for (int q = 0; q < QC; ++q)
+        if (q0 + q < ns) Z[(size_t)(q0 + q) * n + e] = make_double2((double)acc[q].re, (double)acc[q].im);
+}
+
 int defl_coeffs(mpmc_ctx *ctx, const mpmc_defl *d, const void *x, int nrhs, double *c_dev, int divide_by_lambda) {
     RET_IF(blas_multi_dot(ctx, d->U, ctx->n, 1, d->k, x, nrhs, MPMC_FP64, c_dev, 0, 0));
     if (divide_by_lambda) {
@@ -180,25 +210,30 @@ MPMC_API int mpmc_deflate(mpmc_ctx *ctx, const mpmc_poly *p_in, uint64_t seed, u
     double *MZ = (double *)S.get(vb * ns);
     double *tmp = (double *)S.get(vb);
     double *scal = (double *)S.get(sizeof(double2) * 8);
-    void *z32 = bprec == MPMC_FP64 ? nullptr : S.get(vec_bytes(ctx, 1, bprec));
-    if (!mus || !Y || !Zc || !MZ || !tmp || !scal || (bprec != MPMC_FP64 && !z32)) return MPMC_ENOMEM;
+    if (!mus || !Y || !Zc || !MZ || !tmp || !scal) return MPMC_ENOMEM;
     HIP_OR_RET(ctx, hipMemcpyAsync(mus, musel.data(), sizeof(double2) * ns, hipMemcpyHostToDevice, ctx->stream));
     RET_IF(dense_inverse_iteration(ctx, H, m + 1, me, mus, ns, Y));
 
-    // Ritz vectors z = V y (unit norm), M z, Rayleigh quotients
+    // Ritz vectors z = V y in the basis precision (FP64 coefficients), widened
+    // to FP64: all of them in passes over the basis (20 per pass from an FP32
+    // basis, 8 from an FP64 one), then unit norm, M z, Rayleigh quotients
+    {
+        const unsigned grid = grid_for(n, 256);
+        if (bprec == MPMC_FP64) {
+            for (int q0 = 0; q0 < ns; q0 += 8)
+                k_ritz_vectors<MPMC_FP64, 8><<<grid, 256, 0, ctx->stream>>>(V, (size_t)n * 16, me, (const double2 *)Y,
+                                                                           ns, q0, (double2 *)Zc, n);
+        } else {
+            for (int q0 = 0; q0 < ns; q0 += 20)
+                k_ritz_vectors<MPMC_FP32, 20><<<grid, 256, 0, ctx->stream>>>(V, (size_t)n * 8, me, (const double2 *)Y,
+                                                                            ns, q0, (double2 *)Zc, n);
+        }
+        HIP_OR_RET(ctx, hipGetLastError());
+    }
     std::vector<std::complex<double>> lam(ns);
     std::vector<double> rres(ns);
     for (int q = 0; q < ns; ++q) {
         double *z = Zc + 2 * (size_t)q * n, *mz = MZ + 2 * (size_t)q * n;
-        if (bprec == MPMC_FP64) {
-            HIP_OR_RET(ctx, hipMemsetAsync(z, 0, vb, ctx->stream));
-            RET_IF(blas_multi_axpy(ctx, V, n, 1, me, z, 1, MPMC_FP64, Y + 2 * (size_t)q * me, 1, 1.0, nullptr));
-        } else {
-            // z = V y in the basis precision (FP64 coefficients), then widened
-            HIP_OR_RET(ctx, hipMemsetAsync(z32, 0, vec_bytes(ctx, 1, bprec), ctx->stream));
-            RET_IF(blas_multi_axpy(ctx, V, n, 1, me, z32, 1, bprec, Y + 2 * (size_t)q * me, 1, 1.0, nullptr));
-            RET_IF(blas_convert(ctx, z32, bprec, z, MPMC_FP64, 1));
-        }
         RET_IF(blas_norm2(ctx, z, 1, MPMC_FP64, scal));
         RET_IF(blas_scale_rhs(ctx, z, z, 1, MPMC_FP64, scal, 1));
         RET_IF(wilson_launch_full(ctx, z, nullptr, mz, nullptr, 1, MPMC_FP64, make_double2(0, 0), make_double2(1, 0),
