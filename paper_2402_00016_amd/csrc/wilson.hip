@@ -207,6 +207,16 @@ struct SiteAcc {
         if constexpr (kBuf) return ldbuf<P>(rs, k, N, r);
         else return ldspin<P, UNI>(b, bsc, site, k, N, r);
     }
+    // FP32 store with the non-temporal policy (cache-policy bit 1): the L2
+    // keeps the line first in line for eviction, leaving its capacity to lines
+    // that other workgroups of the XCD are about to read
+    __device__ __forceinline__ void st_stream(int k, cpx<float> v) const {
+        static_assert(kBuf && P == MPMC_FP32, "FP32 buffer accessor only");
+        f32x2 d;
+        d.x = v.re;
+        d.y = v.im;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, d), rs, (int)(r * 8u), k * N * 8, 2);
+    }
     __device__ __forceinline__ void st(int k, cpx<typename Store<P>::real> v) const {
         if constexpr (kBuf) stbuf<P>(rs, k, N, r, v);
         else stspin<P, UNI>(const_cast<void *>(b), site, k, N, r, v);
@@ -1434,7 +1444,10 @@ __global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) v
         load_link_lanes<MPMC_FP32>(links + (col_site(ca, xb, y, z, t) * 4 + 0) * 9, lb[0]);
         load_link_lanes<MPMC_FP32>(links + (col_site(ca, x, yb, z, t) * 4 + 1) * 9, lb[1]);
         load_link_lanes<MPMC_FP32>(links + (col_site(ca, x, y, zb, t) * 4 + 2) * 9, lb[2]);
-        const uint32_t code = MODE == 1 ? codes[s * N + r] : 0u;
+        // the noise code and the step's output are touched once per launch:
+        // non-temporal, so the L2 keeps the slices that neighbouring tiles read
+        // (fused step 1,373 -> 1,352 us at 24^4 x 64)
+        const uint32_t code = MODE == 1 ? __builtin_nontemporal_load(codes + s * N + r) : 0u;
         // slice t of every column of the tile (published one step ahead) is now
         // visible, and every read of step t-1 is done (three buffers rotate)
         __syncthreads();
@@ -1506,7 +1519,7 @@ __global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) v
             for (int k = 0; k < 12; ++k) {
                 const cpx<T> mb = cur[k] - kap * acc[k / 3][k % 3];
                 res[k] = (k >= 6 ? beg5 : be) * mb + al * av[k];
-                O.st(k, res[k]);
+                O.st_stream(k, res[k]);
             }
             if (o.y) {
                 const cpx<T> ga = mk((T)o.gamma.x, (T)o.gamma.y);
@@ -1532,7 +1545,7 @@ __global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) v
                 const cpx<T> mw = cur[k] - kap * acc[k / 3][k % 3];
                 cpx<T> wn = cur[k] - ccf * mw;
                 if constexpr (CMB) wn = al * av[k] + be * wn;
-                O.st(k, wn);
+                O.st_stream(k, wn);
                 const uint32_t sym = (code >> (2 * k)) & 3u;
                 const double ar = (double)wn.re, ai = (double)wn.im;
                 const double sg = (sym & 2u) ? -1.0 : 1.0;
