@@ -95,11 +95,12 @@ TRAFFIC_FILES = {"8x4": os.path.join(ROOT, "profiles", "k_wilson_dot_fp32_8x4x12
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2402_00016_amd", "csrc", "wilson.hip")
 
 
-def measured_traffic(workload, kernel):
+def measured_traffic(workload, kernel, variant=None):
     """HBM bytes per launch of `kernel` ("fused" or "plain") from the committed
     counter summary of the workload, or None when the summary is missing or the
     kernel source changed since the counters were taken (the summary records
-    the source's SHA-256)."""
+    the source's SHA-256).  variant: the traversal the run used (fused-step
+    order or apply variant), when the summary lists it separately."""
     import hashlib
     try:
         txt = open(TRAFFIC_FILES[workload]).read()
@@ -109,9 +110,11 @@ def measured_traffic(workload, kernel):
     vals = {}
     for line in txt.splitlines():
         line = line.strip().strip("`")
-        if ":" in line and line.split(":", 1)[0] in ("kernel_source_sha256", key):
+        if ":" in line and line.split(":", 1)[0].startswith(("kernel_source_sha256", key)):
             k, v = line.split(":", 1)
             vals[k] = v.strip()
+    if variant is not None and "%s_%s" % (key, variant) in vals:
+        key = "%s_%s" % (key, variant)
     if key not in vals:
         return None
     if vals.get("kernel_source_sha256") != hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest():
@@ -287,6 +290,9 @@ def main():
     kf = kern("k_wilson_dot<FP32> (fused polynomial level step: w' = w - c M w, eta^H Theta w')", fused)
     kp = kern("k_wilson<FP32> (multi-RHS apply: solves, polynomial applications)", plain32)
     dom, dom_key = (kf, "fused") if fused[1] >= plain32[1] else (kp, "plain")
+    tuned64 = getattr(ctx, "tuned", {}).get((noises if not W["max_batch"] else W["max_batch"], mpmc.FP32), {})
+    dom_variant = ("order%s" % tuned64.get("level_order") if dom_key == "fused" else
+                   "variant%s" % tuned64.get("variant")) if tuned64 else None
     out = {
         "metric": "multi-RHS Dslash HBM GB/s; time to fixed trace std-error, learned vs plain",
         "value": round(dslash_bytes / (dslash_ms * 1e-3) / 1e9, 3) if dslash_ms > 0 else None,
@@ -312,7 +318,7 @@ def main():
                                               "note": "nrhs = 1 (Arnoldi cycles): counted, not timed, not in value"}},
         "roofline": {"bound": "hbm", "achieved": dom["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom["GBs"] / HBM_PEAK_GBS, 4) if dom["GBs"] else None,
-                     "traffic": measured_traffic(a.workload, dom_key),
+                     "traffic": measured_traffic(a.workload, dom_key, dom_variant),
                      "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy)",
                      **{k: dom[k] for k in ("kernel", "launches", "avg_launch_us", "algorithmic_bytes_per_launch")}},
         "autotuned": {"%d_%s" % (k[0], {0: "fp64", 1: "fp32", 2: "fp16s"}[k[1]]): v

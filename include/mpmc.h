@@ -354,7 +354,7 @@ int mpmc_solve_batch(mpmc_ctx *const *ctxs, int count, const void *const *b, voi
 
 /* ---------------------------------------------------------------- autotuner */
 /* The multi-RHS Wilson kernel (nrhs a multiple of 64) has variants
- * 0 .. mpmc_wilson_variant_count() - 1 (currently 12) that differ only in how
+ * 0 .. mpmc_wilson_variant_count() - 1 (currently 13) that differ only in how
  * the work is laid out on the GPU, never in the arithmetic (results are
  * bit-identical):
  *   0-9, bit 0 -- occupancy target: 1 = more wavefronts per SIMD (FP32/FP16S:
@@ -377,7 +377,13 @@ int mpmc_solve_batch(mpmc_ctx *const *ctxs, int count, const void *const *b, voi
  *   11       -- column streaming with 2 x 2 x 1 tiles (FP32, even Lx, Ly,
  *               Lt >= 4; else 5): 4 wavefronts per workgroup and half the
  *               LDS, so two workgroups share a compute unit; both z
- *               neighbours come from memory (5 reads per site).
+ *               neighbours come from memory (5 reads per site);
+ *   12       -- column streaming with 2 x 2 x 4 tiles and 32-wide
+ *               right-hand-side chunks (FP32, even Lx, Ly, Lz % 4 == 0,
+ *               Lt >= 4, buffer ranges below 2 GiB; else 5): a wavefront holds
+ *               two sites of a column pair (32 lanes each), so an XCD's
+ *               concurrent workgroups cover twice the sites and fewer
+ *               neighbours fall outside them (3.5 reads per site).
  * Defaults: variant 10 where it applies (FP32), else 5 for FP32/FP16S and 4
  * for FP64.
  * mpmc_autotune times every variant on (nrhs, prec) with scratch vectors of
@@ -394,8 +400,8 @@ int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host, double *
 int mpmc_wilson_variant_count(void);
 /* Pin a variant for (nrhs, prec); -1 restores the default.  A pinned variant
  * also fixes the traversal of the fused polynomial step of the level
- * estimators (variants 0-3: site-major, 4-9: blocked chunks, 10 and 11:
- * column streaming with 2x2x2 and 2x2x1 tiles), overriding
+ * estimators (variants 0-3: site-major, 4-9: blocked chunks, 10, 11 and 12:
+ * column streaming with 2x2x2, 2x2x1 and 2x2x4 tiles), overriding
  * mpmc_autotune_level.  For nrhs = 1 (single vectors) variant 0 selects
  * eight lanes per site (one hop each), 1 the generic kernel with one site per
  * lane, 2 the single-vector kernel with one site per lane (coordinate-derived
@@ -405,14 +411,15 @@ int mpmc_tune_set(mpmc_ctx *ctx, int nrhs, int prec, int variant);
 /* Autotune the fused polynomial step of mpmc_level_estimate (the dominant
  * kernel of the polynomial levels, Sec. 6): every traversal valid for the
  * shape -- order 0 site-major, 2 blocked 64-wide chunks, 3 / 4 blocked 16- /
- * 32-wide chunks (V % 16 == 0), 5 / 6 column streaming (FP32, as variants
- * 10 / 11) --
- * is timed on (nrhs, prec) (2 warm-up + 5 timed steps, HIP events) and the
- * fastest is kept for later level estimates on ctx.  Without this call the
- * step takes the column streaming kernel where it applies, else blocked
- * 64-wide chunks (V % 4 == 0), else site-major.  prec FP64 or FP32, nrhs a
- * multiple of 64 (and of 256 above 256).  order_host (may be NULL): the
- * choice; us_host (may be NULL): double[7] microseconds per step by order (0
+ * 32-wide chunks (V % 16 == 0), 5 / 6 / 7 column streaming (FP32, as
+ * variants 10 / 11 / 12) --
+ * is timed on (nrhs, prec) (2 warm-up + 5 timed steps, HIP events, best of
+ * three interleaved rounds) and the fastest is kept for later level
+ * estimates on ctx.  Without this call the step takes the column streaming
+ * kernel with 2x2x2 tiles where it applies, else blocked 64-wide chunks
+ * (V % 4 == 0), else site-major.  prec FP64 or FP32, nrhs a multiple of 64
+ * (and of 256 above 256).  order_host (may be NULL): the choice; us_host
+ * (may be NULL): double[8] microseconds per step by order (0
  * for orders not tried).  Samples are the same up to the grouping of the FP64
  * partial sums.  Does not count MVPs.  Synchronises. */
 int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_host, double *us_host);

@@ -29,6 +29,8 @@
 //                quadratic form eta^H Theta w' is accumulated on the fly
 //                (eta regenerated from 2-bit Z(4) codes), so a step moves one
 //                spinor read and one spinor write per (site, rhs).
+#include <algorithm>
+
 #include "common.h"
 
 // Phase codes: 0 -> +1, 1 -> +i, 2 -> -1, 3 -> -i.
@@ -576,9 +578,10 @@ struct Occ {
 // chunk-major, 2 chunk-major over the blocked site order, 3 and 4 the same with
 // 16- and 32-wide chunks, four and two sites per wavefront and per-lane
 // links).  Orders 3 and 4 need V % 16 == 0; elsewhere they fall back to 2.
-constexpr int WILSON_VARIANTS = 12;
+constexpr int WILSON_VARIANTS = 13;
 constexpr int WILSON_COLUMN = 10;    // FP32 column-streaming kernel (k_wilson_col), 2x2x2 tiles
 constexpr int WILSON_COLUMN1 = 11;   // the same with 2x2x1 tiles (two workgroups per compute unit)
+constexpr int WILSON_COLUMNP = 12;   // 2x2x4 tiles, 32-wide chunks, two sites per wavefront (k_wilson_colp)
 
 // Everything one thread does for (site s, rhs r) once located.
 template <int P, bool UNI, int ORDER>
@@ -1581,6 +1584,333 @@ __global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) v
     }
 }
 
+// ------------------------------------ column streaming, 32-wide chunks --
+// The same walk along t with twice the sites per workgroup: 2x2x4 tiles of
+// (x, y, z) columns and 32-wide right-hand-side chunks, wavefront w holding
+// the sites (w & 1, w >> 1 & 1, 2 (w >> 2) + h) of the tile in its lanes
+// 32 h .. 32 h + 31 (h = 0, 1).  LDS per slice is the same 48 KB, but an
+// XCD's round of 32 workgroups now covers an 8x8x8 block of sites instead of
+// 8x8x4, so fewer out-of-tile neighbours fall outside the block the XCD's L2
+// holds (0.75 instead of 1.0 per site) and the in-tile z neighbours cut the
+// out-of-tile reads per site from three to two and a half; the links are read
+// once per 32 right-hand sides instead of 64.  The two sites of a wavefront
+// have different links: each 16-lane row loads its site's link and the
+// values are broadcast within rows (DPP), as in the narrow-chunk traversals.
+
+// Spinor access to the wavefront's two sites (z and z + 1): one buffer
+// resource based at the lower site, the upper half's offset in the VGPR.
+struct PairAcc {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t vo;
+    int N;
+    __device__ __forceinline__ PairAcc(const void *base, long site0, uint32_t vo_, uint32_t range, int N_)
+        : vo(vo_), N(N_) {
+        const char *p = reinterpret_cast<const char *>(base) + site0 * 12L * N_ * 8;
+        rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, (int)range, kBufWord3);
+    }
+    __device__ __forceinline__ cpx<float> ld(int k) const {
+        const f32x2 v = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)vo, k * N * 8, 0));
+        return mk(v.x, v.y);
+    }
+    __device__ __forceinline__ void st_stream(int k, cpx<float> v) const {   // non-temporal, as in k_wilson_col
+        f32x2 d;
+        d.x = v.re;
+        d.y = v.im;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, d), rs, (int)vo, k * N * 8, 2);
+    }
+    __device__ __forceinline__ void st(int k, cpx<float> v) const {
+        f32x2 d;
+        d.x = v.re;
+        d.y = v.im;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, d), rs, (int)vo, k * N * 8, 0);
+    }
+};
+
+// A link spread over 16-lane rows (as load_link_rows) at a uniform base
+// (the pair's lower site) plus the lane's constant byte offset (its own site's
+// link, dword i of the row): the address arithmetic stays scalar.
+__device__ __forceinline__ void colp_link(const float2 *base, uint32_t off0, uint32_t off1, uint32_t (&lw)[2]) {
+    const char *p = reinterpret_cast<const char *>(base);
+    lw[0] = *reinterpret_cast<const uint32_t *>(p + off0);
+    lw[1] = *reinterpret_cast<const uint32_t *>(p + off1);
+}
+
+__device__ __forceinline__ void colp_load(const void *b, long site0, uint32_t vo, uint32_t range, int N,
+                                          cpx<float> (&psi)[12]) {
+    const PairAcc A(b, site0, vo, range, N);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) psi[k] = A.ld(k);
+}
+
+// hop MU from a spinor held by the lane, link spread over the lane's row
+template <int MU, bool FWD>
+__device__ __forceinline__ void colp_hop(const cpx<float> (&psi)[12], const uint32_t (&lw)[2], float bsign, float g,
+                                         cpx<float> acc[4][3]) {
+    HopData<MPMC_FP32> H;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) H.psi[k] = psi[k];
+    H.lw[0] = lw[0];
+    H.lw[1] = lw[1];
+    H.bsign = bsign;
+    apply<MPMC_FP32, false, MU, FWD, true>(H, g, acc);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// the partner's spinor from LDS: wavefront wv, lane ln (both per lane)
+__device__ __forceinline__ void colp_lds_read(const ColLds<2> &L, int buf, int wv, unsigned ln, cpx<float> (&psi)[12]) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const float2 v = L.v[buf][wv][k][ln];
+        psi[k] = mk(v.x, v.y);
+    }
+}
+
+// x or y hops (the in-tile neighbour is the partner wavefront's same lane)
+template <int MU>
+__device__ __forceinline__ void colp_dir(const ColLds<2> &L, int curb, int w, unsigned lane, int upper,
+                                         const cpx<float> (&og)[12], const uint32_t (&lf)[2], const uint32_t (&lb)[2],
+                                         float g, cpx<float> acc[4][3]) {
+    cpx<float> nb[12];
+    colp_lds_read(L, curb, w ^ (1 << MU), lane, nb);
+    if (!upper) {
+        colp_hop<MU, true>(nb, lf, 1.f, g, acc);
+        colp_hop<MU, false>(og, lb, 1.f, g, acc);
+    } else {
+        colp_hop<MU, true>(og, lf, 1.f, g, acc);
+        colp_hop<MU, false>(nb, lb, 1.f, g, acc);
+    }
+}
+
+template <int MODE, bool CMB>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k_wilson_colp(
+    const void *__restrict__ b, const float2 *__restrict__ links, ColArgs ca, int N, WOut o,
+    const uint32_t *__restrict__ codes, double2 c, double2 cnext, int theta, double2 *__restrict__ partial,
+    int first_step, const void *__restrict__ a2, double2 alpha, double2 beta) {
+    using T = float;
+    __shared__ ColLds<2> L;
+    // the lane's running quadratic form in LDS (live registers are the limit here)
+    __shared__ double2 dotl[MODE == 1 ? 512 : 1];
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned h = lane >> 5;                  // the wavefront's lower (0) or upper (1) site
+    const int wx = w & 1, wy = (w >> 1) & 1, wzp = w >> 2;
+    // XCD rounds and the z-first snake of blocks exactly as in k_wilson_col
+    const int bsz = ca.bx * ca.by * ca.bz, nbx = ca.ntx / ca.bx, nbz = ca.ntz / ca.bz;
+    const long xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
+    const long lb = slot / bsz;
+    const long gb = lb * 8 + xcd;
+    if (gb >= ca.nblk) return;
+    const long nbc = ca.ntiles / bsz;
+    const long chunk = gb / nbc, blk = gb - chunk * nbc;
+    const int in = (int)(slot - lb * bsz);
+    const unsigned tile = (unsigned)(chunk * ca.ntiles + blk * bsz + in);
+    const long zrow = blk / nbz;
+    const int bzi = (int)(zrow & 1 ? nbz - 1 - (blk - zrow * nbz) : blk - zrow * nbz);
+    const int xrow = (int)(zrow / nbx);
+    const int bxi = (int)(xrow & 1 ? nbx - 1 - (zrow - (long)xrow * nbx) : zrow - (long)xrow * nbx);
+    const int tx = bxi * ca.bx + in % ca.bx;
+    const int ty = xrow * ca.by + (in / ca.bx) % ca.by;
+    const int tz = bzi * ca.bz + in / (ca.bx * ca.by);
+    const int x = 2 * tx + wx, y = 2 * ty + wy, z0 = 4 * tz + 2 * wzp, Lt = ca.L[3];
+    const uint32_t r = (uint32_t)(chunk * 32 + (lane & 31u));
+    const long plane = (long)ca.L[0] * ca.L[1];   // sites between z and z + 1
+    // pair accessors: lower site's resource, upper half offset plane sites
+    const uint32_t pbytes = (uint32_t)(plane * 12 * N * 8);
+    const uint32_t range = pbytes + (uint32_t)(12 * N * 8);
+    const uint32_t vo = h * pbytes + r * 8u;
+    const long lsite_off = h ? plane : 0;          // the lane's own site = pair site + lsite_off
+    const int xo = wx ? (x + 1 == ca.L[0] ? 0 : x + 1) : (x == 0 ? ca.L[0] - 1 : x - 1);
+    const int yo = wy ? (y + 1 == ca.L[1] ? 0 : y + 1) : (y == 0 ? ca.L[1] - 1 : y - 1);
+    // the one out-of-tile z neighbour of the wavefront: below the lower site
+    // (wzp = 0, needed by the lower half) or above the upper one (wzp = 1,
+    // upper half); the other half finds its z neighbours in LDS
+    const int zq = wzp ? (z0 + 2 == ca.L[2] ? 0 : z0 + 2) : (z0 == 0 ? ca.L[2] - 1 : z0 - 1);
+    const bool zglob = (int)h == wzp;
+    const int xb = x == 0 ? ca.L[0] - 1 : x - 1, yb = y == 0 ? ca.L[1] - 1 : y - 1;
+    // per-lane byte offsets of the links from the pair's lower site's: a
+    // row's lanes take dwords i and 16 + (i < 2 ? i : 0) of their site's link
+    const unsigned li = lane & 15u;
+    const uint32_t lrow0 = li * 4u, lrow1 = (16u + (li < 2u ? li : 0u)) * 4u;
+    const uint32_t lh = (uint32_t)(lsite_off * 4 * 9 * 8);
+    // backward z links: based at the lower of the two halves' backward sites
+    // (z0 - 1 and z0, or z0 and Lz - 1 when z0 = 0), so both offsets are >= 0
+    const long zbase = z0 == 0 ? 0 : -plane;
+    const uint32_t lhz = (uint32_t)((z0 == 0 ? (h ? 0 : (long)(ca.L[2] - 1) * plane) : (h ? plane : 0)) * 4 * 9 * 8);
+    const uint32_t cofs = (uint32_t)((lsite_off * N + r) * 4);          // noise code offset
+    const float g = o.g;
+    const T kap = (T)o.kappa;
+    // LDS partners across z (lane ^ 32 of the own or the other z-pair wavefront)
+    const unsigned lz = lane ^ 32u;
+    const int wzf = h ? (w ^ 4) : w;               // forward z partner's wavefront
+    const int wzb = h ? w : (w ^ 4);               // backward z partner's wavefront
+
+    {
+        cpx<float> v[12];
+        colp_load(b, col_site(ca, x, y, z0, Lt - 1), vo, range, N, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) L.v[2][w][k][lane] = make_float2(v[k].re, v[k].im);
+        colp_load(b, col_site(ca, x, y, z0, 0), vo, range, N, v);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) L.v[0][w][k][lane] = make_float2(v[k].re, v[k].im);
+    }
+    uint32_t ltprev[2];
+    colp_link(links + (col_site(ca, x, y, z0, Lt - 1) * 4 + 3) * 9, lh + lrow0, lh + lrow1, ltprev);
+    if constexpr (MODE == 1) dotl[threadIdx.x] = make_double2(0.0, 0.0);
+
+    cpx<float> ogx[12], ogy[12], ogz[12];
+    colp_load(b, col_site(ca, xo, y, z0, 0), vo, range, N, ogx);
+    colp_load(b, col_site(ca, x, yo, z0, 0), vo, range, N, ogy);
+    if (zglob) col_load(b, col_site(ca, x, y, zq, 0), N, r, ogz);
+
+    for (int t = 0; t < Lt; ++t) {
+        const int curb = t % 3, prevb = (t + 2) % 3, nextb = (t + 1) % 3;
+        const long sp = col_site(ca, x, y, z0, t);   // the pair's lower site
+        const bool more = t + 1 < Lt;
+        cpx<float> nx[12];
+        colp_load(b, col_site(ca, x, y, z0, more ? t + 1 : 0), vo, range, N, nx);
+        uint32_t lf[4][2], lbk[3][2];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) colp_link(links + (sp * 4 + mu) * 9, lh + lrow0, lh + lrow1, lf[mu]);
+        colp_link(links + (col_site(ca, xb, y, z0, t) * 4 + 0) * 9, lh + lrow0, lh + lrow1, lbk[0]);
+        colp_link(links + (col_site(ca, x, yb, z0, t) * 4 + 1) * 9, lh + lrow0, lh + lrow1, lbk[1]);
+        colp_link(links + ((sp + zbase) * 4 + 2) * 9, lhz + lrow0, lhz + lrow1, lbk[2]);
+        const uint32_t code =
+            MODE == 1 ? __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(
+                            reinterpret_cast<const char *>(codes + sp * N) + cofs))
+                      : 0u;
+        __syncthreads();
+
+        cpx<float> acc[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int cc = 0; cc < 3; ++cc) acc[q][cc] = mk(0.f, 0.f);
+        colp_dir<0>(L, curb, w, lane, wx, ogx, lf[0], lbk[0], g, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) colp_load(b, col_site(ca, xo, y, z0, t + 1), vo, range, N, ogx);
+        __builtin_amdgcn_sched_barrier(0);
+        colp_dir<1>(L, curb, w, lane, wy, ogy, lf[1], lbk[1], g, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) colp_load(b, col_site(ca, x, yo, z0, t + 1), vo, range, N, ogy);
+        __builtin_amdgcn_sched_barrier(0);
+        // z: forward, then backward; the half without an out-of-tile
+        // neighbour takes the partner's spinor from LDS into ogz's registers
+        {
+            cpx<float> nb[12];
+            if (wzp == 0) {
+                colp_lds_read(L, curb, wzf, lz, nb);
+                colp_hop<2, true>(nb, lf[2], 1.f, g, acc);
+                if (!zglob) colp_lds_read(L, curb, wzb, lz, ogz);
+                colp_hop<2, false>(ogz, lbk[2], 1.f, g, acc);
+            } else {
+                if (!zglob) colp_lds_read(L, curb, wzf, lz, ogz);
+                colp_hop<2, true>(ogz, lf[2], 1.f, g, acc);
+                colp_lds_read(L, curb, wzb, lz, nb);
+                colp_hop<2, false>(nb, lbk[2], 1.f, g, acc);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (more && zglob) col_load(b, col_site(ca, x, y, zq, t + 1), N, r, ogz);
+        __builtin_amdgcn_sched_barrier(0);
+        colp_hop<3, true>(nx, lf[3], (ca.tap && t == Lt - 1) ? -1.f : 1.f, g, acc);
+        {
+            cpx<float> pv[12];
+            colp_lds_read(L, prevb, w, lane, pv);
+            colp_hop<3, false>(pv, ltprev, (ca.tap && t == 0) ? -1.f : 1.f, g, acc);
+        }
+        pin_acc(acc);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) L.v[nextb][w][k][lane] = make_float2(nx[k].re, nx[k].im);
+
+        cpx<float> cur[12];
+        colp_lds_read(L, curb, w, lane, cur);
+        const PairAcc O(o.out, sp, vo, range, N);
+        if constexpr (MODE == 0) {
+            const bool has_a = o.a_is_b || o.a;
+            const cpx<T> al = has_a ? mk((T)o.alpha.x, (T)o.alpha.y) : mk(T(0), T(0));
+            const cpx<T> be = mk((T)o.beta.x, (T)o.beta.y);
+            const cpx<T> beg5 = o.theta ? mk(-be.re, -be.im) : be;
+            cpx<T> av[12];
+            if (o.a && !o.a_is_b) {
+                const PairAcc A(o.a, sp, vo, range, N);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) av[k] = A.ld(k);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 12; ++k) av[k] = cur[k];
+            }
+            cpx<T> res[12];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const cpx<T> mb = cur[k] - kap * acc[k / 3][k % 3];
+                res[k] = (k >= 6 ? beg5 : be) * mb + al * av[k];
+                O.st_stream(k, res[k]);
+            }
+            if (o.y) {
+                const cpx<T> ga = mk((T)o.gamma.x, (T)o.gamma.y);
+                const PairAcc Y(o.y, sp, vo, range, N);
+                cpx<T> yv[12];
+#pragma unroll
+                for (int k = 0; k < 12; ++k) yv[k] = Y.ld(k);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) Y.st(k, yv[k] + ga * res[k]);
+            }
+        } else {
+            const cpx<T> ccf = mk((T)c.x, (T)c.y);
+            cpx<T> av[12];
+            if constexpr (CMB) {
+                const PairAcc A(a2, sp, vo, range, N);
+#pragma unroll
+                for (int k = 0; k < 12; ++k) av[k] = A.ld(k);
+            }
+            const cpx<T> al = mk((T)alpha.x, (T)alpha.y), be = mk((T)beta.x, (T)beta.y);
+            const double tsg = theta ? -1.0 : 1.0;
+            const double2 d0 = dotl[threadIdx.x];
+            cpx<double> dot = mk(d0.x, d0.y);
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                const cpx<T> mw = cur[k] - kap * acc[k / 3][k % 3];
+                cpx<T> wn = cur[k] - ccf * mw;
+                if constexpr (CMB) wn = al * av[k] + be * wn;
+                O.st_stream(k, wn);
+                const uint32_t sym = (code >> (2 * k)) & 3u;
+                const double ar = (double)wn.re, ai = (double)wn.im;
+                const double sg = (sym & 2u) ? -1.0 : 1.0;
+                const double gg = k >= 6 ? sg * tsg : sg;
+                dot.re += gg * ((sym & 1u) ? ai : ar);
+                dot.im += gg * ((sym & 1u) ? -ar : ai);
+            }
+            dotl[threadIdx.x] = make_double2(dot.re, dot.im);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) ltprev[q] = lf[3][q];
+    }
+    if constexpr (MODE == 1) {
+        // per-tile partial of each of the 32 right-hand sides: the 16 columns
+        // summed in a fixed order (wavefront, then lower before upper site)
+        __syncthreads();
+        const double2 *red = dotl;
+        if (threadIdx.x < 32) {
+            double sx = 0, sy = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    sx += red[q * 64 + hh * 32 + threadIdx.x].x;
+                    sy += red[q * 64 + hh * 32 + threadIdx.x].y;
+                }
+            const cpx<double> term = mk(cnext.x, cnext.y) * mk(sx, sy);
+            double2 *pp = partial + (long)tile * 32 + threadIdx.x;
+            if (first_step) {
+                *pp = make_double2(term.re, term.im);
+            } else {
+                const double2 old = *pp;
+                *pp = make_double2(old.x + term.re, old.y + term.im);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------- launch --
 
 static double spinor_bytes(int prec) { return prec == MPMC_FP64 ? 192.0 : (prec == MPMC_FP32 ? 96.0 : 52.0); }
@@ -1588,8 +1918,14 @@ static double spinor_bytes(int prec) { return prec == MPMC_FP64 ? 192.0 : (prec 
 // The column-streaming kernel needs even Lx, Ly (and Lz for 2x2x2 tiles),
 // Lt >= 4, FP32 and 64-wide chunks.
 static bool col_ok(const mpmc_ctx *ctx, int nrhs, int prec, int tz = 2) {
-    return prec == MPMC_FP32 && nrhs % 64 == 0 && ctx->dims[0] % 2 == 0 && ctx->dims[1] % 2 == 0 &&
-           ctx->dims[2] % tz == 0 && ctx->dims[3] >= 4;
+    const bool ok = prec == MPMC_FP32 && nrhs % 64 == 0 && ctx->dims[0] % 2 == 0 && ctx->dims[1] % 2 == 0 &&
+                    ctx->dims[2] % tz == 0 && ctx->dims[3] >= 4;
+    if (!ok || tz != 4) return ok;
+    // 2x2x4 tiles: a wavefront's two sites (one z-plane apart) share one
+    // buffer resource, whose range must stay below 2 GiB
+    // (and per-lane link offsets below 2 GiB as well)
+    const double range = ((double)ctx->dims[0] * ctx->dims[1] + 1) * 12.0 * nrhs * 8.0;
+    return range < 2147483648.0 && (double)ctx->V * 288.0 < 2147483648.0;
 }
 static ColArgs col_args(const mpmc_ctx *ctx, int tz = 2) {
     ColArgs a;
@@ -1598,23 +1934,24 @@ static ColArgs col_args(const mpmc_ctx *ctx, int tz = 2) {
     a.nty = ctx->dims[1] / 2;
     a.ntz = ctx->dims[2] / tz;
     // blocks of 8 x 8 x 4 sites where the extents allow (32 tiles of 2x2x2,
-    // 64 of 2x2x1: one round of workgroups of an XCD)
+    // 64 of 2x2x1: one round of workgroups of an XCD; 8 x 8 x 8 sites of
+    // 2x2x4 tiles)
     auto ext = [](int n, int want) {
         while (want > 1 && n % want != 0) want /= 2;
         return want;
     };
     a.bx = ext(a.ntx, 4);
     a.by = ext(a.nty, 4);
-    a.bz = ext(a.ntz, tz == 2 ? 2 : 4);
+    a.bz = ext(a.ntz, tz == 1 ? 4 : 2);   // 2x2x4 tiles: 4x4x2 of them, 8x8x8 sites
     a.ntiles = (long)a.ntx * a.nty * a.ntz;
     a.nblk = 0;
     a.tap = ctx->t_antiperiodic;
     return a;
 }
-// Grid of a column launch over nrhs / 64 chunks (sets ca.nblk).
-static unsigned col_grid(ColArgs &ca, int nrhs) {
+// Grid of a column launch over nrhs / width chunks (sets ca.nblk).
+static unsigned col_grid(ColArgs &ca, int nrhs, int width = 64) {
     const long bsz = (long)ca.bx * ca.by * ca.bz;
-    ca.nblk = ca.ntiles / bsz * (nrhs / 64);
+    ca.nblk = ca.ntiles / bsz * (nrhs / width);
     return (unsigned)(8 * ((ca.nblk + 7) / 8) * bsz);
 }
 static int default_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
@@ -1641,19 +1978,24 @@ static int wilson_variant(const mpmc_ctx *ctx, int nrhs, int prec) {
     const int v = it == ctx->tune.end() ? default_variant(ctx, nrhs, prec) : it->second;
     if (v == WILSON_COLUMN) return col_ok(ctx, nrhs, prec) ? v : (prec == MPMC_FP64 ? 4 : 5);
     if (v == WILSON_COLUMN1) return col_ok(ctx, nrhs, prec, 1) ? v : (prec == MPMC_FP64 ? 4 : 5);
+    if (v == WILSON_COLUMNP) return col_ok(ctx, nrhs, prec, 4) ? v : (prec == MPMC_FP64 ? 4 : 5);
     return (v >> 1) >= 3 && ctx->V % 16 != 0 ? (v & 1) | 4 : v;
 }
 
-// The fused level step takes the 64-wide blocked order whenever its chunk
-// tiles hold one chunk each (V % 4 == 0), and the site-major order otherwise;
+// The fused level step (FP32) takes the column kernel with 2x2x2 tiles where
+// the lattice allows it; otherwise (FP64 and other shapes) the 64-wide
+// blocked order whenever its chunk tiles hold one chunk each (V % 4 == 0),
+// and the site-major order otherwise;
 // a variant set explicitly for (nrhs, prec) with mpmc_tune_set selects its
-// traversal (orders 0 and 1: site-major; 3 and 4 need V % 16 == 0).  The
-// autotuner, which times the plain operator, does not change it.
+// traversal (orders 0 and 1: site-major; 3 and 4 need V % 16 == 0), and
+// otherwise mpmc_autotune_level's choice, once made, replaces the default.
 constexpr int kDotDefaultOrder = 2;   // 64-wide blocked chunks (FP64; FP32 takes the column kernel)
 constexpr int kDotColumn = 5;         // order code of the column-streaming fused step (2x2x2 tiles)
 constexpr int kDotColumn1 = 6;        // the same with 2x2x1 tiles
-constexpr int kDotOrders = 7;
-static bool is_col_order(int o) { return o == kDotColumn || o == kDotColumn1; }
+constexpr int kDotColumnP = 7;        // 2x2x4 tiles, 32-wide chunks (k_wilson_colp)
+constexpr int kDotOrders = 8;
+static bool is_col_order(int o) { return o == kDotColumn || o == kDotColumn1 || o == kDotColumnP; }
+static int col_order_tz(int o) { return o == kDotColumn1 ? 1 : (o == kDotColumnP ? 4 : 2); }
 static int dot_order(const mpmc_ctx *ctx, int nrhs, int prec) {
     const auto td = ctx->tune_dot.find(std::make_pair(nrhs, prec));
     if (td != ctx->tune_dot.end() && ctx->tune_explicit.find(std::make_pair(nrhs, prec)) == ctx->tune_explicit.end()) {
@@ -1663,7 +2005,9 @@ static int dot_order(const mpmc_ctx *ctx, int nrhs, int prec) {
     const auto it = ctx->tune_explicit.find(std::make_pair(nrhs, prec));
     if (it != ctx->tune_explicit.end() && it->second == WILSON_COLUMN1 && col_ok(ctx, nrhs, prec, 1) && nrhs <= 256)
         return kDotColumn1;
-    if (it == ctx->tune_explicit.end() || it->second == WILSON_COLUMN || it->second == WILSON_COLUMN1)
+    if (it != ctx->tune_explicit.end() && it->second == WILSON_COLUMNP && col_ok(ctx, nrhs, prec, 4) && nrhs <= 256)
+        return kDotColumnP;
+    if (it == ctx->tune_explicit.end() || it->second >= WILSON_COLUMN)
         if (col_ok(ctx, nrhs, prec) && nrhs <= 256) return kDotColumn;
     if (ctx->V % 4 != 0) return 0;
     const int o = (it == ctx->tune_explicit.end() || it->second >= WILSON_COLUMN) ? kDotDefaultOrder : it->second >> 1;
@@ -1673,10 +2017,11 @@ static int dot_order(const mpmc_ctx *ctx, int nrhs, int prec) {
 int wilson_dot_order(const mpmc_ctx *ctx, int nrhs, int prec) { return dot_order(ctx, nrhs, prec); }
 
 static int dot_width(int order, int nrhs) {
-    return order == 3 ? 16 : order == 4 ? 32 : (order == 2 || is_col_order(order)) ? 64 : (nrhs < 256 ? nrhs : 256);
+    return order == 3 ? 16 : (order == 4 || order == kDotColumnP) ? 32
+                             : (order == 2 || is_col_order(order)) ? 64 : (nrhs < 256 ? nrhs : 256);
 }
 static long dot_tiles_per_chunk(const mpmc_ctx *ctx, int order, int width) {
-    if (is_col_order(order)) return col_args(ctx, order == kDotColumn1 ? 1 : 2).ntiles;
+    if (is_col_order(order)) return col_args(ctx, col_order_tz(order)).ntiles;
     return ctx->V * width / 256;
 }
 
@@ -1740,6 +2085,13 @@ static void launch_w(mpmc_ctx *ctx, const void *b, WOut &o, int nrhs, double2 yi
         if (cv == WILSON_COLUMN) {
             ColArgs ca = col_args(ctx, 2);
             k_wilson_col<0, false, 2><<<col_grid(ca, nrhs), 512, 0, ctx->stream>>>(
+                in.b, in.links, ca, nrhs, o, nullptr, make_double2(0, 0), make_double2(0, 0), 0, nullptr, 0, nullptr,
+                make_double2(0, 0), make_double2(1, 0));
+            return;
+        }
+        if (cv == WILSON_COLUMNP) {
+            ColArgs ca = col_args(ctx, 4);
+            k_wilson_colp<0, false><<<col_grid(ca, nrhs, 32), 512, 0, ctx->stream>>>(
                 in.b, in.links, ca, nrhs, o, nullptr, make_double2(0, 0), make_double2(0, 0), 0, nullptr, 0, nullptr,
                 make_double2(0, 0), make_double2(1, 0));
             return;
@@ -1861,14 +2213,17 @@ static void launch_dot(mpmc_ctx *ctx, int dord, unsigned grid, const WIn<P> &in,
     const int *ord = dord ? ctx->site_order : nullptr;
     if constexpr (P == MPMC_FP32) {
         if (is_col_order(dord)) {
-            const int tz = dord == kDotColumn1 ? 1 : 2;
+            const int tz = col_order_tz(dord);
             ColArgs ca = col_args(ctx, tz);
-            const unsigned grid_c = col_grid(ca, nrhs);
+            const unsigned grid_c = col_grid(ca, nrhs, tz == 4 ? 32 : 64);
             WOut o{};
             o.out = wout;   // the step's output w'
             o.kappa = ctx->kappa;
             o.g = 1.f;
-            if (tz == 2)
+            if (tz == 4)
+                k_wilson_colp<1, CMB><<<grid_c, 512, 0, ctx->stream>>>(
+                    in.b, in.links, ca, nrhs, o, codes, c, cnext, theta, partial, first_step, a, alpha, beta);
+            else if (tz == 2)
                 k_wilson_col<1, CMB, 2><<<grid_c, 512, 0, ctx->stream>>>(
                     in.b, in.links, ca, nrhs, o, codes, c, cnext, theta, partial, first_step, a, alpha, beta);
             else
@@ -2142,9 +2497,9 @@ MPMC_API int mpmc_autotune(mpmc_ctx *ctx, int nrhs, int prec, int *variant_host,
 }
 
 // Fused level step traversal (orders 0 site-major, 2 blocked 64-wide chunks,
-// 3 / 4 blocked 16- / 32-wide chunks, 5 / 6 column streaming with 2x2x2 /
-// 2x2x1 tiles): each valid one is
-// timed (2 warm-up + 5 timed steps) and the fastest kept for (nrhs, prec).
+// 3 / 4 blocked 16- / 32-wide chunks, 5 / 6 / 7 column streaming with 2x2x2 /
+// 2x2x1 / 2x2x4 tiles): each valid one is timed (2 warm-up + 5 timed steps,
+// best of three rounds) and the fastest kept for (nrhs, prec).
 MPMC_API int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_host, double *us_host) {
     if (!ctx) return MPMC_EINVAL;
     if ((prec != MPMC_FP64 && prec != MPMC_FP32) || nrhs < 64 || nrhs % 64 != 0 || (nrhs > 256 && nrhs % 256 != 0))
@@ -2181,27 +2536,34 @@ MPMC_API int mpmc_autotune_level(mpmc_ctx *ctx, int nrhs, int prec, int *order_h
     }
     if (col_ok(ctx, nrhs, prec) && nrhs <= 256) cand.push_back(kDotColumn);
     if (col_ok(ctx, nrhs, prec, 1) && nrhs <= 256) cand.push_back(kDotColumn1);
+    if (col_ok(ctx, nrhs, prec, 4) && nrhs <= 256) cand.push_back(kDotColumnP);
     int best = cand.back(), rc = MPMC_OK;
     double best_us = 1e300;
-    constexpr int warm = 2, reps = 5;
-    for (size_t q = 0; q < cand.size() && rc == MPMC_OK; ++q) {
-        const int o = cand[q];
-        ctx->tune_dot[key] = o;
-        for (int i = 0; i < warm + reps && rc == MPMC_OK; ++i) {
-            if (i == warm && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = MPMC_EHIP;
-            if (rc == MPMC_OK)
-                rc = wilson_dot_step(ctx, (i & 1) ? y : x, (i & 1) ? x : y, codes, nrhs, prec, make_double2(0.1, 0),
-                                     make_double2(0.1, 0), 0, part, i == 0);
+    // candidates timed in three interleaved rounds, each keeping its best
+    // round: traversals a percent apart are then told apart reliably
+    constexpr int warm = 2, reps = 5, rounds = 3;
+    std::vector<double> us_min(cand.size(), 1e300);
+    for (int round = 0; round < rounds && rc == MPMC_OK; ++round)
+        for (size_t q = 0; q < cand.size() && rc == MPMC_OK; ++q) {
+            ctx->tune_dot[key] = cand[q];
+            for (int i = 0; i < warm + reps && rc == MPMC_OK; ++i) {
+                if (i == warm && hipEventRecord(e0, ctx->stream) != hipSuccess) rc = MPMC_EHIP;
+                if (rc == MPMC_OK)
+                    rc = wilson_dot_step(ctx, (i & 1) ? y : x, (i & 1) ? x : y, codes, nrhs, prec,
+                                         make_double2(0.1, 0), make_double2(0.1, 0), 0, part, i == 0);
+            }
+            float ms = 0.f;
+            if (rc == MPMC_OK &&
+                (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = set_err(ctx, MPMC_EHIP, "mpmc_autotune_level: timing failed");
+            us_min[q] = std::min(us_min[q], 1e3 * ms / reps);
         }
-        float ms = 0.f;
-        if (rc == MPMC_OK && (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-            rc = set_err(ctx, MPMC_EHIP, "mpmc_autotune_level: timing failed");
-        const double us = 1e3 * ms / reps;
-        if (us_host) us_host[o] = us;
-        if (rc == MPMC_OK && us < best_us) {
-            best_us = us;
-            best = o;
+    for (size_t q = 0; q < cand.size() && rc == MPMC_OK; ++q) {
+        if (us_host) us_host[cand[q]] = us_min[q];
+        if (us_min[q] < best_us) {
+            best_us = us_min[q];
+            best = cand[q];
         }
     }
     (void)hipEventDestroy(e0);

@@ -386,9 +386,9 @@ WILSON_VARIANTS = _L.mpmc_wilson_variant_count()   # kernel variants of the mult
 
 
 def mpmc_autotune_level(ctx, nrhs, prec):
-    """(chosen traversal order, microseconds per fused step for orders 0..6; 0 = not a candidate)."""
+    """(chosen traversal order, microseconds per fused step for orders 0..7; 0 = not a candidate)."""
     o = ctypes.c_int()
-    us = np.zeros(7)
+    us = np.zeros(8)
     _check(_L.mpmc_autotune_level(ctx, int(nrhs), int(prec), ctypes.byref(o), us.ctypes.data), ctx)
     return o.value, us
 

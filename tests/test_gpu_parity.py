@@ -621,7 +621,7 @@ def test_autotune_variants_bit_identical(f44, prec):
     assert ctx.autotune(20, prec)[0] == -1     # not a multiple of 64: nothing to tune
 
 
-@pytest.mark.parametrize("prec,variants", [(FP32, (1, 3, 5, 7, 9, 10, 11)), (FP64, (0, 2, 4, 6, 8))])
+@pytest.mark.parametrize("prec,variants", [(FP32, (1, 3, 5, 7, 9, 10, 11, 12)), (FP64, (0, 2, 4, 6, 8))])
 def test_fused_level_step_traversals(f44, prec, variants):
     """The fused level step under each traversal (site-major, chunk-major,
     4D-blocked with 64-, 16- and 32-wide chunks and their per-chunk
@@ -647,6 +647,43 @@ def test_fused_level_step_traversals(f44, prec, variants):
             assert abs(outs[-1][j] - Xr[j]) < 1e-10 * abs(Xr[j])
         else:   # FP32 kernels, FP64 sums: ~1e-6 n (bound 1e-5 n)
             assert abs(outs[-1][j] - Xr[j]) < 1e-5 * op.n
+
+
+@pytest.mark.parametrize("dims", [(8, 12, 8, 6), (6, 4, 12, 4)])
+def test_column_pair_kernel_matches_column(dims):
+    """The column kernel with 2x2x4 tiles and 32-wide chunks (two sites per
+    wavefront, links broadcast within 16-lane rows; variant 12) against the
+    2x2x2-tile one (variant 10) on lattices whose block grid is ragged: M, M^H
+    and gamma5 M bit for bit; the fused steps of a single and of a double
+    polynomial (combining steps) up to the grouping of the FP64 sums; two
+    samples against the oracle."""
+    kappa = 0.12
+    U = inputs.gauge_links(dims, 0.5, seed=6)
+    op, ctx = WilsonOp(dims, kappa, U), mpmc.Context(dims, kappa, U)
+    N = 128
+    x = ctx.noise(7, 1, 0, N, FP32)
+    for dagger, theta in ((False, 0), (True, 0), (False, 1)):
+        out = {}
+        for v in (10, 12):
+            ctx.tune_set(N, FP32, v)
+            out[v] = ctx.apply_M(x, N, FP32, dagger=dagger, theta=theta)
+        ctx.tune_set(N, FP32, -1)
+        assert torch.equal(out[10], out[12]), (dagger, theta)
+    P1, _, _ = OK.gmres_poly(op, z4_noise(1, 0x100, 0, op.n), 9)
+    g1 = ctx.poly_from_roots(P1.roots)
+    inner = ctx.gmres_poly(1, 0x101, 3)
+    dp = ctx.gmres_poly(1, 0x102, 4, inner=inner)
+    for P in (g1, dp):
+        X = {}
+        for v in (10, 12):
+            ctx.tune_set(N, FP32, v)
+            X[v], T, mv = ctx.level(P, None, None, 0, 5, 1, 0, N, prec=FP32)
+        ctx.tune_set(N, FP32, -1)
+        assert rel(X[12], X[10]) < 1e-13
+        if P is g1:
+            Xr, _ = OES.level_samples(op, P1, None, None, "I", 5, 1, 0, 2)
+            for j in range(2):   # FP32 kernels, FP64 sums
+                assert abs(X[12][j] - Xr[j]) < 1e-5 * op.n
 
 
 @pytest.mark.parametrize("prec,variant", [(FP32, 5), (FP64, 4)])
