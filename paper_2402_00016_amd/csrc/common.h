@@ -69,6 +69,7 @@ struct mpmc_ctx {
     // projections per inner GMRES step of mpmc_solve / mpmc_solve_batch: 1, 2, or 0 = one for
     // FP32 and FP16S inner cycles, two for FP64 ones
     int solve_gs_passes = 0;
+    unsigned col_flip = 0;   // column-kernel launches alternate their block order (bit 0)
     // fused polynomial recurrences replayed from captured hipGraphs (mpmc_set_graph_recurrences)
     int use_graphs = 0;
     hipStream_t gstream = nullptr;          // capture / replay stream (default priority)

@@ -1290,6 +1290,7 @@ struct ColArgs {
     long ntiles;         // tiles per 64-wide chunk
     long nblk;           // blocks over all chunks of the launch (col_grid)
     int tap;             // antiperiodic time direction
+    int rev;             // blocks in reverse order (see k_wilson_col)
 };
 
 template <int TZ>
@@ -1386,8 +1387,13 @@ __global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) v
     const int bsz = ca.bx * ca.by * ca.bz, nbx = ca.ntx / ca.bx, nbz = ca.ntz / ca.bz;
     const long xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
     const long lb = slot / bsz;
-    const long gb = lb * 8 + xcd;                              // block over all chunks
-    if (gb >= ca.nblk) return;
+    const long gb0 = lb * 8 + xcd;
+    if (gb0 >= ca.nblk) return;
+    // consecutive launches of a recurrence alternate the direction of the
+    // block sequence, so the first blocks of a launch read what the last
+    // blocks of the previous one wrote, while it is still in the memory-side
+    // cache (same arithmetic per tile: the results do not change)
+    const long gb = ca.rev ? ca.nblk - 1 - gb0 : gb0;          // block over all chunks
     const long nbc = ca.ntiles / bsz;                          // blocks per 64-wide chunk
     const long chunk = gb / nbc, blk = gb - chunk * nbc;
     const int in = (int)(slot - lb * bsz);
@@ -1698,8 +1704,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int bsz = ca.bx * ca.by * ca.bz, nbx = ca.ntx / ca.bx, nbz = ca.ntz / ca.bz;
     const long xcd = blockIdx.x % 8u, slot = blockIdx.x / 8u;
     const long lb = slot / bsz;
-    const long gb = lb * 8 + xcd;
-    if (gb >= ca.nblk) return;
+    const long gb0 = lb * 8 + xcd;
+    if (gb0 >= ca.nblk) return;
+    const long gb = ca.rev ? ca.nblk - 1 - gb0 : gb0;
     const long nbc = ca.ntiles / bsz;
     const long chunk = gb / nbc, blk = gb - chunk * nbc;
     const int in = (int)(slot - lb * bsz);
@@ -1946,6 +1953,7 @@ static ColArgs col_args(const mpmc_ctx *ctx, int tz = 2) {
     a.ntiles = (long)a.ntx * a.nty * a.ntz;
     a.nblk = 0;
     a.tap = ctx->t_antiperiodic;
+    a.rev = 0;
     return a;
 }
 // Grid of a column launch over nrhs / width chunks (sets ca.nblk).
@@ -2215,6 +2223,7 @@ static void launch_dot(mpmc_ctx *ctx, int dord, unsigned grid, const WIn<P> &in,
         if (is_col_order(dord)) {
             const int tz = col_order_tz(dord);
             ColArgs ca = col_args(ctx, tz);
+            ca.rev = (int)(ctx->col_flip++ & 1u);
             const unsigned grid_c = col_grid(ca, nrhs, tz == 4 ? 32 : 64);
             WOut o{};
             o.out = wout;   // the step's output w'
