@@ -105,6 +105,31 @@ def test_24_fused_level_step_sampled(f24, theta):
         assert abs(X[j] - ref) < 1e-5 * op.n
 
 
+def test_24_column_kernels_agree(f24):
+    """At the bench's shape (24^4, 64 right-hand sides) the column kernel with
+    2x2x4 tiles and 32-wide chunks (variant 12) gives the 2x2x2 kernel's
+    operator bit for bit and its fused level samples up to the grouping of
+    the FP64 sums, with the block order alternating between the launches."""
+    dims, kappa, U, op, ctx = f24
+    N = 64
+    x = ctx.noise(4, 5, 0, N, FP32)
+    out = {}
+    for v in (10, 12):
+        ctx.tune_set(N, FP32, v)
+        out[v] = ctx.apply_M(x, N, FP32)
+    assert torch.equal(out[10], out[12])
+    P = ctx.gmres_poly(4, 0x104, 6)
+    X = {}
+    for v in (10, 12):
+        ctx.tune_set(N, FP32, v)
+        X[v] = ctx.level(P, None, None, mpmc.THETA_I, 4, 6, 0, N, prec=FP32)[0]
+        # five fused launches: the repeat starts with the other block order
+        again = ctx.level(P, None, None, mpmc.THETA_I, 4, 6, 0, N, prec=FP32)[0]
+        assert np.array_equal(again, X[v])
+    ctx.tune_set(N, FP32, -1)
+    assert np.max(np.abs(X[12] - X[10])) < 1e-12 * np.max(np.abs(X[10]))
+
+
 def test_24_double_poly_fp64_sampled(f24):
     dims, kappa, U, op, ctx = f24
     pin = ctx.gmres_poly(4, 0x100, 16)
