@@ -1108,7 +1108,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_F
         // conj(eta_k) wn with eta_k = i^sym, by selects (no per-lane branches):
         // odd sym swaps (re, im) -> (im, -re), sym >= 2 negates; Theta = gamma5
         // negates spins 2 and 3.
-        const double tsg = theta ? -1.0 : 1.0;
+        // The site's 12 terms are summed in the storage precision (exact
+        // signs, 12 additions: the rounding of the stored w' is of the same
+        // size), every sum over sites, steps and blocks in FP64.
+        const T tsg = theta ? T(-1) : T(1);
+        T sr = T(0), si = T(0);
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
             const cpx<T> mw = wv[k] - kap * acc[k / 3][k % 3];
@@ -1116,12 +1120,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P == MPMC_F
             if constexpr (CMB) wn = al * av[k] + be * wn;
             O.st(k, wn);
             const uint32_t sym = (code >> (2 * k)) & 3u;
-            const double a = (double)wn.re, b = (double)wn.im;
-            const double sg = (sym & 2u) ? -1.0 : 1.0;
-            const double g = k >= 6 ? sg * tsg : sg;
-            dot.re += g * ((sym & 1u) ? b : a);
-            dot.im += g * ((sym & 1u) ? -a : b);
+            const T sg = (sym & 2u) ? T(-1) : T(1);
+            const T g = k >= 6 ? sg * tsg : sg;
+            sr += g * ((sym & 1u) ? wn.im : wn.re);
+            si += g * ((sym & 1u) ? -wn.re : wn.im);
         }
+        dot = mk((double)sr, (double)si);
     }
     red[threadIdx.x] = make_double2(dot.re, dot.im);
     __syncthreads();
@@ -1548,7 +1552,9 @@ __global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) v
                 for (int k = 0; k < 12; ++k) av[k] = A.ld(k);
             }
             const cpx<T> al = mk((T)alpha.x, (T)alpha.y), be = mk((T)beta.x, (T)beta.y);
-            const double tsg = theta ? -1.0 : 1.0;
+            // the site's terms in FP32, the running sum in FP64 (as k_wilson_dot)
+            const T tsg = theta ? T(-1) : T(1);
+            T sr = T(0), si = T(0);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const cpx<T> mw = cur[k] - kap * acc[k / 3][k % 3];
@@ -1556,12 +1562,13 @@ __global__ __launch_bounds__(256 * TZ) __attribute__((amdgpu_waves_per_eu(2))) v
                 if constexpr (CMB) wn = al * av[k] + be * wn;
                 O.st_stream(k, wn);
                 const uint32_t sym = (code >> (2 * k)) & 3u;
-                const double ar = (double)wn.re, ai = (double)wn.im;
-                const double sg = (sym & 2u) ? -1.0 : 1.0;
-                const double gg = k >= 6 ? sg * tsg : sg;
-                dot.re += gg * ((sym & 1u) ? ai : ar);
-                dot.im += gg * ((sym & 1u) ? -ar : ai);
+                const T sg = (sym & 2u) ? T(-1) : T(1);
+                const T gg = k >= 6 ? sg * tsg : sg;
+                sr += gg * ((sym & 1u) ? wn.im : wn.re);
+                si += gg * ((sym & 1u) ? -wn.re : wn.im);
             }
+            dot.re += (double)sr;
+            dot.im += (double)si;
         }
         ltprev[0] = lf[3][0];
     }
@@ -1871,9 +1878,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                 for (int k = 0; k < 12; ++k) av[k] = A.ld(k);
             }
             const cpx<T> al = mk((T)alpha.x, (T)alpha.y), be = mk((T)beta.x, (T)beta.y);
-            const double tsg = theta ? -1.0 : 1.0;
-            const double2 d0 = dotl[threadIdx.x];
-            cpx<double> dot = mk(d0.x, d0.y);
+            const T tsg = theta ? T(-1) : T(1);
+            T sr = T(0), si = T(0);
 #pragma unroll
             for (int k = 0; k < 12; ++k) {
                 const cpx<T> mw = cur[k] - kap * acc[k / 3][k % 3];
@@ -1881,13 +1887,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void k
                 if constexpr (CMB) wn = al * av[k] + be * wn;
                 O.st_stream(k, wn);
                 const uint32_t sym = (code >> (2 * k)) & 3u;
-                const double ar = (double)wn.re, ai = (double)wn.im;
-                const double sg = (sym & 2u) ? -1.0 : 1.0;
-                const double gg = k >= 6 ? sg * tsg : sg;
-                dot.re += gg * ((sym & 1u) ? ai : ar);
-                dot.im += gg * ((sym & 1u) ? -ar : ai);
+                const T sg = (sym & 2u) ? T(-1) : T(1);
+                const T gg = k >= 6 ? sg * tsg : sg;
+                sr += gg * ((sym & 1u) ? wn.im : wn.re);
+                si += gg * ((sym & 1u) ? -wn.re : wn.im);
             }
-            dotl[threadIdx.x] = make_double2(dot.re, dot.im);
+            const double2 d0 = dotl[threadIdx.x];
+            dotl[threadIdx.x] = make_double2(d0.x + (double)sr, d0.y + (double)si);
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) ltprev[q] = lf[3][q];
