@@ -576,7 +576,8 @@ int mpmc_solve_pairs(mpmc_ctx *ctx, const void *b, void *x, int nrhs, const mpmc
  * in effect, is deflated the same way with c_i = 1/lambda_i - lower(lambda_i).
  * Otherwise *corr_host = 0.
  * prec: precision of the polynomial applications (MPMC_FP64 or MPMC_FP32);
- * dot products and samples are accumulated in FP64.  Noise vectors are
+ * dot products and samples are accumulated in FP64 (in the fused steps the
+ * twelve terms of one site in prec first).  Noise vectors are
  * processed in batches of at most max_batch right-hand sides (0 = all).
  * samples_host: complex double [nnoise]; mvps_host (may be NULL): MVPs used.
  * Synchronises. */
