@@ -649,6 +649,30 @@ def test_fused_level_step_traversals(f44, prec, variants):
             assert abs(outs[-1][j] - Xr[j]) < 1e-5 * op.n
 
 
+@pytest.mark.parametrize("prec", [FP32, FP64])
+def test_autotune_level_orders(prec):
+    """mpmc_autotune_level times every traversal valid for the shape (the three
+    column kernels only in FP32), keeps the fastest, reports a time per order,
+    and the level estimate after it gives the default traversal's samples up
+    to the grouping of the FP64 sums."""
+    dims, kappa = (4, 4, 4, 4), 0.115
+    U = inputs.gauge_links(dims, 0.5, seed=1)
+    ctx = mpmc.Context(dims, kappa, U)
+    N = 128
+    P = ctx.poly_from_roots(np.array([1.0 + 0.1j * k for k in range(7)]))
+    X0 = ctx.level(P, None, None, 0, 5, 1, 0, N, prec=prec)[0]
+    order, us = ctx.autotune_level(N, prec)
+    assert us.shape == (8,)
+    tried = us > 0
+    assert tried[order] and us[order] == us[tried].min()
+    expect = {0, 2, 3, 4} | ({5, 6, 7} if prec == FP32 else set())
+    assert set(np.flatnonzero(tried)) == expect
+    X1 = ctx.level(P, None, None, 0, 5, 1, 0, N, prec=prec)[0]
+    assert rel(X1, X0) < 1e-13
+    with pytest.raises(mpmc.MpmcError):
+        ctx.autotune_level(96, prec)   # not a multiple of 64
+
+
 @pytest.mark.parametrize("dims", [(8, 12, 8, 6), (6, 4, 12, 4)])
 def test_column_pair_kernel_matches_column(dims):
     """The column kernel with 2x2x4 tiles and 32-wide chunks (two sites per
